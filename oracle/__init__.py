@@ -1,0 +1,243 @@
+"""ctypes binding of the plain FP64 CPU oracle (``oracle/mgard_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY.  The oracle follows the paper (arXiv 2010.05872)
+step by step: decomposition and recomposition of Sec. 2, the level-centric
+reordering of Sec. 5.1, and the level-wise quantization of Sec. 4.1.  Only
+the test suite, ``__graft_entry__.smoke`` and the CPU-baseline leg of
+``bench.py`` may import this package; the product library never does.
+
+All arrays are numpy float64 (int32 for labels), C order, interleaved layout
+(indexed by the finest-grid node), unless stated otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mgard_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libmgard_oracle.so")
+
+ERRORS = {0: "ok", 2: "shape", 3: "coords", 4: "level", 5: "tol", 6: "range", 9: "alloc"}
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"oracle {what}: error {code} ({ERRORS.get(code, '?')})")
+        self.code = code
+
+
+def build() -> str:
+    """Compile the oracle with gcc (plain C99, no FMA contraction)."""
+    cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-ffp-contract=off", "-fPIC", "-shared",
+           _SRC, "-o", _LIB_PATH + ".tmp", "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        vp = ctypes.c_void_p
+        L.mgo_num_levels.argtypes = [ctypes.c_int, i64p]
+        for name in ("mgo_decompose", "mgo_recompose"):
+            getattr(L, name).argtypes = [vp, ctypes.c_int, i64p, vp, ctypes.c_int]
+        L.mgo_correction.argtypes = [vp, vp, ctypes.c_int, i64p, vp]
+        L.mgo_mass_apply_1d.argtypes = [vp, ctypes.c_int64, vp, vp]
+        L.mgo_restrict_1d.argtypes = [vp, ctypes.c_int64, vp, vp]
+        L.mgo_coarse_mass_1d.argtypes = [vp, ctypes.c_int64, vp, vp, vp]
+        L.mgo_project_line_1d.argtypes = [vp, ctypes.c_int64, vp, vp]
+        L.mgo_axis_operator_norm.argtypes = [vp, ctypes.c_int64]
+        L.mgo_axis_operator_norm.restype = ctypes.c_double
+        L.mgo_level_map.argtypes = [vp, ctypes.c_int, i64p, ctypes.c_int]
+        L.mgo_level_centric_index.argtypes = [vp, ctypes.c_int, i64p, ctypes.c_int]
+        L.mgo_linf_constant.argtypes = [ctypes.c_int, i64p, vp, ctypes.c_int]
+        L.mgo_linf_constant.restype = ctypes.c_double
+        L.mgo_level_tolerances.argtypes = [ctypes.c_int, i64p, vp, ctypes.c_double, ctypes.c_int,
+                                           ctypes.c_double, dp]
+        for name in ("mgo_quantize", "mgo_dequantize"):
+            getattr(L, name).argtypes = [vp, vp, ctypes.c_int, i64p, vp, ctypes.c_double,
+                                         ctypes.c_int, ctypes.c_double]
+        _lib = L
+    return _lib
+
+
+def _dims(shape):
+    arr = (ctypes.c_int64 * len(shape))(*[int(s) for s in shape])
+    return arr
+
+
+class _Coords:
+    """Keeps the per-axis coordinate arrays alive for one call."""
+
+    def __init__(self, shape, coords):
+        self.keep = []
+        if coords is None:
+            self.ptr = None
+            return
+        if len(coords) != len(shape):
+            raise ValueError("coords must have one entry per axis")
+        ptrs = (ctypes.c_void_p * len(shape))()
+        for k, c in enumerate(coords):
+            if c is None:
+                ptrs[k] = None
+                continue
+            a = np.ascontiguousarray(c, dtype=np.float64)
+            if a.shape != (shape[k],):
+                raise ValueError(f"coords[{k}] must have {shape[k]} entries")
+            self.keep.append(a)
+            ptrs[k] = a.ctypes.data
+        self.keep.append(ptrs)
+        self.ptr = ctypes.cast(ptrs, ctypes.c_void_p)
+
+
+def _check(code, what):
+    if code != 0:
+        raise OracleError(code, what)
+
+
+def num_levels(shape) -> int:
+    r = lib().mgo_num_levels(len(shape), _dims(shape))
+    if r < 0:
+        raise OracleError(-r, "num_levels")
+    return r
+
+
+def decompose(u, coords=None, stop_level=0) -> np.ndarray:
+    """Interleaved u_mc of u (float64 copy), Sec. 2 decomposition."""
+    v = np.array(u, dtype=np.float64, order="C", copy=True)
+    c = _Coords(v.shape, coords)
+    _check(lib().mgo_decompose(v.ctypes.data, v.ndim, _dims(v.shape), c.ptr, int(stop_level)), "decompose")
+    return v
+
+
+def recompose(u_mc, coords=None, stop_level=0) -> np.ndarray:
+    v = np.array(u_mc, dtype=np.float64, order="C", copy=True)
+    c = _Coords(v.shape, coords)
+    _check(lib().mgo_recompose(v.ctypes.data, v.ndim, _dims(v.shape), c.ptr, int(stop_level)), "recompose")
+    return v
+
+
+def correction(z, coords=None) -> np.ndarray:
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    out_shape = tuple((n + 1) // 2 for n in z.shape)
+    y = np.empty(out_shape, dtype=np.float64)
+    c = _Coords(z.shape, coords)
+    _check(lib().mgo_correction(z.ctypes.data, y.ctypes.data, z.ndim, _dims(z.shape), c.ptr), "correction")
+    return y
+
+
+def mass_apply_1d(X, g):
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    out = np.empty_like(g)
+    lib().mgo_mass_apply_1d(X.ctypes.data, len(X), g.ctypes.data, out.ctypes.data)
+    return out
+
+
+def restrict_1d(X, g):
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    f = np.empty((len(X) + 1) // 2)
+    lib().mgo_restrict_1d(X.ctypes.data, len(X), g.ctypes.data, f.ctypes.data)
+    return f
+
+
+def coarse_mass_1d(X):
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    mc = (len(X) + 1) // 2
+    sub, diag, sup = np.empty(mc), np.empty(mc), np.empty(mc)
+    lib().mgo_coarse_mass_1d(X.ctypes.data, len(X), sub.ctypes.data, diag.ctypes.data, sup.ctypes.data)
+    return sub, diag, sup
+
+
+def project_line_1d(X, z):
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    y = np.empty((len(X) + 1) // 2)
+    lib().mgo_project_line_1d(X.ctypes.data, len(X), z.ctypes.data, y.ctypes.data)
+    return y
+
+
+def axis_operator_norm(X) -> float:
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    return lib().mgo_axis_operator_norm(X.ctypes.data, len(X))
+
+
+def level_map(shape, stop_level=0) -> np.ndarray:
+    lev = np.empty(shape, dtype=np.int8)
+    _check(lib().mgo_level_map(lev.ctypes.data, len(shape), _dims(shape), int(stop_level)), "level_map")
+    return lev
+
+
+def level_centric_index(shape, stop_level=0) -> np.ndarray:
+    pos = np.empty(shape, dtype=np.int64)
+    _check(lib().mgo_level_centric_index(pos.ctypes.data, len(shape), _dims(shape), int(stop_level)),
+           "level_centric_index")
+    return pos
+
+
+def to_level_centric(a, stop_level=0) -> np.ndarray:
+    """Sec. 5.1 reordering of an interleaved array (any dtype)."""
+    a = np.ascontiguousarray(a)
+    pos = level_centric_index(a.shape, stop_level).ravel()
+    out = np.empty(a.size, dtype=a.dtype)
+    out[pos] = a.ravel()
+    return out.reshape(a.shape)
+
+
+def from_level_centric(a, stop_level=0) -> np.ndarray:
+    a = np.ascontiguousarray(a)
+    pos = level_centric_index(a.shape, stop_level).ravel()
+    return a.ravel()[pos].reshape(a.shape)
+
+
+def linf_constant(shape, coords=None, stop_level=0) -> float:
+    c = _Coords(shape, coords)
+    r = lib().mgo_linf_constant(len(shape), _dims(shape), c.ptr, int(stop_level))
+    if r < 0:
+        raise OracleError(1, "linf_constant")
+    return r
+
+
+def level_tolerances(shape, tol, coords=None, stop_level=0, c_linf=0.0) -> np.ndarray:
+    L = num_levels(shape)
+    tau = np.empty(L + 1 - stop_level, dtype=np.float64)
+    c = _Coords(shape, coords)
+    _check(lib().mgo_level_tolerances(len(shape), _dims(shape), c.ptr, float(tol), int(stop_level),
+                                      float(c_linf), tau.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+           "level_tolerances")
+    return tau
+
+
+def quantize(u_mc, tol, coords=None, stop_level=0, c_linf=0.0):
+    """Labels (int32, interleaved) and the status code (0 or 6 = range)."""
+    v = np.ascontiguousarray(u_mc, dtype=np.float64)
+    labels = np.empty(v.shape, dtype=np.int32)
+    c = _Coords(v.shape, coords)
+    code = lib().mgo_quantize(v.ctypes.data, labels.ctypes.data, v.ndim, _dims(v.shape), c.ptr,
+                              float(tol), int(stop_level), float(c_linf))
+    if code not in (0, 6):
+        raise OracleError(code, "quantize")
+    return labels, code
+
+
+def dequantize(labels, tol, coords=None, stop_level=0, c_linf=0.0) -> np.ndarray:
+    lab = np.ascontiguousarray(labels, dtype=np.int32)
+    out = np.empty(lab.shape, dtype=np.float64)
+    c = _Coords(lab.shape, coords)
+    _check(lib().mgo_dequantize(lab.ctypes.data, out.ctypes.data, lab.ndim, _dims(lab.shape), c.ptr,
+                                float(tol), int(stop_level), float(c_linf)), "dequantize")
+    return out

@@ -1,0 +1,626 @@
+/*
+ * Plain FP64 CPU oracle for MGARD+ multilevel decomposition, recomposition
+ * and level-wise quantization (arXiv 2010.05872).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file.  Only the test suite, the smoke check and the benchmark's
+ * CPU-baseline leg may use it.  It shares no source, header, table or helper
+ * with the HIP path.
+ *
+ * Everything here is single threaded, unblocked and unfused: it follows the
+ * paper's definitions step by step so that a reader can check it by eye.
+ *
+ * Layout: arrays are C order with shape (n_0, ..., n_{d-1}); the last axis is
+ * contiguous.  The multilevel coefficients u_mc are kept "interleaved", i.e.
+ * indexed by the node of the finest grid N_L exactly as in Sec. 2 (u_mc[x]
+ * holds the coefficient of the coarsest level that contains x).  The
+ * level-centric layout of Sec. 5.1 is produced by mgo_level_centric_index.
+ */
+#include "mgard_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Grid hierarchy (Sec. 2, Table 1).                                          */
+/* Axes are padded to three: a padded axis has one node and never coarsens.   */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  int d;              /* spatial dimension (number of real axes) */
+  int64_t n[3];       /* node counts, padded axes have n = 1 */
+  int real[3];        /* 1 for a real (coarsening) axis */
+  double *X[3];       /* owned copies of the fine coordinates */
+  int L;              /* finest level index */
+} grid_t;
+
+static int is_dyadic_plus_one(int64_t n, int *m) {
+  if (n < 3) return 0;
+  int64_t t = n - 1;
+  int k = 0;
+  while ((t & 1) == 0) { t >>= 1; k++; }
+  if (t != 1) return 0;
+  *m = k;
+  return 1;
+}
+
+static void grid_free(grid_t *g) {
+  for (int k = 0; k < 3; k++) { free(g->X[k]); g->X[k] = NULL; }
+}
+
+/* The level count: every axis halves together, and the coarsest grid N_0 has
+ * three nodes on the shortest axis (the example grids of Sec. 6 are
+ * decomposed down to 3^d nodes). */
+static int grid_init(grid_t *g, int ndim, const int64_t *dims,
+                     const double *const *coords) {
+  memset(g, 0, sizeof(*g));
+  if (ndim < 1 || ndim > 3 || dims == NULL) return MGO_ERR_SHAPE;
+  g->d = ndim;
+  int mmin = 1 << 30;
+  for (int k = 0; k < 3; k++) {
+    int src = k - (3 - ndim);
+    if (src < 0) { g->n[k] = 1; g->real[k] = 0; continue; }
+    int m;
+    if (!is_dyadic_plus_one(dims[src], &m)) return MGO_ERR_SHAPE;
+    g->n[k] = dims[src];
+    g->real[k] = 1;
+    if (m < mmin) mmin = m;
+  }
+  g->L = mmin - 1;
+  for (int k = 0; k < 3; k++) {
+    int src = k - (3 - ndim);
+    g->X[k] = (double *)malloc(sizeof(double) * (size_t)g->n[k]);
+    if (!g->X[k]) { grid_free(g); return MGO_ERR_ALLOC; }
+    for (int64_t i = 0; i < g->n[k]; i++) {
+      double x = (src >= 0 && coords && coords[src]) ? coords[src][i] : (double)i;
+      if (!isfinite(x)) { grid_free(g); return MGO_ERR_COORDS; }
+      if (i > 0 && !(x > g->X[k][i - 1])) { grid_free(g); return MGO_ERR_COORDS; }
+      g->X[k][i] = x;
+    }
+  }
+  return MGO_OK;
+}
+
+/* Number of level-l nodes along axis k: N_l keeps every 2^(L-l)-th node. */
+static int64_t level_size(const grid_t *g, int k, int l) {
+  if (!g->real[k]) return 1;
+  return (g->n[k] - 1) / ((int64_t)1 << (g->L - l)) + 1;
+}
+
+/* Level-l coordinates along axis k. */
+static void level_coords(const grid_t *g, int k, int l, double *Xl) {
+  int64_t s = (int64_t)1 << (g->L - l);
+  int64_t m = level_size(g, k, l);
+  for (int64_t j = 0; j < m; j++) Xl[j] = g->real[k] ? g->X[k][j * s] : 0.0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One-dimensional building blocks on a line with nodes X_0 < ... < X_{m-1}. */
+/* ------------------------------------------------------------------------ */
+
+/* Weight of the left and right nodal neighbour when piecewise linear
+ * interpolation predicts the odd node j from nodes j-1 and j+1 (Sec. 2,
+ * operator Pi; on uniform grids both weights are 1/2, eq. of Sec. 4.2). */
+static double w_left(const double *X, int64_t j)  { return (X[j + 1] - X[j]) / (X[j + 1] - X[j - 1]); }
+static double w_right(const double *X, int64_t j) { return (X[j] - X[j - 1]) / (X[j + 1] - X[j - 1]); }
+
+/* Mass matrix of the piecewise linear hat functions on X applied to g:
+ * (Mg)_j = h_{j-1}/6 g_{j-1} + (h_{j-1}+h_j)/3 g_j + h_j/6 g_{j+1}
+ * with h_j = X_{j+1}-X_j and terms beyond the ends dropped. */
+void mgo_mass_apply_1d(const double *X, int64_t m, const double *g, double *out) {
+  for (int64_t j = 0; j < m; j++) {
+    double hl = (j > 0) ? X[j] - X[j - 1] : 0.0;
+    double hr = (j < m - 1) ? X[j + 1] - X[j] : 0.0;
+    double acc = (hl + hr) / 3.0 * g[j];
+    if (j > 0) acc += hl / 6.0 * g[j - 1];
+    if (j < m - 1) acc += hr / 6.0 * g[j + 1];
+    out[j] = acc;
+  }
+}
+
+/* Restriction R = P^T, P the prolongation by linear interpolation from the
+ * even nodes: f_J = g_{2J} + w_right(2J-1) g_{2J-1} + w_left(2J+1) g_{2J+1}. */
+void mgo_restrict_1d(const double *X, int64_t m, const double *g, double *f) {
+  int64_t mc = (m + 1) / 2;
+  for (int64_t J = 0; J < mc; J++) {
+    int64_t j = 2 * J;
+    double acc = g[j];
+    if (j - 1 >= 0) acc += w_right(X, j - 1) * g[j - 1];
+    if (j + 1 <= m - 1) acc += w_left(X, j + 1) * g[j + 1];
+    f[J] = acc;
+  }
+}
+
+/* Tridiagonal coarse mass matrix on the even nodes of X (spacing
+ * H_J = X_{2J+2}-X_{2J}): sub H_{J-1}/6, diag (H_{J-1}+H_J)/3, sup H_J/6.
+ * On a uniform grid of fine spacing h this is the matrix printed in Sec. 5.4. */
+void mgo_coarse_mass_1d(const double *X, int64_t m, double *sub, double *diag, double *sup) {
+  int64_t mc = (m + 1) / 2;
+  for (int64_t J = 0; J < mc; J++) {
+    double Hl = (J > 0) ? X[2 * J] - X[2 * J - 2] : 0.0;
+    double Hr = (J < mc - 1) ? X[2 * J + 2] - X[2 * J] : 0.0;
+    sub[J] = Hl / 6.0;
+    diag[J] = (Hl + Hr) / 3.0;
+    sup[J] = Hr / 6.0;
+  }
+}
+
+/* Thomas algorithm (forward elimination, back substitution, no pivoting;
+ * the coarse mass matrix is symmetric and diagonally dominant). In place. */
+static void thomas_solve(int64_t mc, const double *sub, const double *diag,
+                         const double *sup, double *f, double *work) {
+  /* work holds the modified diagonal */
+  work[0] = diag[0];
+  for (int64_t J = 1; J < mc; J++) {
+    double mult = sub[J] / work[J - 1];
+    work[J] = diag[J] - mult * sup[J - 1];
+    f[J] = f[J] - mult * f[J - 1];
+  }
+  f[mc - 1] = f[mc - 1] / work[mc - 1];
+  for (int64_t J = mc - 2; J >= 0; J--) f[J] = (f[J] - sup[J] * f[J + 1]) / work[J];
+}
+
+/* L2 projection onto the coarse line of a fine-line function z:
+ * y = Mc^{-1} R M z (mass apply, restriction, tridiagonal solve). */
+void mgo_project_line_1d(const double *X, int64_t m, const double *z, double *y) {
+  int64_t mc = (m + 1) / 2;
+  double *g = (double *)malloc(sizeof(double) * (size_t)m);
+  double *sub = (double *)malloc(sizeof(double) * (size_t)mc * 4);
+  double *diag = sub + mc, *sup = sub + 2 * mc, *work = sub + 3 * mc;
+  mgo_mass_apply_1d(X, m, z, g);
+  mgo_restrict_1d(X, m, g, y);
+  mgo_coarse_mass_1d(X, m, sub, diag, sup);
+  thomas_solve(mc, sub, diag, sup, y, work);
+  free(g);
+  free(sub);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Correction computation (Sec. 2, step 4): the L2 projection onto V_{l-1} of */
+/* the multilevel component z, one axis after the other, the contiguous axis  */
+/* first ("row sweep, then column sweep", Sec. 5.1).                          */
+/* z has level-l shape m[0..2]; y receives the level-(l-1) shape.             */
+/* ------------------------------------------------------------------------ */
+static int correction_box(const int64_t m_in[3], const int real[3],
+                          double *const Xl[3], const double *z, double *y) {
+  int64_t a[3] = {m_in[0], m_in[1], m_in[2]};
+  size_t total = (size_t)(a[0] * a[1] * a[2]);
+  double *cur = (double *)malloc(sizeof(double) * total);
+  if (!cur) return MGO_ERR_ALLOC;
+  memcpy(cur, z, sizeof(double) * total);
+  for (int k = 2; k >= 0; k--) {
+    if (!real[k]) continue;
+    int64_t mk = a[k], mc = (mk + 1) / 2;
+    int64_t b[3] = {a[0], a[1], a[2]};
+    b[k] = mc;
+    double *next = (double *)malloc(sizeof(double) * (size_t)(b[0] * b[1] * b[2]));
+    double *line = (double *)malloc(sizeof(double) * (size_t)mk);
+    double *res = (double *)malloc(sizeof(double) * (size_t)mc);
+    if (!next || !line || !res) { free(cur); free(next); free(line); free(res); return MGO_ERR_ALLOC; }
+    /* strides of the current and next arrays */
+    int64_t sa[3] = {a[1] * a[2], a[2], 1};
+    int64_t sb[3] = {b[1] * b[2], b[2], 1};
+    int o1 = (k == 0) ? 1 : 0, o2 = (k == 2) ? 1 : 2; /* the two other axes */
+    for (int64_t p = 0; p < a[o1]; p++) {
+      for (int64_t q = 0; q < a[o2]; q++) {
+        int64_t base_a = p * sa[o1] + q * sa[o2];
+        int64_t base_b = p * sb[o1] + q * sb[o2];
+        for (int64_t j = 0; j < mk; j++) line[j] = cur[base_a + j * sa[k]];
+        mgo_project_line_1d(Xl[k], mk, line, res);
+        for (int64_t J = 0; J < mc; J++) next[base_b + J * sb[k]] = res[J];
+      }
+    }
+    free(line);
+    free(res);
+    free(cur);
+    cur = next;
+    a[k] = mc;
+  }
+  memcpy(y, cur, sizeof(double) * (size_t)(a[0] * a[1] * a[2]));
+  free(cur);
+  return MGO_OK;
+}
+
+int mgo_correction(const double *z, double *y, int ndim, const int64_t *dims,
+                   const double *const *coords) {
+  grid_t g;
+  int st = grid_init(&g, ndim, dims, coords);
+  if (st) return st;
+  int64_t m[3] = {g.n[0], g.n[1], g.n[2]};
+  st = correction_box(m, g.real, g.X, z, y);
+  grid_free(&g);
+  return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Level-l view of the interleaved array: level index (j0,j1,j2) is the fine */
+/* node (j0 s, j1 s, j2 s), s = 2^(L-l).                                      */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  double *v;
+  int64_t stride[3]; /* fine-array stride times s, per axis */
+  int64_t m[3];
+  double *Xl[3];
+  int real[3];
+} level_view_t;
+
+static int view_init(level_view_t *w, const grid_t *g, double *v, int l) {
+  int64_t s = (int64_t)1 << (g->L - l);
+  int64_t fs[3] = {g->n[1] * g->n[2], g->n[2], 1};
+  w->v = v;
+  for (int k = 0; k < 3; k++) {
+    w->real[k] = g->real[k];
+    w->m[k] = level_size(g, k, l);
+    w->stride[k] = g->real[k] ? fs[k] * s : 0;
+    w->Xl[k] = (double *)malloc(sizeof(double) * (size_t)w->m[k]);
+    if (!w->Xl[k]) return MGO_ERR_ALLOC;
+    level_coords(g, k, l, w->Xl[k]);
+  }
+  return MGO_OK;
+}
+
+static void view_free(level_view_t *w) {
+  for (int k = 0; k < 3; k++) { free(w->Xl[k]); w->Xl[k] = NULL; }
+}
+
+static double *at(const level_view_t *w, int64_t j0, int64_t j1, int64_t j2) {
+  return w->v + j0 * w->stride[0] + j1 * w->stride[1] + j2 * w->stride[2];
+}
+
+/* Piecewise multilinear interpolant Pi_{l-1} at the level-l node j, built
+ * from the 2^(#odd axes) nodal corners (eq. of Sec. 4.2: edge, plane and cube
+ * nodes use 2, 4 and 8 corners with weights 1/2, 1/4, 1/8 on uniform grids). */
+static double interpolant(const level_view_t *w, const int64_t j[3]) {
+  int odd[3];
+  for (int k = 0; k < 3; k++) odd[k] = w->real[k] && (j[k] & 1);
+  double pred = 0.0;
+  for (int c = 0; c < 8; c++) {
+    int64_t q[3];
+    double wt = 1.0;
+    int skip = 0;
+    for (int k = 0; k < 3; k++) {
+      int bit = (c >> k) & 1;
+      if (!odd[k]) {
+        if (bit) { skip = 1; break; }
+        q[k] = j[k];
+      } else if (bit == 0) {
+        q[k] = j[k] - 1;
+        wt *= w_left(w->Xl[k], j[k]);
+      } else {
+        q[k] = j[k] + 1;
+        wt *= w_right(w->Xl[k], j[k]);
+      }
+    }
+    if (skip) continue;
+    pred += wt * *at(w, q[0], q[1], q[2]);
+  }
+  return pred;
+}
+
+static int is_nodal(const level_view_t *w, const int64_t j[3]) {
+  for (int k = 0; k < 3; k++)
+    if (w->real[k] && (j[k] & 1)) return 0;
+  return 1;
+}
+
+/* The multilevel component (I - Pi_{l-1}) Q_l u as a level-l box: the value
+ * stored at coefficient nodes, zero at nodal nodes. */
+static double *component_box(const level_view_t *w) {
+  size_t total = (size_t)(w->m[0] * w->m[1] * w->m[2]);
+  double *z = (double *)malloc(sizeof(double) * total);
+  if (!z) return NULL;
+  size_t t = 0;
+  for (int64_t j0 = 0; j0 < w->m[0]; j0++)
+    for (int64_t j1 = 0; j1 < w->m[1]; j1++)
+      for (int64_t j2 = 0; j2 < w->m[2]; j2++, t++) {
+        int64_t j[3] = {j0, j1, j2};
+        z[t] = is_nodal(w, j) ? 0.0 : *at(w, j0, j1, j2);
+      }
+  return z;
+}
+
+/* Add sign * y (level-(l-1) box) to the nodal values. */
+static void apply_correction(const level_view_t *w, const double *y, double sign) {
+  int64_t mc[3];
+  for (int k = 0; k < 3; k++) mc[k] = w->real[k] ? (w->m[k] + 1) / 2 : 1;
+  size_t t = 0;
+  for (int64_t J0 = 0; J0 < mc[0]; J0++)
+    for (int64_t J1 = 0; J1 < mc[1]; J1++)
+      for (int64_t J2 = 0; J2 < mc[2]; J2++, t++) {
+        double *p = at(w, w->real[0] ? 2 * J0 : 0, w->real[1] ? 2 * J1 : 0, w->real[2] ? 2 * J2 : 0);
+        *p += sign * y[t];
+      }
+}
+
+static size_t coarse_total(const level_view_t *w) {
+  size_t t = 1;
+  for (int k = 0; k < 3; k++) t *= (size_t)(w->real[k] ? (w->m[k] + 1) / 2 : 1);
+  return t;
+}
+
+/* One decomposition step Q_l u -> (Q_{l-1} u, coefficients on N*_l), Sec. 2
+ * steps 2-5. */
+static int decompose_level(const grid_t *g, double *v, int l) {
+  level_view_t w;
+  int st = view_init(&w, g, v, l);
+  if (st) { view_free(&w); return st; }
+  /* steps 2+3 (coefficient computation): subtract the interpolant at every
+   * coefficient node; nodal corners are never modified, so order is free. */
+  for (int64_t j0 = 0; j0 < w.m[0]; j0++)
+    for (int64_t j1 = 0; j1 < w.m[1]; j1++)
+      for (int64_t j2 = 0; j2 < w.m[2]; j2++) {
+        int64_t j[3] = {j0, j1, j2};
+        if (is_nodal(&w, j)) continue;
+        double pred = interpolant(&w, j);
+        *at(&w, j0, j1, j2) -= pred;
+      }
+  /* step 4 (correction computation) */
+  double *z = component_box(&w);
+  double *y = (double *)malloc(sizeof(double) * coarse_total(&w));
+  if (!z || !y) { free(z); free(y); view_free(&w); return MGO_ERR_ALLOC; }
+  st = correction_box(w.m, w.real, w.Xl, z, y);
+  /* step 5 (correction application): nodal values become Q_{l-1} u */
+  if (!st) apply_correction(&w, y, +1.0);
+  free(z);
+  free(y);
+  view_free(&w);
+  return st;
+}
+
+/* One recomposition step (Sec. 2, recomposition steps 2-4). */
+static int recompose_level(const grid_t *g, double *v, int l) {
+  level_view_t w;
+  int st = view_init(&w, g, v, l);
+  if (st) { view_free(&w); return st; }
+  double *z = component_box(&w);
+  double *y = (double *)malloc(sizeof(double) * coarse_total(&w));
+  if (!z || !y) { free(z); free(y); view_free(&w); return MGO_ERR_ALLOC; }
+  /* step 2: correction from the coefficients; step 3: subtract it */
+  st = correction_box(w.m, w.real, w.Xl, z, y);
+  if (!st) apply_correction(&w, y, -1.0);
+  /* step 4: add the interpolant of the corrected nodal values */
+  if (!st) {
+    for (int64_t j0 = 0; j0 < w.m[0]; j0++)
+      for (int64_t j1 = 0; j1 < w.m[1]; j1++)
+        for (int64_t j2 = 0; j2 < w.m[2]; j2++) {
+          int64_t j[3] = {j0, j1, j2};
+          if (is_nodal(&w, j)) continue;
+          double pred = interpolant(&w, j);
+          *at(&w, j0, j1, j2) += pred;
+        }
+  }
+  free(z);
+  free(y);
+  view_free(&w);
+  return st;
+}
+
+int mgo_num_levels(int ndim, const int64_t *dims) {
+  grid_t g;
+  int st = grid_init(&g, ndim, dims, NULL);
+  if (st) return -st;
+  int L = g.L;
+  grid_free(&g);
+  return L;
+}
+
+int mgo_decompose(double *v, int ndim, const int64_t *dims,
+                  const double *const *coords, int stop_level) {
+  grid_t g;
+  int st = grid_init(&g, ndim, dims, coords);
+  if (st) return st;
+  if (stop_level < 0 || stop_level > g.L) { grid_free(&g); return MGO_ERR_LEVEL; }
+  for (int l = g.L; l > stop_level && !st; l--) st = decompose_level(&g, v, l);
+  grid_free(&g);
+  return st;
+}
+
+int mgo_recompose(double *v, int ndim, const int64_t *dims,
+                  const double *const *coords, int stop_level) {
+  grid_t g;
+  int st = grid_init(&g, ndim, dims, coords);
+  if (st) return st;
+  if (stop_level < 0 || stop_level > g.L) { grid_free(&g); return MGO_ERR_LEVEL; }
+  for (int l = stop_level + 1; l <= g.L && !st; l++) st = recompose_level(&g, v, l);
+  grid_free(&g);
+  return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Level membership and the level-centric reordering (Sec. 5.1).              */
+/* ------------------------------------------------------------------------ */
+
+/* Level of fine index i along one real axis: the coarsest level whose grid
+ * contains it, with everything in N_{stop} reported as level stop. */
+static int axis_level(int64_t i, int L, int stop) {
+  int64_t sstop = (int64_t)1 << (L - stop);
+  if (i % sstop == 0) return stop;
+  int tz = 0;
+  while (((i >> tz) & 1) == 0) tz++;
+  return L - tz;
+}
+
+int mgo_level_map(int8_t *lev, int ndim, const int64_t *dims, int stop_level) {
+  grid_t g;
+  int st = grid_init(&g, ndim, dims, NULL);
+  if (st) return st;
+  if (stop_level < 0 || stop_level > g.L) { grid_free(&g); return MGO_ERR_LEVEL; }
+  size_t t = 0;
+  for (int64_t i0 = 0; i0 < g.n[0]; i0++)
+    for (int64_t i1 = 0; i1 < g.n[1]; i1++)
+      for (int64_t i2 = 0; i2 < g.n[2]; i2++, t++) {
+        int64_t i[3] = {i0, i1, i2};
+        int lv = stop_level;
+        for (int k = 0; k < 3; k++) {
+          if (!g.real[k]) continue;
+          int a = axis_level(i[k], g.L, stop_level);
+          if (a > lv) lv = a;
+        }
+        lev[t] = (int8_t)lv;
+      }
+  grid_free(&g);
+  return MGO_OK;
+}
+
+/* Position along one axis after the recursive reordering: at every level,
+ * from the finest down, the nodal (even) indices of the level move to the
+ * front of the level's box keeping their order, and the coefficient (odd)
+ * indices follow them; the level-stop box ends up at the front. */
+static int64_t reordered_position(int64_t i, int64_t n, int L, int stop) {
+  int64_t j = i;     /* index within the current level box */
+  int64_t m = n;     /* size of the current level box */
+  for (int l = L; l > stop; l--) {
+    int64_t mc = (m + 1) / 2;
+    if (j & 1) return mc + (j - 1) / 2;
+    j /= 2;
+    m = mc;
+  }
+  return j;
+}
+
+int mgo_level_centric_index(int64_t *pos, int ndim, const int64_t *dims, int stop_level) {
+  grid_t g;
+  int st = grid_init(&g, ndim, dims, NULL);
+  if (st) return st;
+  if (stop_level < 0 || stop_level > g.L) { grid_free(&g); return MGO_ERR_LEVEL; }
+  size_t t = 0;
+  for (int64_t i0 = 0; i0 < g.n[0]; i0++)
+    for (int64_t i1 = 0; i1 < g.n[1]; i1++)
+      for (int64_t i2 = 0; i2 < g.n[2]; i2++, t++) {
+        int64_t p0 = g.real[0] ? reordered_position(i0, g.n[0], g.L, stop_level) : 0;
+        int64_t p1 = g.real[1] ? reordered_position(i1, g.n[1], g.L, stop_level) : 0;
+        int64_t p2 = g.real[2] ? reordered_position(i2, g.n[2], g.L, stop_level) : 0;
+        pos[t] = (p0 * g.n[1] + p1) * g.n[2] + p2;
+      }
+  grid_free(&g);
+  return MGO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* L-infinity constant and level tolerances (Sec. 4.1).                       */
+/* ------------------------------------------------------------------------ */
+
+/* The paper takes C_{L^inf} from a cited analysis and prints no value.  This
+ * oracle uses the rigorous per-level bound: a change delta of the level-l
+ * coefficients moves the reconstruction by at most
+ * (1 + prod_k ||Mc_k^{-1} R_k M_k||_inf) ||delta||_inf, and finer
+ * recomposition steps only interpolate it.  The 1-D operator is built column
+ * by column from unit vectors. */
+double mgo_axis_operator_norm(const double *X, int64_t m) {
+  int64_t mc = (m + 1) / 2;
+  double *A = (double *)calloc((size_t)(mc * m), sizeof(double)); /* A[J*m + j] */
+  double *e = (double *)calloc((size_t)m, sizeof(double));
+  double *col = (double *)malloc(sizeof(double) * (size_t)mc);
+  for (int64_t j = 0; j < m; j++) {
+    memset(e, 0, sizeof(double) * (size_t)m);
+    e[j] = 1.0;
+    mgo_project_line_1d(X, m, e, col);
+    for (int64_t J = 0; J < mc; J++) A[J * m + j] = col[J];
+  }
+  double best = 0.0;
+  for (int64_t J = 0; J < mc; J++) {
+    double s = 0.0;
+    for (int64_t j = 0; j < m; j++) s += fabs(A[J * m + j]);
+    if (s > best) best = s;
+  }
+  free(A);
+  free(e);
+  free(col);
+  return best;
+}
+
+double mgo_linf_constant(int ndim, const int64_t *dims, const double *const *coords,
+                         int stop_level) {
+  grid_t g;
+  if (grid_init(&g, ndim, dims, coords)) return -1.0;
+  if (stop_level < 0 || stop_level > g.L) { grid_free(&g); return -1.0; }
+  double C = 1.0;
+  for (int l = g.L; l > stop_level; l--) {
+    double prod = 1.0;
+    for (int k = 0; k < 3; k++) {
+      if (!g.real[k]) continue;
+      int64_t m = level_size(&g, k, l);
+      double *Xl = (double *)malloc(sizeof(double) * (size_t)m);
+      level_coords(&g, k, l, Xl);
+      prod *= mgo_axis_operator_norm(Xl, m);
+      free(Xl);
+    }
+    if (1.0 + prod > C) C = 1.0 + prod;
+  }
+  grid_free(&g);
+  return C;
+}
+
+/* Level tolerances of eq. (LinfTau) with the stop level of Algorithm 1:
+ * kappa = sqrt(2^d), tau_stop = (1-kappa)/(1-kappa^(L+1-stop)) * tau/C and
+ * tau_l = kappa tau_{l-1}.  Fixed operation order, no contraction. */
+int mgo_level_tolerances(int ndim, const int64_t *dims, const double *const *coords,
+                         double tol, int stop_level, double c_linf, double *tau) {
+  grid_t g;
+  int st = grid_init(&g, ndim, dims, coords);
+  if (st) return st;
+  int L = g.L;
+  grid_free(&g);
+  if (stop_level < 0 || stop_level > L) return MGO_ERR_LEVEL;
+  if (!(tol > 0.0) || !isfinite(tol)) return MGO_ERR_TOL;
+  double C = c_linf;
+  if (!(C > 0.0)) C = mgo_linf_constant(ndim, dims, coords, stop_level);
+  if (!(C >= 1.0) || !isfinite(C)) return MGO_ERR_TOL;
+  double kappa = sqrt((double)(1 << ndim));
+  double p = 1.0;
+  for (int i = 0; i < L + 1 - stop_level; i++) p = p * kappa;
+  tau[0] = ((1.0 - kappa) / (1.0 - p)) * (tol / C);
+  for (int l = 1; l <= L - stop_level; l++) tau[l] = tau[l - 1] * kappa;
+  return MGO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Level-wise quantization (Sec. 4.1, Algorithm 1 quantize step).             */
+/* Bins of width q_l = 2 tau_l anchored at zero; the reconstruction is the    */
+/* bin centre label * q_l, so |c - c~| <= q_l / 2 = tau_l.                    */
+/* ------------------------------------------------------------------------ */
+int mgo_quantize(const double *u_mc, int32_t *labels, int ndim, const int64_t *dims,
+                 const double *const *coords, double tol, int stop_level, double c_linf) {
+  int L = mgo_num_levels(ndim, dims);
+  if (L < 0) return -L;
+  if (stop_level < 0 || stop_level > L) return MGO_ERR_LEVEL;
+  double tau[64];
+  int st = mgo_level_tolerances(ndim, dims, coords, tol, stop_level, c_linf, tau);
+  if (st) return st;
+  size_t total = 1;
+  for (int k = 0; k < ndim; k++) total *= (size_t)dims[k];
+  int8_t *lev = (int8_t *)malloc(total);
+  if (!lev) return MGO_ERR_ALLOC;
+  mgo_level_map(lev, ndim, dims, stop_level);
+  int bad = 0;
+  for (size_t t = 0; t < total; t++) {
+    double q = 2.0 * tau[lev[t] - stop_level];
+    double x = u_mc[t] / q;
+    if (!isfinite(x) || fabs(x) >= 2147483647.0) { labels[t] = INT32_MIN; bad = 1; continue; }
+    labels[t] = (int32_t)rint(x);
+  }
+  free(lev);
+  return bad ? MGO_ERR_RANGE : MGO_OK;
+}
+
+int mgo_dequantize(const int32_t *labels, double *u_mc, int ndim, const int64_t *dims,
+                   const double *const *coords, double tol, int stop_level, double c_linf) {
+  int L = mgo_num_levels(ndim, dims);
+  if (L < 0) return -L;
+  if (stop_level < 0 || stop_level > L) return MGO_ERR_LEVEL;
+  double tau[64];
+  int st = mgo_level_tolerances(ndim, dims, coords, tol, stop_level, c_linf, tau);
+  if (st) return st;
+  size_t total = 1;
+  for (int k = 0; k < ndim; k++) total *= (size_t)dims[k];
+  int8_t *lev = (int8_t *)malloc(total);
+  if (!lev) return MGO_ERR_ALLOC;
+  mgo_level_map(lev, ndim, dims, stop_level);
+  for (size_t t = 0; t < total; t++) {
+    double q = 2.0 * tau[lev[t] - stop_level];
+    u_mc[t] = (double)labels[t] * q;
+  }
+  free(lev);
+  return MGO_OK;
+}
