@@ -463,22 +463,15 @@ int mgo_level_map(int8_t *lev, int ndim, const int64_t *dims, int stop_level) {
   return MGO_OK;
 }
 
-/* Position along one axis after the recursive reordering: at every level,
- * from the finest down, the nodal (even) indices of the level move to the
- * front of the level's box keeping their order, and the coefficient (odd)
- * indices follow them; the level-stop box ends up at the front. */
-static int64_t reordered_position(int64_t i, int64_t n, int L, int stop) {
-  int64_t j = i;     /* index within the current level box */
-  int64_t m = n;     /* size of the current level box */
-  for (int l = L; l > stop; l--) {
-    int64_t mc = (m + 1) / 2;
-    if (j & 1) return mc + (j - 1) / 2;
-    j /= 2;
-    m = mc;
-  }
-  return j;
-}
-
+/* Level-centric reordering of Sec. 5.1.  At every level l, from the finest
+ * down, the level-l grid (which sits in the corner box [0, m_l) on every
+ * axis) is reordered: along each axis its nodal (even) indices move to the
+ * front, keeping their order, and its coefficient (odd) indices follow.  The
+ * next level only reorders the nodal block (its own grid), so a level-l
+ * coefficient stays where the level-l reordering put it.  A node of N*_l
+ * with level indices j_k therefore lands at j_k/2 (even j_k) or
+ * c_k + (j_k-1)/2 (odd j_k) on each axis, c_k the level-(l-1) node count;
+ * a node of N_stop keeps its natural position in the stop-level box. */
 int mgo_level_centric_index(int64_t *pos, int ndim, const int64_t *dims, int stop_level) {
   grid_t g;
   int st = grid_init(&g, ndim, dims, NULL);
@@ -488,10 +481,25 @@ int mgo_level_centric_index(int64_t *pos, int ndim, const int64_t *dims, int sto
   for (int64_t i0 = 0; i0 < g.n[0]; i0++)
     for (int64_t i1 = 0; i1 < g.n[1]; i1++)
       for (int64_t i2 = 0; i2 < g.n[2]; i2++, t++) {
-        int64_t p0 = g.real[0] ? reordered_position(i0, g.n[0], g.L, stop_level) : 0;
-        int64_t p1 = g.real[1] ? reordered_position(i1, g.n[1], g.L, stop_level) : 0;
-        int64_t p2 = g.real[2] ? reordered_position(i2, g.n[2], g.L, stop_level) : 0;
-        pos[t] = (p0 * g.n[1] + p1) * g.n[2] + p2;
+        int64_t i[3] = {i0, i1, i2};
+        int lv = stop_level;
+        for (int k = 0; k < 3; k++)
+          if (g.real[k]) {
+            int a = axis_level(i[k], g.L, stop_level);
+            if (a > lv) lv = a;
+          }
+        int64_t s = (int64_t)1 << (g.L - lv);
+        int64_t p[3];
+        for (int k = 0; k < 3; k++) {
+          int64_t j = i[k] / s; /* level-lv index (the node is in N_lv) */
+          if (lv == stop_level) {
+            p[k] = j;
+          } else {
+            int64_t c = level_size(&g, k, lv - 1);
+            p[k] = (j & 1) ? c + (j - 1) / 2 : j / 2;
+          }
+        }
+        pos[t] = (p[0] * g.n[1] + p[1]) * g.n[2] + p[2];
       }
   grid_free(&g);
   return MGO_OK;

@@ -365,6 +365,25 @@ def test_level_centric_1d_example():
     assert pos1.tolist() == [0, 5, 1, 6, 2, 7, 3, 8, 4]
 
 
+def test_level_centric_only_reorders_the_nodal_block():
+    """Sec. 5.1: each level reorders its own grid; the coefficients of a level
+    stay where that level's reordering put them (9x9, two levels)."""
+    pos = oracle.level_centric_index((9, 9), 0)
+    def at(p):
+        return divmod(int(p), 9)
+    # level-2 coefficient in a nodal row (row 2 even, column 1 odd): row 2 -> 1,
+    # column 1 -> 5 + 0; the level-1 reordering does not move it again
+    assert at(pos[2, 1]) == (1, 5)
+    assert at(pos[1, 2]) == (5, 1)
+    assert at(pos[3, 3]) == (6, 6)
+    # level-1 coefficient (level-1 indices (1, 2)): rows/cols of the 5x5 level-1 box
+    assert at(pos[2, 4]) == (3, 1)
+    # coarsest grid N_0 = {0, 4, 8}^2 in natural order in the 3x3 corner
+    assert at(pos[4, 8]) == (1, 2)
+    # a permutation
+    assert sorted(pos.ravel().tolist()) == list(range(81))
+
+
 @pytest.mark.parametrize("shape,stop", [((17, 9, 33), 0), ((33, 33), 1), ((9, 9, 9), 2)])
 def test_level_centric_boxes(shape, stop):
     lev = oracle.level_map(shape, stop)
