@@ -1,0 +1,187 @@
+/*
+ * mgx — MGARD+ multilevel decomposition, recomposition and level-wise
+ * quantization on AMD Instinct MI355X (gfx950).  C ABI.
+ *
+ * The method is that of "MGARD+: Optimizing Multilevel Methods for
+ * Error-bounded Scientific Data Reduction" (arXiv 2010.05872).
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ * - Arrays are C order with shape dims[0] x ... x dims[ndim-1]; the last axis
+ *   is contiguous.  1 <= ndim <= 3.  Every dims[k] must be 2^m + 1 with
+ *   1 <= m <= 13 (3 <= n <= 8193).
+ * - The level count L = min_k m_k - 1: all axes coarsen together and the
+ *   coarsest grid N_0 has 3 nodes on the shortest axis.  Level l keeps every
+ *   2^(L-l)-th node of the input grid N_L (Sec. 2).
+ * - coords is NULL or an array of ndim host pointers; coords[k] is NULL
+ *   (meaning coordinates 0, 1, ..., dims[k]-1) or dims[k] finite, strictly
+ *   increasing doubles.  Coordinates are copied into a cached plan; the
+ *   caller may free them after the call returns.
+ * - stop_level l~ in [0, L]: levels L ... l~+1 are decomposed and Q_{l~} u is
+ *   kept (the stop level of Algorithm 1).
+ * - Device pointers (u, u_mc, labels, workspace) are caller-owned device
+ *   memory on the current HIP device; the library never frees them.  They
+ *   must be aligned to their element size.
+ * - Every call validates its arguments on the host before any launch.  A
+ *   non-MGX_OK status means nothing was enqueued.  Launches are asynchronous
+ *   on `stream`; errors reported by the HIP runtime at launch time become
+ *   MGX_ERR_HIP.  No call throws across the ABI.
+ * - The multilevel coefficients u_mc use the level-centric layout of Sec. 5.1:
+ *   along every axis, at every level from the finest down, the nodal (even)
+ *   indices of the level are moved to the front of the level's box and the
+ *   coefficient (odd) indices follow, both in increasing order.  So the box
+ *   [0, n_k^(l)) on every axis holds level l, its corner box
+ *   [0, n_k^(l-1)) holds level l-1, and the box of the stop level holds
+ *   Q_{l~} u in natural order.  u_mc has the same shape as u.
+ * - Calls that use the same workspace must not overlap; calls on different
+ *   streams with distinct workspaces may run concurrently.
+ */
+#ifndef MGX_H
+#define MGX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { MGX_F32 = 0, MGX_F64 = 1 } mgx_dtype;
+
+typedef enum {
+  MGX_OK = 0,
+  MGX_ERR_ARG = 1,       /* null pointer, in/out aliasing, bad enum value      */
+  MGX_ERR_SHAPE = 2,     /* ndim not in [1,3] or some dims[k] != 2^m+1, 1<=m<=13 */
+  MGX_ERR_COORDS = 3,    /* non-finite or not strictly increasing coordinates  */
+  MGX_ERR_LEVEL = 4,     /* stop_level outside [0, L]                          */
+  MGX_ERR_TOL = 5,       /* tolerance not positive and finite, or 0 < C < 1    */
+  MGX_ERR_RANGE = 6,     /* a quantization label overflowed int32 or a
+                            coefficient was not finite (quantize with stats)    */
+  MGX_ERR_WORKSPACE = 7, /* workspace NULL or smaller than mgx_workspace_size  */
+  MGX_ERR_HIP = 8        /* the HIP runtime reported an error                  */
+} mgx_status;
+
+#define MGX_MAX_LEVELS 16
+
+/* Per-call quantization statistics (filled by mgx_quantize when requested).
+ * Entry i of max_abs_label belongs to level first_level + i; labels of
+ * out-of-range coefficients are excluded from it. */
+typedef struct {
+  int32_t first_level;                   /* the stop level l~                   */
+  int32_t num_levels;                    /* L + 1 - l~                          */
+  int32_t max_abs_label[MGX_MAX_LEVELS]; /* max |label| per level              */
+  int64_t n_overflow;                    /* finite |c/q_l| >= 2^31 - 1         */
+  int64_t n_nonfinite;                   /* c/q_l not finite (NaN or Inf input) */
+} mgx_quant_stats;
+
+/* Human-readable name of a status code (static storage). */
+const char *mgx_status_string(mgx_status s);
+
+/* Finest level index L for this shape, or -MGX_ERR_SHAPE. */
+int mgx_num_levels(int ndim, const int64_t *dims);
+
+/* Workspace bytes needed by mgx_decompose / mgx_recompose for this shape,
+ * dtype and stop level (0 on invalid arguments).  About 0.3 N element sizes:
+ * two compact coarse boxes for the nodal values and one coarse load-vector
+ * box. */
+size_t mgx_workspace_size(mgx_dtype dtype, int ndim, const int64_t *dims, int stop_level);
+
+/* Multilevel decomposition (Sec. 2, decomposition steps 1-6, with the
+ * level-centric output layout of Sec. 5.1):
+ * for l = L ... l~+1, coefficients u_mc[N*_l] = ((I - Pi_{l-1}) Q_l u)(x),
+ * then Q_{l-1} u = Pi_{l-1} Q_l u + Q_{l-1}(I - Pi_{l-1}) Q_l u, where the
+ * correction is the L2 projection of the multilevel component (mass matrix
+ * apply, restriction, tridiagonal solve per axis).
+ *   u        in:  device, dims, dtype, natural order.  Not modified.
+ *   u_mc     out: device, dims, dtype, level-centric layout.  Must not
+ *                 overlap u.
+ *   workspace, workspace_bytes: device scratch of at least
+ *                 mgx_workspace_size(...) bytes, contents undefined after.
+ * Errors: MGX_ERR_ARG, _SHAPE, _COORDS, _LEVEL, _WORKSPACE, _HIP. */
+mgx_status mgx_decompose(const void *u, void *u_mc, mgx_dtype dtype, int ndim,
+                         const int64_t *dims, const double *const *coords, int stop_level,
+                         void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Multilevel recomposition (Sec. 2, recomposition steps 1-5): the exact
+ * inverse of mgx_decompose.  For l = l~+1 ... L: the correction computed
+ * from the level-l coefficients is subtracted from Q_{l-1} u, giving
+ * Pi_{l-1} Q_l u on N_{l-1}, and the interpolant is added back to the
+ * coefficients on N*_l.
+ *   u_mc     in:  device, level-centric layout.  Not modified.
+ *   u        out: device, natural order.  Must not overlap u_mc.
+ * Errors as mgx_decompose. */
+mgx_status mgx_recompose(const void *u_mc, void *u, mgx_dtype dtype, int ndim,
+                         const int64_t *dims, const double *const *coords, int stop_level,
+                         void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Level-wise quantization (Sec. 4.1, eq. (LinfTau); Algorithm 1, quantize
+ * step).  tau_l~ = (1-kappa)/(1-kappa^(L+1-l~)) * tol_linf / C and
+ * tau_l = kappa tau_{l-1} with kappa = sqrt(2^d), all in FP64 in that
+ * operation order; q_l = 2 tau_l.  Every coefficient c of level l (the
+ * level-l~ box counts as level l~) becomes label = rint(c / q_l), computed
+ * in FP64 with a correctly rounded division and ties to even, so that
+ * |c - label q_l| <= tau_l.
+ *   u_mc     in:  device, level-centric layout.
+ *   labels   out: device int32, dims.  A coefficient whose |c/q_l| >= 2^31-1
+ *                 or is not finite gets INT32_MIN.
+ *   tol_linf absolute L-infinity tolerance tau > 0.
+ *   c_linf   the constant C_{L^inf} (>= 1), or <= 0 for the library default
+ *            mgx_linf_constant(...).
+ *   stats    NULL: fully asynchronous, no reductions.  Non-NULL: the call
+ *            also reduces per-level max |label| and the overflow/non-finite
+ *            counts, waits for the stream, fills *stats and returns
+ *            MGX_ERR_RANGE when any label overflowed.
+ * Errors: MGX_ERR_ARG, _SHAPE, _COORDS, _LEVEL, _TOL, _RANGE, _HIP. */
+mgx_status mgx_quantize(const void *u_mc, int32_t *labels, mgx_dtype dtype, int ndim,
+                        const int64_t *dims, const double *const *coords, double tol_linf,
+                        int stop_level, double c_linf, mgx_quant_stats *stats,
+                        hipStream_t stream);
+
+/* Dequantization: c~ = (double)label * q_l, rounded to dtype (nearest).
+ *   labels   in:  device int32, level-centric positions.
+ *   u_mc     out: device, dtype.
+ * Errors: MGX_ERR_ARG, _SHAPE, _COORDS, _LEVEL, _TOL, _HIP. */
+mgx_status mgx_dequantize(const int32_t *labels, void *u_mc, mgx_dtype dtype, int ndim,
+                          const int64_t *dims, const double *const *coords, double tol_linf,
+                          int stop_level, double c_linf, hipStream_t stream);
+
+/* The default C_{L^inf} (Sec. 4.1, eq. (LInfNormEstimator)).  The paper cites
+ * its value without printing it; the library uses the rigorous bound
+ * max(1, max over levels l~ < l <= L of 1 + prod_k ||Mc_k^-1 R_k M_k||_inf),
+ * the per-level amplification of a coefficient error through recomposition.
+ * Host, synchronous.  Returns a negative value on invalid arguments. */
+double mgx_linf_constant(int ndim, const int64_t *dims, const double *const *coords,
+                         int stop_level);
+
+/* tau_out[0 .. L-l~] = tolerances of levels l~ ... L as used by
+ * mgx_quantize.  Host, synchronous. */
+mgx_status mgx_level_tolerances(int ndim, const int64_t *dims, const double *const *coords,
+                                double tol_linf, int stop_level, double c_linf,
+                                double *tau_out);
+
+/* Kernel tracing.  While enabled, every kernel this library launches is
+ * bracketed by two HIP events recorded on the stream it is launched on, and
+ * mgx_trace_read reports the summed durations per (kernel, level).  Meant
+ * for measurement: the events cost a few microseconds per launch.  Tracing
+ * state is process-wide; enable/read are not meant to race with launches
+ * from other host threads. */
+typedef struct {
+  char name[40];     /* e.g. "load_vector_dec", "solve_contig"             */
+  int32_t level;     /* level l being decomposed/recomposed, -1 if none  */
+  int32_t count;     /* launches recorded                               */
+  double total_ms;   /* summed event-to-event time                      */
+} mgx_kernel_time;
+
+/* on != 0 starts recording (and clears earlier records); 0 stops. */
+mgx_status mgx_trace_enable(int on);
+/* Waits for the recorded events, writes up to max aggregated entries to
+ * out (host), clears the records and returns the number of entries, or -1
+ * on a HIP error. */
+int mgx_trace_read(mgx_kernel_time *out, int max);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MGX_H */

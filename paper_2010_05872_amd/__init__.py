@@ -1,0 +1,287 @@
+"""mgx: MGARD+ multilevel decomposition on MI355X — Python binding of libmgx.
+
+Thin ctypes layer over the C ABI of ``include/mgx.h``: it marshals torch
+tensors (device memory) and the current HIP stream into the C calls and
+raises ``MgxError`` on a non-zero status.  Every step of the computation runs
+in the HIP kernels of ``libmgx.so``; there is no Python or CPU fallback, and
+importing the compute functions fails loudly when the library is not built.
+
+Method: "MGARD+: Optimizing Multilevel Methods for Error-bounded Scientific
+Data Reduction" (arXiv 2010.05872).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmgx.so")
+
+MGX_F32, MGX_F64 = 0, 1
+MAX_LEVELS = 16
+
+STATUS = {
+    0: "MGX_OK", 1: "MGX_ERR_ARG", 2: "MGX_ERR_SHAPE", 3: "MGX_ERR_COORDS", 4: "MGX_ERR_LEVEL",
+    5: "MGX_ERR_TOL", 6: "MGX_ERR_RANGE", 7: "MGX_ERR_WORKSPACE", 8: "MGX_ERR_HIP",
+}
+
+
+class MgxError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        msg = lib().mgx_status_string(code).decode() if _lib is not None else ""
+        super().__init__(f"{what}: {STATUS.get(code, code)} ({msg})")
+        self.code = code
+
+
+class QuantStats(ctypes.Structure):
+    _fields_ = [
+        ("first_level", ctypes.c_int32),
+        ("num_levels", ctypes.c_int32),
+        ("max_abs_label", ctypes.c_int32 * MAX_LEVELS),
+        ("n_overflow", ctypes.c_int64),
+        ("n_nonfinite", ctypes.c_int64),
+    ]
+
+    def as_dict(self):
+        return {
+            "first_level": self.first_level,
+            "num_levels": self.num_levels,
+            "max_abs_label": list(self.max_abs_label[: self.num_levels]),
+            "n_overflow": self.n_overflow,
+            "n_nonfinite": self.n_nonfinite,
+        }
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [
+        ("name", ctypes.c_char * 40),
+        ("level", ctypes.c_int32),
+        ("count", ctypes.c_int32),
+        ("total_ms", ctypes.c_double),
+    ]
+
+
+# Every symbol declared in include/mgx.h.
+EXPORTS = (
+    "mgx_status_string", "mgx_num_levels", "mgx_workspace_size", "mgx_decompose", "mgx_recompose",
+    "mgx_quantize", "mgx_dequantize", "mgx_linf_constant", "mgx_level_tolerances",
+    "mgx_trace_enable", "mgx_trace_read",
+)
+
+_lib = None
+
+
+def lib():
+    """Load libmgx.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2010_05872_amd/build.py "
+                              "(or __graft_entry__.build()); there is no fallback path")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64p, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
+        ci, cd, sz = ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+        L.mgx_status_string.argtypes = [ci]
+        L.mgx_status_string.restype = ctypes.c_char_p
+        L.mgx_num_levels.argtypes = [ci, i64p]
+        L.mgx_num_levels.restype = ci
+        L.mgx_workspace_size.argtypes = [ci, ci, i64p, ci]
+        L.mgx_workspace_size.restype = sz
+        for name in ("mgx_decompose", "mgx_recompose"):
+            f = getattr(L, name)
+            f.argtypes = [vp, vp, ci, ci, i64p, vp, ci, vp, sz, vp]
+            f.restype = ci
+        L.mgx_quantize.argtypes = [vp, vp, ci, ci, i64p, vp, cd, ci, cd, ctypes.POINTER(QuantStats), vp]
+        L.mgx_quantize.restype = ci
+        L.mgx_dequantize.argtypes = [vp, vp, ci, ci, i64p, vp, cd, ci, cd, vp]
+        L.mgx_dequantize.restype = ci
+        L.mgx_linf_constant.argtypes = [ci, i64p, vp, ci]
+        L.mgx_linf_constant.restype = cd
+        L.mgx_level_tolerances.argtypes = [ci, i64p, vp, cd, ci, cd, dp]
+        L.mgx_level_tolerances.restype = ci
+        L.mgx_trace_enable.argtypes = [ci]
+        L.mgx_trace_enable.restype = ci
+        L.mgx_trace_read.argtypes = [ctypes.POINTER(KernelTime), ci]
+        L.mgx_trace_read.restype = ci
+        _lib = L
+    return _lib
+
+
+def _dims(shape):
+    return (ctypes.c_int64 * len(shape))(*[int(s) for s in shape])
+
+
+class Coords:
+    """Per-axis coordinate arrays as the ``const double *const *`` of the C ABI."""
+
+    def __init__(self, shape, coords):
+        self._keep = []
+        self.ptr = None
+        if coords is None:
+            return
+        if len(coords) != len(shape):
+            raise ValueError("coords needs one entry (array or None) per axis")
+        arr = (ctypes.c_void_p * len(shape))()
+        for k, c in enumerate(coords):
+            if c is None:
+                arr[k] = None
+                continue
+            a = np.ascontiguousarray(np.asarray(c, dtype=np.float64))
+            if a.shape != (int(shape[k]),):
+                raise ValueError(f"coords[{k}] must have {shape[k]} entries")
+            self._keep.append(a)
+            arr[k] = a.ctypes.data
+        self._keep.append(arr)
+        self.ptr = ctypes.cast(arr, ctypes.c_void_p)
+
+
+def _check(code, what):
+    if code != 0:
+        raise MgxError(code, what)
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.float32:
+        return MGX_F32
+    if t.dtype == torch.float64:
+        return MGX_F64
+    raise TypeError(f"unsupported dtype {t.dtype}; float32 and float64 are supported")
+
+
+def _stream(device):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check_tensor(t, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor (no CPU path)")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+# ---------------------------------------------------------------- host utilities
+def num_levels(shape) -> int:
+    r = lib().mgx_num_levels(len(shape), _dims(shape))
+    if r < 0:
+        raise MgxError(-r, "mgx_num_levels")
+    return r
+
+
+def workspace_size(dtype_code: int, shape, stop_level: int = 0) -> int:
+    return int(lib().mgx_workspace_size(dtype_code, len(shape), _dims(shape), int(stop_level)))
+
+
+def linf_constant(shape, coords=None, stop_level=0) -> float:
+    c = Coords(shape, coords)
+    r = lib().mgx_linf_constant(len(shape), _dims(shape), c.ptr, int(stop_level))
+    if r < 0:
+        raise MgxError(1, "mgx_linf_constant")
+    return r
+
+
+def level_tolerances(shape, tol, coords=None, stop_level=0, c_linf=0.0) -> np.ndarray:
+    L = num_levels(shape)
+    tau = np.zeros(L + 1 - int(stop_level), dtype=np.float64)
+    c = Coords(shape, coords)
+    code = lib().mgx_level_tolerances(len(shape), _dims(shape), c.ptr, float(tol), int(stop_level),
+                                      float(c_linf), tau.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    _check(code, "mgx_level_tolerances")
+    return tau
+
+
+def trace_enable(on: bool = True) -> None:
+    """Bracket every library kernel launch with HIP events on its stream."""
+    _check(lib().mgx_trace_enable(1 if on else 0), "mgx_trace_enable")
+
+
+def trace_read(max_entries: int = 512):
+    """Aggregated kernel times since the last read: list of dicts
+    {name, level, count, total_ms}; waits for the recorded events."""
+    buf = (KernelTime * max_entries)()
+    n = lib().mgx_trace_read(buf, max_entries)
+    if n < 0:
+        raise MgxError(8, "mgx_trace_read")
+    return [{"name": buf[i].name.decode(), "level": buf[i].level, "count": buf[i].count,
+             "total_ms": buf[i].total_ms} for i in range(n)]
+
+
+# ---------------------------------------------------------------- device entry points
+def _workspace(t, stop_level, workspace):
+    import torch
+    need = workspace_size(_dtype_code(t), t.shape, stop_level)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=t.device)
+    return workspace, need
+
+
+def decompose(u, coords=None, stop_level=0, out=None, workspace=None):
+    """u (natural order) -> u_mc (level-centric layout), on the current stream."""
+    import torch
+    _check_tensor(u, "u")
+    if out is None:
+        out = torch.empty_like(u)
+    _check_tensor(out, "out")
+    ws, _ = _workspace(u, stop_level, workspace)
+    c = Coords(u.shape, coords)
+    code = lib().mgx_decompose(u.data_ptr(), out.data_ptr(), _dtype_code(u), u.dim(), _dims(u.shape), c.ptr,
+                               int(stop_level), ws.data_ptr(), ws.numel() * ws.element_size(), _stream(u.device))
+    _check(code, "mgx_decompose")
+    return out
+
+
+def recompose(u_mc, coords=None, stop_level=0, out=None, workspace=None):
+    """u_mc (level-centric layout) -> u (natural order), on the current stream."""
+    import torch
+    _check_tensor(u_mc, "u_mc")
+    if out is None:
+        out = torch.empty_like(u_mc)
+    _check_tensor(out, "out")
+    ws, _ = _workspace(u_mc, stop_level, workspace)
+    c = Coords(u_mc.shape, coords)
+    code = lib().mgx_recompose(u_mc.data_ptr(), out.data_ptr(), _dtype_code(u_mc), u_mc.dim(), _dims(u_mc.shape),
+                               c.ptr, int(stop_level), ws.data_ptr(), ws.numel() * ws.element_size(),
+                               _stream(u_mc.device))
+    _check(code, "mgx_recompose")
+    return out
+
+
+def quantize(u_mc, tol, coords=None, stop_level=0, c_linf=0.0, out=None, stats=False):
+    """Level-wise labels (int32).  With stats=True returns (labels, stats dict) and
+    raises MgxError(MGX_ERR_RANGE) if any label overflowed."""
+    import torch
+    _check_tensor(u_mc, "u_mc")
+    if out is None:
+        out = torch.empty(u_mc.shape, dtype=torch.int32, device=u_mc.device)
+    _check_tensor(out, "labels")
+    c = Coords(u_mc.shape, coords)
+    st = QuantStats() if stats else None
+    code = lib().mgx_quantize(u_mc.data_ptr(), out.data_ptr(), _dtype_code(u_mc), u_mc.dim(), _dims(u_mc.shape),
+                              c.ptr, float(tol), int(stop_level), float(c_linf),
+                              ctypes.byref(st) if st is not None else None, _stream(u_mc.device))
+    if stats:
+        if code not in (0, 6):
+            _check(code, "mgx_quantize")
+        return out, st.as_dict(), code
+    _check(code, "mgx_quantize")
+    return out
+
+
+def dequantize(labels, tol, dtype, coords=None, stop_level=0, c_linf=0.0, out=None):
+    """Labels -> coefficients of `dtype` (level-centric layout)."""
+    import torch
+    _check_tensor(labels, "labels")
+    if labels.dtype != torch.int32:
+        raise TypeError("labels must be int32")
+    if out is None:
+        out = torch.empty(labels.shape, dtype=dtype, device=labels.device)
+    _check_tensor(out, "out")
+    c = Coords(labels.shape, coords)
+    code = lib().mgx_dequantize(labels.data_ptr(), out.data_ptr(), _dtype_code(out), labels.dim(),
+                                _dims(labels.shape), c.ptr, float(tol), int(stop_level), float(c_linf),
+                                _stream(labels.device))
+    _check(code, "mgx_dequantize")
+    return out

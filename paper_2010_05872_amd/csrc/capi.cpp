@@ -1,0 +1,573 @@
+// C ABI of libmgx (include/mgx.h): argument validation, workspace layout and
+// the per-level launch sequences of decomposition and recomposition.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "kernels.hpp"
+#include "mgx.h"
+#include "plan.hpp"
+
+namespace mgx {
+namespace {
+
+size_t elem_size(mgx_dtype d) { return d == MGX_F64 ? 8 : 4; }
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int64_t round4(int64_t v) { return (v + 3) / 4 * 4; }
+
+struct Layout {
+  size_t offA = 0, offB = 0, offF = 0, total = 0;
+};
+
+// Two compact coarse boxes (levels L-1 and L-2) for nodal values and one
+// coarse box with padded rows for the load vector.
+Layout layout(const int64_t n[3], const bool real[3], int L, int stop, size_t es) {
+  Layout w;
+  if (stop >= L) return w;
+  int64_t cA = 1, cB = 1, cF = 1;
+  for (int k = 0; k < 3; k++) {
+    int64_t a = real[k] ? (n[k] - 1) / 2 + 1 : 1;
+    int64_t b = real[k] ? (n[k] - 1) / 4 + 1 : 1;
+    cA *= a;
+    cB *= b;
+    cF *= (k == 2) ? round4(a) : a;
+  }
+  size_t off = 0;
+  w.offA = off;
+  off = align_up(off + (size_t)cA * es, 256);
+  w.offB = off;
+  if (L - stop >= 2) off = align_up(off + (size_t)cB * es, 256);
+  w.offF = off;
+  off = align_up(off + (size_t)cF * es, 256);
+  w.total = off;
+  return w;
+}
+
+bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
+  const char *x = (const char *)a, *y = (const char *)b;
+  return x < y + nb && y < x + na;
+}
+
+mgx_status hip_status(hipError_t e) { return e == hipSuccess ? MGX_OK : MGX_ERR_HIP; }
+
+// ---- kernel tracing (mgx_trace_enable / mgx_trace_read) ----
+struct TraceRec {
+  const char *name;
+  int level;
+  hipEvent_t a, b;
+};
+struct Tracer {
+  std::mutex mu;
+  bool on = false;
+  std::vector<TraceRec> recs;
+  std::vector<hipEvent_t> pool;
+};
+Tracer &tracer() {
+  static Tracer *t = new Tracer();
+  return *t;
+}
+hipEvent_t take_event(Tracer &t) {
+  if (!t.pool.empty()) {
+    hipEvent_t e = t.pool.back();
+    t.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+// Runs launch() bracketed by events on st when tracing is on.
+template <class F>
+hipError_t traced(const char *name, int level, hipStream_t st, F &&launch) {
+  Tracer &t = tracer();
+  if (!t.on) return launch();
+  std::lock_guard<std::mutex> g(t.mu);
+  hipEvent_t a = take_event(t), b = take_event(t);
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, st);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b, st);
+  t.recs.push_back({name, level, a, b});
+  return e;
+}
+
+template <typename T>
+AxisTab<T> axis_tab(const Plan *P, int l, int k, const T *tab) {
+  const AxisLevel &a = P->ax[l][k];
+  AxisTab<T> t;
+  t.wl = tab + a.off_wl;
+  t.wr = tab + a.off_wr;
+  t.w5 = tab + a.off_w5;
+  t.mult = tab + a.off_mult;
+  t.invd = tab + a.off_invd;
+  t.qsup = tab + a.off_qsup;
+  t.m = (int)a.m;
+  t.c = (int)a.c;
+  return t;
+}
+
+// The three coarse solves of one level on F (c0 x c1 x c2, pitches fp0,fp1),
+// the last one applying out = in + sign * correction.
+template <typename T>
+hipError_t solve_and_apply(int level, const AxisTab<T> ax[3], const bool real[3], T *F, int64_t fp0,
+                           int64_t fp1, const T *in, int64_t ip0, int64_t ip1, T *out, int64_t op0, int64_t op1,
+                           T sign, hipStream_t st) {
+  const int c0 = ax[0].c, c1 = ax[1].c, c2 = ax[2].c;
+  hipError_t e;
+  // contiguous axis (always real)
+  {
+    SolveArgs<T> s{F, (int64_t)c0 * c1, fp1, c2, ax[2].mult, ax[2].invd, ax[2].qsup};
+    if ((e = traced("solve_contig", level, st, [&] { return launch_solve_contig<T>(s, st); })) != hipSuccess)
+      return e;
+  }
+  if (!real[1]) {  // 1-D: apply the solved row
+    StridedArgs<T> s{};
+    s.F = F;
+    s.nx = c2;
+    s.in = in;
+    s.out = out;
+    s.sign = sign;
+    return traced("apply", level, st, [&] { return launch_apply<T>(s, st); });
+  }
+  {
+    StridedArgs<T> s{};
+    s.F = F;
+    s.c = c1;
+    s.sj = fp1;
+    s.nx = c2;
+    s.so = fp0;
+    s.nouter = c0;
+    s.mult = ax[1].mult;
+    s.invd = ax[1].invd;
+    s.qsup = ax[1].qsup;
+    const bool apply = !real[0];
+    if (apply) {  // 2-D: line index Y, outer Z (= 0)
+      s.in = in;
+      s.ij = ip1;
+      s.io = ip0;
+      s.out = out;
+      s.oj = op1;
+      s.oo = op0;
+      s.sign = sign;
+    }
+    e = traced(apply ? "solve_strided_apply" : "solve_strided", level, st,
+               [&] { return launch_solve_strided<T>(s, apply, st); });
+    if (e != hipSuccess) return e;
+    if (apply) return hipSuccess;
+  }
+  StridedArgs<T> s{};
+  s.F = F;
+  s.c = c0;
+  s.sj = fp0;
+  s.nx = c2;
+  s.so = fp1;
+  s.nouter = c1;
+  s.mult = ax[0].mult;
+  s.invd = ax[0].invd;
+  s.qsup = ax[0].qsup;
+  s.in = in;
+  s.ij = ip0;
+  s.io = ip1;
+  s.out = out;
+  s.oj = op0;
+  s.oo = op1;
+  s.sign = sign;
+  return traced("solve_strided_apply", level, st, [&] { return launch_solve_strided<T>(s, true, st); });
+}
+
+template <typename T>
+mgx_status run_decompose(Plan *P, int stop, const T *u, T *umc, char *ws, const Layout &lay, const T *tab,
+                         hipStream_t st) {
+  const int L = P->L;
+  const int64_t n1 = P->n[1], n2 = P->n[2];
+  const int64_t up0 = n1 * n2, up1 = n2;
+  if (stop == L) return hip_status(hipMemcpyAsync(umc, u, sizeof(T) * P->n[0] * up0, hipMemcpyDeviceToDevice, st));
+  T *A = (T *)(ws + lay.offA), *B = (T *)(ws + lay.offB), *F = (T *)(ws + lay.offF);
+  const T *src = u;
+  int64_t sp0 = up0, sp1 = up1;
+  for (int l = L; l > stop; l--) {
+    AxisTab<T> ax[3] = {axis_tab(P, l, 0, tab), axis_tab(P, l, 1, tab), axis_tab(P, l, 2, tab)};
+    const int c1 = ax[1].c, c2 = ax[2].c;
+    T *dst = ((L - 1 - (l - 1)) % 2 == 0) ? A : B;  // holds level l-1
+    const int64_t cp1 = c2, cp0 = (int64_t)c1 * c2;
+    const int64_t fp1 = round4(c2), fp0 = (int64_t)c1 * fp1;
+    StencilArgs<T> s{};
+    for (int k = 0; k < 3; k++) s.ax[k] = ax[k];
+    s.V = src;
+    s.vp0 = sp0;
+    s.vp1 = sp1;
+    s.umc_w = umc;
+    s.up0 = up0;
+    s.up1 = up1;
+    s.Vc = dst;
+    s.cp0 = cp0;
+    s.cp1 = cp1;
+    s.F = F;
+    s.fp0 = fp0;
+    s.fp1 = fp1;
+    hipError_t e = traced("load_vector_dec", l, st, [&] { return launch_load_vector<T>(s, true, st); });
+    if (e != hipSuccess) return MGX_ERR_HIP;
+    const bool last = (l == stop + 1);
+    T *out = last ? umc : dst;
+    const int64_t op0 = last ? up0 : cp0, op1 = last ? up1 : cp1;
+    e = solve_and_apply<T>(l, ax, P->real, F, fp0, fp1, dst, cp0, cp1, out, op0, op1, T(1), st);
+    if (e != hipSuccess) return MGX_ERR_HIP;
+    src = dst;
+    sp0 = cp0;
+    sp1 = cp1;
+  }
+  return MGX_OK;
+}
+
+template <typename T>
+mgx_status run_recompose(Plan *P, int stop, const T *umc, T *u, char *ws, const Layout &lay, const T *tab,
+                         hipStream_t st) {
+  const int L = P->L;
+  const int64_t n1 = P->n[1], n2 = P->n[2];
+  const int64_t up0 = n1 * n2, up1 = n2;
+  if (stop == L) return hip_status(hipMemcpyAsync(u, umc, sizeof(T) * P->n[0] * up0, hipMemcpyDeviceToDevice, st));
+  T *A = (T *)(ws + lay.offA), *B = (T *)(ws + lay.offB), *F = (T *)(ws + lay.offF);
+  for (int l = stop + 1; l <= L; l++) {
+    AxisTab<T> ax[3] = {axis_tab(P, l, 0, tab), axis_tab(P, l, 1, tab), axis_tab(P, l, 2, tab)};
+    const int c1 = ax[1].c, c2 = ax[2].c;
+    const int m1 = ax[1].m, m2 = ax[2].m;
+    T *nb = ((L - 1 - (l - 1)) % 2 == 0) ? A : B;  // level l-1 nodal values
+    const int64_t cp1 = c2, cp0 = (int64_t)c1 * c2;
+    const int64_t fp1 = round4(c2), fp0 = (int64_t)c1 * fp1;
+    const bool first = (l == stop + 1);
+    const T *nin = first ? umc : nb;
+    const int64_t ip0 = first ? up0 : cp0, ip1 = first ? up1 : cp1;
+    StencilArgs<T> s{};
+    for (int k = 0; k < 3; k++) s.ax[k] = ax[k];
+    s.umc_r = umc;
+    s.up0 = up0;
+    s.up1 = up1;
+    s.F = F;
+    s.fp0 = fp0;
+    s.fp1 = fp1;
+    hipError_t e = traced("load_vector_rec", l, st, [&] { return launch_load_vector<T>(s, false, st); });
+    if (e != hipSuccess) return MGX_ERR_HIP;
+    e = solve_and_apply<T>(l, ax, P->real, F, fp0, fp1, nin, ip0, ip1, nb, cp0, cp1, T(-1), st);
+    if (e != hipSuccess) return MGX_ERR_HIP;
+    InterpArgs<T> ia{};
+    for (int k = 0; k < 3; k++) ia.ax[k] = ax[k];
+    ia.nodal = nb;
+    ia.np0 = cp0;
+    ia.np1 = cp1;
+    ia.umc = umc;
+    ia.up0 = up0;
+    ia.up1 = up1;
+    if (l == L) {
+      ia.out = u;
+      ia.op0 = up0;
+      ia.op1 = up1;
+    } else {
+      ia.out = ((L - 1 - l) % 2 == 0) ? A : B;
+      ia.op1 = m2;
+      ia.op0 = (int64_t)m1 * m2;
+    }
+    e = traced("interp_add", l, st, [&] { return launch_interp_add<T>(ia, st); });
+    if (e != hipSuccess) return MGX_ERR_HIP;
+  }
+  return MGX_OK;
+}
+
+// Common validation of decompose / recompose.
+mgx_status prepare(const void *in, void *out, mgx_dtype dtype, int ndim, const int64_t *dims,
+                   const double *const *coords, int stop, void *ws, size_t ws_bytes, Plan **plan,
+                   Layout *lay, const void **tab) {
+  if (dtype != MGX_F32 && dtype != MGX_F64) return MGX_ERR_ARG;
+  int64_t n[3];
+  bool real[3];
+  int L;
+  int st = parse_shape(ndim, dims, n, real, &L);
+  if (st) return (mgx_status)st;
+  if (!in || !out) return MGX_ERR_ARG;
+  const size_t es = elem_size(dtype);
+  const size_t bytes = (size_t)(n[0] * n[1] * n[2]) * es;
+  if (overlaps(in, bytes, out, bytes)) return MGX_ERR_ARG;
+  Plan *P = get_plan(ndim, dims, coords, &st);
+  if (!P) return (mgx_status)st;
+  if (stop < 0 || stop > L) return MGX_ERR_LEVEL;
+  *lay = layout(n, real, L, stop, es);
+  if (lay->total > 0) {
+    if (!ws || ws_bytes < lay->total) return MGX_ERR_WORKSPACE;
+    if (overlaps(ws, lay->total, in, bytes) || overlaps(ws, lay->total, out, bytes)) return MGX_ERR_ARG;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MGX_ERR_HIP;
+  int herr = 0;
+  *tab = P->device_tables(dev, dtype == MGX_F64, &herr);
+  if (!*tab) return MGX_ERR_HIP;
+  *plan = P;
+  return MGX_OK;
+}
+
+// Level tolerances of Sec. 4.1, eq. (LinfTau) with the stop level of
+// Algorithm 1, in a fixed FP64 operation order.
+mgx_status tolerances(Plan *P, int ndim, double tol, int stop, double c_linf, double *tau) {
+  if (!(tol > 0.0) || !std::isfinite(tol)) return MGX_ERR_TOL;
+  if (std::isnan(c_linf) || std::isinf(c_linf)) return MGX_ERR_TOL;
+  double C = c_linf > 0.0 ? c_linf : P->linf_constant(stop);
+  if (!(C >= 1.0)) return MGX_ERR_TOL;
+  const int L = P->L;
+  volatile double kappa = std::sqrt((double)(1 << ndim));
+  double p = 1.0;
+  for (int i = 0; i < L + 1 - stop; i++) p = p * kappa;
+  double t = ((1.0 - kappa) / (1.0 - p)) * (tol / C);
+  tau[0] = t;
+  for (int l = 1; l <= L - stop; l++) tau[l] = tau[l - 1] * kappa;
+  return MGX_OK;
+}
+
+mgx_status quant_args(int ndim, const int64_t *dims, const double *const *coords, double tol, int stop,
+                      double c_linf, QuantArgs *qa, Plan **plan) {
+  int st = 0;
+  Plan *P = get_plan(ndim, dims, coords, &st);
+  if (!P) return (mgx_status)st;
+  if (stop < 0 || stop > P->L) return MGX_ERR_LEVEL;
+  double tau[kMaxLevels];
+  mgx_status s = tolerances(P, ndim, tol, stop, c_linf, tau);
+  if (s) return s;
+  const int L = P->L;
+  std::memset(qa, 0, sizeof(*qa));
+  qa->nrows = P->n[0] * P->n[1];
+  qa->n1 = (int)P->n[1];
+  qa->n2 = (int)P->n[2];
+  qa->first = stop;
+  qa->nlev = L + 1 - stop;
+  for (int k = 0; k < 3; k++)
+    for (int i = 0; i < qa->nlev; i++) {
+      int l = stop + i;
+      qa->sizes[k][i] = P->real[k] ? (int)((P->n[k] - 1) / ((int64_t)1 << (L - l)) + 1) : 1;
+    }
+  for (int i = 0; i < qa->nlev; i++) qa->q[i] = 2.0 * tau[i];
+  *plan = P;
+  return MGX_OK;
+}
+
+struct StatsBuf {
+  std::mutex mu;
+  std::vector<void *> per_dev;
+};
+StatsBuf &stats_buf() {
+  static StatsBuf *s = new StatsBuf();
+  return *s;
+}
+
+}  // namespace
+}  // namespace mgx
+
+using namespace mgx;
+
+extern "C" {
+
+const char *mgx_status_string(mgx_status s) {
+  switch (s) {
+    case MGX_OK: return "ok";
+    case MGX_ERR_ARG: return "invalid argument";
+    case MGX_ERR_SHAPE: return "invalid shape (ndim 1..3, each dim 2^m+1 with 1<=m<=13)";
+    case MGX_ERR_COORDS: return "coordinates not finite or not strictly increasing";
+    case MGX_ERR_LEVEL: return "stop level out of range";
+    case MGX_ERR_TOL: return "invalid tolerance or L-infinity constant";
+    case MGX_ERR_RANGE: return "quantization label out of int32 range or non-finite coefficient";
+    case MGX_ERR_WORKSPACE: return "workspace missing or too small";
+    case MGX_ERR_HIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+int mgx_num_levels(int ndim, const int64_t *dims) {
+  int64_t n[3];
+  bool real[3];
+  int L;
+  int st = parse_shape(ndim, dims, n, real, &L);
+  return st ? -st : L;
+}
+
+size_t mgx_workspace_size(mgx_dtype dtype, int ndim, const int64_t *dims, int stop_level) {
+  if (dtype != MGX_F32 && dtype != MGX_F64) return 0;
+  int64_t n[3];
+  bool real[3];
+  int L;
+  if (parse_shape(ndim, dims, n, real, &L)) return 0;
+  if (stop_level < 0 || stop_level > L) return 0;
+  return layout(n, real, L, stop_level, elem_size(dtype)).total;
+}
+
+mgx_status mgx_decompose(const void *u, void *u_mc, mgx_dtype dtype, int ndim, const int64_t *dims,
+                         const double *const *coords, int stop_level, void *workspace, size_t workspace_bytes,
+                         hipStream_t stream) {
+  Plan *P;
+  Layout lay;
+  const void *tab;
+  mgx_status s = prepare(u, u_mc, dtype, ndim, dims, coords, stop_level, workspace, workspace_bytes, &P, &lay, &tab);
+  if (s) return s;
+  if (dtype == MGX_F32)
+    return run_decompose<float>(P, stop_level, (const float *)u, (float *)u_mc, (char *)workspace, lay,
+                                (const float *)tab, stream);
+  return run_decompose<double>(P, stop_level, (const double *)u, (double *)u_mc, (char *)workspace, lay,
+                               (const double *)tab, stream);
+}
+
+mgx_status mgx_recompose(const void *u_mc, void *u, mgx_dtype dtype, int ndim, const int64_t *dims,
+                         const double *const *coords, int stop_level, void *workspace, size_t workspace_bytes,
+                         hipStream_t stream) {
+  Plan *P;
+  Layout lay;
+  const void *tab;
+  mgx_status s = prepare(u_mc, u, dtype, ndim, dims, coords, stop_level, workspace, workspace_bytes, &P, &lay, &tab);
+  if (s) return s;
+  if (dtype == MGX_F32)
+    return run_recompose<float>(P, stop_level, (const float *)u_mc, (float *)u, (char *)workspace, lay,
+                                (const float *)tab, stream);
+  return run_recompose<double>(P, stop_level, (const double *)u_mc, (double *)u, (char *)workspace, lay,
+                               (const double *)tab, stream);
+}
+
+mgx_status mgx_quantize(const void *u_mc, int32_t *labels, mgx_dtype dtype, int ndim, const int64_t *dims,
+                        const double *const *coords, double tol_linf, int stop_level, double c_linf,
+                        mgx_quant_stats *stats, hipStream_t stream) {
+  if (dtype != MGX_F32 && dtype != MGX_F64) return MGX_ERR_ARG;
+  int64_t n[3];
+  bool real[3];
+  int L;
+  int st = parse_shape(ndim, dims, n, real, &L);
+  if (st) return (mgx_status)st;
+  if (!u_mc || !labels) return MGX_ERR_ARG;
+  const size_t cnt = (size_t)(n[0] * n[1] * n[2]);
+  if (overlaps(u_mc, cnt * elem_size(dtype), labels, cnt * 4)) return MGX_ERR_ARG;
+  QuantArgs qa;
+  Plan *P;
+  mgx_status s = quant_args(ndim, dims, coords, tol_linf, stop_level, c_linf, &qa, &P);
+  if (s) return s;
+  if (!stats) {
+    hipError_t e = traced("quantize", -1, stream, [&] {
+      return dtype == MGX_F32 ? launch_quantize<float>((const float *)u_mc, labels, qa, false, stream)
+                              : launch_quantize<double>((const double *)u_mc, labels, qa, false, stream);
+    });
+    return hip_status(e);
+  }
+  StatsBuf &sb = stats_buf();
+  std::lock_guard<std::mutex> g(sb.mu);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MGX_ERR_HIP;
+  if ((int)sb.per_dev.size() <= dev) sb.per_dev.resize(dev + 1, nullptr);
+  const size_t sbytes = sizeof(int) * kMaxLevels + 2 * sizeof(unsigned long long);
+  if (!sb.per_dev[dev] && hipMalloc(&sb.per_dev[dev], sbytes) != hipSuccess) return MGX_ERR_HIP;
+  char *base = (char *)sb.per_dev[dev];
+  qa.stats_max = (int *)base;
+  qa.stats_ovf = (unsigned long long *)(base + sizeof(int) * kMaxLevels);
+  qa.stats_nan = qa.stats_ovf + 1;
+  if (hipMemsetAsync(base, 0, sbytes, stream) != hipSuccess) return MGX_ERR_HIP;
+  hipError_t e = traced("quantize_stats", -1, stream, [&] {
+    return dtype == MGX_F32 ? launch_quantize<float>((const float *)u_mc, labels, qa, true, stream)
+                            : launch_quantize<double>((const double *)u_mc, labels, qa, true, stream);
+  });
+  if (e != hipSuccess) return MGX_ERR_HIP;
+  char host[sizeof(int) * kMaxLevels + 2 * sizeof(unsigned long long)];
+  if (hipMemcpyAsync(host, base, sbytes, hipMemcpyDeviceToHost, stream) != hipSuccess) return MGX_ERR_HIP;
+  if (hipStreamSynchronize(stream) != hipSuccess) return MGX_ERR_HIP;
+  std::memset(stats, 0, sizeof(*stats));
+  stats->first_level = qa.first;
+  stats->num_levels = qa.nlev;
+  std::memcpy(stats->max_abs_label, host, sizeof(int) * qa.nlev);
+  unsigned long long ovf, nan;
+  std::memcpy(&ovf, host + sizeof(int) * kMaxLevels, sizeof(ovf));
+  std::memcpy(&nan, host + sizeof(int) * kMaxLevels + sizeof(ovf), sizeof(nan));
+  stats->n_overflow = (int64_t)ovf;
+  stats->n_nonfinite = (int64_t)nan;
+  return (ovf || nan) ? MGX_ERR_RANGE : MGX_OK;
+}
+
+mgx_status mgx_dequantize(const int32_t *labels, void *u_mc, mgx_dtype dtype, int ndim, const int64_t *dims,
+                          const double *const *coords, double tol_linf, int stop_level, double c_linf,
+                          hipStream_t stream) {
+  if (dtype != MGX_F32 && dtype != MGX_F64) return MGX_ERR_ARG;
+  int64_t n[3];
+  bool real[3];
+  int L;
+  int st = parse_shape(ndim, dims, n, real, &L);
+  if (st) return (mgx_status)st;
+  if (!u_mc || !labels) return MGX_ERR_ARG;
+  const size_t cnt = (size_t)(n[0] * n[1] * n[2]);
+  if (overlaps(u_mc, cnt * elem_size(dtype), labels, cnt * 4)) return MGX_ERR_ARG;
+  QuantArgs qa;
+  Plan *P;
+  mgx_status s = quant_args(ndim, dims, coords, tol_linf, stop_level, c_linf, &qa, &P);
+  if (s) return s;
+  hipError_t e = traced("dequantize", -1, stream, [&] {
+    return dtype == MGX_F32 ? launch_dequantize<float>(labels, (float *)u_mc, qa, stream)
+                            : launch_dequantize<double>(labels, (double *)u_mc, qa, stream);
+  });
+  return hip_status(e);
+}
+
+double mgx_linf_constant(int ndim, const int64_t *dims, const double *const *coords, int stop_level) {
+  int st = 0;
+  Plan *P = get_plan(ndim, dims, coords, &st);
+  if (!P || stop_level < 0 || stop_level > P->L) return -1.0;
+  return P->linf_constant(stop_level);
+}
+
+mgx_status mgx_level_tolerances(int ndim, const int64_t *dims, const double *const *coords, double tol_linf,
+                                int stop_level, double c_linf, double *tau_out) {
+  if (!tau_out) return MGX_ERR_ARG;
+  int st = 0;
+  Plan *P = get_plan(ndim, dims, coords, &st);
+  if (!P) return (mgx_status)st;
+  if (stop_level < 0 || stop_level > P->L) return MGX_ERR_LEVEL;
+  return tolerances(P, ndim, tol_linf, stop_level, c_linf, tau_out);
+}
+
+mgx_status mgx_trace_enable(int on) {
+  Tracer &t = tracer();
+  std::lock_guard<std::mutex> g(t.mu);
+  for (auto &r : t.recs) {
+    (void)hipEventSynchronize(r.b);
+    t.pool.push_back(r.a);
+    t.pool.push_back(r.b);
+  }
+  t.recs.clear();
+  t.on = on != 0;
+  return MGX_OK;
+}
+
+int mgx_trace_read(mgx_kernel_time *out, int max) {
+  Tracer &t = tracer();
+  std::lock_guard<std::mutex> g(t.mu);
+  std::vector<mgx_kernel_time> agg;
+  bool ok = true;
+  for (auto &r : t.recs) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) ok = false;
+    t.pool.push_back(r.a);
+    t.pool.push_back(r.b);
+    size_t i = 0;
+    for (; i < agg.size(); i++)
+      if (agg[i].level == r.level && std::strncmp(agg[i].name, r.name, sizeof(agg[i].name)) == 0) break;
+    if (i == agg.size()) {
+      mgx_kernel_time k;
+      std::memset(&k, 0, sizeof(k));
+      std::strncpy(k.name, r.name, sizeof(k.name) - 1);
+      k.level = r.level;
+      agg.push_back(k);
+    }
+    agg[i].count += 1;
+    agg[i].total_ms += ms;
+  }
+  t.recs.clear();
+  if (!ok) return -1;
+  int n = (int)agg.size() < max ? (int)agg.size() : max;
+  for (int i = 0; i < n; i++) out[i] = agg[i];
+  return n;
+}
+
+}  // extern "C"

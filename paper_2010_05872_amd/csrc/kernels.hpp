@@ -1,0 +1,92 @@
+// Kernel argument blocks and host launchers (internal to libmgx).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mgx {
+
+constexpr int kMaxLevelsK = 16;
+
+// Tables of one axis at the level being processed (see plan.hpp).
+template <typename T>
+struct AxisTab {
+  const T *wl, *wr;               // interpolation weights at odd fine nodes [m]
+  const T *w5;                    // load-vector stencil, 5 per coarse node [5c]
+  const T *mult, *invd, *qsup;    // Thomas factors of the coarse mass matrix [c]
+  int m, c;                       // fine and coarse node counts
+};
+
+template <typename T>
+struct StencilArgs {
+  AxisTab<T> ax[3];
+  const T *V;                 // level-l box (decompose), compact
+  int64_t vp0, vp1;           // its plane and row pitches
+  T *umc_w;                   // u_mc (decompose writes coefficients)
+  const T *umc_r;             // u_mc (recompose reads coefficients)
+  int64_t up0, up1;           // u_mc pitches (finest grid)
+  T *Vc;                      // nodal values out (decompose), compact coarse
+  int64_t cp0, cp1;
+  T *F;                       // load vector out, coarse box
+  int64_t fp0, fp1;
+  int ntx, nty, nzc, tz;      // set by the launcher
+};
+
+template <typename T>
+struct InterpArgs {
+  AxisTab<T> ax[3];
+  const T *nodal;             // corrected nodal values, coarse box
+  int64_t np0, np1;
+  const T *umc;               // coefficients (level-centric)
+  int64_t up0, up1;
+  T *out;                     // level-l box out
+  int64_t op0, op1;
+  int ntx, nty, nzc, tz;
+};
+
+template <typename T>
+struct SolveArgs {            // contiguous-axis solve, in place on F rows
+  T *F;
+  int64_t nlines, pitch;
+  int c;
+  const T *mult, *invd, *qsup;
+};
+
+template <typename T>
+struct StridedArgs {          // strided-axis solve (optionally applying)
+  T *F;
+  int c;                      // line length
+  int64_t sj;                 // element stride along the line
+  int nx;                     // contiguous extent (threads)
+  int64_t so;                 // stride between outer lines
+  int nouter;
+  const T *mult, *invd, *qsup;
+  const T *in;                // apply: nodal in (index J*ij + o*io + x)
+  int64_t ij, io;
+  T *out;                     // apply: nodal out (index J*oj + o*oo + x)
+  int64_t oj, oo;
+  T sign;
+};
+
+struct QuantArgs {
+  int64_t nrows;              // n0 * n1
+  int n1, n2;
+  int first, nlev;            // levels first .. first+nlev-1
+  int sizes[3][kMaxLevelsK];  // box size of level first+i along each axis
+  double q[kMaxLevelsK];      // bin width per level
+  int *stats_max;             // [nlev] device
+  unsigned long long *stats_ovf, *stats_nan;
+};
+
+template <typename T> hipError_t launch_load_vector(StencilArgs<T> a, bool dec, hipStream_t st);
+template <typename T> hipError_t launch_interp_add(InterpArgs<T> a, hipStream_t st);
+template <typename T> hipError_t launch_solve_contig(SolveArgs<T> a, hipStream_t st);
+template <typename T> hipError_t launch_solve_strided(StridedArgs<T> a, bool apply, hipStream_t st);
+template <typename T> hipError_t launch_apply(StridedArgs<T> a, hipStream_t st);
+template <typename T>
+hipError_t launch_quantize(const T *umc, int32_t *labels, QuantArgs a, bool stats, hipStream_t st);
+template <typename T>
+hipError_t launch_dequantize(const int32_t *labels, T *umc, QuantArgs a, hipStream_t st);
+
+}  // namespace mgx
