@@ -108,6 +108,10 @@ AxisTab<T> axis_tab(const Plan *P, int l, int k, const T *tab) {
   t.mult = tab + a.off_mult;
   t.invd = tab + a.off_invd;
   t.qsup = tab + a.off_qsup;
+  t.multb = tab + a.off_multb;
+  t.invdb = tab + a.off_invdb;
+  t.qsub = tab + a.off_qsub;
+  t.mid = tab + a.off_mid;
   t.m = (int)a.m;
   t.c = (int)a.c;
   return t;
@@ -147,6 +151,10 @@ hipError_t solve_and_apply(int level, const AxisTab<T> ax[3], const bool real[3]
     s.mult = ax[1].mult;
     s.invd = ax[1].invd;
     s.qsup = ax[1].qsup;
+    s.multb = ax[1].multb;
+    s.invdb = ax[1].invdb;
+    s.qsub = ax[1].qsub;
+    s.mid = ax[1].mid;
     const bool apply = !real[0];
     if (apply) {  // 2-D: line index Y, outer Z (= 0)
       s.in = in;
@@ -172,6 +180,10 @@ hipError_t solve_and_apply(int level, const AxisTab<T> ax[3], const bool real[3]
   s.mult = ax[0].mult;
   s.invd = ax[0].invd;
   s.qsup = ax[0].qsup;
+  s.multb = ax[0].multb;
+  s.invdb = ax[0].invdb;
+  s.qsub = ax[0].qsub;
+  s.mid = ax[0].mid;
   s.in = in;
   s.ij = ip0;
   s.io = ip1;
@@ -338,16 +350,21 @@ mgx_status quant_args(int ndim, const int64_t *dims, const double *const *coords
   if (s) return s;
   const int L = P->L;
   std::memset(qa, 0, sizeof(*qa));
-  qa->nrows = P->n[0] * P->n[1];
+  qa->n = P->n[0] * P->n[1] * P->n[2];
+  if (qa->n >= ((int64_t)1 << 32)) return MGX_ERR_SHAPE;  // flat 32-bit indexing
   qa->n1 = (int)P->n[1];
   qa->n2 = (int)P->n[2];
+  auto magic = [](uint64_t d) -> uint64_t { return d < 2 ? 0 : (~(uint64_t)0) / d + 1; };
+  qa->mag1 = magic((uint64_t)qa->n1);
+  qa->mag2 = magic((uint64_t)qa->n2);
+  for (int k = 0; k < 3; k++) {
+    int m = 0;
+    if (P->real[k])
+      while (((int64_t)1 << m) < P->n[k] - 1) m++;
+    qa->off[k] = P->real[k] ? m - L : 0;
+  }
   qa->first = stop;
   qa->nlev = L + 1 - stop;
-  for (int k = 0; k < 3; k++)
-    for (int i = 0; i < qa->nlev; i++) {
-      int l = stop + i;
-      qa->sizes[k][i] = P->real[k] ? (int)((P->n[k] - 1) / ((int64_t)1 << (L - l)) + 1) : 1;
-    }
   for (int i = 0; i < qa->nlev; i++) qa->q[i] = 2.0 * tau[i];
   *plan = P;
   return MGX_OK;

@@ -45,9 +45,12 @@ __device__ __forceinline__ int64_t lc_pos(int j, int c) {
   return (j & 1) ? (int64_t)c + (j >> 1) : (int64_t)(j >> 1);
 }
 
-template <typename T>
-__device__ __forceinline__ T ld(const T *p) {
-  return *p;
+// Returns v unchanged but opaque to the optimizer, so that per-element index
+// arithmetic is recomputed inside plane loops instead of being hoisted into
+// dozens of live registers (an empty asm statement: no instruction emitted).
+__device__ __forceinline__ int opaque(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
 }
 
 // ---------------------------------------------------------------------------
@@ -60,13 +63,19 @@ __device__ __forceinline__ T ld(const T *p) {
 // owned (written) by the tile are [2Y0, min(2Y1,m1)) etc.  The kernel
 // marches over fine planes j = 2Z0-2 .. 2Z1; plane j adds its yx-restricted
 // values into the load vector of the up to three coarse planes it touches.
-template <typename T, int TX, int TY, bool DEC>
-__global__ void __launch_bounds__(256) k_load_vector(StencilArgs<T> a) {
+//
+// Every thread owns the same NE region elements in every plane; the next
+// plane's values are fetched into registers while the current plane is
+// processed (one memory latency per plane, overlapped with compute), then
+// committed to LDS.  Two workgroup barriers per plane.
+template <typename T, int TX, int TY, int NT, bool DEC>
+__global__ void __launch_bounds__(NT) k_load_vector(StencilArgs<T> a) {
   constexpr int HR = 2 * TY + 5;  // region rows incl. halo and the extension
   constexpr int W = 2 * TX + 5;   // region row pitch
   constexpr int GW = TX + 1;      // coarse columns per tile (max)
   constexpr int GH = TY + 1;      // coarse rows per tile (max)
-  constexpr int NOUT = (GH * GW + 255) / 256;
+  constexpr int NE = (HR * W + NT - 1) / NT;
+  constexpr int NOUT = (GH * GW + NT - 1) / NT;
   constexpr int NV = DEC ? 3 : 1;
 
   __shared__ T sV[NV][HR * W];
@@ -87,37 +96,65 @@ __global__ void __launch_bounds__(256) k_load_vector(StencilArgs<T> a) {
   const int Y0 = ty * TY, Y1 = (ty == a.nty - 1) ? c1 : Y0 + TY;
   const int Z0 = tz * a.tz, Z1 = (tz == a.nzc - 1) ? c0 : Z0 + a.tz;
   const int nX = X1 - X0, nY = Y1 - Y0;
-  const int r0 = 2 * Y0 - 2, q0 = 2 * X0 - 2;  // fine row / column at local 0
+  const int r0 = 2 * Y0 - 2, q0 = 2 * X0 - 2;  // fine row / column at local 0 (even)
   const int nr = 2 * nY + 3, nq = 2 * nX + 3;
   const int own_r0 = 2 * Y0, own_r1 = min(2 * Y1, m1);
   const int own_q0 = 2 * X0, own_q1 = min(2 * X1, m2);
   const int own_p0 = 2 * Z0, own_p1 = min(2 * Z1, m0);
 
   // stage per-tile weights
-  for (int q = tid; q < nq; q += 256) {
+  for (int q = tid; q < nq; q += NT) {
     int j2 = q0 + q;
     bool in = j2 >= 0 && j2 < m2;
     sWxl[q] = in ? a.ax[2].wl[j2] : T(0);
     sWxr[q] = in ? a.ax[2].wr[j2] : T(0);
   }
-  for (int r = tid; r < nr; r += 256) {
+  for (int r = tid; r < nr; r += NT) {
     int j1 = r0 + r;
     bool in = j1 >= 0 && j1 < m1;
     sWyl[r] = in ? a.ax[1].wl[j1] : T(0);
     sWyr[r] = in ? a.ax[1].wr[j1] : T(0);
   }
-  for (int i = tid; i < nX * 5; i += 256) sW5x[i] = a.ax[2].w5[X0 * 5 + i];
-  for (int i = tid; i < nY * 5; i += 256) sW5y[i] = a.ax[1].w5[Y0 * 5 + i];
+  for (int i = tid; i < nX * 5; i += NT) sW5x[i] = a.ax[2].w5[X0 * 5 + i];
+  for (int i = tid; i < nY * 5; i += NT) sW5y[i] = a.ax[1].w5[Y0 * 5 + i];
 
-  // load a fine plane of the level box into an LDS slot
-  auto load_plane = [&](int j, T *dst) {
-    const T *src = a.V + (int64_t)j * a.vp0;
-    for (int idx = tid; idx < nr * W; idx += 256) {
-      int r = idx / W, q = idx - r * W;
-      int j1 = r0 + r, j2 = q0 + q;
-      T v = T(0);
-      if (q < nq && j1 >= 0 && j1 < m1 && j2 >= 0 && j2 < m2) v = src[(int64_t)j1 * a.vp1 + j2];
-      dst[idx] = v;
+  // element k of this thread: region index tid + NT k, valid if inside the
+  // region and the level box
+  unsigned valid = 0;
+#pragma unroll
+  for (int k = 0; k < NE; k++) {
+    const int idx = tid + NT * k;
+    const int r = idx / W, q = idx - r * W;
+    const int j1 = r0 + r, j2 = q0 + q;
+    const bool in = idx < nr * W && q < nq && j1 >= 0 && j1 < m1 && j2 >= 0 && j2 < m2;
+    valid |= (unsigned)in << k;
+  }
+
+  T stage[NE];
+  // issue the loads of fine plane j into registers (zeros outside)
+  auto fetch = [&](int j) {
+    const bool pin = j >= 0 && j < m0;
+    if (DEC) {
+      const T *base = a.V + (int64_t)(pin ? j : 0) * a.vp0;
+#pragma unroll
+      for (int k = 0; k < NE; k++) {
+        const int idx = opaque(tid) + NT * k;
+        const int r = idx / W, q = idx - r * W;
+        const bool ok = pin && ((valid >> k) & 1u);
+        stage[k] = ok ? base[(int64_t)(r0 + r) * a.vp1 + (q0 + q)] : T(0);
+      }
+    } else {
+      const T *base = a.umc_r + (pin ? lc_pos(j, c0) : 0) * a.up0;
+      const int jodd = j & 1;
+#pragma unroll
+      for (int k = 0; k < NE; k++) {
+        const int idx = opaque(tid) + NT * k;
+        const int r = idx / W, q = idx - r * W;
+        const int j1 = r0 + r, j2 = q0 + q;
+        // nodal nodes (all indices even) carry no multilevel component
+        const bool ok = pin && ((valid >> k) & 1u) && (jodd | (j1 & 1) | (j2 & 1));
+        stage[k] = ok ? base[lc_pos(j1, c1) * a.up1 + lc_pos(j2, c2)] : T(0);
+      }
     }
   };
 
@@ -128,104 +165,123 @@ __global__ void __launch_bounds__(256) k_load_vector(StencilArgs<T> a) {
     for (int k = 0; k < NOUT; k++) acc[s][k] = T(0);
 
   const int jstart = 2 * Z0 - 2, jend = 2 * Z1;
-  if (DEC && jstart >= 0 && jstart < m0) load_plane(jstart, sV[(jstart + 3) % 3]);
+  if (DEC) {
+    fetch(jstart);
+#pragma unroll
+    for (int k = 0; k < NE; k++)
+      if (tid + NT * k < HR * W) sV[(jstart + 3) % 3][tid + NT * k] = stage[k];
+    fetch(jstart + 1);
+#pragma unroll
+    for (int k = 0; k < NE; k++)
+      if (tid + NT * k < HR * W) sV[(jstart + 4) % 3][tid + NT * k] = stage[k];
+    fetch(jstart + 2);
+    __syncthreads();
+  } else {
+    fetch(jstart);
+  }
 
   for (int j = jstart; j <= jend; j++) {
     const bool plane_in = (j >= 0 && j < m0);
-    if (DEC && j + 1 >= 0 && j + 1 < m0) load_plane(j + 1, sV[(j + 4) % 3]);
-    if (plane_in) {
-      __syncthreads();
-      // ---- multilevel component z of plane j into sZ (+ DEC stores) ----
-      const int pz = j & 1;
-      const bool own_plane = (j >= own_p0 && j < own_p1);
-      if (DEC) {
-        const T *Vm = sV[(j + 2) % 3];  // plane j-1
-        const T *V0 = sV[(j + 3) % 3];  // plane j
-        const T *Vp = sV[(j + 4) % 3];  // plane j+1
+    const int pz = j & 1;
+    if (DEC) {
+      // ---- multilevel component z of plane j into sZ, plus the stores ----
+      if (plane_in) {
+        const int s0 = (j + 3) % 3;
+        const int sa = pz ? (j + 2) % 3 : s0;  // plane j-1 for odd j
+        const int sb = pz ? (j + 4) % 3 : s0;  // plane j+1 for odd j
         const T wzl = pz ? a.ax[0].wl[j] : T(1);
         const T wzr = pz ? a.ax[0].wr[j] : T(0);
-        const T *Za = pz ? Vm : V0;
-        const T *Zb = pz ? Vp : V0;
-        for (int idx = tid; idx < nr * W; idx += 256) {
-          int r = idx / W, q = idx - r * W;
-          int j1 = r0 + r, j2 = q0 + q;
-          bool in = q < nq && j1 >= 0 && j1 < m1 && j2 >= 0 && j2 < m2;
-          int py = j1 & 1, px = j2 & 1;
+        const bool own_plane = (j >= own_p0 && j < own_p1);
+        const int64_t pz_off = lc_pos(j, c0) * a.up0;
+#pragma unroll
+        for (int k = 0; k < NE; k++) {
+          const int idx = opaque(tid) + NT * k;
+          if (idx >= HR * W) break;
+          const int r = idx / W, q = idx - r * W;
+          const int j1 = r0 + r, j2 = q0 + q;
+          const int py = r & 1, px = q & 1;
           T z = T(0);
-          if (in) {
-            const T v = V0[idx];
+          if ((valid >> k) & 1u) {
+            const T v = sV[s0][idx];
+            const bool own = own_plane && j1 >= own_r0 && j1 < own_r1 && j2 >= own_q0 && j2 < own_q1;
             if (pz | py | px) {
               // 2x2x2 corner stencil with zero weights on even axes
               const T wyl = py ? sWyl[r] : T(1), wyr = py ? sWyr[r] : T(0);
               const T wxl = px ? sWxl[q] : T(1), wxr = px ? sWxr[q] : T(0);
-              const int ra = (r - py) * W, rb = (r + py) * W;
-              const int qa = q - px, qb = q + px;
-              T sa = wyl * (wxl * Za[ra + qa] + wxr * Za[ra + qb]) +
-                     wyr * (wxl * Za[rb + qa] + wxr * Za[rb + qb]);
-              T sb = wyl * (wxl * Zb[ra + qa] + wxr * Zb[ra + qb]) +
-                     wyr * (wxl * Zb[rb + qa] + wxr * Zb[rb + qb]);
-              z = v - (wzl * sa + wzr * sb);
-              if (own_plane && j1 >= own_r0 && j1 < own_r1 && j2 >= own_q0 && j2 < own_q1)
-                a.umc_w[lc_pos(j, c0) * a.up0 + lc_pos(j1, c1) * a.up1 + lc_pos(j2, c2)] = z;
-            } else if (own_plane && j1 >= own_r0 && j1 < own_r1 && j2 >= own_q0 && j2 < own_q1) {
+              const int ia = (r - py) * W + (q - px), ib = (r - py) * W + (q + px);
+              const int ic = (r + py) * W + (q - px), id = (r + py) * W + (q + px);
+              const T pa = wyl * (wxl * sV[sa][ia] + wxr * sV[sa][ib]) + wyr * (wxl * sV[sa][ic] + wxr * sV[sa][id]);
+              const T pb = wyl * (wxl * sV[sb][ia] + wxr * sV[sb][ib]) + wyr * (wxl * sV[sb][ic] + wxr * sV[sb][id]);
+              z = v - (wzl * pa + wzr * pb);
+              if (own) a.umc_w[pz_off + lc_pos(j1, c1) * a.up1 + lc_pos(j2, c2)] = z;
+            } else if (own) {
               a.Vc[(int64_t)(j >> 1) * a.cp0 + (int64_t)(j1 >> 1) * a.cp1 + (j2 >> 1)] = v;
             }
           }
           sZ[idx] = z;
         }
-      } else {
-        for (int idx = tid; idx < nr * W; idx += 256) {
-          int r = idx / W, q = idx - r * W;
-          int j1 = r0 + r, j2 = q0 + q;
-          bool in = q < nq && j1 >= 0 && j1 < m1 && j2 >= 0 && j2 < m2;
-          T z = T(0);
-          if (in && (pz | (j1 & 1) | (j2 & 1)))
-            z = a.umc_r[lc_pos(j, c0) * a.up0 + lc_pos(j1, c1) * a.up1 + lc_pos(j2, c2)];
-          sZ[idx] = z;
-        }
       }
       __syncthreads();
-      // ---- restriction along x: sG[r][X] ----
-      for (int idx = tid; idx < nr * GW; idx += 256) {
-        int r = idx / GW, X = idx - r * GW;
+      // commit plane j+2 into the slot of plane j-1 (no longer read)
+#pragma unroll
+      for (int k = 0; k < NE; k++)
+        if (tid + NT * k < HR * W) sV[(j + 5) % 3][tid + NT * k] = stage[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < NE; k++)
+        if (tid + NT * k < HR * W) sZ[tid + NT * k] = stage[k];
+      fetch(j + 1);
+      __syncthreads();
+    }
+    // ---- restriction along x: sG[r][X] ----
+    if (plane_in) {
+      for (int idx = tid; idx < nr * GW; idx += NT) {
+        const int r = idx / GW, X = idx - r * GW;
         if (X < nX) {
-          const T *zr = sZ + r * W + 2 * X;
+          const int b = r * W + 2 * X;
           const T *w = sW5x + X * 5;
-          sG[idx] = w[0] * zr[0] + w[1] * zr[1] + w[2] * zr[2] + w[3] * zr[3] + w[4] * zr[4];
+          sG[idx] = w[0] * sZ[b] + w[1] * sZ[b + 1] + w[2] * sZ[b + 2] + w[3] * sZ[b + 3] + w[4] * sZ[b + 4];
         }
       }
-      __syncthreads();
-      // ---- restriction along y, accumulation along z ----
+    }
+    __syncthreads();
+    if (DEC) fetch(j + 3);
+    // ---- restriction along y, accumulation along z ----
+    if (plane_in) {
       const int Jc = j >> 1;  // j even: Z = Jc-1, Jc, Jc+1; j odd: Z = Jc, Jc+1
+      T wz0, wz1, wz2;
+      if (!pz) {
+        wz0 = Jc - 1 >= 0 ? a.ax[0].w5[(Jc - 1) * 5 + 4] : T(0);
+        wz1 = a.ax[0].w5[Jc * 5 + 2];
+        wz2 = Jc + 1 < c0 ? a.ax[0].w5[(Jc + 1) * 5 + 0] : T(0);
+      } else {
+        wz0 = a.ax[0].w5[Jc * 5 + 3];
+        wz1 = Jc + 1 < c0 ? a.ax[0].w5[(Jc + 1) * 5 + 1] : T(0);
+        wz2 = T(0);
+      }
 #pragma unroll
       for (int k = 0; k < NOUT; k++) {
-        int idx = tid + k * 256;
-        int Y = idx / GW, X = idx - Y * GW;
+        const int idx = tid + k * NT;
+        const int Y = idx / GW, X = idx - Y * GW;
         if (idx < GH * GW && Y < nY && X < nX) {
           const T *w = sW5y + Y * 5;
-          const T *g = sG + (2 * Y) * GW + X;
-          T gyx = w[0] * g[0] + w[1] * g[GW] + w[2] * g[2 * GW] + w[3] * g[3 * GW] + w[4] * g[4 * GW];
-          if (!pz) {
-            // contributes to Z = Jc-1 (offset +2), Jc (0), Jc+1 (-2)
-            if (Jc - 1 >= 0) acc[0][k] += a.ax[0].w5[(Jc - 1) * 5 + 4] * gyx;
-            acc[1][k] += a.ax[0].w5[Jc * 5 + 2] * gyx;
-            if (Jc + 1 < c0) acc[2][k] += a.ax[0].w5[(Jc + 1) * 5 + 0] * gyx;
-          } else {
-            // contributes to Z = Jc (offset +1), Jc+1 (-1)
-            acc[0][k] += a.ax[0].w5[Jc * 5 + 3] * gyx;
-            if (Jc + 1 < c0) acc[1][k] += a.ax[0].w5[(Jc + 1) * 5 + 1] * gyx;
-          }
+          const int b = (2 * Y) * GW + X;
+          const T gyx = w[0] * sG[b] + w[1] * sG[b + GW] + w[2] * sG[b + 2 * GW] + w[3] * sG[b + 3 * GW] +
+                        w[4] * sG[b + 4 * GW];
+          acc[0][k] += wz0 * gyx;
+          acc[1][k] += wz1 * gyx;
+          acc[2][k] += wz2 * gyx;
         }
       }
     }
     // after an even plane j, coarse plane j/2 - 1 is complete
-    if (!(j & 1)) {
+    if (!pz) {
       const int Zdone = (j >> 1) - 1;
       if (Zdone >= Z0 && Zdone < Z1) {
 #pragma unroll
         for (int k = 0; k < NOUT; k++) {
-          int idx = tid + k * 256;
-          int Y = idx / GW, X = idx - Y * GW;
+          const int idx = tid + k * NT;
+          const int Y = idx / GW, X = idx - Y * GW;
           if (idx < GH * GW && Y < nY && X < nX)
             a.F[(int64_t)Zdone * a.fp0 + (int64_t)(Y0 + Y) * a.fp1 + X0 + X] = acc[0][k];
         }
@@ -237,7 +293,6 @@ __global__ void __launch_bounds__(256) k_load_vector(StencilArgs<T> a) {
         acc[2][k] = T(0);
       }
     }
-    if (plane_in) __syncthreads();  // sZ / sG / ring slots are rewritten next
   }
 }
 
@@ -338,12 +393,14 @@ __global__ void __launch_bounds__(256) k_solve_contig(SolveArgs<T> a) {
 // ---------------------------------------------------------------------------
 // k_solve_strided: Thomas solve along a strided axis of the coarse box.
 // One thread per line, consecutive lanes on consecutive contiguous indices
-// (coalesced rows).  The forward sweep writes f' in place; the backward
-// sweep reads it back.  With APPLY the solution is not stored but added
-// (sign +1, decomposition) or subtracted (sign -1, recomposition) to the
-// nodal values: out = in + sign * y.
+// (coalesced rows).  The line is processed in chunks of CH nodes whose loads
+// are issued together, the next chunk's loads before the current chunk's
+// stores, so one memory latency is paid per chunk rather than per node.  The
+// forward sweep writes f' in place; the backward sweep reads it back.  With
+// APPLY the solution is not stored but added (sign +1, decomposition) or
+// subtracted (sign -1, recomposition) to the nodal values: out = in + sign*y.
 // ---------------------------------------------------------------------------
-template <typename T, bool APPLY>
+template <typename T, bool APPLY, int CH>
 __global__ void __launch_bounds__(256) k_solve_strided(StridedArgs<T> a) {
   const int x = blockIdx.x * 256 + threadIdx.x;
   const int o = blockIdx.y;
@@ -351,27 +408,172 @@ __global__ void __launch_bounds__(256) k_solve_strided(StridedArgs<T> a) {
   T *p = a.F + (int64_t)o * a.so + x;
   const int c = a.c;
   const int64_t s = a.sj;
-  T fp = p[0];
-  for (int J = 1; J < c; J++) {
-    fp = p[J * s] - a.mult[J] * fp;
-    p[J * s] = fp;
+  const int nch = (c + CH - 1) / CH;
+  T v[CH], w[CH];
+  // ---- forward elimination ----
+#pragma unroll
+  for (int k = 0; k < CH; k++) v[k] = k < c ? p[k * s] : T(0);
+  T fp = T(0);
+  for (int ch = 0; ch < nch; ch++) {
+    const int J0 = ch * CH;
+    if (ch + 1 < nch) {
+#pragma unroll
+      for (int k = 0; k < CH; k++) w[k] = (J0 + CH + k < c) ? p[(int64_t)(J0 + CH + k) * s] : T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < CH; k++) {
+      const int J = J0 + k;
+      if (J < c) {
+        fp = v[k] - a.mult[J] * fp;  // mult[0] = 0
+        v[k] = fp;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < CH; k++)
+      if (J0 + k < c) p[(int64_t)(J0 + k) * s] = v[k];
+#pragma unroll
+    for (int k = 0; k < CH; k++) v[k] = w[k];
   }
-  T y = a.invd[c - 1] * fp;
-  if (APPLY) {
-    const int64_t ii = (int64_t)(c - 1) * a.ij + (int64_t)o * a.io + x;
-    const int64_t oo = (int64_t)(c - 1) * a.oj + (int64_t)o * a.oo + x;
-    a.out[oo] = a.in[ii] + a.sign * y;
+  // ---- back substitution, from the last chunk down ----
+  T iv[CH], iw[CH];
+  {
+    const int J0 = (nch - 1) * CH;
+#pragma unroll
+    for (int k = 0; k < CH; k++) {
+      const bool in = J0 + k < c;
+      v[k] = in ? p[(int64_t)(J0 + k) * s] : T(0);
+      if (APPLY) iv[k] = in ? a.in[(int64_t)(J0 + k) * a.ij + (int64_t)o * a.io + x] : T(0);
+    }
+  }
+  T y = T(0);
+  for (int ch = nch - 1; ch >= 0; ch--) {
+    const int J0 = ch * CH;
+    if (ch > 0) {
+#pragma unroll
+      for (int k = 0; k < CH; k++) {
+        w[k] = p[(int64_t)(J0 - CH + k) * s];
+        if (APPLY) iw[k] = a.in[(int64_t)(J0 - CH + k) * a.ij + (int64_t)o * a.io + x];
+      }
+    }
+#pragma unroll
+    for (int k = CH - 1; k >= 0; k--) {
+      const int J = J0 + k;
+      if (J < c) {
+        y = a.invd[J] * v[k] - a.qsup[J] * y;  // qsup[c-1] = 0
+        v[k] = y;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < CH; k++) {
+      const int J = J0 + k;
+      if (J < c) {
+        if (APPLY)
+          a.out[(int64_t)J * a.oj + (int64_t)o * a.oo + x] = iv[k] + a.sign * v[k];
+        else
+          p[(int64_t)J * s] = v[k];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < CH; k++) {
+      v[k] = w[k];
+      if (APPLY) iv[k] = iw[k];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_solve_twisted: Thomas solve along a strided axis of the coarse box as a
+// two-ended ("twisted") factorization of the same tridiagonal matrix.  A
+// workgroup takes 128 lines (consecutive contiguous indices): waves 0-1
+// eliminate rows 0..K-1 from the top, waves 2-3 rows C-1..K+1 from the
+// bottom (C = 2K+1), each lane keeping its half line in registers; the two
+// values next to the middle row K are swapped through LDS, the middle row is
+// solved, and both halves back-substitute outwards.  A direct method (the
+// same matrix factored from both ends), every element read once and written
+// once; the row index is uniform per wave, so row offsets and the factor
+// tables are scalar operands.
+// ---------------------------------------------------------------------------
+template <typename T, int C, bool APPLY>
+__global__ void __launch_bounds__(256) k_solve_twisted(StridedArgs<T> a) {
+  constexpr int K = C / 2;
+  __shared__ T sE[2][128];
+  const int wave = threadIdx.x >> 6;
+  const int half = wave >> 1;  // 0: top rows, 1: bottom rows (uniform per wave)
+  const int line = (wave & 1) * 64 + (threadIdx.x & 63);
+  const int x = blockIdx.x * 128 + line;
+  const int o = blockIdx.y;
+  const bool active = x < a.nx;
+  T *p = a.F + (int64_t)o * a.so + (active ? x : 0);
+  const int64_t s = a.sj;
+  T r[K];
+  if (!half) {
+#pragma unroll
+    for (int i = 0; i < K; i++) r[i] = p[(int64_t)i * s];
   } else {
-    p[(c - 1) * s] = y;
+#pragma unroll
+    for (int i = 0; i < K; i++) r[i] = p[(int64_t)(C - 1 - i) * s];
   }
-  for (int J = c - 2; J >= 0; J--) {
-    y = a.invd[J] * p[J * s] - a.qsup[J] * y;
-    if (APPLY) {
-      const int64_t ii = (int64_t)J * a.ij + (int64_t)o * a.io + x;
-      const int64_t oo = (int64_t)J * a.oj + (int64_t)o * a.oo + x;
-      a.out[oo] = a.in[ii] + a.sign * y;
+  const T fK = p[(int64_t)K * s];
+  T e = r[0];
+  if (!half) {
+#pragma unroll
+    for (int i = 1; i < K; i++) {
+      e = r[i] - a.mult[i] * e;
+      r[i] = e;
+    }
+  } else {
+#pragma unroll
+    for (int i = 1; i < K; i++) {
+      e = r[i] - a.multb[C - 1 - i] * e;
+      r[i] = e;
+    }
+  }
+  sE[half][line] = e;  // f'_{K-1} (top) or g'_{K+1} (bottom)
+  __syncthreads();
+  const T yK = a.mid[0] * (fK - a.mid[1] * sE[0][line] - a.mid[2] * sE[1][line]);
+  T y = yK;
+  if (!half) {
+#pragma unroll
+    for (int i = K - 1; i >= 0; i--) {
+      y = a.invd[i] * r[i] - a.qsup[i] * y;
+      r[i] = y;
+    }
+  } else {
+#pragma unroll
+    for (int i = K - 1; i >= 0; i--) {
+      const int J = C - 1 - i;
+      y = a.invdb[J] * r[i] - a.qsub[J] * y;
+      r[i] = y;
+    }
+  }
+  if (!active) return;
+  if (APPLY) {
+    const T *in = a.in + (int64_t)o * a.io + x;
+    T *out = a.out + (int64_t)o * a.oo + x;
+    constexpr int CHA = 16;
+#pragma unroll
+    for (int i0 = 0; i0 < K; i0 += CHA) {
+      T iv[CHA];
+#pragma unroll
+      for (int k = 0; k < CHA; k++) {
+        const int i = i0 + k;
+        if (i < K) iv[k] = in[(int64_t)(half ? C - 1 - i : i) * a.ij];
+      }
+#pragma unroll
+      for (int k = 0; k < CHA; k++) {
+        const int i = i0 + k;
+        if (i < K) out[(int64_t)(half ? C - 1 - i : i) * a.oj] = iv[k] + a.sign * r[i];
+      }
+    }
+    if (!half) out[(int64_t)K * a.oj] = in[(int64_t)K * a.ij] + a.sign * yK;
+  } else {
+    if (!half) {
+#pragma unroll
+      for (int i = 0; i < K; i++) p[(int64_t)i * s] = r[i];
+      p[(int64_t)K * s] = yK;
     } else {
-      p[J * s] = y;
+#pragma unroll
+      for (int i = 0; i < K; i++) p[(int64_t)(C - 1 - i) * s] = r[i];
     }
   }
 }
@@ -389,15 +591,20 @@ __global__ void __launch_bounds__(256) k_apply(StridedArgs<T> a) {
 // k_interp_add: recomposition step 4 — Q_l u = coefficient + Pi_{l-1} of the
 // corrected nodal values (and the nodal values themselves on N_{l-1}).
 // Tile as in k_load_vector; the kernel marches over coarse planes J with a
-// two-slot ring of nodal planes (J, J+1) and emits fine planes 2J, 2J+1.
+// two-slot LDS ring of nodal planes (J, J+1) and emits fine planes 2J, 2J+1.
+// The coefficients of the next two fine planes and the nodal plane after
+// next are fetched into registers while the current pair is computed.
 // ---------------------------------------------------------------------------
-template <typename T, int TX, int TY>
-__global__ void __launch_bounds__(256) k_interp_add(InterpArgs<T> a) {
+template <typename T, int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT) k_interp_add(InterpArgs<T> a) {
   constexpr int NW = TX + 2;  // nodal tile pitch
   constexpr int NH = TY + 2;
   constexpr int OW = 2 * TX + 2;  // owned fine columns (max)
+  constexpr int OH = 2 * TY + 2;  // owned fine rows (max)
+  constexpr int NO = (OH * OW + NT - 1) / NT;
+  constexpr int NN = (NH * NW + NT - 1) / NT;
   __shared__ T sN[2][NH * NW];
-  __shared__ T sWxl[OW], sWxr[OW], sWyl[2 * TY + 2], sWyr[2 * TY + 2];
+  __shared__ T sWxl[OW], sWxr[OW], sWyl[OH], sWyr[OH];
 
   const int tid = threadIdx.x;
   const int m0 = a.ax[0].m, m1 = a.ax[1].m, m2 = a.ax[2].m;
@@ -415,71 +622,137 @@ __global__ void __launch_bounds__(256) k_interp_add(InterpArgs<T> a) {
   const int fq = min(2 * X1, m2) - 2 * X0;  // owned fine columns
   const int fr = min(2 * Y1, m1) - 2 * Y0;  // owned fine rows
 
-  for (int q = tid; q < fq; q += 256) {
+  for (int q = tid; q < fq; q += NT) {
     sWxl[q] = a.ax[2].wl[2 * X0 + q];
     sWxr[q] = a.ax[2].wr[2 * X0 + q];
   }
-  for (int r = tid; r < fr; r += 256) {
+  for (int r = tid; r < fr; r += NT) {
     sWyl[r] = a.ax[1].wl[2 * Y0 + r];
     sWyr[r] = a.ax[1].wr[2 * Y0 + r];
   }
-  auto load_nodal = [&](int J, T *dst) {
-    const T *src = a.nodal + (int64_t)J * a.np0;
-    for (int idx = tid; idx < NH * NW; idx += 256) {
-      int r = idx / NW, q = idx - r * NW;
-      T v = T(0);
-      if (r < ncy && q < ncx) v = src[(int64_t)(Y0 + r) * a.np1 + X0 + q];
-      dst[idx] = v;
+
+  unsigned ownmask = 0;
+#pragma unroll
+  for (int k = 0; k < NO; k++) {
+    const int idx = tid + NT * k;
+    const int rr = idx / OW, qq = idx - rr * OW;
+    ownmask |= (unsigned)(idx < OH * OW && rr < fr && qq < fq) << k;
+  }
+
+  T nst[NN];
+  auto fetch_nodal = [&](int J) {
+    const bool pin = J < c0;
+    const T *src = a.nodal + (int64_t)(pin ? J : 0) * a.np0;
+#pragma unroll
+    for (int k = 0; k < NN; k++) {
+      const int idx = opaque(tid) + NT * k;
+      const int r = idx / NW, q = idx - r * NW;
+      const bool ok = pin && idx < NH * NW && r < ncy && q < ncx;
+      nst[k] = ok ? src[(int64_t)(Y0 + r) * a.np1 + X0 + q] : T(0);
     }
   };
-  load_nodal(Z0, sN[Z0 & 1]);
+  T cf[2][NO];
+  auto fetch_coef = [&](int J) {
+#pragma unroll
+    for (int pz = 0; pz < 2; pz++) {
+      const int j = 2 * J + pz;
+      const bool pin = J < Z1 && j < m0;
+      const T *base = a.umc + (pin ? lc_pos(j, c0) : 0) * a.up0;
+#pragma unroll
+      for (int k = 0; k < NO; k++) {
+        const int idx = opaque(tid) + NT * k;
+        const int rr = idx / OW, qq = idx - rr * OW;
+        const int j1 = 2 * Y0 + rr, j2 = 2 * X0 + qq;
+        const bool ok = pin && ((ownmask >> k) & 1u) && (pz | (j1 & 1) | (j2 & 1));
+        cf[pz][k] = ok ? base[lc_pos(j1, c1) * a.up1 + lc_pos(j2, c2)] : T(0);
+      }
+    }
+  };
+  auto commit_nodal = [&](int slot) {
+#pragma unroll
+    for (int k = 0; k < NN; k++)
+      if (tid + NT * k < NH * NW) sN[slot][tid + NT * k] = nst[k];
+  };
+
+  fetch_nodal(Z0);
+  commit_nodal(Z0 & 1);
+  fetch_nodal(Z0 + 1);
+  commit_nodal((Z0 + 1) & 1);
+  fetch_coef(Z0);
+  fetch_nodal(Z0 + 2);
+  __syncthreads();
+
   for (int J = Z0; J < Z1; J++) {
-    if (J + 1 < c0) load_nodal(J + 1, sN[(J + 1) & 1]);
-    __syncthreads();
-    const T *N0 = sN[J & 1];
-    const T *N1 = sN[(J + 1) & 1];
+    const int sa = J & 1, sb = (J + 1) & 1;
+    T cur[2][NO];
+#pragma unroll
+    for (int pz = 0; pz < 2; pz++)
+#pragma unroll
+      for (int k = 0; k < NO; k++) cur[pz][k] = cf[pz][k];
+    fetch_coef(J + 1);
+#pragma unroll
     for (int pz = 0; pz < 2; pz++) {
       const int j = 2 * J + pz;
       if (j >= m0) break;
       const T wzl = pz ? a.ax[0].wl[j] : T(1);
       const T wzr = pz ? a.ax[0].wr[j] : T(0);
-      const T *Na = N0;
-      const T *Nb = pz ? N1 : N0;
-      for (int idx = tid; idx < fr * OW; idx += 256) {
-        int rr = idx / OW, qq = idx - rr * OW;
-        if (qq >= fq) continue;
-        int j1 = 2 * Y0 + rr, j2 = 2 * X0 + qq;
-        int py = j1 & 1, px = j2 & 1;
-        int ra = (rr >> 1) * NW, rb = ((rr >> 1) + py) * NW;
-        int qa = qq >> 1, qb = (qq >> 1) + px;
+      const int s2 = pz ? sb : sa;
+      T *outp = a.out + (int64_t)j * a.op0;
+#pragma unroll
+      for (int k = 0; k < NO; k++) {
+        if (!((ownmask >> k) & 1u)) continue;
+        const int idx = opaque(tid) + NT * k;
+        const int rr = idx / OW, qq = idx - rr * OW;
+        const int j1 = 2 * Y0 + rr, j2 = 2 * X0 + qq;
+        const int py = j1 & 1, px = j2 & 1;
+        const int ra = (rr >> 1) * NW, rb = ((rr >> 1) + py) * NW;
+        const int qa = qq >> 1, qb = (qq >> 1) + px;
         T outv;
         if (pz | py | px) {
           const T wyl = py ? sWyl[rr] : T(1), wyr = py ? sWyr[rr] : T(0);
           const T wxl = px ? sWxl[qq] : T(1), wxr = px ? sWxr[qq] : T(0);
-          T sa = wyl * (wxl * Na[ra + qa] + wxr * Na[ra + qb]) + wyr * (wxl * Na[rb + qa] + wxr * Na[rb + qb]);
-          T sb = wyl * (wxl * Nb[ra + qa] + wxr * Nb[ra + qb]) + wyr * (wxl * Nb[rb + qa] + wxr * Nb[rb + qb]);
-          T cf = a.umc[lc_pos(j, c0) * a.up0 + lc_pos(j1, c1) * a.up1 + lc_pos(j2, c2)];
-          outv = cf + (wzl * sa + wzr * sb);
+          const T pa = wyl * (wxl * sN[sa][ra + qa] + wxr * sN[sa][ra + qb]) +
+                       wyr * (wxl * sN[sa][rb + qa] + wxr * sN[sa][rb + qb]);
+          const T pb = wyl * (wxl * sN[s2][ra + qa] + wxr * sN[s2][ra + qb]) +
+                       wyr * (wxl * sN[s2][rb + qa] + wxr * sN[s2][rb + qb]);
+          outv = cur[pz][k] + (wzl * pa + wzr * pb);
         } else {
-          outv = Na[ra + qa];
+          outv = sN[sa][ra + qa];
         }
-        a.out[(int64_t)j * a.op0 + (int64_t)j1 * a.op1 + j2] = outv;
+        outp[(int64_t)j1 * a.op1 + j2] = outv;
       }
     }
+    __syncthreads();  // slot sa (plane J) is free
+    commit_nodal(sa);  // plane J+2
+    fetch_nodal(J + 3);
     __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
-// Quantization (Sec. 4.1): label = rint(c / q_l) in FP64; level of a
-// position in the level-centric layout = the smallest l whose box holds it.
+// Quantization (Sec. 4.1): label = rint(c / q_l) in FP64.
+// The level of a position in the level-centric layout is the smallest l whose
+// box holds it.  Along an axis with n - 1 = 2^m, the level-l box has
+// 2^(m-L+l) + 1 nodes, so position p >= 2 lies in level
+// max(first, bitlength(p-1) - (m - L)); positions 0 and 1 are in every box.
+// The array is processed flat, four consecutive elements per thread.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int axis_level(int p, const QuantArgs &a, int k) {
-  // sizes[k][i] = box size of level first+i along axis k (increasing)
-  int lev = a.first;
-  for (int i = 0; i < a.nlev - 1; i++)
-    if (p >= a.sizes[k][i]) lev = a.first + i + 1;
-  return lev;
+__device__ __forceinline__ int pos_level(uint32_t p, int off, int first) {
+  if (p < 2) return first;
+  const int bl = 32 - __clz((int)(p - 1));
+  return max(first, bl - off);
+}
+
+__device__ __forceinline__ int elem_level(uint32_t idx, const QuantArgs &a) {
+  // idx = (z * n1 + y) * n2 + x, all < 2^32; divisions by precomputed magics
+  const uint32_t row = (uint32_t)__umul64hi((uint64_t)idx, a.mag2);
+  const uint32_t x = idx - row * (uint32_t)a.n2;
+  const uint32_t z = a.n1 == 1 ? row : (uint32_t)__umul64hi((uint64_t)row, a.mag1);
+  const uint32_t y = row - z * (uint32_t)a.n1;
+  int l = pos_level(x, a.off[2], a.first);
+  l = max(l, pos_level(y, a.off[1], a.first));
+  l = max(l, pos_level(z, a.off[0], a.first));
+  return l;
 }
 
 template <typename T, bool STATS>
@@ -497,41 +770,59 @@ __global__ void __launch_bounds__(256) k_quantize(const T *__restrict__ umc, int
   }
   const int lane = threadIdx.x & 63;
   unsigned long long my_ovf = 0, my_nan = 0;
-  for (int64_t row = blockIdx.x; row < a.nrows; row += gridDim.x) {
-    const int z = (int)(row / a.n1), y = (int)(row - (int64_t)z * a.n1);
-    const int rl = max(axis_level(z, a, 0), axis_level(y, a, 1));
-    const T *src = umc + row * a.n2;
-    int32_t *dst = labels + row * a.n2;
-    for (int x0 = 0; x0 < a.n2; x0 += 256) {
-      const int x = x0 + threadIdx.x;
-      const bool in = x < a.n2;
-      int lev = a.first;
-      int absl = 0;
-      if (in) {
-        lev = max(rl, axis_level(x, a, 2));
-        const double qv = a.q[lev - a.first];
-        const double v = (double)src[x] / qv;
-        int32_t lab;
-        if (!(fabs(v) < 2147483647.0)) {
-          lab = INT32_MIN;
-          if (isnan(v) || isinf(v)) my_nan++;
-          else my_ovf++;
-        } else {
-          lab = (int32_t)rint(v);
-          absl = lab < 0 ? -lab : lab;
+  const uint32_t N = (uint32_t)a.n;
+  const uint32_t stride = gridDim.x * 256u * 4u;
+  for (uint32_t base = (blockIdx.x * 256u + threadIdx.x) * 4u; base < N; base += stride) {
+    T v[4];
+    if (base + 3 < N) {
+#pragma unroll
+      for (int e = 0; e < 4; e++) v[e] = umc[base + e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; e++) v[e] = base + e < N ? umc[base + e] : T(0);
+    }
+    int32_t lab[4];
+    int lev[4], absl[4];
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      lev[e] = base + e < N ? elem_level(base + e, a) : a.first;
+      const double qv = a.q[lev[e] - a.first];
+      const double t = (double)v[e] / qv;
+      absl[e] = 0;
+      if (!(fabs(t) < 2147483647.0)) {
+        lab[e] = INT32_MIN;
+        if (base + e < N) {
+          if (isnan(t) || isinf(t))
+            my_nan++;
+          else
+            my_ovf++;
         }
-        dst[x] = lab;
+      } else {
+        lab[e] = (int32_t)rint(t);
+        absl[e] = lab[e] < 0 ? -lab[e] : lab[e];
       }
-      if (STATS) {
-        // per-level wave reduction; usually one level per wave
+    }
+    if (base + 3 < N) {
+#pragma unroll
+      for (int e = 0; e < 4; e++) labels[base + e] = lab[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; e++)
+        if (base + e < N) labels[base + e] = lab[e];
+    }
+    if (STATS) {
+      // per-level maxima: reduce each distinct level present in the wave
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        const bool in = base + e < N;
         unsigned long long todo = __ballot(in);
         while (todo) {
           const int leader = __ffsll((long long)todo) - 1;
-          const int L0 = __shfl(lev, leader);
-          const bool mine = in && lev == L0;
-          int v = mine ? absl : 0;
-          for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
-          if (lane == leader) atomicMax(&s_max[L0 - a.first], v);
+          const int L0 = __shfl(lev[e], leader);
+          const bool mine = in && lev[e] == L0;
+          int m = mine ? absl[e] : 0;
+          for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off));
+          if (lane == leader) atomicMax(&s_max[L0 - a.first], m);
           todo &= ~__ballot(mine);
         }
       }
@@ -558,14 +849,21 @@ __global__ void __launch_bounds__(256) k_quantize(const T *__restrict__ umc, int
 template <typename T>
 __global__ void __launch_bounds__(256) k_dequantize(const int32_t *__restrict__ labels, T *__restrict__ umc,
                                                     QuantArgs a) {
-  for (int64_t row = blockIdx.x; row < a.nrows; row += gridDim.x) {
-    const int z = (int)(row / a.n1), y = (int)(row - (int64_t)z * a.n1);
-    const int rl = max(axis_level(z, a, 0), axis_level(y, a, 1));
-    const int32_t *src = labels + row * a.n2;
-    T *dst = umc + row * a.n2;
-    for (int x = threadIdx.x; x < a.n2; x += 256) {
-      const int lev = max(rl, axis_level(x, a, 2));
-      dst[x] = (T)((double)src[x] * a.q[lev - a.first]);
+  const uint32_t N = (uint32_t)a.n;
+  const uint32_t stride = gridDim.x * 256u * 4u;
+  for (uint32_t base = (blockIdx.x * 256u + threadIdx.x) * 4u; base < N; base += stride) {
+    int32_t lab[4];
+    if (base + 3 < N) {
+#pragma unroll
+      for (int e = 0; e < 4; e++) lab[e] = labels[base + e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; e++) lab[e] = base + e < N ? labels[base + e] : 0;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      const int lev = elem_level(base + e, a);
+      if (base + e < N) umc[base + e] = (T)((double)lab[e] * a.q[lev - a.first]);
     }
   }
 }
@@ -576,13 +874,28 @@ __global__ void __launch_bounds__(256) k_dequantize(const int32_t *__restrict__ 
 
 template <typename T>
 struct Tiles;
+#ifndef MGX_DEEP_CH
+#define MGX_DEEP_CH 32
+#endif
+#ifndef MGX_F32_TY
+#define MGX_F32_TY 16
+#endif
+#ifndef MGX_F32_NT
+#define MGX_F32_NT 256
+#endif
+#ifndef MGX_F64_TY
+#define MGX_F64_TY 16
+#endif
+#ifndef MGX_F64_NT
+#define MGX_F64_NT 256
+#endif
 template <>
 struct Tiles<float> {
-  static constexpr int TX = 32, TY = 16;
+  static constexpr int TX = 32, TY = MGX_F32_TY, NT = MGX_F32_NT;
 };
 template <>
 struct Tiles<double> {
-  static constexpr int TX = 16, TY = 16;
+  static constexpr int TX = 16, TY = MGX_F64_TY, NT = MGX_F64_NT;
 };
 
 // Tiles of TX x TY coarse columns/rows (the last tile takes the extra node of
@@ -597,7 +910,10 @@ static bool tile_grid(int c0, int c1, int c2, int TX, int TY, int *ntx, int *nty
   *nty = (c1 - 1) / TY > 0 ? (c1 - 1) / TY : 1;
   const int per = *ntx * *nty;
   int want = (2048 + per - 1) / per;
-  int maxz = c0 / 4 > 0 ? c0 / 4 : 1;
+  // large levels keep z-chunks of >= 8 coarse planes (halo re-reads stay
+  // small); small levels take one coarse plane per workgroup (latency bound)
+  const bool large = (int64_t)c0 * c1 * c2 >= (1 << 20);
+  int maxz = large ? (c0 / 8 > 0 ? c0 / 8 : 1) : c0;
   if (want > maxz) want = maxz;
   if (want < 1) want = 1;
   *nzc = want;
@@ -607,24 +923,24 @@ static bool tile_grid(int c0, int c1, int c2, int TX, int TY, int *ntx, int *nty
 
 template <typename T>
 hipError_t launch_load_vector(StencilArgs<T> a, bool dec, hipStream_t st) {
-  constexpr int TX = Tiles<T>::TX, TY = Tiles<T>::TY;
+  constexpr int TX = Tiles<T>::TX, TY = Tiles<T>::TY, NT = Tiles<T>::NT;
   if (!tile_grid(a.ax[0].c, a.ax[1].c, a.ax[2].c, TX, TY, &a.ntx, &a.nty, &a.nzc, &a.tz))
     return hipErrorInvalidValue;
   dim3 grid(a.ntx * a.nty * a.nzc);
   if (dec)
-    hipLaunchKernelGGL((k_load_vector<T, TX, TY, true>), grid, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_load_vector<T, TX, TY, NT, true>), grid, dim3(NT), 0, st, a);
   else
-    hipLaunchKernelGGL((k_load_vector<T, TX, TY, false>), grid, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_load_vector<T, TX, TY, NT, false>), grid, dim3(NT), 0, st, a);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_interp_add(InterpArgs<T> a, hipStream_t st) {
-  constexpr int TX = Tiles<T>::TX, TY = Tiles<T>::TY;
+  constexpr int TX = Tiles<T>::TX, TY = Tiles<T>::TY, NT = Tiles<T>::NT;
   if (!tile_grid(a.ax[0].c, a.ax[1].c, a.ax[2].c, TX, TY, &a.ntx, &a.nty, &a.nzc, &a.tz))
     return hipErrorInvalidValue;
   dim3 grid(a.ntx * a.nty * a.nzc);
-  hipLaunchKernelGGL((k_interp_add<T, TX, TY>), grid, dim3(256), 0, st, a);
+  hipLaunchKernelGGL((k_interp_add<T, TX, TY, NT>), grid, dim3(NT), 0, st, a);
   return hipGetLastError();
 }
 
@@ -655,13 +971,51 @@ hipError_t launch_solve_contig(SolveArgs<T> a, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <typename T, int C>
+static void launch_twisted_c(StridedArgs<T> a, bool apply, hipStream_t st) {
+  dim3 grid((unsigned)((a.nx + 127) / 128), (unsigned)a.nouter);
+  if (apply)
+    hipLaunchKernelGGL((k_solve_twisted<T, C, true>), grid, dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_solve_twisted<T, C, false>), grid, dim3(256), 0, st, a);
+}
+
 template <typename T>
 hipError_t launch_solve_strided(StridedArgs<T> a, bool apply, hipStream_t st) {
+  // two-ended register solve for lines that fit (half a line in registers)
+  switch (a.c) {
+    case 3: launch_twisted_c<T, 3>(a, apply, st); return hipGetLastError();
+    case 5: launch_twisted_c<T, 5>(a, apply, st); return hipGetLastError();
+    case 9: launch_twisted_c<T, 9>(a, apply, st); return hipGetLastError();
+    case 17: launch_twisted_c<T, 17>(a, apply, st); return hipGetLastError();
+    case 33: launch_twisted_c<T, 33>(a, apply, st); return hipGetLastError();
+    case 65: launch_twisted_c<T, 65>(a, apply, st); return hipGetLastError();
+    case 129: launch_twisted_c<T, 129>(a, apply, st); return hipGetLastError();
+    case 257:
+      if constexpr (sizeof(T) == 4) {
+        launch_twisted_c<T, 257>(a, apply, st);
+        return hipGetLastError();
+      }
+      break;
+    default: break;
+  }
   dim3 grid((unsigned)((a.nx + 255) / 256), (unsigned)a.nouter);
-  if (apply)
-    hipLaunchKernelGGL((k_solve_strided<T, true>), grid, dim3(256), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_solve_strided<T, false>), grid, dim3(256), 0, st, a);
+  // longer lines: chunked sweeps; few lines (one wave per SIMD or less) use
+  // deep chunks to keep enough loads in flight
+  const bool deep = (int64_t)a.nx * a.nouter < (1 << 18);
+  constexpr int CS = sizeof(T) == 8 ? 8 : 16;
+  constexpr int CD = sizeof(T) == 8 ? MGX_DEEP_CH / 2 : MGX_DEEP_CH;
+  if (apply) {
+    if (deep)
+      hipLaunchKernelGGL((k_solve_strided<T, true, CD>), grid, dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_solve_strided<T, true, CS>), grid, dim3(256), 0, st, a);
+  } else {
+    if (deep)
+      hipLaunchKernelGGL((k_solve_strided<T, false, CD>), grid, dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_solve_strided<T, false, CS>), grid, dim3(256), 0, st, a);
+  }
   return hipGetLastError();
 }
 
@@ -672,14 +1026,15 @@ hipError_t launch_apply(StridedArgs<T> a, hipStream_t st) {
   return hipGetLastError();
 }
 
-static unsigned quant_grid(int64_t nrows) {
-  int64_t g = nrows < 8192 ? nrows : 8192;
+static unsigned quant_grid(int64_t n) {
+  int64_t g = (n + 1023) / 1024;
+  if (g > 8192) g = 8192;
   return (unsigned)(g > 0 ? g : 1);
 }
 
 template <typename T>
 hipError_t launch_quantize(const T *umc, int32_t *labels, QuantArgs a, bool stats, hipStream_t st) {
-  dim3 grid(quant_grid(a.nrows));
+  dim3 grid(quant_grid(a.n));
   if (stats)
     hipLaunchKernelGGL((k_quantize<T, true>), grid, dim3(256), 0, st, umc, labels, a);
   else
@@ -689,7 +1044,7 @@ hipError_t launch_quantize(const T *umc, int32_t *labels, QuantArgs a, bool stat
 
 template <typename T>
 hipError_t launch_dequantize(const int32_t *labels, T *umc, QuantArgs a, hipStream_t st) {
-  dim3 grid(quant_grid(a.nrows));
+  dim3 grid(quant_grid(a.n));
   hipLaunchKernelGGL((k_dequantize<T>), grid, dim3(256), 0, st, labels, umc, a);
   return hipGetLastError();
 }

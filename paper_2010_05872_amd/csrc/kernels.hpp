@@ -15,6 +15,8 @@ struct AxisTab {
   const T *wl, *wr;               // interpolation weights at odd fine nodes [m]
   const T *w5;                    // load-vector stencil, 5 per coarse node [5c]
   const T *mult, *invd, *qsup;    // Thomas factors of the coarse mass matrix [c]
+  const T *multb, *invdb, *qsub;  // the same, eliminating from the last row [c]
+  const T *mid;                   // middle-row factors of the two-ended solve [3]
   int m, c;                       // fine and coarse node counts
 };
 
@@ -62,6 +64,7 @@ struct StridedArgs {          // strided-axis solve (optionally applying)
   int64_t so;                 // stride between outer lines
   int nouter;
   const T *mult, *invd, *qsup;
+  const T *multb, *invdb, *qsub, *mid;
   const T *in;                // apply: nodal in (index J*ij + o*io + x)
   int64_t ij, io;
   T *out;                     // apply: nodal out (index J*oj + o*oo + x)
@@ -70,10 +73,11 @@ struct StridedArgs {          // strided-axis solve (optionally applying)
 };
 
 struct QuantArgs {
-  int64_t nrows;              // n0 * n1
-  int n1, n2;
+  int64_t n;                  // element count (< 2^32)
+  int n1, n2;                 // padded dims 1 and 2
+  uint64_t mag1, mag2;        // ceil(2^64 / n1), ceil(2^64 / n2): exact 32-bit division
+  int off[3];                 // log2(n_k - 1) - L per axis (0 for padded axes)
   int first, nlev;            // levels first .. first+nlev-1
-  int sizes[3][kMaxLevelsK];  // box size of level first+i along each axis
   double q[kMaxLevelsK];      // bin width per level
   int *stats_max;             // [nlev] device
   unsigned long long *stats_ovf, *stats_nan;

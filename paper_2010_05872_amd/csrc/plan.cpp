@@ -115,6 +115,33 @@ void build_axis(const std::vector<double> &Y, AxisLevel &a, std::vector<double> 
   for (int64_t J = 0; J < c; J++) tab.push_back(1.0 / dp[J]);
   a.off_qsup = tab.size();
   for (int64_t J = 0; J < c; J++) tab.push_back(sup[J] / dp[J]);
+  // elimination from the last row upwards
+  std::vector<double> ep(c), multb(c, 0.0);
+  ep[c - 1] = dia[c - 1];
+  for (int64_t J = c - 2; J >= 0; J--) {
+    multb[J] = sup[J] / ep[J + 1];
+    ep[J] = dia[J] - multb[J] * sub[J + 1];
+  }
+  a.off_multb = tab.size();
+  for (int64_t J = 0; J < c; J++) tab.push_back(multb[J]);
+  a.off_invdb = tab.size();
+  for (int64_t J = 0; J < c; J++) tab.push_back(1.0 / ep[J]);
+  a.off_qsub = tab.size();
+  for (int64_t J = 0; J < c; J++) tab.push_back(sub[J] / ep[J]);
+  // the middle row K, where the two eliminations meet
+  const int64_t K = c / 2;
+  a.off_mid = tab.size();
+  if (c >= 3) {
+    const double al = sub[K] / dp[K - 1];
+    const double be = sup[K] / ep[K + 1];
+    tab.push_back(1.0 / (dia[K] - al * sup[K - 1] - be * sub[K + 1]));
+    tab.push_back(al);
+    tab.push_back(be);
+  } else {
+    tab.push_back(1.0 / dia[0]);
+    tab.push_back(0.0);
+    tab.push_back(0.0);
+  }
 }
 
 // Trivial tables of a padded axis (one node, identity operators).
@@ -133,6 +160,16 @@ void build_padded(AxisLevel &a, std::vector<double> &tab) {
   a.off_invd = tab.size();
   tab.push_back(1.0);
   a.off_qsup = tab.size();
+  tab.push_back(0.0);
+  a.off_multb = tab.size();
+  tab.push_back(0.0);
+  a.off_invdb = tab.size();
+  tab.push_back(1.0);
+  a.off_qsub = tab.size();
+  tab.push_back(0.0);
+  a.off_mid = tab.size();
+  tab.push_back(1.0);
+  tab.push_back(0.0);
   tab.push_back(0.0);
 }
 

@@ -10,7 +10,11 @@
 //   mult, invd, qsup  precomputed Thomas factors of the coarse mass matrix
 //           (Sec. 5.4, reuse of intermediate variables): forward
 //           f'_J = f_J - mult_J f'_{J-1}, backward
-//           y_J = invd_J f'_J - qsup_J y_{J+1}.
+//           y_J = invd_J f'_J - qsup_J y_{J+1},
+//   multb, invdb, qsub, mid  the same elimination run from the last row up
+//           (g'_J = f_J - multb_J g'_{J+1}, y_J = invdb_J g'_J - qsub_J y_{J-1})
+//           and the row K = c/2 where the two meet:
+//           y_K = mid[0] (f_K - mid[1] f'_{K-1} - mid[2] g'_{K+1}).
 // The common factor h_l of Sec. 5.4 needs no separate elimination: the
 // factors are tabulated once per axis and level, so no per-element product
 // with h_l remains.
@@ -33,6 +37,9 @@ struct AxisLevel {
   int64_t c = 1;       // coarse (level l-1) node count
   bool real = false;   // false for padded axes (ndim < 3)
   size_t off_wl = 0, off_wr = 0, off_w5 = 0, off_mult = 0, off_invd = 0, off_qsup = 0;
+  // factors of the elimination from the last row upwards and of the middle
+  // row, for the two-ended (twisted) factorization of the same matrix
+  size_t off_multb = 0, off_invdb = 0, off_qsub = 0, off_mid = 0;
 };
 
 struct Plan {

@@ -62,6 +62,10 @@ CASES = [
     ((1025,), torch.float64, None),
     ((8193,), torch.float64, "random"),
     ((33, 4097), torch.float32, None),
+    ((513, 9, 17), torch.float32, None),       # 257-long strided lines (two-ended solve)
+    ((17, 513, 33), torch.float32, "random"),
+    ((513, 9, 9), torch.float64, None),        # fp64 257-long strided lines (chunked sweeps)
+    ((9, 1025, 17), torch.float64, "tanh"),    # 513-long strided lines (chunked sweeps)
 ]
 
 
