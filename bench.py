@@ -109,6 +109,8 @@ def main():
     ap.add_argument("--n", type=int, default=513)
     ap.add_argument("--rel-tol", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain device copy of the field (counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -190,6 +192,11 @@ def main():
     traffic = measured_traffic(dom["name"], dom["level"], shape)
     total_alg = sum(algorithmic_bytes(k["name"], k["level"], shape, L, 4) * k["count"] for k in ktimes)
     kernel_sum_ms = sum(k["total_ms"] for k in ktimes) / args.steps
+
+    if args.copy_calibration:
+        # a plain copy kernel of known size (N * 4 bytes read, N * 4 written)
+        ut.copy_(u)
+        torch.cuda.synchronize()
 
     # ---- correctness of the measured run ----
     err = float((ut.double() - u.double()).abs().max().item())

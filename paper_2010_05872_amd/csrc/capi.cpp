@@ -117,81 +117,60 @@ AxisTab<T> axis_tab(const Plan *P, int l, int k, const T *tab) {
   return t;
 }
 
-// The three coarse solves of one level on F (c0 x c1 x c2, pitches fp0,fp1),
-// the last one applying out = in + sign * correction.
+// The coarse solves of one level on F (c0 x c1 x c2, pitches fp0,fp1), one
+// per real axis, the contiguous axis first.  The last one either stores the
+// solution (decomposition: out = Q_{l-1} u) or applies it to the nodal
+// values (recomposition: out = in - correction).
 template <typename T>
-hipError_t solve_and_apply(int level, const AxisTab<T> ax[3], const bool real[3], T *F, int64_t fp0,
-                           int64_t fp1, const T *in, int64_t ip0, int64_t ip1, T *out, int64_t op0, int64_t op1,
-                           T sign, hipStream_t st) {
+hipError_t solve_level(int level, const AxisTab<T> ax[3], const bool real[3], T *F, int64_t fp0, int64_t fp1,
+                       int last_mode, const T *in, int64_t ip0, int64_t ip1, T *out, int64_t op0, int64_t op1,
+                       hipStream_t st) {
   const int c0 = ax[0].c, c1 = ax[1].c, c2 = ax[2].c;
   hipError_t e;
-  // contiguous axis (always real)
   {
     SolveArgs<T> s{F, (int64_t)c0 * c1, fp1, c2, ax[2].mult, ax[2].invd, ax[2].qsup};
     if ((e = traced("solve_contig", level, st, [&] { return launch_solve_contig<T>(s, st); })) != hipSuccess)
       return e;
   }
-  if (!real[1]) {  // 1-D: apply the solved row
+  const T sign = T(-1);
+  if (!real[1]) {  // 1-D: the solved row is the result
     StridedArgs<T> s{};
     s.F = F;
     s.nx = c2;
-    s.in = in;
+    s.in = last_mode == kSolveApply ? in : nullptr;
     s.out = out;
     s.sign = sign;
-    return traced("apply", level, st, [&] { return launch_apply<T>(s, st); });
+    return traced("finish_1d", level, st, [&] { return launch_apply<T>(s, st); });
   }
-  {
+  auto strided = [&](int k, int mode, const char *name) {
     StridedArgs<T> s{};
     s.F = F;
-    s.c = c1;
-    s.sj = fp1;
+    s.c = ax[k].c;
+    s.sj = k == 1 ? fp1 : fp0;  // line stride
     s.nx = c2;
-    s.so = fp0;
-    s.nouter = c0;
-    s.mult = ax[1].mult;
-    s.invd = ax[1].invd;
-    s.qsup = ax[1].qsup;
-    s.multb = ax[1].multb;
-    s.invdb = ax[1].invdb;
-    s.qsub = ax[1].qsub;
-    s.mid = ax[1].mid;
-    const bool apply = !real[0];
-    if (apply) {  // 2-D: line index Y, outer Z (= 0)
+    s.so = k == 1 ? fp0 : fp1;  // outer stride (plane for the y solve, row for the z solve)
+    s.nouter = k == 1 ? c0 : c1;
+    s.mult = ax[k].mult;
+    s.invd = ax[k].invd;
+    s.qsup = ax[k].qsup;
+    s.multb = ax[k].multb;
+    s.invdb = ax[k].invdb;
+    s.qsub = ax[k].qsub;
+    s.mid = ax[k].mid;
+    if (mode != kSolveInPlace) {
       s.in = in;
-      s.ij = ip1;
-      s.io = ip0;
+      s.ij = k == 1 ? ip1 : ip0;
+      s.io = k == 1 ? ip0 : ip1;
       s.out = out;
-      s.oj = op1;
-      s.oo = op0;
+      s.oj = k == 1 ? op1 : op0;
+      s.oo = k == 1 ? op0 : op1;
       s.sign = sign;
     }
-    e = traced(apply ? "solve_strided_apply" : "solve_strided", level, st,
-               [&] { return launch_solve_strided<T>(s, apply, st); });
-    if (e != hipSuccess) return e;
-    if (apply) return hipSuccess;
-  }
-  StridedArgs<T> s{};
-  s.F = F;
-  s.c = c0;
-  s.sj = fp0;
-  s.nx = c2;
-  s.so = fp1;
-  s.nouter = c1;
-  s.mult = ax[0].mult;
-  s.invd = ax[0].invd;
-  s.qsup = ax[0].qsup;
-  s.multb = ax[0].multb;
-  s.invdb = ax[0].invdb;
-  s.qsub = ax[0].qsub;
-  s.mid = ax[0].mid;
-  s.in = in;
-  s.ij = ip0;
-  s.io = ip1;
-  s.out = out;
-  s.oj = op0;
-  s.oo = op1;
-  s.sign = sign;
-  return traced("solve_strided_apply", level, st, [&] { return launch_solve_strided<T>(s, true, st); });
+    return traced(name, level, st, [&] { return launch_solve_strided<T>(s, mode, st); });
+  };
+  if (!real[0]) return strided(1, last_mode, "solve_strided_last");  // 2-D
+  if ((e = strided(1, kSolveInPlace, "solve_strided")) != hipSuccess) return e;
+  return strided(0, last_mode, "solve_strided_last");
 }
 
 template <typename T>
@@ -207,7 +186,6 @@ mgx_status run_decompose(Plan *P, int stop, const T *u, T *umc, char *ws, const 
   for (int l = L; l > stop; l--) {
     AxisTab<T> ax[3] = {axis_tab(P, l, 0, tab), axis_tab(P, l, 1, tab), axis_tab(P, l, 2, tab)};
     const int c1 = ax[1].c, c2 = ax[2].c;
-    T *dst = ((L - 1 - (l - 1)) % 2 == 0) ? A : B;  // holds level l-1
     const int64_t cp1 = c2, cp0 = (int64_t)c1 * c2;
     const int64_t fp1 = round4(c2), fp0 = (int64_t)c1 * fp1;
     StencilArgs<T> s{};
@@ -218,18 +196,17 @@ mgx_status run_decompose(Plan *P, int stop, const T *u, T *umc, char *ws, const 
     s.umc_w = umc;
     s.up0 = up0;
     s.up1 = up1;
-    s.Vc = dst;
-    s.cp0 = cp0;
-    s.cp1 = cp1;
     s.F = F;
     s.fp0 = fp0;
     s.fp1 = fp1;
     hipError_t e = traced("load_vector_dec", l, st, [&] { return launch_load_vector<T>(s, true, st); });
     if (e != hipSuccess) return MGX_ERR_HIP;
+    // Q_{l-1} u goes to the compact box of level l-1, or into the corner of
+    // u_mc after the last decomposed level
     const bool last = (l == stop + 1);
-    T *out = last ? umc : dst;
+    T *dst = last ? umc : (((L - 1 - (l - 1)) % 2 == 0) ? A : B);
     const int64_t op0 = last ? up0 : cp0, op1 = last ? up1 : cp1;
-    e = solve_and_apply<T>(l, ax, P->real, F, fp0, fp1, dst, cp0, cp1, out, op0, op1, T(1), st);
+    e = solve_level<T>(l, ax, P->real, F, fp0, fp1, kSolveStore, nullptr, 0, 0, dst, op0, op1, st);
     if (e != hipSuccess) return MGX_ERR_HIP;
     src = dst;
     sp0 = cp0;
@@ -266,7 +243,7 @@ mgx_status run_recompose(Plan *P, int stop, const T *umc, T *u, char *ws, const 
     s.fp1 = fp1;
     hipError_t e = traced("load_vector_rec", l, st, [&] { return launch_load_vector<T>(s, false, st); });
     if (e != hipSuccess) return MGX_ERR_HIP;
-    e = solve_and_apply<T>(l, ax, P->real, F, fp0, fp1, nin, ip0, ip1, nb, cp0, cp1, T(-1), st);
+    e = solve_level<T>(l, ax, P->real, F, fp0, fp1, kSolveApply, nin, ip0, ip1, nb, cp0, cp1, st);
     if (e != hipSuccess) return MGX_ERR_HIP;
     InterpArgs<T> ia{};
     for (int k = 0; k < 3; k++) ia.ax[k] = ax[k];

@@ -40,6 +40,13 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return base + idx;
 }
 
+// Column of region column q in a de-interleaved LDS row: even columns first,
+// then odd ones (stride-1 reads in the restriction along x).
+template <int TX>
+__device__ __forceinline__ int zcol(int q) {
+  return (q & 1) ? (TX + 3) + (q >> 1) : (q >> 1);
+}
+
 __device__ __forceinline__ int64_t lc_pos(int j, int c) {
   // level-centric position of level index j on an axis with c coarse nodes
   return (j & 1) ? (int64_t)c + (j >> 1) : (int64_t)(j >> 1);
@@ -54,34 +61,47 @@ __device__ __forceinline__ int opaque(int v) {
 }
 
 // ---------------------------------------------------------------------------
-// k_load_vector: coefficients + load vector of one level
+// k_load_vector: load vector of one level (+ coefficients when decomposing)
 // ---------------------------------------------------------------------------
+//
+// DEC: reads the level box V = Q_l u and
+//   - writes the coefficients c = V - Pi_{l-1} V of the nodes in N*_l to
+//     their level-centric positions (Sec. 2 steps 2-3, Sec. 5.1), and
+//   - writes the load vector F = (R M)^{x3} V of V itself.  The solves then
+//     give M_c^{-1} F = Q_{l-1} u directly: the correction of Sec. 2 step 4
+//     equals Q_{l-1}u - Pi_{l-1}Q_l u, and R M P = M_c, so nodal values plus
+//     correction is the L2 projection of V (identical up to rounding).
+// REC: reads the stored coefficients z (zero on N_{l-1}) and writes
+//   F = (R M)^{x3} z, whose solve is the correction of recomposition.
 //
 // Tile: coarse columns [X0,X1) x rows [Y0,Y1) x planes [Z0,Z1); the last tile
 // along an axis also takes the final coarse node (c = 2^k+1).  The fine
-// region needed is [2Y0-2, 2Y1] x [2X0-2, 2X1] (stencil reach 2); fine nodes
-// owned (written) by the tile are [2Y0, min(2Y1,m1)) etc.  The kernel
-// marches over fine planes j = 2Z0-2 .. 2Z1; plane j adds its yx-restricted
-// values into the load vector of the up to three coarse planes it touches.
-//
-// Every thread owns the same NE region elements in every plane; the next
-// plane's values are fetched into registers while the current plane is
-// processed (one memory latency per plane, overlapped with compute), then
-// committed to LDS.  Two workgroup barriers per plane.
+// region read is [2Y0-2, 2Y1] x [2X0-2, 2X1] (restriction reach 2); the
+// coefficients written are those of the owned nodes [2Y0, min(2Y1,m1)) x
+// [2X0, min(2X1,m2)) of the owned planes.  The kernel marches over fine
+// planes j = 2Z0-2 .. 2Z1; plane j adds its yx-restricted values into the
+// load vector of the up to three coarse planes it touches.  Rows are stored
+// de-interleaved in LDS (even columns first), so both the restriction and
+// the interpolation corners read consecutive LDS words.  Planes are fetched
+// two iterations ahead into double-buffered registers.
 template <typename T, int TX, int TY, int NT, bool DEC>
 __global__ void __launch_bounds__(NT) k_load_vector(StencilArgs<T> a) {
   constexpr int HR = 2 * TY + 5;  // region rows incl. halo and the extension
   constexpr int W = 2 * TX + 5;   // region row pitch
+  constexpr int E = TX + 3;       // even columns of a region row
   constexpr int GW = TX + 1;      // coarse columns per tile (max)
   constexpr int GH = TY + 1;      // coarse rows per tile (max)
+  constexpr int OW = 2 * TX + 2;  // owned fine columns (max)
+  constexpr int OH = 2 * TY + 2;  // owned fine rows (max)
   constexpr int NE = (HR * W + NT - 1) / NT;
+  constexpr int NC = (OH * OW + NT - 1) / NT;
   constexpr int NOUT = (GH * GW + NT - 1) / NT;
-  constexpr int NV = DEC ? 3 : 1;
+  constexpr int NV = DEC ? 3 : 1;        // planes kept in LDS
+  constexpr int AHEAD = DEC ? 2 : 1;     // plane committed at iteration j is j + AHEAD
 
   __shared__ T sV[NV][HR * W];
-  __shared__ T sZ[HR * W];
   __shared__ T sG[HR * GW];
-  __shared__ T sWxl[W], sWxr[W], sWyl[HR], sWyr[HR];
+  __shared__ T sWxl[OW], sWxr[OW], sWyl[OH], sWyr[OH];
   __shared__ T sW5x[GW * 5], sW5y[GH * 5];
 
   const int tid = threadIdx.x;
@@ -96,29 +116,26 @@ __global__ void __launch_bounds__(NT) k_load_vector(StencilArgs<T> a) {
   const int Y0 = ty * TY, Y1 = (ty == a.nty - 1) ? c1 : Y0 + TY;
   const int Z0 = tz * a.tz, Z1 = (tz == a.nzc - 1) ? c0 : Z0 + a.tz;
   const int nX = X1 - X0, nY = Y1 - Y0;
-  const int r0 = 2 * Y0 - 2, q0 = 2 * X0 - 2;  // fine row / column at local 0 (even)
+  const int r0 = 2 * Y0 - 2, q0 = 2 * X0 - 2;  // fine row / column at region 0 (even)
   const int nr = 2 * nY + 3, nq = 2 * nX + 3;
-  const int own_r0 = 2 * Y0, own_r1 = min(2 * Y1, m1);
-  const int own_q0 = 2 * X0, own_q1 = min(2 * X1, m2);
+  const int fr = min(2 * Y1, m1) - 2 * Y0;  // owned fine rows
+  const int fq = min(2 * X1, m2) - 2 * X0;  // owned fine columns
   const int own_p0 = 2 * Z0, own_p1 = min(2 * Z1, m0);
 
-  // stage per-tile weights
-  for (int q = tid; q < nq; q += NT) {
-    int j2 = q0 + q;
-    bool in = j2 >= 0 && j2 < m2;
-    sWxl[q] = in ? a.ax[2].wl[j2] : T(0);
-    sWxr[q] = in ? a.ax[2].wr[j2] : T(0);
-  }
-  for (int r = tid; r < nr; r += NT) {
-    int j1 = r0 + r;
-    bool in = j1 >= 0 && j1 < m1;
-    sWyl[r] = in ? a.ax[1].wl[j1] : T(0);
-    sWyr[r] = in ? a.ax[1].wr[j1] : T(0);
+  if (DEC) {
+    for (int q = tid; q < fq; q += NT) {
+      sWxl[q] = a.ax[2].wl[2 * X0 + q];
+      sWxr[q] = a.ax[2].wr[2 * X0 + q];
+    }
+    for (int r = tid; r < fr; r += NT) {
+      sWyl[r] = a.ax[1].wl[2 * Y0 + r];
+      sWyr[r] = a.ax[1].wr[2 * Y0 + r];
+    }
   }
   for (int i = tid; i < nX * 5; i += NT) sW5x[i] = a.ax[2].w5[X0 * 5 + i];
   for (int i = tid; i < nY * 5; i += NT) sW5y[i] = a.ax[1].w5[Y0 * 5 + i];
 
-  // element k of this thread: region index tid + NT k, valid if inside the
+  // region element k of this thread: index tid + NT k; valid if inside the
   // region and the level box
   unsigned valid = 0;
 #pragma unroll
@@ -130,9 +147,8 @@ __global__ void __launch_bounds__(NT) k_load_vector(StencilArgs<T> a) {
     valid |= (unsigned)in << k;
   }
 
-  T stage[NE];
   // issue the loads of fine plane j into registers (zeros outside)
-  auto fetch = [&](int j) {
+  auto fetch = [&](int j, T (&st)[NE]) {
     const bool pin = j >= 0 && j < m0;
     if (DEC) {
       const T *base = a.V + (int64_t)(pin ? j : 0) * a.vp0;
@@ -141,7 +157,7 @@ __global__ void __launch_bounds__(NT) k_load_vector(StencilArgs<T> a) {
         const int idx = opaque(tid) + NT * k;
         const int r = idx / W, q = idx - r * W;
         const bool ok = pin && ((valid >> k) & 1u);
-        stage[k] = ok ? base[(int64_t)(r0 + r) * a.vp1 + (q0 + q)] : T(0);
+        st[k] = ok ? base[(uint32_t)(r0 + r) * (uint32_t)a.vp1 + (uint32_t)(q0 + q)] : T(0);
       }
     } else {
       const T *base = a.umc_r + (pin ? lc_pos(j, c0) : 0) * a.up0;
@@ -153,10 +169,21 @@ __global__ void __launch_bounds__(NT) k_load_vector(StencilArgs<T> a) {
         const int j1 = r0 + r, j2 = q0 + q;
         // nodal nodes (all indices even) carry no multilevel component
         const bool ok = pin && ((valid >> k) & 1u) && (jodd | (j1 & 1) | (j2 & 1));
-        stage[k] = ok ? base[lc_pos(j1, c1) * a.up1 + lc_pos(j2, c2)] : T(0);
+        st[k] = ok ? base[(uint32_t)lc_pos(j1, c1) * (uint32_t)a.up1 + (uint32_t)lc_pos(j2, c2)] : T(0);
       }
     }
   };
+  auto commit = [&](int slot, const T (&st)[NE]) {
+#pragma unroll
+    for (int k = 0; k < NE; k++) {
+      const int idx = opaque(tid) + NT * k;
+      if (idx < HR * W) {
+        const int r = idx / W, q = idx - r * W;
+        sV[slot][r * W + zcol<TX>(q)] = st[k];
+      }
+    }
+  };
+  auto slot_of = [&](int j) { return DEC ? (j + 3) % 3 : 0; };
 
   T acc[3][NOUT];
 #pragma unroll
@@ -164,88 +191,63 @@ __global__ void __launch_bounds__(NT) k_load_vector(StencilArgs<T> a) {
 #pragma unroll
     for (int k = 0; k < NOUT; k++) acc[s][k] = T(0);
 
-  const int jstart = 2 * Z0 - 2, jend = 2 * Z1;
-  if (DEC) {
-    fetch(jstart);
-#pragma unroll
-    for (int k = 0; k < NE; k++)
-      if (tid + NT * k < HR * W) sV[(jstart + 3) % 3][tid + NT * k] = stage[k];
-    fetch(jstart + 1);
-#pragma unroll
-    for (int k = 0; k < NE; k++)
-      if (tid + NT * k < HR * W) sV[(jstart + 4) % 3][tid + NT * k] = stage[k];
-    fetch(jstart + 2);
-    __syncthreads();
-  } else {
-    fetch(jstart);
-  }
-
-  for (int j = jstart; j <= jend; j++) {
+  // one plane of the march; st holds plane j + AHEAD on entry and receives
+  // plane j + AHEAD + 2 on exit
+  auto plane = [&](int j, T (&st)[NE]) {
     const bool plane_in = (j >= 0 && j < m0);
     const int pz = j & 1;
-    if (DEC) {
-      // ---- multilevel component z of plane j into sZ, plus the stores ----
-      if (plane_in) {
-        const int s0 = (j + 3) % 3;
-        const int sa = pz ? (j + 2) % 3 : s0;  // plane j-1 for odd j
-        const int sb = pz ? (j + 4) % 3 : s0;  // plane j+1 for odd j
-        const T wzl = pz ? a.ax[0].wl[j] : T(1);
-        const T wzr = pz ? a.ax[0].wr[j] : T(0);
-        const bool own_plane = (j >= own_p0 && j < own_p1);
-        const int64_t pz_off = lc_pos(j, c0) * a.up0;
-#pragma unroll
-        for (int k = 0; k < NE; k++) {
-          const int idx = opaque(tid) + NT * k;
-          if (idx >= HR * W) break;
-          const int r = idx / W, q = idx - r * W;
-          const int j1 = r0 + r, j2 = q0 + q;
-          const int py = r & 1, px = q & 1;
-          T z = T(0);
-          if ((valid >> k) & 1u) {
-            const T v = sV[s0][idx];
-            const bool own = own_plane && j1 >= own_r0 && j1 < own_r1 && j2 >= own_q0 && j2 < own_q1;
-            if (pz | py | px) {
-              // 2x2x2 corner stencil with zero weights on even axes
-              const T wyl = py ? sWyl[r] : T(1), wyr = py ? sWyr[r] : T(0);
-              const T wxl = px ? sWxl[q] : T(1), wxr = px ? sWxr[q] : T(0);
-              const int ia = (r - py) * W + (q - px), ib = (r - py) * W + (q + px);
-              const int ic = (r + py) * W + (q - px), id = (r + py) * W + (q + px);
-              const T pa = wyl * (wxl * sV[sa][ia] + wxr * sV[sa][ib]) + wyr * (wxl * sV[sa][ic] + wxr * sV[sa][id]);
-              const T pb = wyl * (wxl * sV[sb][ia] + wxr * sV[sb][ib]) + wyr * (wxl * sV[sb][ic] + wxr * sV[sb][id]);
-              z = v - (wzl * pa + wzr * pb);
-              if (own) a.umc_w[pz_off + lc_pos(j1, c1) * a.up1 + lc_pos(j2, c2)] = z;
-            } else if (own) {
-              a.Vc[(int64_t)(j >> 1) * a.cp0 + (int64_t)(j1 >> 1) * a.cp1 + (j2 >> 1)] = v;
-            }
-          }
-          sZ[idx] = z;
-        }
-      }
-      __syncthreads();
-      // commit plane j+2 into the slot of plane j-1 (no longer read)
-#pragma unroll
-      for (int k = 0; k < NE; k++)
-        if (tid + NT * k < HR * W) sV[(j + 5) % 3][tid + NT * k] = stage[k];
-    } else {
-#pragma unroll
-      for (int k = 0; k < NE; k++)
-        if (tid + NT * k < HR * W) sZ[tid + NT * k] = stage[k];
-      fetch(j + 1);
-      __syncthreads();
-    }
-    // ---- restriction along x: sG[r][X] ----
+    const int s0 = slot_of(j);
+    // ---- restriction along x of plane j: sG[r][X] ----
     if (plane_in) {
       for (int idx = tid; idx < nr * GW; idx += NT) {
         const int r = idx / GW, X = idx - r * GW;
         if (X < nX) {
-          const int b = r * W + 2 * X;
+          // fine columns 2X..2X+4 of the region: even ones at X, X+1, X+2,
+          // odd ones at E+X, E+X+1
+          const int b = r * W + X;
           const T *w = sW5x + X * 5;
-          sG[idx] = w[0] * sZ[b] + w[1] * sZ[b + 1] + w[2] * sZ[b + 2] + w[3] * sZ[b + 3] + w[4] * sZ[b + 4];
+          sG[idx] = w[0] * sV[s0][b] + w[1] * sV[s0][b + E] + w[2] * sV[s0][b + 1] + w[3] * sV[s0][b + E + 1] +
+                    w[4] * sV[s0][b + 2];
+        }
+      }
+    }
+    // ---- coefficients of the owned nodes of plane j (decomposition) ----
+    if (DEC && plane_in && j >= own_p0 && j < own_p1) {
+      T *const cbase = a.umc_w + lc_pos(j, c0) * a.up0;
+      const uint32_t up1 = (uint32_t)a.up1;
+      const int sa = pz ? (j + 2) % 3 : s0;  // plane j-1 for odd j
+      const int sb = pz ? (j + 4) % 3 : s0;  // plane j+1 for odd j
+      const T wzl = pz ? a.ax[0].wl[j] : T(1);
+      const T wzr = pz ? a.ax[0].wr[j] : T(0);
+#pragma unroll
+      for (int k = 0; k < NC; k++) {
+        const int idx = opaque(tid) + NT * k;
+        const int rr = idx / OW, qq = idx - rr * OW;
+        if (idx < OH * OW && rr < fr && qq < fq) {
+          const int py = rr & 1, px = qq & 1;
+          if (pz | py | px) {
+            const int r = rr + 2, q = qq + 2;  // region coordinates
+            const T v = sV[s0][r * W + zcol<TX>(q)];
+            // corners: rows r -+ py, even columns (q >> 1) and (q >> 1) + px
+            const int ra = (r - py) * W + (q >> 1), rb = (r + py) * W + (q >> 1);
+            const T wyl = py ? sWyl[rr] : T(1), wyr = py ? sWyr[rr] : T(0);
+            const T wxl = px ? sWxl[qq] : T(1), wxr = px ? sWxr[qq] : T(0);
+            T pa = wyl * (wxl * sV[sa][ra] + wxr * sV[sa][ra + px]) + wyr * (wxl * sV[sa][rb] + wxr * sV[sa][rb + px]);
+            if (pz) {
+              const T pb =
+                  wyl * (wxl * sV[sb][ra] + wxr * sV[sb][ra + px]) + wyr * (wxl * sV[sb][rb] + wxr * sV[sb][rb + px]);
+              pa = wzl * pa + wzr * pb;
+            }
+            const int j1 = 2 * Y0 + rr, j2 = 2 * X0 + qq;
+            cbase[(uint32_t)lc_pos(j1, c1) * up1 + (uint32_t)lc_pos(j2, c2)] = v - pa;
+          }
         }
       }
     }
     __syncthreads();
-    if (DEC) fetch(j + 3);
+    // plane j + AHEAD replaces the slot no longer read (j - 1 for DEC, j for REC)
+    commit(slot_of(j + AHEAD), st);
+    fetch(j + AHEAD + 2, st);
     // ---- restriction along y, accumulation along z ----
     if (plane_in) {
       const int Jc = j >> 1;  // j even: Z = Jc-1, Jc, Jc+1; j odd: Z = Jc, Jc+1
@@ -293,7 +295,27 @@ __global__ void __launch_bounds__(NT) k_load_vector(StencilArgs<T> a) {
         acc[2][k] = T(0);
       }
     }
+    __syncthreads();
+  };
+
+  const int jstart = 2 * Z0 - 2, jend = 2 * Z1;  // both even
+  T stA[NE], stB[NE];
+  // prologue: planes jstart .. jstart+AHEAD-1 in LDS, the next two in registers
+  fetch(jstart, stA);
+  commit(slot_of(jstart), stA);
+  if (DEC) {
+    fetch(jstart + 1, stA);
+    commit(slot_of(jstart + 1), stA);
   }
+  fetch(jstart + AHEAD, stA);
+  fetch(jstart + AHEAD + 1, stB);
+  __syncthreads();
+  int j = jstart;
+  for (; j + 1 <= jend; j += 2) {
+    plane(j, stA);
+    plane(j + 1, stB);
+  }
+  plane(j, stA);  // the last (even) plane
 }
 
 // ---------------------------------------------------------------------------
@@ -400,8 +422,9 @@ __global__ void __launch_bounds__(256) k_solve_contig(SolveArgs<T> a) {
 // APPLY the solution is not stored but added (sign +1, decomposition) or
 // subtracted (sign -1, recomposition) to the nodal values: out = in + sign*y.
 // ---------------------------------------------------------------------------
-template <typename T, bool APPLY, int CH>
+template <typename T, int MODE, int CH>
 __global__ void __launch_bounds__(256) k_solve_strided(StridedArgs<T> a) {
+  constexpr bool APPLY = MODE == kSolveApply;
   const int x = blockIdx.x * 256 + threadIdx.x;
   const int o = blockIdx.y;
   if (x >= a.nx) return;
@@ -469,6 +492,8 @@ __global__ void __launch_bounds__(256) k_solve_strided(StridedArgs<T> a) {
       if (J < c) {
         if (APPLY)
           a.out[(int64_t)J * a.oj + (int64_t)o * a.oo + x] = iv[k] + a.sign * v[k];
+        else if (MODE == kSolveStore)
+          a.out[(int64_t)J * a.oj + (int64_t)o * a.oo + x] = v[k];
         else
           p[(int64_t)J * s] = v[k];
       }
@@ -493,7 +518,7 @@ __global__ void __launch_bounds__(256) k_solve_strided(StridedArgs<T> a) {
 // once; the row index is uniform per wave, so row offsets and the factor
 // tables are scalar operands.
 // ---------------------------------------------------------------------------
-template <typename T, int C, bool APPLY>
+template <typename T, int C, int MODE>
 __global__ void __launch_bounds__(256) k_solve_twisted(StridedArgs<T> a) {
   constexpr int K = C / 2;
   __shared__ T sE[2][128];
@@ -547,25 +572,28 @@ __global__ void __launch_bounds__(256) k_solve_twisted(StridedArgs<T> a) {
     }
   }
   if (!active) return;
-  if (APPLY) {
+  if (MODE == kSolveApply || MODE == kSolveStore) {
     const T *in = a.in + (int64_t)o * a.io + x;
     T *out = a.out + (int64_t)o * a.oo + x;
     constexpr int CHA = 16;
 #pragma unroll
     for (int i0 = 0; i0 < K; i0 += CHA) {
       T iv[CHA];
+      if (MODE == kSolveApply) {
 #pragma unroll
-      for (int k = 0; k < CHA; k++) {
-        const int i = i0 + k;
-        if (i < K) iv[k] = in[(int64_t)(half ? C - 1 - i : i) * a.ij];
+        for (int k = 0; k < CHA; k++) {
+          const int i = i0 + k;
+          if (i < K) iv[k] = in[(int64_t)(half ? C - 1 - i : i) * a.ij];
+        }
       }
 #pragma unroll
       for (int k = 0; k < CHA; k++) {
         const int i = i0 + k;
-        if (i < K) out[(int64_t)(half ? C - 1 - i : i) * a.oj] = iv[k] + a.sign * r[i];
+        if (i < K)
+          out[(int64_t)(half ? C - 1 - i : i) * a.oj] = MODE == kSolveApply ? iv[k] + a.sign * r[i] : r[i];
       }
     }
-    if (!half) out[(int64_t)K * a.oj] = in[(int64_t)K * a.ij] + a.sign * yK;
+    if (!half) out[(int64_t)K * a.oj] = MODE == kSolveApply ? in[(int64_t)K * a.ij] + a.sign * yK : yK;
   } else {
     if (!half) {
 #pragma unroll
@@ -578,13 +606,13 @@ __global__ void __launch_bounds__(256) k_solve_twisted(StridedArgs<T> a) {
   }
 }
 
-// Correction application for one-dimensional fields (no strided solve):
-// out = in + sign * F over a row of the coarse box.
+// Last step for one-dimensional fields (no strided solve): out = in + sign * F
+// (recomposition) or out = F (decomposition) over a row of the coarse box.
 template <typename T>
 __global__ void __launch_bounds__(256) k_apply(StridedArgs<T> a) {
   const int x = blockIdx.x * 256 + threadIdx.x;
   if (x >= a.nx) return;
-  a.out[x] = a.in[x] + a.sign * a.F[x];
+  a.out[x] = a.in ? a.in[x] + a.sign * a.F[x] : a.F[x];
 }
 
 // ---------------------------------------------------------------------------
@@ -648,7 +676,7 @@ __global__ void __launch_bounds__(NT) k_interp_add(InterpArgs<T> a) {
       const int idx = opaque(tid) + NT * k;
       const int r = idx / NW, q = idx - r * NW;
       const bool ok = pin && idx < NH * NW && r < ncy && q < ncx;
-      nst[k] = ok ? src[(int64_t)(Y0 + r) * a.np1 + X0 + q] : T(0);
+      nst[k] = ok ? src[(uint32_t)(Y0 + r) * (uint32_t)a.np1 + (uint32_t)(X0 + q)] : T(0);
     }
   };
   T cf[2][NO];
@@ -664,7 +692,7 @@ __global__ void __launch_bounds__(NT) k_interp_add(InterpArgs<T> a) {
         const int rr = idx / OW, qq = idx - rr * OW;
         const int j1 = 2 * Y0 + rr, j2 = 2 * X0 + qq;
         const bool ok = pin && ((ownmask >> k) & 1u) && (pz | (j1 & 1) | (j2 & 1));
-        cf[pz][k] = ok ? base[lc_pos(j1, c1) * a.up1 + lc_pos(j2, c2)] : T(0);
+        cf[pz][k] = ok ? base[(uint32_t)lc_pos(j1, c1) * (uint32_t)a.up1 + (uint32_t)lc_pos(j2, c2)] : T(0);
       }
     }
   };
@@ -719,7 +747,7 @@ __global__ void __launch_bounds__(NT) k_interp_add(InterpArgs<T> a) {
         } else {
           outv = sN[sa][ra + qa];
         }
-        outp[(int64_t)j1 * a.op1 + j2] = outv;
+        outp[(uint32_t)j1 * (uint32_t)a.op1 + (uint32_t)j2] = outv;
       }
     }
     __syncthreads();  // slot sa (plane J) is free
@@ -881,7 +909,7 @@ struct Tiles;
 #define MGX_F32_TY 16
 #endif
 #ifndef MGX_F32_NT
-#define MGX_F32_NT 256
+#define MGX_F32_NT 512
 #endif
 #ifndef MGX_F64_TY
 #define MGX_F64_TY 16
@@ -972,50 +1000,55 @@ hipError_t launch_solve_contig(SolveArgs<T> a, hipStream_t st) {
 }
 
 template <typename T, int C>
-static void launch_twisted_c(StridedArgs<T> a, bool apply, hipStream_t st) {
+static void launch_twisted_c(StridedArgs<T> a, int mode, hipStream_t st) {
   dim3 grid((unsigned)((a.nx + 127) / 128), (unsigned)a.nouter);
-  if (apply)
-    hipLaunchKernelGGL((k_solve_twisted<T, C, true>), grid, dim3(256), 0, st, a);
+  if (mode == kSolveApply)
+    hipLaunchKernelGGL((k_solve_twisted<T, C, kSolveApply>), grid, dim3(256), 0, st, a);
+  else if (mode == kSolveStore)
+    hipLaunchKernelGGL((k_solve_twisted<T, C, kSolveStore>), grid, dim3(256), 0, st, a);
   else
-    hipLaunchKernelGGL((k_solve_twisted<T, C, false>), grid, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_solve_twisted<T, C, kSolveInPlace>), grid, dim3(256), 0, st, a);
+}
+
+template <typename T, int CH>
+static void launch_chunked(StridedArgs<T> a, int mode, hipStream_t st) {
+  dim3 grid((unsigned)((a.nx + 255) / 256), (unsigned)a.nouter);
+  if (mode == kSolveApply)
+    hipLaunchKernelGGL((k_solve_strided<T, kSolveApply, CH>), grid, dim3(256), 0, st, a);
+  else if (mode == kSolveStore)
+    hipLaunchKernelGGL((k_solve_strided<T, kSolveStore, CH>), grid, dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_solve_strided<T, kSolveInPlace, CH>), grid, dim3(256), 0, st, a);
 }
 
 template <typename T>
-hipError_t launch_solve_strided(StridedArgs<T> a, bool apply, hipStream_t st) {
+hipError_t launch_solve_strided(StridedArgs<T> a, int mode, hipStream_t st) {
   // two-ended register solve for lines that fit (half a line in registers)
   switch (a.c) {
-    case 3: launch_twisted_c<T, 3>(a, apply, st); return hipGetLastError();
-    case 5: launch_twisted_c<T, 5>(a, apply, st); return hipGetLastError();
-    case 9: launch_twisted_c<T, 9>(a, apply, st); return hipGetLastError();
-    case 17: launch_twisted_c<T, 17>(a, apply, st); return hipGetLastError();
-    case 33: launch_twisted_c<T, 33>(a, apply, st); return hipGetLastError();
-    case 65: launch_twisted_c<T, 65>(a, apply, st); return hipGetLastError();
-    case 129: launch_twisted_c<T, 129>(a, apply, st); return hipGetLastError();
+    case 3: launch_twisted_c<T, 3>(a, mode, st); return hipGetLastError();
+    case 5: launch_twisted_c<T, 5>(a, mode, st); return hipGetLastError();
+    case 9: launch_twisted_c<T, 9>(a, mode, st); return hipGetLastError();
+    case 17: launch_twisted_c<T, 17>(a, mode, st); return hipGetLastError();
+    case 33: launch_twisted_c<T, 33>(a, mode, st); return hipGetLastError();
+    case 65: launch_twisted_c<T, 65>(a, mode, st); return hipGetLastError();
+    case 129: launch_twisted_c<T, 129>(a, mode, st); return hipGetLastError();
     case 257:
       if constexpr (sizeof(T) == 4) {
-        launch_twisted_c<T, 257>(a, apply, st);
+        launch_twisted_c<T, 257>(a, mode, st);
         return hipGetLastError();
       }
       break;
     default: break;
   }
-  dim3 grid((unsigned)((a.nx + 255) / 256), (unsigned)a.nouter);
   // longer lines: chunked sweeps; few lines (one wave per SIMD or less) use
   // deep chunks to keep enough loads in flight
   const bool deep = (int64_t)a.nx * a.nouter < (1 << 18);
   constexpr int CS = sizeof(T) == 8 ? 8 : 16;
   constexpr int CD = sizeof(T) == 8 ? MGX_DEEP_CH / 2 : MGX_DEEP_CH;
-  if (apply) {
-    if (deep)
-      hipLaunchKernelGGL((k_solve_strided<T, true, CD>), grid, dim3(256), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_solve_strided<T, true, CS>), grid, dim3(256), 0, st, a);
-  } else {
-    if (deep)
-      hipLaunchKernelGGL((k_solve_strided<T, false, CD>), grid, dim3(256), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_solve_strided<T, false, CS>), grid, dim3(256), 0, st, a);
-  }
+  if (deep)
+    launch_chunked<T, CD>(a, mode, st);
+  else
+    launch_chunked<T, CS>(a, mode, st);
   return hipGetLastError();
 }
 
@@ -1053,7 +1086,7 @@ hipError_t launch_dequantize(const int32_t *labels, T *umc, QuantArgs a, hipStre
   template hipError_t launch_load_vector<T>(StencilArgs<T>, bool, hipStream_t);               \
   template hipError_t launch_interp_add<T>(InterpArgs<T>, hipStream_t);                       \
   template hipError_t launch_solve_contig<T>(SolveArgs<T>, hipStream_t);                      \
-  template hipError_t launch_solve_strided<T>(StridedArgs<T>, bool, hipStream_t);             \
+  template hipError_t launch_solve_strided<T>(StridedArgs<T>, int, hipStream_t);              \
   template hipError_t launch_apply<T>(StridedArgs<T>, hipStream_t);                           \
   template hipError_t launch_quantize<T>(const T *, int32_t *, QuantArgs, bool, hipStream_t); \
   template hipError_t launch_dequantize<T>(const int32_t *, T *, QuantArgs, hipStream_t);

@@ -9,6 +9,11 @@ namespace mgx {
 
 constexpr int kMaxLevelsK = 16;
 
+// What the last solve of a level does with the solution y.
+constexpr int kSolveInPlace = 0;  // y replaces the load vector
+constexpr int kSolveApply = 1;    // out = in + sign * y (recomposition)
+constexpr int kSolveStore = 2;    // out = y (decomposition: y = Q_{l-1} u)
+
 // Tables of one axis at the level being processed (see plan.hpp).
 template <typename T>
 struct AxisTab {
@@ -28,8 +33,6 @@ struct StencilArgs {
   T *umc_w;                   // u_mc (decompose writes coefficients)
   const T *umc_r;             // u_mc (recompose reads coefficients)
   int64_t up0, up1;           // u_mc pitches (finest grid)
-  T *Vc;                      // nodal values out (decompose), compact coarse
-  int64_t cp0, cp1;
   T *F;                       // load vector out, coarse box
   int64_t fp0, fp1;
   int ntx, nty, nzc, tz;      // set by the launcher
@@ -65,7 +68,7 @@ struct StridedArgs {          // strided-axis solve (optionally applying)
   int nouter;
   const T *mult, *invd, *qsup;
   const T *multb, *invdb, *qsub, *mid;
-  const T *in;                // apply: nodal in (index J*ij + o*io + x)
+  const T *in;                // apply: nodal in (index J*ij + o*io + x); unused by store
   int64_t ij, io;
   T *out;                     // apply: nodal out (index J*oj + o*oo + x)
   int64_t oj, oo;
@@ -86,7 +89,7 @@ struct QuantArgs {
 template <typename T> hipError_t launch_load_vector(StencilArgs<T> a, bool dec, hipStream_t st);
 template <typename T> hipError_t launch_interp_add(InterpArgs<T> a, hipStream_t st);
 template <typename T> hipError_t launch_solve_contig(SolveArgs<T> a, hipStream_t st);
-template <typename T> hipError_t launch_solve_strided(StridedArgs<T> a, bool apply, hipStream_t st);
+template <typename T> hipError_t launch_solve_strided(StridedArgs<T> a, int mode, hipStream_t st);
 template <typename T> hipError_t launch_apply(StridedArgs<T> a, hipStream_t st);
 template <typename T>
 hipError_t launch_quantize(const T *umc, int32_t *labels, QuantArgs a, bool stats, hipStream_t st);
