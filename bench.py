@@ -46,13 +46,14 @@ def algorithmic_bytes(name, level, shape, L, s):
     Nl = level_sizes(shape, L, level)
     Nc = level_sizes(shape, L, level - 1)
     table = {
-        "load_vector_dec": 2 * Nl + Nc,   # read Q_l u; write coefficients, nodal values, load vector
-        "load_vector_rec": Nl,            # read coefficients; write load vector
-        "interp_add": 2 * Nl,             # read nodal + coefficients; write Q_l u
-        "solve_contig": 2 * Nc,
+        "load_vector_dec": 2 * Nl,        # read Q_l u; write coefficients (N_l - N_c) and load vector (N_c)
+        "load_vector_rec": Nl,            # read coefficients (N_l - N_c); write load vector (N_c)
+        "interp_add": 2 * Nl,             # read nodal (N_c) + coefficients (N_l - N_c); write Q_l u
+        "solve_contig": 2 * Nc,           # load vector in, solved rows out
         "solve_strided": 2 * Nc,
+        "solve_strided_store": 2 * Nc,    # read load vector, write Q_{l-1} u
         "solve_strided_apply": 3 * Nc,    # read load vector + nodal, write nodal
-        "apply": 3 * Nc,
+        "finish_1d": 3 * Nc,
     }
     return table[name] * s
 

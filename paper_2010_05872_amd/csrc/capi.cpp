@@ -168,9 +168,10 @@ hipError_t solve_level(int level, const AxisTab<T> ax[3], const bool real[3], T 
     }
     return traced(name, level, st, [&] { return launch_solve_strided<T>(s, mode, st); });
   };
-  if (!real[0]) return strided(1, last_mode, "solve_strided_last");  // 2-D
+  const char *last_name = last_mode == kSolveApply ? "solve_strided_apply" : "solve_strided_store";
+  if (!real[0]) return strided(1, last_mode, last_name);  // 2-D
   if ((e = strided(1, kSolveInPlace, "solve_strided")) != hipSuccess) return e;
-  return strided(0, last_mode, "solve_strided_last");
+  return strided(0, last_mode, last_name);
 }
 
 template <typename T>

@@ -40,6 +40,15 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return base + idx;
 }
 
+// Load of a uniform table entry through the constant address space: the
+// compiler emits a scalar load (counted separately from vector memory
+// operations), so waiting for it never waits for in-flight vector loads or
+// stores.
+template <typename T>
+__device__ __forceinline__ T ldu(const T *p, int i) {
+  return ((const __attribute__((address_space(4))) T *)p)[i];
+}
+
 // Column of region column q in a de-interleaved LDS row: even columns first,
 // then odd ones (stride-1 reads in the restriction along x).
 template <int TX>
@@ -96,7 +105,7 @@ __global__ void __launch_bounds__(NT) k_load_vector(StencilArgs<T> a) {
   constexpr int NE = (HR * W + NT - 1) / NT;
   constexpr int NC = (OH * OW + NT - 1) / NT;
   constexpr int NOUT = (GH * GW + NT - 1) / NT;
-  constexpr int NV = DEC ? 3 : 1;        // planes kept in LDS
+  constexpr int NV = DEC ? 4 : 2;        // ring of planes kept in LDS
   constexpr int AHEAD = DEC ? 2 : 1;     // plane committed at iteration j is j + AHEAD
 
   __shared__ T sV[NV][HR * W];
@@ -147,7 +156,10 @@ __global__ void __launch_bounds__(NT) k_load_vector(StencilArgs<T> a) {
     valid |= (unsigned)in << k;
   }
 
-  // issue the loads of fine plane j into registers (zeros outside)
+  // issue the loads of fine plane j into registers (zeros outside).  Every
+  // lane issues every load (masked lanes read a valid element and discard
+  // it), so the number of outstanding memory operations is static and later
+  // waits can be partial.
   auto fetch = [&](int j, T (&st)[NE]) {
     const bool pin = j >= 0 && j < m0;
     if (DEC) {
@@ -157,7 +169,9 @@ __global__ void __launch_bounds__(NT) k_load_vector(StencilArgs<T> a) {
         const int idx = opaque(tid) + NT * k;
         const int r = idx / W, q = idx - r * W;
         const bool ok = pin && ((valid >> k) & 1u);
-        st[k] = ok ? base[(uint32_t)(r0 + r) * (uint32_t)a.vp1 + (uint32_t)(q0 + q)] : T(0);
+        const uint32_t off = ok ? (uint32_t)(r0 + r) * (uint32_t)a.vp1 + (uint32_t)(q0 + q) : 0u;
+        const T v = base[off];
+        st[k] = ok ? v : T(0);
       }
     } else {
       const T *base = a.umc_r + (pin ? lc_pos(j, c0) : 0) * a.up0;
@@ -169,7 +183,9 @@ __global__ void __launch_bounds__(NT) k_load_vector(StencilArgs<T> a) {
         const int j1 = r0 + r, j2 = q0 + q;
         // nodal nodes (all indices even) carry no multilevel component
         const bool ok = pin && ((valid >> k) & 1u) && (jodd | (j1 & 1) | (j2 & 1));
-        st[k] = ok ? base[(uint32_t)lc_pos(j1, c1) * (uint32_t)a.up1 + (uint32_t)lc_pos(j2, c2)] : T(0);
+        const uint32_t off = ok ? (uint32_t)lc_pos(j1, c1) * (uint32_t)a.up1 + (uint32_t)lc_pos(j2, c2) : 0u;
+        const T v = base[off];
+        st[k] = ok ? v : T(0);
       }
     }
   };
@@ -183,7 +199,7 @@ __global__ void __launch_bounds__(NT) k_load_vector(StencilArgs<T> a) {
       }
     }
   };
-  auto slot_of = [&](int j) { return DEC ? (j + 3) % 3 : 0; };
+  auto slot_of = [&](int j) { return (j + 4) % NV; };
 
   T acc[3][NOUT];
 #pragma unroll
@@ -192,8 +208,10 @@ __global__ void __launch_bounds__(NT) k_load_vector(StencilArgs<T> a) {
     for (int k = 0; k < NOUT; k++) acc[s][k] = T(0);
 
   // one plane of the march; st holds plane j + AHEAD on entry and receives
-  // plane j + AHEAD + 2 on exit
+  // plane j + AHEAD + 2 on exit.  The commit of plane j + AHEAD goes to a
+  // slot this iteration does not read (last read two iterations ago).
   auto plane = [&](int j, T (&st)[NE]) {
+    commit(slot_of(j + AHEAD), st);
     const bool plane_in = (j >= 0 && j < m0);
     const int pz = j & 1;
     const int s0 = slot_of(j);
@@ -215,10 +233,10 @@ __global__ void __launch_bounds__(NT) k_load_vector(StencilArgs<T> a) {
     if (DEC && plane_in && j >= own_p0 && j < own_p1) {
       T *const cbase = a.umc_w + lc_pos(j, c0) * a.up0;
       const uint32_t up1 = (uint32_t)a.up1;
-      const int sa = pz ? (j + 2) % 3 : s0;  // plane j-1 for odd j
-      const int sb = pz ? (j + 4) % 3 : s0;  // plane j+1 for odd j
-      const T wzl = pz ? a.ax[0].wl[j] : T(1);
-      const T wzr = pz ? a.ax[0].wr[j] : T(0);
+      const int sa = pz ? slot_of(j - 1) : s0;
+      const int sb = pz ? slot_of(j + 1) : s0;
+      const T wzl = pz ? ldu(a.ax[0].wl, j) : T(1);
+      const T wzr = pz ? ldu(a.ax[0].wr, j) : T(0);
 #pragma unroll
       for (int k = 0; k < NC; k++) {
         const int idx = opaque(tid) + NT * k;
@@ -245,20 +263,17 @@ __global__ void __launch_bounds__(NT) k_load_vector(StencilArgs<T> a) {
       }
     }
     __syncthreads();
-    // plane j + AHEAD replaces the slot no longer read (j - 1 for DEC, j for REC)
-    commit(slot_of(j + AHEAD), st);
-    fetch(j + AHEAD + 2, st);
     // ---- restriction along y, accumulation along z ----
     if (plane_in) {
       const int Jc = j >> 1;  // j even: Z = Jc-1, Jc, Jc+1; j odd: Z = Jc, Jc+1
       T wz0, wz1, wz2;
       if (!pz) {
-        wz0 = Jc - 1 >= 0 ? a.ax[0].w5[(Jc - 1) * 5 + 4] : T(0);
-        wz1 = a.ax[0].w5[Jc * 5 + 2];
-        wz2 = Jc + 1 < c0 ? a.ax[0].w5[(Jc + 1) * 5 + 0] : T(0);
+        wz0 = Jc - 1 >= 0 ? ldu(a.ax[0].w5, (Jc - 1) * 5 + 4) : T(0);
+        wz1 = ldu(a.ax[0].w5, Jc * 5 + 2);
+        wz2 = Jc + 1 < c0 ? ldu(a.ax[0].w5, (Jc + 1) * 5 + 0) : T(0);
       } else {
-        wz0 = a.ax[0].w5[Jc * 5 + 3];
-        wz1 = Jc + 1 < c0 ? a.ax[0].w5[(Jc + 1) * 5 + 1] : T(0);
+        wz0 = ldu(a.ax[0].w5, Jc * 5 + 3);
+        wz1 = Jc + 1 < c0 ? ldu(a.ax[0].w5, (Jc + 1) * 5 + 1) : T(0);
         wz2 = T(0);
       }
 #pragma unroll
@@ -296,11 +311,15 @@ __global__ void __launch_bounds__(NT) k_load_vector(StencilArgs<T> a) {
       }
     }
     __syncthreads();
+    // the loads for plane j + AHEAD + 2 are issued after every store of this
+    // iteration, so the commit two iterations later needs a partial wait only
+    fetch(j + AHEAD + 2, st);
   };
 
   const int jstart = 2 * Z0 - 2, jend = 2 * Z1;  // both even
   T stA[NE], stB[NE];
-  // prologue: planes jstart .. jstart+AHEAD-1 in LDS, the next two in registers
+  // prologue: planes jstart .. jstart+AHEAD-1 in LDS; plane jstart+AHEAD in
+  // stA and jstart+AHEAD+1 in stB (committed by the first two iterations)
   fetch(jstart, stA);
   commit(slot_of(jstart), stA);
   if (DEC) {
@@ -722,8 +741,8 @@ __global__ void __launch_bounds__(NT) k_interp_add(InterpArgs<T> a) {
     for (int pz = 0; pz < 2; pz++) {
       const int j = 2 * J + pz;
       if (j >= m0) break;
-      const T wzl = pz ? a.ax[0].wl[j] : T(1);
-      const T wzr = pz ? a.ax[0].wr[j] : T(0);
+      const T wzl = pz ? ldu(a.ax[0].wl, j) : T(1);
+      const T wzr = pz ? ldu(a.ax[0].wr, j) : T(0);
       const int s2 = pz ? sb : sa;
       T *outp = a.out + (int64_t)j * a.op0;
 #pragma unroll
@@ -783,39 +802,88 @@ __device__ __forceinline__ int elem_level(uint32_t idx, const QuantArgs &a) {
   return l;
 }
 
-template <typename T, bool STATS>
+// Four consecutive elements of T / int32 as one 16-byte (float, int32) or
+// two 16-byte (double) accesses when the buffers are 16-byte aligned.
+template <typename T, bool VEC>
+__device__ __forceinline__ void load4(const T *p, uint32_t base, uint32_t N, T (&v)[4]) {
+  if (VEC && base + 3 < N) {
+    if constexpr (sizeof(T) == 4) {
+      const float4 t = *(const float4 *)(p + base);
+      v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+    } else {
+      const double2 t0 = *(const double2 *)(p + base), t1 = *(const double2 *)(p + base + 2);
+      v[0] = t0.x; v[1] = t0.y; v[2] = t1.x; v[3] = t1.y;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; e++) v[e] = base + e < N ? p[base + e] : T(0);
+  }
+}
+
+template <typename T, bool VEC>
+__device__ __forceinline__ void store4(T *p, uint32_t base, uint32_t N, const T (&v)[4]) {
+  if (VEC && base + 3 < N) {
+    if constexpr (sizeof(T) == 4) {
+      *(float4 *)(p + base) = make_float4(v[0], v[1], v[2], v[3]);
+    } else {
+      *(double2 *)(p + base) = make_double2(v[0], v[1]);
+      *(double2 *)(p + base + 2) = make_double2(v[2], v[3]);
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; e++)
+      if (base + e < N) p[base + e] = v[e];
+  }
+}
+
+__device__ __forceinline__ void load4i(const int32_t *p, uint32_t base, uint32_t N, int32_t (&v)[4], bool vec) {
+  if (vec && base + 3 < N) {
+    const int4 t = *(const int4 *)(p + base);
+    v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; e++) v[e] = base + e < N ? p[base + e] : 0;
+  }
+}
+
+__device__ __forceinline__ void store4i(int32_t *p, uint32_t base, uint32_t N, const int32_t (&v)[4], bool vec) {
+  if (vec && base + 3 < N) {
+    *(int4 *)(p + base) = make_int4(v[0], v[1], v[2], v[3]);
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; e++)
+      if (base + e < N) p[base + e] = v[e];
+  }
+}
+
+template <typename T, bool STATS, bool VEC>
 __global__ void __launch_bounds__(256) k_quantize(const T *__restrict__ umc, int32_t *__restrict__ labels,
                                                   QuantArgs a) {
   __shared__ int s_max[kMaxLevelsK];
+  __shared__ double s_q[kMaxLevelsK];
   __shared__ unsigned long long s_ovf, s_nan;
-  if (STATS) {
-    if (threadIdx.x < kMaxLevelsK) s_max[threadIdx.x] = 0;
-    if (threadIdx.x == 0) {
-      s_ovf = 0;
-      s_nan = 0;
-    }
-    __syncthreads();
+  if (threadIdx.x < kMaxLevelsK) {
+    s_q[threadIdx.x] = a.q[threadIdx.x];
+    if (STATS) s_max[threadIdx.x] = 0;
   }
+  if (STATS && threadIdx.x == 0) {
+    s_ovf = 0;
+    s_nan = 0;
+  }
+  __syncthreads();
   const int lane = threadIdx.x & 63;
   unsigned long long my_ovf = 0, my_nan = 0;
   const uint32_t N = (uint32_t)a.n;
   const uint32_t stride = gridDim.x * 256u * 4u;
   for (uint32_t base = (blockIdx.x * 256u + threadIdx.x) * 4u; base < N; base += stride) {
     T v[4];
-    if (base + 3 < N) {
-#pragma unroll
-      for (int e = 0; e < 4; e++) v[e] = umc[base + e];
-    } else {
-#pragma unroll
-      for (int e = 0; e < 4; e++) v[e] = base + e < N ? umc[base + e] : T(0);
-    }
+    load4<T, VEC>(umc, base, N, v);
     int32_t lab[4];
     int lev[4], absl[4];
 #pragma unroll
     for (int e = 0; e < 4; e++) {
       lev[e] = base + e < N ? elem_level(base + e, a) : a.first;
-      const double qv = a.q[lev[e] - a.first];
-      const double t = (double)v[e] / qv;
+      const double t = (double)v[e] / s_q[lev[e] - a.first];
       absl[e] = 0;
       if (!(fabs(t) < 2147483647.0)) {
         lab[e] = INT32_MIN;
@@ -830,14 +898,7 @@ __global__ void __launch_bounds__(256) k_quantize(const T *__restrict__ umc, int
         absl[e] = lab[e] < 0 ? -lab[e] : lab[e];
       }
     }
-    if (base + 3 < N) {
-#pragma unroll
-      for (int e = 0; e < 4; e++) labels[base + e] = lab[e];
-    } else {
-#pragma unroll
-      for (int e = 0; e < 4; e++)
-        if (base + e < N) labels[base + e] = lab[e];
-    }
+    store4i(labels, base, N, lab, VEC);
     if (STATS) {
       // per-level maxima: reduce each distinct level present in the wave
 #pragma unroll
@@ -874,25 +935,24 @@ __global__ void __launch_bounds__(256) k_quantize(const T *__restrict__ umc, int
   }
 }
 
-template <typename T>
+template <typename T, bool VEC>
 __global__ void __launch_bounds__(256) k_dequantize(const int32_t *__restrict__ labels, T *__restrict__ umc,
                                                     QuantArgs a) {
+  __shared__ double s_q[kMaxLevelsK];
+  if (threadIdx.x < kMaxLevelsK) s_q[threadIdx.x] = a.q[threadIdx.x];
+  __syncthreads();
   const uint32_t N = (uint32_t)a.n;
   const uint32_t stride = gridDim.x * 256u * 4u;
   for (uint32_t base = (blockIdx.x * 256u + threadIdx.x) * 4u; base < N; base += stride) {
     int32_t lab[4];
-    if (base + 3 < N) {
-#pragma unroll
-      for (int e = 0; e < 4; e++) lab[e] = labels[base + e];
-    } else {
-#pragma unroll
-      for (int e = 0; e < 4; e++) lab[e] = base + e < N ? labels[base + e] : 0;
-    }
+    load4i(labels, base, N, lab, VEC);
+    T v[4];
 #pragma unroll
     for (int e = 0; e < 4; e++) {
-      const int lev = elem_level(base + e, a);
-      if (base + e < N) umc[base + e] = (T)((double)lab[e] * a.q[lev - a.first]);
+      const int lev = base + e < N ? elem_level(base + e, a) : a.first;
+      v[e] = (T)((double)lab[e] * s_q[lev - a.first]);
     }
+    store4<T, VEC>(umc, base, N, v);
   }
 }
 
@@ -1065,20 +1125,33 @@ static unsigned quant_grid(int64_t n) {
   return (unsigned)(g > 0 ? g : 1);
 }
 
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
 template <typename T>
 hipError_t launch_quantize(const T *umc, int32_t *labels, QuantArgs a, bool stats, hipStream_t st) {
   dim3 grid(quant_grid(a.n));
-  if (stats)
-    hipLaunchKernelGGL((k_quantize<T, true>), grid, dim3(256), 0, st, umc, labels, a);
-  else
-    hipLaunchKernelGGL((k_quantize<T, false>), grid, dim3(256), 0, st, umc, labels, a);
+  const bool vec = aligned16(umc) && aligned16(labels);
+  if (stats) {
+    if (vec)
+      hipLaunchKernelGGL((k_quantize<T, true, true>), grid, dim3(256), 0, st, umc, labels, a);
+    else
+      hipLaunchKernelGGL((k_quantize<T, true, false>), grid, dim3(256), 0, st, umc, labels, a);
+  } else {
+    if (vec)
+      hipLaunchKernelGGL((k_quantize<T, false, true>), grid, dim3(256), 0, st, umc, labels, a);
+    else
+      hipLaunchKernelGGL((k_quantize<T, false, false>), grid, dim3(256), 0, st, umc, labels, a);
+  }
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_dequantize(const int32_t *labels, T *umc, QuantArgs a, hipStream_t st) {
   dim3 grid(quant_grid(a.n));
-  hipLaunchKernelGGL((k_dequantize<T>), grid, dim3(256), 0, st, labels, umc, a);
+  if (aligned16(umc) && aligned16(labels))
+    hipLaunchKernelGGL((k_dequantize<T, true>), grid, dim3(256), 0, st, labels, umc, a);
+  else
+    hipLaunchKernelGGL((k_dequantize<T, false>), grid, dim3(256), 0, st, labels, umc, a);
   return hipGetLastError();
 }
 
