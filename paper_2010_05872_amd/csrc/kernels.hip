@@ -24,6 +24,37 @@
 
 #include "kernels.hpp"
 
+// Tuning parameters (compile-time; overridable with -D for measurements).
+#ifndef MGX_STENCIL_DEPTH
+#define MGX_STENCIL_DEPTH 2
+#endif
+#ifndef MGX_STENCIL_WAVES
+#define MGX_STENCIL_WAVES 4
+#endif
+#ifndef MGX_DEEP_CH
+#define MGX_DEEP_CH 32
+#endif
+#ifndef MGX_F32_TY
+#define MGX_F32_TY 16
+#endif
+#ifndef MGX_F32_NT
+#define MGX_F32_NT 512
+#endif
+#ifndef MGX_F64_TY
+#define MGX_F64_TY 16
+#endif
+#ifndef MGX_F64_NT
+#define MGX_F64_NT 256
+#endif
+// workgroups a stencil launch aims for, and the fewest coarse planes a
+// z-chunk of a large level holds
+#ifndef MGX_TARGET_BLOCKS
+#define MGX_TARGET_BLOCKS 2048
+#endif
+#ifndef MGX_MIN_ZCHUNK
+#define MGX_MIN_ZCHUNK 8
+#endif
+
 namespace mgx {
 
 // ---------------------------------------------------------------------------
@@ -47,6 +78,18 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 template <typename T>
 __device__ __forceinline__ T ldu(const T *p, int i) {
   return ((const __attribute__((address_space(4))) T *)p)[i];
+}
+
+// Element access at a 32-bit byte offset from a (wave-uniform) base pointer:
+// lets the compiler use the scalar-base + 32-bit vector-offset addressing
+// form instead of 64-bit per-lane address arithmetic.
+template <typename T>
+__device__ __forceinline__ T ld_at(const T *base, uint32_t byte_off) {
+  return *(const T *)((const char *)base + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ void st_at(T *base, uint32_t byte_off, T v) {
+  *(T *)((char *)base + byte_off) = v;
 }
 
 // Column of region column q in a de-interleaved LDS row: even columns first,
@@ -94,24 +137,24 @@ __device__ __forceinline__ int opaque(int v) {
 // the interpolation corners read consecutive LDS words.  Planes are fetched
 // two iterations ahead into double-buffered registers.
 template <typename T, int TX, int TY, int NT, bool DEC>
-__global__ void __launch_bounds__(NT) k_load_vector(StencilArgs<T> a) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MGX_STENCIL_WAVES, 8)))
+k_load_vector(StencilArgs<T> a) {
   constexpr int HR = 2 * TY + 5;  // region rows incl. halo and the extension
   constexpr int W = 2 * TX + 5;   // region row pitch
   constexpr int E = TX + 3;       // even columns of a region row
   constexpr int GW = TX + 1;      // coarse columns per tile (max)
   constexpr int GH = TY + 1;      // coarse rows per tile (max)
-  constexpr int OW = 2 * TX + 2;  // owned fine columns (max)
-  constexpr int OH = 2 * TY + 2;  // owned fine rows (max)
-  constexpr int NE = (HR * W + NT - 1) / NT;
-  constexpr int NC = (OH * OW + NT - 1) / NT;
-  constexpr int NOUT = (GH * GW + NT - 1) / NT;
-  constexpr int NV = DEC ? 4 : 2;        // ring of planes kept in LDS
-  constexpr int AHEAD = DEC ? 2 : 1;     // plane committed at iteration j is j + AHEAD
+  constexpr int NE = (HR * W + NT - 1) / NT;  // region elements per thread
+  constexpr int NV = DEC ? 4 : 2;             // ring of planes kept in LDS
+  constexpr int AHEAD = DEC ? 2 : 1;          // plane committed at iteration j is j + AHEAD
+  constexpr int DEPTH = MGX_STENCIL_DEPTH;    // register buffers in flight
+  constexpr int XRS = NT / GW;                // x-restriction: rows per sweep
+  constexpr int XR = (HR + XRS - 1) / XRS;    // x-restriction: rows per thread
+  constexpr int NOUT = (GH * GW + NT - 1) / NT;  // y-restriction outputs per thread
+  constexpr int NB = NOUT;                       // 2x2 coefficient blocks per thread
 
   __shared__ T sV[NV][HR * W];
   __shared__ T sG[HR * GW];
-  __shared__ T sWxl[OW], sWxr[OW], sWyl[OH], sWyr[OH];
-  __shared__ T sW5x[GW * 5], sW5y[GH * 5];
 
   const int tid = threadIdx.x;
   const int m0 = a.ax[0].m, m1 = a.ax[1].m, m2 = a.ax[2].m;
@@ -131,22 +174,10 @@ __global__ void __launch_bounds__(NT) k_load_vector(StencilArgs<T> a) {
   const int fq = min(2 * X1, m2) - 2 * X0;  // owned fine columns
   const int own_p0 = 2 * Z0, own_p1 = min(2 * Z1, m0);
 
-  if (DEC) {
-    for (int q = tid; q < fq; q += NT) {
-      sWxl[q] = a.ax[2].wl[2 * X0 + q];
-      sWxr[q] = a.ax[2].wr[2 * X0 + q];
-    }
-    for (int r = tid; r < fr; r += NT) {
-      sWyl[r] = a.ax[1].wl[2 * Y0 + r];
-      sWyr[r] = a.ax[1].wr[2 * Y0 + r];
-    }
-  }
-  for (int i = tid; i < nX * 5; i += NT) sW5x[i] = a.ax[2].w5[X0 * 5 + i];
-  for (int i = tid; i < nY * 5; i += NT) sW5y[i] = a.ax[1].w5[Y0 * 5 + i];
-
-  // region element k of this thread: index tid + NT k; valid if inside the
-  // region and the level box
-  unsigned valid = 0;
+  // ---- plane loads: global and LDS offsets of this thread's NE region
+  //      elements (the same in every plane) ----
+  int goff[NE], loff[NE];
+  unsigned valid = 0, inlds = 0, yxeven = 0;
 #pragma unroll
   for (int k = 0; k < NE; k++) {
     const int idx = tid + NT * k;
@@ -154,52 +185,87 @@ __global__ void __launch_bounds__(NT) k_load_vector(StencilArgs<T> a) {
     const int j1 = r0 + r, j2 = q0 + q;
     const bool in = idx < nr * W && q < nq && j1 >= 0 && j1 < m1 && j2 >= 0 && j2 < m2;
     valid |= (unsigned)in << k;
+    inlds |= (unsigned)(idx < HR * W) << k;
+    yxeven |= (unsigned)(!(j1 & 1) && !(j2 & 1)) << k;
+    loff[k] = r * W + zcol<TX>(q);
+    // byte offsets within a plane
+    if (DEC)
+      goff[k] = in ? (j1 * (int)a.vp1 + j2) * (int)sizeof(T) : 0;
+    else
+      goff[k] = in ? (int)(lc_pos(j1, c1) * a.up1 + lc_pos(j2, c2)) * (int)sizeof(T) : 0;
   }
-
   // issue the loads of fine plane j into registers (zeros outside).  Every
   // lane issues every load (masked lanes read a valid element and discard
   // it), so the number of outstanding memory operations is static and later
   // waits can be partial.
   auto fetch = [&](int j, T (&st)[NE]) {
     const bool pin = j >= 0 && j < m0;
-    if (DEC) {
-      const T *base = a.V + (int64_t)(pin ? j : 0) * a.vp0;
+    const T *base = DEC ? a.V + (int64_t)(pin ? j : 0) * a.vp0 : a.umc_r + (pin ? lc_pos(j, c0) : 0) * a.up0;
+    // recomposition: nodal nodes (all indices even) carry no multilevel component
+    const unsigned keep = DEC ? valid : ((j & 1) ? valid : (valid & ~yxeven));
 #pragma unroll
-      for (int k = 0; k < NE; k++) {
-        const int idx = opaque(tid) + NT * k;
-        const int r = idx / W, q = idx - r * W;
-        const bool ok = pin && ((valid >> k) & 1u);
-        const uint32_t off = ok ? (uint32_t)(r0 + r) * (uint32_t)a.vp1 + (uint32_t)(q0 + q) : 0u;
-        const T v = base[off];
-        st[k] = ok ? v : T(0);
-      }
-    } else {
-      const T *base = a.umc_r + (pin ? lc_pos(j, c0) : 0) * a.up0;
-      const int jodd = j & 1;
-#pragma unroll
-      for (int k = 0; k < NE; k++) {
-        const int idx = opaque(tid) + NT * k;
-        const int r = idx / W, q = idx - r * W;
-        const int j1 = r0 + r, j2 = q0 + q;
-        // nodal nodes (all indices even) carry no multilevel component
-        const bool ok = pin && ((valid >> k) & 1u) && (jodd | (j1 & 1) | (j2 & 1));
-        const uint32_t off = ok ? (uint32_t)lc_pos(j1, c1) * (uint32_t)a.up1 + (uint32_t)lc_pos(j2, c2) : 0u;
-        const T v = base[off];
-        st[k] = ok ? v : T(0);
-      }
+    for (int k = 0; k < NE; k++) {
+      const T v = ld_at(base, (uint32_t)goff[k]);
+      st[k] = (pin && ((keep >> k) & 1u)) ? v : T(0);
     }
   };
   auto commit = [&](int slot, const T (&st)[NE]) {
 #pragma unroll
-    for (int k = 0; k < NE; k++) {
-      const int idx = opaque(tid) + NT * k;
-      if (idx < HR * W) {
-        const int r = idx / W, q = idx - r * W;
-        sV[slot][r * W + zcol<TX>(q)] = st[k];
-      }
-    }
+    for (int k = 0; k < NE; k++)
+      if ((inlds >> k) & 1u) sV[slot][loff[k]] = st[k];
   };
   auto slot_of = [&](int j) { return (j + 4) % NV; };
+
+  // ---- x-restriction role: coarse column xX, region rows xr0 + XRS i ----
+  const int xX = tid % GW, xr0 = tid / GW;
+  const bool xact = tid < XRS * GW && xX < nX;
+  T xw[5];
+#pragma unroll
+  for (int d = 0; d < 5; d++) xw[d] = xact ? a.ax[2].w5[(X0 + xX) * 5 + d] : T(0);
+
+  // ---- y-restriction role: coarse outputs (Y, X), weights and offsets ----
+  T yw[NOUT][5];
+  int foff[NOUT], ysrc[NOUT];
+  unsigned yact = 0;
+#pragma unroll
+  for (int k = 0; k < NOUT; k++) {
+    const int o = tid + NT * k;
+    const int Y = o / GW, X = o - Y * GW;
+    const bool act = o < GH * GW && Y < nY && X < nX;
+    yact |= (unsigned)act << k;
+#pragma unroll
+    for (int d = 0; d < 5; d++) yw[k][d] = act ? a.ax[1].w5[(Y0 + Y) * 5 + d] : T(0);
+    foff[k] = act ? ((Y0 + Y) * (int)a.fp1 + X0 + X) * (int)sizeof(T) : 0;
+    ysrc[k] = (2 * Y) * GW + X;
+  }
+
+  // ---- coefficient role (decomposition): 2x2 blocks of owned fine nodes
+  //      (rows 2ca, 2ca+1; columns 2cb, 2cb+1) sharing their nodal corners ----
+  int cR0[NB], cE0[NB], cRowE[NB], cColE[NB];
+  T cwxl[NB], cwxr[NB], cwyl[NB], cwyr[NB];
+  unsigned cn = 0;  // 4 bits per block: nodes 00, 01, 10, 11 inside the owned box
+  if (DEC) {
+#pragma unroll
+    for (int k = 0; k < NB; k++) {
+      const int o = tid + NT * k;
+      const int ca = o / GW, cb = o - ca * GW;
+      const bool blk = o < GH * GW;
+      const bool r0ok = blk && 2 * ca < fr, r1ok = blk && 2 * ca + 1 < fr;
+      const bool q0ok = 2 * cb < fq, q1ok = 2 * cb + 1 < fq;
+      cn |= (unsigned)((r0ok && q0ok) | ((r0ok && q1ok) << 1) | ((r1ok && q0ok) << 2) | ((r1ok && q1ok) << 3))
+            << (4 * k);
+      cR0[k] = (2 * ca + 2) * W;  // region row of owned row 2ca
+      cE0[k] = cb + 1;            // de-interleaved position of region column 2cb+2 (even)
+      cRowE[k] = (int)((Y0 + ca) * a.up1) * (int)sizeof(T);
+      cColE[k] = (X0 + cb) * (int)sizeof(T);
+      cwxl[k] = q1ok ? a.ax[2].wl[2 * X0 + 2 * cb + 1] : T(0);
+      cwxr[k] = q1ok ? a.ax[2].wr[2 * X0 + 2 * cb + 1] : T(0);
+      cwyl[k] = r1ok ? a.ax[1].wl[2 * Y0 + 2 * ca + 1] : T(0);
+      cwyr[k] = r1ok ? a.ax[1].wr[2 * Y0 + 2 * ca + 1] : T(0);
+    }
+  }
+  const int rowOdd = (int)(c1 * a.up1) * (int)sizeof(T);  // level-centric shift of odd rows (bytes)
+  const int colOdd = c2 * (int)sizeof(T);                   // ... and of odd columns
 
   T acc[3][NOUT];
 #pragma unroll
@@ -208,7 +274,7 @@ __global__ void __launch_bounds__(NT) k_load_vector(StencilArgs<T> a) {
     for (int k = 0; k < NOUT; k++) acc[s][k] = T(0);
 
   // one plane of the march; st holds plane j + AHEAD on entry and receives
-  // plane j + AHEAD + 2 on exit.  The commit of plane j + AHEAD goes to a
+  // plane j + AHEAD + DEPTH on exit.  The commit of plane j + AHEAD goes to a
   // slot this iteration does not read (last read two iterations ago).
   auto plane = [&](int j, T (&st)[NE]) {
     commit(slot_of(j + AHEAD), st);
@@ -216,48 +282,59 @@ __global__ void __launch_bounds__(NT) k_load_vector(StencilArgs<T> a) {
     const int pz = j & 1;
     const int s0 = slot_of(j);
     // ---- restriction along x of plane j: sG[r][X] ----
-    if (plane_in) {
-      for (int idx = tid; idx < nr * GW; idx += NT) {
-        const int r = idx / GW, X = idx - r * GW;
-        if (X < nX) {
-          // fine columns 2X..2X+4 of the region: even ones at X, X+1, X+2,
-          // odd ones at E+X, E+X+1
-          const int b = r * W + X;
-          const T *w = sW5x + X * 5;
-          sG[idx] = w[0] * sV[s0][b] + w[1] * sV[s0][b + E] + w[2] * sV[s0][b + 1] + w[3] * sV[s0][b + E + 1] +
-                    w[4] * sV[s0][b + 2];
+    if (plane_in && xact) {
+#pragma unroll
+      for (int i = 0; i < XR; i++) {
+        const int r = xr0 + XRS * i;
+        if (r < nr) {
+          const int b = r * W + xX;
+          sG[r * GW + xX] = xw[0] * sV[s0][b] + xw[1] * sV[s0][b + E] + xw[2] * sV[s0][b + 1] +
+                            xw[3] * sV[s0][b + E + 1] + xw[4] * sV[s0][b + 2];
         }
       }
     }
     // ---- coefficients of the owned nodes of plane j (decomposition) ----
     if (DEC && plane_in && j >= own_p0 && j < own_p1) {
       T *const cbase = a.umc_w + lc_pos(j, c0) * a.up0;
-      const uint32_t up1 = (uint32_t)a.up1;
-      const int sa = pz ? slot_of(j - 1) : s0;
-      const int sb = pz ? slot_of(j + 1) : s0;
-      const T wzl = pz ? ldu(a.ax[0].wl, j) : T(1);
-      const T wzr = pz ? ldu(a.ax[0].wr, j) : T(0);
+      if (!pz) {
+        // even plane: corners in the plane itself; node 00 is nodal
 #pragma unroll
-      for (int k = 0; k < NC; k++) {
-        const int idx = opaque(tid) + NT * k;
-        const int rr = idx / OW, qq = idx - rr * OW;
-        if (idx < OH * OW && rr < fr && qq < fq) {
-          const int py = rr & 1, px = qq & 1;
-          if (pz | py | px) {
-            const int r = rr + 2, q = qq + 2;  // region coordinates
-            const T v = sV[s0][r * W + zcol<TX>(q)];
-            // corners: rows r -+ py, even columns (q >> 1) and (q >> 1) + px
-            const int ra = (r - py) * W + (q >> 1), rb = (r + py) * W + (q >> 1);
-            const T wyl = py ? sWyl[rr] : T(1), wyr = py ? sWyr[rr] : T(0);
-            const T wxl = px ? sWxl[qq] : T(1), wxr = px ? sWxr[qq] : T(0);
-            T pa = wyl * (wxl * sV[sa][ra] + wxr * sV[sa][ra + px]) + wyr * (wxl * sV[sa][rb] + wxr * sV[sa][rb + px]);
-            if (pz) {
-              const T pb =
-                  wyl * (wxl * sV[sb][ra] + wxr * sV[sb][ra + px]) + wyr * (wxl * sV[sb][rb] + wxr * sV[sb][rb + px]);
-              pa = wzl * pa + wzr * pb;
-            }
-            const int j1 = 2 * Y0 + rr, j2 = 2 * X0 + qq;
-            cbase[(uint32_t)lc_pos(j1, c1) * up1 + (uint32_t)lc_pos(j2, c2)] = v - pa;
+        for (int k = 0; k < NB; k++) {
+          const unsigned f = cn >> (4 * k);
+          if (f & 0xEu) {
+            const int R0 = cR0[k], R2 = cR0[k] + 2 * W, e0 = cE0[k];
+            const T C00 = sV[s0][R0 + e0], C02 = sV[s0][R0 + e0 + 1];
+            const T C20 = sV[s0][R2 + e0], C22 = sV[s0][R2 + e0 + 1];
+            const T t0 = cwxl[k] * C00 + cwxr[k] * C02, t2 = cwxl[k] * C20 + cwxr[k] * C22;
+            const uint32_t oE = (uint32_t)(cRowE[k] + cColE[k]);
+            if (f & 2u) st_at(cbase, oE + colOdd, sV[s0][R0 + E + e0] - t0);
+            if (f & 4u) st_at(cbase, oE + rowOdd, sV[s0][R0 + W + e0] - (cwyl[k] * C00 + cwyr[k] * C20));
+            if (f & 8u) st_at(cbase, oE + rowOdd + colOdd, sV[s0][R0 + W + E + e0] - (cwyl[k] * t0 + cwyr[k] * t2));
+          }
+        }
+      } else {
+        // odd plane: corners on the even planes j-1 and j+1
+        const int sa = slot_of(j - 1), sb = slot_of(j + 1);
+        const T wzl = ldu(a.ax[0].wl, j), wzr = ldu(a.ax[0].wr, j);
+#pragma unroll
+        for (int k = 0; k < NB; k++) {
+          const unsigned f = cn >> (4 * k);
+          if (f & 0xFu) {
+            const int R0 = cR0[k], R2 = cR0[k] + 2 * W, e0 = cE0[k];
+            const T A00 = sV[sa][R0 + e0], A02 = sV[sa][R0 + e0 + 1], A20 = sV[sa][R2 + e0], A22 = sV[sa][R2 + e0 + 1];
+            const T B00 = sV[sb][R0 + e0], B02 = sV[sb][R0 + e0 + 1], B20 = sV[sb][R2 + e0], B22 = sV[sb][R2 + e0 + 1];
+            const T wxl = cwxl[k], wxr = cwxr[k], wyl = cwyl[k], wyr = cwyr[k];
+            const T ta0 = wxl * A00 + wxr * A02, ta2 = wxl * A20 + wxr * A22;
+            const T tb0 = wxl * B00 + wxr * B02, tb2 = wxl * B20 + wxr * B22;
+            const uint32_t oE = (uint32_t)(cRowE[k] + cColE[k]);
+            if (f & 1u) st_at(cbase, oE, sV[s0][R0 + e0] - (wzl * A00 + wzr * B00));
+            if (f & 2u) st_at(cbase, oE + colOdd, sV[s0][R0 + E + e0] - (wzl * ta0 + wzr * tb0));
+            if (f & 4u)
+              st_at(cbase, oE + rowOdd,
+                    sV[s0][R0 + W + e0] - (wzl * (wyl * A00 + wyr * A20) + wzr * (wyl * B00 + wyr * B20)));
+            if (f & 8u)
+              st_at(cbase, oE + rowOdd + colOdd,
+                    sV[s0][R0 + W + E + e0] - (wzl * (wyl * ta0 + wyr * ta2) + wzr * (wyl * tb0 + wyr * tb2)));
           }
         }
       }
@@ -278,13 +355,10 @@ __global__ void __launch_bounds__(NT) k_load_vector(StencilArgs<T> a) {
       }
 #pragma unroll
       for (int k = 0; k < NOUT; k++) {
-        const int idx = tid + k * NT;
-        const int Y = idx / GW, X = idx - Y * GW;
-        if (idx < GH * GW && Y < nY && X < nX) {
-          const T *w = sW5y + Y * 5;
-          const int b = (2 * Y) * GW + X;
-          const T gyx = w[0] * sG[b] + w[1] * sG[b + GW] + w[2] * sG[b + 2 * GW] + w[3] * sG[b + 3 * GW] +
-                        w[4] * sG[b + 4 * GW];
+        if ((yact >> k) & 1u) {
+          const int b = ysrc[k];
+          const T gyx = yw[k][0] * sG[b] + yw[k][1] * sG[b + GW] + yw[k][2] * sG[b + 2 * GW] +
+                        yw[k][3] * sG[b + 3 * GW] + yw[k][4] * sG[b + 4 * GW];
           acc[0][k] += wz0 * gyx;
           acc[1][k] += wz1 * gyx;
           acc[2][k] += wz2 * gyx;
@@ -295,13 +369,10 @@ __global__ void __launch_bounds__(NT) k_load_vector(StencilArgs<T> a) {
     if (!pz) {
       const int Zdone = (j >> 1) - 1;
       if (Zdone >= Z0 && Zdone < Z1) {
+        T *const fbase = a.F + (int64_t)Zdone * a.fp0;
 #pragma unroll
-        for (int k = 0; k < NOUT; k++) {
-          const int idx = tid + k * NT;
-          const int Y = idx / GW, X = idx - Y * GW;
-          if (idx < GH * GW && Y < nY && X < nX)
-            a.F[(int64_t)Zdone * a.fp0 + (int64_t)(Y0 + Y) * a.fp1 + X0 + X] = acc[0][k];
-        }
+        for (int k = 0; k < NOUT; k++)
+          if ((yact >> k) & 1u) st_at(fbase, (uint32_t)foff[k], acc[0][k]);
       }
 #pragma unroll
       for (int k = 0; k < NOUT; k++) {
@@ -311,30 +382,31 @@ __global__ void __launch_bounds__(NT) k_load_vector(StencilArgs<T> a) {
       }
     }
     __syncthreads();
-    // the loads for plane j + AHEAD + 2 are issued after every store of this
-    // iteration, so the commit two iterations later needs a partial wait only
-    fetch(j + AHEAD + 2, st);
+    // the loads for plane j + AHEAD + DEPTH are issued after every store of
+    // this iteration, so the commit DEPTH iterations later needs a partial
+    // wait only
+    fetch(j + AHEAD + DEPTH, st);
   };
 
   const int jstart = 2 * Z0 - 2, jend = 2 * Z1;  // both even
-  T stA[NE], stB[NE];
-  // prologue: planes jstart .. jstart+AHEAD-1 in LDS; plane jstart+AHEAD in
-  // stA and jstart+AHEAD+1 in stB (committed by the first two iterations)
-  fetch(jstart, stA);
-  commit(slot_of(jstart), stA);
+  T st[DEPTH][NE];
+  fetch(jstart, st[0]);
+  commit(slot_of(jstart), st[0]);
   if (DEC) {
-    fetch(jstart + 1, stA);
-    commit(slot_of(jstart + 1), stA);
+    fetch(jstart + 1, st[0]);
+    commit(slot_of(jstart + 1), st[0]);
   }
-  fetch(jstart + AHEAD, stA);
-  fetch(jstart + AHEAD + 1, stB);
+#pragma unroll
+  for (int d = 0; d < DEPTH; d++) fetch(jstart + AHEAD + d, st[d]);
   __syncthreads();
   int j = jstart;
-  for (; j + 1 <= jend; j += 2) {
-    plane(j, stA);
-    plane(j + 1, stB);
+  for (; j + DEPTH - 1 <= jend; j += DEPTH) {
+#pragma unroll
+    for (int d = 0; d < DEPTH; d++) plane(j + d, st[d]);
   }
-  plane(j, stA);  // the last (even) plane
+#pragma unroll
+  for (int d = 0; d < DEPTH - 1; d++)
+    if (j + d <= jend) plane(j + d, st[d]);
 }
 
 // ---------------------------------------------------------------------------
@@ -637,21 +709,23 @@ __global__ void __launch_bounds__(256) k_apply(StridedArgs<T> a) {
 // ---------------------------------------------------------------------------
 // k_interp_add: recomposition step 4 — Q_l u = coefficient + Pi_{l-1} of the
 // corrected nodal values (and the nodal values themselves on N_{l-1}).
-// Tile as in k_load_vector; the kernel marches over coarse planes J with a
-// two-slot LDS ring of nodal planes (J, J+1) and emits fine planes 2J, 2J+1.
-// The coefficients of the next two fine planes and the nodal plane after
-// next are fetched into registers while the current pair is computed.
+// Tile as in k_load_vector.  The kernel marches over coarse planes J with a
+// four-slot LDS ring of nodal planes and emits fine planes 2J and 2J+1.
+// Each thread owns 2x2 blocks of fine nodes (rows 2a, 2a+1; columns 2b,
+// 2b+1) that share four nodal corners per coarse plane; its weights and
+// offsets are fixed for the whole march, and the coefficients of the next
+// coarse plane are fetched into registers while the current one is done.
 // ---------------------------------------------------------------------------
 template <typename T, int TX, int TY, int NT>
 __global__ void __launch_bounds__(NT) k_interp_add(InterpArgs<T> a) {
   constexpr int NW = TX + 2;  // nodal tile pitch
   constexpr int NH = TY + 2;
-  constexpr int OW = 2 * TX + 2;  // owned fine columns (max)
-  constexpr int OH = 2 * TY + 2;  // owned fine rows (max)
-  constexpr int NO = (OH * OW + NT - 1) / NT;
+  constexpr int BW = TX + 1;  // 2x2 blocks per tile row (max)
+  constexpr int BH = TY + 1;
+  constexpr int NB = (BH * BW + NT - 1) / NT;
   constexpr int NN = (NH * NW + NT - 1) / NT;
-  __shared__ T sN[2][NH * NW];
-  __shared__ T sWxl[OW], sWxr[OW], sWyl[OH], sWyr[OH];
+  constexpr int NR = 4;  // nodal ring slots
+  __shared__ T sN[NR][NH * NW];
 
   const int tid = threadIdx.x;
   const int m0 = a.ax[0].m, m1 = a.ax[1].m, m2 = a.ax[2].m;
@@ -668,112 +742,147 @@ __global__ void __launch_bounds__(NT) k_interp_add(InterpArgs<T> a) {
   const int ncx = min(nX + 1, c2 - X0), ncy = min(nY + 1, c1 - Y0);  // nodal tile extent
   const int fq = min(2 * X1, m2) - 2 * X0;  // owned fine columns
   const int fr = min(2 * Y1, m1) - 2 * Y0;  // owned fine rows
+  constexpr int ES = (int)sizeof(T);
 
-  for (int q = tid; q < fq; q += NT) {
-    sWxl[q] = a.ax[2].wl[2 * X0 + q];
-    sWxr[q] = a.ax[2].wr[2 * X0 + q];
-  }
-  for (int r = tid; r < fr; r += NT) {
-    sWyl[r] = a.ax[1].wl[2 * Y0 + r];
-    sWyr[r] = a.ax[1].wr[2 * Y0 + r];
-  }
-
-  unsigned ownmask = 0;
+  // ---- nodal plane loads: NN elements per thread ----
+  int noff[NN];
+  unsigned nvalid = 0, ninlds = 0;
 #pragma unroll
-  for (int k = 0; k < NO; k++) {
+  for (int k = 0; k < NN; k++) {
     const int idx = tid + NT * k;
-    const int rr = idx / OW, qq = idx - rr * OW;
-    ownmask |= (unsigned)(idx < OH * OW && rr < fr && qq < fq) << k;
+    const int r = idx / NW, q = idx - r * NW;
+    const bool ok = idx < NH * NW && r < ncy && q < ncx;
+    nvalid |= (unsigned)ok << k;
+    ninlds |= (unsigned)(idx < NH * NW) << k;
+    noff[k] = ok ? ((Y0 + r) * (int)a.np1 + X0 + q) * ES : 0;
   }
-
-  T nst[NN];
-  auto fetch_nodal = [&](int J) {
+  auto fetch_nodal = [&](int J, T (&v)[NN]) {
     const bool pin = J < c0;
     const T *src = a.nodal + (int64_t)(pin ? J : 0) * a.np0;
 #pragma unroll
     for (int k = 0; k < NN; k++) {
-      const int idx = opaque(tid) + NT * k;
-      const int r = idx / NW, q = idx - r * NW;
-      const bool ok = pin && idx < NH * NW && r < ncy && q < ncx;
-      nst[k] = ok ? src[(uint32_t)(Y0 + r) * (uint32_t)a.np1 + (uint32_t)(X0 + q)] : T(0);
+      const T x = ld_at(src, (uint32_t)noff[k]);
+      v[k] = (pin && ((nvalid >> k) & 1u)) ? x : T(0);
     }
   };
-  T cf[2][NO];
-  auto fetch_coef = [&](int J) {
-#pragma unroll
-    for (int pz = 0; pz < 2; pz++) {
-      const int j = 2 * J + pz;
-      const bool pin = J < Z1 && j < m0;
-      const T *base = a.umc + (pin ? lc_pos(j, c0) : 0) * a.up0;
-#pragma unroll
-      for (int k = 0; k < NO; k++) {
-        const int idx = opaque(tid) + NT * k;
-        const int rr = idx / OW, qq = idx - rr * OW;
-        const int j1 = 2 * Y0 + rr, j2 = 2 * X0 + qq;
-        const bool ok = pin && ((ownmask >> k) & 1u) && (pz | (j1 & 1) | (j2 & 1));
-        cf[pz][k] = ok ? base[(uint32_t)lc_pos(j1, c1) * (uint32_t)a.up1 + (uint32_t)lc_pos(j2, c2)] : T(0);
-      }
-    }
-  };
-  auto commit_nodal = [&](int slot) {
+  auto commit_nodal = [&](int slot, const T (&v)[NN]) {
 #pragma unroll
     for (int k = 0; k < NN; k++)
-      if (tid + NT * k < NH * NW) sN[slot][tid + NT * k] = nst[k];
+      if ((ninlds >> k) & 1u) sN[slot][tid + NT * k] = v[k];
   };
 
-  fetch_nodal(Z0);
-  commit_nodal(Z0 & 1);
-  fetch_nodal(Z0 + 1);
-  commit_nodal((Z0 + 1) & 1);
-  fetch_coef(Z0);
-  fetch_nodal(Z0 + 2);
-  __syncthreads();
+  // ---- 2x2 blocks ----
+  // byte offsets of the block's coefficients in a level-centric plane:
+  // (even row, even col), (even, odd), (odd, even), (odd, odd).  Positions of
+  // nodes outside the owned box fall back to the even ones (and a block
+  // outside the box to the tile origin), so every load stays in the level box.
+  int bN[NB], bEE[NB], bEO[NB], bOE[NB], bOO[NB], bOut[NB];
+  T bwxl[NB], bwxr[NB], bwyl[NB], bwyr[NB];
+  unsigned bn = 0;  // 4 bits per block: nodes 00, 01, 10, 11 inside the owned box
+#pragma unroll
+  for (int k = 0; k < NB; k++) {
+    const int o = tid + NT * k;
+    const int ba = o / BW, bb = o - ba * BW;
+    const bool blk = o < BH * BW;
+    const bool r0ok = blk && 2 * ba < fr, r1ok = blk && 2 * ba + 1 < fr;
+    const bool q0ok = 2 * bb < fq, q1ok = 2 * bb + 1 < fq;
+    bn |= (unsigned)((r0ok && q0ok) | ((r0ok && q1ok) << 1) | ((r1ok && q0ok) << 2) | ((r1ok && q1ok) << 3)) << (4 * k);
+    const bool inbox = r0ok && q0ok;
+    bN[k] = inbox ? ba * NW + bb : 0;
+    const int rE = (int)((Y0 + (inbox ? ba : 0)) * a.up1) * ES;
+    const int rO = r1ok && inbox ? rE + (int)(c1 * a.up1) * ES : rE;
+    const int cE = (X0 + (inbox ? bb : 0)) * ES;
+    const int cO = q1ok && inbox ? cE + c2 * ES : cE;
+    bEE[k] = rE + cE;
+    bEO[k] = rE + cO;
+    bOE[k] = rO + cE;
+    bOO[k] = rO + cO;
+    bOut[k] = inbox ? ((2 * (Y0 + ba)) * (int)a.op1 + 2 * (X0 + bb)) * ES : 0;
+    bwxl[k] = q1ok ? a.ax[2].wl[2 * X0 + 2 * bb + 1] : T(0);
+    bwxr[k] = q1ok ? a.ax[2].wr[2 * X0 + 2 * bb + 1] : T(0);
+    bwyl[k] = r1ok ? a.ax[1].wl[2 * Y0 + 2 * ba + 1] : T(0);
+    bwyr[k] = r1ok ? a.ax[1].wr[2 * Y0 + 2 * ba + 1] : T(0);
+  }
+  const int outRow = (int)a.op1 * ES;
 
-  for (int J = Z0; J < Z1; J++) {
-    const int sa = J & 1, sb = (J + 1) & 1;
-    T cur[2][NO];
+  // coefficients of coarse plane J: fine plane 2J (nodes 01, 10, 11) and
+  // 2J+1 (nodes 00, 01, 10, 11), 7 per block
+  auto fetch_coef = [&](int J, T (&cv)[NB][7]) {
+    const bool pin = J < Z1;
+    const T *be = a.umc + (int64_t)(pin ? J : 0) * a.up0;
+    const bool odd_in = pin && 2 * J + 1 < m0;
+    const T *bo = a.umc + (int64_t)(odd_in ? c0 + J : 0) * a.up0;
 #pragma unroll
-    for (int pz = 0; pz < 2; pz++)
+    for (int k = 0; k < NB; k++) {
+      cv[k][0] = ld_at(be, (uint32_t)bEO[k]);
+      cv[k][1] = ld_at(be, (uint32_t)bOE[k]);
+      cv[k][2] = ld_at(be, (uint32_t)bOO[k]);
+      cv[k][3] = ld_at(bo, (uint32_t)bEE[k]);
+      cv[k][4] = ld_at(bo, (uint32_t)bEO[k]);
+      cv[k][5] = ld_at(bo, (uint32_t)bOE[k]);
+      cv[k][6] = ld_at(bo, (uint32_t)bOO[k]);
+    }
+  };
+
+  auto step = [&](int J, T (&cv)[NB][7], T (&nv)[NN]) {
+    commit_nodal((J + 2) % NR, nv);  // plane J+2; its slot was last read two steps ago
+    __syncthreads();
+    const int sa = J % NR, sb = (J + 1) % NR;
+    const bool odd_in = 2 * J + 1 < m0;
+    const T wzl = odd_in ? ldu(a.ax[0].wl, 2 * J + 1) : T(0);
+    const T wzr = odd_in ? ldu(a.ax[0].wr, 2 * J + 1) : T(0);
+    T *const oe = a.out + (int64_t)(2 * J) * a.op0;
+    T *const oo = a.out + (int64_t)(odd_in ? 2 * J + 1 : 2 * J) * a.op0;
 #pragma unroll
-      for (int k = 0; k < NO; k++) cur[pz][k] = cf[pz][k];
-    fetch_coef(J + 1);
-#pragma unroll
-    for (int pz = 0; pz < 2; pz++) {
-      const int j = 2 * J + pz;
-      if (j >= m0) break;
-      const T wzl = pz ? ldu(a.ax[0].wl, j) : T(1);
-      const T wzr = pz ? ldu(a.ax[0].wr, j) : T(0);
-      const int s2 = pz ? sb : sa;
-      T *outp = a.out + (int64_t)j * a.op0;
-#pragma unroll
-      for (int k = 0; k < NO; k++) {
-        if (!((ownmask >> k) & 1u)) continue;
-        const int idx = opaque(tid) + NT * k;
-        const int rr = idx / OW, qq = idx - rr * OW;
-        const int j1 = 2 * Y0 + rr, j2 = 2 * X0 + qq;
-        const int py = j1 & 1, px = j2 & 1;
-        const int ra = (rr >> 1) * NW, rb = ((rr >> 1) + py) * NW;
-        const int qa = qq >> 1, qb = (qq >> 1) + px;
-        T outv;
-        if (pz | py | px) {
-          const T wyl = py ? sWyl[rr] : T(1), wyr = py ? sWyr[rr] : T(0);
-          const T wxl = px ? sWxl[qq] : T(1), wxr = px ? sWxr[qq] : T(0);
-          const T pa = wyl * (wxl * sN[sa][ra + qa] + wxr * sN[sa][ra + qb]) +
-                       wyr * (wxl * sN[sa][rb + qa] + wxr * sN[sa][rb + qb]);
-          const T pb = wyl * (wxl * sN[s2][ra + qa] + wxr * sN[s2][ra + qb]) +
-                       wyr * (wxl * sN[s2][rb + qa] + wxr * sN[s2][rb + qb]);
-          outv = cur[pz][k] + (wzl * pa + wzr * pb);
-        } else {
-          outv = sN[sa][ra + qa];
-        }
-        outp[(uint32_t)j1 * (uint32_t)a.op1 + (uint32_t)j2] = outv;
+    for (int k = 0; k < NB; k++) {
+      const unsigned f = bn >> (4 * k);
+      if (!(f & 0xFu)) continue;
+      const T wxl = bwxl[k], wxr = bwxr[k], wyl = bwyl[k], wyr = bwyr[k];
+      const int n = bN[k];
+      const T A00 = sN[sa][n], A01 = sN[sa][n + 1], A10 = sN[sa][n + NW], A11 = sN[sa][n + NW + 1];
+      // interpolants of plane J at the block's nodes
+      const T ea = wxl * A00 + wxr * A01;
+      const T eb = wxl * A10 + wxr * A11;
+      const T e10 = wyl * A00 + wyr * A10;
+      const T e11 = wyl * ea + wyr * eb;
+      const uint32_t o0 = (uint32_t)bOut[k];
+      if (f & 1u) st_at(oe, o0, A00);
+      if (f & 2u) st_at(oe, o0 + ES, cv[k][0] + ea);
+      if (f & 4u) st_at(oe, o0 + outRow, cv[k][1] + e10);
+      if (f & 8u) st_at(oe, o0 + outRow + ES, cv[k][2] + e11);
+      if (odd_in) {
+        const T B00 = sN[sb][n], B01 = sN[sb][n + 1], B10 = sN[sb][n + NW], B11 = sN[sb][n + NW + 1];
+        const T fa = wxl * B00 + wxr * B01;
+        const T fb = wxl * B10 + wxr * B11;
+        const T f10 = wyl * B00 + wyr * B10;
+        const T f11 = wyl * fa + wyr * fb;
+        if (f & 1u) st_at(oo, o0, cv[k][3] + (wzl * A00 + wzr * B00));
+        if (f & 2u) st_at(oo, o0 + ES, cv[k][4] + (wzl * ea + wzr * fa));
+        if (f & 4u) st_at(oo, o0 + outRow, cv[k][5] + (wzl * e10 + wzr * f10));
+        if (f & 8u) st_at(oo, o0 + outRow + ES, cv[k][6] + (wzl * e11 + wzr * f11));
       }
     }
-    __syncthreads();  // slot sa (plane J) is free
-    commit_nodal(sa);  // plane J+2
-    fetch_nodal(J + 3);
-    __syncthreads();
+    // loads for step J+2 after every store of this step (partial waits later)
+    fetch_coef(J + 2, cv);
+    fetch_nodal(J + 4, nv);
+  };
+
+  T nv0[NN], nv1[NN];
+  T cv0[NB][7], cv1[NB][7];
+  fetch_nodal(Z0, nv0);
+  commit_nodal(Z0 % NR, nv0);
+  fetch_nodal(Z0 + 1, nv0);
+  commit_nodal((Z0 + 1) % NR, nv0);
+  fetch_nodal(Z0 + 2, nv0);
+  fetch_nodal(Z0 + 3, nv1);
+  fetch_coef(Z0, cv0);
+  fetch_coef(Z0 + 1, cv1);
+  int J = Z0;
+  for (; J + 1 < Z1; J += 2) {
+    step(J, cv0, nv0);
+    step(J + 1, cv1, nv1);
   }
+  if (J < Z1) step(J, cv0, nv0);
 }
 
 // ---------------------------------------------------------------------------
@@ -962,21 +1071,6 @@ __global__ void __launch_bounds__(256) k_dequantize(const int32_t *__restrict__ 
 
 template <typename T>
 struct Tiles;
-#ifndef MGX_DEEP_CH
-#define MGX_DEEP_CH 32
-#endif
-#ifndef MGX_F32_TY
-#define MGX_F32_TY 16
-#endif
-#ifndef MGX_F32_NT
-#define MGX_F32_NT 512
-#endif
-#ifndef MGX_F64_TY
-#define MGX_F64_TY 16
-#endif
-#ifndef MGX_F64_NT
-#define MGX_F64_NT 256
-#endif
 template <>
 struct Tiles<float> {
   static constexpr int TX = 32, TY = MGX_F32_TY, NT = MGX_F32_NT;
@@ -997,11 +1091,12 @@ static bool tile_grid(int c0, int c1, int c2, int TX, int TY, int *ntx, int *nty
   *ntx = (c2 - 1) / TX > 0 ? (c2 - 1) / TX : 1;
   *nty = (c1 - 1) / TY > 0 ? (c1 - 1) / TY : 1;
   const int per = *ntx * *nty;
-  int want = (2048 + per - 1) / per;
-  // large levels keep z-chunks of >= 8 coarse planes (halo re-reads stay
-  // small); small levels take one coarse plane per workgroup (latency bound)
+  int want = (MGX_TARGET_BLOCKS + per - 1) / per;
+  // large levels keep z-chunks of >= MGX_MIN_ZCHUNK coarse planes (halo
+  // re-reads stay small); small levels take one coarse plane per workgroup
+  // (latency bound)
   const bool large = (int64_t)c0 * c1 * c2 >= (1 << 20);
-  int maxz = large ? (c0 / 8 > 0 ? c0 / 8 : 1) : c0;
+  int maxz = large ? (c0 / MGX_MIN_ZCHUNK > 0 ? c0 / MGX_MIN_ZCHUNK : 1) : c0;
   if (want > maxz) want = maxz;
   if (want < 1) want = 1;
   *nzc = want;
