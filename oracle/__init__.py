@@ -52,8 +52,9 @@ def lib():
         dp = ctypes.POINTER(ctypes.c_double)
         vp = ctypes.c_void_p
         L.mgo_num_levels.argtypes = [ctypes.c_int, i64p]
-        for name in ("mgo_decompose", "mgo_recompose"):
+        for name in ("mgo_decompose", "mgo_recompose", "mgo_decompose_adjoint", "mgo_recompose_adjoint"):
             getattr(L, name).argtypes = [vp, ctypes.c_int, i64p, vp, ctypes.c_int]
+        L.mgo_project_line_adjoint_1d.argtypes = [vp, ctypes.c_int64, vp, vp]
         L.mgo_correction.argtypes = [vp, vp, ctypes.c_int, i64p, vp]
         L.mgo_mass_apply_1d.argtypes = [vp, ctypes.c_int64, vp, vp]
         L.mgo_restrict_1d.argtypes = [vp, ctypes.c_int64, vp, vp]
@@ -128,6 +129,33 @@ def recompose(u_mc, coords=None, stop_level=0) -> np.ndarray:
     c = _Coords(v.shape, coords)
     _check(lib().mgo_recompose(v.ctypes.data, v.ndim, _dims(v.shape), c.ptr, int(stop_level)), "recompose")
     return v
+
+
+def decompose_adjoint(g_mc, coords=None, stop_level=0) -> np.ndarray:
+    """D^T applied to an interleaved coefficient-space array (transpose of
+    decompose; not in the paper)."""
+    v = np.array(g_mc, dtype=np.float64, order="C", copy=True)
+    c = _Coords(v.shape, coords)
+    _check(lib().mgo_decompose_adjoint(v.ctypes.data, v.ndim, _dims(v.shape), c.ptr, int(stop_level)),
+           "decompose_adjoint")
+    return v
+
+
+def recompose_adjoint(g_u, coords=None, stop_level=0) -> np.ndarray:
+    """R^T applied to a field-space array; returns interleaved coefficient space."""
+    v = np.array(g_u, dtype=np.float64, order="C", copy=True)
+    c = _Coords(v.shape, coords)
+    _check(lib().mgo_recompose_adjoint(v.ctypes.data, v.ndim, _dims(v.shape), c.ptr, int(stop_level)),
+           "recompose_adjoint")
+    return v
+
+
+def project_line_adjoint_1d(X, y):
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    out = np.empty(len(X))
+    lib().mgo_project_line_adjoint_1d(X.ctypes.data, len(X), y.ctypes.data, out.ctypes.data)
+    return out
 
 
 def correction(z, coords=None) -> np.ndarray:

@@ -396,6 +396,201 @@ static int recompose_level(const grid_t *g, double *v, int l) {
   return st;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Adjoint (transpose) of decomposition and recomposition.                   */
+/* Not part of the paper: the transposes of the level maps above, written    */
+/* out step by step in reverse order.  A decomposition level is              */
+/*   D_l = (I + S^T C Z)(I - E),                                             */
+/* E the interpolant at the coefficient nodes (zero rows at nodal nodes), Z  */
+/* the restriction to coefficient nodes, C the per-axis projection of        */
+/* correction_box and S^T the scatter of a coarse box onto the nodal nodes.  */
+/* A recomposition level is R_l = (I + E)(I - S^T C Z).  So                  */
+/*   D_l^T = (I - E^T)(I + Z C^T S),   R_l^T = (I - Z C^T S)(I + E^T),       */
+/* with C^T = prod_k M P Mc^{-1} along each axis (M and Mc are symmetric and */
+/* R = P^T).                                                                 */
+/* ------------------------------------------------------------------------ */
+
+/* Transpose of mgo_project_line_1d: out = M P Mc^{-1} y (coarse -> fine). */
+void mgo_project_line_adjoint_1d(const double *X, int64_t m, const double *y, double *out) {
+  int64_t mc = (m + 1) / 2;
+  double *a = (double *)malloc(sizeof(double) * (size_t)mc);
+  double *b = (double *)malloc(sizeof(double) * (size_t)m);
+  double *sub = (double *)malloc(sizeof(double) * (size_t)mc * 4);
+  double *diag = sub + mc, *sup = sub + 2 * mc, *work = sub + 3 * mc;
+  memcpy(a, y, sizeof(double) * (size_t)mc);
+  mgo_coarse_mass_1d(X, m, sub, diag, sup);
+  thomas_solve(mc, sub, diag, sup, a, work);
+  /* prolongation P: even nodes copy, odd nodes interpolate (transpose of R) */
+  for (int64_t j = 0; j < m; j++) {
+    if ((j & 1) == 0) b[j] = a[j / 2];
+    else b[j] = w_left(X, j) * a[(j - 1) / 2] + w_right(X, j) * a[(j + 1) / 2];
+  }
+  mgo_mass_apply_1d(X, m, b, out);
+  free(a);
+  free(b);
+  free(sub);
+}
+
+/* C^T: coarse box y (shape of the level-(l-1) grid) -> level-l box out.
+ * The forward projection runs axes 2, 1, 0; its transpose runs 0, 1, 2. */
+static int correction_box_adjoint(const int64_t m_out[3], const int real[3],
+                                  double *const Xl[3], const double *y, double *out) {
+  int64_t a[3];
+  for (int k = 0; k < 3; k++) a[k] = real[k] ? (m_out[k] + 1) / 2 : m_out[k];
+  size_t total = (size_t)(a[0] * a[1] * a[2]);
+  double *cur = (double *)malloc(sizeof(double) * total);
+  if (!cur) return MGO_ERR_ALLOC;
+  memcpy(cur, y, sizeof(double) * total);
+  for (int k = 0; k < 3; k++) {
+    if (!real[k]) continue;
+    int64_t mc = a[k], mk = m_out[k];
+    int64_t b[3] = {a[0], a[1], a[2]};
+    b[k] = mk;
+    double *next = (double *)malloc(sizeof(double) * (size_t)(b[0] * b[1] * b[2]));
+    double *line = (double *)malloc(sizeof(double) * (size_t)mc);
+    double *res = (double *)malloc(sizeof(double) * (size_t)mk);
+    if (!next || !line || !res) { free(cur); free(next); free(line); free(res); return MGO_ERR_ALLOC; }
+    int64_t sa[3] = {a[1] * a[2], a[2], 1};
+    int64_t sb[3] = {b[1] * b[2], b[2], 1};
+    int o1 = (k == 0) ? 1 : 0, o2 = (k == 2) ? 1 : 2;
+    for (int64_t p = 0; p < a[o1]; p++) {
+      for (int64_t q = 0; q < a[o2]; q++) {
+        int64_t base_a = p * sa[o1] + q * sa[o2];
+        int64_t base_b = p * sb[o1] + q * sb[o2];
+        for (int64_t J = 0; J < mc; J++) line[J] = cur[base_a + J * sa[k]];
+        mgo_project_line_adjoint_1d(Xl[k], mk, line, res);
+        for (int64_t j = 0; j < mk; j++) next[base_b + j * sb[k]] = res[j];
+      }
+    }
+    free(line);
+    free(res);
+    free(cur);
+    cur = next;
+    a[k] = mk;
+  }
+  memcpy(out, cur, sizeof(double) * (size_t)(a[0] * a[1] * a[2]));
+  free(cur);
+  return MGO_OK;
+}
+
+/* sign * E^T: every coefficient node x sends weight * g(x) to each nodal
+ * corner of its interpolant (the corner weights of interpolant()). */
+static void scatter_interpolant_transpose(const level_view_t *w, double sign) {
+  for (int64_t j0 = 0; j0 < w->m[0]; j0++)
+    for (int64_t j1 = 0; j1 < w->m[1]; j1++)
+      for (int64_t j2 = 0; j2 < w->m[2]; j2++) {
+        int64_t j[3] = {j0, j1, j2};
+        if (is_nodal(w, j)) continue;
+        double gx = *at(w, j0, j1, j2);
+        int odd[3];
+        for (int k = 0; k < 3; k++) odd[k] = w->real[k] && (j[k] & 1);
+        for (int c = 0; c < 8; c++) {
+          int64_t q[3];
+          double wt = 1.0;
+          int skip = 0;
+          for (int k = 0; k < 3; k++) {
+            int bit = (c >> k) & 1;
+            if (!odd[k]) {
+              if (bit) { skip = 1; break; }
+              q[k] = j[k];
+            } else if (bit == 0) {
+              q[k] = j[k] - 1;
+              wt *= w_left(w->Xl[k], j[k]);
+            } else {
+              q[k] = j[k] + 1;
+              wt *= w_right(w->Xl[k], j[k]);
+            }
+          }
+          if (skip) continue;
+          *at(w, q[0], q[1], q[2]) += sign * wt * gx;
+        }
+      }
+}
+
+/* Nodal values of the level-l view as a coarse box (the operator S). */
+static void gather_nodal(const level_view_t *w, double *y) {
+  int64_t mc[3];
+  for (int k = 0; k < 3; k++) mc[k] = w->real[k] ? (w->m[k] + 1) / 2 : 1;
+  size_t t = 0;
+  for (int64_t J0 = 0; J0 < mc[0]; J0++)
+    for (int64_t J1 = 0; J1 < mc[1]; J1++)
+      for (int64_t J2 = 0; J2 < mc[2]; J2++, t++)
+        y[t] = *at(w, w->real[0] ? 2 * J0 : 0, w->real[1] ? 2 * J1 : 0, w->real[2] ? 2 * J2 : 0);
+}
+
+/* g(x) += sign * t(x) at the coefficient nodes (the operator Z^T). */
+static void add_at_coefficients(const level_view_t *w, const double *t, double sign) {
+  size_t i = 0;
+  for (int64_t j0 = 0; j0 < w->m[0]; j0++)
+    for (int64_t j1 = 0; j1 < w->m[1]; j1++)
+      for (int64_t j2 = 0; j2 < w->m[2]; j2++, i++) {
+        int64_t j[3] = {j0, j1, j2};
+        if (!is_nodal(w, j)) *at(w, j0, j1, j2) += sign * t[i];
+      }
+}
+
+/* D_l^T = (I - E^T)(I + Z C^T S), applied in place to the level-l view. */
+static int decompose_level_adjoint(const grid_t *g, double *v, int l) {
+  level_view_t w;
+  int st = view_init(&w, g, v, l);
+  if (st) { view_free(&w); return st; }
+  double *y = (double *)malloc(sizeof(double) * coarse_total(&w));
+  double *t = (double *)malloc(sizeof(double) * (size_t)(w.m[0] * w.m[1] * w.m[2]));
+  if (!y || !t) { free(y); free(t); view_free(&w); return MGO_ERR_ALLOC; }
+  gather_nodal(&w, y);
+  st = correction_box_adjoint(w.m, w.real, w.Xl, y, t);
+  if (!st) {
+    add_at_coefficients(&w, t, +1.0);
+    scatter_interpolant_transpose(&w, -1.0);
+  }
+  free(y);
+  free(t);
+  view_free(&w);
+  return st;
+}
+
+/* R_l^T = (I - Z C^T S)(I + E^T), applied in place to the level-l view. */
+static int recompose_level_adjoint(const grid_t *g, double *v, int l) {
+  level_view_t w;
+  int st = view_init(&w, g, v, l);
+  if (st) { view_free(&w); return st; }
+  double *y = (double *)malloc(sizeof(double) * coarse_total(&w));
+  double *t = (double *)malloc(sizeof(double) * (size_t)(w.m[0] * w.m[1] * w.m[2]));
+  if (!y || !t) { free(y); free(t); view_free(&w); return MGO_ERR_ALLOC; }
+  scatter_interpolant_transpose(&w, +1.0);
+  gather_nodal(&w, y);
+  st = correction_box_adjoint(w.m, w.real, w.Xl, y, t);
+  if (!st) add_at_coefficients(&w, t, -1.0);
+  free(y);
+  free(t);
+  view_free(&w);
+  return st;
+}
+
+int mgo_decompose_adjoint(double *v, int ndim, const int64_t *dims,
+                          const double *const *coords, int stop_level) {
+  grid_t g;
+  int st = grid_init(&g, ndim, dims, coords);
+  if (st) return st;
+  if (stop_level < 0 || stop_level > g.L) { grid_free(&g); return MGO_ERR_LEVEL; }
+  /* D = D_{stop+1} ... D_L, so D^T applies D_{stop+1}^T first */
+  for (int l = stop_level + 1; l <= g.L && !st; l++) st = decompose_level_adjoint(&g, v, l);
+  grid_free(&g);
+  return st;
+}
+
+int mgo_recompose_adjoint(double *v, int ndim, const int64_t *dims,
+                          const double *const *coords, int stop_level) {
+  grid_t g;
+  int st = grid_init(&g, ndim, dims, coords);
+  if (st) return st;
+  if (stop_level < 0 || stop_level > g.L) { grid_free(&g); return MGO_ERR_LEVEL; }
+  /* R = R_L ... R_{stop+1}, so R^T applies R_L^T first */
+  for (int l = g.L; l > stop_level && !st; l--) st = recompose_level_adjoint(&g, v, l);
+  grid_free(&g);
+  return st;
+}
+
 int mgo_num_levels(int ndim, const int64_t *dims) {
   grid_t g;
   int st = grid_init(&g, ndim, dims, NULL);

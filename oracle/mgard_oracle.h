@@ -41,6 +41,14 @@ int mgo_decompose(double *v, int ndim, const int64_t *dims,
 int mgo_recompose(double *v, int ndim, const int64_t *dims,
                   const double *const *coords, int stop_level);
 
+/* Transposes (adjoints) of mgo_decompose and mgo_recompose, in place on the
+ * interleaved layout: for all x, y, <D x, y> = <x, D^T y>. */
+int mgo_decompose_adjoint(double *v, int ndim, const int64_t *dims,
+                          const double *const *coords, int stop_level);
+int mgo_recompose_adjoint(double *v, int ndim, const int64_t *dims,
+                          const double *const *coords, int stop_level);
+void mgo_project_line_adjoint_1d(const double *X, int64_t m, const double *y, double *out);
+
 /* The correction Q_{l-1}(I - Pi_{l-1}) of a single level: z is a full
  * level box of shape dims (zeros expected at even-index nodes), y receives
  * the coarse box of shape (dims+1)/2. */
