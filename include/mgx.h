@@ -116,6 +116,34 @@ mgx_status mgx_recompose(const void *u_mc, void *u, mgx_dtype dtype, int ndim,
                          const int64_t *dims, const double *const *coords, int stop_level,
                          void *workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* ---- Adjoints (project extension, not in the paper) ----
+ * The transposes of the linear maps mgx_decompose (D) and mgx_recompose
+ * (R = D^{-1}): for all x, y, <D x, y> = <x, D^T y>.  They let gradients of
+ * a loss on a reconstructed field flow back to the coefficients and the
+ * input.  Per level they run the transposed steps of Sec. 2 in reverse
+ * order: the coarse solve, the transposed load-vector stencil (M P per
+ * axis, the transpose of the fused R M of Sec. 5.2) and the restriction R.
+ * Workspace: at least mgx_adjoint_workspace_size(...) bytes (the forward
+ * workspace plus one more coarse load-vector box). */
+size_t mgx_adjoint_workspace_size(mgx_dtype dtype, int ndim, const int64_t *dims, int stop_level);
+
+/* g_u = D^T g_mc.
+ *   g_mc     in:  device, dims, dtype, level-centric layout (the layout of
+ *                 mgx_decompose's output).  Not modified.
+ *   g_u      out: device, natural order.  Must not overlap g_mc.
+ * Errors as mgx_decompose (MGX_ERR_WORKSPACE against the adjoint size). */
+mgx_status mgx_decompose_adjoint(const void *g_mc, void *g_u, mgx_dtype dtype, int ndim,
+                                 const int64_t *dims, const double *const *coords, int stop_level,
+                                 void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* g_mc = R^T g_u.
+ *   g_u      in:  device, natural order.  Not modified.
+ *   g_mc     out: device, level-centric layout.  Must not overlap g_u.
+ * Errors as mgx_decompose_adjoint. */
+mgx_status mgx_recompose_adjoint(const void *g_u, void *g_mc, mgx_dtype dtype, int ndim,
+                                 const int64_t *dims, const double *const *coords, int stop_level,
+                                 void *workspace, size_t workspace_bytes, hipStream_t stream);
+
 /* Level-wise quantization (Sec. 4.1, eq. (LinfTau); Algorithm 1, quantize
  * step).  tau_l~ = (1-kappa)/(1-kappa^(L+1-l~)) * tol_linf / C and
  * tau_l = kappa tau_{l-1} with kappa = sqrt(2^d), all in FP64 in that

@@ -67,7 +67,8 @@ class KernelTime(ctypes.Structure):
 EXPORTS = (
     "mgx_status_string", "mgx_num_levels", "mgx_workspace_size", "mgx_decompose", "mgx_recompose",
     "mgx_quantize", "mgx_dequantize", "mgx_linf_constant", "mgx_level_tolerances",
-    "mgx_trace_enable", "mgx_trace_read",
+    "mgx_trace_enable", "mgx_trace_read", "mgx_adjoint_workspace_size", "mgx_decompose_adjoint",
+    "mgx_recompose_adjoint",
 )
 
 _lib = None
@@ -89,7 +90,9 @@ def lib():
         L.mgx_num_levels.restype = ci
         L.mgx_workspace_size.argtypes = [ci, ci, i64p, ci]
         L.mgx_workspace_size.restype = sz
-        for name in ("mgx_decompose", "mgx_recompose"):
+        L.mgx_adjoint_workspace_size.argtypes = [ci, ci, i64p, ci]
+        L.mgx_adjoint_workspace_size.restype = sz
+        for name in ("mgx_decompose", "mgx_recompose", "mgx_decompose_adjoint", "mgx_recompose_adjoint"):
             f = getattr(L, name)
             f.argtypes = [vp, vp, ci, ci, i64p, vp, ci, vp, sz, vp]
             f.restype = ci
@@ -175,6 +178,10 @@ def workspace_size(dtype_code: int, shape, stop_level: int = 0) -> int:
     return int(lib().mgx_workspace_size(dtype_code, len(shape), _dims(shape), int(stop_level)))
 
 
+def adjoint_workspace_size(dtype_code: int, shape, stop_level: int = 0) -> int:
+    return int(lib().mgx_adjoint_workspace_size(dtype_code, len(shape), _dims(shape), int(stop_level)))
+
+
 def linf_constant(shape, coords=None, stop_level=0) -> float:
     c = Coords(shape, coords)
     r = lib().mgx_linf_constant(len(shape), _dims(shape), c.ptr, int(stop_level))
@@ -249,6 +256,33 @@ def recompose(u_mc, coords=None, stop_level=0, out=None, workspace=None):
     return out
 
 
+def _adjoint_call(name, src, coords, stop_level, out, workspace):
+    import torch
+    _check_tensor(src, "input")
+    if out is None:
+        out = torch.empty_like(src)
+    _check_tensor(out, "out")
+    need = adjoint_workspace_size(_dtype_code(src), src.shape, stop_level)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=src.device)
+    c = Coords(src.shape, coords)
+    code = getattr(lib(), name)(src.data_ptr(), out.data_ptr(), _dtype_code(src), src.dim(), _dims(src.shape),
+                                c.ptr, int(stop_level), workspace.data_ptr(),
+                                workspace.numel() * workspace.element_size(), _stream(src.device))
+    _check(code, name)
+    return out
+
+
+def decompose_adjoint(g_mc, coords=None, stop_level=0, out=None, workspace=None):
+    """D^T: coefficient-space gradient (level-centric) -> field-space gradient."""
+    return _adjoint_call("mgx_decompose_adjoint", g_mc, coords, stop_level, out, workspace)
+
+
+def recompose_adjoint(g_u, coords=None, stop_level=0, out=None, workspace=None):
+    """R^T: field-space gradient -> coefficient-space gradient (level-centric)."""
+    return _adjoint_call("mgx_recompose_adjoint", g_u, coords, stop_level, out, workspace)
+
+
 def quantize(u_mc, tol, coords=None, stop_level=0, c_linf=0.0, out=None, stats=False):
     """Level-wise labels (int32).  With stats=True returns (labels, stats dict) and
     raises MgxError(MGX_ERR_RANGE) if any label overflowed."""
@@ -285,3 +319,6 @@ def dequantize(labels, tol, dtype, coords=None, stop_level=0, c_linf=0.0, out=No
                                 _stream(labels.device))
     _check(code, "mgx_dequantize")
     return out
+
+
+from .autograd import Decompose, MGXRoundTrip, QuantizeSTE, Recompose  # noqa: E402,F401

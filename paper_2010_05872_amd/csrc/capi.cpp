@@ -21,12 +21,13 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 int64_t round4(int64_t v) { return (v + 3) / 4 * 4; }
 
 struct Layout {
-  size_t offA = 0, offB = 0, offF = 0, total = 0;
+  size_t offA = 0, offB = 0, offF = 0, offG = 0, total = 0;
 };
 
 // Two compact coarse boxes (levels L-1 and L-2) for nodal values and one
 // coarse box with padded rows for the load vector.
-Layout layout(const int64_t n[3], const bool real[3], int L, int stop, size_t es) {
+// The adjoints need one more load-vector sized box (G).
+Layout layout(const int64_t n[3], const bool real[3], int L, int stop, size_t es, bool adjoint = false) {
   Layout w;
   if (stop >= L) return w;
   int64_t cA = 1, cB = 1, cF = 1;
@@ -44,6 +45,8 @@ Layout layout(const int64_t n[3], const bool real[3], int L, int stop, size_t es
   if (L - stop >= 2) off = align_up(off + (size_t)cB * es, 256);
   w.offF = off;
   off = align_up(off + (size_t)cF * es, 256);
+  w.offG = off;
+  if (adjoint) off = align_up(off + (size_t)cF * es, 256);
   w.total = off;
   return w;
 }
@@ -269,10 +272,147 @@ mgx_status run_recompose(Plan *P, int stop, const T *umc, T *u, char *ws, const 
   return MGX_OK;
 }
 
+// Tables of level l with the load-vector stencil replaced by the restriction
+// R = P^T alone (adjoint passes).
+template <typename T>
+AxisTab<T> restrict_tab(const Plan *P, int l, int k, const T *tab) {
+  AxisTab<T> t = axis_tab(P, l, k, tab);
+  t.w5 = tab + P->ax[l][k].off_p5;
+  return t;
+}
+
+template <typename T>
+hipError_t copy_box(const T *src, int64_t sp0, int64_t sp1, T *dst, int64_t dp0, int64_t dp1, int n0, int n1,
+                    int n2, int level, hipStream_t st) {
+  CopyArgs<T> c{src, sp0, sp1, dst, dp0, dp1, n0, n1, n2};
+  return traced("copy_box", level, st, [&] { return launch_copy_box<T>(c, st); });
+}
+
+// Adjoint of decomposition (not in the paper): g_u = D^T g_mc.  D is the
+// product of the level maps D_L first ... D_{stop+1} last, so the transpose
+// runs the levels upwards.  Per level, with gW the gradient of the coarse
+// values and gz that of the level's coefficients:
+//   y = Mc^{-1} gW,  r = R gz,
+//   g_V = (M P)^{x3} y + gz at coefficient nodes, - r at nodal nodes.
+template <typename T>
+mgx_status run_decompose_adjoint(Plan *P, int stop, const T *gmc, T *gu, char *ws, const Layout &lay,
+                                 const T *tab, hipStream_t st) {
+  const int L = P->L;
+  const int64_t n1 = P->n[1], n2 = P->n[2];
+  const int64_t up0 = n1 * n2, up1 = n2;
+  if (stop == L) return hip_status(hipMemcpyAsync(gu, gmc, sizeof(T) * P->n[0] * up0, hipMemcpyDeviceToDevice, st));
+  T *A = (T *)(ws + lay.offA), *B = (T *)(ws + lay.offB), *F = (T *)(ws + lay.offF), *G = (T *)(ws + lay.offG);
+  for (int l = stop + 1; l <= L; l++) {
+    AxisTab<T> ax[3] = {axis_tab(P, l, 0, tab), axis_tab(P, l, 1, tab), axis_tab(P, l, 2, tab)};
+    const int c0 = ax[0].c, c1 = ax[1].c, c2 = ax[2].c;
+    const int m1 = ax[1].m, m2 = ax[2].m;
+    const int64_t cp1 = c2, cp0 = (int64_t)c1 * c2;
+    const int64_t fp1 = round4(c2), fp0 = (int64_t)c1 * fp1;
+    const bool first = (l == stop + 1);
+    const T *gW = first ? gmc : (((L - 1 - (l - 1)) % 2 == 0) ? A : B);
+    const int64_t wp0 = first ? up0 : cp0, wp1 = first ? up1 : cp1;
+    hipError_t e = copy_box<T>(gW, wp0, wp1, F, fp0, fp1, c0, c1, c2, l, st);
+    if (e != hipSuccess) return MGX_ERR_HIP;
+    e = solve_level<T>(l, ax, P->real, F, fp0, fp1, kSolveInPlace, nullptr, 0, 0, F, fp0, fp1, st);
+    if (e != hipSuccess) return MGX_ERR_HIP;
+    StencilArgs<T> s{};
+    for (int k = 0; k < 3; k++) s.ax[k] = restrict_tab(P, l, k, tab);
+    s.umc_r = gmc;
+    s.up0 = up0;
+    s.up1 = up1;
+    s.F = G;
+    s.fp0 = fp0;
+    s.fp1 = fp1;
+    e = traced("restrict_coef", l, st, [&] { return launch_load_vector<T>(s, false, st); });
+    if (e != hipSuccess) return MGX_ERR_HIP;
+    ProlongArgs<T> pa{};
+    for (int k = 0; k < 3; k++) pa.ax[k] = ax[k];
+    pa.y = F;
+    pa.yp0 = fp0;
+    pa.yp1 = fp1;
+    pa.lc_in = gmc;
+    pa.up0 = up0;
+    pa.up1 = up1;
+    pa.r = G;
+    pa.rp0 = fp0;
+    pa.rp1 = fp1;
+    if (l == L) {
+      pa.out = gu;
+      pa.op0 = up0;
+      pa.op1 = up1;
+    } else {
+      pa.out = ((L - 1 - l) % 2 == 0) ? A : B;
+      pa.op1 = m2;
+      pa.op0 = (int64_t)m1 * m2;
+    }
+    e = traced("prolong_mass_dec_adj", l, st, [&] { return launch_prolong_mass<T>(pa, kProlongDecAdj, st); });
+    if (e != hipSuccess) return MGX_ERR_HIP;
+  }
+  return MGX_OK;
+}
+
+// Adjoint of recomposition: g_mc = R^T g_u, levels downwards.  Per level,
+// with g_V the gradient of the level-l values:
+//   a = R g_V (the gradient of the coarse values), y = Mc^{-1} a,
+//   gz = g_V - (M P)^{x3} y at the coefficient nodes.
+template <typename T>
+mgx_status run_recompose_adjoint(Plan *P, int stop, const T *gu, T *gmc, char *ws, const Layout &lay,
+                                 const T *tab, hipStream_t st) {
+  const int L = P->L;
+  const int64_t n1 = P->n[1], n2 = P->n[2];
+  const int64_t up0 = n1 * n2, up1 = n2;
+  if (stop == L) return hip_status(hipMemcpyAsync(gmc, gu, sizeof(T) * P->n[0] * up0, hipMemcpyDeviceToDevice, st));
+  T *A = (T *)(ws + lay.offA), *B = (T *)(ws + lay.offB), *F = (T *)(ws + lay.offF);
+  for (int l = L; l > stop; l--) {
+    AxisTab<T> ax[3] = {axis_tab(P, l, 0, tab), axis_tab(P, l, 1, tab), axis_tab(P, l, 2, tab)};
+    const int c0 = ax[0].c, c1 = ax[1].c, c2 = ax[2].c;
+    const int m1 = ax[1].m, m2 = ax[2].m;
+    const int64_t cp1 = c2, cp0 = (int64_t)c1 * c2;
+    const int64_t fp1 = round4(c2), fp0 = (int64_t)c1 * fp1;
+    const T *gV = (l == L) ? gu : (((L - 1 - l) % 2 == 0) ? A : B);
+    const int64_t vp0 = (l == L) ? up0 : (int64_t)m1 * m2, vp1 = (l == L) ? up1 : m2;
+    StencilArgs<T> s{};
+    for (int k = 0; k < 3; k++) s.ax[k] = restrict_tab(P, l, k, tab);
+    s.V = gV;
+    s.vp0 = vp0;
+    s.vp1 = vp1;
+    s.umc_w = nullptr;
+    s.up0 = up0;
+    s.up1 = up1;
+    s.F = F;
+    s.fp0 = fp0;
+    s.fp1 = fp1;
+    hipError_t e = traced("restrict_field", l, st, [&] { return launch_load_vector<T>(s, true, st); });
+    if (e != hipSuccess) return MGX_ERR_HIP;
+    // the coarse gradient: the stop box of g_mc, or the next level's input
+    const bool last = (l == stop + 1);
+    T *gW = last ? gmc : (((L - 1 - (l - 1)) % 2 == 0) ? A : B);
+    const int64_t wp0 = last ? up0 : cp0, wp1 = last ? up1 : cp1;
+    e = copy_box<T>(F, fp0, fp1, gW, wp0, wp1, c0, c1, c2, l, st);
+    if (e != hipSuccess) return MGX_ERR_HIP;
+    e = solve_level<T>(l, ax, P->real, F, fp0, fp1, kSolveInPlace, nullptr, 0, 0, F, fp0, fp1, st);
+    if (e != hipSuccess) return MGX_ERR_HIP;
+    ProlongArgs<T> pa{};
+    for (int k = 0; k < 3; k++) pa.ax[k] = ax[k];
+    pa.y = F;
+    pa.yp0 = fp0;
+    pa.yp1 = fp1;
+    pa.fine = gV;
+    pa.fp0 = vp0;
+    pa.fp1 = vp1;
+    pa.lc_out = gmc;
+    pa.up0 = up0;
+    pa.up1 = up1;
+    e = traced("prolong_mass_rec_adj", l, st, [&] { return launch_prolong_mass<T>(pa, kProlongRecAdj, st); });
+    if (e != hipSuccess) return MGX_ERR_HIP;
+  }
+  return MGX_OK;
+}
+
 // Common validation of decompose / recompose.
 mgx_status prepare(const void *in, void *out, mgx_dtype dtype, int ndim, const int64_t *dims,
                    const double *const *coords, int stop, void *ws, size_t ws_bytes, Plan **plan,
-                   Layout *lay, const void **tab) {
+                   Layout *lay, const void **tab, bool adjoint = false) {
   if (dtype != MGX_F32 && dtype != MGX_F64) return MGX_ERR_ARG;
   int64_t n[3];
   bool real[3];
@@ -286,7 +426,7 @@ mgx_status prepare(const void *in, void *out, mgx_dtype dtype, int ndim, const i
   Plan *P = get_plan(ndim, dims, coords, &st);
   if (!P) return (mgx_status)st;
   if (stop < 0 || stop > L) return MGX_ERR_LEVEL;
-  *lay = layout(n, real, L, stop, es);
+  *lay = layout(n, real, L, stop, es, adjoint);
   if (lay->total > 0) {
     if (!ws || ws_bytes < lay->total) return MGX_ERR_WORKSPACE;
     if (overlaps(ws, lay->total, in, bytes) || overlaps(ws, lay->total, out, bytes)) return MGX_ERR_ARG;
@@ -425,6 +565,48 @@ mgx_status mgx_recompose(const void *u_mc, void *u, mgx_dtype dtype, int ndim, c
                                 (const float *)tab, stream);
   return run_recompose<double>(P, stop_level, (const double *)u_mc, (double *)u, (char *)workspace, lay,
                                (const double *)tab, stream);
+}
+
+size_t mgx_adjoint_workspace_size(mgx_dtype dtype, int ndim, const int64_t *dims, int stop_level) {
+  if (dtype != MGX_F32 && dtype != MGX_F64) return 0;
+  int64_t n[3];
+  bool real[3];
+  int L;
+  if (parse_shape(ndim, dims, n, real, &L)) return 0;
+  if (stop_level < 0 || stop_level > L) return 0;
+  return layout(n, real, L, stop_level, elem_size(dtype), true).total;
+}
+
+mgx_status mgx_decompose_adjoint(const void *g_mc, void *g_u, mgx_dtype dtype, int ndim, const int64_t *dims,
+                                 const double *const *coords, int stop_level, void *workspace,
+                                 size_t workspace_bytes, hipStream_t stream) {
+  Plan *P;
+  Layout lay;
+  const void *tab;
+  mgx_status s = prepare(g_mc, g_u, dtype, ndim, dims, coords, stop_level, workspace, workspace_bytes, &P, &lay,
+                         &tab, true);
+  if (s) return s;
+  if (dtype == MGX_F32)
+    return run_decompose_adjoint<float>(P, stop_level, (const float *)g_mc, (float *)g_u, (char *)workspace, lay,
+                                        (const float *)tab, stream);
+  return run_decompose_adjoint<double>(P, stop_level, (const double *)g_mc, (double *)g_u, (char *)workspace, lay,
+                                       (const double *)tab, stream);
+}
+
+mgx_status mgx_recompose_adjoint(const void *g_u, void *g_mc, mgx_dtype dtype, int ndim, const int64_t *dims,
+                                 const double *const *coords, int stop_level, void *workspace,
+                                 size_t workspace_bytes, hipStream_t stream) {
+  Plan *P;
+  Layout lay;
+  const void *tab;
+  mgx_status s = prepare(g_u, g_mc, dtype, ndim, dims, coords, stop_level, workspace, workspace_bytes, &P, &lay,
+                         &tab, true);
+  if (s) return s;
+  if (dtype == MGX_F32)
+    return run_recompose_adjoint<float>(P, stop_level, (const float *)g_u, (float *)g_mc, (char *)workspace, lay,
+                                        (const float *)tab, stream);
+  return run_recompose_adjoint<double>(P, stop_level, (const double *)g_u, (double *)g_mc, (char *)workspace, lay,
+                                       (const double *)tab, stream);
 }
 
 mgx_status mgx_quantize(const void *u_mc, int32_t *labels, mgx_dtype dtype, int ndim, const int64_t *dims,

@@ -294,7 +294,7 @@ k_load_vector(StencilArgs<T> a) {
       }
     }
     // ---- coefficients of the owned nodes of plane j (decomposition) ----
-    if (DEC && plane_in && j >= own_p0 && j < own_p1) {
+    if (DEC && a.umc_w != nullptr && plane_in && j >= own_p0 && j < own_p1) {
       T *const cbase = a.umc_w + lc_pos(j, c0) * a.up0;
       if (!pz) {
         // even plane: corners in the plane itself; node 00 is nodal
@@ -886,6 +886,210 @@ __global__ void __launch_bounds__(NT) k_interp_add(InterpArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------
+// k_prolong_mass: one level of the adjoint (not in the paper).  Applies the
+// transpose of the fused load-vector operator, (M P) along every axis, to a
+// coarse box y and combines the level-l result with the level's other terms:
+//   kProlongRecAdj: lc_out[x] = fine[x] - ((M P) y)(x) at coefficient nodes,
+//   kProlongDecAdj: out[x] = ((M P) y)(x) + (x a coefficient node ? lc_in[x]
+//                                            : -r[x/2]).
+// Along one axis, (M P)[j][I] = (R M)[I][j] = w5[I][j - 2I + 2]: fine node 2I
+// takes coarse I-1, I, I+1 (entries 4, 2, 0) and fine node 2I+1 takes I, I+1
+// (entries 3, 1).  Tile as in k_interp_add.  The kernel marches over coarse
+// planes; each thread keeps, for its fixed fine positions, the 2-D product
+// (M P)_y (M P)_x of coarse planes J-1, J, J+1 in registers and combines
+// them along z into fine planes 2J and 2J+1.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void mp_weights(const T *w5, int c, int j, T &w0, T &w1, T &w2) {
+  const int I = j >> 1;
+  if (!(j & 1)) {
+    w0 = I - 1 >= 0 ? w5[(I - 1) * 5 + 4] : T(0);
+    w1 = w5[I * 5 + 2];
+    w2 = I + 1 < c ? w5[(I + 1) * 5 + 0] : T(0);
+  } else {
+    w0 = T(0);
+    w1 = w5[I * 5 + 3];
+    w2 = I + 1 < c ? w5[(I + 1) * 5 + 1] : T(0);
+  }
+}
+
+template <typename T, int TX, int TY, int NT, int MODE>
+__global__ void __launch_bounds__(NT) k_prolong_mass(ProlongArgs<T> a) {
+  constexpr int CW = TX + 3, CH = TY + 3;          // coarse tile with halo, from (Y0-1, X0-1)
+  constexpr int FW = 2 * TX + 1, FH = 2 * TY + 1;  // owned fine extent (max)
+  constexpr int NP = (FW * FH + NT - 1) / NT;
+  constexpr int NC = (CW * CH + NT - 1) / NT;
+  constexpr int ES = (int)sizeof(T);
+  __shared__ T sC[2][CH * CW];
+  __shared__ T sWx[3][FW], sWy[3][FH];
+
+  const int tid = threadIdx.x;
+  const int m0 = a.ax[0].m, m1 = a.ax[1].m, m2 = a.ax[2].m;
+  const int c0 = a.ax[0].c, c1 = a.ax[1].c, c2 = a.ax[2].c;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int tx = lb % a.ntx;
+  const int t2 = lb / a.ntx;
+  const int ty = t2 % a.nty;
+  const int tz = t2 / a.nty;
+  const int X0 = tx * TX, X1 = (tx == a.ntx - 1) ? c2 : X0 + TX;
+  const int Y0 = ty * TY, Y1 = (ty == a.nty - 1) ? c1 : Y0 + TY;
+  const int Z0 = tz * a.tz, Z1 = (tz == a.nzc - 1) ? c0 : Z0 + a.tz;
+  const int fq = min(2 * X1, m2) - 2 * X0;  // owned fine columns
+  const int fr = min(2 * Y1, m1) - 2 * Y0;  // owned fine rows
+
+  for (int q = tid; q < FW; q += NT) {
+    T w0 = T(0), w1 = T(0), w2 = T(0);
+    if (q < fq) mp_weights(a.ax[2].w5, c2, 2 * X0 + q, w0, w1, w2);
+    sWx[0][q] = w0;
+    sWx[1][q] = w1;
+    sWx[2][q] = w2;
+  }
+  for (int r = tid; r < FH; r += NT) {
+    T w0 = T(0), w1 = T(0), w2 = T(0);
+    if (r < fr) mp_weights(a.ax[1].w5, c1, 2 * Y0 + r, w0, w1, w2);
+    sWy[0][r] = w0;
+    sWy[1][r] = w1;
+    sWy[2][r] = w2;
+  }
+
+  // ---- coarse plane loads (zeros outside the box) ----
+  int coff[NC];
+  unsigned cvalid = 0;
+#pragma unroll
+  for (int k = 0; k < NC; k++) {
+    const int idx = tid + NT * k;
+    const int r = idx / CW, q = idx - r * CW;
+    const int J1 = Y0 - 1 + r, J2 = X0 - 1 + q;
+    const bool ok = idx < CH * CW && J1 >= 0 && J1 < c1 && J2 >= 0 && J2 < c2;
+    cvalid |= (unsigned)ok << k;
+    coff[k] = ok ? (J1 * (int)a.yp1 + J2) * ES : 0;
+  }
+  auto fetch = [&](int K, T (&v)[NC]) {
+    const bool pin = K >= 0 && K < c0;
+    const T *base = a.y + (int64_t)(pin ? K : 0) * a.yp0;
+#pragma unroll
+    for (int k = 0; k < NC; k++) {
+      const T x = ld_at(base, (uint32_t)coff[k]);
+      v[k] = (pin && ((cvalid >> k) & 1u)) ? x : T(0);
+    }
+  };
+  auto commit = [&](int slot, const T (&v)[NC]) {
+#pragma unroll
+    for (int k = 0; k < NC; k++)
+      if (tid + NT * k < CH * CW) sC[slot][tid + NT * k] = v[k];
+  };
+
+  // ---- owned fine positions ----
+  int pbase[NP], prq[NP], lcoff[NP], boff[NP], roff[NP];
+  unsigned pval = 0, pnod = 0;
+#pragma unroll
+  for (int k = 0; k < NP; k++) {
+    const int p = tid + NT * k;
+    const int r = p / FW, q = p - r * FW;
+    const bool ok = p < FW * FH && r < fr && q < fq;
+    pval |= (unsigned)ok << k;
+    const int j1 = 2 * Y0 + r, j2 = 2 * X0 + q;
+    pnod |= (unsigned)(!(j1 & 1) && !(j2 & 1)) << k;
+    pbase[k] = ok ? (r >> 1) * CW + (q >> 1) : 0;
+    prq[k] = ok ? (r << 16) | q : 0;
+    lcoff[k] = ok ? (int)(lc_pos(j1, c1) * a.up1 + lc_pos(j2, c2)) * ES : 0;
+    if (MODE == kProlongRecAdj)
+      boff[k] = ok ? (j1 * (int)a.fp1 + j2) * ES : 0;
+    else
+      boff[k] = ok ? (j1 * (int)a.op1 + j2) * ES : 0;
+    roff[k] = ok ? ((j1 >> 1) * (int)a.rp1 + (j2 >> 1)) * ES : 0;
+  }
+
+  auto computeH = [&](int slot, T (&H)[NP]) {
+#pragma unroll
+    for (int k = 0; k < NP; k++) {
+      H[k] = T(0);
+      if ((pval >> k) & 1u) {
+        const int r = prq[k] >> 16, q = prq[k] & 0xFFFF, b = pbase[k];
+        const T wx0 = sWx[0][q], wx1 = sWx[1][q], wx2 = sWx[2][q];
+        const T *C = &sC[slot][b];
+        const T h0 = wx0 * C[0] + wx1 * C[1] + wx2 * C[2];
+        const T h1 = wx0 * C[CW] + wx1 * C[CW + 1] + wx2 * C[CW + 2];
+        const T h2 = wx0 * C[2 * CW] + wx1 * C[2 * CW + 1] + wx2 * C[2 * CW + 2];
+        H[k] = sWy[0][r] * h0 + sWy[1][r] * h1 + sWy[2][r] * h2;
+      }
+    }
+  };
+
+  auto output = [&](int J, const T (&Hm)[NP], const T (&H0)[NP], const T (&Hp)[NP]) {
+    const T we0 = J - 1 >= 0 ? ldu(a.ax[0].w5, (J - 1) * 5 + 4) : T(0);
+    const T we1 = ldu(a.ax[0].w5, J * 5 + 2);
+    const T we2 = J + 1 < c0 ? ldu(a.ax[0].w5, (J + 1) * 5 + 0) : T(0);
+    const bool odd_in = 2 * J + 1 < m0;
+    const T wo1 = odd_in ? ldu(a.ax[0].w5, J * 5 + 3) : T(0);
+    const T wo2 = odd_in && J + 1 < c0 ? ldu(a.ax[0].w5, (J + 1) * 5 + 1) : T(0);
+    if (MODE == kProlongRecAdj) {
+      const T *fe = a.fine + (int64_t)(2 * J) * a.fp0;
+      const T *fo = a.fine + (int64_t)(odd_in ? 2 * J + 1 : 2 * J) * a.fp0;
+      T *le = a.lc_out + (int64_t)J * a.up0;
+      T *lo = a.lc_out + (int64_t)(odd_in ? c0 + J : J) * a.up0;
+#pragma unroll
+      for (int k = 0; k < NP; k++) {
+        if (!((pval >> k) & 1u)) continue;
+        if (!((pnod >> k) & 1u))
+          st_at(le, (uint32_t)lcoff[k], ld_at(fe, (uint32_t)boff[k]) - (we0 * Hm[k] + we1 * H0[k] + we2 * Hp[k]));
+        if (odd_in) st_at(lo, (uint32_t)lcoff[k], ld_at(fo, (uint32_t)boff[k]) - (wo1 * H0[k] + wo2 * Hp[k]));
+      }
+    } else {
+      T *oe = a.out + (int64_t)(2 * J) * a.op0;
+      T *oo = a.out + (int64_t)(odd_in ? 2 * J + 1 : 2 * J) * a.op0;
+      const T *le = a.lc_in + (int64_t)J * a.up0;
+      const T *lo = a.lc_in + (int64_t)(odd_in ? c0 + J : J) * a.up0;
+      const T *rb = a.r + (int64_t)J * a.rp0;
+#pragma unroll
+      for (int k = 0; k < NP; k++) {
+        if (!((pval >> k) & 1u)) continue;
+        const T other = ((pnod >> k) & 1u) ? -ld_at(rb, (uint32_t)roff[k]) : ld_at(le, (uint32_t)lcoff[k]);
+        st_at(oe, (uint32_t)boff[k], (we0 * Hm[k] + we1 * H0[k] + we2 * Hp[k]) + other);
+        if (odd_in) st_at(oo, (uint32_t)boff[k], (wo1 * H0[k] + wo2 * Hp[k]) + ld_at(lo, (uint32_t)lcoff[k]));
+      }
+    }
+  };
+
+  // slot of coarse plane K: (K - Z0 + 1) & 1
+  T creg[NC];
+  T Hm[NP], H0[NP], Hp[NP];
+  fetch(Z0 - 1, creg);
+  commit(0, creg);
+  fetch(Z0, creg);
+  __syncthreads();
+  computeH(0, Hm);
+  commit(1, creg);
+  fetch(Z0 + 1, creg);
+  __syncthreads();
+  computeH(1, H0);
+  for (int J = Z0; J < Z1; J++) {
+    const int s = (J - Z0) & 1;  // slot of plane J+1
+    commit(s, creg);
+    fetch(J + 2, creg);
+    __syncthreads();
+    computeH(s, Hp);
+    output(J, Hm, H0, Hp);
+#pragma unroll
+    for (int k = 0; k < NP; k++) {
+      Hm[k] = H0[k];
+      H0[k] = Hp[k];
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_copy_box(CopyArgs<T> a) {
+  const int64_t n = (int64_t)a.n0 * a.n1 * a.n2;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / a.n2;
+    const int i2 = (int)(i - r * a.n2);
+    const int i0 = (int)(r / a.n1), i1 = (int)(r - (int64_t)i0 * a.n1);
+    a.dst[i0 * a.dp0 + i1 * a.dp1 + i2] = a.src[i0 * a.sp0 + i1 * a.sp1 + i2];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Quantization (Sec. 4.1): label = rint(c / q_l) in FP64.
 // The level of a position in the level-centric layout is the smallest l whose
 // box holds it.  Along an axis with n - 1 = 2^m, the level-l box has
@@ -1214,6 +1418,29 @@ hipError_t launch_apply(StridedArgs<T> a, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_prolong_mass(ProlongArgs<T> a, int mode, hipStream_t st) {
+  constexpr int TX = Tiles<T>::TX, TY = Tiles<T>::TY, NT = Tiles<T>::NT;
+  if (!tile_grid(a.ax[0].c, a.ax[1].c, a.ax[2].c, TX, TY, &a.ntx, &a.nty, &a.nzc, &a.tz))
+    return hipErrorInvalidValue;
+  dim3 grid(a.ntx * a.nty * a.nzc);
+  if (mode == kProlongRecAdj)
+    hipLaunchKernelGGL((k_prolong_mass<T, TX, TY, NT, kProlongRecAdj>), grid, dim3(NT), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_prolong_mass<T, TX, TY, NT, kProlongDecAdj>), grid, dim3(NT), 0, st, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_copy_box(CopyArgs<T> a, hipStream_t st) {
+  const int64_t n = (int64_t)a.n0 * a.n1 * a.n2;
+  int64_t g = (n + 255) / 256;
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL((k_copy_box<T>), dim3((unsigned)g), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
 static unsigned quant_grid(int64_t n) {
   int64_t g = (n + 1023) / 1024;
   if (g > 8192) g = 8192;
@@ -1256,6 +1483,8 @@ hipError_t launch_dequantize(const int32_t *labels, T *umc, QuantArgs a, hipStre
   template hipError_t launch_solve_contig<T>(SolveArgs<T>, hipStream_t);                      \
   template hipError_t launch_solve_strided<T>(StridedArgs<T>, int, hipStream_t);              \
   template hipError_t launch_apply<T>(StridedArgs<T>, hipStream_t);                           \
+  template hipError_t launch_prolong_mass<T>(ProlongArgs<T>, int, hipStream_t);               \
+  template hipError_t launch_copy_box<T>(CopyArgs<T>, hipStream_t);                           \
   template hipError_t launch_quantize<T>(const T *, int32_t *, QuantArgs, bool, hipStream_t); \
   template hipError_t launch_dequantize<T>(const int32_t *, T *, QuantArgs, hipStream_t);
 

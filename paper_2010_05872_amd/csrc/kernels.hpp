@@ -30,7 +30,7 @@ struct StencilArgs {
   AxisTab<T> ax[3];
   const T *V;                 // level-l box (decompose), compact
   int64_t vp0, vp1;           // its plane and row pitches
-  T *umc_w;                   // u_mc (decompose writes coefficients)
+  T *umc_w;                   // u_mc (decompose writes coefficients; null: load vector only)
   const T *umc_r;             // u_mc (recompose reads coefficients)
   int64_t up0, up1;           // u_mc pitches (finest grid)
   T *F;                       // load vector out, coarse box
@@ -75,6 +75,37 @@ struct StridedArgs {          // strided-axis solve (optionally applying)
   T sign;
 };
 
+// Adjoint: the transposed load-vector operator (M P) along every axis, from a
+// coarse box y to the level-l box, combined with the level's other terms.
+constexpr int kProlongRecAdj = 0;  // lc_out[x] = fine[x] - (MP)y at coefficient nodes
+constexpr int kProlongDecAdj = 1;  // out[x] = (MP)y + (coef node ? lc_in[x] : -r[x/2])
+
+template <typename T>
+struct ProlongArgs {
+  AxisTab<T> ax[3];           // w5 (the R M stencil), m, c
+  const T *y;                 // coarse box
+  int64_t yp0, yp1;
+  const T *fine;              // recompose adjoint: level-l box in
+  int64_t fp0, fp1;
+  T *lc_out;                  // recompose adjoint: coefficient gradient out (level-centric)
+  const T *lc_in;             // decompose adjoint: coefficient gradient in (level-centric)
+  int64_t up0, up1;           // level-centric array pitches
+  const T *r;                 // decompose adjoint: R of the coefficient gradient, coarse box
+  int64_t rp0, rp1;
+  T *out;                     // decompose adjoint: level-l box out
+  int64_t op0, op1;
+  int ntx, nty, nzc, tz;
+};
+
+template <typename T>
+struct CopyArgs {             // strided copy of an n0 x n1 x n2 box
+  const T *src;
+  int64_t sp0, sp1;
+  T *dst;
+  int64_t dp0, dp1;
+  int n0, n1, n2;
+};
+
 struct QuantArgs {
   int64_t n;                  // element count (< 2^32)
   int n1, n2;                 // padded dims 1 and 2
@@ -91,6 +122,8 @@ template <typename T> hipError_t launch_interp_add(InterpArgs<T> a, hipStream_t 
 template <typename T> hipError_t launch_solve_contig(SolveArgs<T> a, hipStream_t st);
 template <typename T> hipError_t launch_solve_strided(StridedArgs<T> a, int mode, hipStream_t st);
 template <typename T> hipError_t launch_apply(StridedArgs<T> a, hipStream_t st);
+template <typename T> hipError_t launch_prolong_mass(ProlongArgs<T> a, int mode, hipStream_t st);
+template <typename T> hipError_t launch_copy_box(CopyArgs<T> a, hipStream_t st);
 template <typename T>
 hipError_t launch_quantize(const T *umc, int32_t *labels, QuantArgs a, bool stats, hipStream_t st);
 template <typename T>

@@ -94,6 +94,16 @@ void build_axis(const std::vector<double> &Y, AxisLevel &a, std::vector<double> 
     }
     for (int d = 0; d < 5; d++) tab.push_back(w[d]);
   }
+  // restriction alone, same layout (the transpose of the prolongation P)
+  a.off_p5 = tab.size();
+  for (int64_t J = 0; J < c; J++) {
+    const int64_t j = 2 * J;
+    tab.push_back(0.0);
+    tab.push_back(j - 1 >= 0 ? rl(J) : 0.0);
+    tab.push_back(1.0);
+    tab.push_back(j + 1 < m ? rr(J) : 0.0);
+    tab.push_back(0.0);
+  }
   // coarse mass matrix on the even nodes and its Thomas factors
   std::vector<double> sub(c), dia(c), sup(c), dp(c);
   for (int64_t J = 0; J < c; J++) {
@@ -154,6 +164,8 @@ void build_padded(AxisLevel &a, std::vector<double> &tab) {
   a.off_wr = tab.size();
   tab.push_back(0.0);
   a.off_w5 = tab.size();
+  for (int d = 0; d < 5; d++) tab.push_back(d == 2 ? 1.0 : 0.0);
+  a.off_p5 = tab.size();
   for (int d = 0; d < 5; d++) tab.push_back(d == 2 ? 1.0 : 0.0);
   a.off_mult = tab.size();
   tab.push_back(0.0);

@@ -11,6 +11,7 @@
 //           (Sec. 5.4, reuse of intermediate variables): forward
 //           f'_J = f_J - mult_J f'_{J-1}, backward
 //           y_J = invd_J f'_J - qsup_J y_{J+1},
+//   p5      the restriction R = P^T alone, in the layout of w5 (adjoint),
 //   multb, invdb, qsub, mid  the same elimination run from the last row up
 //           (g'_J = f_J - multb_J g'_{J+1}, y_J = invdb_J g'_J - qsub_J y_{J-1})
 //           and the row K = c/2 where the two meet:
@@ -40,6 +41,9 @@ struct AxisLevel {
   // factors of the elimination from the last row upwards and of the middle
   // row, for the two-ended (twisted) factorization of the same matrix
   size_t off_multb = 0, off_invdb = 0, off_qsub = 0, off_mid = 0;
+  // the restriction R = P^T alone as a 5-point stencil in the layout of w5
+  // (0, weight of fine 2J-1, 1, weight of fine 2J+1, 0): used by the adjoint
+  size_t off_p5 = 0;
 };
 
 struct Plan {
