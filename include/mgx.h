@@ -144,6 +144,63 @@ mgx_status mgx_recompose_adjoint(const void *g_u, void *g_mc, mgx_dtype dtype, i
                                  const int64_t *dims, const double *const *coords, int stop_level,
                                  void *workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* ---- Batched fields (project extension, not in the paper) ----
+ * Many independent fields of uneven shapes in one graph launch.  The
+ * library records every field's launch sequence (the steps of
+ * mgx_decompose / mgx_recompose, and the quantizer when labels are given),
+ * runs the same step of all fields as one multi-field kernel launch (one per
+ * kernel instance), captures the whole sequence into a HIP graph once per
+ * batch (keyed by the field list and the workspace pointer) and replays it.
+ * The first call of a batch also picks the launch shape of the tiled
+ * stencil kernels by timing candidate graphs (autotuning; it synchronizes
+ * the stream), unless mgx_batch_set_autotune(0).  The paper processes each
+ * field separately (one field per core, Sec. 6). */
+typedef struct {
+  const void *in;            /* decompose: u; recompose: u_mc (unused when labels is set)   */
+  void *out;                 /* decompose: u_mc; recompose: u                               */
+  mgx_dtype dtype;
+  int ndim;
+  int64_t dims[3];           /* C order, first ndim entries used                            */
+  const double *coords[3];   /* per axis, NULL: 0 .. n-1                                    */
+  int stop_level;
+  double tol_linf;           /* with labels: the absolute L-infinity tolerance              */
+  double c_linf;             /* <= 0: library default                                       */
+  int32_t *labels;           /* decompose: labels out (NULL: no quantization);
+                                recompose: labels in (NULL: recompose from in)              */
+  void *coef;                /* recompose from labels: device buffer (dims, dtype) that
+                                receives the dequantized coefficients                      */
+} mgx_field;
+
+typedef struct {
+  int launches;              /* kernel launches in the batch's graph                        */
+  int target_blocks;         /* chosen launch shape of the stencil kernels                  */
+  int min_zchunk;
+  double tuned_ms;           /* time of the chosen graph during tuning (0: not tuned)       */
+} mgx_batch_info;
+
+/* Workspace bytes for mgx_decompose_batched / mgx_recompose_batched (the
+ * sum of the fields' mgx_workspace_size, each 256-byte aligned; 0 on
+ * invalid fields). */
+size_t mgx_batch_workspace_size(int nfields, const mgx_field *fields);
+
+/* Every field as mgx_decompose (then mgx_quantize into labels when
+ * labels != NULL, without statistics).  Outputs and labels of different
+ * fields must not overlap.  Errors: those of the single-field calls (the
+ * first failing field decides), MGX_ERR_WORKSPACE, MGX_ERR_HIP. */
+mgx_status mgx_decompose_batched(int nfields, const mgx_field *fields, void *workspace,
+                                 size_t workspace_bytes, hipStream_t stream);
+
+/* Every field as mgx_recompose; with labels != NULL first as
+ * mgx_dequantize(labels) into coef, then recomposed from coef. */
+mgx_status mgx_recompose_batched(int nfields, const mgx_field *fields, void *workspace,
+                                 size_t workspace_bytes, hipStream_t stream);
+
+/* Autotuning of batches on first use: 1 (default) or 0 (default shape). */
+mgx_status mgx_batch_set_autotune(int on);
+
+/* Shape of the most recent batched call of this thread. */
+mgx_status mgx_batch_last_info(mgx_batch_info *info);
+
 /* Level-wise quantization (Sec. 4.1, eq. (LinfTau); Algorithm 1, quantize
  * step).  tau_l~ = (1-kappa)/(1-kappa^(L+1-l~)) * tol_linf / C and
  * tau_l = kappa tau_{l-1} with kappa = sqrt(2^d), all in FP64 in that

@@ -54,6 +54,32 @@ class QuantStats(ctypes.Structure):
         }
 
 
+class Field(ctypes.Structure):
+    """mgx_field of include/mgx.h."""
+    _fields_ = [
+        ("in_", ctypes.c_void_p),
+        ("out", ctypes.c_void_p),
+        ("dtype", ctypes.c_int),
+        ("ndim", ctypes.c_int),
+        ("dims", ctypes.c_int64 * 3),
+        ("coords", ctypes.c_void_p * 3),
+        ("stop_level", ctypes.c_int),
+        ("tol_linf", ctypes.c_double),
+        ("c_linf", ctypes.c_double),
+        ("labels", ctypes.c_void_p),
+        ("coef", ctypes.c_void_p),
+    ]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [
+        ("launches", ctypes.c_int),
+        ("target_blocks", ctypes.c_int),
+        ("min_zchunk", ctypes.c_int),
+        ("tuned_ms", ctypes.c_double),
+    ]
+
+
 class KernelTime(ctypes.Structure):
     _fields_ = [
         ("name", ctypes.c_char * 40),
@@ -68,7 +94,8 @@ EXPORTS = (
     "mgx_status_string", "mgx_num_levels", "mgx_workspace_size", "mgx_decompose", "mgx_recompose",
     "mgx_quantize", "mgx_dequantize", "mgx_linf_constant", "mgx_level_tolerances",
     "mgx_trace_enable", "mgx_trace_read", "mgx_adjoint_workspace_size", "mgx_decompose_adjoint",
-    "mgx_recompose_adjoint",
+    "mgx_recompose_adjoint", "mgx_batch_workspace_size", "mgx_decompose_batched", "mgx_recompose_batched",
+    "mgx_batch_set_autotune", "mgx_batch_last_info",
 )
 
 _lib = None
@@ -96,6 +123,17 @@ def lib():
             f = getattr(L, name)
             f.argtypes = [vp, vp, ci, ci, i64p, vp, ci, vp, sz, vp]
             f.restype = ci
+        fp = ctypes.POINTER(Field)
+        L.mgx_batch_workspace_size.argtypes = [ci, fp]
+        L.mgx_batch_workspace_size.restype = sz
+        for name in ("mgx_decompose_batched", "mgx_recompose_batched"):
+            f = getattr(L, name)
+            f.argtypes = [ci, fp, vp, sz, vp]
+            f.restype = ci
+        L.mgx_batch_set_autotune.argtypes = [ci]
+        L.mgx_batch_set_autotune.restype = ci
+        L.mgx_batch_last_info.argtypes = [ctypes.POINTER(BatchInfo)]
+        L.mgx_batch_last_info.restype = ci
         L.mgx_quantize.argtypes = [vp, vp, ci, ci, i64p, vp, cd, ci, cd, ctypes.POINTER(QuantStats), vp]
         L.mgx_quantize.restype = ci
         L.mgx_dequantize.argtypes = [vp, vp, ci, ci, i64p, vp, cd, ci, cd, vp]
@@ -281,6 +319,78 @@ def decompose_adjoint(g_mc, coords=None, stop_level=0, out=None, workspace=None)
 def recompose_adjoint(g_u, coords=None, stop_level=0, out=None, workspace=None):
     """R^T: field-space gradient -> coefficient-space gradient (level-centric)."""
     return _adjoint_call("mgx_recompose_adjoint", g_u, coords, stop_level, out, workspace)
+
+
+# ---------------------------------------------------------------- batches of fields
+class Batch:
+    """A fixed list of fields for mgx_decompose_batched / mgx_recompose_batched.
+
+    fields: list of dicts with keys
+      in (tensor), out (tensor), coords (per-axis list or None), stop_level,
+      tol (with labels), c_linf, labels (int32 tensor or None), coef (tensor,
+      recompose from labels).
+    The same Batch object (same tensors) replays the captured graph; the
+    workspace is allocated once per Batch.
+    """
+
+    def __init__(self, fields, workspace=None):
+        import torch
+        self._keep = []
+        n = len(fields)
+        self.arr = (Field * n)()
+        dev = None
+        for i, f in enumerate(fields):
+            t_in, t_out = f.get("in"), f["out"]
+            ref = t_in if t_in is not None else t_out
+            dev = ref.device
+            x = self.arr[i]
+            x.in_ = t_in.data_ptr() if t_in is not None else None
+            x.out = t_out.data_ptr()
+            x.dtype = _dtype_code(t_out)
+            x.ndim = t_out.dim()
+            for k in range(3):
+                x.dims[k] = int(t_out.shape[k]) if k < t_out.dim() else 0
+            c = Coords(t_out.shape, f.get("coords"))
+            self._keep.append(c)
+            if c.ptr is not None:
+                ptrs = ctypes.cast(c.ptr, ctypes.POINTER(ctypes.c_void_p))
+                for k in range(t_out.dim()):
+                    x.coords[k] = ptrs[k]
+            x.stop_level = int(f.get("stop_level", 0))
+            x.tol_linf = float(f.get("tol", 0.0))
+            x.c_linf = float(f.get("c_linf", 0.0))
+            lab = f.get("labels")
+            x.labels = lab.data_ptr() if lab is not None else None
+            coef = f.get("coef")
+            x.coef = coef.data_ptr() if coef is not None else None
+            self._keep.extend([t for t in (t_in, t_out, lab, coef) if t is not None])
+        self.n = n
+        self.device = dev
+        need = int(lib().mgx_batch_workspace_size(n, self.arr))
+        if need == 0 and n > 0:
+            raise MgxError(1, "mgx_batch_workspace_size")
+        self.workspace = workspace if workspace is not None else torch.empty(max(need, 1), dtype=torch.uint8,
+                                                                             device=dev)
+        self.ws_bytes = self.workspace.numel() * self.workspace.element_size()
+
+    def decompose(self):
+        _check(lib().mgx_decompose_batched(self.n, self.arr, self.workspace.data_ptr(), self.ws_bytes,
+                                           _stream(self.device)), "mgx_decompose_batched")
+
+    def recompose(self):
+        _check(lib().mgx_recompose_batched(self.n, self.arr, self.workspace.data_ptr(), self.ws_bytes,
+                                           _stream(self.device)), "mgx_recompose_batched")
+
+
+def batch_set_autotune(on: bool) -> None:
+    _check(lib().mgx_batch_set_autotune(1 if on else 0), "mgx_batch_set_autotune")
+
+
+def batch_last_info() -> dict:
+    info = BatchInfo()
+    _check(lib().mgx_batch_last_info(ctypes.byref(info)), "mgx_batch_last_info")
+    return {"launches": info.launches, "target_blocks": info.target_blocks, "min_zchunk": info.min_zchunk,
+            "tuned_ms": info.tuned_ms}
 
 
 def quantize(u_mc, tol, coords=None, stop_level=0, c_linf=0.0, out=None, stats=False):

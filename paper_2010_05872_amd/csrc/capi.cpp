@@ -2,9 +2,13 @@
 // the per-level launch sequences of decomposition and recomposition.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "kernels.hpp"
@@ -120,33 +124,66 @@ AxisTab<T> axis_tab(const Plan *P, int l, int k, const T *tab) {
   return t;
 }
 
+// Sink of the launch sequences below.  Immediately launched (single field,
+// traced when tracing is on), or recorded for a multi-field batch: the
+// batch runs ops of equal (step, phase) of all its fields together, where
+// step counts levels from the finest and phase counts ops within a level.
+template <typename T>
+struct RecordedOp {
+  int kind, mode, step, phase;
+  const char *name;
+  int level;
+  OpArgs<T> a;
+};
+
+template <typename T>
+struct Emitter {
+  hipStream_t st = nullptr;
+  Tuning tn{};
+  std::vector<RecordedOp<T>> *rec = nullptr;
+  int base = 0, step = 0, phase = 0;
+  void begin_step(int s) {
+    step = base + s;
+    phase = 0;
+  }
+  hipError_t op(int kind, int mode, const char *name, int level, const OpArgs<T> &a) {
+    if (rec) {
+      rec->push_back({kind, mode, step, phase++, name, level, a});
+      return hipSuccess;
+    }
+    return traced(name, level, st, [&] { return launch_op<T>(kind, mode, a, tn, st); });
+  }
+};
+
 // The coarse solves of one level on F (c0 x c1 x c2, pitches fp0,fp1), one
 // per real axis, the contiguous axis first.  The last one either stores the
-// solution (decomposition: out = Q_{l-1} u) or applies it to the nodal
-// values (recomposition: out = in - correction).
+// solution (decomposition: out = Q_{l-1} u), applies it to the nodal values
+// (recomposition: out = in - correction) or leaves it in F (in place).
 template <typename T>
 hipError_t solve_level(int level, const AxisTab<T> ax[3], const bool real[3], T *F, int64_t fp0, int64_t fp1,
                        int last_mode, const T *in, int64_t ip0, int64_t ip1, T *out, int64_t op0, int64_t op1,
-                       hipStream_t st) {
+                       Emitter<T> &em) {
   const int c0 = ax[0].c, c1 = ax[1].c, c2 = ax[2].c;
   hipError_t e;
   {
-    SolveArgs<T> s{F, (int64_t)c0 * c1, fp1, c2, ax[2].mult, ax[2].invd, ax[2].qsup};
-    if ((e = traced("solve_contig", level, st, [&] { return launch_solve_contig<T>(s, st); })) != hipSuccess)
-      return e;
+    OpArgs<T> o{};
+    o.so = SolveArgs<T>{F, (int64_t)c0 * c1, fp1, c2, ax[2].mult, ax[2].invd, ax[2].qsup};
+    if ((e = em.op(kOpSolveContig, 0, "solve_contig", level, o)) != hipSuccess) return e;
   }
   const T sign = T(-1);
   if (!real[1]) {  // 1-D: the solved row is the result
-    StridedArgs<T> s{};
+    OpArgs<T> o{};
+    StridedArgs<T> &s = o.sd;
     s.F = F;
     s.nx = c2;
     s.in = last_mode == kSolveApply ? in : nullptr;
     s.out = out;
     s.sign = sign;
-    return traced("finish_1d", level, st, [&] { return launch_apply<T>(s, st); });
+    return em.op(kOpApply, 0, "finish_1d", level, o);
   }
   auto strided = [&](int k, int mode, const char *name) {
-    StridedArgs<T> s{};
+    OpArgs<T> o{};
+    StridedArgs<T> &s = o.sd;
     s.F = F;
     s.c = ax[k].c;
     s.sj = k == 1 ? fp1 : fp0;  // line stride
@@ -169,30 +206,45 @@ hipError_t solve_level(int level, const AxisTab<T> ax[3], const bool real[3], T 
       s.oo = k == 1 ? op0 : op1;
       s.sign = sign;
     }
-    return traced(name, level, st, [&] { return launch_solve_strided<T>(s, mode, st); });
+    return em.op(kOpSolveStrided, mode, name, level, o);
   };
-  const char *last_name = last_mode == kSolveApply ? "solve_strided_apply" : "solve_strided_store";
+  const char *last_name = last_mode == kSolveApply   ? "solve_strided_apply"
+                          : last_mode == kSolveStore ? "solve_strided_store"
+                                                     : "solve_strided";
   if (!real[0]) return strided(1, last_mode, last_name);  // 2-D
   if ((e = strided(1, kSolveInPlace, "solve_strided")) != hipSuccess) return e;
   return strided(0, last_mode, last_name);
 }
 
 template <typename T>
+hipError_t copy_box(const T *src, int64_t sp0, int64_t sp1, T *dst, int64_t dp0, int64_t dp1, int n0, int n1,
+                    int n2, int level, Emitter<T> &em) {
+  OpArgs<T> o{};
+  o.cp = CopyArgs<T>{src, sp0, sp1, dst, dp0, dp1, n0, n1, n2};
+  return em.op(kOpCopyBox, 0, "copy_box", level, o);
+}
+
+template <typename T>
 mgx_status run_decompose(Plan *P, int stop, const T *u, T *umc, char *ws, const Layout &lay, const T *tab,
-                         hipStream_t st) {
+                         Emitter<T> &em) {
   const int L = P->L;
   const int64_t n1 = P->n[1], n2 = P->n[2];
   const int64_t up0 = n1 * n2, up1 = n2;
-  if (stop == L) return hip_status(hipMemcpyAsync(umc, u, sizeof(T) * P->n[0] * up0, hipMemcpyDeviceToDevice, st));
+  if (stop == L) {
+    em.begin_step(0);
+    return hip_status(copy_box<T>(u, up0, up1, umc, up0, up1, (int)P->n[0], (int)n1, (int)n2, L, em));
+  }
   T *A = (T *)(ws + lay.offA), *B = (T *)(ws + lay.offB), *F = (T *)(ws + lay.offF);
   const T *src = u;
   int64_t sp0 = up0, sp1 = up1;
   for (int l = L; l > stop; l--) {
+    em.begin_step(L - l);
     AxisTab<T> ax[3] = {axis_tab(P, l, 0, tab), axis_tab(P, l, 1, tab), axis_tab(P, l, 2, tab)};
     const int c1 = ax[1].c, c2 = ax[2].c;
     const int64_t cp1 = c2, cp0 = (int64_t)c1 * c2;
     const int64_t fp1 = round4(c2), fp0 = (int64_t)c1 * fp1;
-    StencilArgs<T> s{};
+    OpArgs<T> o{};
+    StencilArgs<T> &s = o.st;
     for (int k = 0; k < 3; k++) s.ax[k] = ax[k];
     s.V = src;
     s.vp0 = sp0;
@@ -203,14 +255,14 @@ mgx_status run_decompose(Plan *P, int stop, const T *u, T *umc, char *ws, const 
     s.F = F;
     s.fp0 = fp0;
     s.fp1 = fp1;
-    hipError_t e = traced("load_vector_dec", l, st, [&] { return launch_load_vector<T>(s, true, st); });
+    hipError_t e = em.op(kOpLoadVecDec, 0, "load_vector_dec", l, o);
     if (e != hipSuccess) return MGX_ERR_HIP;
     // Q_{l-1} u goes to the compact box of level l-1, or into the corner of
     // u_mc after the last decomposed level
     const bool last = (l == stop + 1);
     T *dst = last ? umc : (((L - 1 - (l - 1)) % 2 == 0) ? A : B);
     const int64_t op0 = last ? up0 : cp0, op1 = last ? up1 : cp1;
-    e = solve_level<T>(l, ax, P->real, F, fp0, fp1, kSolveStore, nullptr, 0, 0, dst, op0, op1, st);
+    e = solve_level<T>(l, ax, P->real, F, fp0, fp1, kSolveStore, nullptr, 0, 0, dst, op0, op1, em);
     if (e != hipSuccess) return MGX_ERR_HIP;
     src = dst;
     sp0 = cp0;
@@ -221,13 +273,17 @@ mgx_status run_decompose(Plan *P, int stop, const T *u, T *umc, char *ws, const 
 
 template <typename T>
 mgx_status run_recompose(Plan *P, int stop, const T *umc, T *u, char *ws, const Layout &lay, const T *tab,
-                         hipStream_t st) {
+                         Emitter<T> &em) {
   const int L = P->L;
   const int64_t n1 = P->n[1], n2 = P->n[2];
   const int64_t up0 = n1 * n2, up1 = n2;
-  if (stop == L) return hip_status(hipMemcpyAsync(u, umc, sizeof(T) * P->n[0] * up0, hipMemcpyDeviceToDevice, st));
+  if (stop == L) {
+    em.begin_step(0);
+    return hip_status(copy_box<T>(umc, up0, up1, u, up0, up1, (int)P->n[0], (int)n1, (int)n2, L, em));
+  }
   T *A = (T *)(ws + lay.offA), *B = (T *)(ws + lay.offB), *F = (T *)(ws + lay.offF);
   for (int l = stop + 1; l <= L; l++) {
+    em.begin_step(l - stop - 1);
     AxisTab<T> ax[3] = {axis_tab(P, l, 0, tab), axis_tab(P, l, 1, tab), axis_tab(P, l, 2, tab)};
     const int c1 = ax[1].c, c2 = ax[2].c;
     const int m1 = ax[1].m, m2 = ax[2].m;
@@ -237,7 +293,8 @@ mgx_status run_recompose(Plan *P, int stop, const T *umc, T *u, char *ws, const 
     const bool first = (l == stop + 1);
     const T *nin = first ? umc : nb;
     const int64_t ip0 = first ? up0 : cp0, ip1 = first ? up1 : cp1;
-    StencilArgs<T> s{};
+    OpArgs<T> o{};
+    StencilArgs<T> &s = o.st;
     for (int k = 0; k < 3; k++) s.ax[k] = ax[k];
     s.umc_r = umc;
     s.up0 = up0;
@@ -245,11 +302,12 @@ mgx_status run_recompose(Plan *P, int stop, const T *umc, T *u, char *ws, const 
     s.F = F;
     s.fp0 = fp0;
     s.fp1 = fp1;
-    hipError_t e = traced("load_vector_rec", l, st, [&] { return launch_load_vector<T>(s, false, st); });
+    hipError_t e = em.op(kOpLoadVecRec, 0, "load_vector_rec", l, o);
     if (e != hipSuccess) return MGX_ERR_HIP;
-    e = solve_level<T>(l, ax, P->real, F, fp0, fp1, kSolveApply, nin, ip0, ip1, nb, cp0, cp1, st);
+    e = solve_level<T>(l, ax, P->real, F, fp0, fp1, kSolveApply, nin, ip0, ip1, nb, cp0, cp1, em);
     if (e != hipSuccess) return MGX_ERR_HIP;
-    InterpArgs<T> ia{};
+    OpArgs<T> oi{};
+    InterpArgs<T> &ia = oi.ia;
     for (int k = 0; k < 3; k++) ia.ax[k] = ax[k];
     ia.nodal = nb;
     ia.np0 = cp0;
@@ -266,7 +324,7 @@ mgx_status run_recompose(Plan *P, int stop, const T *umc, T *u, char *ws, const 
       ia.op1 = m2;
       ia.op0 = (int64_t)m1 * m2;
     }
-    e = traced("interp_add", l, st, [&] { return launch_interp_add<T>(ia, st); });
+    e = em.op(kOpInterpAdd, 0, "interp_add", l, oi);
     if (e != hipSuccess) return MGX_ERR_HIP;
   }
   return MGX_OK;
@@ -281,13 +339,6 @@ AxisTab<T> restrict_tab(const Plan *P, int l, int k, const T *tab) {
   return t;
 }
 
-template <typename T>
-hipError_t copy_box(const T *src, int64_t sp0, int64_t sp1, T *dst, int64_t dp0, int64_t dp1, int n0, int n1,
-                    int n2, int level, hipStream_t st) {
-  CopyArgs<T> c{src, sp0, sp1, dst, dp0, dp1, n0, n1, n2};
-  return traced("copy_box", level, st, [&] { return launch_copy_box<T>(c, st); });
-}
-
 // Adjoint of decomposition (not in the paper): g_u = D^T g_mc.  D is the
 // product of the level maps D_L first ... D_{stop+1} last, so the transpose
 // runs the levels upwards.  Per level, with gW the gradient of the coarse
@@ -297,6 +348,8 @@ hipError_t copy_box(const T *src, int64_t sp0, int64_t sp1, T *dst, int64_t dp0,
 template <typename T>
 mgx_status run_decompose_adjoint(Plan *P, int stop, const T *gmc, T *gu, char *ws, const Layout &lay,
                                  const T *tab, hipStream_t st) {
+  Emitter<T> em;
+  em.st = st;
   const int L = P->L;
   const int64_t n1 = P->n[1], n2 = P->n[2];
   const int64_t up0 = n1 * n2, up1 = n2;
@@ -311,9 +364,9 @@ mgx_status run_decompose_adjoint(Plan *P, int stop, const T *gmc, T *gu, char *w
     const bool first = (l == stop + 1);
     const T *gW = first ? gmc : (((L - 1 - (l - 1)) % 2 == 0) ? A : B);
     const int64_t wp0 = first ? up0 : cp0, wp1 = first ? up1 : cp1;
-    hipError_t e = copy_box<T>(gW, wp0, wp1, F, fp0, fp1, c0, c1, c2, l, st);
+    hipError_t e = copy_box<T>(gW, wp0, wp1, F, fp0, fp1, c0, c1, c2, l, em);
     if (e != hipSuccess) return MGX_ERR_HIP;
-    e = solve_level<T>(l, ax, P->real, F, fp0, fp1, kSolveInPlace, nullptr, 0, 0, F, fp0, fp1, st);
+    e = solve_level<T>(l, ax, P->real, F, fp0, fp1, kSolveInPlace, nullptr, 0, 0, F, fp0, fp1, em);
     if (e != hipSuccess) return MGX_ERR_HIP;
     StencilArgs<T> s{};
     for (int k = 0; k < 3; k++) s.ax[k] = restrict_tab(P, l, k, tab);
@@ -358,6 +411,8 @@ mgx_status run_decompose_adjoint(Plan *P, int stop, const T *gmc, T *gu, char *w
 template <typename T>
 mgx_status run_recompose_adjoint(Plan *P, int stop, const T *gu, T *gmc, char *ws, const Layout &lay,
                                  const T *tab, hipStream_t st) {
+  Emitter<T> em;
+  em.st = st;
   const int L = P->L;
   const int64_t n1 = P->n[1], n2 = P->n[2];
   const int64_t up0 = n1 * n2, up1 = n2;
@@ -388,9 +443,9 @@ mgx_status run_recompose_adjoint(Plan *P, int stop, const T *gu, T *gmc, char *w
     const bool last = (l == stop + 1);
     T *gW = last ? gmc : (((L - 1 - (l - 1)) % 2 == 0) ? A : B);
     const int64_t wp0 = last ? up0 : cp0, wp1 = last ? up1 : cp1;
-    e = copy_box<T>(F, fp0, fp1, gW, wp0, wp1, c0, c1, c2, l, st);
+    e = copy_box<T>(F, fp0, fp1, gW, wp0, wp1, c0, c1, c2, l, em);
     if (e != hipSuccess) return MGX_ERR_HIP;
-    e = solve_level<T>(l, ax, P->real, F, fp0, fp1, kSolveInPlace, nullptr, 0, 0, F, fp0, fp1, st);
+    e = solve_level<T>(l, ax, P->real, F, fp0, fp1, kSolveInPlace, nullptr, 0, 0, F, fp0, fp1, em);
     if (e != hipSuccess) return MGX_ERR_HIP;
     ProlongArgs<T> pa{};
     for (int k = 0; k < 3; k++) pa.ax[k] = ax[k];
@@ -497,6 +552,341 @@ StatsBuf &stats_buf() {
   return *s;
 }
 
+// ---- batches of fields (multi-field launches in one captured graph) ----
+struct BatchField {
+  Plan *P = nullptr;
+  const void *tab = nullptr;
+  Layout lay;
+  size_t ws_off = 0;
+};
+
+mgx_status batch_validate(int nfields, const mgx_field *f, bool dec, std::vector<BatchField> &out,
+                          size_t *ws_total, bool check_ptrs = true) {
+  if (nfields < 1 || !f) return MGX_ERR_ARG;
+  out.assign(nfields, BatchField{});
+  size_t off = 0;
+  int dev = 0;
+  if (check_ptrs && hipGetDevice(&dev) != hipSuccess) return MGX_ERR_HIP;
+  for (int i = 0; i < nfields; i++) {
+    const mgx_field &x = f[i];
+    if (x.dtype != MGX_F32 && x.dtype != MGX_F64) return MGX_ERR_ARG;
+    int64_t n[3];
+    bool real[3];
+    int L;
+    int st = parse_shape(x.ndim, x.dims, n, real, &L);
+    if (st) return (mgx_status)st;
+    const size_t es = elem_size(x.dtype);
+    const size_t bytes = (size_t)(n[0] * n[1] * n[2]) * es;
+    if (check_ptrs) {
+      if (!x.out) return MGX_ERR_ARG;
+      if (dec || !x.labels) {
+        if (!x.in || overlaps(x.in, bytes, x.out, bytes)) return MGX_ERR_ARG;
+      } else {
+        if (!x.coef || overlaps(x.coef, bytes, x.out, bytes)) return MGX_ERR_ARG;
+      }
+      if (x.labels && overlaps(x.labels, (size_t)(n[0] * n[1] * n[2]) * 4, x.out, bytes)) return MGX_ERR_ARG;
+    }
+    Plan *P = get_plan(x.ndim, x.dims, x.coords, &st);
+    if (!P) return (mgx_status)st;
+    if (x.stop_level < 0 || x.stop_level > L) return MGX_ERR_LEVEL;
+    BatchField &b = out[i];
+    b.P = P;
+    b.lay = layout(n, real, L, x.stop_level, es);
+    b.ws_off = off;
+    off = align_up(off + b.lay.total, 256);
+    if (check_ptrs) {
+      int herr = 0;
+      b.tab = P->device_tables(dev, x.dtype == MGX_F64, &herr);
+      if (!b.tab) return MGX_ERR_HIP;
+    }
+  }
+  *ws_total = off;
+  return MGX_OK;
+}
+
+template <typename T>
+mgx_status batch_record(const mgx_field &x, const BatchField &b, char *ws, bool dec,
+                        std::vector<RecordedOp<T>> &ops) {
+  Emitter<T> em;
+  em.rec = &ops;
+  char *w = ws + b.ws_off;
+  if (dec) {
+    mgx_status s = run_decompose<T>(b.P, x.stop_level, (const T *)x.in, (T *)x.out, w, b.lay, (const T *)b.tab, em);
+    if (s) return s;
+    if (x.labels) {
+      QuantArgs qa;
+      Plan *P;
+      s = quant_args(x.ndim, x.dims, x.coords, x.tol_linf, x.stop_level, x.c_linf, &qa, &P);
+      if (s) return s;
+      OpArgs<T> o{};
+      o.qj = QuantJob<T>{(const T *)x.out, x.labels, qa};
+      em.base = 0;
+      em.begin_step(1 << 20);  // after every level of every field
+      if (em.op(kOpQuantize, 0, "quantize", -1, o) != hipSuccess) return MGX_ERR_HIP;
+    }
+    return MGX_OK;
+  }
+  const T *src = (const T *)x.in;
+  if (x.labels) {
+    QuantArgs qa;
+    Plan *P;
+    mgx_status s = quant_args(x.ndim, x.dims, x.coords, x.tol_linf, x.stop_level, x.c_linf, &qa, &P);
+    if (s) return s;
+    OpArgs<T> o{};
+    o.dj = DequantJob<T>{x.labels, (T *)x.coef, qa};
+    em.begin_step(0);
+    if (em.op(kOpDequantize, 0, "dequantize", -1, o) != hipSuccess) return MGX_ERR_HIP;
+    em.base = 1;
+    src = (const T *)x.coef;
+  }
+  return run_recompose<T>(b.P, x.stop_level, src, (T *)x.out, w, b.lay, (const T *)b.tab, em);
+}
+
+// Multi-field launches of one dtype: ops sorted by (step, phase, kind, key);
+// each run of equal values is one launch.  Argument tables are appended to
+// blob (host) at 256-byte aligned offsets.
+struct BatchLaunch {
+  int kind, key, n, total;
+  size_t args_off, start_off;
+  bool f64;
+};
+
+template <typename T>
+mgx_status batch_plan(std::vector<RecordedOp<T>> ops, const Tuning &tn, std::vector<BatchLaunch> &launches,
+                      std::vector<char> &blob) {
+  std::vector<int> blocks(ops.size()), keys(ops.size());
+  for (size_t i = 0; i < ops.size(); i++) {
+    blocks[i] = op_blocks<T>(ops[i].kind, ops[i].mode, ops[i].a, tn);
+    if (blocks[i] < 0) return MGX_ERR_SHAPE;
+    keys[i] = op_key<T>(ops[i].kind, ops[i].mode, ops[i].a);
+  }
+  std::vector<size_t> idx(ops.size());
+  for (size_t i = 0; i < idx.size(); i++) idx[i] = i;
+  std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) {
+    const RecordedOp<T> &x = ops[a], &y = ops[b];
+    if (x.step != y.step) return x.step < y.step;
+    if (x.phase != y.phase) return x.phase < y.phase;
+    if (x.kind != y.kind) return x.kind < y.kind;
+    return keys[a] < keys[b];
+  });
+  size_t i = 0;
+  while (i < idx.size()) {
+    size_t j = i + 1;
+    const RecordedOp<T> &h = ops[idx[i]];
+    while (j < idx.size()) {
+      const RecordedOp<T> &o = ops[idx[j]];
+      if (o.step != h.step || o.phase != h.phase || o.kind != h.kind || keys[idx[j]] != keys[idx[i]]) break;
+      j++;
+    }
+    BatchLaunch L{};
+    L.kind = h.kind;
+    L.key = keys[idx[i]];
+    L.n = (int)(j - i);
+    L.f64 = sizeof(T) == 8;
+    L.args_off = align_up(blob.size(), 256);
+    blob.resize(L.args_off + sizeof(OpArgs<T>) * L.n);
+    std::vector<int> start(L.n + 1, 0);
+    for (size_t k = i; k < j; k++) {
+      std::memcpy(blob.data() + L.args_off + sizeof(OpArgs<T>) * (k - i), &ops[idx[k]].a, sizeof(OpArgs<T>));
+      start[k - i + 1] = start[k - i] + blocks[idx[k]];
+    }
+    L.total = start[L.n];
+    L.start_off = align_up(blob.size(), 256);
+    blob.resize(L.start_off + sizeof(int) * (L.n + 1));
+    std::memcpy(blob.data() + L.start_off, start.data(), sizeof(int) * (L.n + 1));
+    if (L.total > 0) launches.push_back(L);
+    i = j;
+  }
+  return MGX_OK;
+}
+
+struct BatchEntry {
+  hipGraphExec_t exec = nullptr;
+  void *dev = nullptr;
+  int launches = 0;
+  Tuning tn{};
+  double tuned_ms = 0.0;
+};
+
+struct BatchCache {
+  std::mutex mu;
+  std::unordered_map<std::string, BatchEntry> map;
+  std::vector<std::string> order;
+  std::vector<hipStream_t> streams;  // per device: the capture / tuning stream
+};
+BatchCache &batch_cache() {
+  static BatchCache *c = new BatchCache();
+  return *c;
+}
+std::atomic<int> g_batch_autotune{1};
+thread_local mgx_batch_info g_batch_info{};
+
+void batch_entry_free(BatchEntry &e) {
+  if (e.exec) (void)hipGraphExecDestroy(e.exec);
+  if (e.dev) (void)hipFree(e.dev);
+  e.exec = nullptr;
+  e.dev = nullptr;
+}
+
+// Records every field, plans the launches for tn, uploads the argument
+// tables and captures the launches on cs into an executable graph.
+mgx_status batch_build(int nfields, const mgx_field *f, const std::vector<BatchField> &bf, char *ws, bool dec,
+                       const Tuning &tn, hipStream_t cs, BatchEntry &out) {
+  std::vector<RecordedOp<float>> o32;
+  std::vector<RecordedOp<double>> o64;
+  for (int i = 0; i < nfields; i++) {
+    mgx_status s = f[i].dtype == MGX_F32 ? batch_record<float>(f[i], bf[i], ws, dec, o32)
+                                         : batch_record<double>(f[i], bf[i], ws, dec, o64);
+    if (s) return s;
+  }
+  std::vector<BatchLaunch> launches;
+  std::vector<char> blob;
+  mgx_status s = batch_plan<float>(o32, tn, launches, blob);
+  if (s) return s;
+  if ((s = batch_plan<double>(o64, tn, launches, blob))) return s;
+  void *dev = nullptr;
+  if (hipMalloc(&dev, blob.size() > 0 ? blob.size() : 256) != hipSuccess) return MGX_ERR_HIP;
+  if (!blob.empty() && hipMemcpy(dev, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(dev);
+    return MGX_ERR_HIP;
+  }
+  char *d = (char *)dev;
+  hipGraph_t graph = nullptr;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipFree(dev);
+    return MGX_ERR_HIP;
+  }
+  hipError_t le = hipSuccess;
+  for (const BatchLaunch &L : launches) {
+    if (L.f64)
+      le = launch_op_multi<double>(L.kind, L.key, (const OpArgs<double> *)(d + L.args_off),
+                                   (const int *)(d + L.start_off), L.n, L.total, cs);
+    else
+      le = launch_op_multi<float>(L.kind, L.key, (const OpArgs<float> *)(d + L.args_off),
+                                  (const int *)(d + L.start_off), L.n, L.total, cs);
+    if (le != hipSuccess) break;
+  }
+  hipError_t ce = hipStreamEndCapture(cs, &graph);
+  if (le != hipSuccess || ce != hipSuccess || !graph) {
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipFree(dev);
+    return MGX_ERR_HIP;
+  }
+  hipGraphExec_t exec = nullptr;
+  hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) {
+    (void)hipFree(dev);
+    return MGX_ERR_HIP;
+  }
+  out.exec = exec;
+  out.dev = dev;
+  out.launches = (int)launches.size();
+  out.tn = tn;
+  return MGX_OK;
+}
+
+// Mean time of one replay of e on cs (ms), or a negative value on error.
+double batch_time(const BatchEntry &e, hipStream_t cs, int reps) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return -1.0;
+  double ms = -1.0;
+  if (hipGraphLaunch(e.exec, cs) == hipSuccess && hipStreamSynchronize(cs) == hipSuccess &&
+      hipEventRecord(a, cs) == hipSuccess) {
+    bool ok = true;
+    for (int r = 0; r < reps && ok; r++) ok = hipGraphLaunch(e.exec, cs) == hipSuccess;
+    float t = 0.f;
+    if (ok && hipEventRecord(b, cs) == hipSuccess && hipEventSynchronize(b) == hipSuccess &&
+        hipEventElapsedTime(&t, a, b) == hipSuccess)
+      ms = t / reps;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return ms;
+}
+
+std::string batch_key(int nfields, const mgx_field *f, const void *ws, bool dec, const std::vector<BatchField> &bf) {
+  std::string k;
+  k.push_back(dec ? 'D' : 'R');
+  k.append((const char *)&ws, sizeof(ws));
+  for (int i = 0; i < nfields; i++) {
+    k.append((const char *)&f[i], sizeof(mgx_field));
+    k.append((const char *)&bf[i].P, sizeof(Plan *));  // coordinates by content
+  }
+  return k;
+}
+
+mgx_status run_batched(int nfields, const mgx_field *f, void *ws, size_t ws_bytes, hipStream_t stream, bool dec) {
+  std::vector<BatchField> bf;
+  size_t need = 0;
+  mgx_status s = batch_validate(nfields, f, dec, bf, &need);
+  if (s) return s;
+  if (need > 0 && (!ws || ws_bytes < need)) return MGX_ERR_WORKSPACE;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MGX_ERR_HIP;
+  BatchCache &C = batch_cache();
+  std::lock_guard<std::mutex> g(C.mu);
+  if ((int)C.streams.size() <= dev) C.streams.resize(dev + 1, nullptr);
+  if (!C.streams[dev] && hipStreamCreateWithFlags(&C.streams[dev], hipStreamNonBlocking) != hipSuccess)
+    return MGX_ERR_HIP;
+  hipStream_t cs = C.streams[dev];
+  const std::string key = batch_key(nfields, f, ws, dec, bf);
+  auto it = C.map.find(key);
+  if (it == C.map.end()) {
+    BatchEntry best;
+    if (g_batch_autotune.load()) {
+      // candidate launch shapes of the stencil kernels; inputs must be ready
+      if (hipStreamSynchronize(stream) != hipSuccess) return MGX_ERR_HIP;
+      const Tuning cand[] = {{2048, 8}, {512, 4}, {128, 2}, {8192, 8}};
+      double best_ms = -1.0;
+      for (const Tuning &tn : cand) {
+        BatchEntry e;
+        s = batch_build(nfields, f, bf, (char *)ws, dec, tn, cs, e);
+        if (s) {
+          batch_entry_free(best);
+          return s;
+        }
+        const double ms = batch_time(e, cs, 3);
+        if (ms < 0.0) {
+          batch_entry_free(e);
+          batch_entry_free(best);
+          return MGX_ERR_HIP;
+        }
+        if (best_ms < 0.0 || ms < best_ms) {
+          batch_entry_free(best);
+          best = e;
+          best_ms = ms;
+          best.tuned_ms = ms;
+        } else {
+          batch_entry_free(e);
+        }
+      }
+    } else {
+      s = batch_build(nfields, f, bf, (char *)ws, dec, Tuning{}, cs, best);
+      if (s) return s;
+    }
+    if (C.order.size() >= 32) {  // bounded cache: drop the oldest batch
+      auto old = C.map.find(C.order.front());
+      if (old != C.map.end()) {
+        (void)hipStreamSynchronize(cs);
+        batch_entry_free(old->second);
+        C.map.erase(old);
+      }
+      C.order.erase(C.order.begin());
+    }
+    it = C.map.emplace(key, best).first;
+    C.order.push_back(key);
+  }
+  const BatchEntry &e = it->second;
+  g_batch_info.launches = e.launches;
+  g_batch_info.target_blocks = e.tn.target_blocks;
+  g_batch_info.min_zchunk = e.tn.min_zchunk;
+  g_batch_info.tuned_ms = e.tuned_ms;
+  hipError_t le = traced(dec ? "decompose_batched" : "recompose_batched", -2, stream,
+                         [&] { return hipGraphLaunch(e.exec, stream); });
+  return hip_status(le);
+}
+
 }  // namespace
 }  // namespace mgx
 
@@ -545,11 +935,16 @@ mgx_status mgx_decompose(const void *u, void *u_mc, mgx_dtype dtype, int ndim, c
   const void *tab;
   mgx_status s = prepare(u, u_mc, dtype, ndim, dims, coords, stop_level, workspace, workspace_bytes, &P, &lay, &tab);
   if (s) return s;
-  if (dtype == MGX_F32)
+  if (dtype == MGX_F32) {
+    Emitter<float> em;
+    em.st = stream;
     return run_decompose<float>(P, stop_level, (const float *)u, (float *)u_mc, (char *)workspace, lay,
-                                (const float *)tab, stream);
+                                (const float *)tab, em);
+  }
+  Emitter<double> em;
+  em.st = stream;
   return run_decompose<double>(P, stop_level, (const double *)u, (double *)u_mc, (char *)workspace, lay,
-                               (const double *)tab, stream);
+                               (const double *)tab, em);
 }
 
 mgx_status mgx_recompose(const void *u_mc, void *u, mgx_dtype dtype, int ndim, const int64_t *dims,
@@ -560,11 +955,16 @@ mgx_status mgx_recompose(const void *u_mc, void *u, mgx_dtype dtype, int ndim, c
   const void *tab;
   mgx_status s = prepare(u_mc, u, dtype, ndim, dims, coords, stop_level, workspace, workspace_bytes, &P, &lay, &tab);
   if (s) return s;
-  if (dtype == MGX_F32)
+  if (dtype == MGX_F32) {
+    Emitter<float> em;
+    em.st = stream;
     return run_recompose<float>(P, stop_level, (const float *)u_mc, (float *)u, (char *)workspace, lay,
-                                (const float *)tab, stream);
+                                (const float *)tab, em);
+  }
+  Emitter<double> em;
+  em.st = stream;
   return run_recompose<double>(P, stop_level, (const double *)u_mc, (double *)u, (char *)workspace, lay,
-                               (const double *)tab, stream);
+                               (const double *)tab, em);
 }
 
 size_t mgx_adjoint_workspace_size(mgx_dtype dtype, int ndim, const int64_t *dims, int stop_level) {
@@ -745,6 +1145,34 @@ int mgx_trace_read(mgx_kernel_time *out, int max) {
   int n = (int)agg.size() < max ? (int)agg.size() : max;
   for (int i = 0; i < n; i++) out[i] = agg[i];
   return n;
+}
+
+size_t mgx_batch_workspace_size(int nfields, const mgx_field *fields) {
+  std::vector<BatchField> bf;
+  size_t need = 0;
+  if (batch_validate(nfields, fields, true, bf, &need, false) != MGX_OK) return 0;
+  return need;
+}
+
+mgx_status mgx_decompose_batched(int nfields, const mgx_field *fields, void *workspace, size_t workspace_bytes,
+                                 hipStream_t stream) {
+  return run_batched(nfields, fields, workspace, workspace_bytes, stream, true);
+}
+
+mgx_status mgx_recompose_batched(int nfields, const mgx_field *fields, void *workspace, size_t workspace_bytes,
+                                 hipStream_t stream) {
+  return run_batched(nfields, fields, workspace, workspace_bytes, stream, false);
+}
+
+mgx_status mgx_batch_set_autotune(int on) {
+  g_batch_autotune.store(on ? 1 : 0);
+  return MGX_OK;
+}
+
+mgx_status mgx_batch_last_info(mgx_batch_info *info) {
+  if (!info) return MGX_ERR_ARG;
+  *info = g_batch_info;
+  return MGX_OK;
 }
 
 }  // extern "C"

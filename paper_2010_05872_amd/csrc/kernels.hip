@@ -46,14 +46,6 @@
 #ifndef MGX_F64_NT
 #define MGX_F64_NT 256
 #endif
-// workgroups a stencil launch aims for, and the fewest coarse planes a
-// z-chunk of a large level holds
-#ifndef MGX_TARGET_BLOCKS
-#define MGX_TARGET_BLOCKS 2048
-#endif
-#ifndef MGX_MIN_ZCHUNK
-#define MGX_MIN_ZCHUNK 8
-#endif
 
 namespace mgx {
 
@@ -137,8 +129,7 @@ __device__ __forceinline__ int opaque(int v) {
 // the interpolation corners read consecutive LDS words.  Planes are fetched
 // two iterations ahead into double-buffered registers.
 template <typename T, int TX, int TY, int NT, bool DEC>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MGX_STENCIL_WAVES, 8)))
-k_load_vector(StencilArgs<T> a) {
+__device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const int lb) {
   constexpr int HR = 2 * TY + 5;  // region rows incl. halo and the extension
   constexpr int W = 2 * TX + 5;   // region row pitch
   constexpr int E = TX + 3;       // even columns of a region row
@@ -159,7 +150,6 @@ k_load_vector(StencilArgs<T> a) {
   const int tid = threadIdx.x;
   const int m0 = a.ax[0].m, m1 = a.ax[1].m, m2 = a.ax[2].m;
   const int c0 = a.ax[0].c, c1 = a.ax[1].c, c2 = a.ax[2].c;
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int tx = lb % a.ntx;
   const int t2 = lb / a.ntx;
   const int ty = t2 % a.nty;
@@ -409,6 +399,12 @@ k_load_vector(StencilArgs<T> a) {
     if (j + d <= jend) plane(j + d, st[d]);
 }
 
+template <typename T, int TX, int TY, int NT, bool DEC>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MGX_STENCIL_WAVES, 8)))
+k_load_vector(StencilArgs<T> a) {
+  load_vector_body<T, TX, TY, NT, DEC>(a, xcd_remap(blockIdx.x, gridDim.x));
+}
+
 // ---------------------------------------------------------------------------
 // k_solve_contig: Thomas solve along the contiguous axis, one line per group
 // of G lanes, E nodes per lane, line length c = G*E + 1.
@@ -418,10 +414,10 @@ k_load_vector(StencilArgs<T> a) {
 // maps with shuffles, and each lane then replays its E steps.
 // ---------------------------------------------------------------------------
 template <typename T, int E, int G>
-__global__ void __launch_bounds__(256) k_solve_contig(SolveArgs<T> a) {
+__device__ __forceinline__ void solve_contig_body(const SolveArgs<T> a, const int bx) {
   const int lane = threadIdx.x & 63;
   const int li = lane % G;
-  const int64_t line = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * (64 / G) + lane / G;
+  const int64_t line = ((int64_t)bx * 4 + (threadIdx.x >> 6)) * (64 / G) + lane / G;
   const bool active = line < a.nlines;
   const int c = G * E + 1;
   T *row = a.F + (active ? line : 0) * a.pitch;
@@ -503,6 +499,11 @@ __global__ void __launch_bounds__(256) k_solve_contig(SolveArgs<T> a) {
   }
 }
 
+template <typename T, int E, int G>
+__global__ void __launch_bounds__(256) k_solve_contig(SolveArgs<T> a) {
+  solve_contig_body<T, E, G>(a, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // k_solve_strided: Thomas solve along a strided axis of the coarse box.
 // One thread per line, consecutive lanes on consecutive contiguous indices
@@ -514,10 +515,9 @@ __global__ void __launch_bounds__(256) k_solve_contig(SolveArgs<T> a) {
 // subtracted (sign -1, recomposition) to the nodal values: out = in + sign*y.
 // ---------------------------------------------------------------------------
 template <typename T, int MODE, int CH>
-__global__ void __launch_bounds__(256) k_solve_strided(StridedArgs<T> a) {
+__device__ __forceinline__ void solve_strided_body(const StridedArgs<T> a, const int bx, const int o) {
   constexpr bool APPLY = MODE == kSolveApply;
-  const int x = blockIdx.x * 256 + threadIdx.x;
-  const int o = blockIdx.y;
+  const int x = bx * 256 + threadIdx.x;
   if (x >= a.nx) return;
   T *p = a.F + (int64_t)o * a.so + x;
   const int c = a.c;
@@ -597,6 +597,11 @@ __global__ void __launch_bounds__(256) k_solve_strided(StridedArgs<T> a) {
   }
 }
 
+template <typename T, int MODE, int CH>
+__global__ void __launch_bounds__(256) k_solve_strided(StridedArgs<T> a) {
+  solve_strided_body<T, MODE, CH>(a, blockIdx.x, blockIdx.y);
+}
+
 // ---------------------------------------------------------------------------
 // k_solve_twisted: Thomas solve along a strided axis of the coarse box as a
 // two-ended ("twisted") factorization of the same tridiagonal matrix.  A
@@ -610,14 +615,13 @@ __global__ void __launch_bounds__(256) k_solve_strided(StridedArgs<T> a) {
 // tables are scalar operands.
 // ---------------------------------------------------------------------------
 template <typename T, int C, int MODE>
-__global__ void __launch_bounds__(256) k_solve_twisted(StridedArgs<T> a) {
+__device__ __forceinline__ void solve_twisted_body(const StridedArgs<T> a, const int bx, const int o) {
   constexpr int K = C / 2;
   __shared__ T sE[2][128];
   const int wave = threadIdx.x >> 6;
   const int half = wave >> 1;  // 0: top rows, 1: bottom rows (uniform per wave)
   const int line = (wave & 1) * 64 + (threadIdx.x & 63);
-  const int x = blockIdx.x * 128 + line;
-  const int o = blockIdx.y;
+  const int x = bx * 128 + line;
   const bool active = x < a.nx;
   T *p = a.F + (int64_t)o * a.so + (active ? x : 0);
   const int64_t s = a.sj;
@@ -697,13 +701,23 @@ __global__ void __launch_bounds__(256) k_solve_twisted(StridedArgs<T> a) {
   }
 }
 
+template <typename T, int C, int MODE>
+__global__ void __launch_bounds__(256) k_solve_twisted(StridedArgs<T> a) {
+  solve_twisted_body<T, C, MODE>(a, blockIdx.x, blockIdx.y);
+}
+
 // Last step for one-dimensional fields (no strided solve): out = in + sign * F
 // (recomposition) or out = F (decomposition) over a row of the coarse box.
 template <typename T>
-__global__ void __launch_bounds__(256) k_apply(StridedArgs<T> a) {
-  const int x = blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void apply_body(const StridedArgs<T> a, const int bx) {
+  const int x = bx * 256 + threadIdx.x;
   if (x >= a.nx) return;
   a.out[x] = a.in ? a.in[x] + a.sign * a.F[x] : a.F[x];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_apply(StridedArgs<T> a) {
+  apply_body<T>(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -717,7 +731,7 @@ __global__ void __launch_bounds__(256) k_apply(StridedArgs<T> a) {
 // coarse plane are fetched into registers while the current one is done.
 // ---------------------------------------------------------------------------
 template <typename T, int TX, int TY, int NT>
-__global__ void __launch_bounds__(NT) k_interp_add(InterpArgs<T> a) {
+__device__ __forceinline__ void interp_add_body(const InterpArgs<T> a, const int lb) {
   constexpr int NW = TX + 2;  // nodal tile pitch
   constexpr int NH = TY + 2;
   constexpr int BW = TX + 1;  // 2x2 blocks per tile row (max)
@@ -730,7 +744,6 @@ __global__ void __launch_bounds__(NT) k_interp_add(InterpArgs<T> a) {
   const int tid = threadIdx.x;
   const int m0 = a.ax[0].m, m1 = a.ax[1].m, m2 = a.ax[2].m;
   const int c0 = a.ax[0].c, c1 = a.ax[1].c, c2 = a.ax[2].c;
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int tx = lb % a.ntx;
   const int t2 = lb / a.ntx;
   const int ty = t2 % a.nty;
@@ -883,6 +896,11 @@ __global__ void __launch_bounds__(NT) k_interp_add(InterpArgs<T> a) {
     step(J + 1, cv1, nv1);
   }
   if (J < Z1) step(J, cv0, nv0);
+}
+
+template <typename T, int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT) k_interp_add(InterpArgs<T> a) {
+  interp_add_body<T, TX, TY, NT>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -1079,14 +1097,19 @@ __global__ void __launch_bounds__(NT) k_prolong_mass(ProlongArgs<T> a) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_copy_box(CopyArgs<T> a) {
+__device__ __forceinline__ void copy_box_body(const CopyArgs<T> a, const int b, const int nb) {
   const int64_t n = (int64_t)a.n0 * a.n1 * a.n2;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i = b * (int64_t)256 + threadIdx.x; i < n; i += (int64_t)nb * 256) {
     const int64_t r = i / a.n2;
     const int i2 = (int)(i - r * a.n2);
     const int i0 = (int)(r / a.n1), i1 = (int)(r - (int64_t)i0 * a.n1);
     a.dst[i0 * a.dp0 + i1 * a.dp1 + i2] = a.src[i0 * a.sp0 + i1 * a.sp1 + i2];
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_copy_box(CopyArgs<T> a) {
+  copy_box_body<T>(a, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1170,8 +1193,8 @@ __device__ __forceinline__ void store4i(int32_t *p, uint32_t base, uint32_t N, c
 }
 
 template <typename T, bool STATS, bool VEC>
-__global__ void __launch_bounds__(256) k_quantize(const T *__restrict__ umc, int32_t *__restrict__ labels,
-                                                  QuantArgs a) {
+__device__ __forceinline__ void quantize_body(const T *__restrict__ umc, int32_t *__restrict__ labels,
+                                              const QuantArgs &a, const int b, const int nb) {
   __shared__ int s_max[kMaxLevelsK];
   __shared__ double s_q[kMaxLevelsK];
   __shared__ unsigned long long s_ovf, s_nan;
@@ -1187,8 +1210,8 @@ __global__ void __launch_bounds__(256) k_quantize(const T *__restrict__ umc, int
   const int lane = threadIdx.x & 63;
   unsigned long long my_ovf = 0, my_nan = 0;
   const uint32_t N = (uint32_t)a.n;
-  const uint32_t stride = gridDim.x * 256u * 4u;
-  for (uint32_t base = (blockIdx.x * 256u + threadIdx.x) * 4u; base < N; base += stride) {
+  const uint32_t stride = (uint32_t)nb * 256u * 4u;
+  for (uint32_t base = ((uint32_t)b * 256u + threadIdx.x) * 4u; base < N; base += stride) {
     T v[4];
     load4<T, VEC>(umc, base, N, v);
     int32_t lab[4];
@@ -1248,15 +1271,21 @@ __global__ void __launch_bounds__(256) k_quantize(const T *__restrict__ umc, int
   }
 }
 
+template <typename T, bool STATS, bool VEC>
+__global__ void __launch_bounds__(256) k_quantize(const T *__restrict__ umc, int32_t *__restrict__ labels,
+                                                  QuantArgs a) {
+  quantize_body<T, STATS, VEC>(umc, labels, a, blockIdx.x, gridDim.x);
+}
+
 template <typename T, bool VEC>
-__global__ void __launch_bounds__(256) k_dequantize(const int32_t *__restrict__ labels, T *__restrict__ umc,
-                                                    QuantArgs a) {
+__device__ __forceinline__ void dequantize_body(const int32_t *__restrict__ labels, T *__restrict__ umc,
+                                                const QuantArgs &a, const int b, const int nb) {
   __shared__ double s_q[kMaxLevelsK];
   if (threadIdx.x < kMaxLevelsK) s_q[threadIdx.x] = a.q[threadIdx.x];
   __syncthreads();
   const uint32_t N = (uint32_t)a.n;
-  const uint32_t stride = gridDim.x * 256u * 4u;
-  for (uint32_t base = (blockIdx.x * 256u + threadIdx.x) * 4u; base < N; base += stride) {
+  const uint32_t stride = (uint32_t)nb * 256u * 4u;
+  for (uint32_t base = ((uint32_t)b * 256u + threadIdx.x) * 4u; base < N; base += stride) {
     int32_t lab[4];
     load4i(labels, base, N, lab, VEC);
     T v[4];
@@ -1267,6 +1296,12 @@ __global__ void __launch_bounds__(256) k_dequantize(const int32_t *__restrict__ 
     }
     store4<T, VEC>(umc, base, N, v);
   }
+}
+
+template <typename T, bool VEC>
+__global__ void __launch_bounds__(256) k_dequantize(const int32_t *__restrict__ labels, T *__restrict__ umc,
+                                                    QuantArgs a) {
+  dequantize_body<T, VEC>(labels, umc, a, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1288,19 +1323,21 @@ struct Tiles<double> {
 // c = 2^k + 1) and z-chunks of tz coarse planes.  Returns false when an axis
 // length does not satisfy the tiling assumption (c - 1 a multiple of the
 // tile, or smaller than it), so that no kernel is launched on a bad shape.
-static bool tile_grid(int c0, int c1, int c2, int TX, int TY, int *ntx, int *nty, int *nzc, int *tz) {
+static bool tile_grid(int c0, int c1, int c2, int TX, int TY, int *ntx, int *nty, int *nzc, int *tz,
+                      const Tuning &tn = Tuning{}) {
   if (c0 < 1 || c1 < 1 || c2 < 1) return false;
   if ((c2 - 1) >= TX && (c2 - 1) % TX != 0) return false;
   if ((c1 - 1) >= TY && (c1 - 1) % TY != 0) return false;
   *ntx = (c2 - 1) / TX > 0 ? (c2 - 1) / TX : 1;
   *nty = (c1 - 1) / TY > 0 ? (c1 - 1) / TY : 1;
   const int per = *ntx * *nty;
-  int want = (MGX_TARGET_BLOCKS + per - 1) / per;
-  // large levels keep z-chunks of >= MGX_MIN_ZCHUNK coarse planes (halo
-  // re-reads stay small); small levels take one coarse plane per workgroup
-  // (latency bound)
+  int want = (tn.target_blocks + per - 1) / per;
+  // large levels keep z-chunks of >= min_zchunk coarse planes (halo re-reads
+  // stay small); small levels take one coarse plane per workgroup (latency
+  // bound)
   const bool large = (int64_t)c0 * c1 * c2 >= (1 << 20);
-  int maxz = large ? (c0 / MGX_MIN_ZCHUNK > 0 ? c0 / MGX_MIN_ZCHUNK : 1) : c0;
+  const int mz = tn.min_zchunk > 0 ? tn.min_zchunk : 1;
+  int maxz = large ? (c0 / mz > 0 ? c0 / mz : 1) : c0;
   if (want > maxz) want = maxz;
   if (want < 1) want = 1;
   *nzc = want;
@@ -1309,9 +1346,9 @@ static bool tile_grid(int c0, int c1, int c2, int TX, int TY, int *ntx, int *nty
 }
 
 template <typename T>
-hipError_t launch_load_vector(StencilArgs<T> a, bool dec, hipStream_t st) {
+hipError_t launch_load_vector(StencilArgs<T> a, bool dec, hipStream_t st, Tuning tn) {
   constexpr int TX = Tiles<T>::TX, TY = Tiles<T>::TY, NT = Tiles<T>::NT;
-  if (!tile_grid(a.ax[0].c, a.ax[1].c, a.ax[2].c, TX, TY, &a.ntx, &a.nty, &a.nzc, &a.tz))
+  if (!tile_grid(a.ax[0].c, a.ax[1].c, a.ax[2].c, TX, TY, &a.ntx, &a.nty, &a.nzc, &a.tz, tn))
     return hipErrorInvalidValue;
   dim3 grid(a.ntx * a.nty * a.nzc);
   if (dec)
@@ -1322,9 +1359,9 @@ hipError_t launch_load_vector(StencilArgs<T> a, bool dec, hipStream_t st) {
 }
 
 template <typename T>
-hipError_t launch_interp_add(InterpArgs<T> a, hipStream_t st) {
+hipError_t launch_interp_add(InterpArgs<T> a, hipStream_t st, Tuning tn) {
   constexpr int TX = Tiles<T>::TX, TY = Tiles<T>::TY, NT = Tiles<T>::NT;
-  if (!tile_grid(a.ax[0].c, a.ax[1].c, a.ax[2].c, TX, TY, &a.ntx, &a.nty, &a.nzc, &a.tz))
+  if (!tile_grid(a.ax[0].c, a.ax[1].c, a.ax[2].c, TX, TY, &a.ntx, &a.nty, &a.nzc, &a.tz, tn))
     return hipErrorInvalidValue;
   dim3 grid(a.ntx * a.nty * a.nzc);
   hipLaunchKernelGGL((k_interp_add<T, TX, TY, NT>), grid, dim3(NT), 0, st, a);
@@ -1477,9 +1514,293 @@ hipError_t launch_dequantize(const int32_t *labels, T *umc, QuantArgs a, hipStre
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Multi-field launches.  One grid covers several ops of one kernel instance
+// (for example the load-vector step of every field of a batch at the same
+// level depth): workgroup g belongs to op f with start[f] <= g < start[f+1]
+// and runs the op's body with local index g - start[f].  The op arguments
+// are read from device memory; they are uniform per workgroup.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct MultiArgs {
+  const OpArgs<T> *__restrict__ args;
+  const int *__restrict__ start;
+  int n;
+};
+
+__device__ __forceinline__ int find_op(const int *__restrict__ start, int n, int g) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename T, int TX, int TY, int NT, bool DEC>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MGX_STENCIL_WAVES, 8)))
+k_load_vector_multi(MultiArgs<T> m) {
+  const int g = xcd_remap(blockIdx.x, gridDim.x);
+  const int f = find_op(m.start, m.n, g);
+  load_vector_body<T, TX, TY, NT, DEC>(m.args[f].st, g - m.start[f]);
+}
+
+template <typename T, int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT) k_interp_add_multi(MultiArgs<T> m) {
+  const int g = xcd_remap(blockIdx.x, gridDim.x);
+  const int f = find_op(m.start, m.n, g);
+  interp_add_body<T, TX, TY, NT>(m.args[f].ia, g - m.start[f]);
+}
+
+template <typename T, int E, int G>
+__global__ void __launch_bounds__(256) k_solve_contig_multi(MultiArgs<T> m) {
+  const int g = blockIdx.x;
+  const int f = find_op(m.start, m.n, g);
+  solve_contig_body<T, E, G>(m.args[f].so, g - m.start[f]);
+}
+
+template <typename T, int C, int MODE>
+__global__ void __launch_bounds__(256) k_solve_twisted_multi(MultiArgs<T> m) {
+  const int g = blockIdx.x;
+  const int f = find_op(m.start, m.n, g);
+  const StridedArgs<T> a = m.args[f].sd;
+  const int b = g - m.start[f], nbx = (a.nx + 127) / 128;
+  solve_twisted_body<T, C, MODE>(a, b % nbx, b / nbx);
+}
+
+template <typename T, int MODE, int CH>
+__global__ void __launch_bounds__(256) k_solve_strided_multi(MultiArgs<T> m) {
+  const int g = blockIdx.x;
+  const int f = find_op(m.start, m.n, g);
+  const StridedArgs<T> a = m.args[f].sd;
+  const int b = g - m.start[f], nbx = (a.nx + 255) / 256;
+  solve_strided_body<T, MODE, CH>(a, b % nbx, b / nbx);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_apply_multi(MultiArgs<T> m) {
+  const int g = blockIdx.x;
+  const int f = find_op(m.start, m.n, g);
+  apply_body<T>(m.args[f].sd, g - m.start[f]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_copy_box_multi(MultiArgs<T> m) {
+  const int g = blockIdx.x;
+  const int f = find_op(m.start, m.n, g);
+  copy_box_body<T>(m.args[f].cp, g - m.start[f], m.start[f + 1] - m.start[f]);
+}
+
+template <typename T, bool VEC>
+__global__ void __launch_bounds__(256) k_quantize_multi(MultiArgs<T> m) {
+  const int g = blockIdx.x;
+  const int f = find_op(m.start, m.n, g);
+  const QuantJob<T> &j = m.args[f].qj;
+  quantize_body<T, false, VEC>(j.umc, j.labels, j.a, g - m.start[f], m.start[f + 1] - m.start[f]);
+}
+
+template <typename T, bool VEC>
+__global__ void __launch_bounds__(256) k_dequantize_multi(MultiArgs<T> m) {
+  const int g = blockIdx.x;
+  const int f = find_op(m.start, m.n, g);
+  const DequantJob<T> &j = m.args[f].dj;
+  dequantize_body<T, VEC>(j.labels, j.umc, j.a, g - m.start[f], m.start[f + 1] - m.start[f]);
+}
+
+// ---- op dispatch (host) ----
+// line length c of the contiguous solve -> (E, G) instance index
+static int contig_index(int c) {
+  switch (c) {
+    case 3: return 0;
+    case 5: return 1;
+    case 9: return 2;
+    case 17: return 3;
+    case 33: return 4;
+    case 65: return 5;
+    case 129: return 6;
+    case 257: return 7;
+    case 513: return 8;
+    case 1025: return 9;
+    case 2049: return 10;
+    case 4097: return 11;
+    default: return -1;
+  }
+}
+static int contig_group(int c) {  // G: lanes per line
+  return c <= 65 ? (c - 1) : 64;
+}
+
+template <typename T>
+static bool strided_twisted(int c) {
+  return c <= 129 || (sizeof(T) == 4 && c == 257);
+}
+template <typename T>
+static bool strided_deep(const StridedArgs<T> &a) {
+  return (int64_t)a.nx * a.nouter < (1 << 18);
+}
+
+static int grid_cap(int64_t blocks) {
+  if (blocks > 8192) blocks = 8192;
+  return (int)(blocks > 0 ? blocks : 1);
+}
+
+template <typename T>
+int op_blocks(int kind, int mode, OpArgs<T> &a, const Tuning &tn) {
+  constexpr int TX = Tiles<T>::TX, TY = Tiles<T>::TY;
+  (void)mode;
+  switch (kind) {
+    case kOpLoadVecDec:
+    case kOpLoadVecRec: {
+      StencilArgs<T> &s = a.st;
+      if (!tile_grid(s.ax[0].c, s.ax[1].c, s.ax[2].c, TX, TY, &s.ntx, &s.nty, &s.nzc, &s.tz, tn)) return -1;
+      return s.ntx * s.nty * s.nzc;
+    }
+    case kOpInterpAdd: {
+      InterpArgs<T> &s = a.ia;
+      if (!tile_grid(s.ax[0].c, s.ax[1].c, s.ax[2].c, TX, TY, &s.ntx, &s.nty, &s.nzc, &s.tz, tn)) return -1;
+      return s.ntx * s.nty * s.nzc;
+    }
+    case kOpSolveContig: {
+      if (contig_index(a.so.c) < 0) return -1;
+      const int64_t lpb = 4 * (64 / contig_group(a.so.c));
+      return (int)((a.so.nlines + lpb - 1) / lpb);
+    }
+    case kOpSolveStrided: {
+      const int per = strided_twisted<T>(a.sd.c) ? 128 : 256;
+      return (int)(((int64_t)a.sd.nx + per - 1) / per * a.sd.nouter);
+    }
+    case kOpApply: return (a.sd.nx + 255) / 256;
+    case kOpQuantize: return grid_cap((a.qj.a.n + 1023) / 1024);
+    case kOpDequantize: return grid_cap((a.dj.a.n + 1023) / 1024);
+    case kOpCopyBox: return grid_cap(((int64_t)a.cp.n0 * a.cp.n1 * a.cp.n2 + 255) / 256);
+  }
+  return -1;
+}
+
+template <typename T>
+int op_key(int kind, int mode, const OpArgs<T> &a) {
+  switch (kind) {
+    case kOpSolveContig: return a.so.c;
+    case kOpSolveStrided: return (a.sd.c << 4) | (mode << 1) | (strided_deep(a.sd) ? 1 : 0);
+    case kOpQuantize: return aligned16(a.qj.umc) && aligned16(a.qj.labels);
+    case kOpDequantize: return aligned16(a.dj.umc) && aligned16(a.dj.labels);
+    default: return 0;
+  }
+}
+
+template <typename T>
+hipError_t launch_op(int kind, int mode, OpArgs<T> a, const Tuning &tn, hipStream_t st) {
+  switch (kind) {
+    case kOpLoadVecDec: return launch_load_vector<T>(a.st, true, st, tn);
+    case kOpLoadVecRec: return launch_load_vector<T>(a.st, false, st, tn);
+    case kOpInterpAdd: return launch_interp_add<T>(a.ia, st, tn);
+    case kOpSolveContig: return launch_solve_contig<T>(a.so, st);
+    case kOpSolveStrided: return launch_solve_strided<T>(a.sd, mode, st);
+    case kOpApply: return launch_apply<T>(a.sd, st);
+    case kOpQuantize: return launch_quantize<T>(a.qj.umc, a.qj.labels, a.qj.a, false, st);
+    case kOpDequantize: return launch_dequantize<T>(a.dj.labels, a.dj.umc, a.dj.a, st);
+    case kOpCopyBox: return launch_copy_box<T>(a.cp, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+#define MGX_MULTI(KERNEL, NT_)                                                    \
+  do {                                                                            \
+    hipLaunchKernelGGL((KERNEL), dim3((unsigned)total), dim3(NT_), 0, st, m);     \
+  } while (0)
+
+template <typename T, int C>
+static void twisted_multi(int mode, MultiArgs<T> m, int total, hipStream_t st) {
+  if (mode == kSolveApply) MGX_MULTI((k_solve_twisted_multi<T, C, kSolveApply>), 256);
+  else if (mode == kSolveStore) MGX_MULTI((k_solve_twisted_multi<T, C, kSolveStore>), 256);
+  else MGX_MULTI((k_solve_twisted_multi<T, C, kSolveInPlace>), 256);
+}
+
+template <typename T, int CH>
+static void chunked_multi(int mode, MultiArgs<T> m, int total, hipStream_t st) {
+  if (mode == kSolveApply) MGX_MULTI((k_solve_strided_multi<T, kSolveApply, CH>), 256);
+  else if (mode == kSolveStore) MGX_MULTI((k_solve_strided_multi<T, kSolveStore, CH>), 256);
+  else MGX_MULTI((k_solve_strided_multi<T, kSolveInPlace, CH>), 256);
+}
+
+template <typename T>
+hipError_t launch_op_multi(int kind, int key, const OpArgs<T> *dargs, const int *dstart, int n, int total,
+                           hipStream_t st) {
+  constexpr int TX = Tiles<T>::TX, TY = Tiles<T>::TY, NT = Tiles<T>::NT;
+  if (n <= 0 || total <= 0) return hipSuccess;
+  MultiArgs<T> m{dargs, dstart, n};
+  switch (kind) {
+    case kOpLoadVecDec: MGX_MULTI((k_load_vector_multi<T, TX, TY, NT, true>), NT); break;
+    case kOpLoadVecRec: MGX_MULTI((k_load_vector_multi<T, TX, TY, NT, false>), NT); break;
+    case kOpInterpAdd: MGX_MULTI((k_interp_add_multi<T, TX, TY, NT>), NT); break;
+    case kOpApply: MGX_MULTI((k_apply_multi<T>), 256); break;
+    case kOpCopyBox: MGX_MULTI((k_copy_box_multi<T>), 256); break;
+    case kOpQuantize:
+      if (key) MGX_MULTI((k_quantize_multi<T, true>), 256);
+      else MGX_MULTI((k_quantize_multi<T, false>), 256);
+      break;
+    case kOpDequantize:
+      if (key) MGX_MULTI((k_dequantize_multi<T, true>), 256);
+      else MGX_MULTI((k_dequantize_multi<T, false>), 256);
+      break;
+    case kOpSolveContig:
+      switch (key) {
+        case 3: MGX_MULTI((k_solve_contig_multi<T, 1, 2>), 256); break;
+        case 5: MGX_MULTI((k_solve_contig_multi<T, 1, 4>), 256); break;
+        case 9: MGX_MULTI((k_solve_contig_multi<T, 1, 8>), 256); break;
+        case 17: MGX_MULTI((k_solve_contig_multi<T, 1, 16>), 256); break;
+        case 33: MGX_MULTI((k_solve_contig_multi<T, 1, 32>), 256); break;
+        case 65: MGX_MULTI((k_solve_contig_multi<T, 1, 64>), 256); break;
+        case 129: MGX_MULTI((k_solve_contig_multi<T, 2, 64>), 256); break;
+        case 257: MGX_MULTI((k_solve_contig_multi<T, 4, 64>), 256); break;
+        case 513: MGX_MULTI((k_solve_contig_multi<T, 8, 64>), 256); break;
+        case 1025: MGX_MULTI((k_solve_contig_multi<T, 16, 64>), 256); break;
+        case 2049: MGX_MULTI((k_solve_contig_multi<T, 32, 64>), 256); break;
+        case 4097: MGX_MULTI((k_solve_contig_multi<T, 64, 64>), 256); break;
+        default: return hipErrorInvalidValue;
+      }
+      break;
+    case kOpSolveStrided: {
+      const int c = key >> 4, mode = (key >> 1) & 7;
+      const bool deep = key & 1;
+      switch (c) {
+        case 3: twisted_multi<T, 3>(mode, m, total, st); break;
+        case 5: twisted_multi<T, 5>(mode, m, total, st); break;
+        case 9: twisted_multi<T, 9>(mode, m, total, st); break;
+        case 17: twisted_multi<T, 17>(mode, m, total, st); break;
+        case 33: twisted_multi<T, 33>(mode, m, total, st); break;
+        case 65: twisted_multi<T, 65>(mode, m, total, st); break;
+        case 129: twisted_multi<T, 129>(mode, m, total, st); break;
+        default:
+          if constexpr (sizeof(T) == 4) {
+            if (c == 257) {
+              twisted_multi<T, 257>(mode, m, total, st);
+              break;
+            }
+          }
+          {
+            constexpr int CS = sizeof(T) == 8 ? 8 : 16;
+            constexpr int CD = sizeof(T) == 8 ? MGX_DEEP_CH / 2 : MGX_DEEP_CH;
+            if (deep) chunked_multi<T, CD>(mode, m, total, st);
+            else chunked_multi<T, CS>(mode, m, total, st);
+          }
+      }
+      break;
+    }
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+#undef MGX_MULTI
+
 #define MGX_INSTANTIATE(T)                                                                    \
-  template hipError_t launch_load_vector<T>(StencilArgs<T>, bool, hipStream_t);               \
-  template hipError_t launch_interp_add<T>(InterpArgs<T>, hipStream_t);                       \
+  template hipError_t launch_load_vector<T>(StencilArgs<T>, bool, hipStream_t, Tuning);       \
+  template hipError_t launch_interp_add<T>(InterpArgs<T>, hipStream_t, Tuning);               \
+  template int op_blocks<T>(int, int, OpArgs<T> &, const Tuning &);                           \
+  template int op_key<T>(int, int, const OpArgs<T> &);                                        \
+  template hipError_t launch_op<T>(int, int, OpArgs<T>, const Tuning &, hipStream_t);         \
+  template hipError_t launch_op_multi<T>(int, int, const OpArgs<T> *, const int *, int, int, hipStream_t); \
   template hipError_t launch_solve_contig<T>(SolveArgs<T>, hipStream_t);                      \
   template hipError_t launch_solve_strided<T>(StridedArgs<T>, int, hipStream_t);              \
   template hipError_t launch_apply<T>(StridedArgs<T>, hipStream_t);                           \

@@ -117,8 +117,16 @@ struct QuantArgs {
   unsigned long long *stats_ovf, *stats_nan;
 };
 
-template <typename T> hipError_t launch_load_vector(StencilArgs<T> a, bool dec, hipStream_t st);
-template <typename T> hipError_t launch_interp_add(InterpArgs<T> a, hipStream_t st);
+// Launch shape of the tiled stencil kernels: the workgroups a launch aims
+// for, and the fewest coarse planes one workgroup marches through on large
+// levels (smaller levels take one coarse plane per workgroup).
+struct Tuning {
+  int target_blocks = 2048;
+  int min_zchunk = 8;
+};
+
+template <typename T> hipError_t launch_load_vector(StencilArgs<T> a, bool dec, hipStream_t st, Tuning tn = {});
+template <typename T> hipError_t launch_interp_add(InterpArgs<T> a, hipStream_t st, Tuning tn = {});
 template <typename T> hipError_t launch_solve_contig(SolveArgs<T> a, hipStream_t st);
 template <typename T> hipError_t launch_solve_strided(StridedArgs<T> a, int mode, hipStream_t st);
 template <typename T> hipError_t launch_apply(StridedArgs<T> a, hipStream_t st);
@@ -128,5 +136,49 @@ template <typename T>
 hipError_t launch_quantize(const T *umc, int32_t *labels, QuantArgs a, bool stats, hipStream_t st);
 template <typename T>
 hipError_t launch_dequantize(const int32_t *labels, T *umc, QuantArgs a, hipStream_t st);
+
+// ---- ops: one kernel launch of one field, and multi-field launches ----
+enum OpKind {
+  kOpLoadVecDec, kOpLoadVecRec, kOpSolveContig, kOpSolveStrided, kOpApply, kOpInterpAdd,
+  kOpQuantize, kOpDequantize, kOpCopyBox
+};
+
+template <typename T>
+struct QuantJob {
+  const T *umc;
+  int32_t *labels;
+  QuantArgs a;
+};
+template <typename T>
+struct DequantJob {
+  const int32_t *labels;
+  T *umc;
+  QuantArgs a;
+};
+
+template <typename T>
+union OpArgs {
+  StencilArgs<T> st;
+  SolveArgs<T> so;
+  StridedArgs<T> sd;
+  InterpArgs<T> ia;
+  QuantJob<T> qj;
+  DequantJob<T> dj;
+  CopyArgs<T> cp;
+};
+
+// Workgroups of one op (fills the tile-grid fields of stencil ops); -1 when
+// the shape is not launchable.
+template <typename T> int op_blocks(int kind, int mode, OpArgs<T> &a, const Tuning &tn);
+// Ops of one kind with equal key run the same kernel instance, so a single
+// multi-field launch can take them all.
+template <typename T> int op_key(int kind, int mode, const OpArgs<T> &a);
+// One op on its own grid.
+template <typename T> hipError_t launch_op(int kind, int mode, OpArgs<T> a, const Tuning &tn, hipStream_t st);
+// n ops of equal (kind, key) in one launch: dargs[n] and dstart[n+1] (prefix
+// sums of the ops' workgroup counts, dstart[n] = total) live in device memory.
+template <typename T>
+hipError_t launch_op_multi(int kind, int key, const OpArgs<T> *dargs, const int *dstart, int n, int total,
+                           hipStream_t st);
 
 }  // namespace mgx

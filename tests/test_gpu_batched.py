@@ -1,0 +1,130 @@
+"""Batched fields: many uneven fields in one captured graph of multi-field
+launches (mgx_decompose_batched / mgx_recompose_batched).
+
+The batched results must equal the single-field calls bit for bit (the same
+kernel bodies; tiling does not change any summation order), hence also the
+oracle to the parity bars, which is checked on two fields directly.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2010_05872_amd as mgx  # noqa: E402
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+SPECS = [
+    ((33, 65, 33), torch.float32, None, 0),
+    ((65, 33, 129), torch.float32, "random", 0),
+    ((129, 129, 65), torch.float32, None, 1),
+    ((33, 33, 33), torch.float64, "tanh", 0),
+    ((17, 257), torch.float32, None, 0),
+    ((1025,), torch.float64, "random", 2),
+    ((65, 65, 65), torch.float64, None, 5),   # stop = L: copy only
+    ((257, 33, 65), torch.float32, "tanh", 0),
+]
+
+
+def _coords(shape, kind, seed):
+    if kind is None:
+        return None
+    if kind == "tanh":
+        return [workloads.tanh_coordinates(shape[0])] + [None] * (len(shape) - 1)
+    return [workloads.random_coordinates(n, seed + k) for k, n in enumerate(shape)]
+
+
+def _fields():
+    out = []
+    for i, (shape, dt, kind, stop) in enumerate(SPECS):
+        u = workloads.gaussian_random_field(shape, slope=2.0 + (i % 3), seed=900 + i)
+        out.append(dict(u=torch.as_tensor(u, dtype=dt, device="cuda"), coords=_coords(shape, kind, 10 * i),
+                        stop=stop, tol=10 ** (-2 - (i % 3)) * float(u.max() - u.min())))
+    return out
+
+
+@pytest.mark.parametrize("autotune", [True, False])
+def test_batched_equals_single(autotune):
+    _say(f"[batched] autotune={autotune}")
+    mgx.batch_set_autotune(autotune)
+    try:
+        F = _fields()
+        outs = [torch.empty_like(f["u"]) for f in F]
+        labels = [torch.empty(f["u"].shape, dtype=torch.int32, device="cuda") for f in F]
+        b = mgx.Batch([dict(**{"in": f["u"]}, out=o, coords=f["coords"], stop_level=f["stop"], tol=f["tol"],
+                            labels=lab) for f, o, lab in zip(F, outs, labels)])
+        b.decompose()
+        torch.cuda.synchronize()
+        info = mgx.batch_last_info()
+        _say("info", info)
+        assert info["launches"] > 0
+        for f, o, lab in zip(F, outs, labels):
+            ref = mgx.decompose(f["u"], f["coords"], f["stop"])
+            assert torch.equal(o, ref)
+            rl = mgx.quantize(ref, f["tol"], f["coords"], f["stop"])
+            assert torch.equal(lab, rl)
+        # replay with new input values in the same buffers
+        for f in F:
+            f["u"].mul_(-0.5).add_(0.25)
+        b.decompose()
+        torch.cuda.synchronize()
+        for f, o in zip(F, outs):
+            assert torch.equal(o, mgx.decompose(f["u"], f["coords"], f["stop"]))
+        # recomposition from the coefficients
+        recs = [torch.empty_like(f["u"]) for f in F]
+        r = mgx.Batch([dict(**{"in": o}, out=rr, coords=f["coords"], stop_level=f["stop"])
+                       for f, o, rr in zip(F, outs, recs)])
+        r.recompose()
+        torch.cuda.synchronize()
+        for f, o, rr in zip(F, outs, recs):
+            assert torch.equal(rr, mgx.recompose(o, f["coords"], f["stop"]))
+        # recomposition from labels (dequantize into coef, then recompose)
+        coefs = [torch.empty_like(f["u"]) for f in F]
+        recs2 = [torch.empty_like(f["u"]) for f in F]
+        # labels still hold the first input's quantization
+        r2 = mgx.Batch([dict(out=rr, coords=f["coords"], stop_level=f["stop"], tol=f["tol"], labels=lab, coef=c)
+                        for f, lab, c, rr in zip(F, labels, coefs, recs2)])
+        r2.recompose()
+        torch.cuda.synchronize()
+        for f, lab, c, rr in zip(F, labels, coefs, recs2):
+            dq = mgx.dequantize(lab, f["tol"], f["u"].dtype, f["coords"], f["stop"])
+            assert torch.equal(c, dq)
+            assert torch.equal(rr, mgx.recompose(dq, f["coords"], f["stop"]))
+    finally:
+        mgx.batch_set_autotune(True)
+
+
+def test_batched_parity_with_oracle():
+    _say("[batched] oracle")
+    F = _fields()[:4]
+    outs = [torch.empty_like(f["u"]) for f in F]
+    b = mgx.Batch([dict(**{"in": f["u"]}, out=o, coords=f["coords"], stop_level=f["stop"]) for f, o in zip(F, outs)])
+    b.decompose()
+    torch.cuda.synchronize()
+    for f, o in zip(F, outs):
+        u64 = f["u"].double().cpu().numpy()
+        ref = oracle.to_level_centric(oracle.decompose(u64, f["coords"], f["stop"]), f["stop"])
+        bar = 1e-12 if f["u"].dtype == torch.float64 else 1e-5
+        assert np.abs(o.double().cpu().numpy() - ref).max() <= bar * np.abs(u64).max()
+
+
+def test_batched_errors():
+    u = torch.zeros((33, 33, 33), dtype=torch.float32, device="cuda")
+    o = torch.empty_like(u)
+    b = mgx.Batch([dict(**{"in": u}, out=o)], workspace=torch.empty(16, dtype=torch.uint8, device="cuda"))
+    with pytest.raises(mgx.MgxError) as e:
+        b.decompose()
+    assert e.value.code == 7
+    with pytest.raises(mgx.MgxError) as e:
+        mgx.Batch([dict(**{"in": u}, out=u)]).decompose()
+    assert e.value.code == 1
