@@ -81,12 +81,12 @@ def measured_traffic(kernel, level, shape):
 
 
 def cpu_baseline(u_gpu, rel_tol):
-    """The FP64 oracle, as it stands, on a bounded sample of the same field:
-    the 257^3 corner sub-box, one full step."""
+    """The FP64 oracle, as it stands (single-threaded C), on the benchmark
+    field itself: one full step, timed on one host core."""
     import numpy as np
 
     import oracle
-    sub = u_gpu[:257, :257, :257].double().cpu().numpy()
+    sub = u_gpu.double().cpu().numpy()
     tol = rel_tol * float(sub.max() - sub.min())
     t0 = time.perf_counter()
     v = oracle.decompose(sub)
@@ -96,10 +96,119 @@ def cpu_baseline(u_gpu, rel_tol):
     dt = time.perf_counter() - t0
     err = float(np.abs(r - sub).max())
     nbytes = 2 * sub.size * 4
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": nbytes / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": "257^3 corner sub-box of the benchmark field, one step (decompose, quantize, "
-                      "dequantize, recompose), FP64 single-threaded C oracle; bytes counted as 2*N*4",
-            "seconds": dt, "max_err_over_tau": err / tol, "quantize_status": int(code)}
+            "sample": f"the full {'x'.join(map(str, sub.shape))} benchmark field (promoted to FP64), one step "
+                      "(decompose, quantize, dequantize, recompose); bytes counted as 2*N*4 like the GPU value",
+            "seconds": dt, "host_cpu": cpu, "host_cores_available": len(os.sched_getaffinity(0)),
+            "max_err_over_tau": err / tol, "quantize_status": int(code)}
+
+
+def timed(torch, fn, reps):
+    """Mean ms of fn() over reps calls, bracketed by device synchronizations."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps * 1e3
+
+
+def batched_section(torch, mgx, workloads, dev, reps):
+    """64 fp32 fields of uneven shapes (axes from {33,65,129,257}), k^-2..k^-4
+    spectra, per-field tolerances log-uniform in [1e-4,1e-2]*range: decompose +
+    quantize, then dequantize + recompose, per field (plain) or as one batch."""
+    specs = workloads.batch_specs()
+    us = [workloads.batch_field(s, device=dev) for s in specs]
+    tols = [s["rel_tol"] * float((u.max() - u.min()).item()) for s, u in zip(specs, us)]
+    mk = lambda: [torch.empty_like(u) for u in us]  # noqa: E731
+    outs_p, coef_p, rec_p = mk(), mk(), mk()
+    outs_b, coef_b, rec_b = mk(), mk(), mk()
+    lab_p = [torch.empty(u.shape, dtype=torch.int32, device=dev) for u in us]
+    lab_b = [torch.empty(u.shape, dtype=torch.int32, device=dev) for u in us]
+    ws = torch.empty(max(mgx.workspace_size(mgx.MGX_F32, u.shape, 0) for u in us), dtype=torch.uint8, device=dev)
+
+    def plain():
+        for u, o, lab, t in zip(us, outs_p, lab_p, tols):
+            mgx.decompose(u, out=o, workspace=ws)
+            mgx.quantize(o, t, out=lab)
+        for lab, c, r, t in zip(lab_p, coef_p, rec_p, tols):
+            mgx.dequantize(lab, t, torch.float32, out=c)
+            mgx.recompose(c, out=r, workspace=ws)
+
+    bd = mgx.Batch([{"in": u, "out": o, "tol": t, "labels": lab} for u, o, t, lab in zip(us, outs_b, tols, lab_b)])
+    br = mgx.Batch([{"out": r, "tol": t, "labels": lab, "coef": c}
+                    for r, t, lab, c in zip(rec_b, tols, lab_b, coef_b)])
+
+    def batched():
+        bd.decompose()
+        br.recompose()
+
+    for _ in range(2):  # warmup; the first batched call captures and tunes the graphs
+        plain()
+        batched()
+    bd.decompose()
+    info_d = mgx.batch_last_info()
+    br.recompose()
+    info_r = mgx.batch_last_info()
+    plain_ms = timed(torch, plain, reps)
+    batched_ms = timed(torch, batched, reps)
+    same = all(torch.equal(a, b) for a, b in zip(rec_p, rec_b)) and all(torch.equal(a, b) for a, b in zip(lab_p, lab_b))
+    N = sum(u.numel() for u in us)
+    nbytes = 2 * N * 4
+    return {"fields": len(us), "values": N, "bytes_counted": nbytes,
+            "step": "decompose+quantize, dequantize+recompose of every field",
+            "plain_ms": round(plain_ms, 4), "batched_ms": round(batched_ms, 4),
+            "plain_GBps": round(nbytes / (plain_ms * 1e-3) / 1e9, 2),
+            "batched_GBps": round(nbytes / (batched_ms * 1e-3) / 1e9, 2),
+            "speedup": round(plain_ms / batched_ms, 3), "batched_equals_plain": bool(same),
+            "graph_launches": {"decompose": info_d["launches"], "recompose": info_r["launches"]},
+            "tuned_shape": {"decompose": [info_d["target_blocks"], info_d["min_zchunk"]],
+                            "recompose": [info_r["target_blocks"], info_r["min_zchunk"]]},
+            }
+
+
+def adjoint_section(torch, mgx, workloads, dev, reps):
+    """8 fp32 257^3 fields (k^-3): forward y = R(D x + delta) against the
+    backward pass D^T R^T g of the autograd Function."""
+    X = workloads.adjoint_fields(device=dev)
+    delta = 1e-3 * torch.randn(X.shape, device=dev, generator=torch.Generator(device=dev).manual_seed(5))
+    g = torch.randn(X.shape, device=dev, generator=torch.Generator(device=dev).manual_seed(6))
+    ws = torch.empty(mgx.adjoint_workspace_size(mgx.MGX_F32, X.shape[1:], 0), dtype=torch.uint8, device=dev)
+    c, y, gc, gx = (torch.empty_like(X) for _ in range(4))
+
+    def forward():
+        for i in range(X.shape[0]):
+            mgx.decompose(X[i], out=c[i], workspace=ws)
+            c[i].add_(delta[i])
+            mgx.recompose(c[i], out=y[i], workspace=ws)
+
+    def backward():
+        for i in range(X.shape[0]):
+            mgx.recompose_adjoint(g[i], out=gc[i], workspace=ws)
+            mgx.decompose_adjoint(gc[i], out=gx[i], workspace=ws)
+
+    forward()
+    backward()
+    f_ms = timed(torch, forward, reps)
+    b_ms = timed(torch, backward, reps)
+    N = X.numel()
+    # D^T R^T = (R D)^T = I: the backward pass of the linear part returns g
+    ident_err = float((gx - g).abs().max().item() / g.abs().max().item())
+    nbytes = 2 * N * 4
+    return {"fields": X.shape[0], "shape": list(X.shape[1:]), "values": N,
+            "forward_ms": round(f_ms, 4), "backward_ms": round(b_ms, 4),
+            "forward_GBps": round(nbytes / (f_ms * 1e-3) / 1e9, 2),
+            "backward_GBps": round(nbytes / (b_ms * 1e-3) / 1e9, 2),
+            "backward_over_forward": round(b_ms / f_ms, 3),
+            "rel_err_DtRt_identity": ident_err}
 
 
 def main():
@@ -110,6 +219,7 @@ def main():
     ap.add_argument("--n", type=int, default=513)
     ap.add_argument("--rel-tol", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extensions", action="store_true", help="skip the batched and adjoint comparisons")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of the field (counter calibration)")
     args = ap.parse_args()
@@ -242,6 +352,9 @@ def main():
                            for k in ktimes), key=lambda k: -k["avg_ms"])[:12],
         "max_err_over_tau": round(err / tol, 5),
     }
+    if not args.no_extensions:
+        out["batched"] = batched_section(torch, mgx, workloads, dev, max(3, args.steps // 4))
+        out["adjoint"] = adjoint_section(torch, mgx, workloads, dev, max(3, args.steps // 4))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(u, args.rel_tol)
     print(json.dumps(out), flush=True)
