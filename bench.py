@@ -54,6 +54,9 @@ def algorithmic_bytes(name, level, shape, L, s):
         "solve_strided_store": 2 * Nc,    # read load vector, write Q_{l-1} u
         "solve_strided_apply": 3 * Nc,    # read load vector + nodal, write nodal
         "finish_1d": 3 * Nc,
+        "tail_dec": 2 * Nl,               # levels lt..stop+1 in one workgroup: read Q_lt u, write its coefficients
+        "tail_rec": 2 * Nl,               # read the coefficients of levels <= lt, write Q_lt u
+        "copy_box": 2 * Nl,
     }
     return table[name] * s
 

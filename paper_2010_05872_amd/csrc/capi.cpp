@@ -26,7 +26,20 @@ int64_t round4(int64_t v) { return (v + 3) / 4 * 4; }
 
 struct Layout {
   size_t offA = 0, offB = 0, offF = 0, offG = 0, total = 0;
+  int lt = -1;  // finest level of the single-workgroup tail, -1: none
 };
+
+// Finest level whose box has at most kTailBox nodes on every axis (the
+// tail runs levels lt .. stop+1 in one workgroup), or -1.
+int tail_level(const int64_t n[3], const bool real[3], int L, int stop) {
+  for (int l = L; l > stop; l--) {
+    bool ok = true;
+    for (int k = 0; k < 3; k++)
+      if (real[k] && (n[k] - 1) / ((int64_t)1 << (L - l)) + 1 > kTailBox) ok = false;
+    if (ok) return l;
+  }
+  return -1;
+}
 
 // Two compact coarse boxes (levels L-1 and L-2) for nodal values and one
 // coarse box with padded rows for the load vector.
@@ -51,6 +64,7 @@ Layout layout(const int64_t n[3], const bool real[3], int L, int stop, size_t es
   off = align_up(off + (size_t)cF * es, 256);
   w.offG = off;
   if (adjoint) off = align_up(off + (size_t)cF * es, 256);
+  w.lt = tail_level(n, real, L, stop);
   w.total = off;
   return w;
 }
@@ -225,6 +239,21 @@ hipError_t copy_box(const T *src, int64_t sp0, int64_t sp1, T *dst, int64_t dp0,
 }
 
 template <typename T>
+OpArgs<T> tail_args(const Plan *P, int stop, const T *tab, char *ws, const Layout &lay) {
+  OpArgs<T> o{};
+  TailArgs<T> &t = o.tl;
+  t.nlev = lay.lt - stop;
+  for (int i = 0; i < t.nlev; i++)
+    for (int k = 0; k < 3; k++) {
+      const AxisLevel &a = P->ax[lay.lt - i][k];
+      t.ax[i][k] = TailAxis<T>{tab + a.off_wl, tab + a.off_wr,   tab + a.off_w5, tab + a.off_mult,
+                               tab + a.off_invd, tab + a.off_qsup, (int)a.m,       (int)a.c};
+    }
+  (void)ws;
+  return o;
+}
+
+template <typename T>
 mgx_status run_decompose(Plan *P, int stop, const T *u, T *umc, char *ws, const Layout &lay, const T *tab,
                          Emitter<T> &em) {
   const int L = P->L;
@@ -237,7 +266,8 @@ mgx_status run_decompose(Plan *P, int stop, const T *u, T *umc, char *ws, const 
   T *A = (T *)(ws + lay.offA), *B = (T *)(ws + lay.offB), *F = (T *)(ws + lay.offF);
   const T *src = u;
   int64_t sp0 = up0, sp1 = up1;
-  for (int l = L; l > stop; l--) {
+  const int lowest = lay.lt > stop ? lay.lt : stop;  // tiled levels L .. lowest+1
+  for (int l = L; l > lowest; l--) {
     em.begin_step(L - l);
     AxisTab<T> ax[3] = {axis_tab(P, l, 0, tab), axis_tab(P, l, 1, tab), axis_tab(P, l, 2, tab)};
     const int c1 = ax[1].c, c2 = ax[2].c;
@@ -268,6 +298,17 @@ mgx_status run_decompose(Plan *P, int stop, const T *u, T *umc, char *ws, const 
     sp0 = cp0;
     sp1 = cp1;
   }
+  if (lay.lt > stop) {  // levels lt .. stop+1 in one workgroup
+    em.begin_step(L - lay.lt);
+    OpArgs<T> o = tail_args<T>(P, stop, tab, ws, lay);
+    o.tl.src = src;
+    o.tl.sp0 = sp0;
+    o.tl.sp1 = sp1;
+    o.tl.umc = umc;
+    o.tl.up0 = up0;
+    o.tl.up1 = up1;
+    if (em.op(kOpTailDec, 0, "tail_dec", lay.lt, o) != hipSuccess) return MGX_ERR_HIP;
+  }
   return MGX_OK;
 }
 
@@ -282,15 +323,35 @@ mgx_status run_recompose(Plan *P, int stop, const T *umc, T *u, char *ws, const 
     return hip_status(copy_box<T>(umc, up0, up1, u, up0, up1, (int)P->n[0], (int)n1, (int)n2, L, em));
   }
   T *A = (T *)(ws + lay.offA), *B = (T *)(ws + lay.offB), *F = (T *)(ws + lay.offF);
-  for (int l = stop + 1; l <= L; l++) {
-    em.begin_step(l - stop - 1);
+  int first_tiled = stop + 1;
+  if (lay.lt > stop) {  // levels stop+1 .. lt in one workgroup, into the level-lt box
+    em.begin_step(0);
+    OpArgs<T> o = tail_args<T>(P, stop, tab, ws, lay);
+    o.tl.umc_r = umc;
+    o.tl.up0 = up0;
+    o.tl.up1 = up1;
+    if (lay.lt == L) {
+      o.tl.dst = u;
+      o.tl.dp0 = up0;
+      o.tl.dp1 = up1;
+    } else {
+      const AxisLevel &a1 = P->ax[lay.lt][1], &a2 = P->ax[lay.lt][2];
+      o.tl.dst = ((L - 1 - lay.lt) % 2 == 0) ? A : B;
+      o.tl.dp1 = a2.m;
+      o.tl.dp0 = a1.m * a2.m;
+    }
+    if (em.op(kOpTailRec, 0, "tail_rec", lay.lt, o) != hipSuccess) return MGX_ERR_HIP;
+    first_tiled = lay.lt + 1;
+  }
+  for (int l = first_tiled; l <= L; l++) {
+    em.begin_step(l - stop - 1 + (lay.lt > stop ? 1 : 0));
     AxisTab<T> ax[3] = {axis_tab(P, l, 0, tab), axis_tab(P, l, 1, tab), axis_tab(P, l, 2, tab)};
     const int c1 = ax[1].c, c2 = ax[2].c;
     const int m1 = ax[1].m, m2 = ax[2].m;
     T *nb = ((L - 1 - (l - 1)) % 2 == 0) ? A : B;  // level l-1 nodal values
     const int64_t cp1 = c2, cp0 = (int64_t)c1 * c2;
     const int64_t fp1 = round4(c2), fp0 = (int64_t)c1 * fp1;
-    const bool first = (l == stop + 1);
+    const bool first = (l == stop + 1);  // with a tail, level lt+1 reads the tail's box nb
     const T *nin = first ? umc : nb;
     const int64_t ip0 = first ? up0 : cp0, ip1 = first ? up1 : cp1;
     OpArgs<T> o{};

@@ -84,6 +84,30 @@ __device__ __forceinline__ void st_at(T *base, uint32_t byte_off, T v) {
   *(T *)((char *)base + byte_off) = v;
 }
 
+// Accesses of data that one pass writes or reads exactly once (outputs of
+// the level kernels, the coefficients read by the interpolation): with
+// MGX_STREAM_HINT bit 0 (stores) / bit 1 (loads) they carry the
+// non-temporal cache hint.
+#ifndef MGX_STREAM_HINT
+#define MGX_STREAM_HINT 0
+#endif
+template <typename T>
+__device__ __forceinline__ void st_once(T *base, uint32_t byte_off, T v) {
+#if MGX_STREAM_HINT & 1
+  __builtin_nontemporal_store(v, (T *)((char *)base + byte_off));
+#else
+  *(T *)((char *)base + byte_off) = v;
+#endif
+}
+template <typename T>
+__device__ __forceinline__ T ld_once(const T *base, uint32_t byte_off) {
+#if MGX_STREAM_HINT & 2
+  return __builtin_nontemporal_load((const T *)((const char *)base + byte_off));
+#else
+  return *(const T *)((const char *)base + byte_off);
+#endif
+}
+
 // Column of region column q in a de-interleaved LDS row: even columns first,
 // then odd ones (stride-1 reads in the restriction along x).
 template <int TX>
@@ -191,11 +215,15 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
   auto fetch = [&](int j, T (&st)[NE]) {
     const bool pin = j >= 0 && j < m0;
     const T *base = DEC ? a.V + (int64_t)(pin ? j : 0) * a.vp0 : a.umc_r + (pin ? lc_pos(j, c0) : 0) * a.up0;
-    // recomposition: nodal nodes (all indices even) carry no multilevel component
-    const unsigned keep = DEC ? valid : ((j & 1) ? valid : (valid & ~yxeven));
+    // recomposition: nodal nodes (all indices even) carry no multilevel
+    // component; their lanes read the plane's first element instead (one
+    // shared line) rather than the coarse corner
+    const bool skip_nodal = !DEC && !(j & 1);
+    const unsigned keep = skip_nodal ? (valid & ~yxeven) : valid;
 #pragma unroll
     for (int k = 0; k < NE; k++) {
-      const T v = ld_at(base, (uint32_t)goff[k]);
+      const uint32_t off = (skip_nodal && ((yxeven >> k) & 1u)) ? 0u : (uint32_t)goff[k];
+      const T v = ld_at(base, off);
       st[k] = (pin && ((keep >> k) & 1u)) ? v : T(0);
     }
   };
@@ -297,9 +325,9 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
             const T C20 = sV[s0][R2 + e0], C22 = sV[s0][R2 + e0 + 1];
             const T t0 = cwxl[k] * C00 + cwxr[k] * C02, t2 = cwxl[k] * C20 + cwxr[k] * C22;
             const uint32_t oE = (uint32_t)(cRowE[k] + cColE[k]);
-            if (f & 2u) st_at(cbase, oE + colOdd, sV[s0][R0 + E + e0] - t0);
-            if (f & 4u) st_at(cbase, oE + rowOdd, sV[s0][R0 + W + e0] - (cwyl[k] * C00 + cwyr[k] * C20));
-            if (f & 8u) st_at(cbase, oE + rowOdd + colOdd, sV[s0][R0 + W + E + e0] - (cwyl[k] * t0 + cwyr[k] * t2));
+            if (f & 2u) st_once(cbase, oE + colOdd, sV[s0][R0 + E + e0] - t0);
+            if (f & 4u) st_once(cbase, oE + rowOdd, sV[s0][R0 + W + e0] - (cwyl[k] * C00 + cwyr[k] * C20));
+            if (f & 8u) st_once(cbase, oE + rowOdd + colOdd, sV[s0][R0 + W + E + e0] - (cwyl[k] * t0 + cwyr[k] * t2));
           }
         }
       } else {
@@ -317,13 +345,13 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
             const T ta0 = wxl * A00 + wxr * A02, ta2 = wxl * A20 + wxr * A22;
             const T tb0 = wxl * B00 + wxr * B02, tb2 = wxl * B20 + wxr * B22;
             const uint32_t oE = (uint32_t)(cRowE[k] + cColE[k]);
-            if (f & 1u) st_at(cbase, oE, sV[s0][R0 + e0] - (wzl * A00 + wzr * B00));
-            if (f & 2u) st_at(cbase, oE + colOdd, sV[s0][R0 + E + e0] - (wzl * ta0 + wzr * tb0));
+            if (f & 1u) st_once(cbase, oE, sV[s0][R0 + e0] - (wzl * A00 + wzr * B00));
+            if (f & 2u) st_once(cbase, oE + colOdd, sV[s0][R0 + E + e0] - (wzl * ta0 + wzr * tb0));
             if (f & 4u)
-              st_at(cbase, oE + rowOdd,
+              st_once(cbase, oE + rowOdd,
                     sV[s0][R0 + W + e0] - (wzl * (wyl * A00 + wyr * A20) + wzr * (wyl * B00 + wyr * B20)));
             if (f & 8u)
-              st_at(cbase, oE + rowOdd + colOdd,
+              st_once(cbase, oE + rowOdd + colOdd,
                     sV[s0][R0 + W + E + e0] - (wzl * (wyl * ta0 + wyr * ta2) + wzr * (wyl * tb0 + wyr * tb2)));
           }
         }
@@ -362,7 +390,7 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
         T *const fbase = a.F + (int64_t)Zdone * a.fp0;
 #pragma unroll
         for (int k = 0; k < NOUT; k++)
-          if ((yact >> k) & 1u) st_at(fbase, (uint32_t)foff[k], acc[0][k]);
+          if ((yact >> k) & 1u) st_once(fbase, (uint32_t)foff[k], acc[0][k]);
       }
 #pragma unroll
       for (int k = 0; k < NOUT; k++) {
@@ -827,13 +855,13 @@ __device__ __forceinline__ void interp_add_body(const InterpArgs<T> a, const int
     const T *bo = a.umc + (int64_t)(odd_in ? c0 + J : 0) * a.up0;
 #pragma unroll
     for (int k = 0; k < NB; k++) {
-      cv[k][0] = ld_at(be, (uint32_t)bEO[k]);
-      cv[k][1] = ld_at(be, (uint32_t)bOE[k]);
-      cv[k][2] = ld_at(be, (uint32_t)bOO[k]);
-      cv[k][3] = ld_at(bo, (uint32_t)bEE[k]);
-      cv[k][4] = ld_at(bo, (uint32_t)bEO[k]);
-      cv[k][5] = ld_at(bo, (uint32_t)bOE[k]);
-      cv[k][6] = ld_at(bo, (uint32_t)bOO[k]);
+      cv[k][0] = ld_once(be, (uint32_t)bEO[k]);
+      cv[k][1] = ld_once(be, (uint32_t)bOE[k]);
+      cv[k][2] = ld_once(be, (uint32_t)bOO[k]);
+      cv[k][3] = ld_once(bo, (uint32_t)bEE[k]);
+      cv[k][4] = ld_once(bo, (uint32_t)bEO[k]);
+      cv[k][5] = ld_once(bo, (uint32_t)bOE[k]);
+      cv[k][6] = ld_once(bo, (uint32_t)bOO[k]);
     }
   };
 
@@ -859,20 +887,20 @@ __device__ __forceinline__ void interp_add_body(const InterpArgs<T> a, const int
       const T e10 = wyl * A00 + wyr * A10;
       const T e11 = wyl * ea + wyr * eb;
       const uint32_t o0 = (uint32_t)bOut[k];
-      if (f & 1u) st_at(oe, o0, A00);
-      if (f & 2u) st_at(oe, o0 + ES, cv[k][0] + ea);
-      if (f & 4u) st_at(oe, o0 + outRow, cv[k][1] + e10);
-      if (f & 8u) st_at(oe, o0 + outRow + ES, cv[k][2] + e11);
+      if (f & 1u) st_once(oe, o0, A00);
+      if (f & 2u) st_once(oe, o0 + ES, cv[k][0] + ea);
+      if (f & 4u) st_once(oe, o0 + outRow, cv[k][1] + e10);
+      if (f & 8u) st_once(oe, o0 + outRow + ES, cv[k][2] + e11);
       if (odd_in) {
         const T B00 = sN[sb][n], B01 = sN[sb][n + 1], B10 = sN[sb][n + NW], B11 = sN[sb][n + NW + 1];
         const T fa = wxl * B00 + wxr * B01;
         const T fb = wxl * B10 + wxr * B11;
         const T f10 = wyl * B00 + wyr * B10;
         const T f11 = wyl * fa + wyr * fb;
-        if (f & 1u) st_at(oo, o0, cv[k][3] + (wzl * A00 + wzr * B00));
-        if (f & 2u) st_at(oo, o0 + ES, cv[k][4] + (wzl * ea + wzr * fa));
-        if (f & 4u) st_at(oo, o0 + outRow, cv[k][5] + (wzl * e10 + wzr * f10));
-        if (f & 8u) st_at(oo, o0 + outRow + ES, cv[k][6] + (wzl * e11 + wzr * f11));
+        if (f & 1u) st_once(oo, o0, cv[k][3] + (wzl * A00 + wzr * B00));
+        if (f & 2u) st_once(oo, o0 + ES, cv[k][4] + (wzl * ea + wzr * fa));
+        if (f & 4u) st_once(oo, o0 + outRow, cv[k][5] + (wzl * e10 + wzr * f10));
+        if (f & 8u) st_once(oo, o0 + outRow + ES, cv[k][6] + (wzl * e11 + wzr * f11));
       }
     }
     // loads for step J+2 after every store of this step (partial waits later)
@@ -1515,6 +1543,247 @@ hipError_t launch_dequantize(const int32_t *labels, T *umc, QuantArgs a, hipStre
 }
 
 // ---------------------------------------------------------------------------
+// Tail of the hierarchy in one workgroup.  Every level of the tail has at
+// most kTailBox nodes per axis, so a step is too small to fill the chip and a
+// launch per step is latency bound.  One workgroup of 1024 threads runs all
+// the tail's levels with the same arithmetic as the tiled kernels, entirely
+// in LDS, phase by phase with a workgroup barrier between phases:
+// coefficients, the load vector as three separable 5-point passes (x, y, z)
+// and the three Thomas solves.  Global memory is touched once per level for
+// the coefficients and once for the tail's input or output box.
+// ---------------------------------------------------------------------------
+constexpr int kTailThreads = 1024;
+constexpr int kTailM = kTailBox, kTailC = (kTailBox + 1) / 2;
+constexpr int kTailV = kTailM * kTailM * kTailM;   // a level box
+constexpr int kTailG1 = kTailM * kTailM * kTailC;  // after the x pass
+constexpr int kTailG2 = kTailM * kTailC * kTailC;  // after the y pass
+constexpr int kTailF = kTailC * kTailC * kTailC;   // a coarse box
+constexpr int kTailLds = kTailV + kTailG1 + kTailG2 + 2 * kTailF;
+
+__device__ __forceinline__ int lcp(int j, int c) { return (j & 1) ? c + (j >> 1) : (j >> 1); }
+
+// Weights and corner offsets (along one axis) of the multilinear interpolant
+// at level index j: corners lo/hi in units of the coarse index.
+template <typename T>
+__device__ __forceinline__ void tail_corner(const TailAxis<T> &ax, int j, int &lo, int &hi, T &wlo, T &whi) {
+  if (j & 1) {
+    lo = (j - 1) >> 1;
+    hi = (j + 1) >> 1;
+    wlo = ax.wl[j];
+    whi = ax.wr[j];
+  } else {
+    lo = hi = j >> 1;
+    wlo = T(1);
+    whi = T(0);
+  }
+}
+
+// Interpolant at level node (j0,j1,j2) from a coarse box C (pitches cp0, cp1).
+template <typename T>
+__device__ __forceinline__ T tail_interp(const T *C, int cp0, int cp1, int cp2, const TailAxis<T> (&ax)[3], int j0,
+                                         int j1, int j2) {
+  int lo[3], hi[3];
+  T wlo[3], whi[3];
+  tail_corner(ax[0], j0, lo[0], hi[0], wlo[0], whi[0]);
+  tail_corner(ax[1], j1, lo[1], hi[1], wlo[1], whi[1]);
+  tail_corner(ax[2], j2, lo[2], hi[2], wlo[2], whi[2]);
+  T acc = T(0);
+#pragma unroll
+  for (int c = 0; c < 8; c++) {
+    const T w = ((c & 1) ? whi[0] : wlo[0]) * ((c & 2) ? whi[1] : wlo[1]) * ((c & 4) ? whi[2] : wlo[2]);
+    if (w != T(0))
+      acc += w * C[((c & 1) ? hi[0] : lo[0]) * cp0 + ((c & 2) ? hi[1] : lo[1]) * cp1 +
+                   ((c & 4) ? hi[2] : lo[2]) * cp2];
+  }
+  return acc;
+}
+
+// F = (R M)^{x3} of the level box V (compact, in LDS), via g1 and g2.
+template <typename T>
+__device__ __forceinline__ void tail_load_vector(const TailAxis<T> (&ax)[3], const T *V, T *g1, T *g2, T *F) {
+  const int m0 = ax[0].m, m1 = ax[1].m, m2 = ax[2].m, c0 = ax[0].c, c1 = ax[1].c, c2 = ax[2].c;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < m0 * m1 * c2; i += kTailThreads) {
+    const int X = i % c2, r = i / c2;
+    T acc = T(0);
+#pragma unroll
+    for (int d = 0; d < 5; d++) {
+      const int x = 2 * X + d - 2;
+      if (x >= 0 && x < m2) acc += ax[2].w5[X * 5 + d] * V[r * m2 + x];
+    }
+    g1[i] = acc;
+  }
+  __syncthreads();
+  for (int i = tid; i < m0 * c1 * c2; i += kTailThreads) {
+    const int X = i % c2, r = i / c2, Y = r % c1, z = r / c1;
+    T acc = T(0);
+#pragma unroll
+    for (int d = 0; d < 5; d++) {
+      const int y = 2 * Y + d - 2;
+      if (y >= 0 && y < m1) acc += ax[1].w5[Y * 5 + d] * g1[(z * m1 + y) * c2 + X];
+    }
+    g2[i] = acc;
+  }
+  __syncthreads();
+  for (int i = tid; i < c0 * c1 * c2; i += kTailThreads) {
+    const int X = i % c2, r = i / c2, Y = r % c1, Z = r / c1;
+    T acc = T(0);
+#pragma unroll
+    for (int d = 0; d < 5; d++) {
+      const int z = 2 * Z + d - 2;
+      if (z >= 0 && z < m0) acc += ax[0].w5[Z * 5 + d] * g2[(z * c1 + Y) * c2 + X];
+    }
+    F[i] = acc;
+  }
+  __syncthreads();
+}
+
+// Thomas solves of the coarse mass matrix along x, y and z, in place on F.
+template <typename T>
+__device__ __forceinline__ void tail_solves(const TailAxis<T> (&ax)[3], T *F) {
+  const int c0 = ax[0].c, c1 = ax[1].c, c2 = ax[2].c;
+  const int tid = threadIdx.x;
+  const int n[3] = {c0, c1, c2};
+  const int stride[3] = {c1 * c2, c2, 1};
+  for (int k = 2; k >= 0; k--) {
+    const int c = n[k];
+    const int o1 = k == 0 ? 1 : 0, o2 = k == 2 ? 1 : 2;
+    const int nl = n[o1] * n[o2];
+    const T *mult = ax[k].mult, *invd = ax[k].invd, *qsup = ax[k].qsup;
+    if (tid < nl) {
+      T *p = F + (tid / n[o2]) * stride[o1] + (tid % n[o2]) * stride[o2];
+      const int s = stride[k];
+      T prev = p[0];
+      for (int J = 1; J < c; J++) {
+        prev = p[J * s] - mult[J] * prev;
+        p[J * s] = prev;
+      }
+      T y = invd[c - 1] * prev;
+      p[(c - 1) * s] = y;
+      for (int J = c - 2; J >= 0; J--) {
+        y = invd[J] * p[J * s] - qsup[J] * y;
+        p[J * s] = y;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void tail_dec_body(const TailArgs<T> &a) {
+  __shared__ T sm[kTailLds];
+  T *const sV = sm, *const g1 = sV + kTailV, *const g2 = g1 + kTailG1, *const fA = g2 + kTailG2, *const fB = fA + kTailF;
+  const int tid = threadIdx.x;
+  {  // the level-lt box into LDS (all loads issued before the first wait)
+    const int m0 = a.ax[0][0].m, m1 = a.ax[0][1].m, m2 = a.ax[0][2].m, n = m0 * m1 * m2;
+    constexpr int R = (kTailV + kTailThreads - 1) / kTailThreads;
+    T r[R];
+#pragma unroll
+    for (int k = 0; k < R; k++) {
+      const int q = tid + k * kTailThreads;
+      const int j2 = q % m2, t = q / m2, j1 = t % m1, j0 = t / m1;
+      r[k] = q < n ? a.src[j0 * a.sp0 + j1 * a.sp1 + j2] : T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < R; k++)
+      if (tid + k * kTailThreads < n) sV[tid + k * kTailThreads] = r[k];
+    __syncthreads();
+  }
+  const T *V = sV;
+  for (int i = 0; i < a.nlev; i++) {
+    const TailAxis<T>(&ax)[3] = a.ax[i];
+    const int m1 = ax[1].m, m2 = ax[2].m, c0 = ax[0].c, c1 = ax[1].c, c2 = ax[2].c;
+    const int m0 = ax[0].m;
+    // coefficients of the level's non-nodal nodes, at level-centric positions
+    for (int q = tid; q < m0 * m1 * m2; q += kTailThreads) {
+      const int j2 = q % m2, r = q / m2, j1 = r % m1, j0 = r / m1;
+      if (!((j0 | j1 | j2) & 1)) continue;
+      // nodal corners of V at level indices: the interpolant reads V at
+      // 2*lo, 2*hi, i.e. a coarse view with doubled pitches
+      const T v = V[q] - tail_interp<T>(V, 2 * m1 * m2, 2 * m2, 2, ax, j0, j1, j2);
+      a.umc[lcp(j0, c0) * a.up0 + lcp(j1, c1) * a.up1 + lcp(j2, c2)] = v;
+    }
+    // Q_{l-1} u = Mc^{-1} (R M)^{x3} V (as in the tiled decomposition)
+    T *F = (i & 1) ? fB : fA;
+    tail_load_vector<T>(ax, V, g1, g2, F);
+    tail_solves<T>(ax, F);
+    if (i == a.nlev - 1) {
+      for (int q = tid; q < c0 * c1 * c2; q += kTailThreads) {
+        const int X = q % c2, r = q / c2, Y = r % c1, Z = r / c1;
+        a.umc[Z * a.up0 + Y * a.up1 + X] = F[q];
+      }
+    }
+    V = F;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void tail_rec_body(const TailArgs<T> &a) {
+  __shared__ T sm[kTailLds];
+  T *const sZ = sm, *const g1 = sZ + kTailV, *const g2 = g1 + kTailG1, *const fA = g2 + kTailG2, *const vB = fA + kTailF;
+  const int tid = threadIdx.x;
+  const T *U = a.umc_r;
+  // nodal values of the level below: the stop box of u_mc first
+  {
+    const TailAxis<T>(&ax)[3] = a.ax[a.nlev - 1];
+    const int c0 = ax[0].c, c1 = ax[1].c, c2 = ax[2].c;
+    for (int q = tid; q < c0 * c1 * c2; q += kTailThreads) {
+      const int X = q % c2, r = q / c2, Y = r % c1, Z = r / c1;
+      vB[q] = U[Z * a.up0 + Y * a.up1 + X];
+    }
+  }
+  for (int i = 0; i < a.nlev; i++) {
+    const TailAxis<T>(&ax)[3] = a.ax[a.nlev - 1 - i];
+    const int m0 = ax[0].m, m1 = ax[1].m, m2 = ax[2].m, c0 = ax[0].c, c1 = ax[1].c, c2 = ax[2].c;
+    // the level's coefficients (zero at nodal nodes) into LDS, all loads
+    // issued before the first wait
+    {
+      const int n = m0 * m1 * m2;
+      constexpr int R = (kTailV + kTailThreads - 1) / kTailThreads;
+      T r[R];
+#pragma unroll
+      for (int k = 0; k < R; k++) {
+        const int q = tid + k * kTailThreads;
+        const int j2 = q % m2, t = q / m2, j1 = t % m1, j0 = t / m1;
+        const bool coef = q < n && ((j0 | j1 | j2) & 1);
+        r[k] = coef ? U[lcp(j0, c0) * a.up0 + lcp(j1, c1) * a.up1 + lcp(j2, c2)] : T(0);
+      }
+#pragma unroll
+      for (int k = 0; k < R; k++)
+        if (tid + k * kTailThreads < n) sZ[tid + k * kTailThreads] = r[k];
+    }
+    __syncthreads();
+    // correction from the coefficients, subtracted from the nodal values
+    tail_load_vector<T>(ax, sZ, g1, g2, fA);
+    tail_solves<T>(ax, fA);
+    for (int q = tid; q < c0 * c1 * c2; q += kTailThreads) fA[q] = vB[q] - fA[q];
+    __syncthreads();
+    // level box: nodal values, coefficients plus the interpolant
+    const bool last = i == a.nlev - 1;
+    for (int q = tid; q < m0 * m1 * m2; q += kTailThreads) {
+      const int j2 = q % m2, r = q / m2, j1 = r % m1, j0 = r / m1;
+      const T v = ((j0 | j1 | j2) & 1) ? sZ[q] + tail_interp<T>(fA, c1 * c2, c2, 1, ax, j0, j1, j2)
+                                       : fA[((j0 >> 1) * c1 + (j1 >> 1)) * c2 + (j2 >> 1)];
+      if (last)
+        a.dst[j0 * a.dp0 + j1 * a.dp1 + j2] = v;
+      else
+        vB[q] = v;  // the next level's nodal values (its coarse box)
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kTailThreads) k_tail_dec(TailArgs<T> a) {
+  tail_dec_body<T>(a);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kTailThreads) k_tail_rec(TailArgs<T> a) {
+  tail_rec_body<T>(a);
+}
+
+// ---------------------------------------------------------------------------
 // Multi-field launches.  One grid covers several ops of one kernel instance
 // (for example the load-vector step of every field of a batch at the same
 // level depth): workgroup g belongs to op f with start[f] <= g < start[f+1]
@@ -1608,6 +1877,16 @@ __global__ void __launch_bounds__(256) k_dequantize_multi(MultiArgs<T> m) {
   dequantize_body<T, VEC>(j.labels, j.umc, j.a, g - m.start[f], m.start[f + 1] - m.start[f]);
 }
 
+template <typename T>
+__global__ void __launch_bounds__(kTailThreads) k_tail_dec_multi(MultiArgs<T> m) {
+  tail_dec_body<T>(m.args[find_op(m.start, m.n, blockIdx.x)].tl);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kTailThreads) k_tail_rec_multi(MultiArgs<T> m) {
+  tail_rec_body<T>(m.args[find_op(m.start, m.n, blockIdx.x)].tl);
+}
+
 // ---- op dispatch (host) ----
 // line length c of the contiguous solve -> (E, G) instance index
 static int contig_index(int c) {
@@ -1674,6 +1953,8 @@ int op_blocks(int kind, int mode, OpArgs<T> &a, const Tuning &tn) {
     case kOpQuantize: return grid_cap((a.qj.a.n + 1023) / 1024);
     case kOpDequantize: return grid_cap((a.dj.a.n + 1023) / 1024);
     case kOpCopyBox: return grid_cap(((int64_t)a.cp.n0 * a.cp.n1 * a.cp.n2 + 255) / 256);
+    case kOpTailDec:
+    case kOpTailRec: return 1;
   }
   return -1;
 }
@@ -1701,6 +1982,12 @@ hipError_t launch_op(int kind, int mode, OpArgs<T> a, const Tuning &tn, hipStrea
     case kOpQuantize: return launch_quantize<T>(a.qj.umc, a.qj.labels, a.qj.a, false, st);
     case kOpDequantize: return launch_dequantize<T>(a.dj.labels, a.dj.umc, a.dj.a, st);
     case kOpCopyBox: return launch_copy_box<T>(a.cp, st);
+    case kOpTailDec:
+      hipLaunchKernelGGL((k_tail_dec<T>), dim3(1), dim3(kTailThreads), 0, st, a.tl);
+      return hipGetLastError();
+    case kOpTailRec:
+      hipLaunchKernelGGL((k_tail_rec<T>), dim3(1), dim3(kTailThreads), 0, st, a.tl);
+      return hipGetLastError();
   }
   return hipErrorInvalidValue;
 }
@@ -1736,6 +2023,8 @@ hipError_t launch_op_multi(int kind, int key, const OpArgs<T> *dargs, const int 
     case kOpInterpAdd: MGX_MULTI((k_interp_add_multi<T, TX, TY, NT>), NT); break;
     case kOpApply: MGX_MULTI((k_apply_multi<T>), 256); break;
     case kOpCopyBox: MGX_MULTI((k_copy_box_multi<T>), 256); break;
+    case kOpTailDec: MGX_MULTI((k_tail_dec_multi<T>), kTailThreads); break;
+    case kOpTailRec: MGX_MULTI((k_tail_rec_multi<T>), kTailThreads); break;
     case kOpQuantize:
       if (key) MGX_MULTI((k_quantize_multi<T, true>), 256);
       else MGX_MULTI((k_quantize_multi<T, false>), 256);

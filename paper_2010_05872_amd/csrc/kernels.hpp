@@ -106,6 +106,31 @@ struct CopyArgs {             // strided copy of an n0 x n1 x n2 box
   int n0, n1, n2;
 };
 
+// The coarse tail of the hierarchy (every level box at most kTailBox nodes
+// per axis) in one workgroup: all its levels in one launch instead of one
+// latency-bound launch per step and level.
+constexpr int kTailBox = 17;
+constexpr int kTailMax = 6;  // levels of a tail (17 -> 3 takes 3 steps)
+
+template <typename T>
+struct TailAxis {
+  const T *wl, *wr, *w5, *mult, *invd, *qsup;
+  int m, c;
+};
+
+template <typename T>
+struct TailArgs {
+  TailAxis<T> ax[kTailMax][3];  // [i][k]: level lt - i, lt the tail's finest level
+  int nlev;                      // levels lt .. lt - nlev + 1 are processed
+  const T *src;                  // decompose: the level-lt box (Q_lt u)
+  int64_t sp0, sp1;
+  T *umc;                        // decompose: coefficients and stop box out
+  const T *umc_r;                // recompose: coefficients and stop box in
+  int64_t up0, up1;
+  T *dst;                        // recompose: the level-lt box out
+  int64_t dp0, dp1;
+};
+
 struct QuantArgs {
   int64_t n;                  // element count (< 2^32)
   int n1, n2;                 // padded dims 1 and 2
@@ -140,7 +165,7 @@ hipError_t launch_dequantize(const int32_t *labels, T *umc, QuantArgs a, hipStre
 // ---- ops: one kernel launch of one field, and multi-field launches ----
 enum OpKind {
   kOpLoadVecDec, kOpLoadVecRec, kOpSolveContig, kOpSolveStrided, kOpApply, kOpInterpAdd,
-  kOpQuantize, kOpDequantize, kOpCopyBox
+  kOpQuantize, kOpDequantize, kOpCopyBox, kOpTailDec, kOpTailRec
 };
 
 template <typename T>
@@ -165,6 +190,7 @@ union OpArgs {
   QuantJob<T> qj;
   DequantJob<T> dj;
   CopyArgs<T> cp;
+  TailArgs<T> tl;
 };
 
 // Workgroups of one op (fills the tile-grid fields of stencil ops); -1 when
