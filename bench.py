@@ -42,6 +42,11 @@ def algorithmic_bytes(name, level, shape, L, s):
         N = 1
         for n in shape:
             N *= n
+        Nfine = N - level_sizes(shape, L, L - 1)  # coefficients of the finest level
+        if name.endswith("_finest"):
+            return Nfine * (s + 4)
+        if name.endswith("_coarse"):
+            return (N - Nfine) * (s + 4)
         return N * (s + 4)  # quantize / dequantize: coefficients + int32 labels
     Nl = level_sizes(shape, L, level)
     Nc = level_sizes(shape, L, level - 1)
@@ -274,6 +279,9 @@ def main():
 
     # ---- per-operation times (events on the stream the library launches on) ----
     ops = {
+        "decompose_quantize": lambda: mgx.decompose_quantize(u, tol, out=umc, labels=labels, workspace=ws),
+        "dequantize_recompose": lambda: mgx.dequantize_recompose(labels, tol, torch.float32, coef=uq, out=ut,
+                                                                 workspace=ws),
         "decompose": lambda: mgx.decompose(u, out=umc, workspace=ws),
         "quantize": lambda: mgx.quantize(umc, tol, out=labels),
         "dequantize": lambda: mgx.dequantize(labels, tol, torch.float32, out=uq),

@@ -95,7 +95,7 @@ EXPORTS = (
     "mgx_quantize", "mgx_dequantize", "mgx_linf_constant", "mgx_level_tolerances",
     "mgx_trace_enable", "mgx_trace_read", "mgx_adjoint_workspace_size", "mgx_decompose_adjoint",
     "mgx_recompose_adjoint", "mgx_batch_workspace_size", "mgx_decompose_batched", "mgx_recompose_batched",
-    "mgx_batch_set_autotune", "mgx_batch_last_info",
+    "mgx_batch_set_autotune", "mgx_batch_last_info", "mgx_decompose_quantize", "mgx_dequantize_recompose",
 )
 
 _lib = None
@@ -117,6 +117,10 @@ def lib():
         L.mgx_num_levels.restype = ci
         L.mgx_workspace_size.argtypes = [ci, ci, i64p, ci]
         L.mgx_workspace_size.restype = sz
+        L.mgx_decompose_quantize.argtypes = [vp, vp, vp, ci, ci, i64p, vp, cd, ci, cd, vp, sz, vp]
+        L.mgx_decompose_quantize.restype = ci
+        L.mgx_dequantize_recompose.argtypes = [vp, vp, vp, ci, ci, i64p, vp, cd, ci, cd, vp, sz, vp]
+        L.mgx_dequantize_recompose.restype = ci
         L.mgx_adjoint_workspace_size.argtypes = [ci, ci, i64p, ci]
         L.mgx_adjoint_workspace_size.restype = sz
         for name in ("mgx_decompose", "mgx_recompose", "mgx_decompose_adjoint", "mgx_recompose_adjoint"):
@@ -291,6 +295,48 @@ def recompose(u_mc, coords=None, stop_level=0, out=None, workspace=None):
                                c.ptr, int(stop_level), ws.data_ptr(), ws.numel() * ws.element_size(),
                                _stream(u_mc.device))
     _check(code, "mgx_recompose")
+    return out
+
+
+def decompose_quantize(u, tol, coords=None, stop_level=0, c_linf=0.0, out=None, labels=None, workspace=None):
+    """decompose then quantize (same results), the finest level's quantization
+    overlapped with the coarser levels.  Returns (u_mc, labels)."""
+    import torch
+    _check_tensor(u, "u")
+    if out is None:
+        out = torch.empty_like(u)
+    if labels is None:
+        labels = torch.empty(u.shape, dtype=torch.int32, device=u.device)
+    _check_tensor(out, "out")
+    _check_tensor(labels, "labels")
+    ws, _ = _workspace(u, stop_level, workspace)
+    c = Coords(u.shape, coords)
+    code = lib().mgx_decompose_quantize(u.data_ptr(), out.data_ptr(), labels.data_ptr(), _dtype_code(u), u.dim(),
+                                        _dims(u.shape), c.ptr, float(tol), int(stop_level), float(c_linf),
+                                        ws.data_ptr(), ws.numel() * ws.element_size(), _stream(u.device))
+    _check(code, "mgx_decompose_quantize")
+    return out, labels
+
+
+def dequantize_recompose(labels, tol, dtype, coords=None, stop_level=0, c_linf=0.0, coef=None, out=None,
+                         workspace=None):
+    """dequantize into coef, then recompose into out (same results), the finest
+    level's dequantization overlapped with the coarser levels.  Returns out."""
+    import torch
+    _check_tensor(labels, "labels")
+    if coef is None:
+        coef = torch.empty(labels.shape, dtype=dtype, device=labels.device)
+    if out is None:
+        out = torch.empty(labels.shape, dtype=dtype, device=labels.device)
+    _check_tensor(coef, "coef")
+    _check_tensor(out, "out")
+    ws, _ = _workspace(coef, stop_level, workspace)
+    c = Coords(labels.shape, coords)
+    code = lib().mgx_dequantize_recompose(labels.data_ptr(), coef.data_ptr(), out.data_ptr(), _dtype_code(coef),
+                                          labels.dim(), _dims(labels.shape), c.ptr, float(tol), int(stop_level),
+                                          float(c_linf), ws.data_ptr(), ws.numel() * ws.element_size(),
+                                          _stream(labels.device))
+    _check(code, "mgx_dequantize_recompose")
     return out
 
 

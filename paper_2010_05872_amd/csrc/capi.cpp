@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <functional>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -155,6 +156,8 @@ struct Emitter {
   hipStream_t st = nullptr;
   Tuning tn{};
   std::vector<RecordedOp<T>> *rec = nullptr;
+  // immediate mode only: called before and after each launch with (kind, level)
+  std::function<hipError_t(int, int)> before, after;
   int base = 0, step = 0, phase = 0;
   void begin_step(int s) {
     step = base + s;
@@ -165,7 +168,11 @@ struct Emitter {
       rec->push_back({kind, mode, step, phase++, name, level, a});
       return hipSuccess;
     }
-    return traced(name, level, st, [&] { return launch_op<T>(kind, mode, a, tn, st); });
+    hipError_t e;
+    if (before && (e = before(kind, level)) != hipSuccess) return e;
+    e = traced(name, level, st, [&] { return launch_op<T>(kind, mode, a, tn, st); });
+    if (e == hipSuccess && after) e = after(kind, level);
+    return e;
   }
 };
 
@@ -599,6 +606,8 @@ mgx_status quant_args(int ndim, const int64_t *dims, const double *const *coords
   }
   qa->first = stop;
   qa->nlev = L + 1 - stop;
+  qa->sel_lo = stop;
+  qa->sel_hi = L;
   for (int i = 0; i < qa->nlev; i++) qa->q[i] = 2.0 * tau[i];
   *plan = P;
   return MGX_OK;
@@ -611,6 +620,140 @@ struct StatsBuf {
 StatsBuf &stats_buf() {
   static StatsBuf *s = new StatsBuf();
   return *s;
+}
+
+// The corner box of level L-1 (the coarser levels' coefficients) as the
+// visited region of a quantization pass.
+void quant_box(const Plan *P, QuantArgs &qa) {
+  const int L = P->L;
+  int64_t b[3];
+  for (int k = 0; k < 3; k++) b[k] = P->real[k] ? (P->n[k] - 1) / 2 + 1 : 1;
+  auto magic = [](uint64_t d) -> uint64_t { return d < 2 ? 0 : (~(uint64_t)0) / d + 1; };
+  qa.box = 1;
+  qa.b1 = (int)b[1];
+  qa.b2 = (int)b[2];
+  qa.bn = b[0] * b[1] * b[2];
+  qa.bmag1 = magic((uint64_t)b[1]);
+  qa.bmag2 = magic((uint64_t)b[2]);
+  (void)L;
+}
+
+// ---- fused quantization: the finest level on a second stream ----
+// The finest level holds 7/8 of the coefficients and is complete after its
+// first kernel, while the coarser levels are many small latency-bound
+// launches; quantizing (or dequantizing) the finest level on a library
+// stream overlaps the two.  Results are those of the separate calls.
+struct SideStreams {
+  std::mutex mu;
+  std::vector<hipStream_t> st;
+  std::vector<hipEvent_t> ev;  // per device: fork and join events
+};
+SideStreams &side_streams() {
+  static SideStreams *s = new SideStreams();
+  return *s;
+}
+
+// Locks the side-stream state of the current device (held by the caller for
+// the whole enqueue sequence) and returns its stream and two events.
+mgx_status side_stream(std::unique_lock<std::mutex> &lk, hipStream_t *q, hipEvent_t *fork, hipEvent_t *join) {
+  SideStreams &S = side_streams();
+  lk = std::unique_lock<std::mutex>(S.mu);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MGX_ERR_HIP;
+  if ((int)S.st.size() <= dev) {
+    S.st.resize(dev + 1, nullptr);
+    S.ev.resize(2 * (dev + 1), nullptr);
+  }
+  if (!S.st[dev]) {
+    if (hipStreamCreateWithFlags(&S.st[dev], hipStreamNonBlocking) != hipSuccess) return MGX_ERR_HIP;
+    for (int i = 0; i < 2; i++)
+      if (hipEventCreateWithFlags(&S.ev[2 * dev + i], hipEventDisableTiming) != hipSuccess) return MGX_ERR_HIP;
+  }
+  *q = S.st[dev];
+  *fork = S.ev[2 * dev];
+  *join = S.ev[2 * dev + 1];
+  return MGX_OK;
+}
+
+template <typename T>
+mgx_status run_decompose_quantize(Plan *P, int stop, const T *u, T *umc, int32_t *labels, QuantArgs qa, char *ws,
+                                  const Layout &lay, const T *tab, hipStream_t st) {
+  const int L = P->L;
+  std::unique_lock<std::mutex> lk;
+  hipStream_t q;
+  hipEvent_t fork, join;
+  mgx_status s = side_stream(lk, &q, &fork, &join);
+  if (s) return s;
+  QuantArgs fine = qa, rest = qa;
+  fine.sel_lo = fine.sel_hi = L;
+  fine.max_blocks = MGX_SIDE_BLOCKS;
+  rest.sel_hi = L - 1;
+  if (L > 0) quant_box(P, rest);
+  bool forked = false;
+  // The finest level's coefficients are final once its first kernel ran;
+  // its quantization starts after the level's last kernel, when the stream
+  // turns to the small latency-bound levels.
+  auto fork_quantize = [&]() -> hipError_t {
+    forked = true;
+    hipError_t e = hipEventRecord(fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(q, fork, 0);
+    if (e == hipSuccess)
+      e = traced("quantize_finest", -1, q, [&] { return launch_quantize<T>(umc, labels, fine, false, q); });
+    if (e == hipSuccess) e = hipEventRecord(join, q);
+    return e;
+  };
+  Emitter<T> em;
+  em.st = st;
+  em.before = [&](int kind, int level) -> hipError_t {
+    (void)kind;
+    return (!forked && level < L) ? fork_quantize() : hipSuccess;
+  };
+  s = run_decompose<T>(P, stop, u, umc, ws, lay, tab, em);
+  if (s) return s;
+  if (!forked && fork_quantize() != hipSuccess) return MGX_ERR_HIP;
+  if (rest.sel_hi >= rest.sel_lo &&
+      traced("quantize_coarse", -1, st, [&] { return launch_quantize<T>(umc, labels, rest, false, st); }) !=
+          hipSuccess)
+    return MGX_ERR_HIP;
+  return hip_status(hipStreamWaitEvent(st, join, 0));
+}
+
+template <typename T>
+mgx_status run_dequantize_recompose(Plan *P, int stop, const int32_t *labels, T *umc, T *u, QuantArgs qa,
+                                    char *ws, const Layout &lay, const T *tab, hipStream_t st) {
+  const int L = P->L;
+  std::unique_lock<std::mutex> lk;
+  hipStream_t q;
+  hipEvent_t fork, join;
+  mgx_status s = side_stream(lk, &q, &fork, &join);
+  if (s) return s;
+  QuantArgs fine = qa, rest = qa;
+  fine.sel_lo = fine.sel_hi = L;
+  fine.max_blocks = MGX_SIDE_BLOCKS;
+  rest.sel_hi = L - 1;
+  if (L > 0) quant_box(P, rest);
+  // the coarse levels first (small; the recomposition starts with them),
+  // then the finest level beside the coarse recomposition
+  if (rest.sel_hi >= rest.sel_lo &&
+      traced("dequantize_coarse", -1, st, [&] { return launch_dequantize<T>(labels, umc, rest, st); }) != hipSuccess)
+    return MGX_ERR_HIP;
+  if (hipEventRecord(fork, st) != hipSuccess || hipStreamWaitEvent(q, fork, 0) != hipSuccess) return MGX_ERR_HIP;
+  if (traced("dequantize_finest", -1, q, [&] { return launch_dequantize<T>(labels, umc, fine, q); }) != hipSuccess ||
+      hipEventRecord(join, q) != hipSuccess)
+    return MGX_ERR_HIP;
+  bool joined = false;
+  Emitter<T> em;
+  em.st = st;
+  em.before = [&](int kind, int level) -> hipError_t {
+    (void)kind;
+    if (joined || level < L) return hipSuccess;
+    joined = true;  // first launch that reads finest-level coefficients
+    return hipStreamWaitEvent(st, join, 0);
+  };
+  s = run_recompose<T>(P, stop, umc, u, ws, lay, tab, em);
+  if (s) return s;
+  if (!joined) return hip_status(hipStreamWaitEvent(st, join, 0));
+  return MGX_OK;
 }
 
 // ---- batches of fields (multi-field launches in one captured graph) ----
@@ -898,7 +1041,7 @@ mgx_status run_batched(int nfields, const mgx_field *f, void *ws, size_t ws_byte
     if (g_batch_autotune.load()) {
       // candidate launch shapes of the stencil kernels; inputs must be ready
       if (hipStreamSynchronize(stream) != hipSuccess) return MGX_ERR_HIP;
-      const Tuning cand[] = {{2048, 8}, {512, 4}, {128, 2}, {8192, 8}};
+      const Tuning cand[] = {{2048, 8, 8}, {512, 4, 4}, {128, 2, 2}, {8192, 8, 4}};
       double best_ms = -1.0;
       for (const Tuning &tn : cand) {
         BatchEntry e;
@@ -1206,6 +1349,51 @@ int mgx_trace_read(mgx_kernel_time *out, int max) {
   int n = (int)agg.size() < max ? (int)agg.size() : max;
   for (int i = 0; i < n; i++) out[i] = agg[i];
   return n;
+}
+
+mgx_status mgx_decompose_quantize(const void *u, void *u_mc, int32_t *labels, mgx_dtype dtype, int ndim,
+                                  const int64_t *dims, const double *const *coords, double tol_linf, int stop_level,
+                                  double c_linf, void *workspace, size_t workspace_bytes, hipStream_t stream) {
+  Plan *P;
+  Layout lay;
+  const void *tab;
+  mgx_status s = prepare(u, u_mc, dtype, ndim, dims, coords, stop_level, workspace, workspace_bytes, &P, &lay, &tab);
+  if (s) return s;
+  if (!labels) return MGX_ERR_ARG;
+  const size_t cnt = (size_t)(P->n[0] * P->n[1] * P->n[2]);
+  if (overlaps(labels, cnt * 4, u_mc, cnt * elem_size(dtype)) || overlaps(labels, cnt * 4, u, cnt * elem_size(dtype)))
+    return MGX_ERR_ARG;
+  QuantArgs qa;
+  Plan *Pq;
+  if ((s = quant_args(ndim, dims, coords, tol_linf, stop_level, c_linf, &qa, &Pq))) return s;
+  if (dtype == MGX_F32)
+    return run_decompose_quantize<float>(P, stop_level, (const float *)u, (float *)u_mc, labels, qa,
+                                         (char *)workspace, lay, (const float *)tab, stream);
+  return run_decompose_quantize<double>(P, stop_level, (const double *)u, (double *)u_mc, labels, qa,
+                                        (char *)workspace, lay, (const double *)tab, stream);
+}
+
+mgx_status mgx_dequantize_recompose(const int32_t *labels, void *u_mc, void *u, mgx_dtype dtype, int ndim,
+                                    const int64_t *dims, const double *const *coords, double tol_linf,
+                                    int stop_level, double c_linf, void *workspace, size_t workspace_bytes,
+                                    hipStream_t stream) {
+  Plan *P;
+  Layout lay;
+  const void *tab;
+  mgx_status s = prepare(u_mc, u, dtype, ndim, dims, coords, stop_level, workspace, workspace_bytes, &P, &lay, &tab);
+  if (s) return s;
+  if (!labels) return MGX_ERR_ARG;
+  const size_t cnt = (size_t)(P->n[0] * P->n[1] * P->n[2]);
+  if (overlaps(labels, cnt * 4, u_mc, cnt * elem_size(dtype)) || overlaps(labels, cnt * 4, u, cnt * elem_size(dtype)))
+    return MGX_ERR_ARG;
+  QuantArgs qa;
+  Plan *Pq;
+  if ((s = quant_args(ndim, dims, coords, tol_linf, stop_level, c_linf, &qa, &Pq))) return s;
+  if (dtype == MGX_F32)
+    return run_dequantize_recompose<float>(P, stop_level, labels, (float *)u_mc, (float *)u, qa, (char *)workspace,
+                                           lay, (const float *)tab, stream);
+  return run_dequantize_recompose<double>(P, stop_level, labels, (double *)u_mc, (double *)u, qa,
+                                          (char *)workspace, lay, (const double *)tab, stream);
 }
 
 size_t mgx_batch_workspace_size(int nfields, const mgx_field *fields) {

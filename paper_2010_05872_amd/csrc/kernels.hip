@@ -1240,34 +1240,55 @@ __device__ __forceinline__ void quantize_body(const T *__restrict__ umc, int32_t
   const uint32_t N = (uint32_t)a.n;
   const uint32_t stride = (uint32_t)nb * 256u * 4u;
   for (uint32_t base = ((uint32_t)b * 256u + threadIdx.x) * 4u; base < N; base += stride) {
-    T v[4];
-    load4<T, VEC>(umc, base, N, v);
-    int32_t lab[4];
     int lev[4], absl[4];
+    bool sel[4];
+    int nsel = 0;
 #pragma unroll
     for (int e = 0; e < 4; e++) {
-      lev[e] = base + e < N ? elem_level(base + e, a) : a.first;
-      const double t = (double)v[e] / s_q[lev[e] - a.first];
+      const bool in = base + e < N;
+      lev[e] = in ? elem_level(base + e, a) : a.first;
+      sel[e] = in && lev[e] >= a.sel_lo && lev[e] <= a.sel_hi;
+      nsel += sel[e] ? 1 : 0;
       absl[e] = 0;
-      if (!(fabs(t) < 2147483647.0)) {
-        lab[e] = INT32_MIN;
-        if (base + e < N) {
-          if (isnan(t) || isinf(t))
-            my_nan++;
-          else
-            my_ovf++;
-        }
+    }
+    if (nsel > 0) {
+      T v[4];
+      if (nsel == 4) {
+        load4<T, VEC>(umc, base, N, v);
       } else {
-        lab[e] = (int32_t)rint(t);
-        absl[e] = lab[e] < 0 ? -lab[e] : lab[e];
+#pragma unroll
+        for (int e = 0; e < 4; e++) v[e] = sel[e] ? umc[base + e] : T(0);
+      }
+      int32_t lab[4];
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        const double t = (double)v[e] / s_q[lev[e] - a.first];
+        if (!(fabs(t) < 2147483647.0)) {
+          lab[e] = INT32_MIN;
+          if (sel[e]) {
+            if (isnan(t) || isinf(t))
+              my_nan++;
+            else
+              my_ovf++;
+          }
+        } else {
+          lab[e] = (int32_t)rint(t);
+          absl[e] = sel[e] ? (lab[e] < 0 ? -lab[e] : lab[e]) : 0;
+        }
+      }
+      if (nsel == 4) {
+        store4i(labels, base, N, lab, VEC);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; e++)
+          if (sel[e]) labels[base + e] = lab[e];
       }
     }
-    store4i(labels, base, N, lab, VEC);
     if (STATS) {
       // per-level maxima: reduce each distinct level present in the wave
 #pragma unroll
       for (int e = 0; e < 4; e++) {
-        const bool in = base + e < N;
+        const bool in = sel[e];
         unsigned long long todo = __ballot(in);
         while (todo) {
           const int leader = __ffsll((long long)todo) - 1;
@@ -1314,15 +1335,34 @@ __device__ __forceinline__ void dequantize_body(const int32_t *__restrict__ labe
   const uint32_t N = (uint32_t)a.n;
   const uint32_t stride = (uint32_t)nb * 256u * 4u;
   for (uint32_t base = ((uint32_t)b * 256u + threadIdx.x) * 4u; base < N; base += stride) {
-    int32_t lab[4];
-    load4i(labels, base, N, lab, VEC);
-    T v[4];
+    int lev[4];
+    bool sel[4];
+    int nsel = 0;
 #pragma unroll
     for (int e = 0; e < 4; e++) {
-      const int lev = base + e < N ? elem_level(base + e, a) : a.first;
-      v[e] = (T)((double)lab[e] * s_q[lev - a.first]);
+      const bool in = base + e < N;
+      lev[e] = in ? elem_level(base + e, a) : a.first;
+      sel[e] = in && lev[e] >= a.sel_lo && lev[e] <= a.sel_hi;
+      nsel += sel[e] ? 1 : 0;
     }
-    store4<T, VEC>(umc, base, N, v);
+    if (nsel == 0) continue;
+    int32_t lab[4];
+    if (nsel == 4) {
+      load4i(labels, base, N, lab, VEC);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; e++) lab[e] = sel[e] ? labels[base + e] : 0;
+    }
+    T v[4];
+#pragma unroll
+    for (int e = 0; e < 4; e++) v[e] = (T)((double)lab[e] * s_q[lev[e] - a.first]);
+    if (nsel == 4) {
+      store4<T, VEC>(umc, base, N, v);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; e++)
+        if (sel[e]) umc[base + e] = v[e];
+    }
   }
 }
 
@@ -1330,6 +1370,64 @@ template <typename T, bool VEC>
 __global__ void __launch_bounds__(256) k_dequantize(const int32_t *__restrict__ labels, T *__restrict__ umc,
                                                     QuantArgs a) {
   dequantize_body<T, VEC>(labels, umc, a, blockIdx.x, gridDim.x);
+}
+
+// Quantization restricted to the corner box b0 x b1 x b2 of the array (the
+// coarser levels' coefficients): every element of the box is visited once,
+// one element per thread and iteration.
+template <typename T>
+__device__ __forceinline__ void quantize_box_body(const T *__restrict__ umc, int32_t *__restrict__ labels,
+                                                  const QuantArgs &a, const int b, const int nb) {
+  __shared__ double s_q[kMaxLevelsK];
+  if (threadIdx.x < kMaxLevelsK) s_q[threadIdx.x] = a.q[threadIdx.x];
+  __syncthreads();
+  const uint32_t B = (uint32_t)a.bn;
+  for (uint32_t i = (uint32_t)b * 256u + threadIdx.x; i < B; i += (uint32_t)nb * 256u) {
+    const uint32_t row = (uint32_t)__umul64hi((uint64_t)i, a.bmag2);
+    const uint32_t x = i - row * (uint32_t)a.b2;
+    const uint32_t z = a.b1 == 1 ? row : (uint32_t)__umul64hi((uint64_t)row, a.bmag1);
+    const uint32_t y = row - z * (uint32_t)a.b1;
+    int l = pos_level(x, a.off[2], a.first);
+    l = max(l, pos_level(y, a.off[1], a.first));
+    l = max(l, pos_level(z, a.off[0], a.first));
+    if (l < a.sel_lo || l > a.sel_hi) continue;
+    const uint32_t idx = (z * (uint32_t)a.n1 + y) * (uint32_t)a.n2 + x;
+    const double t = (double)umc[idx] / s_q[l - a.first];
+    labels[idx] = !(fabs(t) < 2147483647.0) ? INT32_MIN : (int32_t)rint(t);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void dequantize_box_body(const int32_t *__restrict__ labels, T *__restrict__ umc,
+                                                    const QuantArgs &a, const int b, const int nb) {
+  __shared__ double s_q[kMaxLevelsK];
+  if (threadIdx.x < kMaxLevelsK) s_q[threadIdx.x] = a.q[threadIdx.x];
+  __syncthreads();
+  const uint32_t B = (uint32_t)a.bn;
+  for (uint32_t i = (uint32_t)b * 256u + threadIdx.x; i < B; i += (uint32_t)nb * 256u) {
+    const uint32_t row = (uint32_t)__umul64hi((uint64_t)i, a.bmag2);
+    const uint32_t x = i - row * (uint32_t)a.b2;
+    const uint32_t z = a.b1 == 1 ? row : (uint32_t)__umul64hi((uint64_t)row, a.bmag1);
+    const uint32_t y = row - z * (uint32_t)a.b1;
+    int l = pos_level(x, a.off[2], a.first);
+    l = max(l, pos_level(y, a.off[1], a.first));
+    l = max(l, pos_level(z, a.off[0], a.first));
+    if (l < a.sel_lo || l > a.sel_hi) continue;
+    const uint32_t idx = (z * (uint32_t)a.n1 + y) * (uint32_t)a.n2 + x;
+    umc[idx] = (T)((double)labels[idx] * s_q[l - a.first]);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_quantize_box(const T *__restrict__ umc, int32_t *__restrict__ labels,
+                                                      QuantArgs a) {
+  quantize_box_body<T>(umc, labels, a, blockIdx.x, gridDim.x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_dequantize_box(const int32_t *__restrict__ labels, T *__restrict__ umc,
+                                                        QuantArgs a) {
+  dequantize_box_body<T>(labels, umc, a, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1363,8 +1461,10 @@ static bool tile_grid(int c0, int c1, int c2, int TX, int TY, int *ntx, int *nty
   // large levels keep z-chunks of >= min_zchunk coarse planes (halo re-reads
   // stay small); small levels take one coarse plane per workgroup (latency
   // bound)
-  const bool large = (int64_t)c0 * c1 * c2 >= (1 << 20);
-  const int mz = tn.min_zchunk > 0 ? tn.min_zchunk : 1;
+  const int64_t cn = (int64_t)c0 * c1 * c2;
+  const bool large = cn >= (1 << 20);
+  const int mz0 = cn >= (1 << 24) ? tn.min_zchunk : tn.mid_zchunk;
+  const int mz = mz0 > 0 ? mz0 : 1;
   int maxz = large ? (c0 / mz > 0 ? c0 / mz : 1) : c0;
   if (want > maxz) want = maxz;
   if (want < 1) want = 1;
@@ -1516,7 +1616,14 @@ static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
 template <typename T>
 hipError_t launch_quantize(const T *umc, int32_t *labels, QuantArgs a, bool stats, hipStream_t st) {
+  if (a.box && !stats) {
+    int64_t g = (a.bn + 255) / 256;
+    hipLaunchKernelGGL((k_quantize_box<T>), dim3((unsigned)(g < 1 ? 1 : (g > 8192 ? 8192 : g))), dim3(256), 0, st,
+                       umc, labels, a);
+    return hipGetLastError();
+  }
   dim3 grid(quant_grid(a.n));
+  if (a.max_blocks > 0 && grid.x > (unsigned)a.max_blocks) grid.x = (unsigned)a.max_blocks;
   const bool vec = aligned16(umc) && aligned16(labels);
   if (stats) {
     if (vec)
@@ -1534,7 +1641,14 @@ hipError_t launch_quantize(const T *umc, int32_t *labels, QuantArgs a, bool stat
 
 template <typename T>
 hipError_t launch_dequantize(const int32_t *labels, T *umc, QuantArgs a, hipStream_t st) {
+  if (a.box) {
+    int64_t g = (a.bn + 255) / 256;
+    hipLaunchKernelGGL((k_dequantize_box<T>), dim3((unsigned)(g < 1 ? 1 : (g > 8192 ? 8192 : g))), dim3(256), 0,
+                       st, labels, umc, a);
+    return hipGetLastError();
+  }
   dim3 grid(quant_grid(a.n));
+  if (a.max_blocks > 0 && grid.x > (unsigned)a.max_blocks) grid.x = (unsigned)a.max_blocks;
   if (aligned16(umc) && aligned16(labels))
     hipLaunchKernelGGL((k_dequantize<T, true>), grid, dim3(256), 0, st, labels, umc, a);
   else
@@ -1559,6 +1673,34 @@ constexpr int kTailG1 = kTailM * kTailM * kTailC;  // after the x pass
 constexpr int kTailG2 = kTailM * kTailC * kTailC;  // after the y pass
 constexpr int kTailF = kTailC * kTailC * kTailC;   // a coarse box
 constexpr int kTailLds = kTailV + kTailG1 + kTailG2 + 2 * kTailF;
+// per level and axis: wl, wr (m each), w5 (5c), mult, invd, qsup (c each)
+constexpr int kTailTab = 2 * kTailM + 8 * kTailC;
+
+// Copies the tables of the tail's levels into LDS (they are read inside
+// dependent chains, e.g. every step of a line solve) and returns views of
+// them.  Ends with a workgroup barrier.
+template <typename T>
+__device__ __forceinline__ void tail_tables(const TailArgs<T> &a, T *sT, TailAxis<T> (&ax)[kTailMax][3]) {
+  for (int i = 0; i < a.nlev; i++)
+    for (int k = 0; k < 3; k++) {
+      const TailAxis<T> &g = a.ax[i][k];
+      T *b = sT + (i * 3 + k) * kTailTab;
+      const int m = g.m, c = g.c;
+      for (int q = threadIdx.x; q < 2 * m + 8 * c; q += kTailThreads) {
+        T v;
+        if (q < m) v = g.wl[q];
+        else if (q < 2 * m) v = g.wr[q - m];
+        else if (q < 2 * m + 5 * c) v = g.w5[q - 2 * m];
+        else if (q < 2 * m + 6 * c) v = g.mult[q - 2 * m - 5 * c];
+        else if (q < 2 * m + 7 * c) v = g.invd[q - 2 * m - 6 * c];
+        else v = g.qsup[q - 2 * m - 7 * c];
+        b[q] = v;
+      }
+      if (threadIdx.x == 0)
+        ax[i][k] = TailAxis<T>{b, b + m, b + 2 * m, b + 2 * m + 5 * c, b + 2 * m + 6 * c, b + 2 * m + 7 * c, m, c};
+    }
+  __syncthreads();
+}
 
 __device__ __forceinline__ int lcp(int j, int c) { return (j & 1) ? c + (j >> 1) : (j >> 1); }
 
@@ -1672,8 +1814,11 @@ __device__ __forceinline__ void tail_solves(const TailAxis<T> (&ax)[3], T *F) {
 template <typename T>
 __device__ __forceinline__ void tail_dec_body(const TailArgs<T> &a) {
   __shared__ T sm[kTailLds];
+  __shared__ T sT[kTailMax * 3 * kTailTab];
   T *const sV = sm, *const g1 = sV + kTailV, *const g2 = g1 + kTailG1, *const fA = g2 + kTailG2, *const fB = fA + kTailF;
   const int tid = threadIdx.x;
+  __shared__ TailAxis<T> tabs[kTailMax][3];  // views of sT
+  tail_tables<T>(a, sT, tabs);
   {  // the level-lt box into LDS (all loads issued before the first wait)
     const int m0 = a.ax[0][0].m, m1 = a.ax[0][1].m, m2 = a.ax[0][2].m, n = m0 * m1 * m2;
     constexpr int R = (kTailV + kTailThreads - 1) / kTailThreads;
@@ -1691,7 +1836,7 @@ __device__ __forceinline__ void tail_dec_body(const TailArgs<T> &a) {
   }
   const T *V = sV;
   for (int i = 0; i < a.nlev; i++) {
-    const TailAxis<T>(&ax)[3] = a.ax[i];
+    const TailAxis<T>(&ax)[3] = tabs[i];
     const int m1 = ax[1].m, m2 = ax[2].m, c0 = ax[0].c, c1 = ax[1].c, c2 = ax[2].c;
     const int m0 = ax[0].m;
     // coefficients of the level's non-nodal nodes, at level-centric positions
@@ -1720,12 +1865,15 @@ __device__ __forceinline__ void tail_dec_body(const TailArgs<T> &a) {
 template <typename T>
 __device__ __forceinline__ void tail_rec_body(const TailArgs<T> &a) {
   __shared__ T sm[kTailLds];
+  __shared__ T sT[kTailMax * 3 * kTailTab];
   T *const sZ = sm, *const g1 = sZ + kTailV, *const g2 = g1 + kTailG1, *const fA = g2 + kTailG2, *const vB = fA + kTailF;
   const int tid = threadIdx.x;
+  __shared__ TailAxis<T> tabs[kTailMax][3];  // views of sT
+  tail_tables<T>(a, sT, tabs);
   const T *U = a.umc_r;
   // nodal values of the level below: the stop box of u_mc first
   {
-    const TailAxis<T>(&ax)[3] = a.ax[a.nlev - 1];
+    const TailAxis<T>(&ax)[3] = tabs[a.nlev - 1];
     const int c0 = ax[0].c, c1 = ax[1].c, c2 = ax[2].c;
     for (int q = tid; q < c0 * c1 * c2; q += kTailThreads) {
       const int X = q % c2, r = q / c2, Y = r % c1, Z = r / c1;
@@ -1733,7 +1881,7 @@ __device__ __forceinline__ void tail_rec_body(const TailArgs<T> &a) {
     }
   }
   for (int i = 0; i < a.nlev; i++) {
-    const TailAxis<T>(&ax)[3] = a.ax[a.nlev - 1 - i];
+    const TailAxis<T>(&ax)[3] = tabs[a.nlev - 1 - i];
     const int m0 = ax[0].m, m1 = ax[1].m, m2 = ax[2].m, c0 = ax[0].c, c1 = ax[1].c, c2 = ax[2].c;
     // the level's coefficients (zero at nodal nodes) into LDS, all loads
     // issued before the first wait

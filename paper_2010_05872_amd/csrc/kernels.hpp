@@ -137,6 +137,12 @@ struct QuantArgs {
   uint64_t mag1, mag2;        // ceil(2^64 / n1), ceil(2^64 / n2): exact 32-bit division
   int off[3];                 // log2(n_k - 1) - L per axis (0 for padded axes)
   int first, nlev;            // levels first .. first+nlev-1
+  int sel_lo, sel_hi;         // only elements of levels sel_lo .. sel_hi are read and written
+  int box;                    // nonzero: visit only the corner box b0 x b1 x b2 of the array
+  int b1, b2;
+  int64_t bn;                 // b0 * b1 * b2
+  uint64_t bmag1, bmag2;      // ceil(2^64 / b1), ceil(2^64 / b2)
+  int max_blocks;             // > 0: at most this many workgroups (work running beside other kernels)
   double q[kMaxLevelsK];      // bin width per level
   int *stats_max;             // [nlev] device
   unsigned long long *stats_ovf, *stats_nan;
@@ -145,9 +151,25 @@ struct QuantArgs {
 // Launch shape of the tiled stencil kernels: the workgroups a launch aims
 // for, and the fewest coarse planes one workgroup marches through on large
 // levels (smaller levels take one coarse plane per workgroup).
+// Workgroups of a (de)quantization pass that runs on the library's second
+// stream beside the coarse levels (a small grid leaves compute units free
+// for the latency-bound kernels of the main stream).
+#ifndef MGX_SIDE_BLOCKS
+#define MGX_SIDE_BLOCKS 512
+#endif
+#ifndef MGX_TUNE_TARGET
+#define MGX_TUNE_TARGET 2048
+#endif
+#ifndef MGX_TUNE_MINZ
+#define MGX_TUNE_MINZ 8
+#endif
+#ifndef MGX_TUNE_MIDZ
+#define MGX_TUNE_MIDZ 8
+#endif
 struct Tuning {
-  int target_blocks = 2048;
-  int min_zchunk = 8;
+  int target_blocks = MGX_TUNE_TARGET;
+  int min_zchunk = MGX_TUNE_MINZ;  // levels of at least 2^24 coarse nodes
+  int mid_zchunk = MGX_TUNE_MIDZ;  // levels of 2^20 .. 2^24 coarse nodes
 };
 
 template <typename T> hipError_t launch_load_vector(StencilArgs<T> a, bool dec, hipStream_t st, Tuning tn = {});
