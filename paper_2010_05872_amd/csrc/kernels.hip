@@ -28,6 +28,12 @@
 #ifndef MGX_STENCIL_DEPTH
 #define MGX_STENCIL_DEPTH 2
 #endif
+#ifndef MGX_INTERP_AHEAD
+#define MGX_INTERP_AHEAD 2
+#endif
+#ifndef MGX_REC_DEPTH
+#define MGX_REC_DEPTH 4
+#endif
 #ifndef MGX_STENCIL_WAVES
 #define MGX_STENCIL_WAVES 4
 #endif
@@ -162,7 +168,7 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
   constexpr int NE = (HR * W + NT - 1) / NT;  // region elements per thread
   constexpr int NV = DEC ? 4 : 2;             // ring of planes kept in LDS
   constexpr int AHEAD = DEC ? 2 : 1;          // plane committed at iteration j is j + AHEAD
-  constexpr int DEPTH = MGX_STENCIL_DEPTH;    // register buffers in flight
+  constexpr int DEPTH = DEC ? MGX_STENCIL_DEPTH : MGX_REC_DEPTH;  // register buffers in flight
   constexpr int XRS = NT / GW;                // x-restriction: rows per sweep
   constexpr int XR = (HR + XRS - 1) / XRS;    // x-restriction: rows per thread
   constexpr int NOUT = (GH * GW + NT - 1) / NT;  // y-restriction outputs per thread
@@ -767,6 +773,7 @@ __device__ __forceinline__ void interp_add_body(const InterpArgs<T> a, const int
   constexpr int NB = (BH * BW + NT - 1) / NT;
   constexpr int NN = (NH * NW + NT - 1) / NT;
   constexpr int NR = 4;  // nodal ring slots
+  constexpr int AH = MGX_INTERP_AHEAD;  // steps of coefficients and nodal planes in flight
   __shared__ T sN[NR][NH * NW];
 
   const int tid = threadIdx.x;
@@ -903,27 +910,30 @@ __device__ __forceinline__ void interp_add_body(const InterpArgs<T> a, const int
         if (f & 8u) st_once(oo, o0 + outRow + ES, cv[k][6] + (wzl * e11 + wzr * f11));
       }
     }
-    // loads for step J+2 after every store of this step (partial waits later)
-    fetch_coef(J + 2, cv);
-    fetch_nodal(J + 4, nv);
+    // loads for step J+AH after every store of this step (partial waits later)
+    fetch_coef(J + AH, cv);
+    fetch_nodal(J + 2 + AH, nv);
   };
 
-  T nv0[NN], nv1[NN];
-  T cv0[NB][7], cv1[NB][7];
-  fetch_nodal(Z0, nv0);
-  commit_nodal(Z0 % NR, nv0);
-  fetch_nodal(Z0 + 1, nv0);
-  commit_nodal((Z0 + 1) % NR, nv0);
-  fetch_nodal(Z0 + 2, nv0);
-  fetch_nodal(Z0 + 3, nv1);
-  fetch_coef(Z0, cv0);
-  fetch_coef(Z0 + 1, cv1);
-  int J = Z0;
-  for (; J + 1 < Z1; J += 2) {
-    step(J, cv0, nv0);
-    step(J + 1, cv1, nv1);
+  T nv[AH][NN];
+  T cv[AH][NB][7];
+  fetch_nodal(Z0, nv[0]);
+  commit_nodal(Z0 % NR, nv[0]);
+  fetch_nodal(Z0 + 1, nv[0]);
+  commit_nodal((Z0 + 1) % NR, nv[0]);
+#pragma unroll
+  for (int k = 0; k < AH; k++) {
+    fetch_nodal(Z0 + 2 + k, nv[k]);
+    fetch_coef(Z0 + k, cv[k]);
   }
-  if (J < Z1) step(J, cv0, nv0);
+  int J = Z0;
+  for (; J + AH - 1 < Z1; J += AH) {
+#pragma unroll
+    for (int k = 0; k < AH; k++) step(J + k, cv[k], nv[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < AH - 1; k++)
+    if (J + k < Z1) step(J + k, cv[k], nv[k]);
 }
 
 template <typename T, int TX, int TY, int NT>

@@ -152,10 +152,11 @@ struct QuantArgs {
 // for, and the fewest coarse planes one workgroup marches through on large
 // levels (smaller levels take one coarse plane per workgroup).
 // Workgroups of a (de)quantization pass that runs on the library's second
-// stream beside the coarse levels (a small grid leaves compute units free
-// for the latency-bound kernels of the main stream).
+// stream beside the coarse levels; 0: the pass's full grid (a capped grid
+// leaves compute units to the main stream but makes the pass the longer
+// branch, measured slower at every cap tried).
 #ifndef MGX_SIDE_BLOCKS
-#define MGX_SIDE_BLOCKS 512
+#define MGX_SIDE_BLOCKS 0
 #endif
 #ifndef MGX_TUNE_TARGET
 #define MGX_TUNE_TARGET 2048
