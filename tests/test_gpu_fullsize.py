@@ -1,0 +1,124 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times (default tuning, caller-provided workspace).
+
+513^3 fp32 (turbulence spectrum): the whole decomposition (stop levels 0 and
+4), the recomposition of the same coefficients and the quantization labels
+against the oracle; the L-infinity bound end to end at three tolerances.
+
+257x1025x1025 fp32 on the tanh-stretched axis (too large for the oracle in a
+test): the finest level's coefficients at sampled nodes against their
+definition (value minus the multilinear interpolant of its nodal corners,
+computed here in FP64), the round trip, and the L-infinity bound.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2010_05872_amd as mgx  # noqa: E402
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def field513():
+    u = workloads.turbulence_field(513, device="cuda", dtype=torch.float32)
+    torch.cuda.synchronize()
+    return u
+
+
+@pytest.mark.parametrize("stop", [0, 4])
+def test_513_fp32_decompose_recompose_against_oracle(field513, stop):
+    _say(f"[full] 513^3 fp32 stop={stop}")
+    u = field513
+    ws = torch.empty(mgx.workspace_size(mgx.MGX_F32, u.shape, stop), dtype=torch.uint8, device="cuda")
+    g = mgx.decompose(u, None, stop, out=torch.empty_like(u), workspace=ws)
+    torch.cuda.synchronize()
+    u64 = u.double().cpu().numpy()
+    scale = np.abs(u64).max()
+    ref = oracle.to_level_centric(oracle.decompose(u64, None, stop), stop)
+    g64 = g.double().cpu().numpy()
+    err = np.abs(g64 - ref).max()
+    _say(f"  decompose max err / max|u| = {err / scale:.3e}")
+    assert err <= 1e-5 * scale
+    del ref
+    r = mgx.recompose(g, None, stop, out=torch.empty_like(u), workspace=ws)
+    torch.cuda.synchronize()
+    rref = oracle.recompose(oracle.from_level_centric(g64, stop), None, stop)
+    r64 = r.double().cpu().numpy()
+    rerr = np.abs(r64 - rref).max()
+    _say(f"  recompose max err / max|u| = {rerr / scale:.3e}")
+    assert rerr <= 1e-5 * scale
+    assert np.abs(r64 - u64).max() <= 1e-5 * scale
+    if stop == 0:
+        # labels from identical coefficients, bit-exact
+        tol = 1e-3 * float(u64.max() - u64.min())
+        lab = mgx.quantize(g, tol, None, stop)
+        torch.cuda.synchronize()
+        rl, code = oracle.quantize(oracle.from_level_centric(g64, stop), tol, None, stop)
+        assert code == 0
+        assert np.array_equal(lab.cpu().numpy(), oracle.to_level_centric(rl, stop))
+
+
+@pytest.mark.parametrize("rel", [1e-2, 1e-3, 1e-4])
+def test_513_fp32_linf_bound(field513, rel):
+    _say(f"[full] 513^3 fp32 L-inf at {rel:g} * range")
+    u = field513
+    tol = rel * float((u.max() - u.min()).item())
+    for stop in (0, 4):
+        g, lab = mgx.decompose_quantize(u, tol, None, stop)
+        r = mgx.dequantize_recompose(lab, tol, torch.float32, None, stop)
+        err = (r.double() - u.double()).abs().max().item()
+        assert err <= tol, (stop, err / tol)
+
+
+def test_config3_properties():
+    _say("[full] 257x1025x1025 fp32 tanh")
+    u, coords = workloads.layered_lognormal_field(device="cuda")
+    torch.cuda.synchronize()
+    shape = tuple(u.shape)
+    g = mgx.decompose(u, coords)
+    torch.cuda.synchronize()
+    uh = u.cpu().numpy().astype(np.float64)
+    gh = g.cpu().numpy()
+    scale = np.abs(uh).max()
+    X = [np.asarray(coords[0], dtype=np.float64), np.arange(shape[1], dtype=np.float64),
+         np.arange(shape[2], dtype=np.float64)]
+    c = [(n + 1) // 2 for n in shape]  # coarse counts of the finest step
+    rng = np.random.default_rng(11)
+    checked = 0
+    while checked < 20000:
+        i = [int(rng.integers(0, n)) for n in shape]
+        if not any(v & 1 for v in i):
+            continue
+        pred = 0.0
+        corners = [[]]
+        for k in range(3):
+            if i[k] & 1:
+                wl = (X[k][i[k] + 1] - X[k][i[k]]) / (X[k][i[k] + 1] - X[k][i[k] - 1])
+                opts = [(i[k] - 1, wl), (i[k] + 1, 1.0 - wl)]
+            else:
+                opts = [(i[k], 1.0)]
+            corners = [cc + [o] for cc in corners for o in opts]
+        for cc in corners:
+            w = cc[0][1] * cc[1][1] * cc[2][1]
+            pred += w * uh[cc[0][0], cc[1][0], cc[2][0]]
+        want = uh[i[0], i[1], i[2]] - pred
+        pos = [c[k] + (i[k] - 1) // 2 if i[k] & 1 else i[k] // 2 for k in range(3)]
+        assert abs(float(gh[pos[0], pos[1], pos[2]]) - want) <= 1e-5 * scale, (i, gh[tuple(pos)], want)
+        checked += 1
+    r = mgx.recompose(g, coords)
+    assert (r.double() - u.double()).abs().max().item() <= 1e-5 * scale
+    tol = 1e-3 * float((u.max() - u.min()).item())
+    g2, lab = mgx.decompose_quantize(u, tol, coords)
+    r2 = mgx.dequantize_recompose(lab, tol, torch.float32, coords)
+    assert (r2.double() - u.double()).abs().max().item() <= tol
