@@ -116,11 +116,13 @@ mgx_status mgx_recompose(const void *u_mc, void *u, mgx_dtype dtype, int ndim,
                          const int64_t *dims, const double *const *coords, int stop_level,
                          void *workspace, size_t workspace_bytes, hipStream_t stream);
 
-/* mgx_decompose followed by mgx_quantize (no statistics), with the same
- * results.  The finest level's coefficients (7/8 of them) are final after
- * its first kernel; the library quantizes them on a second stream of its
- * own while the coarser levels run on `stream`, which waits for that work
- * before the call's last operation.  labels must not overlap u or u_mc.
+/* mgx_decompose followed by mgx_quantize (no statistics) in one call, with
+ * the same results.  A build with MGX_FUSED_OVERLAP quantizes the finest
+ * level's coefficients (7/8 of them, final after that level's kernels) on a
+ * second stream of the library while the coarser levels run on `stream`,
+ * which waits for that work before the call's last operation; measured
+ * slower than the sequence on MI355X, so the default build runs the two in
+ * sequence on `stream`.  labels must not overlap u or u_mc.
  * Errors as mgx_decompose and mgx_quantize (MGX_ERR_TOL). */
 mgx_status mgx_decompose_quantize(const void *u, void *u_mc, int32_t *labels, mgx_dtype dtype, int ndim,
                                   const int64_t *dims, const double *const *coords, double tol_linf,
@@ -128,8 +130,9 @@ mgx_status mgx_decompose_quantize(const void *u, void *u_mc, int32_t *labels, mg
                                   hipStream_t stream);
 
 /* mgx_dequantize(labels) into u_mc followed by mgx_recompose(u_mc) into u,
- * with the same results; the finest level is dequantized on the library's
- * second stream while the coarser levels are recomposed. */
+ * with the same results (with MGX_FUSED_OVERLAP the finest level is
+ * dequantized on the library's second stream while the coarser levels are
+ * recomposed). */
 mgx_status mgx_dequantize_recompose(const int32_t *labels, void *u_mc, void *u, mgx_dtype dtype, int ndim,
                                     const int64_t *dims, const double *const *coords, double tol_linf,
                                     int stop_level, double c_linf, void *workspace, size_t workspace_bytes,

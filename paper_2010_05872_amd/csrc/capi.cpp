@@ -675,9 +675,24 @@ mgx_status side_stream(std::unique_lock<std::mutex> &lk, hipStream_t *q, hipEven
   return MGX_OK;
 }
 
+// Overlap of the finest level's (de)quantization with the coarse levels on
+// a second stream: measured slower than running the two in sequence on this
+// part (the side pass takes every compute unit and the latency-bound coarse
+// kernels wait for slots), so off by default.
+#ifndef MGX_FUSED_OVERLAP
+#define MGX_FUSED_OVERLAP 0
+#endif
+
 template <typename T>
 mgx_status run_decompose_quantize(Plan *P, int stop, const T *u, T *umc, int32_t *labels, QuantArgs qa, char *ws,
                                   const Layout &lay, const T *tab, hipStream_t st) {
+  if (!MGX_FUSED_OVERLAP) {
+    Emitter<T> em;
+    em.st = st;
+    mgx_status s = run_decompose<T>(P, stop, u, umc, ws, lay, tab, em);
+    if (s) return s;
+    return hip_status(traced("quantize", -1, st, [&] { return launch_quantize<T>(umc, labels, qa, false, st); }));
+  }
   const int L = P->L;
   std::unique_lock<std::mutex> lk;
   hipStream_t q;
@@ -721,6 +736,13 @@ mgx_status run_decompose_quantize(Plan *P, int stop, const T *u, T *umc, int32_t
 template <typename T>
 mgx_status run_dequantize_recompose(Plan *P, int stop, const int32_t *labels, T *umc, T *u, QuantArgs qa,
                                     char *ws, const Layout &lay, const T *tab, hipStream_t st) {
+  if (!MGX_FUSED_OVERLAP) {
+    if (traced("dequantize", -1, st, [&] { return launch_dequantize<T>(labels, umc, qa, st); }) != hipSuccess)
+      return MGX_ERR_HIP;
+    Emitter<T> em;
+    em.st = st;
+    return run_recompose<T>(P, stop, umc, u, ws, lay, tab, em);
+  }
   const int L = P->L;
   std::unique_lock<std::mutex> lk;
   hipStream_t q;

@@ -28,6 +28,9 @@
 #ifndef MGX_STENCIL_DEPTH
 #define MGX_STENCIL_DEPTH 2
 #endif
+#ifndef MGX_INTERP_PLANE
+#define MGX_INTERP_PLANE 1
+#endif
 #ifndef MGX_INTERP_AHEAD
 #define MGX_INTERP_AHEAD 2
 #endif
@@ -942,6 +945,99 @@ __global__ void __launch_bounds__(NT) k_interp_add(InterpArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------
+// k_interp_plane: the interpolate-add step with one coarse plane J per
+// workgroup (fine planes 2J and 2J+1 of one tile).  Consecutive workgroups
+// (on the same XCD after the remap) take neighbouring tiles of the same
+// plane, so the stores of the chip advance through memory as one compact
+// front instead of one front per z-marching workgroup.  Each thread owns one
+// 2x2 block of fine nodes; all loads are issued before the first wait.
+// ---------------------------------------------------------------------------
+template <typename T, int TX, int TY, int NTP>
+__device__ __forceinline__ void interp_plane_body(const InterpArgs<T> a, const int lb) {
+  constexpr int NW = TX + 2, NH = TY + 2, BW = TX + 1;
+  constexpr int NNP = (2 * NH * NW + NTP - 1) / NTP;  // nodal loads per thread (planes J, J+1)
+  constexpr int ES = (int)sizeof(T);
+  __shared__ T sN[2][NH * NW];
+  const int tid = threadIdx.x;
+  const int m0 = a.ax[0].m, m1 = a.ax[1].m, m2 = a.ax[2].m;
+  const int c0 = a.ax[0].c, c1 = a.ax[1].c, c2 = a.ax[2].c;
+  const int tx = lb % a.ntx;
+  const int t2 = lb / a.ntx;
+  const int ty = t2 % a.nty;
+  const int J = t2 / a.nty;
+  const int X0 = tx * TX, X1 = (tx == a.ntx - 1) ? c2 : X0 + TX;
+  const int Y0 = ty * TY, Y1 = (ty == a.nty - 1) ? c1 : Y0 + TY;
+  const int ncx = min(X1 - X0 + 1, c2 - X0), ncy = min(Y1 - Y0 + 1, c1 - Y0);
+  const int fq = min(2 * X1, m2) - 2 * X0;
+  const int fr = min(2 * Y1, m1) - 2 * Y0;
+  const bool odd_in = 2 * J + 1 < m0;
+  // nodal planes J and J+1 (zeros outside the box)
+  T nv[NNP];
+#pragma unroll
+  for (int k = 0; k < NNP; k++) {
+    const int idx = tid + NTP * k;
+    const int p = idx / (NH * NW), rem = idx - p * (NH * NW);
+    const int r = rem / NW, q = rem - r * NW;
+    const int Jp = J + p;
+    const bool ok = idx < 2 * NH * NW && r < ncy && q < ncx && Jp < c0;
+    const T *src = a.nodal + (int64_t)(ok ? Jp : 0) * a.np0;
+    const T x = ld_at(src, (uint32_t)(ok ? ((Y0 + r) * (int)a.np1 + X0 + q) * ES : 0));
+    nv[k] = ok ? x : T(0);
+  }
+  // this thread's 2x2 block and its coefficients
+  const int ba = tid / BW, bb = tid - ba * BW;
+  const bool blk = ba < TY + 1;
+  const bool r0ok = blk && 2 * ba < fr, r1ok = blk && 2 * ba + 1 < fr;
+  const bool q0ok = 2 * bb < fq, q1ok = 2 * bb + 1 < fq;
+  const bool inbox = r0ok && q0ok;
+  const int rE = (int)((Y0 + (inbox ? ba : 0)) * a.up1) * ES;
+  const int rO = r1ok && inbox ? rE + (int)(c1 * a.up1) * ES : rE;
+  const int cE = (X0 + (inbox ? bb : 0)) * ES;
+  const int cO = q1ok && inbox ? cE + c2 * ES : cE;
+  const T *be = a.umc + (int64_t)J * a.up0;
+  const T *bo = a.umc + (int64_t)(odd_in ? c0 + J : J) * a.up0;
+  const T cv0 = ld_at(be, (uint32_t)(rE + cO)), cv1 = ld_at(be, (uint32_t)(rO + cE)), cv2 = ld_at(be, (uint32_t)(rO + cO));
+  const T cv3 = ld_at(bo, (uint32_t)(rE + cE)), cv4 = ld_at(bo, (uint32_t)(rE + cO));
+  const T cv5 = ld_at(bo, (uint32_t)(rO + cE)), cv6 = ld_at(bo, (uint32_t)(rO + cO));
+  const T wxl = q1ok ? a.ax[2].wl[2 * X0 + 2 * bb + 1] : T(0), wxr = q1ok ? a.ax[2].wr[2 * X0 + 2 * bb + 1] : T(0);
+  const T wyl = r1ok ? a.ax[1].wl[2 * Y0 + 2 * ba + 1] : T(0), wyr = r1ok ? a.ax[1].wr[2 * Y0 + 2 * ba + 1] : T(0);
+  const T wzl = odd_in ? ldu(a.ax[0].wl, 2 * J + 1) : T(0), wzr = odd_in ? ldu(a.ax[0].wr, 2 * J + 1) : T(0);
+#pragma unroll
+  for (int k = 0; k < NNP; k++) {
+    const int idx = tid + NTP * k;
+    if (idx < 2 * NH * NW) (&sN[0][0])[idx] = nv[k];
+  }
+  __syncthreads();
+  if (!inbox) return;
+  const int n = ba * NW + bb;
+  const T A00 = sN[0][n], A01 = sN[0][n + 1], A10 = sN[0][n + NW], A11 = sN[0][n + NW + 1];
+  const T ea = wxl * A00 + wxr * A01, eb = wxl * A10 + wxr * A11;
+  const T e10 = wyl * A00 + wyr * A10, e11 = wyl * ea + wyr * eb;
+  const uint32_t o0 = (uint32_t)(((2 * (Y0 + ba)) * (int)a.op1 + 2 * (X0 + bb)) * ES);
+  const uint32_t orow = (uint32_t)((int)a.op1 * ES);
+  T *const oe = a.out + (int64_t)(2 * J) * a.op0;
+  st_at(oe, o0, A00);
+  if (q1ok) st_at(oe, o0 + ES, cv0 + ea);
+  if (r1ok) st_at(oe, o0 + orow, cv1 + e10);
+  if (r1ok && q1ok) st_at(oe, o0 + orow + ES, cv2 + e11);
+  if (odd_in) {
+    const T B00 = sN[1][n], B01 = sN[1][n + 1], B10 = sN[1][n + NW], B11 = sN[1][n + NW + 1];
+    const T fa = wxl * B00 + wxr * B01, fb = wxl * B10 + wxr * B11;
+    const T f10 = wyl * B00 + wyr * B10, f11 = wyl * fa + wyr * fb;
+    T *const oo = a.out + (int64_t)(2 * J + 1) * a.op0;
+    st_at(oo, o0, cv3 + (wzl * A00 + wzr * B00));
+    if (q1ok) st_at(oo, o0 + ES, cv4 + (wzl * ea + wzr * fa));
+    if (r1ok) st_at(oo, o0 + orow, cv5 + (wzl * e10 + wzr * f10));
+    if (r1ok && q1ok) st_at(oo, o0 + orow + ES, cv6 + (wzl * e11 + wzr * f11));
+  }
+}
+
+template <typename T, int TX, int TY, int NTP>
+__global__ void __launch_bounds__(NTP) k_interp_plane(InterpArgs<T> a) {
+  interp_plane_body<T, TX, TY, NTP>(a, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// ---------------------------------------------------------------------------
 // k_prolong_mass: one level of the adjoint (not in the paper).  Applies the
 // transpose of the fused load-vector operator, (M P) along every axis, to a
 // coarse box y and combines the level-l result with the level's other terms:
@@ -1496,11 +1592,31 @@ hipError_t launch_load_vector(StencilArgs<T> a, bool dec, hipStream_t st, Tuning
   return hipGetLastError();
 }
 
+// Large levels take the one-plane-per-workgroup interpolation (compact store
+// front); smaller ones the z-marching kernel.
+template <typename T>
+static bool interp_plane(const InterpArgs<T> &a) {
+  return MGX_INTERP_PLANE && (int64_t)a.ax[0].c * a.ax[1].c * a.ax[2].c >= (1 << 20);
+}
+template <typename T>
+constexpr int interp_plane_threads() {
+  return ((Tiles<T>::TY + 1) * (Tiles<T>::TX + 1) + 63) / 64 * 64;
+}
+
 template <typename T>
 hipError_t launch_interp_add(InterpArgs<T> a, hipStream_t st, Tuning tn) {
   constexpr int TX = Tiles<T>::TX, TY = Tiles<T>::TY, NT = Tiles<T>::NT;
   if (!tile_grid(a.ax[0].c, a.ax[1].c, a.ax[2].c, TX, TY, &a.ntx, &a.nty, &a.nzc, &a.tz, tn))
     return hipErrorInvalidValue;
+  if (interp_plane(a)) {
+    // one coarse plane per workgroup
+    constexpr int NTP = interp_plane_threads<T>();
+    a.nzc = a.ax[0].c;
+    a.tz = 1;
+    dim3 grid(a.ntx * a.nty * a.nzc);
+    hipLaunchKernelGGL((k_interp_plane<T, TX, TY, NTP>), grid, dim3(NTP), 0, st, a);
+    return hipGetLastError();
+  }
   dim3 grid(a.ntx * a.nty * a.nzc);
   hipLaunchKernelGGL((k_interp_add<T, TX, TY, NT>), grid, dim3(NT), 0, st, a);
   return hipGetLastError();
@@ -1980,6 +2096,13 @@ __global__ void __launch_bounds__(NT) k_interp_add_multi(MultiArgs<T> m) {
   interp_add_body<T, TX, TY, NT>(m.args[f].ia, g - m.start[f]);
 }
 
+template <typename T, int TX, int TY, int NTP>
+__global__ void __launch_bounds__(NTP) k_interp_plane_multi(MultiArgs<T> m) {
+  const int g = xcd_remap(blockIdx.x, gridDim.x);
+  const int f = find_op(m.start, m.n, g);
+  interp_plane_body<T, TX, TY, NTP>(m.args[f].ia, g - m.start[f]);
+}
+
 template <typename T, int E, int G>
 __global__ void __launch_bounds__(256) k_solve_contig_multi(MultiArgs<T> m) {
   const int g = blockIdx.x;
@@ -2096,6 +2219,10 @@ int op_blocks(int kind, int mode, OpArgs<T> &a, const Tuning &tn) {
     case kOpInterpAdd: {
       InterpArgs<T> &s = a.ia;
       if (!tile_grid(s.ax[0].c, s.ax[1].c, s.ax[2].c, TX, TY, &s.ntx, &s.nty, &s.nzc, &s.tz, tn)) return -1;
+      if (interp_plane(s)) {
+        s.nzc = s.ax[0].c;
+        s.tz = 1;
+      }
       return s.ntx * s.nty * s.nzc;
     }
     case kOpSolveContig: {
@@ -2121,6 +2248,7 @@ template <typename T>
 int op_key(int kind, int mode, const OpArgs<T> &a) {
   switch (kind) {
     case kOpSolveContig: return a.so.c;
+    case kOpInterpAdd: return interp_plane(a.ia) ? 1 : 0;
     case kOpSolveStrided: return (a.sd.c << 4) | (mode << 1) | (strided_deep(a.sd) ? 1 : 0);
     case kOpQuantize: return aligned16(a.qj.umc) && aligned16(a.qj.labels);
     case kOpDequantize: return aligned16(a.dj.umc) && aligned16(a.dj.labels);
@@ -2178,7 +2306,10 @@ hipError_t launch_op_multi(int kind, int key, const OpArgs<T> *dargs, const int 
   switch (kind) {
     case kOpLoadVecDec: MGX_MULTI((k_load_vector_multi<T, TX, TY, NT, true>), NT); break;
     case kOpLoadVecRec: MGX_MULTI((k_load_vector_multi<T, TX, TY, NT, false>), NT); break;
-    case kOpInterpAdd: MGX_MULTI((k_interp_add_multi<T, TX, TY, NT>), NT); break;
+    case kOpInterpAdd:
+      if (key) MGX_MULTI((k_interp_plane_multi<T, TX, TY, interp_plane_threads<T>()>), interp_plane_threads<T>());
+      else MGX_MULTI((k_interp_add_multi<T, TX, TY, NT>), NT);
+      break;
     case kOpApply: MGX_MULTI((k_apply_multi<T>), 256); break;
     case kOpCopyBox: MGX_MULTI((k_copy_box_multi<T>), 256); break;
     case kOpTailDec: MGX_MULTI((k_tail_dec_multi<T>), kTailThreads); break;
