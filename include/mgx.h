@@ -117,22 +117,31 @@ mgx_status mgx_recompose(const void *u_mc, void *u, mgx_dtype dtype, int ndim,
                          void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* mgx_decompose followed by mgx_quantize (no statistics) in one call, with
- * the same results.  A build with MGX_FUSED_OVERLAP quantizes the finest
- * level's coefficients (7/8 of them, final after that level's kernels) on a
- * second stream of the library while the coarser levels run on `stream`,
- * which waits for that work before the call's last operation; measured
- * slower than the sequence on MI355X, so the default build runs the two in
- * sequence on `stream`.  labels must not overlap u or u_mc.
+ * the same results (Sec. 4.1 quantization of the Sec. 3 decomposition):
+ * every kernel that produces coefficients of a level also writes their
+ * labels, so no separate pass over u_mc is made.
+ *   u_mc     out: device, level-centric layout, or NULL: then only labels
+ *            are written (the stop level's box goes through the workspace).
+ *   labels   out: device, int32, same shape; must not overlap u, u_mc or
+ *            the workspace.
+ * A build with MGX_FUSED_OVERLAP (and u_mc given) instead runs the
+ * decomposition and a separate quantization, the finest level's on a second
+ * stream of the library (measured slower on MI355X).
  * Errors as mgx_decompose and mgx_quantize (MGX_ERR_TOL). */
 mgx_status mgx_decompose_quantize(const void *u, void *u_mc, int32_t *labels, mgx_dtype dtype, int ndim,
                                   const int64_t *dims, const double *const *coords, double tol_linf,
                                   int stop_level, double c_linf, void *workspace, size_t workspace_bytes,
                                   hipStream_t stream);
 
-/* mgx_dequantize(labels) into u_mc followed by mgx_recompose(u_mc) into u,
- * with the same results (with MGX_FUSED_OVERLAP the finest level is
- * dequantized on the library's second stream while the coarser levels are
- * recomposed). */
+/* mgx_dequantize(labels) followed by mgx_recompose into u, with the same
+ * results.
+ *   u_mc     NULL: the recomposition's kernels read each coefficient as its
+ *            label times the level's bin width (no u_mc pass); or device,
+ *            dtype: the dequantized coefficients are written there first and
+ *            recomposed from (with MGX_FUSED_OVERLAP the finest level is
+ *            dequantized on the library's second stream).
+ *   labels   in: device, int32; must not overlap u, u_mc or the workspace.
+ * Errors as mgx_recompose and mgx_dequantize. */
 mgx_status mgx_dequantize_recompose(const int32_t *labels, void *u_mc, void *u, mgx_dtype dtype, int ndim,
                                     const int64_t *dims, const double *const *coords, double tol_linf,
                                     int stop_level, double c_linf, void *workspace, size_t workspace_bytes,

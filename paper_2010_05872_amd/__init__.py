@@ -298,44 +298,52 @@ def recompose(u_mc, coords=None, stop_level=0, out=None, workspace=None):
     return out
 
 
-def decompose_quantize(u, tol, coords=None, stop_level=0, c_linf=0.0, out=None, labels=None, workspace=None):
-    """decompose then quantize (same results), the finest level's quantization
-    overlapped with the coarser levels.  Returns (u_mc, labels)."""
+def decompose_quantize(u, tol, coords=None, stop_level=0, c_linf=0.0, out=None, labels=None, workspace=None,
+                       keep_coef=True):
+    """decompose then quantize (same labels and coefficients as the separate
+    calls), the labels written by the decomposition's own kernels.  With
+    keep_coef=False no u_mc is written (out is ignored) and None is returned
+    in its place.  Returns (u_mc, labels)."""
     import torch
     _check_tensor(u, "u")
-    if out is None:
+    if not keep_coef:
+        out = None
+    elif out is None:
         out = torch.empty_like(u)
     if labels is None:
         labels = torch.empty(u.shape, dtype=torch.int32, device=u.device)
-    _check_tensor(out, "out")
+    if out is not None:
+        _check_tensor(out, "out")
     _check_tensor(labels, "labels")
     ws, _ = _workspace(u, stop_level, workspace)
     c = Coords(u.shape, coords)
-    code = lib().mgx_decompose_quantize(u.data_ptr(), out.data_ptr(), labels.data_ptr(), _dtype_code(u), u.dim(),
-                                        _dims(u.shape), c.ptr, float(tol), int(stop_level), float(c_linf),
-                                        ws.data_ptr(), ws.numel() * ws.element_size(), _stream(u.device))
+    code = lib().mgx_decompose_quantize(u.data_ptr(), out.data_ptr() if out is not None else None,
+                                        labels.data_ptr(), _dtype_code(u), u.dim(), _dims(u.shape), c.ptr,
+                                        float(tol), int(stop_level), float(c_linf), ws.data_ptr(),
+                                        ws.numel() * ws.element_size(), _stream(u.device))
     _check(code, "mgx_decompose_quantize")
     return out, labels
 
 
 def dequantize_recompose(labels, tol, dtype, coords=None, stop_level=0, c_linf=0.0, coef=None, out=None,
                          workspace=None):
-    """dequantize into coef, then recompose into out (same results), the finest
-    level's dequantization overlapped with the coarser levels.  Returns out."""
+    """dequantize then recompose into out (same results as the separate
+    calls).  Without coef the recomposition's kernels read the coefficients
+    from the labels; with coef the dequantized coefficients are also written
+    there first.  Returns out."""
     import torch
     _check_tensor(labels, "labels")
-    if coef is None:
-        coef = torch.empty(labels.shape, dtype=dtype, device=labels.device)
     if out is None:
         out = torch.empty(labels.shape, dtype=dtype, device=labels.device)
-    _check_tensor(coef, "coef")
+    if coef is not None:
+        _check_tensor(coef, "coef")
     _check_tensor(out, "out")
-    ws, _ = _workspace(coef, stop_level, workspace)
+    ws, _ = _workspace(out, stop_level, workspace)
     c = Coords(labels.shape, coords)
-    code = lib().mgx_dequantize_recompose(labels.data_ptr(), coef.data_ptr(), out.data_ptr(), _dtype_code(coef),
-                                          labels.dim(), _dims(labels.shape), c.ptr, float(tol), int(stop_level),
-                                          float(c_linf), ws.data_ptr(), ws.numel() * ws.element_size(),
-                                          _stream(labels.device))
+    code = lib().mgx_dequantize_recompose(labels.data_ptr(), coef.data_ptr() if coef is not None else None,
+                                          out.data_ptr(), _dtype_code(out), labels.dim(), _dims(labels.shape),
+                                          c.ptr, float(tol), int(stop_level), float(c_linf), ws.data_ptr(),
+                                          ws.numel() * ws.element_size(), _stream(labels.device))
     _check(code, "mgx_dequantize_recompose")
     return out
 

@@ -26,7 +26,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 int64_t round4(int64_t v) { return (v + 3) / 4 * 4; }
 
 struct Layout {
-  size_t offA = 0, offB = 0, offF = 0, offG = 0, total = 0;
+  size_t offA = 0, offB = 0, offF = 0, offG = 0, offS = 0, total = 0;
   int lt = -1;  // finest level of the single-workgroup tail, -1: none
 };
 
@@ -66,6 +66,11 @@ Layout layout(const int64_t n[3], const bool real[3], int L, int stop, size_t es
   w.offG = off;
   if (adjoint) off = align_up(off + (size_t)cF * es, 256);
   w.lt = tail_level(n, real, L, stop);
+  // the stop box, compact (paths that work on labels without u_mc)
+  int64_t cS = 1;
+  for (int k = 0; k < 3; k++) cS *= real[k] ? (n[k] - 1) / ((int64_t)1 << (L - stop)) + 1 : 1;
+  w.offS = off;
+  off = align_up(off + (size_t)cS * es, 256);
   w.total = off;
   return w;
 }
@@ -260,17 +265,28 @@ OpArgs<T> tail_args(const Plan *P, int stop, const T *tab, char *ws, const Layou
   return o;
 }
 
+void quant_box(const Plan *P, QuantArgs &qa, int level);
+
+// With labels (and the quantizer's arguments qa), every kernel that writes
+// coefficients also writes their labels, and u_mc may be null (labels only).
 template <typename T>
 mgx_status run_decompose(Plan *P, int stop, const T *u, T *umc, char *ws, const Layout &lay, const T *tab,
-                         Emitter<T> &em) {
+                         Emitter<T> &em, int32_t *labels = nullptr, const QuantArgs *qa = nullptr) {
   const int L = P->L;
   const int64_t n1 = P->n[1], n2 = P->n[2];
   const int64_t up0 = n1 * n2, up1 = n2;
   if (stop == L) {
     em.begin_step(0);
-    return hip_status(copy_box<T>(u, up0, up1, umc, up0, up1, (int)P->n[0], (int)n1, (int)n2, L, em));
+    if (umc && copy_box<T>(u, up0, up1, umc, up0, up1, (int)P->n[0], (int)n1, (int)n2, L, em) != hipSuccess)
+      return MGX_ERR_HIP;
+    if (labels && traced("quantize", -1, em.st, [&] {
+          return launch_quantize<T>(umc ? umc : u, labels, *qa, false, em.st);
+        }) != hipSuccess)
+      return MGX_ERR_HIP;
+    return MGX_OK;
   }
   T *A = (T *)(ws + lay.offA), *B = (T *)(ws + lay.offB), *F = (T *)(ws + lay.offF);
+  T *S = (T *)(ws + lay.offS);  // the stop box when u_mc is not written
   const T *src = u;
   int64_t sp0 = up0, sp1 = up1;
   const int lowest = lay.lt > stop ? lay.lt : stop;  // tiled levels L .. lowest+1
@@ -292,13 +308,17 @@ mgx_status run_decompose(Plan *P, int stop, const T *u, T *umc, char *ws, const 
     s.F = F;
     s.fp0 = fp0;
     s.fp1 = fp1;
+    if (labels) {
+      s.lab_w = labels;
+      s.qc = qa->q[l - stop];
+    }
     hipError_t e = em.op(kOpLoadVecDec, 0, "load_vector_dec", l, o);
     if (e != hipSuccess) return MGX_ERR_HIP;
     // Q_{l-1} u goes to the compact box of level l-1, or into the corner of
-    // u_mc after the last decomposed level
+    // u_mc after the last decomposed level (the compact stop box without u_mc)
     const bool last = (l == stop + 1);
-    T *dst = last ? umc : (((L - 1 - (l - 1)) % 2 == 0) ? A : B);
-    const int64_t op0 = last ? up0 : cp0, op1 = last ? up1 : cp1;
+    T *dst = last ? (umc ? umc : S) : (((L - 1 - (l - 1)) % 2 == 0) ? A : B);
+    const int64_t op0 = (last && umc) ? up0 : cp0, op1 = (last && umc) ? up1 : cp1;
     e = solve_level<T>(l, ax, P->real, F, fp0, fp1, kSolveStore, nullptr, 0, 0, dst, op0, op1, em);
     if (e != hipSuccess) return MGX_ERR_HIP;
     src = dst;
@@ -314,22 +334,49 @@ mgx_status run_decompose(Plan *P, int stop, const T *u, T *umc, char *ws, const 
     o.tl.umc = umc;
     o.tl.up0 = up0;
     o.tl.up1 = up1;
+    if (labels) {
+      o.tl.lab_w = labels;
+      for (int i = 0; i < o.tl.nlev; i++) o.tl.q[i] = qa->q[lay.lt - i - stop];
+      o.tl.q[o.tl.nlev] = qa->q[0];
+    }
     if (em.op(kOpTailDec, 0, "tail_dec", lay.lt, o) != hipSuccess) return MGX_ERR_HIP;
+  } else if (labels) {  // the stop box's labels
+    QuantArgs b = *qa;
+    quant_box(P, b, stop);
+    b.sel_lo = b.sel_hi = stop;
+    b.box_compact = umc ? 0 : 1;
+    if (traced("quantize_box", -1, em.st, [&] { return launch_quantize<T>(umc ? umc : S, labels, b, false, em.st); }) !=
+        hipSuccess)
+      return MGX_ERR_HIP;
   }
   return MGX_OK;
 }
 
+// With labels (and qa), the coefficients are read as labels times the
+// level's bin width (u_mc unused, may be null).
 template <typename T>
 mgx_status run_recompose(Plan *P, int stop, const T *umc, T *u, char *ws, const Layout &lay, const T *tab,
-                         Emitter<T> &em) {
+                         Emitter<T> &em, const int32_t *labels = nullptr, const QuantArgs *qa = nullptr) {
   const int L = P->L;
   const int64_t n1 = P->n[1], n2 = P->n[2];
   const int64_t up0 = n1 * n2, up1 = n2;
   if (stop == L) {
     em.begin_step(0);
+    if (labels)
+      return hip_status(traced("dequantize", -1, em.st, [&] { return launch_dequantize<T>(labels, u, *qa, em.st); }));
     return hip_status(copy_box<T>(umc, up0, up1, u, up0, up1, (int)P->n[0], (int)n1, (int)n2, L, em));
   }
   T *A = (T *)(ws + lay.offA), *B = (T *)(ws + lay.offB), *F = (T *)(ws + lay.offF);
+  T *S = (T *)(ws + lay.offS);
+  const bool sbox = labels && !(lay.lt > stop);  // stop box dequantized into S first
+  if (sbox) {
+    QuantArgs b = *qa;
+    quant_box(P, b, stop);
+    b.sel_lo = b.sel_hi = stop;
+    b.box_compact = 1;
+    if (traced("dequantize_box", -1, em.st, [&] { return launch_dequantize<T>(labels, S, b, em.st); }) != hipSuccess)
+      return MGX_ERR_HIP;
+  }
   int first_tiled = stop + 1;
   if (lay.lt > stop) {  // levels stop+1 .. lt in one workgroup, into the level-lt box
     em.begin_step(0);
@@ -337,6 +384,11 @@ mgx_status run_recompose(Plan *P, int stop, const T *umc, T *u, char *ws, const 
     o.tl.umc_r = umc;
     o.tl.up0 = up0;
     o.tl.up1 = up1;
+    if (labels) {
+      o.tl.lab_r = labels;
+      for (int i = 0; i < o.tl.nlev; i++) o.tl.q[i] = qa->q[lay.lt - i - stop];
+      o.tl.q[o.tl.nlev] = qa->q[0];
+    }
     if (lay.lt == L) {
       o.tl.dst = u;
       o.tl.dp0 = up0;
@@ -359,8 +411,8 @@ mgx_status run_recompose(Plan *P, int stop, const T *umc, T *u, char *ws, const 
     const int64_t cp1 = c2, cp0 = (int64_t)c1 * c2;
     const int64_t fp1 = round4(c2), fp0 = (int64_t)c1 * fp1;
     const bool first = (l == stop + 1);  // with a tail, level lt+1 reads the tail's box nb
-    const T *nin = first ? umc : nb;
-    const int64_t ip0 = first ? up0 : cp0, ip1 = first ? up1 : cp1;
+    const T *nin = first ? (sbox ? S : umc) : nb;
+    const int64_t ip0 = (first && !sbox) ? up0 : cp0, ip1 = (first && !sbox) ? up1 : cp1;
     OpArgs<T> o{};
     StencilArgs<T> &s = o.st;
     for (int k = 0; k < 3; k++) s.ax[k] = ax[k];
@@ -370,6 +422,10 @@ mgx_status run_recompose(Plan *P, int stop, const T *umc, T *u, char *ws, const 
     s.F = F;
     s.fp0 = fp0;
     s.fp1 = fp1;
+    if (labels) {
+      s.lab_r = labels;
+      s.qc = qa->q[l - stop];
+    }
     hipError_t e = em.op(kOpLoadVecRec, 0, "load_vector_rec", l, o);
     if (e != hipSuccess) return MGX_ERR_HIP;
     e = solve_level<T>(l, ax, P->real, F, fp0, fp1, kSolveApply, nin, ip0, ip1, nb, cp0, cp1, em);
@@ -383,6 +439,10 @@ mgx_status run_recompose(Plan *P, int stop, const T *umc, T *u, char *ws, const 
     ia.umc = umc;
     ia.up0 = up0;
     ia.up1 = up1;
+    if (labels) {
+      ia.lab = labels;
+      ia.qc = qa->q[l - stop];
+    }
     if (l == L) {
       ia.out = u;
       ia.op0 = up0;
@@ -535,24 +595,26 @@ mgx_status run_recompose_adjoint(Plan *P, int stop, const T *gu, T *gmc, char *w
 // Common validation of decompose / recompose.
 mgx_status prepare(const void *in, void *out, mgx_dtype dtype, int ndim, const int64_t *dims,
                    const double *const *coords, int stop, void *ws, size_t ws_bytes, Plan **plan,
-                   Layout *lay, const void **tab, bool adjoint = false) {
+                   Layout *lay, const void **tab, bool adjoint = false, int may_null = 0) {
   if (dtype != MGX_F32 && dtype != MGX_F64) return MGX_ERR_ARG;
   int64_t n[3];
   bool real[3];
   int L;
   int st = parse_shape(ndim, dims, n, real, &L);
   if (st) return (mgx_status)st;
-  if (!in || !out) return MGX_ERR_ARG;
+  // may_null: 1 = in, 2 = out may be null (the fused calls' u_mc)
+  if ((!in && !(may_null & 1)) || (!out && !(may_null & 2))) return MGX_ERR_ARG;
   const size_t es = elem_size(dtype);
   const size_t bytes = (size_t)(n[0] * n[1] * n[2]) * es;
-  if (overlaps(in, bytes, out, bytes)) return MGX_ERR_ARG;
+  if (in && out && overlaps(in, bytes, out, bytes)) return MGX_ERR_ARG;
   Plan *P = get_plan(ndim, dims, coords, &st);
   if (!P) return (mgx_status)st;
   if (stop < 0 || stop > L) return MGX_ERR_LEVEL;
   *lay = layout(n, real, L, stop, es, adjoint);
   if (lay->total > 0) {
     if (!ws || ws_bytes < lay->total) return MGX_ERR_WORKSPACE;
-    if (overlaps(ws, lay->total, in, bytes) || overlaps(ws, lay->total, out, bytes)) return MGX_ERR_ARG;
+    if ((in && overlaps(ws, lay->total, in, bytes)) || (out && overlaps(ws, lay->total, out, bytes)))
+      return MGX_ERR_ARG;
   }
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return MGX_ERR_HIP;
@@ -622,12 +684,13 @@ StatsBuf &stats_buf() {
   return *s;
 }
 
-// The corner box of level L-1 (the coarser levels' coefficients) as the
-// visited region of a quantization pass.
-void quant_box(const Plan *P, QuantArgs &qa) {
+// The corner box of a level (level L-1: the coarser levels' coefficients)
+// as the visited region of a quantization pass.
+void quant_box(const Plan *P, QuantArgs &qa, int level = -1) {
   const int L = P->L;
+  if (level < 0) level = L - 1;
   int64_t b[3];
-  for (int k = 0; k < 3; k++) b[k] = P->real[k] ? (P->n[k] - 1) / 2 + 1 : 1;
+  for (int k = 0; k < 3; k++) b[k] = P->real[k] ? (P->n[k] - 1) / ((int64_t)1 << (L - level)) + 1 : 1;
   auto magic = [](uint64_t d) -> uint64_t { return d < 2 ? 0 : (~(uint64_t)0) / d + 1; };
   qa.box = 1;
   qa.b1 = (int)b[1];
@@ -686,12 +749,10 @@ mgx_status side_stream(std::unique_lock<std::mutex> &lk, hipStream_t *q, hipEven
 template <typename T>
 mgx_status run_decompose_quantize(Plan *P, int stop, const T *u, T *umc, int32_t *labels, QuantArgs qa, char *ws,
                                   const Layout &lay, const T *tab, hipStream_t st) {
-  if (!MGX_FUSED_OVERLAP) {
+  if (!MGX_FUSED_OVERLAP || !umc) {  // labels written by the level kernels themselves
     Emitter<T> em;
     em.st = st;
-    mgx_status s = run_decompose<T>(P, stop, u, umc, ws, lay, tab, em);
-    if (s) return s;
-    return hip_status(traced("quantize", -1, st, [&] { return launch_quantize<T>(umc, labels, qa, false, st); }));
+    return run_decompose<T>(P, stop, u, umc, ws, lay, tab, em, labels, &qa);
   }
   const int L = P->L;
   std::unique_lock<std::mutex> lk;
@@ -736,11 +797,13 @@ mgx_status run_decompose_quantize(Plan *P, int stop, const T *u, T *umc, int32_t
 template <typename T>
 mgx_status run_dequantize_recompose(Plan *P, int stop, const int32_t *labels, T *umc, T *u, QuantArgs qa,
                                     char *ws, const Layout &lay, const T *tab, hipStream_t st) {
-  if (!MGX_FUSED_OVERLAP) {
-    if (traced("dequantize", -1, st, [&] { return launch_dequantize<T>(labels, umc, qa, st); }) != hipSuccess)
-      return MGX_ERR_HIP;
+  if (!MGX_FUSED_OVERLAP || !umc) {
     Emitter<T> em;
     em.st = st;
+    if (!umc)  // coefficients read from the labels by the level kernels
+      return run_recompose<T>(P, stop, nullptr, u, ws, lay, tab, em, labels, &qa);
+    if (traced("dequantize", -1, st, [&] { return launch_dequantize<T>(labels, umc, qa, st); }) != hipSuccess)
+      return MGX_ERR_HIP;
     return run_recompose<T>(P, stop, umc, u, ws, lay, tab, em);
   }
   const int L = P->L;
@@ -1379,11 +1442,14 @@ mgx_status mgx_decompose_quantize(const void *u, void *u_mc, int32_t *labels, mg
   Plan *P;
   Layout lay;
   const void *tab;
-  mgx_status s = prepare(u, u_mc, dtype, ndim, dims, coords, stop_level, workspace, workspace_bytes, &P, &lay, &tab);
+  mgx_status s = prepare(u, u_mc, dtype, ndim, dims, coords, stop_level, workspace, workspace_bytes, &P, &lay, &tab,
+                         false, 2);
   if (s) return s;
   if (!labels) return MGX_ERR_ARG;
   const size_t cnt = (size_t)(P->n[0] * P->n[1] * P->n[2]);
-  if (overlaps(labels, cnt * 4, u_mc, cnt * elem_size(dtype)) || overlaps(labels, cnt * 4, u, cnt * elem_size(dtype)))
+  if ((u_mc && overlaps(labels, cnt * 4, u_mc, cnt * elem_size(dtype))) ||
+      overlaps(labels, cnt * 4, u, cnt * elem_size(dtype)) ||
+      (lay.total > 0 && overlaps(labels, cnt * 4, workspace, lay.total)))
     return MGX_ERR_ARG;
   QuantArgs qa;
   Plan *Pq;
@@ -1402,11 +1468,14 @@ mgx_status mgx_dequantize_recompose(const int32_t *labels, void *u_mc, void *u, 
   Plan *P;
   Layout lay;
   const void *tab;
-  mgx_status s = prepare(u_mc, u, dtype, ndim, dims, coords, stop_level, workspace, workspace_bytes, &P, &lay, &tab);
+  mgx_status s = prepare(u_mc, u, dtype, ndim, dims, coords, stop_level, workspace, workspace_bytes, &P, &lay, &tab,
+                         false, 1);
   if (s) return s;
   if (!labels) return MGX_ERR_ARG;
   const size_t cnt = (size_t)(P->n[0] * P->n[1] * P->n[2]);
-  if (overlaps(labels, cnt * 4, u_mc, cnt * elem_size(dtype)) || overlaps(labels, cnt * 4, u, cnt * elem_size(dtype)))
+  if ((u_mc && overlaps(labels, cnt * 4, u_mc, cnt * elem_size(dtype))) ||
+      overlaps(labels, cnt * 4, u, cnt * elem_size(dtype)) ||
+      (lay.total > 0 && overlaps(labels, cnt * 4, workspace, lay.total)))
     return MGX_ERR_ARG;
   QuantArgs qa;
   Plan *Pq;

@@ -117,6 +117,26 @@ __device__ __forceinline__ T ld_once(const T *base, uint32_t byte_off) {
 #endif
 }
 
+// The quantizer's decision for one coefficient: rint(c / q) in FP64 (a
+// correctly rounded division, ties to even), INT32_MIN when out of range or
+// not finite -- the same operations as the quantization pass, so labels
+// written by the level kernels equal that pass's labels bit for bit.
+template <typename T>
+__device__ __forceinline__ int32_t label_of(T v, double q) {
+  const double t = (double)v / q;
+  return !(fabs(t) < 2147483647.0) ? INT32_MIN : (int32_t)rint(t);
+}
+// A coefficient from its label (the dequantization pass's operations).
+template <typename T>
+__device__ __forceinline__ T from_label(int32_t l, double q) {
+  return (T)((double)l * q);
+}
+// Byte offset of the label of the element at byte offset off of a T array.
+template <typename T>
+__device__ __forceinline__ uint32_t lab_off(uint32_t off) {
+  return sizeof(T) == 4 ? off : off >> 1;
+}
+
 // Column of region column q in a de-interleaved LDS row: even columns first,
 // then odd ones (stride-1 reads in the restriction along x).
 template <int TX>
@@ -161,7 +181,7 @@ __device__ __forceinline__ int opaque(int v) {
 // de-interleaved in LDS (even columns first), so both the restriction and
 // the interpolation corners read consecutive LDS words.  Planes are fetched
 // two iterations ahead into double-buffered registers.
-template <typename T, int TX, int TY, int NT, bool DEC>
+template <typename T, int TX, int TY, int NT, bool DEC, bool LAB>
 __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const int lb) {
   constexpr int HR = 2 * TY + 5;  // region rows incl. halo and the extension
   constexpr int W = 2 * TX + 5;   // region row pitch
@@ -224,6 +244,7 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
   auto fetch = [&](int j, T (&st)[NE]) {
     const bool pin = j >= 0 && j < m0;
     const T *base = DEC ? a.V + (int64_t)(pin ? j : 0) * a.vp0 : a.umc_r + (pin ? lc_pos(j, c0) : 0) * a.up0;
+    const int32_t *lbase = (!DEC && LAB) ? a.lab_r + (pin ? lc_pos(j, c0) : 0) * a.up0 : nullptr;
     // recomposition: nodal nodes (all indices even) carry no multilevel
     // component; their lanes read the plane's first element instead (one
     // shared line) rather than the coarse corner
@@ -232,7 +253,11 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
 #pragma unroll
     for (int k = 0; k < NE; k++) {
       const uint32_t off = (skip_nodal && ((yxeven >> k) & 1u)) ? 0u : (uint32_t)goff[k];
-      const T v = ld_at(base, off);
+      T v;
+      if (!DEC && LAB)
+        v = from_label<T>(ld_at(lbase, lab_off<T>(off)), a.qc);
+      else
+        v = ld_at(base, off);
       st[k] = (pin && ((keep >> k) & 1u)) ? v : T(0);
     }
   };
@@ -321,8 +346,15 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
       }
     }
     // ---- coefficients of the owned nodes of plane j (decomposition) ----
-    if (DEC && a.umc_w != nullptr && plane_in && j >= own_p0 && j < own_p1) {
+    if (DEC && (a.umc_w != nullptr || LAB) && plane_in && j >= own_p0 && j < own_p1) {
       T *const cbase = a.umc_w + lc_pos(j, c0) * a.up0;
+      int32_t *const lbase = LAB ? a.lab_w + lc_pos(j, c0) * a.up0 : nullptr;
+      const bool wc = a.umc_w != nullptr;
+      // a coefficient to u_mc and / or its label
+      auto put = [&](uint32_t off, T v) {
+        if (wc) st_once(cbase, off, v);
+        if (LAB) st_at(lbase, lab_off<T>(off), label_of(v, a.qc));
+      };
       if (!pz) {
         // even plane: corners in the plane itself; node 00 is nodal
 #pragma unroll
@@ -334,9 +366,9 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
             const T C20 = sV[s0][R2 + e0], C22 = sV[s0][R2 + e0 + 1];
             const T t0 = cwxl[k] * C00 + cwxr[k] * C02, t2 = cwxl[k] * C20 + cwxr[k] * C22;
             const uint32_t oE = (uint32_t)(cRowE[k] + cColE[k]);
-            if (f & 2u) st_once(cbase, oE + colOdd, sV[s0][R0 + E + e0] - t0);
-            if (f & 4u) st_once(cbase, oE + rowOdd, sV[s0][R0 + W + e0] - (cwyl[k] * C00 + cwyr[k] * C20));
-            if (f & 8u) st_once(cbase, oE + rowOdd + colOdd, sV[s0][R0 + W + E + e0] - (cwyl[k] * t0 + cwyr[k] * t2));
+            if (f & 2u) put(oE + colOdd, sV[s0][R0 + E + e0] - t0);
+            if (f & 4u) put(oE + rowOdd, sV[s0][R0 + W + e0] - (cwyl[k] * C00 + cwyr[k] * C20));
+            if (f & 8u) put(oE + rowOdd + colOdd, sV[s0][R0 + W + E + e0] - (cwyl[k] * t0 + cwyr[k] * t2));
           }
         }
       } else {
@@ -354,14 +386,13 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
             const T ta0 = wxl * A00 + wxr * A02, ta2 = wxl * A20 + wxr * A22;
             const T tb0 = wxl * B00 + wxr * B02, tb2 = wxl * B20 + wxr * B22;
             const uint32_t oE = (uint32_t)(cRowE[k] + cColE[k]);
-            if (f & 1u) st_once(cbase, oE, sV[s0][R0 + e0] - (wzl * A00 + wzr * B00));
-            if (f & 2u) st_once(cbase, oE + colOdd, sV[s0][R0 + E + e0] - (wzl * ta0 + wzr * tb0));
+            if (f & 1u) put(oE, sV[s0][R0 + e0] - (wzl * A00 + wzr * B00));
+            if (f & 2u) put(oE + colOdd, sV[s0][R0 + E + e0] - (wzl * ta0 + wzr * tb0));
             if (f & 4u)
-              st_once(cbase, oE + rowOdd,
-                    sV[s0][R0 + W + e0] - (wzl * (wyl * A00 + wyr * A20) + wzr * (wyl * B00 + wyr * B20)));
+              put(oE + rowOdd, sV[s0][R0 + W + e0] - (wzl * (wyl * A00 + wyr * A20) + wzr * (wyl * B00 + wyr * B20)));
             if (f & 8u)
-              st_once(cbase, oE + rowOdd + colOdd,
-                    sV[s0][R0 + W + E + e0] - (wzl * (wyl * ta0 + wyr * ta2) + wzr * (wyl * tb0 + wyr * tb2)));
+              put(oE + rowOdd + colOdd,
+                  sV[s0][R0 + W + E + e0] - (wzl * (wyl * ta0 + wyr * ta2) + wzr * (wyl * tb0 + wyr * tb2)));
           }
         }
       }
@@ -436,10 +467,10 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
     if (j + d <= jend) plane(j + d, st[d]);
 }
 
-template <typename T, int TX, int TY, int NT, bool DEC>
+template <typename T, int TX, int TY, int NT, bool DEC, bool LAB>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MGX_STENCIL_WAVES, 8)))
 k_load_vector(StencilArgs<T> a) {
-  load_vector_body<T, TX, TY, NT, DEC>(a, xcd_remap(blockIdx.x, gridDim.x));
+  load_vector_body<T, TX, TY, NT, DEC, LAB>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -767,7 +798,7 @@ __global__ void __launch_bounds__(256) k_apply(StridedArgs<T> a) {
 // offsets are fixed for the whole march, and the coefficients of the next
 // coarse plane are fetched into registers while the current one is done.
 // ---------------------------------------------------------------------------
-template <typename T, int TX, int TY, int NT>
+template <typename T, int TX, int TY, int NT, bool LAB>
 __device__ __forceinline__ void interp_add_body(const InterpArgs<T> a, const int lb) {
   constexpr int NW = TX + 2;  // nodal tile pitch
   constexpr int NH = TY + 2;
@@ -860,18 +891,32 @@ __device__ __forceinline__ void interp_add_body(const InterpArgs<T> a, const int
   // 2J+1 (nodes 00, 01, 10, 11), 7 per block
   auto fetch_coef = [&](int J, T (&cv)[NB][7]) {
     const bool pin = J < Z1;
-    const T *be = a.umc + (int64_t)(pin ? J : 0) * a.up0;
     const bool odd_in = pin && 2 * J + 1 < m0;
-    const T *bo = a.umc + (int64_t)(odd_in ? c0 + J : 0) * a.up0;
+    const int64_t pe = (int64_t)(pin ? J : 0) * a.up0, po = (int64_t)(odd_in ? c0 + J : 0) * a.up0;
+    if (LAB) {
+      const int32_t *be = a.lab + pe, *bo = a.lab + po;
 #pragma unroll
-    for (int k = 0; k < NB; k++) {
-      cv[k][0] = ld_once(be, (uint32_t)bEO[k]);
-      cv[k][1] = ld_once(be, (uint32_t)bOE[k]);
-      cv[k][2] = ld_once(be, (uint32_t)bOO[k]);
-      cv[k][3] = ld_once(bo, (uint32_t)bEE[k]);
-      cv[k][4] = ld_once(bo, (uint32_t)bEO[k]);
-      cv[k][5] = ld_once(bo, (uint32_t)bOE[k]);
-      cv[k][6] = ld_once(bo, (uint32_t)bOO[k]);
+      for (int k = 0; k < NB; k++) {
+        cv[k][0] = from_label<T>(ld_at(be, lab_off<T>((uint32_t)bEO[k])), a.qc);
+        cv[k][1] = from_label<T>(ld_at(be, lab_off<T>((uint32_t)bOE[k])), a.qc);
+        cv[k][2] = from_label<T>(ld_at(be, lab_off<T>((uint32_t)bOO[k])), a.qc);
+        cv[k][3] = from_label<T>(ld_at(bo, lab_off<T>((uint32_t)bEE[k])), a.qc);
+        cv[k][4] = from_label<T>(ld_at(bo, lab_off<T>((uint32_t)bEO[k])), a.qc);
+        cv[k][5] = from_label<T>(ld_at(bo, lab_off<T>((uint32_t)bOE[k])), a.qc);
+        cv[k][6] = from_label<T>(ld_at(bo, lab_off<T>((uint32_t)bOO[k])), a.qc);
+      }
+    } else {
+      const T *be = a.umc + pe, *bo = a.umc + po;
+#pragma unroll
+      for (int k = 0; k < NB; k++) {
+        cv[k][0] = ld_once(be, (uint32_t)bEO[k]);
+        cv[k][1] = ld_once(be, (uint32_t)bOE[k]);
+        cv[k][2] = ld_once(be, (uint32_t)bOO[k]);
+        cv[k][3] = ld_once(bo, (uint32_t)bEE[k]);
+        cv[k][4] = ld_once(bo, (uint32_t)bEO[k]);
+        cv[k][5] = ld_once(bo, (uint32_t)bOE[k]);
+        cv[k][6] = ld_once(bo, (uint32_t)bOO[k]);
+      }
     }
   };
 
@@ -939,9 +984,9 @@ __device__ __forceinline__ void interp_add_body(const InterpArgs<T> a, const int
     if (J + k < Z1) step(J + k, cv[k], nv[k]);
 }
 
-template <typename T, int TX, int TY, int NT>
+template <typename T, int TX, int TY, int NT, bool LAB>
 __global__ void __launch_bounds__(NT) k_interp_add(InterpArgs<T> a) {
-  interp_add_body<T, TX, TY, NT>(a, xcd_remap(blockIdx.x, gridDim.x));
+  interp_add_body<T, TX, TY, NT, LAB>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -952,7 +997,7 @@ __global__ void __launch_bounds__(NT) k_interp_add(InterpArgs<T> a) {
 // front instead of one front per z-marching workgroup.  Each thread owns one
 // 2x2 block of fine nodes; all loads are issued before the first wait.
 // ---------------------------------------------------------------------------
-template <typename T, int TX, int TY, int NTP>
+template <typename T, int TX, int TY, int NTP, bool LAB>
 __device__ __forceinline__ void interp_plane_body(const InterpArgs<T> a, const int lb) {
   constexpr int NW = TX + 2, NH = TY + 2, BW = TX + 1;
   constexpr int NNP = (2 * NH * NW + NTP - 1) / NTP;  // nodal loads per thread (planes J, J+1)
@@ -994,11 +1039,13 @@ __device__ __forceinline__ void interp_plane_body(const InterpArgs<T> a, const i
   const int rO = r1ok && inbox ? rE + (int)(c1 * a.up1) * ES : rE;
   const int cE = (X0 + (inbox ? bb : 0)) * ES;
   const int cO = q1ok && inbox ? cE + c2 * ES : cE;
-  const T *be = a.umc + (int64_t)J * a.up0;
-  const T *bo = a.umc + (int64_t)(odd_in ? c0 + J : J) * a.up0;
-  const T cv0 = ld_at(be, (uint32_t)(rE + cO)), cv1 = ld_at(be, (uint32_t)(rO + cE)), cv2 = ld_at(be, (uint32_t)(rO + cO));
-  const T cv3 = ld_at(bo, (uint32_t)(rE + cE)), cv4 = ld_at(bo, (uint32_t)(rE + cO));
-  const T cv5 = ld_at(bo, (uint32_t)(rO + cE)), cv6 = ld_at(bo, (uint32_t)(rO + cO));
+  const int64_t pe = (int64_t)J * a.up0, po = (int64_t)(odd_in ? c0 + J : J) * a.up0;
+  auto coef = [&](int64_t plane, int off) -> T {
+    if (LAB) return from_label<T>(ld_at(a.lab + plane, lab_off<T>((uint32_t)off)), a.qc);
+    return ld_at(a.umc + plane, (uint32_t)off);
+  };
+  const T cv0 = coef(pe, rE + cO), cv1 = coef(pe, rO + cE), cv2 = coef(pe, rO + cO);
+  const T cv3 = coef(po, rE + cE), cv4 = coef(po, rE + cO), cv5 = coef(po, rO + cE), cv6 = coef(po, rO + cO);
   const T wxl = q1ok ? a.ax[2].wl[2 * X0 + 2 * bb + 1] : T(0), wxr = q1ok ? a.ax[2].wr[2 * X0 + 2 * bb + 1] : T(0);
   const T wyl = r1ok ? a.ax[1].wl[2 * Y0 + 2 * ba + 1] : T(0), wyr = r1ok ? a.ax[1].wr[2 * Y0 + 2 * ba + 1] : T(0);
   const T wzl = odd_in ? ldu(a.ax[0].wl, 2 * J + 1) : T(0), wzr = odd_in ? ldu(a.ax[0].wr, 2 * J + 1) : T(0);
@@ -1032,9 +1079,9 @@ __device__ __forceinline__ void interp_plane_body(const InterpArgs<T> a, const i
   }
 }
 
-template <typename T, int TX, int TY, int NTP>
+template <typename T, int TX, int TY, int NTP, bool LAB>
 __global__ void __launch_bounds__(NTP) k_interp_plane(InterpArgs<T> a) {
-  interp_plane_body<T, TX, TY, NTP>(a, xcd_remap(blockIdx.x, gridDim.x));
+  interp_plane_body<T, TX, TY, NTP, LAB>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -1498,7 +1545,7 @@ __device__ __forceinline__ void quantize_box_body(const T *__restrict__ umc, int
     l = max(l, pos_level(z, a.off[0], a.first));
     if (l < a.sel_lo || l > a.sel_hi) continue;
     const uint32_t idx = (z * (uint32_t)a.n1 + y) * (uint32_t)a.n2 + x;
-    const double t = (double)umc[idx] / s_q[l - a.first];
+    const double t = (double)umc[a.box_compact ? i : idx] / s_q[l - a.first];
     labels[idx] = !(fabs(t) < 2147483647.0) ? INT32_MIN : (int32_t)rint(t);
   }
 }
@@ -1520,7 +1567,7 @@ __device__ __forceinline__ void dequantize_box_body(const int32_t *__restrict__ 
     l = max(l, pos_level(z, a.off[0], a.first));
     if (l < a.sel_lo || l > a.sel_hi) continue;
     const uint32_t idx = (z * (uint32_t)a.n1 + y) * (uint32_t)a.n2 + x;
-    umc[idx] = (T)((double)labels[idx] * s_q[l - a.first]);
+    umc[a.box_compact ? i : idx] = (T)((double)labels[idx] * s_q[l - a.first]);
   }
 }
 
@@ -1585,10 +1632,17 @@ hipError_t launch_load_vector(StencilArgs<T> a, bool dec, hipStream_t st, Tuning
   if (!tile_grid(a.ax[0].c, a.ax[1].c, a.ax[2].c, TX, TY, &a.ntx, &a.nty, &a.nzc, &a.tz, tn))
     return hipErrorInvalidValue;
   dim3 grid(a.ntx * a.nty * a.nzc);
-  if (dec)
-    hipLaunchKernelGGL((k_load_vector<T, TX, TY, NT, true>), grid, dim3(NT), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_load_vector<T, TX, TY, NT, false>), grid, dim3(NT), 0, st, a);
+  if (dec) {
+    if (a.lab_w)
+      hipLaunchKernelGGL((k_load_vector<T, TX, TY, NT, true, true>), grid, dim3(NT), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_load_vector<T, TX, TY, NT, true, false>), grid, dim3(NT), 0, st, a);
+  } else {
+    if (a.lab_r)
+      hipLaunchKernelGGL((k_load_vector<T, TX, TY, NT, false, true>), grid, dim3(NT), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_load_vector<T, TX, TY, NT, false, false>), grid, dim3(NT), 0, st, a);
+  }
   return hipGetLastError();
 }
 
@@ -1614,11 +1668,17 @@ hipError_t launch_interp_add(InterpArgs<T> a, hipStream_t st, Tuning tn) {
     a.nzc = a.ax[0].c;
     a.tz = 1;
     dim3 grid(a.ntx * a.nty * a.nzc);
-    hipLaunchKernelGGL((k_interp_plane<T, TX, TY, NTP>), grid, dim3(NTP), 0, st, a);
+    if (a.lab)
+      hipLaunchKernelGGL((k_interp_plane<T, TX, TY, NTP, true>), grid, dim3(NTP), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_interp_plane<T, TX, TY, NTP, false>), grid, dim3(NTP), 0, st, a);
     return hipGetLastError();
   }
   dim3 grid(a.ntx * a.nty * a.nzc);
-  hipLaunchKernelGGL((k_interp_add<T, TX, TY, NT>), grid, dim3(NT), 0, st, a);
+  if (a.lab)
+    hipLaunchKernelGGL((k_interp_add<T, TX, TY, NT, true>), grid, dim3(NT), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_interp_add<T, TX, TY, NT, false>), grid, dim3(NT), 0, st, a);
   return hipGetLastError();
 }
 
@@ -1972,7 +2032,9 @@ __device__ __forceinline__ void tail_dec_body(const TailArgs<T> &a) {
       // nodal corners of V at level indices: the interpolant reads V at
       // 2*lo, 2*hi, i.e. a coarse view with doubled pitches
       const T v = V[q] - tail_interp<T>(V, 2 * m1 * m2, 2 * m2, 2, ax, j0, j1, j2);
-      a.umc[lcp(j0, c0) * a.up0 + lcp(j1, c1) * a.up1 + lcp(j2, c2)] = v;
+      const int64_t pos = lcp(j0, c0) * a.up0 + lcp(j1, c1) * a.up1 + lcp(j2, c2);
+      if (a.umc) a.umc[pos] = v;
+      if (a.lab_w) a.lab_w[pos] = label_of(v, a.q[i]);
     }
     // Q_{l-1} u = Mc^{-1} (R M)^{x3} V (as in the tiled decomposition)
     T *F = (i & 1) ? fB : fA;
@@ -1981,7 +2043,9 @@ __device__ __forceinline__ void tail_dec_body(const TailArgs<T> &a) {
     if (i == a.nlev - 1) {
       for (int q = tid; q < c0 * c1 * c2; q += kTailThreads) {
         const int X = q % c2, r = q / c2, Y = r % c1, Z = r / c1;
-        a.umc[Z * a.up0 + Y * a.up1 + X] = F[q];
+        const int64_t pos = Z * a.up0 + Y * a.up1 + X;
+        if (a.umc) a.umc[pos] = F[q];
+        if (a.lab_w) a.lab_w[pos] = label_of(F[q], a.q[a.nlev]);
       }
     }
     V = F;
@@ -2003,7 +2067,8 @@ __device__ __forceinline__ void tail_rec_body(const TailArgs<T> &a) {
     const int c0 = ax[0].c, c1 = ax[1].c, c2 = ax[2].c;
     for (int q = tid; q < c0 * c1 * c2; q += kTailThreads) {
       const int X = q % c2, r = q / c2, Y = r % c1, Z = r / c1;
-      vB[q] = U[Z * a.up0 + Y * a.up1 + X];
+      const int64_t pos = Z * a.up0 + Y * a.up1 + X;
+      vB[q] = a.lab_r ? from_label<T>(a.lab_r[pos], a.q[a.nlev]) : U[pos];
     }
   }
   for (int i = 0; i < a.nlev; i++) {
@@ -2020,7 +2085,14 @@ __device__ __forceinline__ void tail_rec_body(const TailArgs<T> &a) {
         const int q = tid + k * kTailThreads;
         const int j2 = q % m2, t = q / m2, j1 = t % m1, j0 = t / m1;
         const bool coef = q < n && ((j0 | j1 | j2) & 1);
-        r[k] = coef ? U[lcp(j0, c0) * a.up0 + lcp(j1, c1) * a.up1 + lcp(j2, c2)] : T(0);
+        const int64_t pos = coef ? lcp(j0, c0) * a.up0 + lcp(j1, c1) * a.up1 + lcp(j2, c2) : 0;
+        if (a.lab_r) {
+          const int32_t lv = a.lab_r[pos];
+          r[k] = coef ? from_label<T>(lv, a.q[a.nlev - 1 - i]) : T(0);
+        } else {
+          const T cvv = U[pos];
+          r[k] = coef ? cvv : T(0);
+        }
       }
 #pragma unroll
       for (int k = 0; k < R; k++)
@@ -2086,21 +2158,21 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MGX_STE
 k_load_vector_multi(MultiArgs<T> m) {
   const int g = xcd_remap(blockIdx.x, gridDim.x);
   const int f = find_op(m.start, m.n, g);
-  load_vector_body<T, TX, TY, NT, DEC>(m.args[f].st, g - m.start[f]);
+  load_vector_body<T, TX, TY, NT, DEC, false>(m.args[f].st, g - m.start[f]);
 }
 
 template <typename T, int TX, int TY, int NT>
 __global__ void __launch_bounds__(NT) k_interp_add_multi(MultiArgs<T> m) {
   const int g = xcd_remap(blockIdx.x, gridDim.x);
   const int f = find_op(m.start, m.n, g);
-  interp_add_body<T, TX, TY, NT>(m.args[f].ia, g - m.start[f]);
+  interp_add_body<T, TX, TY, NT, false>(m.args[f].ia, g - m.start[f]);
 }
 
 template <typename T, int TX, int TY, int NTP>
 __global__ void __launch_bounds__(NTP) k_interp_plane_multi(MultiArgs<T> m) {
   const int g = xcd_remap(blockIdx.x, gridDim.x);
   const int f = find_op(m.start, m.n, g);
-  interp_plane_body<T, TX, TY, NTP>(m.args[f].ia, g - m.start[f]);
+  interp_plane_body<T, TX, TY, NTP, false>(m.args[f].ia, g - m.start[f]);
 }
 
 template <typename T, int E, int G>

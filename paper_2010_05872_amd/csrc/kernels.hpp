@@ -35,6 +35,9 @@ struct StencilArgs {
   int64_t up0, up1;           // u_mc pitches (finest grid)
   T *F;                       // load vector out, coarse box
   int64_t fp0, fp1;
+  int32_t *lab_w;             // decompose: also write the quantization labels (u_mc's layout)
+  const int32_t *lab_r;       // recompose: read labels instead of coefficients
+  double qc;                  // bin width q_l of the level's coefficients (labels)
   int ntx, nty, nzc, tz;      // set by the launcher
 };
 
@@ -47,6 +50,8 @@ struct InterpArgs {
   int64_t up0, up1;
   T *out;                     // level-l box out
   int64_t op0, op1;
+  const int32_t *lab;         // non-null: read labels (times qc) instead of coefficients
+  double qc;
   int ntx, nty, nzc, tz;
 };
 
@@ -129,6 +134,9 @@ struct TailArgs {
   int64_t up0, up1;
   T *dst;                        // recompose: the level-lt box out
   int64_t dp0, dp1;
+  int32_t *lab_w;                // decompose: also (umc null: only) write labels
+  const int32_t *lab_r;          // recompose: read labels instead of coefficients
+  double q[kTailMax + 1];        // bin widths: q[i] of level lt - i, q[nlev] of the stop box
 };
 
 struct QuantArgs {
@@ -143,6 +151,7 @@ struct QuantArgs {
   int64_t bn;                 // b0 * b1 * b2
   uint64_t bmag1, bmag2;      // ceil(2^64 / b1), ceil(2^64 / b2)
   int max_blocks;             // > 0: at most this many workgroups (work running beside other kernels)
+  int box_compact;            // box mode: the coefficient side is a compact b0 x b1 x b2 buffer
   double q[kMaxLevelsK];      // bin width per level
   int *stats_max;             // [nlev] device
   unsigned long long *stats_ovf, *stats_nan;

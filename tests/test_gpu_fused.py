@@ -1,7 +1,7 @@
-"""Fused decompose+quantize and dequantize+recompose (the finest level's
-(de)quantization on a second stream): results equal the separate calls bit
-for bit, on shapes with and without the single-workgroup tail, 1-D to 3-D,
-both dtypes, and every kind of stop level."""
+"""Fused decompose+quantize and dequantize+recompose (labels written and read
+by the level kernels themselves): results equal the separate calls bit for
+bit, with and without u_mc, on shapes with and without the single-workgroup
+tail, 1-D to 3-D, both dtypes, and every kind of stop level."""
 import sys
 
 import numpy as np
@@ -21,6 +21,7 @@ CASES = [
     ((257, 129), torch.float32, "random"),
     ((4097,), torch.float64, None),
     ((129, 9, 33), torch.float32, "tanh"),
+    ((9, 257, 5), torch.float64, None),      # level boxes never all within the tail
 ]
 
 
@@ -56,6 +57,14 @@ def test_fused_equals_separate(case):
         assert torch.equal(coef, dq), stop
         assert torch.equal(out, rr), stop
         assert (out.double() - u.double()).abs().max().item() <= tol
+        # labels only (no u_mc), and recomposition straight from the labels
+        none, lab2 = mgx.decompose_quantize(u, tol, coords, stop, keep_coef=False)
+        out2 = torch.full_like(u, float("nan"))
+        mgx.dequantize_recompose(lab2, tol, dt, coords, stop, out=out2)
+        torch.cuda.synchronize()
+        assert none is None
+        assert torch.equal(lab2, rlab), stop
+        assert torch.equal(out2, rr), stop
 
 
 def test_fused_back_to_back_reuse():
@@ -77,3 +86,22 @@ def test_fused_back_to_back_reuse():
         ref = mgx.recompose(mgx.dequantize(mgx.quantize(mgx.decompose(u), tol), tol, torch.float32))
         torch.cuda.synchronize()
         assert torch.equal(out, ref), i
+
+
+def test_fused_labels_back_to_back_smaller():
+    """Coefficient-free calls that share one workspace, the second on a
+    smaller field: the stop box held in the workspace is rewritten each call."""
+    ws = torch.full((mgx.workspace_size(mgx.MGX_F32, (129, 129, 65), 0) // 4 + 64,), float("nan"),
+                    dtype=torch.float32, device="cuda").view(torch.uint8)
+    for shape, stop in (((129, 129, 65), 5), ((65, 33, 33), 4)):
+        print(f"[fused-labels] {shape} stop {stop}", flush=True)
+        u = torch.as_tensor(workloads.gaussian_random_field(shape, slope=3.0, seed=11), dtype=torch.float32,
+                            device="cuda")
+        tol = 1e-4 * float((u.max() - u.min()).item())
+        _, lab = mgx.decompose_quantize(u, tol, None, stop, keep_coef=False, workspace=ws)
+        out = mgx.dequantize_recompose(lab, tol, torch.float32, None, stop, workspace=ws)
+        rlab = mgx.quantize(mgx.decompose(u, None, stop), tol, None, stop)
+        rr = mgx.recompose(mgx.dequantize(rlab, tol, torch.float32, None, stop), None, stop)
+        torch.cuda.synchronize()
+        assert torch.equal(lab, rlab)
+        assert torch.equal(out, rr)
