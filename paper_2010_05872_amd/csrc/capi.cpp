@@ -312,7 +312,7 @@ mgx_status run_decompose(Plan *P, int stop, const T *u, T *umc, char *ws, const 
       s.lab_w = labels;
       s.qc = qa->q[l - stop];
     }
-    hipError_t e = em.op(kOpLoadVecDec, 0, "load_vector_dec", l, o);
+    hipError_t e = em.op(kOpLoadVecDec, 0, labels ? "load_vector_dec+q" : "load_vector_dec", l, o);
     if (e != hipSuccess) return MGX_ERR_HIP;
     // Q_{l-1} u goes to the compact box of level l-1, or into the corner of
     // u_mc after the last decomposed level (the compact stop box without u_mc)
@@ -339,7 +339,7 @@ mgx_status run_decompose(Plan *P, int stop, const T *u, T *umc, char *ws, const 
       for (int i = 0; i < o.tl.nlev; i++) o.tl.q[i] = qa->q[lay.lt - i - stop];
       o.tl.q[o.tl.nlev] = qa->q[0];
     }
-    if (em.op(kOpTailDec, 0, "tail_dec", lay.lt, o) != hipSuccess) return MGX_ERR_HIP;
+    if (em.op(kOpTailDec, 0, labels ? "tail_dec+q" : "tail_dec", lay.lt, o) != hipSuccess) return MGX_ERR_HIP;
   } else if (labels) {  // the stop box's labels
     QuantArgs b = *qa;
     quant_box(P, b, stop);
@@ -399,7 +399,7 @@ mgx_status run_recompose(Plan *P, int stop, const T *umc, T *u, char *ws, const 
       o.tl.dp1 = a2.m;
       o.tl.dp0 = a1.m * a2.m;
     }
-    if (em.op(kOpTailRec, 0, "tail_rec", lay.lt, o) != hipSuccess) return MGX_ERR_HIP;
+    if (em.op(kOpTailRec, 0, labels ? "tail_rec+q" : "tail_rec", lay.lt, o) != hipSuccess) return MGX_ERR_HIP;
     first_tiled = lay.lt + 1;
   }
   for (int l = first_tiled; l <= L; l++) {
@@ -426,7 +426,7 @@ mgx_status run_recompose(Plan *P, int stop, const T *umc, T *u, char *ws, const 
       s.lab_r = labels;
       s.qc = qa->q[l - stop];
     }
-    hipError_t e = em.op(kOpLoadVecRec, 0, "load_vector_rec", l, o);
+    hipError_t e = em.op(kOpLoadVecRec, 0, labels ? "load_vector_rec+q" : "load_vector_rec", l, o);
     if (e != hipSuccess) return MGX_ERR_HIP;
     e = solve_level<T>(l, ax, P->real, F, fp0, fp1, kSolveApply, nin, ip0, ip1, nb, cp0, cp1, em);
     if (e != hipSuccess) return MGX_ERR_HIP;
@@ -452,7 +452,7 @@ mgx_status run_recompose(Plan *P, int stop, const T *umc, T *u, char *ws, const 
       ia.op1 = m2;
       ia.op0 = (int64_t)m1 * m2;
     }
-    e = em.op(kOpInterpAdd, 0, "interp_add", l, oi);
+    e = em.op(kOpInterpAdd, 0, labels ? "interp_add+q" : "interp_add", l, oi);
     if (e != hipSuccess) return MGX_ERR_HIP;
   }
   return MGX_OK;

@@ -126,6 +126,40 @@ __device__ __forceinline__ int32_t label_of(T v, double q) {
   const double t = (double)v / q;
   return !(fabs(t) < 2147483647.0) ? INT32_MIN : (int32_t)rint(t);
 }
+// 1/q rounded to FP32 for the fast path below; NaN (fast path never taken)
+// when it falls outside FP32's normal range.
+__device__ __forceinline__ float label_rcp(double q) {
+  const double r = 1.0 / q;
+  return (r >= 1.1754943508222875e-38 && r <= 3.4028234663852886e38) ? (float)r : __builtin_nanf("");
+}
+// The same decision for an FP32 coefficient, mostly without the FP64
+// division.  t = v * rq in FP32 is within about 2^-23 |v/q| of the exact
+// quotient (two roundings of 2^-24, one in rq and one in the product), and
+// the FP64 quotient within 2^-53 of it.  With r = rint(t), d = |t - r| is
+// exact and 0.5 - d is t's distance to the nearest half-integer; when that
+// exceeds |t| 2^-21, both quotients sit strictly inside the same interval
+// between half-integers and round to r.  The test d + |t| 2^-21 < 0.5 is a
+// single FMA (its rounding cannot turn a sum >= 0.5 into one below), it
+// fails for |t| >= 2^20 (labels stay far inside int32) and for non-finite
+// t; there *ok is false and the FP64 division decides.  Relies on IEEE
+// subnormals (no flush to zero in this build).
+__device__ __forceinline__ int32_t label_fast(float v, float rq, bool &ok) {
+  const float t = v * rq;
+  const float r = rintf(t);
+  ok = __builtin_fmaf(fabsf(t), 0x1p-21f, fabsf(t - r)) < 0.5f;
+  return (int32_t)(ok ? r : 0.0f);
+}
+__device__ __forceinline__ int32_t label_fast(double, float, bool &ok) {
+  ok = false;  // FP64 coefficients: always the division
+  return 0;
+}
+template <typename T>
+__device__ __forceinline__ int32_t label_of(T v, double q, float rq) {
+  bool ok;
+  const int32_t l = label_fast(v, rq, ok);
+  if (__builtin_expect(ok, 1)) return l;
+  return label_of<T>(v, q);
+}
 // A coefficient from its label (the dequantization pass's operations).
 template <typename T>
 __device__ __forceinline__ T from_label(int32_t l, double q) {
@@ -216,6 +250,7 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
   const int fr = min(2 * Y1, m1) - 2 * Y0;  // owned fine rows
   const int fq = min(2 * X1, m2) - 2 * X0;  // owned fine columns
   const int own_p0 = 2 * Z0, own_p1 = min(2 * Z1, m0);
+  const float rq = (DEC && LAB) ? label_rcp(a.qc) : 0.0f;
 
   // ---- plane loads: global and LDS offsets of this thread's NE region
   //      elements (the same in every plane) ----
@@ -350,25 +385,47 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
       T *const cbase = a.umc_w + lc_pos(j, c0) * a.up0;
       int32_t *const lbase = LAB ? a.lab_w + lc_pos(j, c0) * a.up0 : nullptr;
       const bool wc = a.umc_w != nullptr;
-      // a coefficient to u_mc and / or its label
-      auto put = [&](uint32_t off, T v) {
-        if (wc) st_once(cbase, off, v);
-        if (LAB) st_at(lbase, lab_off<T>(off), label_of(v, a.qc));
+      // the coefficients cv[p0..3] of one 2x2 block (nodes 00, 01, 10, 11 at
+      // byte offsets oE + {0, colOdd, rowOdd, rowOdd + colOdd}) to u_mc and /
+      // or their labels, for the nodes in f.  Labels are stored from the FP32
+      // fast path; the rare ones it cannot decide are then overwritten (same
+      // lane, same address: the stores stay in order) with the FP64 decision.
+      auto emit = [&](const int p0, const unsigned f, const uint32_t oE, const T (&cv)[4]) {
+        unsigned slow = 0;
+#pragma unroll
+        for (int p = p0; p < 4; p++) {
+          const uint32_t off = oE + ((p & 1) ? colOdd : 0u) + ((p & 2) ? rowOdd : 0u);
+          if ((f >> p) & 1u) {
+            if (wc) st_once(cbase, off, cv[p]);
+            if (LAB) {
+              bool ok;
+              st_at(lbase, lab_off<T>(off), label_fast(cv[p], rq, ok));
+              slow |= (unsigned)!ok << p;
+            }
+          }
+        }
+        if (LAB && __builtin_expect(slow != 0u, 0)) {
+#pragma unroll
+          for (int p = p0; p < 4; p++)
+            if ((slow >> p) & 1u) {
+              const uint32_t off = oE + ((p & 1) ? colOdd : 0u) + ((p & 2) ? rowOdd : 0u);
+              st_at(lbase, lab_off<T>(off), label_of<T>(cv[p], a.qc));
+            }
+        }
       };
       if (!pz) {
         // even plane: corners in the plane itself; node 00 is nodal
 #pragma unroll
         for (int k = 0; k < NB; k++) {
-          const unsigned f = cn >> (4 * k);
-          if (f & 0xEu) {
+          const unsigned f = (cn >> (4 * k)) & 0xEu;
+          if (f) {
             const int R0 = cR0[k], R2 = cR0[k] + 2 * W, e0 = cE0[k];
             const T C00 = sV[s0][R0 + e0], C02 = sV[s0][R0 + e0 + 1];
             const T C20 = sV[s0][R2 + e0], C22 = sV[s0][R2 + e0 + 1];
             const T t0 = cwxl[k] * C00 + cwxr[k] * C02, t2 = cwxl[k] * C20 + cwxr[k] * C22;
-            const uint32_t oE = (uint32_t)(cRowE[k] + cColE[k]);
-            if (f & 2u) put(oE + colOdd, sV[s0][R0 + E + e0] - t0);
-            if (f & 4u) put(oE + rowOdd, sV[s0][R0 + W + e0] - (cwyl[k] * C00 + cwyr[k] * C20));
-            if (f & 8u) put(oE + rowOdd + colOdd, sV[s0][R0 + W + E + e0] - (cwyl[k] * t0 + cwyr[k] * t2));
+            const T cv[4] = {T(0), sV[s0][R0 + E + e0] - t0, sV[s0][R0 + W + e0] - (cwyl[k] * C00 + cwyr[k] * C20),
+                             sV[s0][R0 + W + E + e0] - (cwyl[k] * t0 + cwyr[k] * t2)};
+            emit(1, f, (uint32_t)(cRowE[k] + cColE[k]), cv);
           }
         }
       } else {
@@ -377,22 +434,19 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
         const T wzl = ldu(a.ax[0].wl, j), wzr = ldu(a.ax[0].wr, j);
 #pragma unroll
         for (int k = 0; k < NB; k++) {
-          const unsigned f = cn >> (4 * k);
-          if (f & 0xFu) {
+          const unsigned f = (cn >> (4 * k)) & 0xFu;
+          if (f) {
             const int R0 = cR0[k], R2 = cR0[k] + 2 * W, e0 = cE0[k];
             const T A00 = sV[sa][R0 + e0], A02 = sV[sa][R0 + e0 + 1], A20 = sV[sa][R2 + e0], A22 = sV[sa][R2 + e0 + 1];
             const T B00 = sV[sb][R0 + e0], B02 = sV[sb][R0 + e0 + 1], B20 = sV[sb][R2 + e0], B22 = sV[sb][R2 + e0 + 1];
             const T wxl = cwxl[k], wxr = cwxr[k], wyl = cwyl[k], wyr = cwyr[k];
             const T ta0 = wxl * A00 + wxr * A02, ta2 = wxl * A20 + wxr * A22;
             const T tb0 = wxl * B00 + wxr * B02, tb2 = wxl * B20 + wxr * B22;
-            const uint32_t oE = (uint32_t)(cRowE[k] + cColE[k]);
-            if (f & 1u) put(oE, sV[s0][R0 + e0] - (wzl * A00 + wzr * B00));
-            if (f & 2u) put(oE + colOdd, sV[s0][R0 + E + e0] - (wzl * ta0 + wzr * tb0));
-            if (f & 4u)
-              put(oE + rowOdd, sV[s0][R0 + W + e0] - (wzl * (wyl * A00 + wyr * A20) + wzr * (wyl * B00 + wyr * B20)));
-            if (f & 8u)
-              put(oE + rowOdd + colOdd,
-                  sV[s0][R0 + W + E + e0] - (wzl * (wyl * ta0 + wyr * ta2) + wzr * (wyl * tb0 + wyr * tb2)));
+            const T cv[4] = {
+                sV[s0][R0 + e0] - (wzl * A00 + wzr * B00), sV[s0][R0 + E + e0] - (wzl * ta0 + wzr * tb0),
+                sV[s0][R0 + W + e0] - (wzl * (wyl * A00 + wyr * A20) + wzr * (wyl * B00 + wyr * B20)),
+                sV[s0][R0 + W + E + e0] - (wzl * (wyl * ta0 + wyr * ta2) + wzr * (wyl * tb0 + wyr * tb2))};
+            emit(0, f, (uint32_t)(cRowE[k] + cColE[k]), cv);
           }
         }
       }
@@ -2034,7 +2088,7 @@ __device__ __forceinline__ void tail_dec_body(const TailArgs<T> &a) {
       const T v = V[q] - tail_interp<T>(V, 2 * m1 * m2, 2 * m2, 2, ax, j0, j1, j2);
       const int64_t pos = lcp(j0, c0) * a.up0 + lcp(j1, c1) * a.up1 + lcp(j2, c2);
       if (a.umc) a.umc[pos] = v;
-      if (a.lab_w) a.lab_w[pos] = label_of(v, a.q[i]);
+      if (a.lab_w) a.lab_w[pos] = label_of(v, a.q[i], label_rcp(a.q[i]));
     }
     // Q_{l-1} u = Mc^{-1} (R M)^{x3} V (as in the tiled decomposition)
     T *F = (i & 1) ? fB : fA;
@@ -2045,7 +2099,7 @@ __device__ __forceinline__ void tail_dec_body(const TailArgs<T> &a) {
         const int X = q % c2, r = q / c2, Y = r % c1, Z = r / c1;
         const int64_t pos = Z * a.up0 + Y * a.up1 + X;
         if (a.umc) a.umc[pos] = F[q];
-        if (a.lab_w) a.lab_w[pos] = label_of(F[q], a.q[a.nlev]);
+        if (a.lab_w) a.lab_w[pos] = label_of(F[q], a.q[a.nlev], label_rcp(a.q[a.nlev]));
       }
     }
     V = F;

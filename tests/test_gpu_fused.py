@@ -105,3 +105,46 @@ def test_fused_labels_back_to_back_smaller():
         torch.cuda.synchronize()
         assert torch.equal(lab, rlab)
         assert torch.equal(out, rr)
+
+
+def test_fused_labels_near_ties():
+    """Finest-level coefficients placed on and around the quantizer's
+    half-integer ties (and beyond the FP32 fast path's range): with the
+    coarse nodes zero, each finest coefficient is the field value itself, so
+    the labels the decomposition kernel writes must equal the FP64 division's
+    decision of the separate pass at every such node."""
+    shape = (65, 65, 65)
+    L = mgx.num_levels(shape)
+    stop = L - 1
+    rng = np.random.default_rng(2024)
+    tol = 1.0
+    q = 2.0 * float(mgx.level_tolerances(shape, tol, None, stop)[-1])
+    idx = np.indices(shape)
+    coef_node = ((idx[0] | idx[1] | idx[2]) & 1).astype(bool)
+    n = int(coef_node.sum())
+    k = rng.integers(-3000, 3000, n).astype(np.float64)
+    big = rng.random(n) < 0.1
+    k[big] = rng.integers(60000, 70000, int(big.sum())) * rng.choice([-1.0, 1.0], int(big.sum()))
+    huge = rng.random(n) < 0.02
+    k[huge] = rng.integers(2 ** 20, 2 ** 28, int(huge.sum())).astype(np.float64)
+    v = ((k + 0.5) * q).astype(np.float32)
+    steps = rng.integers(-3, 4, n)
+    for s in range(3):  # nudge by up to 3 ulps either way
+        up, dn = steps > s, steps < -s
+        v[up] = np.nextafter(v[up], np.float32(np.inf))
+        v[dn] = np.nextafter(v[dn], np.float32(-np.inf))
+    off = rng.random(n) < 0.2  # some far from ties
+    v[off] = (rng.normal(size=int(off.sum())) * 1000 * q).astype(np.float32)
+    host = np.zeros(shape, dtype=np.float32)
+    host[coef_node] = v
+    u = torch.as_tensor(host, device="cuda")
+    _, lab = mgx.decompose_quantize(u, tol, None, stop, keep_coef=False)
+    ref = mgx.decompose(u, None, stop)
+    rlab = mgx.quantize(ref, tol, None, stop)
+    torch.cuda.synchronize()
+    assert torch.equal(lab, rlab)
+    # the finest coefficients are the values themselves, at level-centric positions
+    lc = [np.where(np.arange(m) % 2 == 1, (m + 1) // 2 + np.arange(m) // 2, np.arange(m) // 2) for m in shape]
+    pos = lab.cpu().numpy()[np.ix_(*lc)]
+    want = np.rint(host.astype(np.float64) / q).astype(np.int32)
+    assert np.array_equal(pos[coef_node], want[coef_node])
