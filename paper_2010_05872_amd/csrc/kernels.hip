@@ -40,11 +40,23 @@
 #ifndef MGX_STENCIL_WAVES
 #define MGX_STENCIL_WAVES 4
 #endif
+#ifndef MGX_REC_WAVES
+#define MGX_REC_WAVES MGX_STENCIL_WAVES
+#endif
 #ifndef MGX_DEEP_CH
 #define MGX_DEEP_CH 32
 #endif
+#ifndef MGX_F32_TX
+#define MGX_F32_TX 32
+#endif
 #ifndef MGX_F32_TY
 #define MGX_F32_TY 16
+#endif
+#ifndef MGX_F32_INTERP_TX
+#define MGX_F32_INTERP_TX 64
+#endif
+#ifndef MGX_F32_INTERP_TY
+#define MGX_F32_INTERP_TY 8
 #endif
 #ifndef MGX_F32_NT
 #define MGX_F32_NT 512
@@ -232,7 +244,11 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
   constexpr int NB = NOUT;                       // 2x2 coefficient blocks per thread
 
   __shared__ T sV[NV][HR * W];
-  __shared__ T sG[HR * GW];
+  // x-restricted rows of the plane, double-buffered by plane parity: the one
+  // barrier per plane then separates every LDS write from the reads of the
+  // same words (x-restriction of plane j+2 vs y-restriction of plane j;
+  // commit of plane j+AHEAD vs the reads of that slot one iteration before)
+  __shared__ T sGbuf[2][HR * GW];
 
   const int tid = threadIdx.x;
   const int m0 = a.ax[0].m, m1 = a.ax[1].m, m2 = a.ax[2].m;
@@ -368,6 +384,7 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
     const bool plane_in = (j >= 0 && j < m0);
     const int pz = j & 1;
     const int s0 = slot_of(j);
+    T *const sG = sGbuf[j & 1];
     // ---- restriction along x of plane j: sG[r][X] ----
     if (plane_in && xact) {
 #pragma unroll
@@ -493,7 +510,6 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
         acc[2][k] = T(0);
       }
     }
-    __syncthreads();
     // the loads for plane j + AHEAD + DEPTH are issued after every store of
     // this iteration, so the commit DEPTH iterations later needs a partial
     // wait only
@@ -522,7 +538,7 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
 }
 
 template <typename T, int TX, int TY, int NT, bool DEC, bool LAB>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MGX_STENCIL_WAVES, 8)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(DEC ? MGX_STENCIL_WAVES : MGX_REC_WAVES, 8)))
 k_load_vector(StencilArgs<T> a) {
   load_vector_body<T, TX, TY, NT, DEC, LAB>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
@@ -1645,11 +1661,19 @@ template <typename T>
 struct Tiles;
 template <>
 struct Tiles<float> {
-  static constexpr int TX = 32, TY = MGX_F32_TY, NT = MGX_F32_NT;
+  static constexpr int TX = MGX_F32_TX, TY = MGX_F32_TY, NT = MGX_F32_NT;
 };
 template <>
 struct Tiles<double> {
   static constexpr int TX = 16, TY = MGX_F64_TY, NT = MGX_F64_NT;
+};
+// Tiles of the interpolation kernels (wider rows than the load vector's:
+// longer store runs per row, measured faster on MI355X)
+template <typename T>
+struct InterpTiles : Tiles<T> {};
+template <>
+struct InterpTiles<float> {
+  static constexpr int TX = MGX_F32_INTERP_TX, TY = MGX_F32_INTERP_TY, NT = MGX_F32_NT;
 };
 
 // Tiles of TX x TY coarse columns/rows (the last tile takes the extra node of
@@ -1708,12 +1732,12 @@ static bool interp_plane(const InterpArgs<T> &a) {
 }
 template <typename T>
 constexpr int interp_plane_threads() {
-  return ((Tiles<T>::TY + 1) * (Tiles<T>::TX + 1) + 63) / 64 * 64;
+  return ((InterpTiles<T>::TY + 1) * (InterpTiles<T>::TX + 1) + 63) / 64 * 64;
 }
 
 template <typename T>
 hipError_t launch_interp_add(InterpArgs<T> a, hipStream_t st, Tuning tn) {
-  constexpr int TX = Tiles<T>::TX, TY = Tiles<T>::TY, NT = Tiles<T>::NT;
+  constexpr int TX = InterpTiles<T>::TX, TY = InterpTiles<T>::TY, NT = InterpTiles<T>::NT;
   if (!tile_grid(a.ax[0].c, a.ax[1].c, a.ax[2].c, TX, TY, &a.ntx, &a.nty, &a.nzc, &a.tz, tn))
     return hipErrorInvalidValue;
   if (interp_plane(a)) {
@@ -2208,7 +2232,7 @@ __device__ __forceinline__ int find_op(const int *__restrict__ start, int n, int
 }
 
 template <typename T, int TX, int TY, int NT, bool DEC>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MGX_STENCIL_WAVES, 8)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(DEC ? MGX_STENCIL_WAVES : MGX_REC_WAVES, 8)))
 k_load_vector_multi(MultiArgs<T> m) {
   const int g = xcd_remap(blockIdx.x, gridDim.x);
   const int f = find_op(m.start, m.n, g);
@@ -2344,7 +2368,8 @@ int op_blocks(int kind, int mode, OpArgs<T> &a, const Tuning &tn) {
     }
     case kOpInterpAdd: {
       InterpArgs<T> &s = a.ia;
-      if (!tile_grid(s.ax[0].c, s.ax[1].c, s.ax[2].c, TX, TY, &s.ntx, &s.nty, &s.nzc, &s.tz, tn)) return -1;
+      constexpr int IX = InterpTiles<T>::TX, IY = InterpTiles<T>::TY;
+      if (!tile_grid(s.ax[0].c, s.ax[1].c, s.ax[2].c, IX, IY, &s.ntx, &s.nty, &s.nzc, &s.tz, tn)) return -1;
       if (interp_plane(s)) {
         s.nzc = s.ax[0].c;
         s.tz = 1;
@@ -2432,10 +2457,12 @@ hipError_t launch_op_multi(int kind, int key, const OpArgs<T> *dargs, const int 
   switch (kind) {
     case kOpLoadVecDec: MGX_MULTI((k_load_vector_multi<T, TX, TY, NT, true>), NT); break;
     case kOpLoadVecRec: MGX_MULTI((k_load_vector_multi<T, TX, TY, NT, false>), NT); break;
-    case kOpInterpAdd:
-      if (key) MGX_MULTI((k_interp_plane_multi<T, TX, TY, interp_plane_threads<T>()>), interp_plane_threads<T>());
-      else MGX_MULTI((k_interp_add_multi<T, TX, TY, NT>), NT);
+    case kOpInterpAdd: {
+      constexpr int IX = InterpTiles<T>::TX, IY = InterpTiles<T>::TY, INT = InterpTiles<T>::NT;
+      if (key) MGX_MULTI((k_interp_plane_multi<T, IX, IY, interp_plane_threads<T>()>), interp_plane_threads<T>());
+      else MGX_MULTI((k_interp_add_multi<T, IX, IY, INT>), INT);
       break;
+    }
     case kOpApply: MGX_MULTI((k_apply_multi<T>), 256); break;
     case kOpCopyBox: MGX_MULTI((k_copy_box_multi<T>), 256); break;
     case kOpTailDec: MGX_MULTI((k_tail_dec_multi<T>), kTailThreads); break;
