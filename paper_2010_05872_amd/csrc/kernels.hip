@@ -743,7 +743,7 @@ __global__ void __launch_bounds__(256) k_solve_strided(StridedArgs<T> a) {
 // ---------------------------------------------------------------------------
 // k_solve_twisted: Thomas solve along a strided axis of the coarse box as a
 // two-ended ("twisted") factorization of the same tridiagonal matrix.  A
-// workgroup takes 128 lines (consecutive contiguous indices): waves 0-1
+// workgroup takes 128 consecutive lines in (outer, x) order: waves 0-1
 // eliminate rows 0..K-1 from the top, waves 2-3 rows C-1..K+1 from the
 // bottom (C = 2K+1), each lane keeping its half line in registers; the two
 // values next to the middle row K are swapped through LDS, the middle row is
@@ -753,15 +753,19 @@ __global__ void __launch_bounds__(256) k_solve_strided(StridedArgs<T> a) {
 // tables are scalar operands.
 // ---------------------------------------------------------------------------
 template <typename T, int C, int MODE>
-__device__ __forceinline__ void solve_twisted_body(const StridedArgs<T> a, const int bx, const int o) {
+__device__ __forceinline__ void solve_twisted_body(const StridedArgs<T> a, const int b) {
   constexpr int K = C / 2;
   __shared__ T sE[2][128];
   const int wave = threadIdx.x >> 6;
   const int half = wave >> 1;  // 0: top rows, 1: bottom rows (uniform per wave)
   const int line = (wave & 1) * 64 + (threadIdx.x & 63);
-  const int x = bx * 128 + line;
-  const bool active = x < a.nx;
-  T *p = a.F + (int64_t)o * a.so + (active ? x : 0);
+  // lines numbered over (outer, x) with x fastest, 128 per workgroup: no
+  // workgroup is left nearly empty by an extent of 2^k + 1
+  const int64_t g = (int64_t)b * 128 + line;
+  const bool active = g < (int64_t)a.nx * a.nouter;
+  const int o = active ? (int)(g / a.nx) : 0;
+  const int x = active ? (int)(g - (int64_t)o * a.nx) : 0;
+  T *p = a.F + (int64_t)o * a.so + x;
   const int64_t s = a.sj;
   T r[K];
   if (!half) {
@@ -841,7 +845,7 @@ __device__ __forceinline__ void solve_twisted_body(const StridedArgs<T> a, const
 
 template <typename T, int C, int MODE>
 __global__ void __launch_bounds__(256) k_solve_twisted(StridedArgs<T> a) {
-  solve_twisted_body<T, C, MODE>(a, blockIdx.x, blockIdx.y);
+  solve_twisted_body<T, C, MODE>(a, blockIdx.x);
 }
 
 // Last step for one-dimensional fields (no strided solve): out = in + sign * F
@@ -1789,7 +1793,7 @@ hipError_t launch_solve_contig(SolveArgs<T> a, hipStream_t st) {
 
 template <typename T, int C>
 static void launch_twisted_c(StridedArgs<T> a, int mode, hipStream_t st) {
-  dim3 grid((unsigned)((a.nx + 127) / 128), (unsigned)a.nouter);
+  dim3 grid((unsigned)(((int64_t)a.nx * a.nouter + 127) / 128));
   if (mode == kSolveApply)
     hipLaunchKernelGGL((k_solve_twisted<T, C, kSolveApply>), grid, dim3(256), 0, st, a);
   else if (mode == kSolveStore)
@@ -2265,8 +2269,7 @@ __global__ void __launch_bounds__(256) k_solve_twisted_multi(MultiArgs<T> m) {
   const int g = blockIdx.x;
   const int f = find_op(m.start, m.n, g);
   const StridedArgs<T> a = m.args[f].sd;
-  const int b = g - m.start[f], nbx = (a.nx + 127) / 128;
-  solve_twisted_body<T, C, MODE>(a, b % nbx, b / nbx);
+  solve_twisted_body<T, C, MODE>(a, g - m.start[f]);
 }
 
 template <typename T, int MODE, int CH>
@@ -2382,8 +2385,8 @@ int op_blocks(int kind, int mode, OpArgs<T> &a, const Tuning &tn) {
       return (int)((a.so.nlines + lpb - 1) / lpb);
     }
     case kOpSolveStrided: {
-      const int per = strided_twisted<T>(a.sd.c) ? 128 : 256;
-      return (int)(((int64_t)a.sd.nx + per - 1) / per * a.sd.nouter);
+      if (strided_twisted<T>(a.sd.c)) return (int)(((int64_t)a.sd.nx * a.sd.nouter + 127) / 128);
+      return (int)(((int64_t)a.sd.nx + 255) / 256 * a.sd.nouter);
     }
     case kOpApply: return (a.sd.nx + 255) / 256;
     case kOpQuantize: return grid_cap((a.qj.a.n + 1023) / 1024);
