@@ -190,6 +190,26 @@ __device__ __forceinline__ int zcol(int q) {
   return (q & 1) ? (TX + 3) + (q >> 1) : (q >> 1);
 }
 
+// Slot o of a (TY+1) x (TX+1) grid of per-tile work items (coarse outputs or
+// 2x2 fine blocks): the TY x TX interior first, then the last column, then
+// the last row.  Interior tiles own only the interior items, so with one
+// item per thread every thread of such a tile gets exactly one and the
+// per-thread loops over items are balanced across waves; slots past the
+// grid give r = TY and c > TX (callers test o against the grid size).
+template <int TX, int TY>
+__device__ __forceinline__ void tile_slot(int o, int &r, int &c) {
+  if (o < TX * TY) {
+    r = o / TX;
+    c = o - r * TX;
+  } else if (o < TX * TY + TY + 1) {
+    r = o - TX * TY;
+    c = TX;
+  } else {
+    r = TY;
+    c = o - (TX * TY + TY + 1);
+  }
+}
+
 __device__ __forceinline__ int64_t lc_pos(int j, int c) {
   // level-centric position of level index j on an axis with c coarse nodes
   return (j & 1) ? (int64_t)c + (j >> 1) : (int64_t)(j >> 1);
@@ -333,7 +353,8 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
 #pragma unroll
   for (int k = 0; k < NOUT; k++) {
     const int o = tid + NT * k;
-    const int Y = o / GW, X = o - Y * GW;
+    int Y, X;
+    tile_slot<TX, TY>(o, Y, X);
     const bool act = o < GH * GW && Y < nY && X < nX;
     yact |= (unsigned)act << k;
 #pragma unroll
@@ -351,7 +372,8 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
 #pragma unroll
     for (int k = 0; k < NB; k++) {
       const int o = tid + NT * k;
-      const int ca = o / GW, cb = o - ca * GW;
+      int ca, cb;
+      tile_slot<TX, TY>(o, ca, cb);
       const bool blk = o < GH * GW;
       const bool r0ok = blk && 2 * ca < fr, r1ok = blk && 2 * ca + 1 < fr;
       const bool q0ok = 2 * cb < fq, q1ok = 2 * cb + 1 < fq;
@@ -938,7 +960,8 @@ __device__ __forceinline__ void interp_add_body(const InterpArgs<T> a, const int
 #pragma unroll
   for (int k = 0; k < NB; k++) {
     const int o = tid + NT * k;
-    const int ba = o / BW, bb = o - ba * BW;
+    int ba, bb;
+    tile_slot<TX, TY>(o, ba, bb);
     const bool blk = o < BH * BW;
     const bool r0ok = blk && 2 * ba < fr, r1ok = blk && 2 * ba + 1 < fr;
     const bool q0ok = 2 * bb < fq, q1ok = 2 * bb + 1 < fq;
