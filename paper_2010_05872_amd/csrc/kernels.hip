@@ -52,6 +52,12 @@
 #ifndef MGX_F32_TY
 #define MGX_F32_TY 16
 #endif
+#ifndef MGX_F32_RECLAB_TX
+#define MGX_F32_RECLAB_TX 64
+#endif
+#ifndef MGX_F32_RECLAB_TY
+#define MGX_F32_RECLAB_TY 8
+#endif
 #ifndef MGX_F32_INTERP_TX
 #define MGX_F32_INTERP_TX 64
 #endif
@@ -257,7 +263,8 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
   constexpr int NE = (HR * W + NT - 1) / NT;  // region elements per thread
   constexpr int NV = DEC ? 4 : 2;             // ring of planes kept in LDS
   constexpr int AHEAD = DEC ? 2 : 1;          // plane committed at iteration j is j + AHEAD
-  constexpr int DEPTH = DEC ? MGX_STENCIL_DEPTH : MGX_REC_DEPTH;  // register buffers in flight
+  // register buffers in flight (FP64 recomposition: two, within 128 VGPRs)
+  constexpr int DEPTH = DEC ? MGX_STENCIL_DEPTH : (sizeof(T) == 8 ? 2 : MGX_REC_DEPTH);
   constexpr int XRS = NT / GW;                // x-restriction: rows per sweep
   constexpr int XR = (HR + XRS - 1) / XRS;    // x-restriction: rows per thread
   constexpr int NOUT = (GH * GW + NT - 1) / NT;  // y-restriction outputs per thread
@@ -540,14 +547,17 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
 
   const int jstart = 2 * Z0 - 2, jend = 2 * Z1;  // both even
   T st[DEPTH][NE];
-  fetch(jstart, st[0]);
-  commit(slot_of(jstart), st[0]);
-  if (DEC) {
-    fetch(jstart + 1, st[0]);
-    commit(slot_of(jstart + 1), st[0]);
-  }
+  {
+    // the planes before the march and the first DEPTH planes of it are all
+    // requested before the first commit waits
+    T p0[NE], p1[NE];
+    fetch(jstart, p0);
+    if (DEC) fetch(jstart + 1, p1);
 #pragma unroll
-  for (int d = 0; d < DEPTH; d++) fetch(jstart + AHEAD + d, st[d]);
+    for (int d = 0; d < DEPTH; d++) fetch(jstart + AHEAD + d, st[d]);
+    commit(slot_of(jstart), p0);
+    if (DEC) commit(slot_of(jstart + 1), p1);
+  }
   __syncthreads();
   int j = jstart;
   for (; j + DEPTH - 1 <= jend; j += DEPTH) {
@@ -1694,6 +1704,14 @@ template <>
 struct Tiles<double> {
   static constexpr int TX = 16, TY = MGX_F64_TY, NT = MGX_F64_NT;
 };
+// Tiles of the recomposition's load-vector kernel reading labels (measured
+// faster with wider rows; the kernel on coefficients keeps the tiles above)
+template <typename T>
+struct RecLabTiles : Tiles<T> {};
+template <>
+struct RecLabTiles<float> {
+  static constexpr int TX = MGX_F32_RECLAB_TX, TY = MGX_F32_RECLAB_TY, NT = MGX_F32_NT;
+};
 // Tiles of the interpolation kernels (wider rows than the load vector's:
 // longer store runs per row, measured faster on MI355X)
 template <typename T>
@@ -1731,24 +1749,24 @@ static bool tile_grid(int c0, int c1, int c2, int TX, int TY, int *ntx, int *nty
   return true;
 }
 
-template <typename T>
-hipError_t launch_load_vector(StencilArgs<T> a, bool dec, hipStream_t st, Tuning tn) {
-  constexpr int TX = Tiles<T>::TX, TY = Tiles<T>::TY, NT = Tiles<T>::NT;
+template <typename T, typename TL, bool DEC, bool LAB>
+hipError_t launch_load_vector_t(StencilArgs<T> a, hipStream_t st, Tuning tn) {
+  constexpr int TX = TL::TX, TY = TL::TY, NT = TL::NT;
   if (!tile_grid(a.ax[0].c, a.ax[1].c, a.ax[2].c, TX, TY, &a.ntx, &a.nty, &a.nzc, &a.tz, tn))
     return hipErrorInvalidValue;
   dim3 grid(a.ntx * a.nty * a.nzc);
-  if (dec) {
-    if (a.lab_w)
-      hipLaunchKernelGGL((k_load_vector<T, TX, TY, NT, true, true>), grid, dim3(NT), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_load_vector<T, TX, TY, NT, true, false>), grid, dim3(NT), 0, st, a);
-  } else {
-    if (a.lab_r)
-      hipLaunchKernelGGL((k_load_vector<T, TX, TY, NT, false, true>), grid, dim3(NT), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_load_vector<T, TX, TY, NT, false, false>), grid, dim3(NT), 0, st, a);
-  }
+  hipLaunchKernelGGL((k_load_vector<T, TX, TY, NT, DEC, LAB>), grid, dim3(NT), 0, st, a);
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_load_vector(StencilArgs<T> a, bool dec, hipStream_t st, Tuning tn) {
+  if (dec) {
+    if (a.lab_w) return launch_load_vector_t<T, Tiles<T>, true, true>(a, st, tn);
+    return launch_load_vector_t<T, Tiles<T>, true, false>(a, st, tn);
+  }
+  if (a.lab_r) return launch_load_vector_t<T, RecLabTiles<T>, false, true>(a, st, tn);
+  return launch_load_vector_t<T, Tiles<T>, false, false>(a, st, tn);
 }
 
 // Large levels take the one-plane-per-workgroup interpolation (compact store
