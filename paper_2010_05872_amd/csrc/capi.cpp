@@ -267,6 +267,14 @@ OpArgs<T> tail_args(const Plan *P, int stop, const T *tab, char *ws, const Layou
 
 void quant_box(const Plan *P, QuantArgs &qa, int level);
 
+// 1/q in FP64 rounded to FP32, NaN outside FP32's normal range: the factor
+// of the decomposition kernels' FP32 label shortcut (the same rounding the
+// device-side label_rcp performs).
+float label_rcp_host(double q) {
+  const double r = 1.0 / q;
+  return (r >= 1.1754943508222875e-38 && r <= 3.4028234663852886e38) ? (float)r : std::nanf("");
+}
+
 // With labels (and the quantizer's arguments qa), every kernel that writes
 // coefficients also writes their labels, and u_mc may be null (labels only).
 template <typename T>
@@ -311,6 +319,7 @@ mgx_status run_decompose(Plan *P, int stop, const T *u, T *umc, char *ws, const 
     if (labels) {
       s.lab_w = labels;
       s.qc = qa->q[l - stop];
+      s.rqc = label_rcp_host(s.qc);
     }
     hipError_t e = em.op(kOpLoadVecDec, 0, labels ? "load_vector_dec+q" : "load_vector_dec", l, o);
     if (e != hipSuccess) return MGX_ERR_HIP;

@@ -52,6 +52,15 @@
 #ifndef MGX_F32_TY
 #define MGX_F32_TY 16
 #endif
+#ifndef MGX_F32_DEC_TX
+#define MGX_F32_DEC_TX MGX_F32_TX
+#endif
+#ifndef MGX_F32_DEC_TY
+#define MGX_F32_DEC_TY MGX_F32_TY
+#endif
+#ifndef MGX_F32_DEC_NT
+#define MGX_F32_DEC_NT MGX_F32_NT
+#endif
 #ifndef MGX_F32_RECLAB_TX
 #define MGX_F32_RECLAB_TX 64
 #endif
@@ -293,7 +302,7 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
   const int fr = min(2 * Y1, m1) - 2 * Y0;  // owned fine rows
   const int fq = min(2 * X1, m2) - 2 * X0;  // owned fine columns
   const int own_p0 = 2 * Z0, own_p1 = min(2 * Z1, m0);
-  const float rq = (DEC && LAB) ? label_rcp(a.qc) : 0.0f;
+  const float rq = a.rqc;
 
   // ---- plane loads: global and LDS offsets of this thread's NE region
   //      elements (the same in every plane) ----
@@ -1704,6 +1713,13 @@ template <>
 struct Tiles<double> {
   static constexpr int TX = 16, TY = MGX_F64_TY, NT = MGX_F64_NT;
 };
+// Tiles of the decomposition's load-vector kernel (single-field launches)
+template <typename T>
+struct DecTiles : Tiles<T> {};
+template <>
+struct DecTiles<float> {
+  static constexpr int TX = MGX_F32_DEC_TX, TY = MGX_F32_DEC_TY, NT = MGX_F32_DEC_NT;
+};
 // Tiles of the recomposition's load-vector kernel reading labels (measured
 // faster with wider rows; the kernel on coefficients keeps the tiles above)
 template <typename T>
@@ -1762,8 +1778,8 @@ hipError_t launch_load_vector_t(StencilArgs<T> a, hipStream_t st, Tuning tn) {
 template <typename T>
 hipError_t launch_load_vector(StencilArgs<T> a, bool dec, hipStream_t st, Tuning tn) {
   if (dec) {
-    if (a.lab_w) return launch_load_vector_t<T, Tiles<T>, true, true>(a, st, tn);
-    return launch_load_vector_t<T, Tiles<T>, true, false>(a, st, tn);
+    if (a.lab_w) return launch_load_vector_t<T, DecTiles<T>, true, true>(a, st, tn);
+    return launch_load_vector_t<T, DecTiles<T>, true, false>(a, st, tn);
   }
   if (a.lab_r) return launch_load_vector_t<T, RecLabTiles<T>, false, true>(a, st, tn);
   return launch_load_vector_t<T, Tiles<T>, false, false>(a, st, tn);

@@ -38,6 +38,7 @@ struct StencilArgs {
   int32_t *lab_w;             // decompose: also write the quantization labels (u_mc's layout)
   const int32_t *lab_r;       // recompose: read labels instead of coefficients
   double qc;                  // bin width q_l of the level's coefficients (labels)
+  float rqc;                  // 1/q_l rounded to FP32 (NaN outside FP32's normal range)
   int ntx, nty, nzc, tz;      // set by the launcher
 };
 
