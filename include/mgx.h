@@ -116,6 +116,25 @@ mgx_status mgx_recompose(const void *u_mc, void *u, mgx_dtype dtype, int ndim,
                          const int64_t *dims, const double *const *coords, int stop_level,
                          void *workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* Progressive recomposition: the recomposition stopped after level
+ * target_level, giving Q_target u, the coarse representation of the field
+ * on the level-target grid (the partial reconstruction that data refactoring
+ * offers, Sec. 1; the analysis on decomposed representations, Sec. 6.2.2).
+ *   u_mc          in:  device, level-centric layout of a decomposition to
+ *                 stop_level.  Not modified.
+ *   u_t           out: device, the level-target box in natural order, node
+ *                 counts (n_k - 1) / 2^(L - target_level) + 1 per real axis
+ *                 (dims unchanged on padded axes).  Must not overlap u_mc or
+ *                 the workspace.
+ *   target_level  stop_level <= target_level <= L; L gives mgx_recompose's
+ *                 result, stop_level a copy of the stop level's box.
+ * Workspace as mgx_recompose (mgx_workspace_size with stop_level).
+ * Errors: MGX_ERR_LEVEL for a target outside [stop_level, L]; otherwise as
+ * mgx_recompose. */
+mgx_status mgx_recompose_to(const void *u_mc, void *u_t, mgx_dtype dtype, int ndim, const int64_t *dims,
+                            const double *const *coords, int stop_level, int target_level, void *workspace,
+                            size_t workspace_bytes, hipStream_t stream);
+
 /* mgx_decompose followed by mgx_quantize (no statistics) in one call, with
  * the same results (Sec. 4.1 quantization of the Sec. 3 decomposition):
  * every kernel that produces coefficients of a level also writes their

@@ -54,6 +54,7 @@ def lib():
         L.mgo_num_levels.argtypes = [ctypes.c_int, i64p]
         for name in ("mgo_decompose", "mgo_recompose", "mgo_decompose_adjoint", "mgo_recompose_adjoint"):
             getattr(L, name).argtypes = [vp, ctypes.c_int, i64p, vp, ctypes.c_int]
+        L.mgo_recompose_to.argtypes = [vp, ctypes.c_int, i64p, vp, ctypes.c_int, ctypes.c_int]
         L.mgo_project_line_adjoint_1d.argtypes = [vp, ctypes.c_int64, vp, vp]
         L.mgo_correction.argtypes = [vp, vp, ctypes.c_int, i64p, vp]
         L.mgo_mass_apply_1d.argtypes = [vp, ctypes.c_int64, vp, vp]
@@ -129,6 +130,18 @@ def recompose(u_mc, coords=None, stop_level=0) -> np.ndarray:
     c = _Coords(v.shape, coords)
     _check(lib().mgo_recompose(v.ctypes.data, v.ndim, _dims(v.shape), c.ptr, int(stop_level)), "recompose")
     return v
+
+
+def recompose_to(u_mc, target_level, coords=None, stop_level=0) -> np.ndarray:
+    """Progressive recomposition (recomposition of Sec. 2 stopped after level
+    target_level): Q_target u on the level-target grid, as a compact array."""
+    v = np.array(u_mc, dtype=np.float64, order="C", copy=True)
+    c = _Coords(v.shape, coords)
+    _check(lib().mgo_recompose_to(v.ctypes.data, v.ndim, _dims(v.shape), c.ptr, int(stop_level),
+                                  int(target_level)), "recompose_to")
+    L = num_levels(v.shape)
+    s = 2 ** (L - int(target_level))
+    return np.ascontiguousarray(v[tuple(slice(None, None, s) if n > 1 else slice(None) for n in v.shape)])
 
 
 def decompose_adjoint(g_mc, coords=None, stop_level=0) -> np.ndarray:

@@ -622,6 +622,27 @@ int mgo_recompose(double *v, int ndim, const int64_t *dims,
   return st;
 }
 
+/* Progressive (partial) recomposition: the recomposition of Sec. 2 stopped
+ * after level target_level.  The interleaved array then holds Q_target u on
+ * the level-target grid N_target (the nodes whose indices are multiples of
+ * 2^(L - target) on every real axis): the coarse representation that data
+ * refactoring retrieves without the finer components (Sec. 1; the analysis
+ * on decomposed representations of Sec. 6.2.2).  target = L is the full
+ * recomposition; target = stop leaves the array unchanged. */
+int mgo_recompose_to(double *v, int ndim, const int64_t *dims,
+                     const double *const *coords, int stop_level, int target_level) {
+  grid_t g;
+  int st = grid_init(&g, ndim, dims, coords);
+  if (st) return st;
+  if (stop_level < 0 || stop_level > g.L || target_level < stop_level || target_level > g.L) {
+    grid_free(&g);
+    return MGO_ERR_LEVEL;
+  }
+  for (int l = stop_level + 1; l <= target_level && !st; l++) st = recompose_level(&g, v, l);
+  grid_free(&g);
+  return st;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Level membership and the level-centric reordering (Sec. 5.1).              */
 /* ------------------------------------------------------------------------ */

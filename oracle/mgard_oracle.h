@@ -41,6 +41,11 @@ int mgo_decompose(double *v, int ndim, const int64_t *dims,
 int mgo_recompose(double *v, int ndim, const int64_t *dims,
                   const double *const *coords, int stop_level);
 
+/* In place: the recomposition stopped after level target_level (stop <=
+ * target <= L); the level-target grid of v then holds Q_target u. */
+int mgo_recompose_to(double *v, int ndim, const int64_t *dims,
+                     const double *const *coords, int stop_level, int target_level);
+
 /* Transposes (adjoints) of mgo_decompose and mgo_recompose, in place on the
  * interleaved layout: for all x, y, <D x, y> = <x, D^T y>. */
 int mgo_decompose_adjoint(double *v, int ndim, const int64_t *dims,

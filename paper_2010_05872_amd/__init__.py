@@ -96,6 +96,7 @@ EXPORTS = (
     "mgx_trace_enable", "mgx_trace_read", "mgx_adjoint_workspace_size", "mgx_decompose_adjoint",
     "mgx_recompose_adjoint", "mgx_batch_workspace_size", "mgx_decompose_batched", "mgx_recompose_batched",
     "mgx_batch_set_autotune", "mgx_batch_last_info", "mgx_decompose_quantize", "mgx_dequantize_recompose",
+    "mgx_recompose_to",
 )
 
 _lib = None
@@ -121,6 +122,8 @@ def lib():
         L.mgx_decompose_quantize.restype = ci
         L.mgx_dequantize_recompose.argtypes = [vp, vp, vp, ci, ci, i64p, vp, cd, ci, cd, vp, sz, vp]
         L.mgx_dequantize_recompose.restype = ci
+        L.mgx_recompose_to.argtypes = [vp, vp, ci, ci, i64p, vp, ci, ci, vp, sz, vp]
+        L.mgx_recompose_to.restype = ci
         L.mgx_adjoint_workspace_size.argtypes = [ci, ci, i64p, ci]
         L.mgx_adjoint_workspace_size.restype = sz
         for name in ("mgx_decompose", "mgx_recompose", "mgx_decompose_adjoint", "mgx_recompose_adjoint"):
@@ -295,6 +298,35 @@ def recompose(u_mc, coords=None, stop_level=0, out=None, workspace=None):
                                c.ptr, int(stop_level), ws.data_ptr(), ws.numel() * ws.element_size(),
                                _stream(u_mc.device))
     _check(code, "mgx_recompose")
+    return out
+
+
+def level_shape(shape, level):
+    """Node counts of the level-`level` grid of a field of this shape."""
+    L = num_levels(shape)
+    if not 0 <= level <= L:
+        raise ValueError(f"level {level} outside [0, {L}]")
+    return tuple((n - 1) // 2 ** (L - level) + 1 for n in shape)
+
+
+def recompose_to(u_mc, target_level, coords=None, stop_level=0, out=None, workspace=None):
+    """Progressive recomposition: Q_target u on the level-target grid (natural
+    order, shape level_shape(u_mc.shape, target_level)) from a decomposition
+    to stop_level."""
+    import torch
+    _check_tensor(u_mc, "u_mc")
+    shape = level_shape(u_mc.shape, target_level)
+    if out is None:
+        out = torch.empty(shape, dtype=u_mc.dtype, device=u_mc.device)
+    _check_tensor(out, "out")
+    if tuple(out.shape) != shape or out.dtype != u_mc.dtype:
+        raise ValueError(f"out must be {shape} {u_mc.dtype}")
+    ws, _ = _workspace(u_mc, stop_level, workspace)
+    c = Coords(u_mc.shape, coords)
+    code = lib().mgx_recompose_to(u_mc.data_ptr(), out.data_ptr(), _dtype_code(u_mc), u_mc.dim(),
+                                  _dims(u_mc.shape), c.ptr, int(stop_level), int(target_level), ws.data_ptr(),
+                                  ws.numel() * ws.element_size(), _stream(u_mc.device))
+    _check(code, "mgx_recompose_to")
     return out
 
 

@@ -267,6 +267,11 @@ OpArgs<T> tail_args(const Plan *P, int stop, const T *tab, char *ws, const Layou
 
 void quant_box(const Plan *P, QuantArgs &qa, int level);
 
+// Node counts of the level-l box along each axis (1 on padded axes).
+void level_box(const Plan *P, int l, int64_t m[3]) {
+  for (int k = 0; k < 3; k++) m[k] = P->real[k] ? (P->n[k] - 1) / ((int64_t)1 << (P->L - l)) + 1 : 1;
+}
+
 // 1/q in FP64 rounded to FP32, NaN outside FP32's normal range: the factor
 // of the decomposition kernels' FP32 label shortcut (the same rounding the
 // device-side label_rcp performs).
@@ -362,18 +367,28 @@ mgx_status run_decompose(Plan *P, int stop, const T *u, T *umc, char *ws, const 
 }
 
 // With labels (and qa), the coefficients are read as labels times the
-// level's bin width (u_mc unused, may be null).
+// level's bin width (u_mc unused, may be null).  With top < L the
+// recomposition stops after level top and u receives Q_top u as the compact
+// level-top box (progressive recomposition; coefficients from u_mc only).
 template <typename T>
-mgx_status run_recompose(Plan *P, int stop, const T *umc, T *u, char *ws, const Layout &lay, const T *tab,
-                         Emitter<T> &em, const int32_t *labels = nullptr, const QuantArgs *qa = nullptr) {
+mgx_status run_recompose(Plan *P, int stop, const T *umc, T *u, char *ws, const Layout &lay0, const T *tab,
+                         Emitter<T> &em, const int32_t *labels = nullptr, const QuantArgs *qa = nullptr,
+                         int top = -1) {
   const int L = P->L;
+  if (top < 0) top = L;
+  if (top < stop || top > L || (labels && top != L)) return MGX_ERR_LEVEL;
+  Layout lay = lay0;
+  if (lay.lt > top) lay.lt = top;  // the single-workgroup tail ends at the target level
   const int64_t n1 = P->n[1], n2 = P->n[2];
   const int64_t up0 = n1 * n2, up1 = n2;
-  if (stop == L) {
+  int64_t tm[3];
+  level_box(P, top, tm);
+  const int64_t tp1 = tm[2], tp0 = tm[1] * tm[2];  // output pitches (level-top box)
+  if (stop == top) {
     em.begin_step(0);
     if (labels)
       return hip_status(traced("dequantize", -1, em.st, [&] { return launch_dequantize<T>(labels, u, *qa, em.st); }));
-    return hip_status(copy_box<T>(umc, up0, up1, u, up0, up1, (int)P->n[0], (int)n1, (int)n2, L, em));
+    return hip_status(copy_box<T>(umc, up0, up1, u, tp0, tp1, (int)tm[0], (int)tm[1], (int)tm[2], top, em));
   }
   T *A = (T *)(ws + lay.offA), *B = (T *)(ws + lay.offB), *F = (T *)(ws + lay.offF);
   T *S = (T *)(ws + lay.offS);
@@ -398,10 +413,10 @@ mgx_status run_recompose(Plan *P, int stop, const T *umc, T *u, char *ws, const 
       for (int i = 0; i < o.tl.nlev; i++) o.tl.q[i] = qa->q[lay.lt - i - stop];
       o.tl.q[o.tl.nlev] = qa->q[0];
     }
-    if (lay.lt == L) {
+    if (lay.lt == top) {
       o.tl.dst = u;
-      o.tl.dp0 = up0;
-      o.tl.dp1 = up1;
+      o.tl.dp0 = tp0;
+      o.tl.dp1 = tp1;
     } else {
       const AxisLevel &a1 = P->ax[lay.lt][1], &a2 = P->ax[lay.lt][2];
       o.tl.dst = ((L - 1 - lay.lt) % 2 == 0) ? A : B;
@@ -411,7 +426,7 @@ mgx_status run_recompose(Plan *P, int stop, const T *umc, T *u, char *ws, const 
     if (em.op(kOpTailRec, 0, labels ? "tail_rec+q" : "tail_rec", lay.lt, o) != hipSuccess) return MGX_ERR_HIP;
     first_tiled = lay.lt + 1;
   }
-  for (int l = first_tiled; l <= L; l++) {
+  for (int l = first_tiled; l <= top; l++) {
     em.begin_step(l - stop - 1 + (lay.lt > stop ? 1 : 0));
     AxisTab<T> ax[3] = {axis_tab(P, l, 0, tab), axis_tab(P, l, 1, tab), axis_tab(P, l, 2, tab)};
     const int c1 = ax[1].c, c2 = ax[2].c;
@@ -452,10 +467,10 @@ mgx_status run_recompose(Plan *P, int stop, const T *umc, T *u, char *ws, const 
       ia.lab = labels;
       ia.qc = qa->q[l - stop];
     }
-    if (l == L) {
+    if (l == top) {
       ia.out = u;
-      ia.op0 = up0;
-      ia.op1 = up1;
+      ia.op0 = tp0;
+      ia.op1 = tp1;
     } else {
       ia.out = ((L - 1 - l) % 2 == 0) ? A : B;
       ia.op1 = m2;
@@ -1263,6 +1278,36 @@ mgx_status mgx_recompose(const void *u_mc, void *u, mgx_dtype dtype, int ndim, c
   em.st = stream;
   return run_recompose<double>(P, stop_level, (const double *)u_mc, (double *)u, (char *)workspace, lay,
                                (const double *)tab, em);
+}
+
+mgx_status mgx_recompose_to(const void *u_mc, void *u_t, mgx_dtype dtype, int ndim, const int64_t *dims,
+                            const double *const *coords, int stop_level, int target_level, void *workspace,
+                            size_t workspace_bytes, hipStream_t stream) {
+  Plan *P;
+  Layout lay;
+  const void *tab;
+  mgx_status s = prepare(u_mc, nullptr, dtype, ndim, dims, coords, stop_level, workspace, workspace_bytes, &P, &lay,
+                         &tab, false, 2);
+  if (s) return s;
+  if (target_level < stop_level || target_level > P->L) return MGX_ERR_LEVEL;
+  if (!u_t) return MGX_ERR_ARG;
+  const size_t es = elem_size(dtype);
+  const size_t in_bytes = (size_t)(P->n[0] * P->n[1] * P->n[2]) * es;
+  int64_t tm[3];
+  level_box(P, target_level, tm);
+  const size_t out_bytes = (size_t)(tm[0] * tm[1] * tm[2]) * es;
+  if (overlaps(u_t, out_bytes, u_mc, in_bytes) || (lay.total > 0 && overlaps(u_t, out_bytes, workspace, lay.total)))
+    return MGX_ERR_ARG;
+  if (dtype == MGX_F32) {
+    Emitter<float> em;
+    em.st = stream;
+    return run_recompose<float>(P, stop_level, (const float *)u_mc, (float *)u_t, (char *)workspace, lay,
+                                (const float *)tab, em, nullptr, nullptr, target_level);
+  }
+  Emitter<double> em;
+  em.st = stream;
+  return run_recompose<double>(P, stop_level, (const double *)u_mc, (double *)u_t, (char *)workspace, lay,
+                               (const double *)tab, em, nullptr, nullptr, target_level);
 }
 
 size_t mgx_adjoint_workspace_size(mgx_dtype dtype, int ndim, const int64_t *dims, int stop_level) {
