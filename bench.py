@@ -227,6 +227,29 @@ def adjoint_section(torch, mgx, workloads, dev, reps):
             "rel_err_DtRt_identity": ident_err}
 
 
+def progressive_section(torch, mgx, u, umc, ws, reps):
+    """Progressive recomposition of the benchmark field: Q_t u on the level-t
+    grid for every target t, against the full recomposition.  Bytes counted:
+    the coefficients of levels <= t read once (the level-t box of u_mc) and
+    the level-t box written once."""
+    L = mgx.num_levels(u.shape)
+    out = {}
+    for t in range(max(L - 4, 0), L + 1):
+        box = mgx.level_shape(u.shape, t)
+        n = 1
+        for m in box:
+            n *= m
+        dst = torch.empty(box, dtype=u.dtype, device=u.device)
+        fn = lambda: mgx.recompose_to(umc, t, out=dst, workspace=ws)  # noqa: E731
+        fn()
+        ms = timed(torch, fn, reps)
+        out[str(t)] = {"box": list(box), "ms": round(ms, 4), "GBps": round(2 * n * 4 / (ms * 1e-3) / 1e9, 2)}
+    full = mgx.recompose(umc, workspace=ws)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(mgx.recompose_to(umc, L, workspace=ws), full))
+    return {"targets": out, "target_L_equals_recompose": same}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -374,6 +397,8 @@ def main():
         "max_err_over_tau": round(err / tol, 5),
     }
     if not args.no_extensions:
+        mgx.decompose(u, out=umc, workspace=ws)
+        out["progressive"] = progressive_section(torch, mgx, u, umc, ws, max(3, args.steps // 4))
         out["batched"] = batched_section(torch, mgx, workloads, dev, max(3, args.steps // 4))
         out["adjoint"] = adjoint_section(torch, mgx, workloads, dev, max(3, args.steps // 4))
     if not args.no_cpu_baseline:

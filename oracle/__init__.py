@@ -55,6 +55,11 @@ def lib():
         for name in ("mgo_decompose", "mgo_recompose", "mgo_decompose_adjoint", "mgo_recompose_adjoint"):
             getattr(L, name).argtypes = [vp, ctypes.c_int, i64p, vp, ctypes.c_int]
         L.mgo_recompose_to.argtypes = [vp, ctypes.c_int, i64p, vp, ctypes.c_int, ctypes.c_int]
+        L.mgo_adaptive_estimate.argtypes = [vp, ctypes.c_int, i64p, vp, ctypes.c_int, dp, dp, i64p]
+        L.mgo_adaptive_errors.argtypes = [ctypes.c_double, ctypes.c_double, i64p, ctypes.c_double, dp, dp]
+        L.mgo_adaptive_errors.restype = None
+        L.mgo_decompose_adaptive.argtypes = [vp, ctypes.c_int, i64p, vp, ctypes.c_double, ctypes.c_double,
+                                             ctypes.POINTER(ctypes.c_int)]
         L.mgo_project_line_adjoint_1d.argtypes = [vp, ctypes.c_int64, vp, vp]
         L.mgo_correction.argtypes = [vp, vp, ctypes.c_int, i64p, vp]
         L.mgo_mass_apply_1d.argtypes = [vp, ctypes.c_int64, vp, vp]
@@ -142,6 +147,43 @@ def recompose_to(u_mc, target_level, coords=None, stop_level=0) -> np.ndarray:
     L = num_levels(v.shape)
     s = 2 ** (L - int(target_level))
     return np.ascontiguousarray(v[tuple(slice(None, None, s) if n > 1 else slice(None) for n in v.shape)])
+
+
+PENALTY = {"lorenzo": 1.22, "edge": 0.369, "plane": 0.259, "cube": 0.182}  # Sec. 4.2, units of tau
+
+
+def adaptive_estimate(v, level, coords=None):
+    """Sums of |u - Lorenzo| and |u - interpolant| over the coefficient nodes
+    of the sampled 3^3 blocks of level `level` (cells a % 4 == 1 per axis) of
+    the interleaved array v (holding Q_level u), and the sampled edge, plane
+    and cube counts.  Sec. 4.2, Alg. 1 lines 4-9."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    c = _Coords(v.shape, coords)
+    sl, si = ctypes.c_double(), ctypes.c_double()
+    cnt = np.zeros(3, dtype=np.int64)
+    _check(lib().mgo_adaptive_estimate(v.ctypes.data, v.ndim, _dims(v.shape), c.ptr, int(level),
+                                       ctypes.byref(sl), ctypes.byref(si),
+                                       cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))), "adaptive_estimate")
+    return sl.value, si.value, cnt
+
+
+def adaptive_errors(s_lorenzo, s_interp, counts, tau0):
+    """(E_Lorenzo, E_interp): the sums plus the penalty factors times tau0."""
+    cnt = np.ascontiguousarray(counts, dtype=np.int64)
+    el, ei = ctypes.c_double(), ctypes.c_double()
+    lib().mgo_adaptive_errors(float(s_lorenzo), float(s_interp), cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                              float(tau0), ctypes.byref(el), ctypes.byref(ei))
+    return el.value, ei.value
+
+
+def decompose_adaptive(u, tol, coords=None, c_linf=0.0):
+    """Adaptive decomposition (Alg. 1 lines 1-16): (interleaved u_mc, stop level)."""
+    v = np.array(u, dtype=np.float64, order="C", copy=True)
+    c = _Coords(v.shape, coords)
+    stop = ctypes.c_int(-1)
+    _check(lib().mgo_decompose_adaptive(v.ctypes.data, v.ndim, _dims(v.shape), c.ptr, float(tol), float(c_linf),
+                                        ctypes.byref(stop)), "decompose_adaptive")
+    return v, stop.value
 
 
 def decompose_adjoint(g_mc, coords=None, stop_level=0) -> np.ndarray:

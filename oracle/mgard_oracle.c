@@ -622,6 +622,110 @@ int mgo_recompose(double *v, int ndim, const int64_t *dims,
   return st;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Adaptive decomposition (Sec. 4.2, "Adaptive decomposition"; Alg. 1 lines  */
+/* 1-16): before decomposing level l, compare the Lorenzo predictor with the */
+/* multilinear interpolation on sampled 3^d blocks of Q_l u; stop where the  */
+/* Lorenzo estimate is the lower one.                                         */
+/* ------------------------------------------------------------------------ */
+
+/* Penalty factors of Sec. 4.2 (3-D, in units of tau): Lorenzo, and the
+ * interpolation's edge, plane and cube nodes. */
+#define MGO_PEN_LORENZO 1.22
+#define MGO_PEN_EDGE 0.369
+#define MGO_PEN_PLANE 0.259
+#define MGO_PEN_CUBE 0.182
+
+/* Sums over the sampled blocks of level l (3-D fields only): one 3^3 block
+ * (level-l cell) in four along every axis, the cells a with a % 4 == 1, so
+ * that every Lorenzo neighbour (index - 1 on any subset of the axes) lies in
+ * the grid.  For each coefficient node x of a sampled block (at least one odd
+ * level index): s_lorenzo += |u(x) - Lorenzo prediction(x)|, s_interp +=
+ * |u(x) - multilinear interpolant(x)|; counts[0..2] = sampled edge, plane and
+ * cube nodes (1, 2, 3 odd indices).  v is the interleaved array holding
+ * Q_l u on the level-l grid. */
+int mgo_adaptive_estimate(const double *v, int ndim, const int64_t *dims, const double *const *coords,
+                          int level, double *s_lorenzo, double *s_interp, int64_t *counts) {
+  grid_t g;
+  int st = grid_init(&g, ndim, dims, coords);
+  if (st) return st;
+  if (g.d != 3) { grid_free(&g); return MGO_ERR_SHAPE; }
+  if (level < 1 || level > g.L) { grid_free(&g); return MGO_ERR_LEVEL; }
+  level_view_t w;
+  st = view_init(&w, &g, (double *)v, level);
+  if (st) { view_free(&w); grid_free(&g); return st; }
+  double sl = 0.0, si = 0.0;
+  int64_t cnt[3] = {0, 0, 0};
+  int64_t cells[3];
+  for (int k = 0; k < 3; k++) cells[k] = (w.m[k] - 1) / 2;
+  for (int64_t a0 = 1; a0 < cells[0]; a0 += 4)
+    for (int64_t a1 = 1; a1 < cells[1]; a1 += 4)
+      for (int64_t a2 = 1; a2 < cells[2]; a2 += 4)
+        for (int r0 = 0; r0 < 3; r0++)
+          for (int r1 = 0; r1 < 3; r1++)
+            for (int r2 = 0; r2 < 3; r2++) {
+              int64_t j[3] = {2 * a0 + r0, 2 * a1 + r1, 2 * a2 + r2};
+              int nodd = (r0 == 1) + (r1 == 1) + (r2 == 1);
+              if (nodd == 0) continue;
+              double x = *at(&w, j[0], j[1], j[2]);
+              double lor = *at(&w, j[0], j[1] - 1, j[2]) + *at(&w, j[0] - 1, j[1], j[2]) +
+                           *at(&w, j[0], j[1], j[2] - 1) - *at(&w, j[0] - 1, j[1] - 1, j[2]) -
+                           *at(&w, j[0], j[1] - 1, j[2] - 1) - *at(&w, j[0] - 1, j[1], j[2] - 1) +
+                           *at(&w, j[0] - 1, j[1] - 1, j[2] - 1);
+              sl += fabs(x - lor);
+              si += fabs(x - interpolant(&w, j));
+              cnt[nodd - 1]++;
+            }
+  view_free(&w);
+  grid_free(&g);
+  *s_lorenzo = sl;
+  *s_interp = si;
+  for (int k = 0; k < 3; k++) counts[k] = cnt[k];
+  return MGO_OK;
+}
+
+/* The estimated errors E_Lorenzo and E_interp of level l from the sums and
+ * counts above and tau0, the coarsest level's tolerance when the
+ * decomposition stops at l (Alg. 1 line 3: the level tolerances with stop
+ * level l). */
+void mgo_adaptive_errors(double s_lorenzo, double s_interp, const int64_t *counts, double tau0,
+                         double *e_lorenzo, double *e_interp) {
+  double n = (double)(counts[0] + counts[1] + counts[2]);
+  *e_lorenzo = s_lorenzo + MGO_PEN_LORENZO * tau0 * n;
+  *e_interp = s_interp + (MGO_PEN_EDGE * (double)counts[0] + MGO_PEN_PLANE * (double)counts[1] +
+                          MGO_PEN_CUBE * (double)counts[2]) * tau0;
+}
+
+/* In place: decomposition of u (natural order) level by level from L, each
+ * level preceded by the estimate; stops at the first level l whose Lorenzo
+ * estimate is below the interpolation's (*stop_out = l), else at level 0.
+ * The result equals mgo_decompose with stop level *stop_out. */
+int mgo_decompose_adaptive(double *v, int ndim, const int64_t *dims, const double *const *coords,
+                           double tol, double c_linf, int *stop_out) {
+  grid_t g;
+  int st = grid_init(&g, ndim, dims, coords);
+  if (st) return st;
+  if (g.d != 3) { grid_free(&g); return MGO_ERR_SHAPE; }
+  int L = g.L, stop = 0;
+  double *tau = (double *)malloc(sizeof(double) * (size_t)(L + 1));
+  if (!tau) { grid_free(&g); return MGO_ERR_ALLOC; }
+  for (int l = L; l >= 1 && !st; l--) {
+    st = mgo_level_tolerances(ndim, dims, coords, tol, l, c_linf, tau);
+    if (st) break;
+    double sl, si, el, ei;
+    int64_t cnt[3];
+    st = mgo_adaptive_estimate(v, ndim, dims, coords, l, &sl, &si, cnt);
+    if (st) break;
+    mgo_adaptive_errors(sl, si, cnt, tau[0], &el, &ei);
+    if (el < ei) { stop = l; break; }
+    st = decompose_level(&g, v, l);
+  }
+  free(tau);
+  grid_free(&g);
+  if (!st) *stop_out = stop;
+  return st;
+}
+
 /* Progressive (partial) recomposition: the recomposition of Sec. 2 stopped
  * after level target_level.  The interleaved array then holds Q_target u on
  * the level-target grid N_target (the nodes whose indices are multiples of

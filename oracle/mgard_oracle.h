@@ -41,6 +41,20 @@ int mgo_decompose(double *v, int ndim, const int64_t *dims,
 int mgo_recompose(double *v, int ndim, const int64_t *dims,
                   const double *const *coords, int stop_level);
 
+/* Adaptive decomposition (Sec. 4.2; Alg. 1 lines 1-16), 3-D fields only.
+ * Sums of |u - Lorenzo prediction| and |u - multilinear interpolant| over the
+ * coefficient nodes of the sampled 3^3 blocks of level `level` (cells a with
+ * a % 4 == 1 per axis) of the interleaved array, and the sampled edge, plane
+ * and cube node counts. */
+int mgo_adaptive_estimate(const double *v, int ndim, const int64_t *dims, const double *const *coords,
+                          int level, double *s_lorenzo, double *s_interp, int64_t *counts);
+/* E_Lorenzo and E_interp: the sums plus the penalty factors times tau0. */
+void mgo_adaptive_errors(double s_lorenzo, double s_interp, const int64_t *counts, double tau0,
+                         double *e_lorenzo, double *e_interp);
+/* In place: the adaptive decomposition; *stop_out receives the stop level. */
+int mgo_decompose_adaptive(double *v, int ndim, const int64_t *dims, const double *const *coords,
+                           double tol, double c_linf, int *stop_out);
+
 /* In place: the recomposition stopped after level target_level (stop <=
  * target <= L); the level-target grid of v then holds Q_target u. */
 int mgo_recompose_to(double *v, int ndim, const int64_t *dims,
