@@ -116,6 +116,40 @@ mgx_status mgx_recompose(const void *u_mc, void *u, mgx_dtype dtype, int ndim,
                          const int64_t *dims, const double *const *coords, int stop_level,
                          void *workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* Adaptive decomposition (Sec. 4.2 "Adaptive decomposition", Alg. 1 lines
+ * 1-16), 3-D fields only.  Before decomposing level l (from L down), the
+ * Lorenzo predictor and the multilinear interpolation are compared on
+ * sampled 3^3 blocks of Q_l u (the level-l cells a with a % 4 == 1 on every
+ * axis, one block in four per axis): E = sum over their coefficient nodes of
+ * |u - prediction| plus the penalty factors of Sec. 4.2 (Lorenzo 1.22,
+ * interpolation edge 0.369, plane 0.259, cube 0.182) times tau0, the
+ * tolerance of the coarsest level when the decomposition stops at l
+ * (mgx_level_tolerances with stop level l).  The decomposition stops at the
+ * first level whose Lorenzo estimate is the lower one, else at level 0.
+ *   u, u_mc       as mgx_decompose; u_mc holds the decomposition to the
+ *                 chosen stop level (the level-centric layout of that stop).
+ *   tol_linf, c_linf  as mgx_quantize.
+ *   stop_level_out    out: host, the chosen stop level.
+ *   workspace     mgx_workspace_size(dtype, ..., 0) bytes.
+ * Synchronizes `stream` once per level (the decision is taken on the host).
+ * Errors: MGX_ERR_SHAPE for fewer than three real axes; otherwise as
+ * mgx_decompose and mgx_quantize (MGX_ERR_TOL). */
+mgx_status mgx_decompose_adaptive(const void *u, void *u_mc, mgx_dtype dtype, int ndim, const int64_t *dims,
+                                  const double *const *coords, double tol_linf, double c_linf,
+                                  int *stop_level_out, void *workspace, size_t workspace_bytes,
+                                  hipStream_t stream);
+
+/* The estimate alone, on a level box v (device, natural order, the level-
+ * `level` grid of a field of shape dims, holding Q_level u): sums_out[0] =
+ * sum |u - Lorenzo prediction|, sums_out[1] = sum |u - multilinear
+ * interpolant| over the sampled coefficient nodes (FP64), counts_out[0..2] =
+ * sampled edge, plane and cube nodes (host arrays).  Workspace:
+ * mgx_adaptive_workspace_size bytes.  Synchronizes `stream`. */
+mgx_status mgx_adaptive_estimate(const void *v, mgx_dtype dtype, int ndim, const int64_t *dims,
+                                 const double *const *coords, int level, double *sums_out, int64_t *counts_out,
+                                 void *workspace, size_t workspace_bytes, hipStream_t stream);
+size_t mgx_adaptive_workspace_size(int ndim, const int64_t *dims);
+
 /* Progressive recomposition: the recomposition stopped after level
  * target_level, giving Q_target u, the coarse representation of the field
  * on the level-target grid (the partial reconstruction that data refactoring

@@ -96,7 +96,7 @@ EXPORTS = (
     "mgx_trace_enable", "mgx_trace_read", "mgx_adjoint_workspace_size", "mgx_decompose_adjoint",
     "mgx_recompose_adjoint", "mgx_batch_workspace_size", "mgx_decompose_batched", "mgx_recompose_batched",
     "mgx_batch_set_autotune", "mgx_batch_last_info", "mgx_decompose_quantize", "mgx_dequantize_recompose",
-    "mgx_recompose_to",
+    "mgx_recompose_to", "mgx_decompose_adaptive", "mgx_adaptive_estimate", "mgx_adaptive_workspace_size",
 )
 
 _lib = None
@@ -124,6 +124,12 @@ def lib():
         L.mgx_dequantize_recompose.restype = ci
         L.mgx_recompose_to.argtypes = [vp, vp, ci, ci, i64p, vp, ci, ci, vp, sz, vp]
         L.mgx_recompose_to.restype = ci
+        L.mgx_decompose_adaptive.argtypes = [vp, vp, ci, ci, i64p, vp, cd, cd, ctypes.POINTER(ci), vp, sz, vp]
+        L.mgx_decompose_adaptive.restype = ci
+        L.mgx_adaptive_estimate.argtypes = [vp, ci, ci, i64p, vp, ci, dp, i64p, vp, sz, vp]
+        L.mgx_adaptive_estimate.restype = ci
+        L.mgx_adaptive_workspace_size.argtypes = [ci, i64p]
+        L.mgx_adaptive_workspace_size.restype = sz
         L.mgx_adjoint_workspace_size.argtypes = [ci, ci, i64p, ci]
         L.mgx_adjoint_workspace_size.restype = sz
         for name in ("mgx_decompose", "mgx_recompose", "mgx_decompose_adjoint", "mgx_recompose_adjoint"):
@@ -328,6 +334,45 @@ def recompose_to(u_mc, target_level, coords=None, stop_level=0, out=None, worksp
                                   ws.numel() * ws.element_size(), _stream(u_mc.device))
     _check(code, "mgx_recompose_to")
     return out
+
+
+def decompose_adaptive(u, tol, coords=None, c_linf=0.0, out=None, workspace=None):
+    """Adaptive decomposition (Alg. 1 lines 1-16, 3-D): stops at the first
+    level whose Lorenzo estimate is below the interpolation's.  Returns
+    (u_mc, stop_level); u_mc is the level-centric layout of that stop."""
+    import torch
+    _check_tensor(u, "u")
+    if out is None:
+        out = torch.empty_like(u)
+    _check_tensor(out, "out")
+    ws, _ = _workspace(u, 0, workspace)
+    c = Coords(u.shape, coords)
+    stop = ctypes.c_int(-1)
+    code = lib().mgx_decompose_adaptive(u.data_ptr(), out.data_ptr(), _dtype_code(u), u.dim(), _dims(u.shape), c.ptr,
+                                        float(tol), float(c_linf), ctypes.byref(stop), ws.data_ptr(),
+                                        ws.numel() * ws.element_size(), _stream(u.device))
+    _check(code, "mgx_decompose_adaptive")
+    return out, stop.value
+
+
+def adaptive_estimate(v, shape, level, coords=None, workspace=None):
+    """The adaptive estimate on the level box v (Q_level u of a field of
+    `shape`): ((sum |u - Lorenzo|, sum |u - interpolant|), counts)."""
+    import torch
+    _check_tensor(v, "v")
+    if tuple(v.shape) != level_shape(shape, level):
+        raise ValueError(f"v must have the level-{level} shape {level_shape(shape, level)}")
+    need = lib().mgx_adaptive_workspace_size(len(shape), _dims(shape))
+    if workspace is None:
+        workspace = torch.empty(max(need, 8), dtype=torch.uint8, device=v.device)
+    c = Coords(shape, coords)
+    sums = (ctypes.c_double * 2)()
+    cnt = (ctypes.c_int64 * 3)()
+    code = lib().mgx_adaptive_estimate(v.data_ptr(), _dtype_code(v), len(shape), _dims(shape), c.ptr, int(level),
+                                       sums, cnt, workspace.data_ptr(), workspace.numel() * workspace.element_size(),
+                                       _stream(v.device))
+    _check(code, "mgx_adaptive_estimate")
+    return (sums[0], sums[1]), (cnt[0], cnt[1], cnt[2])
 
 
 def decompose_quantize(u, tol, coords=None, stop_level=0, c_linf=0.0, out=None, labels=None, workspace=None,

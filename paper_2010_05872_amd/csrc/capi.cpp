@@ -482,6 +482,125 @@ mgx_status run_recompose(Plan *P, int stop, const T *umc, T *u, char *ws, const 
   return MGX_OK;
 }
 
+mgx_status tolerances(Plan *P, int ndim, double tol, int stop, double c_linf, double *tau);
+
+// ---- adaptive decomposition (Sec. 4.2, Alg. 1 lines 1-16) ----
+// Penalty factors of the estimate (Sec. 4.2, 3-D, in units of tau0).
+constexpr double kPenLorenzo = 1.22, kPenEdge = 0.369, kPenPlane = 0.259, kPenCube = 0.182;
+
+// The estimate's sums on the level-l box V (pitches vp0, vp1): enqueued on
+// st, then the host waits and adds the workgroups' partial sums in order.
+// counts: sampled edge, plane and cube nodes (12, 6, 1 per block).
+template <typename T>
+mgx_status adaptive_sums(Plan *P, int l, const T *V, int64_t vp0, int64_t vp1, const double *tab64, double *part,
+                         hipStream_t st, double *s_lor, double *s_int, int64_t counts[3]) {
+  int64_t m[3];
+  level_box(P, l, m);
+  int nbk[3];
+  for (int k = 0; k < 3; k++) {
+    const int64_t cells = (m[k] - 1) / 2;
+    nbk[k] = cells > 1 ? (int)((cells - 2) / 4 + 1) : 0;  // cells a = 1, 5, 9, ... < cells
+  }
+  const int64_t nb = (int64_t)nbk[0] * nbk[1] * nbk[2];
+  counts[0] = 12 * nb;
+  counts[1] = 6 * nb;
+  counts[2] = nb;
+  *s_lor = *s_int = 0.0;
+  if (nb == 0) return MGX_OK;
+  EstimateArgs<T> a{};
+  a.V = V;
+  a.vp0 = vp0;
+  a.vp1 = vp1;
+  a.nb0 = nbk[0];
+  a.nb1 = nbk[1];
+  a.nb2 = nbk[2];
+  for (int k = 0; k < 3; k++) {
+    a.wl[k] = tab64 + P->ax[l][k].off_wl;
+    a.wr[k] = tab64 + P->ax[l][k].off_wr;
+  }
+  a.partial = part;
+  const int nwg = (int)((nb + kEstimateThreads - 1) / kEstimateThreads);
+  if (traced("adaptive_estimate", l, st, [&] { return launch_adaptive_estimate<T>(a, nwg, st); }) != hipSuccess)
+    return MGX_ERR_HIP;
+  std::vector<double> h((size_t)nwg * 2);
+  if (hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return MGX_ERR_HIP;
+  double sl = 0.0, si = 0.0;
+  for (int i = 0; i < nwg; i++) {
+    sl += h[2 * i];
+    si += h[2 * i + 1];
+  }
+  *s_lor = sl;
+  *s_int = si;
+  return MGX_OK;
+}
+
+// Level by level from L: the estimate of Q_l u, then either stop (Lorenzo's
+// estimate below the interpolation's: *stop_out = l) or one decomposition
+// level.  Q_{l-1} u goes to the compact A/B boxes; the last one is copied
+// into u_mc's corner at the end.  The estimate's partial sums use the load
+// vector's buffer F, which the level's kernels overwrite only afterwards.
+template <typename T>
+mgx_status run_decompose_adaptive(Plan *P, int ndim, const T *u, T *umc, double tol, double c_linf, char *ws,
+                                  const Layout &lay, const T *tab, const double *tab64, hipStream_t st,
+                                  int *stop_out) {
+  const int L = P->L;
+  const int64_t n1 = P->n[1], n2 = P->n[2];
+  const int64_t up0 = n1 * n2, up1 = n2;
+  T *A = (T *)(ws + lay.offA), *B = (T *)(ws + lay.offB), *F = (T *)(ws + lay.offF);
+  double *part = (double *)(ws + lay.offF);
+  Emitter<T> em;
+  em.st = st;
+  const T *src = u;
+  int64_t sp0 = up0, sp1 = up1;
+  int stop = 0;
+  for (int l = L; l >= 1; l--) {
+    double tau[kMaxLevels];
+    mgx_status s = tolerances(P, ndim, tol, l, c_linf, tau);
+    if (s) return s;
+    double sl, si;
+    int64_t cnt[3];
+    if ((s = adaptive_sums<T>(P, l, src, sp0, sp1, tab64, part, st, &sl, &si, cnt))) return s;
+    const double n = (double)(cnt[0] + cnt[1] + cnt[2]);
+    const double el = sl + kPenLorenzo * tau[0] * n;
+    const double ei = si + (kPenEdge * (double)cnt[0] + kPenPlane * (double)cnt[1] + kPenCube * (double)cnt[2]) * tau[0];
+    if (el < ei) {
+      stop = l;
+      break;
+    }
+    AxisTab<T> ax[3] = {axis_tab(P, l, 0, tab), axis_tab(P, l, 1, tab), axis_tab(P, l, 2, tab)};
+    const int c1 = ax[1].c, c2 = ax[2].c;
+    const int64_t cp1 = c2, cp0 = (int64_t)c1 * c2;
+    const int64_t fp1 = round4(c2), fp0 = (int64_t)c1 * fp1;
+    OpArgs<T> o{};
+    StencilArgs<T> &sa = o.st;
+    for (int k = 0; k < 3; k++) sa.ax[k] = ax[k];
+    sa.V = src;
+    sa.vp0 = sp0;
+    sa.vp1 = sp1;
+    sa.umc_w = umc;
+    sa.up0 = up0;
+    sa.up1 = up1;
+    sa.F = F;
+    sa.fp0 = fp0;
+    sa.fp1 = fp1;
+    if (em.op(kOpLoadVecDec, 0, "load_vector_dec", l, o) != hipSuccess) return MGX_ERR_HIP;
+    T *dst = ((L - 1 - (l - 1)) % 2 == 0) ? A : B;
+    if (solve_level<T>(l, ax, P->real, F, fp0, fp1, kSolveStore, nullptr, 0, 0, dst, cp0, cp1, em) != hipSuccess)
+      return MGX_ERR_HIP;
+    src = dst;
+    sp0 = cp0;
+    sp1 = cp1;
+  }
+  int64_t m[3];
+  level_box(P, stop, m);
+  if (copy_box<T>(src, sp0, sp1, umc, up0, up1, (int)m[0], (int)m[1], (int)m[2], stop, em) != hipSuccess)
+    return MGX_ERR_HIP;
+  *stop_out = stop;
+  return MGX_OK;
+}
+
 // Tables of level l with the load-vector stencil replaced by the restriction
 // R = P^T alone (adjoint passes).
 template <typename T>
@@ -1308,6 +1427,74 @@ mgx_status mgx_recompose_to(const void *u_mc, void *u_t, mgx_dtype dtype, int nd
   em.st = stream;
   return run_recompose<double>(P, stop_level, (const double *)u_mc, (double *)u_t, (char *)workspace, lay,
                                (const double *)tab, em, nullptr, nullptr, target_level);
+}
+
+mgx_status mgx_decompose_adaptive(const void *u, void *u_mc, mgx_dtype dtype, int ndim, const int64_t *dims,
+                                  const double *const *coords, double tol_linf, double c_linf, int *stop_level_out,
+                                  void *workspace, size_t workspace_bytes, hipStream_t stream) {
+  if (!stop_level_out) return MGX_ERR_ARG;
+  Plan *P;
+  Layout lay;
+  const void *tab;
+  mgx_status s = prepare(u, u_mc, dtype, ndim, dims, coords, 0, workspace, workspace_bytes, &P, &lay, &tab);
+  if (s) return s;
+  if (ndim != 3 || !P->real[0]) return MGX_ERR_SHAPE;
+  double tau[kMaxLevels];
+  if ((s = tolerances(P, ndim, tol_linf, P->L, c_linf, tau))) return s;
+  int dev = 0, herr = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MGX_ERR_HIP;
+  const double *tab64 = (const double *)P->device_tables(dev, true, &herr);
+  if (!tab64) return MGX_ERR_HIP;
+  if (P->L < 1) {  // nothing to decompose
+    *stop_level_out = 0;
+    return hipMemcpyAsync(u_mc, u, (size_t)(P->n[0] * P->n[1] * P->n[2]) * elem_size(dtype),
+                          hipMemcpyDeviceToDevice, stream) == hipSuccess
+               ? MGX_OK
+               : MGX_ERR_HIP;
+  }
+  if (dtype == MGX_F32)
+    return run_decompose_adaptive<float>(P, ndim, (const float *)u, (float *)u_mc, tol_linf, c_linf,
+                                         (char *)workspace, lay, (const float *)tab, tab64, stream, stop_level_out);
+  return run_decompose_adaptive<double>(P, ndim, (const double *)u, (double *)u_mc, tol_linf, c_linf,
+                                        (char *)workspace, lay, (const double *)tab, tab64, stream, stop_level_out);
+}
+
+mgx_status mgx_adaptive_estimate(const void *v, mgx_dtype dtype, int ndim, const int64_t *dims,
+                                 const double *const *coords, int level, double *sums_out, int64_t *counts_out,
+                                 void *workspace, size_t workspace_bytes, hipStream_t stream) {
+  if (!v || !sums_out || !counts_out || (dtype != MGX_F32 && dtype != MGX_F64)) return MGX_ERR_ARG;
+  int st = 0;
+  Plan *P = get_plan(ndim, dims, coords, &st);
+  if (!P) return (mgx_status)st;
+  if (ndim != 3 || !P->real[0]) return MGX_ERR_SHAPE;
+  if (level < 1 || level > P->L) return MGX_ERR_LEVEL;
+  const size_t need = mgx_adaptive_workspace_size(ndim, dims);
+  if (!workspace || workspace_bytes < need) return MGX_ERR_WORKSPACE;
+  int64_t m[3];
+  level_box(P, level, m);
+  if (overlaps(workspace, need, v, (size_t)(m[0] * m[1] * m[2]) * elem_size(dtype))) return MGX_ERR_ARG;
+  int dev = 0, herr = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MGX_ERR_HIP;
+  const double *tab64 = (const double *)P->device_tables(dev, true, &herr);
+  if (!tab64) return MGX_ERR_HIP;
+  if (dtype == MGX_F32)
+    return adaptive_sums<float>(P, level, (const float *)v, m[1] * m[2], m[2], tab64, (double *)workspace, stream,
+                                &sums_out[0], &sums_out[1], counts_out);
+  return adaptive_sums<double>(P, level, (const double *)v, m[1] * m[2], m[2], tab64, (double *)workspace, stream,
+                               &sums_out[0], &sums_out[1], counts_out);
+}
+
+size_t mgx_adaptive_workspace_size(int ndim, const int64_t *dims) {
+  int64_t n[3];
+  bool real[3];
+  int L;
+  if (parse_shape(ndim, dims, n, real, &L)) return 0;
+  int64_t nb = 1;
+  for (int k = 0; k < 3; k++) {
+    const int64_t cells = real[k] ? (n[k] - 1) / 2 : 0;
+    nb *= cells > 1 ? (cells - 2) / 4 + 1 : 1;
+  }
+  return (size_t)((nb + kEstimateThreads - 1) / kEstimateThreads) * 2 * sizeof(double);
 }
 
 size_t mgx_adjoint_workspace_size(mgx_dtype dtype, int ndim, const int64_t *dims, int stop_level) {

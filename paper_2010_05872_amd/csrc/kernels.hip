@@ -1700,6 +1700,87 @@ __global__ void __launch_bounds__(256) k_dequantize_box(const int32_t *__restric
 }
 
 // ---------------------------------------------------------------------------
+// k_adaptive_estimate: the error estimate of the adaptive decomposition
+// (Sec. 4.2, Alg. 1 lines 4-9) on the level-l box V = Q_l u.  One thread per
+// sampled 3^3 block: it loads the 4x4x4 region of level indices 2a-1 .. 2a+2
+// per axis (the block and its Lorenzo neighbours), and for each of the 19
+// coefficient nodes adds |u - Lorenzo prediction| and |u - multilinear
+// interpolant| (FP64, weights of the level's coordinates).  Each workgroup
+// writes its two sums; the host adds them in workgroup order.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kEstimateThreads) k_adaptive_estimate(EstimateArgs<T> a) {
+  __shared__ double sl[kEstimateThreads], si[kEstimateThreads];
+  const int nb = a.nb0 * a.nb1 * a.nb2;
+  const int b = blockIdx.x * kEstimateThreads + threadIdx.x;
+  double el = 0.0, ei = 0.0;
+  if (b < nb) {
+    const int b2 = b % a.nb2, r = b / a.nb2, b1 = r % a.nb1, b0 = r / a.nb1;
+    const int a0 = 1 + 4 * b0, a1 = 1 + 4 * b1, a2 = 1 + 4 * b2;
+    // region R[i0][i1][i2] = V at level indices (2a0-1+i0, 2a1-1+i1, 2a2-1+i2)
+    double R[4][4][4];
+    const T *base = a.V + (int64_t)(2 * a0 - 1) * a.vp0 + (int64_t)(2 * a1 - 1) * a.vp1 + (2 * a2 - 1);
+#pragma unroll
+    for (int i0 = 0; i0 < 4; i0++)
+#pragma unroll
+      for (int i1 = 0; i1 < 4; i1++)
+#pragma unroll
+        for (int i2 = 0; i2 < 4; i2++) R[i0][i1][i2] = (double)base[i0 * a.vp0 + i1 * a.vp1 + i2];
+    // weights of the odd (middle) level index of the block on each axis
+    const double l0 = a.wl[0][2 * a0 + 1], r0 = a.wr[0][2 * a0 + 1];
+    const double l1 = a.wl[1][2 * a1 + 1], r1 = a.wr[1][2 * a1 + 1];
+    const double l2 = a.wl[2][2 * a2 + 1], r2 = a.wr[2][2 * a2 + 1];
+#pragma unroll
+    for (int q0 = 0; q0 < 3; q0++)
+#pragma unroll
+      for (int q1 = 0; q1 < 3; q1++)
+#pragma unroll
+        for (int q2 = 0; q2 < 3; q2++) {
+          if (q0 != 1 && q1 != 1 && q2 != 1) continue;
+          const int i0 = q0 + 1, i1 = q1 + 1, i2 = q2 + 1;
+          const double x = R[i0][i1][i2];
+          const double lor = R[i0][i1 - 1][i2] + R[i0 - 1][i1][i2] + R[i0][i1][i2 - 1] - R[i0 - 1][i1 - 1][i2] -
+                             R[i0][i1 - 1][i2 - 1] - R[i0 - 1][i1][i2 - 1] + R[i0 - 1][i1 - 1][i2 - 1];
+          // multilinear interpolant from the nodal corners (block positions 0 and 2)
+          double pred = 0.0;
+#pragma unroll
+          for (int c = 0; c < 8; c++) {
+            const int c0 = c & 1, c1 = (c >> 1) & 1, c2 = (c >> 2) & 1;
+            if ((q0 != 1 && c0) || (q1 != 1 && c1) || (q2 != 1 && c2)) continue;
+            const double w0 = q0 != 1 ? 1.0 : (c0 ? r0 : l0);
+            const double w1 = q1 != 1 ? 1.0 : (c1 ? r1 : l1);
+            const double w2 = q2 != 1 ? 1.0 : (c2 ? r2 : l2);
+            const int j0 = q0 != 1 ? i0 : 1 + 2 * c0, j1 = q1 != 1 ? i1 : 1 + 2 * c1, j2 = q2 != 1 ? i2 : 1 + 2 * c2;
+            pred += w0 * w1 * w2 * R[j0][j1][j2];
+          }
+          el += fabs(x - lor);
+          ei += fabs(x - pred);
+        }
+  }
+  sl[threadIdx.x] = el;
+  si[threadIdx.x] = ei;
+  __syncthreads();
+  for (int h = kEstimateThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      sl[threadIdx.x] += sl[threadIdx.x + h];
+      si[threadIdx.x] += si[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    a.partial[2 * blockIdx.x] = sl[0];
+    a.partial[2 * blockIdx.x + 1] = si[0];
+  }
+}
+
+template <typename T>
+hipError_t launch_adaptive_estimate(EstimateArgs<T> a, int nblocks, hipStream_t st) {
+  if (nblocks < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_adaptive_estimate<T>), dim3((unsigned)nblocks), dim3(kEstimateThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 
@@ -2597,6 +2678,7 @@ hipError_t launch_op_multi(int kind, int key, const OpArgs<T> *dargs, const int 
   template hipError_t launch_apply<T>(StridedArgs<T>, hipStream_t);                           \
   template hipError_t launch_prolong_mass<T>(ProlongArgs<T>, int, hipStream_t);               \
   template hipError_t launch_copy_box<T>(CopyArgs<T>, hipStream_t);                           \
+  template hipError_t launch_adaptive_estimate<T>(EstimateArgs<T>, int, hipStream_t);         \
   template hipError_t launch_quantize<T>(const T *, int32_t *, QuantArgs, bool, hipStream_t); \
   template hipError_t launch_dequantize<T>(const int32_t *, T *, QuantArgs, hipStream_t);
 

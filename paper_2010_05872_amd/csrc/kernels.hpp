@@ -64,6 +64,17 @@ struct SolveArgs {            // contiguous-axis solve, in place on F rows
   const T *mult, *invd, *qsup;
 };
 
+// Adaptive decomposition estimate (3-D): one thread per sampled 3^3 block
+// (level-l cells a with a % 4 == 1 per axis) of the level-l box V.
+template <typename T>
+struct EstimateArgs {
+  const T *V;
+  int64_t vp0, vp1;
+  int nb0, nb1, nb2;            // sampled cells per axis
+  const double *wl[3], *wr[3];  // FP64 interpolation weights of level l, by level index
+  double *partial;              // per workgroup: sum |u - Lorenzo|, sum |u - interpolant|
+};
+
 template <typename T>
 struct StridedArgs {          // strided-axis solve (optionally applying)
   T *F;
@@ -225,6 +236,9 @@ union OpArgs {
   CopyArgs<T> cp;
   TailArgs<T> tl;
 };
+
+template <typename T> hipError_t launch_adaptive_estimate(EstimateArgs<T> a, int nblocks, hipStream_t st);
+constexpr int kEstimateThreads = 256;
 
 // Workgroups of one op (fills the tile-grid fields of stencil ops); -1 when
 // the shape is not launchable.
