@@ -250,6 +250,21 @@ def progressive_section(torch, mgx, u, umc, ws, reps):
     return {"targets": out, "target_L_equals_recompose": same}
 
 
+def adaptive_section(torch, mgx, u, umc, ws, reps):
+    """Adaptive decomposition of the benchmark field at three tolerances:
+    the stop level chosen and the time, against the full decomposition."""
+    rng = float((u.max() - u.min()).item())
+    out = {}
+    for rel in (1e-2, 1e-3, 1e-4):
+        res = {}
+        fn = lambda: res.update(stop=mgx.decompose_adaptive(u, rel * rng, out=umc, workspace=ws)[1])  # noqa: E731
+        fn()
+        ms = timed(torch, fn, reps)
+        out[f"{rel:g}"] = {"stop_level": res["stop"], "ms": round(ms, 4)}
+    full_ms = timed(torch, lambda: mgx.decompose(u, out=umc, workspace=ws), reps)
+    return {"tau_over_range": out, "full_decompose_ms": round(full_ms, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -399,6 +414,7 @@ def main():
     if not args.no_extensions:
         mgx.decompose(u, out=umc, workspace=ws)
         out["progressive"] = progressive_section(torch, mgx, u, umc, ws, max(3, args.steps // 4))
+        out["adaptive"] = adaptive_section(torch, mgx, u, umc, ws, max(3, args.steps // 4))
         out["batched"] = batched_section(torch, mgx, workloads, dev, max(3, args.steps // 4))
         out["adjoint"] = adjoint_section(torch, mgx, workloads, dev, max(3, args.steps // 4))
     if not args.no_cpu_baseline:
