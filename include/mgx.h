@@ -116,6 +116,24 @@ mgx_status mgx_recompose(const void *u_mc, void *u, mgx_dtype dtype, int ndim,
                          const int64_t *dims, const double *const *coords, int stop_level,
                          void *workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* Non-dyadic sizes (the dummy nodes of Sec. 6.2.2): an axis of n nodes is
+ * padded to the next 2^m + 1 >= n (m >= 1) with dummy nodes after the last
+ * real node, each carrying the value of the nearest real node; the padded
+ * field goes through the dyadic path (coordinates, if any, continued with
+ * the last spacing by the caller) and the result is cropped back.  The L-inf
+ * bound then holds on every real node.
+ *   mgx_dyadic_dims  padded_out: host, ndim entries.  MGX_ERR_SHAPE if some
+ *                    n < 2.
+ *   mgx_pad          u (device, dims) -> u_pad (device, padded dims).
+ *   mgx_crop         u_pad (device, padded dims) -> u (device, dims).
+ * u and u_pad must not overlap.  Errors: MGX_ERR_ARG, MGX_ERR_SHAPE,
+ * MGX_ERR_HIP. */
+mgx_status mgx_dyadic_dims(int ndim, const int64_t *dims, int64_t *padded_out);
+mgx_status mgx_pad(const void *u, void *u_pad, mgx_dtype dtype, int ndim, const int64_t *dims,
+                   hipStream_t stream);
+mgx_status mgx_crop(const void *u_pad, void *u, mgx_dtype dtype, int ndim, const int64_t *dims,
+                    hipStream_t stream);
+
 /* Adaptive decomposition (Sec. 4.2 "Adaptive decomposition", Alg. 1 lines
  * 1-16), 3-D fields only.  Before decomposing level l (from L down), the
  * Lorenzo predictor and the multilinear interpolation are compared on

@@ -149,6 +149,27 @@ def recompose_to(u_mc, target_level, coords=None, stop_level=0) -> np.ndarray:
     return np.ascontiguousarray(v[tuple(slice(None, None, s) if n > 1 else slice(None) for n in v.shape)])
 
 
+def dyadic_shape(shape):
+    """Every axis to the next 2^m + 1 >= n (m >= 1): the dummy-node padding of
+    non-dyadic sizes (Sec. 6.2.2)."""
+    out = []
+    for n in shape:
+        if n < 2:
+            raise OracleError(2, "dyadic_shape")
+        m = 1
+        while 2 ** m + 1 < n:
+            m += 1
+        out.append(2 ** m + 1)
+    return tuple(out)
+
+
+def pad_to_dyadic(u):
+    """Dummy nodes after the last real node of every axis, each with the value
+    of the nearest real node."""
+    u = np.asarray(u, dtype=np.float64)
+    return np.pad(u, [(0, p - n) for n, p in zip(u.shape, dyadic_shape(u.shape))], mode="edge")
+
+
 PENALTY = {"lorenzo": 1.22, "edge": 0.369, "plane": 0.259, "cube": 0.182}  # Sec. 4.2, units of tau
 
 

@@ -97,6 +97,7 @@ EXPORTS = (
     "mgx_recompose_adjoint", "mgx_batch_workspace_size", "mgx_decompose_batched", "mgx_recompose_batched",
     "mgx_batch_set_autotune", "mgx_batch_last_info", "mgx_decompose_quantize", "mgx_dequantize_recompose",
     "mgx_recompose_to", "mgx_decompose_adaptive", "mgx_adaptive_estimate", "mgx_adaptive_workspace_size",
+    "mgx_dyadic_dims", "mgx_pad", "mgx_crop",
 )
 
 _lib = None
@@ -130,6 +131,11 @@ def lib():
         L.mgx_adaptive_estimate.restype = ci
         L.mgx_adaptive_workspace_size.argtypes = [ci, i64p]
         L.mgx_adaptive_workspace_size.restype = sz
+        L.mgx_dyadic_dims.argtypes = [ci, i64p, i64p]
+        L.mgx_dyadic_dims.restype = ci
+        for name in ("mgx_pad", "mgx_crop"):
+            getattr(L, name).argtypes = [vp, vp, ci, ci, i64p, vp]
+            getattr(L, name).restype = ci
         L.mgx_adjoint_workspace_size.argtypes = [ci, ci, i64p, ci]
         L.mgx_adjoint_workspace_size.restype = sz
         for name in ("mgx_decompose", "mgx_recompose", "mgx_decompose_adjoint", "mgx_recompose_adjoint"):
@@ -333,6 +339,58 @@ def recompose_to(u_mc, target_level, coords=None, stop_level=0, out=None, worksp
                                   _dims(u_mc.shape), c.ptr, int(stop_level), int(target_level), ws.data_ptr(),
                                   ws.numel() * ws.element_size(), _stream(u_mc.device))
     _check(code, "mgx_recompose_to")
+    return out
+
+
+def dyadic_shape(shape):
+    """The padded shape of a non-dyadic field: every axis to the next 2^m + 1."""
+    out = (ctypes.c_int64 * len(shape))()
+    _check(lib().mgx_dyadic_dims(len(shape), _dims(shape), out), "mgx_dyadic_dims")
+    return tuple(int(x) for x in out)
+
+
+def pad_coords(coords, shape):
+    """Coordinates of the padded grid: each axis continued with its last spacing."""
+    if coords is None:
+        return None
+    padded = dyadic_shape(shape)
+    out = []
+    for c, n, p in zip(coords, shape, padded):
+        if c is None:
+            out.append(None)
+            continue
+        c = np.asarray(c, dtype=np.float64)
+        out.append(np.concatenate([c, c[-1] + (c[-1] - c[-2]) * np.arange(1, p - n + 1)]))
+    return out
+
+
+def pad(u, out=None):
+    """Dummy-node padding of u to dyadic_shape(u.shape) (the nearest real node's value)."""
+    import torch
+    _check_tensor(u, "u")
+    shape = dyadic_shape(u.shape)
+    if out is None:
+        out = torch.empty(shape, dtype=u.dtype, device=u.device)
+    _check_tensor(out, "out")
+    if tuple(out.shape) != shape or out.dtype != u.dtype:
+        raise ValueError(f"out must be {shape} {u.dtype}")
+    _check(lib().mgx_pad(u.data_ptr(), out.data_ptr(), _dtype_code(u), u.dim(), _dims(u.shape),
+                         _stream(u.device)), "mgx_pad")
+    return out
+
+
+def crop(u_pad, shape, out=None):
+    """The real nodes of a padded field: the inverse of pad for the shape `shape`."""
+    import torch
+    _check_tensor(u_pad, "u_pad")
+    shape = tuple(shape)
+    if tuple(u_pad.shape) != dyadic_shape(shape):
+        raise ValueError(f"u_pad must have the padded shape {dyadic_shape(shape)}")
+    if out is None:
+        out = torch.empty(shape, dtype=u_pad.dtype, device=u_pad.device)
+    _check_tensor(out, "out")
+    _check(lib().mgx_crop(u_pad.data_ptr(), out.data_ptr(), _dtype_code(u_pad), len(shape), _dims(shape),
+                          _stream(u_pad.device)), "mgx_crop")
     return out
 
 

@@ -1484,6 +1484,75 @@ mgx_status mgx_adaptive_estimate(const void *v, mgx_dtype dtype, int ndim, const
                                &sums_out[0], &sums_out[1], counts_out);
 }
 
+mgx_status mgx_dyadic_dims(int ndim, const int64_t *dims, int64_t *padded_out) {
+  if (ndim < 1 || ndim > 3 || !dims || !padded_out) return MGX_ERR_ARG;
+  for (int k = 0; k < ndim; k++) {
+    if (dims[k] < 2 || dims[k] > ((int64_t)1 << 30) + 1) return MGX_ERR_SHAPE;
+    int64_t p = 3;
+    while (p < dims[k]) p = 2 * p - 1;  // 2^m + 1 -> 2^(m+1) + 1
+    padded_out[k] = p;
+  }
+  return MGX_OK;
+}
+
+// Box extents of dims padded to three axes (leading axes of 1).
+static void box3(int ndim, const int64_t *d, int64_t out[3]) {
+  for (int k = 0; k < 3; k++) {
+    const int src = k - (3 - ndim);
+    out[k] = src >= 0 ? d[src] : 1;
+  }
+}
+
+mgx_status mgx_pad(const void *u, void *u_pad, mgx_dtype dtype, int ndim, const int64_t *dims,
+                   hipStream_t stream) {
+  if (!u || !u_pad || (dtype != MGX_F32 && dtype != MGX_F64)) return MGX_ERR_ARG;
+  int64_t pd[3];
+  mgx_status s = mgx_dyadic_dims(ndim, dims, pd);
+  if (s) return s;
+  int64_t n[3], p[3];
+  box3(ndim, dims, n);
+  box3(ndim, pd, p);
+  const size_t es = elem_size(dtype);
+  if ((p[0] * p[1] * p[2]) > INT32_MAX || overlaps(u, (size_t)(n[0] * n[1] * n[2]) * es, u_pad,
+                                                   (size_t)(p[0] * p[1] * p[2]) * es))
+    return MGX_ERR_ARG;
+  hipError_t e;
+  if (dtype == MGX_F32)
+    e = launch_pad_edge<float>(PadArgs<float>{(const float *)u, (float *)u_pad, (int)n[0], (int)n[1], (int)n[2],
+                                              (int)p[0], (int)p[1], (int)p[2]},
+                               stream);
+  else
+    e = launch_pad_edge<double>(PadArgs<double>{(const double *)u, (double *)u_pad, (int)n[0], (int)n[1], (int)n[2],
+                                                (int)p[0], (int)p[1], (int)p[2]},
+                                stream);
+  return hip_status(e);
+}
+
+mgx_status mgx_crop(const void *u_pad, void *u, mgx_dtype dtype, int ndim, const int64_t *dims,
+                    hipStream_t stream) {
+  if (!u || !u_pad || (dtype != MGX_F32 && dtype != MGX_F64)) return MGX_ERR_ARG;
+  int64_t pd[3];
+  mgx_status s = mgx_dyadic_dims(ndim, dims, pd);
+  if (s) return s;
+  int64_t n[3], p[3];
+  box3(ndim, dims, n);
+  box3(ndim, pd, p);
+  const size_t es = elem_size(dtype);
+  if ((p[0] * p[1] * p[2]) > INT32_MAX || overlaps(u, (size_t)(n[0] * n[1] * n[2]) * es, u_pad,
+                                                   (size_t)(p[0] * p[1] * p[2]) * es))
+    return MGX_ERR_ARG;
+  hipError_t e;
+  if (dtype == MGX_F32)
+    e = launch_copy_box<float>(CopyArgs<float>{(const float *)u_pad, p[1] * p[2], p[2], (float *)u, n[1] * n[2], n[2],
+                                               (int)n[0], (int)n[1], (int)n[2]},
+                               stream);
+  else
+    e = launch_copy_box<double>(CopyArgs<double>{(const double *)u_pad, p[1] * p[2], p[2], (double *)u, n[1] * n[2],
+                                                 n[2], (int)n[0], (int)n[1], (int)n[2]},
+                                stream);
+  return hip_status(e);
+}
+
 size_t mgx_adaptive_workspace_size(int ndim, const int64_t *dims) {
   int64_t n[3];
   bool real[3];

@@ -1409,6 +1409,27 @@ __global__ void __launch_bounds__(256) k_copy_box(CopyArgs<T> a) {
   copy_box_body<T>(a, blockIdx.x, gridDim.x);
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) k_pad_edge(PadArgs<T> a) {
+  const int64_t n = (int64_t)a.p0 * a.p1 * a.p2;
+  for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const int64_t r = i / a.p2;
+    const int i2 = (int)(i - r * a.p2);
+    const int i0 = (int)(r / a.p1), i1 = (int)(r - (int64_t)i0 * a.p1);
+    const int j0 = min(i0, a.n0 - 1), j1 = min(i1, a.n1 - 1), j2 = min(i2, a.n2 - 1);
+    a.dst[i] = a.src[((int64_t)j0 * a.n1 + j1) * a.n2 + j2];
+  }
+}
+
+template <typename T>
+hipError_t launch_pad_edge(PadArgs<T> a, hipStream_t st) {
+  if (a.n0 < 1 || a.n1 < 1 || a.n2 < 1 || a.p0 < a.n0 || a.p1 < a.n1 || a.p2 < a.n2) return hipErrorInvalidValue;
+  int64_t blocks = ((int64_t)a.p0 * a.p1 * a.p2 + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL((k_pad_edge<T>), dim3((unsigned)blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Quantization (Sec. 4.1): label = rint(c / q_l) in FP64.
 // The level of a position in the level-centric layout is the smallest l whose
@@ -2679,6 +2700,7 @@ hipError_t launch_op_multi(int kind, int key, const OpArgs<T> *dargs, const int 
   template hipError_t launch_prolong_mass<T>(ProlongArgs<T>, int, hipStream_t);               \
   template hipError_t launch_copy_box<T>(CopyArgs<T>, hipStream_t);                           \
   template hipError_t launch_adaptive_estimate<T>(EstimateArgs<T>, int, hipStream_t);         \
+  template hipError_t launch_pad_edge<T>(PadArgs<T>, hipStream_t);                             \
   template hipError_t launch_quantize<T>(const T *, int32_t *, QuantArgs, bool, hipStream_t); \
   template hipError_t launch_dequantize<T>(const int32_t *, T *, QuantArgs, hipStream_t);
 

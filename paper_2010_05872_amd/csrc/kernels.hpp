@@ -123,6 +123,17 @@ struct CopyArgs {             // strided copy of an n0 x n1 x n2 box
   int n0, n1, n2;
 };
 
+// Dummy-node padding of a non-dyadic box (n0 x n1 x n2) to a dyadic one
+// (p0 x p1 x p2, every p_k >= n_k): each padded node takes the value of the
+// nearest real node (index clamped to n_k - 1).
+template <typename T>
+struct PadArgs {
+  const T *src;
+  T *dst;
+  int n0, n1, n2, p0, p1, p2;
+};
+template <typename T> hipError_t launch_pad_edge(PadArgs<T> a, hipStream_t st);
+
 // The coarse tail of the hierarchy (every level box at most kTailBox nodes
 // per axis) in one workgroup: all its levels in one launch instead of one
 // latency-bound launch per step and level.
