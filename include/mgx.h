@@ -116,6 +116,38 @@ mgx_status mgx_recompose(const void *u_mc, void *u, mgx_dtype dtype, int ndim,
                          const int64_t *dims, const double *const *coords, int stop_level,
                          void *workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* L2 variant of level-wise quantization (Sec. 4.1, the cost-optimal bin
+ * widths under the L2 error budget): tau_l = tol_l2 / sqrt(c_l2 h_l^d #N_L)
+ * for l = stop_level .. L (tau_out[l - stop_level], host), so that
+ * sum_l #N*_l h_l^d tau_l^2 = tol_l2^2 / c_l2.  h_l^d is the level's cell
+ * volume (extent / intervals on every real axis).  The paper does not print
+ * C_L2: c_l2 > 0 must be given.  Errors: MGX_ERR_TOL, _LEVEL, _SHAPE, _COORDS. */
+mgx_status mgx_level_tolerances_l2(int ndim, const int64_t *dims, const double *const *coords, double tol_l2,
+                                   int stop_level, double c_l2, double *tau_out);
+
+/* Level-wise quantization with caller-given tolerances tau[0 .. L-stop]
+ * (host; level stop_level + i uses tau[i], bin width 2 tau[i]), e.g. from
+ * mgx_level_tolerances_l2; otherwise as mgx_quantize / mgx_dequantize.
+ * MGX_ERR_TOL if some tau[i] is not positive and finite. */
+mgx_status mgx_quantize_levels(const void *u_mc, int32_t *labels, mgx_dtype dtype, int ndim, const int64_t *dims,
+                               const double *const *coords, int stop_level, const double *tau,
+                               mgx_quant_stats *stats, hipStream_t stream);
+mgx_status mgx_dequantize_levels(const int32_t *labels, void *u_mc, mgx_dtype dtype, int ndim, const int64_t *dims,
+                                 const double *const *coords, int stop_level, const double *tau,
+                                 hipStream_t stream);
+
+/* Shannon entropy of the labels of each level, in bits per label (Sec. 4.1:
+ * the estimated cost of storing the labels): bits_out[l - stop_level] =
+ * -sum_k p_k log2 p_k over the distinct labels k of level l (the stop
+ * level's whole box counts as one level), host, L + 1 - stop_level entries.
+ * labels: device, level-centric layout of that stop level.  Workspace:
+ * mgx_label_entropy_workspace_size bytes (about 20 bytes per label), must
+ * not overlap labels.  Synchronizes `stream`.
+ * Errors: MGX_ERR_ARG, _SHAPE, _LEVEL, _WORKSPACE, _HIP. */
+mgx_status mgx_label_entropy(const int32_t *labels, int ndim, const int64_t *dims, int stop_level, double *bits_out,
+                             void *workspace, size_t workspace_bytes, hipStream_t stream);
+size_t mgx_label_entropy_workspace_size(int ndim, const int64_t *dims, int stop_level);
+
 /* Non-dyadic sizes (the dummy nodes of Sec. 6.2.2): an axis of n nodes is
  * padded to the next 2^m + 1 >= n (m >= 1) with dummy nodes after the last
  * real node, each carrying the value of the nearest real node; the padded

@@ -170,6 +170,52 @@ def pad_to_dyadic(u):
     return np.pad(u, [(0, p - n) for n, p in zip(u.shape, dyadic_shape(u.shape))], mode="edge")
 
 
+def level_tolerances_l2(shape, tol_l2, c_l2, coords=None, stop_level=0) -> np.ndarray:
+    """L2 variant of Sec. 4.1: tau_l = tol / sqrt(C_L2 h_l^d #N_L), h_l^d the level's
+    cell volume (extent / intervals per axis), levels stop_level .. L."""
+    L = num_levels(shape)
+    Xs = [np.arange(n, dtype=np.float64) if (coords is None or coords[k] is None)
+          else np.asarray(coords[k], dtype=np.float64) for k, n in enumerate(shape)]
+    nL = float(np.prod(shape))
+    out = []
+    for l in range(int(stop_level), L + 1):
+        hd = 1.0
+        for X, n in zip(Xs, shape):
+            m = (n - 1) // 2 ** (L - l) + 1
+            hd = hd * ((X[-1] - X[0]) / (m - 1))
+        out.append(tol_l2 / np.sqrt(c_l2 * hd * nL))
+    return np.array(out)
+
+
+def quantize_levels(u_mc, tau, stop_level=0):
+    """Labels rint(c / (2 tau_l)) with caller-given per-level tolerances (FP64;
+    interleaved layout in and out)."""
+    v = np.asarray(u_mc, dtype=np.float64)
+    lev = level_map(v.shape, stop_level)
+    q = 2.0 * np.asarray(tau, dtype=np.float64)[lev - int(stop_level)]
+    return np.rint(v / q).astype(np.int32)
+
+
+def dequantize_levels(labels, tau, stop_level=0):
+    lab = np.asarray(labels)
+    lev = level_map(lab.shape, stop_level)
+    return lab.astype(np.float64) * (2.0 * np.asarray(tau, dtype=np.float64)[lev - int(stop_level)])
+
+
+def label_entropy(labels, stop_level=0):
+    """Shannon entropy in bits per label of each level's labels (Sec. 4.1),
+    interleaved layout."""
+    lab = np.asarray(labels)
+    lev = level_map(lab.shape, stop_level)
+    L = num_levels(lab.shape)
+    out = []
+    for l in range(int(stop_level), L + 1):
+        _, counts = np.unique(lab[lev == l], return_counts=True)
+        p = counts / counts.sum()
+        out.append(float(-(p * np.log2(p)).sum()))
+    return np.array(out)
+
+
 PENALTY = {"lorenzo": 1.22, "edge": 0.369, "plane": 0.259, "cube": 0.182}  # Sec. 4.2, units of tau
 
 

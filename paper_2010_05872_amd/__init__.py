@@ -97,7 +97,8 @@ EXPORTS = (
     "mgx_recompose_adjoint", "mgx_batch_workspace_size", "mgx_decompose_batched", "mgx_recompose_batched",
     "mgx_batch_set_autotune", "mgx_batch_last_info", "mgx_decompose_quantize", "mgx_dequantize_recompose",
     "mgx_recompose_to", "mgx_decompose_adaptive", "mgx_adaptive_estimate", "mgx_adaptive_workspace_size",
-    "mgx_dyadic_dims", "mgx_pad", "mgx_crop",
+    "mgx_dyadic_dims", "mgx_pad", "mgx_crop", "mgx_level_tolerances_l2", "mgx_quantize_levels",
+    "mgx_dequantize_levels", "mgx_label_entropy", "mgx_label_entropy_workspace_size",
 )
 
 _lib = None
@@ -131,6 +132,16 @@ def lib():
         L.mgx_adaptive_estimate.restype = ci
         L.mgx_adaptive_workspace_size.argtypes = [ci, i64p]
         L.mgx_adaptive_workspace_size.restype = sz
+        L.mgx_level_tolerances_l2.argtypes = [ci, i64p, vp, cd, ci, cd, dp]
+        L.mgx_level_tolerances_l2.restype = ci
+        L.mgx_quantize_levels.argtypes = [vp, vp, ci, ci, i64p, vp, ci, dp, vp, vp]
+        L.mgx_quantize_levels.restype = ci
+        L.mgx_dequantize_levels.argtypes = [vp, vp, ci, ci, i64p, vp, ci, dp, vp]
+        L.mgx_dequantize_levels.restype = ci
+        L.mgx_label_entropy.argtypes = [vp, ci, i64p, ci, dp, vp, sz, vp]
+        L.mgx_label_entropy.restype = ci
+        L.mgx_label_entropy_workspace_size.argtypes = [ci, i64p, ci]
+        L.mgx_label_entropy_workspace_size.restype = sz
         L.mgx_dyadic_dims.argtypes = [ci, i64p, i64p]
         L.mgx_dyadic_dims.restype = ci
         for name in ("mgx_pad", "mgx_crop"):
@@ -618,6 +629,72 @@ def dequantize(labels, tol, dtype, coords=None, stop_level=0, c_linf=0.0, out=No
                                 _stream(labels.device))
     _check(code, "mgx_dequantize")
     return out
+
+
+def level_tolerances_l2(shape, tol_l2, c_l2, coords=None, stop_level=0) -> np.ndarray:
+    """tau_l of the L2 variant (levels stop_level .. L); c_l2 must be given."""
+    L = num_levels(shape)
+    tau = np.zeros(L + 1 - int(stop_level), dtype=np.float64)
+    c = Coords(shape, coords)
+    code = lib().mgx_level_tolerances_l2(len(shape), _dims(shape), c.ptr, float(tol_l2), int(stop_level),
+                                         float(c_l2), tau.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    _check(code, "mgx_level_tolerances_l2")
+    return tau
+
+
+def _tau_arg(tau, shape, stop_level):
+    tau = np.ascontiguousarray(tau, dtype=np.float64)
+    if tau.shape != (num_levels(shape) + 1 - int(stop_level),):
+        raise ValueError("tau needs one entry per level stop_level .. L")
+    return tau
+
+
+def quantize_levels(u_mc, tau, coords=None, stop_level=0, out=None):
+    """Labels with caller-given per-level tolerances tau (levels stop_level .. L)."""
+    import torch
+    _check_tensor(u_mc, "u_mc")
+    t = _tau_arg(tau, u_mc.shape, stop_level)
+    if out is None:
+        out = torch.empty(u_mc.shape, dtype=torch.int32, device=u_mc.device)
+    _check_tensor(out, "labels")
+    c = Coords(u_mc.shape, coords)
+    code = lib().mgx_quantize_levels(u_mc.data_ptr(), out.data_ptr(), _dtype_code(u_mc), u_mc.dim(),
+                                     _dims(u_mc.shape), c.ptr, int(stop_level),
+                                     t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None, _stream(u_mc.device))
+    _check(code, "mgx_quantize_levels")
+    return out
+
+
+def dequantize_levels(labels, tau, dtype, coords=None, stop_level=0, out=None):
+    """Coefficients from labels with caller-given per-level tolerances."""
+    import torch
+    _check_tensor(labels, "labels")
+    t = _tau_arg(tau, labels.shape, stop_level)
+    if out is None:
+        out = torch.empty(labels.shape, dtype=dtype, device=labels.device)
+    _check_tensor(out, "out")
+    c = Coords(labels.shape, coords)
+    code = lib().mgx_dequantize_levels(labels.data_ptr(), out.data_ptr(), _dtype_code(out), labels.dim(),
+                                       _dims(labels.shape), c.ptr, int(stop_level),
+                                       t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream(labels.device))
+    _check(code, "mgx_dequantize_levels")
+    return out
+
+
+def label_entropy(labels, stop_level=0, workspace=None) -> np.ndarray:
+    """Shannon entropy (bits per label) of the labels of each level stop_level .. L."""
+    import torch
+    _check_tensor(labels, "labels")
+    shape = tuple(labels.shape)
+    need = lib().mgx_label_entropy_workspace_size(len(shape), _dims(shape), int(stop_level))
+    if workspace is None:
+        workspace = torch.empty(max(need, 8), dtype=torch.uint8, device=labels.device)
+    bits = np.zeros(num_levels(shape) + 1 - int(stop_level), dtype=np.float64)
+    code = lib().mgx_label_entropy(labels.data_ptr(), len(shape), _dims(shape), int(stop_level),
+                                   bits.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), workspace.data_ptr(),
+                                   workspace.numel() * workspace.element_size(), _stream(labels.device))
+    _check(code, "mgx_label_entropy")
+    return bits
 
 
 from .autograd import Decompose, MGXRoundTrip, QuantizeSTE, Recompose  # noqa: E402,F401

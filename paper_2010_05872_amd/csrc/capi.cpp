@@ -12,6 +12,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "entropy.hpp"
 #include "kernels.hpp"
 #include "mgx.h"
 #include "plan.hpp"
@@ -785,15 +786,24 @@ mgx_status tolerances(Plan *P, int ndim, double tol, int stop, double c_linf, do
   return MGX_OK;
 }
 
+// tau_in (optional): the tolerances of levels stop .. L given by the caller
+// instead of the L-infinity schedule of tol.
 mgx_status quant_args(int ndim, const int64_t *dims, const double *const *coords, double tol, int stop,
-                      double c_linf, QuantArgs *qa, Plan **plan) {
+                      double c_linf, QuantArgs *qa, Plan **plan, const double *tau_in = nullptr) {
   int st = 0;
   Plan *P = get_plan(ndim, dims, coords, &st);
   if (!P) return (mgx_status)st;
   if (stop < 0 || stop > P->L) return MGX_ERR_LEVEL;
   double tau[kMaxLevels];
-  mgx_status s = tolerances(P, ndim, tol, stop, c_linf, tau);
-  if (s) return s;
+  if (tau_in) {
+    for (int i = 0; i <= P->L - stop; i++) {
+      if (!(tau_in[i] > 0.0) || !std::isfinite(tau_in[i])) return MGX_ERR_TOL;
+      tau[i] = tau_in[i];
+    }
+  } else {
+    mgx_status s = tolerances(P, ndim, tol, stop, c_linf, tau);
+    if (s) return s;
+  }
   const int L = P->L;
   std::memset(qa, 0, sizeof(*qa));
   qa->n = P->n[0] * P->n[1] * P->n[2];
@@ -1608,9 +1618,10 @@ mgx_status mgx_recompose_adjoint(const void *g_u, void *g_mc, mgx_dtype dtype, i
                                        (const double *)tab, stream);
 }
 
-mgx_status mgx_quantize(const void *u_mc, int32_t *labels, mgx_dtype dtype, int ndim, const int64_t *dims,
-                        const double *const *coords, double tol_linf, int stop_level, double c_linf,
-                        mgx_quant_stats *stats, hipStream_t stream) {
+static mgx_status quantize_common(const void *u_mc, int32_t *labels, mgx_dtype dtype, int ndim,
+                                  const int64_t *dims, const double *const *coords, double tol_linf,
+                                  int stop_level, double c_linf, const double *tau_in, mgx_quant_stats *stats,
+                                  hipStream_t stream) {
   if (dtype != MGX_F32 && dtype != MGX_F64) return MGX_ERR_ARG;
   int64_t n[3];
   bool real[3];
@@ -1622,7 +1633,7 @@ mgx_status mgx_quantize(const void *u_mc, int32_t *labels, mgx_dtype dtype, int 
   if (overlaps(u_mc, cnt * elem_size(dtype), labels, cnt * 4)) return MGX_ERR_ARG;
   QuantArgs qa;
   Plan *P;
-  mgx_status s = quant_args(ndim, dims, coords, tol_linf, stop_level, c_linf, &qa, &P);
+  mgx_status s = quant_args(ndim, dims, coords, tol_linf, stop_level, c_linf, &qa, &P, tau_in);
   if (s) return s;
   if (!stats) {
     hipError_t e = traced("quantize", -1, stream, [&] {
@@ -1663,9 +1674,9 @@ mgx_status mgx_quantize(const void *u_mc, int32_t *labels, mgx_dtype dtype, int 
   return (ovf || nan) ? MGX_ERR_RANGE : MGX_OK;
 }
 
-mgx_status mgx_dequantize(const int32_t *labels, void *u_mc, mgx_dtype dtype, int ndim, const int64_t *dims,
-                          const double *const *coords, double tol_linf, int stop_level, double c_linf,
-                          hipStream_t stream) {
+static mgx_status dequantize_common(const int32_t *labels, void *u_mc, mgx_dtype dtype, int ndim,
+                                    const int64_t *dims, const double *const *coords, double tol_linf,
+                                    int stop_level, double c_linf, const double *tau_in, hipStream_t stream) {
   if (dtype != MGX_F32 && dtype != MGX_F64) return MGX_ERR_ARG;
   int64_t n[3];
   bool real[3];
@@ -1677,13 +1688,80 @@ mgx_status mgx_dequantize(const int32_t *labels, void *u_mc, mgx_dtype dtype, in
   if (overlaps(u_mc, cnt * elem_size(dtype), labels, cnt * 4)) return MGX_ERR_ARG;
   QuantArgs qa;
   Plan *P;
-  mgx_status s = quant_args(ndim, dims, coords, tol_linf, stop_level, c_linf, &qa, &P);
+  mgx_status s = quant_args(ndim, dims, coords, tol_linf, stop_level, c_linf, &qa, &P, tau_in);
   if (s) return s;
   hipError_t e = traced("dequantize", -1, stream, [&] {
     return dtype == MGX_F32 ? launch_dequantize<float>(labels, (float *)u_mc, qa, stream)
                             : launch_dequantize<double>(labels, (double *)u_mc, qa, stream);
   });
   return hip_status(e);
+}
+
+mgx_status mgx_quantize(const void *u_mc, int32_t *labels, mgx_dtype dtype, int ndim, const int64_t *dims,
+                        const double *const *coords, double tol_linf, int stop_level, double c_linf,
+                        mgx_quant_stats *stats, hipStream_t stream) {
+  return quantize_common(u_mc, labels, dtype, ndim, dims, coords, tol_linf, stop_level, c_linf, nullptr, stats,
+                         stream);
+}
+
+mgx_status mgx_dequantize(const int32_t *labels, void *u_mc, mgx_dtype dtype, int ndim, const int64_t *dims,
+                          const double *const *coords, double tol_linf, int stop_level, double c_linf,
+                          hipStream_t stream) {
+  return dequantize_common(labels, u_mc, dtype, ndim, dims, coords, tol_linf, stop_level, c_linf, nullptr, stream);
+}
+
+mgx_status mgx_quantize_levels(const void *u_mc, int32_t *labels, mgx_dtype dtype, int ndim, const int64_t *dims,
+                               const double *const *coords, int stop_level, const double *tau,
+                               mgx_quant_stats *stats, hipStream_t stream) {
+  if (!tau) return MGX_ERR_ARG;
+  return quantize_common(u_mc, labels, dtype, ndim, dims, coords, 1.0, stop_level, 0.0, tau, stats, stream);
+}
+
+mgx_status mgx_dequantize_levels(const int32_t *labels, void *u_mc, mgx_dtype dtype, int ndim, const int64_t *dims,
+                                 const double *const *coords, int stop_level, const double *tau,
+                                 hipStream_t stream) {
+  if (!tau) return MGX_ERR_ARG;
+  return dequantize_common(labels, u_mc, dtype, ndim, dims, coords, 1.0, stop_level, 0.0, tau, stream);
+}
+
+size_t mgx_label_entropy_workspace_size(int ndim, const int64_t *dims, int stop_level) {
+  int64_t n[3];
+  bool real[3];
+  int L;
+  if (parse_shape(ndim, dims, n, real, &L) || stop_level < 0 || stop_level > L) return 0;
+  return entropy_workspace(n[0] * n[1] * n[2], L + 1 - stop_level);
+}
+
+mgx_status mgx_label_entropy(const int32_t *labels, int ndim, const int64_t *dims, int stop_level, double *bits_out,
+                             void *workspace, size_t workspace_bytes, hipStream_t stream) {
+  if (!labels || !bits_out) return MGX_ERR_ARG;
+  int64_t n[3];
+  bool real[3];
+  int L;
+  int st = parse_shape(ndim, dims, n, real, &L);
+  if (st) return (mgx_status)st;
+  if (stop_level < 0 || stop_level > L) return MGX_ERR_LEVEL;
+  const int64_t cnt = n[0] * n[1] * n[2];
+  const size_t need = entropy_workspace(cnt, L + 1 - stop_level);
+  if (need == 0) return MGX_ERR_SHAPE;
+  if (!workspace || workspace_bytes < need) return MGX_ERR_WORKSPACE;
+  if (overlaps(workspace, need, labels, (size_t)cnt * 4)) return MGX_ERR_ARG;
+  double ones[kMaxLevels];
+  for (int i = 0; i < kMaxLevels; i++) ones[i] = 1.0;
+  QuantArgs qa;
+  Plan *P;
+  mgx_status s = quant_args(ndim, dims, nullptr, 1.0, stop_level, 0.0, &qa, &P, ones);
+  if (s) return s;
+  // labels per level: the stop level's whole box, then each finer level's new nodes
+  int64_t count[kMaxLevels], prev = 0;
+  for (int l = stop_level; l <= L; l++) {
+    int64_t m[3];
+    level_box(P, l, m);
+    const int64_t box = m[0] * m[1] * m[2];
+    count[l - stop_level] = box - prev;
+    prev = box;
+  }
+  return hip_status(label_entropy(labels, qa, count, (char *)workspace, stream, bits_out));
 }
 
 double mgx_linf_constant(int ndim, const int64_t *dims, const double *const *coords, int stop_level) {
@@ -1701,6 +1779,28 @@ mgx_status mgx_level_tolerances(int ndim, const int64_t *dims, const double *con
   if (!P) return (mgx_status)st;
   if (stop_level < 0 || stop_level > P->L) return MGX_ERR_LEVEL;
   return tolerances(P, ndim, tol_linf, stop_level, c_linf, tau_out);
+}
+
+mgx_status mgx_level_tolerances_l2(int ndim, const int64_t *dims, const double *const *coords, double tol_l2,
+                                   int stop_level, double c_l2, double *tau_out) {
+  if (!tau_out) return MGX_ERR_ARG;
+  int st = 0;
+  Plan *P = get_plan(ndim, dims, coords, &st);
+  if (!P) return (mgx_status)st;
+  if (stop_level < 0 || stop_level > P->L) return MGX_ERR_LEVEL;
+  if (!(tol_l2 > 0.0) || !std::isfinite(tol_l2) || !(c_l2 > 0.0) || !std::isfinite(c_l2)) return MGX_ERR_TOL;
+  const double nL = (double)(P->n[0] * P->n[1] * P->n[2]);
+  for (int l = stop_level; l <= P->L; l++) {
+    // h_l^d: the level's cell volume, extent / intervals on every real axis
+    double hd = 1.0;
+    for (int k = 0; k < 3; k++) {
+      if (!P->real[k]) continue;
+      const int64_t m = (P->n[k] - 1) / ((int64_t)1 << (P->L - l)) + 1;
+      hd = hd * ((P->X[k][P->n[k] - 1] - P->X[k][0]) / (double)(m - 1));
+    }
+    tau_out[l - stop_level] = tol_l2 / std::sqrt(c_l2 * hd * nL);
+  }
+  return MGX_OK;
 }
 
 mgx_status mgx_trace_enable(int on) {

@@ -1456,6 +1456,22 @@ __device__ __forceinline__ int elem_level(uint32_t idx, const QuantArgs &a) {
   return l;
 }
 
+__global__ void __launch_bounds__(256) k_entropy_keys(const int32_t *__restrict__ labels, uint64_t *__restrict__ keys,
+                                                     QuantArgs a) {
+  for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * 256) {
+    const int l = elem_level((uint32_t)i, a);
+    keys[i] = ((uint64_t)(uint32_t)(l - a.first) << 32) | (uint64_t)((uint32_t)labels[i] ^ 0x80000000u);
+  }
+}
+
+hipError_t launch_entropy_keys(const int32_t *labels, uint64_t *keys, const QuantArgs &qa, hipStream_t st) {
+  int64_t blocks = (qa.n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_entropy_keys, dim3((unsigned)blocks), dim3(256), 0, st, labels, keys, qa);
+  return hipGetLastError();
+}
+
 // Four consecutive elements of T / int32 as one 16-byte (float, int32) or
 // two 16-byte (double) accesses when the buffers are 16-byte aligned.
 template <typename T, bool VEC>

@@ -1,0 +1,52 @@
+"""The L2 quantizer schedule and the label entropy on the GPU against the
+oracle: labels from caller-given tolerances bit-exact (quantize and
+dequantize), and the per-level entropies of the labels equal to the oracle's
+(the counts are exact, so 1e-12 relative), on shapes with several levels,
+both dtypes and two stop levels."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2010_05872_amd as mgx  # noqa: E402
+
+
+@pytest.mark.parametrize("case", [((33, 65, 129), torch.float32), ((65, 65, 65), torch.float64), ((257, 129), torch.float32),
+                                  ((4097,), torch.float64)],
+                         ids=lambda c: f"{'x'.join(map(str, c[0]))}-{str(c[1])[6:]}")
+def test_l2_labels_and_entropy(case):
+    shape, dt = case
+    print(f"[l2-entropy] {shape} {dt}", flush=True)
+    sys.stdout.flush()
+    u = torch.as_tensor(workloads.gaussian_random_field(shape, slope=3.0, seed=31), dtype=dt, device="cuda")
+    for stop in (0, 2):
+        umc = mgx.decompose(u, None, stop)
+        tau = mgx.level_tolerances_l2(shape, 1e-3 * float((u.max() - u.min()).item()), 4.0, None, stop)
+        lab = mgx.quantize_levels(umc, tau, None, stop)
+        back = mgx.dequantize_levels(lab, tau, dt, None, stop)
+        torch.cuda.synchronize()
+        umc64 = oracle.from_level_centric(umc.double().cpu().numpy(), stop)
+        want = oracle.to_level_centric(oracle.quantize_levels(umc64, tau, stop), stop)
+        assert np.array_equal(lab.cpu().numpy(), want)
+        wback = oracle.to_level_centric(oracle.dequantize_levels(oracle.from_level_centric(want, stop), tau, stop),
+                                        stop)
+        assert np.array_equal(back.double().cpu().numpy(), wback.astype(np.float32 if dt == torch.float32 else
+                                                                         np.float64).astype(np.float64))
+        H = mgx.label_entropy(lab, stop)
+        Href = oracle.label_entropy(oracle.from_level_centric(lab.cpu().numpy(), stop), stop)
+        assert np.allclose(H, Href, rtol=1e-12, atol=1e-12), (stop, H, Href)
+
+
+def test_entropy_workspace_errors():
+    lab = torch.zeros((33, 33, 33), dtype=torch.int32, device="cuda")
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(mgx.MgxError):
+        mgx.label_entropy(lab, 0, workspace=small)
+    H = mgx.label_entropy(lab, 0)
+    assert np.allclose(H, 0.0)
