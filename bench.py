@@ -265,6 +265,32 @@ def adaptive_section(torch, mgx, u, umc, ws, reps):
     return {"tau_over_range": out, "full_decompose_ms": round(full_ms, 4)}
 
 
+def entropy_section(torch, mgx, u, labels, tol, reps):
+    """Per-level entropy of the step's labels (L-infinity schedule) and the
+    estimated size of the labels in bits per value (Sec. 4.1's cost
+    estimate), with the time of the entropy pass; the same for the L2
+    schedule at the same tolerance with C_L2 = 1 (the paper prints no C_L2)."""
+    L = mgx.num_levels(u.shape)
+    counts, prev = [], 0
+    for l in range(L + 1):
+        box = 1
+        for m in mgx.level_shape(u.shape, l):
+            box *= m
+        counts.append(box - prev)
+        prev = box
+    ws = torch.empty(mgx.lib().mgx_label_entropy_workspace_size(3, mgx._dims(u.shape), 0), dtype=torch.uint8,
+                     device=u.device)
+    H = mgx.label_entropy(labels, 0, workspace=ws)
+    ms = timed(torch, lambda: mgx.label_entropy(labels, 0, workspace=ws), reps)
+    bits = float(sum(c * h for c, h in zip(counts, H)) / u.numel())
+    umc = mgx.decompose(u)
+    tau2 = mgx.level_tolerances_l2(u.shape, tol, 1.0)
+    H2 = mgx.label_entropy(mgx.quantize_levels(umc, tau2), 0, workspace=ws)
+    bits2 = float(sum(c * h for c, h in zip(counts, H2)) / u.numel())
+    return {"linf_bits_per_level": [round(float(h), 4) for h in H], "linf_bits_per_value": round(bits, 4),
+            "l2_bits_per_value_c1": round(bits2, 4), "entropy_ms": round(ms, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -415,6 +441,8 @@ def main():
         mgx.decompose(u, out=umc, workspace=ws)
         out["progressive"] = progressive_section(torch, mgx, u, umc, ws, max(3, args.steps // 4))
         out["adaptive"] = adaptive_section(torch, mgx, u, umc, ws, max(3, args.steps // 4))
+        mgx.decompose_quantize(u, tol, labels=labels, workspace=ws, keep_coef=False)
+        out["entropy"] = entropy_section(torch, mgx, u, labels, tol, 3)
         out["batched"] = batched_section(torch, mgx, workloads, dev, max(3, args.steps // 4))
         out["adjoint"] = adjoint_section(torch, mgx, workloads, dev, max(3, args.steps // 4))
     if not args.no_cpu_baseline:
