@@ -3,7 +3,9 @@ times (default tuning, caller-provided workspace).
 
 513^3 fp32 (turbulence spectrum): the whole decomposition (stop levels 0 and
 4), the recomposition of the same coefficients and the quantization labels
-against the oracle; the L-infinity bound end to end at three tolerances.
+against the oracle; the L-infinity bound end to end at three tolerances; the
+benchmark's fused step, progressive recomposition, the adaptive choice and
+the label entropy against the oracle.
 
 257x1025x1025 fp32 on the tanh-stretched axis (too large for the oracle in a
 test): the finest level's coefficients at sampled nodes against their
@@ -122,3 +124,36 @@ def test_config3_properties():
     g2, lab = mgx.decompose_quantize(u, tol, coords)
     r2 = mgx.dequantize_recompose(lab, tol, torch.float32, coords)
     assert (r2.double() - u.double()).abs().max().item() <= tol
+
+
+def test_513_fp32_fused_progressive_adaptive_entropy(field513):
+    """The benchmark's fused step (labels only) equal to the separate calls;
+    progressive recomposition to levels 6 and 7 against the oracle from the
+    same coefficients; the adaptive decomposition's choice against the
+    oracle's; the labels' per-level entropy against the oracle's."""
+    _say("[full] 513^3 fp32 fused / progressive / adaptive / entropy")
+    u = field513
+    tol = 1e-3 * float((u.max() - u.min()).item())
+    ws = torch.empty(mgx.workspace_size(mgx.MGX_F32, u.shape, 0), dtype=torch.uint8, device="cuda")
+    _, lab = mgx.decompose_quantize(u, tol, workspace=ws, keep_coef=False)
+    g = mgx.decompose(u, workspace=ws)
+    rlab = mgx.quantize(g, tol)
+    torch.cuda.synchronize()
+    assert torch.equal(lab, rlab)
+    u64 = u.double().cpu().numpy()
+    scale = np.abs(u64).max()
+    g64 = oracle.from_level_centric(g.double().cpu().numpy(), 0)
+    for t in (6, 7):
+        got = mgx.recompose_to(g, t, workspace=ws)
+        torch.cuda.synchronize()
+        ref = oracle.recompose_to(g64, t)
+        err = np.abs(got.double().cpu().numpy() - ref).max()
+        _say(f"  recompose_to({t}) max err / max|u| = {err / scale:.3e}")
+        assert err <= 1e-5 * scale
+    _, stop = mgx.decompose_adaptive(u, tol, out=torch.empty_like(u), workspace=ws)
+    _, rstop = oracle.decompose_adaptive(u64, tol)
+    _say(f"  adaptive stop level gpu {stop} oracle {rstop}")
+    assert stop == rstop
+    H = mgx.label_entropy(lab)
+    Href = oracle.label_entropy(oracle.from_level_centric(lab.cpu().numpy(), 0))
+    assert np.allclose(H, Href, rtol=1e-12, atol=1e-12)
