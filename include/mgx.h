@@ -301,8 +301,9 @@ typedef struct {
   double c_linf;             /* <= 0: library default                                       */
   int32_t *labels;           /* decompose: labels out (NULL: no quantization);
                                 recompose: labels in (NULL: recompose from in)              */
-  void *coef;                /* recompose from labels: device buffer (dims, dtype) that
-                                receives the dequantized coefficients                      */
+  void *coef;                /* recompose from labels: NULL, the level kernels read the
+                                labels; or a device buffer (dims, dtype) that receives the
+                                dequantized coefficients first                             */
 } mgx_field;
 
 typedef struct {
@@ -317,15 +318,18 @@ typedef struct {
  * invalid fields). */
 size_t mgx_batch_workspace_size(int nfields, const mgx_field *fields);
 
-/* Every field as mgx_decompose (then mgx_quantize into labels when
- * labels != NULL, without statistics).  Outputs and labels of different
- * fields must not overlap.  Errors: those of the single-field calls (the
- * first failing field decides), MGX_ERR_WORKSPACE, MGX_ERR_HIP. */
+/* Every field as mgx_decompose, with labels != NULL as
+ * mgx_decompose_quantize (labels written by the level kernels; the same
+ * labels as mgx_quantize, without statistics).  Outputs and labels of
+ * different fields must not overlap.  Errors: those of the single-field
+ * calls (the first failing field decides), MGX_ERR_WORKSPACE, MGX_ERR_HIP. */
 mgx_status mgx_decompose_batched(int nfields, const mgx_field *fields, void *workspace,
                                  size_t workspace_bytes, hipStream_t stream);
 
-/* Every field as mgx_recompose; with labels != NULL first as
- * mgx_dequantize(labels) into coef, then recomposed from coef. */
+/* Every field as mgx_recompose; with labels != NULL as
+ * mgx_dequantize_recompose: coef NULL reads the labels in the level kernels,
+ * otherwise the labels are dequantized into coef first and recomposed from
+ * it (the same results either way). */
 mgx_status mgx_recompose_batched(int nfields, const mgx_field *fields, void *workspace,
                                  size_t workspace_bytes, hipStream_t stream);
 

@@ -527,8 +527,8 @@ class Batch:
 
     fields: list of dicts with keys
       in (tensor), out (tensor), coords (per-axis list or None), stop_level,
-      tol (with labels), c_linf, labels (int32 tensor or None), coef (tensor,
-      recompose from labels).
+      tol (with labels), c_linf, labels (int32 tensor or None), coef (tensor or
+      None: recompose from labels; None reads the labels in the level kernels).
     The same Batch object (same tensors) replays the captured graph; the
     workspace is allocated once per Batch.
     """

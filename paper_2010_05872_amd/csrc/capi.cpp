@@ -293,10 +293,12 @@ mgx_status run_decompose(Plan *P, int stop, const T *u, T *umc, char *ws, const 
     em.begin_step(0);
     if (umc && copy_box<T>(u, up0, up1, umc, up0, up1, (int)P->n[0], (int)n1, (int)n2, L, em) != hipSuccess)
       return MGX_ERR_HIP;
-    if (labels && traced("quantize", -1, em.st, [&] {
-          return launch_quantize<T>(umc ? umc : u, labels, *qa, false, em.st);
-        }) != hipSuccess)
-      return MGX_ERR_HIP;
+    if (labels) {
+      OpArgs<T> o{};
+      o.qj = QuantJob<T>{u, labels, *qa};  // at stop == L, u_mc is u itself
+      em.begin_step(1);
+      if (em.op(kOpQuantize, 0, "quantize", -1, o) != hipSuccess) return MGX_ERR_HIP;
+    }
     return MGX_OK;
   }
   T *A = (T *)(ws + lay.offA), *B = (T *)(ws + lay.offB), *F = (T *)(ws + lay.offF);
@@ -355,14 +357,15 @@ mgx_status run_decompose(Plan *P, int stop, const T *u, T *umc, char *ws, const 
       o.tl.q[o.tl.nlev] = qa->q[0];
     }
     if (em.op(kOpTailDec, 0, labels ? "tail_dec+q" : "tail_dec", lay.lt, o) != hipSuccess) return MGX_ERR_HIP;
-  } else if (labels) {  // the stop box's labels
+  } else if (labels) {  // the stop box's labels, after the last level
     QuantArgs b = *qa;
     quant_box(P, b, stop);
     b.sel_lo = b.sel_hi = stop;
     b.box_compact = umc ? 0 : 1;
-    if (traced("quantize_box", -1, em.st, [&] { return launch_quantize<T>(umc ? umc : S, labels, b, false, em.st); }) !=
-        hipSuccess)
-      return MGX_ERR_HIP;
+    OpArgs<T> o{};
+    o.qj = QuantJob<T>{umc ? umc : S, labels, b};
+    em.begin_step(L - stop);
+    if (em.op(kOpQuantize, 0, "quantize_box", -1, o) != hipSuccess) return MGX_ERR_HIP;
   }
   return MGX_OK;
 }
@@ -387,8 +390,11 @@ mgx_status run_recompose(Plan *P, int stop, const T *umc, T *u, char *ws, const 
   const int64_t tp1 = tm[2], tp0 = tm[1] * tm[2];  // output pitches (level-top box)
   if (stop == top) {
     em.begin_step(0);
-    if (labels)
-      return hip_status(traced("dequantize", -1, em.st, [&] { return launch_dequantize<T>(labels, u, *qa, em.st); }));
+    if (labels) {
+      OpArgs<T> o{};
+      o.dj = DequantJob<T>{labels, u, *qa};
+      return hip_status(em.op(kOpDequantize, 0, "dequantize", -1, o));
+    }
     return hip_status(copy_box<T>(umc, up0, up1, u, tp0, tp1, (int)tm[0], (int)tm[1], (int)tm[2], top, em));
   }
   T *A = (T *)(ws + lay.offA), *B = (T *)(ws + lay.offB), *F = (T *)(ws + lay.offF);
@@ -399,8 +405,10 @@ mgx_status run_recompose(Plan *P, int stop, const T *umc, T *u, char *ws, const 
     quant_box(P, b, stop);
     b.sel_lo = b.sel_hi = stop;
     b.box_compact = 1;
-    if (traced("dequantize_box", -1, em.st, [&] { return launch_dequantize<T>(labels, S, b, em.st); }) != hipSuccess)
-      return MGX_ERR_HIP;
+    OpArgs<T> o{};
+    o.dj = DequantJob<T>{labels, S, b};
+    em.begin_step(0);
+    if (em.op(kOpDequantize, 0, "dequantize_box", -1, o) != hipSuccess) return MGX_ERR_HIP;
   }
   int first_tiled = stop + 1;
   if (lay.lt > stop) {  // levels stop+1 .. lt in one workgroup, into the level-lt box
@@ -428,7 +436,7 @@ mgx_status run_recompose(Plan *P, int stop, const T *umc, T *u, char *ws, const 
     first_tiled = lay.lt + 1;
   }
   for (int l = first_tiled; l <= top; l++) {
-    em.begin_step(l - stop - 1 + (lay.lt > stop ? 1 : 0));
+    em.begin_step(l - stop - 1 + ((lay.lt > stop || sbox) ? 1 : 0));
     AxisTab<T> ax[3] = {axis_tab(P, l, 0, tab), axis_tab(P, l, 1, tab), axis_tab(P, l, 2, tab)};
     const int c1 = ax[1].c, c2 = ax[2].c;
     const int m1 = ax[1].m, m2 = ax[2].m;
@@ -1023,8 +1031,8 @@ mgx_status batch_validate(int nfields, const mgx_field *f, bool dec, std::vector
       if (!x.out) return MGX_ERR_ARG;
       if (dec || !x.labels) {
         if (!x.in || overlaps(x.in, bytes, x.out, bytes)) return MGX_ERR_ARG;
-      } else {
-        if (!x.coef || overlaps(x.coef, bytes, x.out, bytes)) return MGX_ERR_ARG;
+      } else if (x.coef && overlaps(x.coef, bytes, x.out, bytes)) {
+        return MGX_ERR_ARG;
       }
       if (x.labels && overlaps(x.labels, (size_t)(n[0] * n[1] * n[2]) * 4, x.out, bytes)) return MGX_ERR_ARG;
     }
@@ -1053,22 +1061,24 @@ mgx_status batch_record(const mgx_field &x, const BatchField &b, char *ws, bool 
   em.rec = &ops;
   char *w = ws + b.ws_off;
   if (dec) {
-    mgx_status s = run_decompose<T>(b.P, x.stop_level, (const T *)x.in, (T *)x.out, w, b.lay, (const T *)b.tab, em);
-    if (s) return s;
-    if (x.labels) {
+    if (x.labels) {  // labels written by the level kernels
       QuantArgs qa;
       Plan *P;
-      s = quant_args(x.ndim, x.dims, x.coords, x.tol_linf, x.stop_level, x.c_linf, &qa, &P);
+      mgx_status s = quant_args(x.ndim, x.dims, x.coords, x.tol_linf, x.stop_level, x.c_linf, &qa, &P);
       if (s) return s;
-      OpArgs<T> o{};
-      o.qj = QuantJob<T>{(const T *)x.out, x.labels, qa};
-      em.base = 0;
-      em.begin_step(1 << 20);  // after every level of every field
-      if (em.op(kOpQuantize, 0, "quantize", -1, o) != hipSuccess) return MGX_ERR_HIP;
+      return run_decompose<T>(b.P, x.stop_level, (const T *)x.in, (T *)x.out, w, b.lay, (const T *)b.tab, em,
+                              x.labels, &qa);
     }
-    return MGX_OK;
+    return run_decompose<T>(b.P, x.stop_level, (const T *)x.in, (T *)x.out, w, b.lay, (const T *)b.tab, em);
   }
   const T *src = (const T *)x.in;
+  if (x.labels && !x.coef) {  // coefficients read from the labels by the level kernels
+    QuantArgs qa;
+    Plan *P;
+    mgx_status s = quant_args(x.ndim, x.dims, x.coords, x.tol_linf, x.stop_level, x.c_linf, &qa, &P);
+    if (s) return s;
+    return run_recompose<T>(b.P, x.stop_level, nullptr, (T *)x.out, w, b.lay, (const T *)b.tab, em, x.labels, &qa);
+  }
   if (x.labels) {
     QuantArgs qa;
     Plan *P;

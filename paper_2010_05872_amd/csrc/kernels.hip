@@ -2410,26 +2410,42 @@ __device__ __forceinline__ int find_op(const int *__restrict__ start, int n, int
   return lo;
 }
 
-template <typename T, int TX, int TY, int NT, bool DEC>
+template <typename T, int TX, int TY, int NT, bool DEC, bool LAB>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(DEC ? MGX_STENCIL_WAVES : MGX_REC_WAVES, 8)))
 k_load_vector_multi(MultiArgs<T> m) {
   const int g = xcd_remap(blockIdx.x, gridDim.x);
   const int f = find_op(m.start, m.n, g);
-  load_vector_body<T, TX, TY, NT, DEC, false>(m.args[f].st, g - m.start[f]);
+  load_vector_body<T, TX, TY, NT, DEC, LAB>(m.args[f].st, g - m.start[f]);
 }
 
-template <typename T, int TX, int TY, int NT>
+template <typename T, int TX, int TY, int NT, bool LAB>
 __global__ void __launch_bounds__(NT) k_interp_add_multi(MultiArgs<T> m) {
   const int g = xcd_remap(blockIdx.x, gridDim.x);
   const int f = find_op(m.start, m.n, g);
-  interp_add_body<T, TX, TY, NT, false>(m.args[f].ia, g - m.start[f]);
+  interp_add_body<T, TX, TY, NT, LAB>(m.args[f].ia, g - m.start[f]);
 }
 
-template <typename T, int TX, int TY, int NTP>
+template <typename T, int TX, int TY, int NTP, bool LAB>
 __global__ void __launch_bounds__(NTP) k_interp_plane_multi(MultiArgs<T> m) {
   const int g = xcd_remap(blockIdx.x, gridDim.x);
   const int f = find_op(m.start, m.n, g);
-  interp_plane_body<T, TX, TY, NTP, false>(m.args[f].ia, g - m.start[f]);
+  interp_plane_body<T, TX, TY, NTP, LAB>(m.args[f].ia, g - m.start[f]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_quantize_box_multi(MultiArgs<T> m) {
+  const int g = blockIdx.x;
+  const int f = find_op(m.start, m.n, g);
+  const QuantJob<T> &j = m.args[f].qj;
+  quantize_box_body<T>(j.umc, j.labels, j.a, g - m.start[f], m.start[f + 1] - m.start[f]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_dequantize_box_multi(MultiArgs<T> m) {
+  const int g = blockIdx.x;
+  const int f = find_op(m.start, m.n, g);
+  const DequantJob<T> &j = m.args[f].dj;
+  dequantize_box_body<T>(j.labels, j.umc, j.a, g - m.start[f], m.start[f + 1] - m.start[f]);
 }
 
 template <typename T, int E, int G>
@@ -2564,8 +2580,8 @@ int op_blocks(int kind, int mode, OpArgs<T> &a, const Tuning &tn) {
       return (int)(((int64_t)a.sd.nx + 255) / 256 * a.sd.nouter);
     }
     case kOpApply: return (a.sd.nx + 255) / 256;
-    case kOpQuantize: return grid_cap((a.qj.a.n + 1023) / 1024);
-    case kOpDequantize: return grid_cap((a.dj.a.n + 1023) / 1024);
+    case kOpQuantize: return grid_cap(a.qj.a.box ? (a.qj.a.bn + 255) / 256 : (a.qj.a.n + 1023) / 1024);
+    case kOpDequantize: return grid_cap(a.dj.a.box ? (a.dj.a.bn + 255) / 256 : (a.dj.a.n + 1023) / 1024);
     case kOpCopyBox: return grid_cap(((int64_t)a.cp.n0 * a.cp.n1 * a.cp.n2 + 255) / 256);
     case kOpTailDec:
     case kOpTailRec: return 1;
@@ -2577,10 +2593,12 @@ template <typename T>
 int op_key(int kind, int mode, const OpArgs<T> &a) {
   switch (kind) {
     case kOpSolveContig: return a.so.c;
-    case kOpInterpAdd: return interp_plane(a.ia) ? 1 : 0;
+    case kOpLoadVecDec: return a.st.lab_w ? 1 : 0;
+    case kOpLoadVecRec: return a.st.lab_r ? 1 : 0;
+    case kOpInterpAdd: return (interp_plane(a.ia) ? 1 : 0) | (a.ia.lab ? 2 : 0);
     case kOpSolveStrided: return (a.sd.c << 4) | (mode << 1) | (strided_deep(a.sd) ? 1 : 0);
-    case kOpQuantize: return aligned16(a.qj.umc) && aligned16(a.qj.labels);
-    case kOpDequantize: return aligned16(a.dj.umc) && aligned16(a.dj.labels);
+    case kOpQuantize: return a.qj.a.box ? 2 : (aligned16(a.qj.umc) && aligned16(a.qj.labels));
+    case kOpDequantize: return a.dj.a.box ? 2 : (aligned16(a.dj.umc) && aligned16(a.dj.labels));
     default: return 0;
   }
 }
@@ -2633,12 +2651,23 @@ hipError_t launch_op_multi(int kind, int key, const OpArgs<T> *dargs, const int 
   if (n <= 0 || total <= 0) return hipSuccess;
   MultiArgs<T> m{dargs, dstart, n};
   switch (kind) {
-    case kOpLoadVecDec: MGX_MULTI((k_load_vector_multi<T, TX, TY, NT, true>), NT); break;
-    case kOpLoadVecRec: MGX_MULTI((k_load_vector_multi<T, TX, TY, NT, false>), NT); break;
+    case kOpLoadVecDec:
+      if (key) MGX_MULTI((k_load_vector_multi<T, TX, TY, NT, true, true>), NT);
+      else MGX_MULTI((k_load_vector_multi<T, TX, TY, NT, true, false>), NT);
+      break;
+    case kOpLoadVecRec:
+      if (key) MGX_MULTI((k_load_vector_multi<T, TX, TY, NT, false, true>), NT);
+      else MGX_MULTI((k_load_vector_multi<T, TX, TY, NT, false, false>), NT);
+      break;
     case kOpInterpAdd: {
       constexpr int IX = InterpTiles<T>::TX, IY = InterpTiles<T>::TY, INT = InterpTiles<T>::NT;
-      if (key) MGX_MULTI((k_interp_plane_multi<T, IX, IY, interp_plane_threads<T>()>), interp_plane_threads<T>());
-      else MGX_MULTI((k_interp_add_multi<T, IX, IY, INT>), INT);
+      constexpr int NTP = interp_plane_threads<T>();
+      switch (key) {
+        case 0: MGX_MULTI((k_interp_add_multi<T, IX, IY, INT, false>), INT); break;
+        case 1: MGX_MULTI((k_interp_plane_multi<T, IX, IY, NTP, false>), NTP); break;
+        case 2: MGX_MULTI((k_interp_add_multi<T, IX, IY, INT, true>), INT); break;
+        default: MGX_MULTI((k_interp_plane_multi<T, IX, IY, NTP, true>), NTP); break;
+      }
       break;
     }
     case kOpApply: MGX_MULTI((k_apply_multi<T>), 256); break;
@@ -2646,11 +2675,13 @@ hipError_t launch_op_multi(int kind, int key, const OpArgs<T> *dargs, const int 
     case kOpTailDec: MGX_MULTI((k_tail_dec_multi<T>), kTailThreads); break;
     case kOpTailRec: MGX_MULTI((k_tail_rec_multi<T>), kTailThreads); break;
     case kOpQuantize:
-      if (key) MGX_MULTI((k_quantize_multi<T, true>), 256);
+      if (key == 2) MGX_MULTI((k_quantize_box_multi<T>), 256);
+      else if (key) MGX_MULTI((k_quantize_multi<T, true>), 256);
       else MGX_MULTI((k_quantize_multi<T, false>), 256);
       break;
     case kOpDequantize:
-      if (key) MGX_MULTI((k_dequantize_multi<T, true>), 256);
+      if (key == 2) MGX_MULTI((k_dequantize_box_multi<T>), 256);
+      else if (key) MGX_MULTI((k_dequantize_multi<T, true>), 256);
       else MGX_MULTI((k_dequantize_multi<T, false>), 256);
       break;
     case kOpSolveContig:

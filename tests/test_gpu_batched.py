@@ -33,6 +33,7 @@ SPECS = [
     ((1025,), torch.float64, "random", 2),
     ((65, 65, 65), torch.float64, None, 5),   # stop = L: copy only
     ((257, 33, 65), torch.float32, "tanh", 0),
+    ((65, 65, 65), torch.float32, "random", 4),  # stop box outside the single-workgroup tail
 ]
 
 
@@ -78,8 +79,10 @@ def test_batched_equals_single(autotune):
             f["u"].mul_(-0.5).add_(0.25)
         b.decompose()
         torch.cuda.synchronize()
-        for f, o in zip(F, outs):
-            assert torch.equal(o, mgx.decompose(f["u"], f["coords"], f["stop"]))
+        for f, o, lab in zip(F, outs, labels):
+            ref = mgx.decompose(f["u"], f["coords"], f["stop"])
+            assert torch.equal(o, ref)
+            assert torch.equal(lab, mgx.quantize(ref, f["tol"], f["coords"], f["stop"]))
         # recomposition from the coefficients
         recs = [torch.empty_like(f["u"]) for f in F]
         r = mgx.Batch([dict(**{"in": o}, out=rr, coords=f["coords"], stop_level=f["stop"])
@@ -100,6 +103,15 @@ def test_batched_equals_single(autotune):
             dq = mgx.dequantize(lab, f["tol"], f["u"].dtype, f["coords"], f["stop"])
             assert torch.equal(c, dq)
             assert torch.equal(rr, mgx.recompose(dq, f["coords"], f["stop"]))
+        # recomposition straight from the labels (no coef): the level kernels dequantize
+        recs3 = [torch.full_like(f["u"], float("nan")) for f in F]
+        r3 = mgx.Batch([dict(out=rr, coords=f["coords"], stop_level=f["stop"], tol=f["tol"], labels=lab)
+                        for f, lab, rr in zip(F, labels, recs3)])
+        r3.recompose()
+        torch.cuda.synchronize()
+        for f, lab, rr, want in zip(F, labels, recs3, recs2):
+            assert torch.equal(rr, want)
+            assert torch.equal(rr, mgx.dequantize_recompose(lab, f["tol"], f["u"].dtype, f["coords"], f["stop"]))
     finally:
         mgx.batch_set_autotune(True)
 
