@@ -140,28 +140,26 @@ def timed(torch, fn, reps):
 def batched_section(torch, mgx, workloads, dev, reps):
     """64 fp32 fields of uneven shapes (axes from {33,65,129,257}), k^-2..k^-4
     spectra, per-field tolerances log-uniform in [1e-4,1e-2]*range: decompose +
-    quantize, then dequantize + recompose, per field (plain) or as one batch."""
+    quantize, then dequantize + recompose (labels written and read by the level
+    kernels), per field (plain) or as one batch."""
     specs = workloads.batch_specs()
     us = [workloads.batch_field(s, device=dev) for s in specs]
     tols = [s["rel_tol"] * float((u.max() - u.min()).item()) for s, u in zip(specs, us)]
     mk = lambda: [torch.empty_like(u) for u in us]  # noqa: E731
-    outs_p, coef_p, rec_p = mk(), mk(), mk()
-    outs_b, coef_b, rec_b = mk(), mk(), mk()
+    outs_p, rec_p = mk(), mk()
+    outs_b, rec_b = mk(), mk()
     lab_p = [torch.empty(u.shape, dtype=torch.int32, device=dev) for u in us]
     lab_b = [torch.empty(u.shape, dtype=torch.int32, device=dev) for u in us]
     ws = torch.empty(max(mgx.workspace_size(mgx.MGX_F32, u.shape, 0) for u in us), dtype=torch.uint8, device=dev)
 
-    def plain():
+    def plain():  # one fused call per field and direction
         for u, o, lab, t in zip(us, outs_p, lab_p, tols):
-            mgx.decompose(u, out=o, workspace=ws)
-            mgx.quantize(o, t, out=lab)
-        for lab, c, r, t in zip(lab_p, coef_p, rec_p, tols):
-            mgx.dequantize(lab, t, torch.float32, out=c)
-            mgx.recompose(c, out=r, workspace=ws)
+            mgx.decompose_quantize(u, t, out=o, labels=lab, workspace=ws)
+        for lab, r, t in zip(lab_p, rec_p, tols):
+            mgx.dequantize_recompose(lab, t, torch.float32, out=r, workspace=ws)
 
     bd = mgx.Batch([{"in": u, "out": o, "tol": t, "labels": lab} for u, o, t, lab in zip(us, outs_b, tols, lab_b)])
-    br = mgx.Batch([{"out": r, "tol": t, "labels": lab, "coef": c}
-                    for r, t, lab, c in zip(rec_b, tols, lab_b, coef_b)])
+    br = mgx.Batch([{"out": r, "tol": t, "labels": lab} for r, t, lab in zip(rec_b, tols, lab_b)])
 
     def batched():
         bd.decompose()
