@@ -2,22 +2,25 @@
 // (arXiv 2010.05872, Sec. 2 and Sec. 5) and level-wise quantization (Sec. 4.1).
 //
 // One decomposition level l (box m0 x m1 x m2 -> coarse c0 x c1 x c2) runs as
-//   k_load_vector<DEC>  coefficient computation u - Pi_{l-1}u on N*_l, stores
-//                       of the coefficients in level-centric positions
-//                       (Sec. 5.1) and of the nodal values into a compact
-//                       coarse box, and the load vector F = (R M)^{x3} z of
-//                       the multilevel component z, all in one pass over the
-//                       level box (z-march over tiles staged in LDS);
+//   k_load_vector<DEC>  the coefficients c = V - Pi_{l-1} V on N*_l, stored at
+//                       their level-centric positions (Sec. 5.1) and / or as
+//                       quantization labels, and the load vector
+//                       F = (R M)^{x3} V, in one pass over the level box
+//                       (z-march over tiles staged in LDS);
 //   k_solve_contig      coarse mass-matrix solve along the contiguous axis
 //                       (one wavefront scan of the Thomas recurrences);
-//   k_solve_strided     solves along the strided axes, lanes across the
-//                       contiguous index, the last one fused with the
-//                       correction application.
+//   k_solve_twisted     solves along the strided axes (two-ended Thomas, one
+//                       line per lane; k_solve_strided for long lines), the
+//                       last one storing Q_{l-1} u = M_c^{-1} F.
 // Mass apply, restriction and the solve act on different tensor axes, so the
 // three load-vector stencils run first, on the fine grid, and the three
 // solves afterwards on the 8x smaller coarse grid.  Recomposition uses
-// k_load_vector<REC> on the stored coefficients, the same solves with the
-// correction subtracted, and k_interp_add.
+// k_load_vector<REC> on the stored coefficients (or labels), the same solves
+// with the correction subtracted, and k_interp_plane / k_interp_add.  Levels
+// whose boxes fit in LDS run in one workgroup (k_tail_dec / k_tail_rec).
+// Also here: the quantization passes, the adjoint's prolongation
+// (k_prolong_mass), the adaptive decomposition's estimate, the dummy-node
+// padding and the sort keys of the label entropy.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -261,7 +264,7 @@ __device__ __forceinline__ int opaque(int v) {
 // load vector of the up to three coarse planes it touches.  Rows are stored
 // de-interleaved in LDS (even columns first), so both the restriction and
 // the interpolation corners read consecutive LDS words.  Planes are fetched
-// two iterations ahead into double-buffered registers.
+// DEPTH iterations ahead into register buffers.
 template <typename T, int TX, int TY, int NT, bool DEC, bool LAB>
 __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const int lb) {
   constexpr int HR = 2 * TY + 5;  // region rows incl. halo and the extension
