@@ -24,14 +24,18 @@
 
 /* ------------------------------------------------------------------------ */
 /* Grid hierarchy (Sec. 2, Table 1).                                          */
-/* Axes are padded to three: a padded axis has one node and never coarsens.   */
+/* Axes are padded to MGO_D = 4 at the front: a padded axis has one node and  */
+/* never coarsens.  1-D to 3-D fields and the 4-D fields of Sec. 6 share the  */
+/* same code.                                                                 */
 /* ------------------------------------------------------------------------ */
+
+#define MGO_D 4
 
 typedef struct {
   int d;              /* spatial dimension (number of real axes) */
-  int64_t n[3];       /* node counts, padded axes have n = 1 */
-  int real[3];        /* 1 for a real (coarsening) axis */
-  double *X[3];       /* owned copies of the fine coordinates */
+  int64_t n[MGO_D];   /* node counts, padded axes have n = 1 */
+  int real[MGO_D];    /* 1 for a real (coarsening) axis */
+  double *X[MGO_D];   /* owned copies of the fine coordinates */
   int L;              /* finest level index */
 } grid_t;
 
@@ -46,7 +50,7 @@ static int is_dyadic_plus_one(int64_t n, int *m) {
 }
 
 static void grid_free(grid_t *g) {
-  for (int k = 0; k < 3; k++) { free(g->X[k]); g->X[k] = NULL; }
+  for (int k = 0; k < MGO_D; k++) { free(g->X[k]); g->X[k] = NULL; }
 }
 
 /* The level count: every axis halves together, and the coarsest grid N_0 has
@@ -55,11 +59,11 @@ static void grid_free(grid_t *g) {
 static int grid_init(grid_t *g, int ndim, const int64_t *dims,
                      const double *const *coords) {
   memset(g, 0, sizeof(*g));
-  if (ndim < 1 || ndim > 3 || dims == NULL) return MGO_ERR_SHAPE;
+  if (ndim < 1 || ndim > MGO_D || dims == NULL) return MGO_ERR_SHAPE;
   g->d = ndim;
   int mmin = 1 << 30;
-  for (int k = 0; k < 3; k++) {
-    int src = k - (3 - ndim);
+  for (int k = 0; k < MGO_D; k++) {
+    int src = k - (MGO_D - ndim);
     if (src < 0) { g->n[k] = 1; g->real[k] = 0; continue; }
     int m;
     if (!is_dyadic_plus_one(dims[src], &m)) return MGO_ERR_SHAPE;
@@ -68,8 +72,8 @@ static int grid_init(grid_t *g, int ndim, const int64_t *dims,
     if (m < mmin) mmin = m;
   }
   g->L = mmin - 1;
-  for (int k = 0; k < 3; k++) {
-    int src = k - (3 - ndim);
+  for (int k = 0; k < MGO_D; k++) {
+    int src = k - (MGO_D - ndim);
     g->X[k] = (double *)malloc(sizeof(double) * (size_t)g->n[k]);
     if (!g->X[k]) { grid_free(g); return MGO_ERR_ALLOC; }
     for (int64_t i = 0; i < g->n[k]; i++) {
@@ -80,6 +84,23 @@ static int grid_init(grid_t *g, int ndim, const int64_t *dims,
     }
   }
   return MGO_OK;
+}
+
+/* Advances the multi-index j through the box m[0..MGO_D-1] in C order (last
+ * axis fastest); returns 0 after the last index.  A loop over a whole box is
+ * "j = 0; do { ... } while (next_index(j, m));" (boxes are never empty). */
+static int next_index(int64_t *j, const int64_t *m) {
+  for (int k = MGO_D - 1; k >= 0; k--) {
+    if (++j[k] < m[k]) return 1;
+    j[k] = 0;
+  }
+  return 0;
+}
+
+static int64_t box_total(const int64_t *m) {
+  int64_t t = 1;
+  for (int k = 0; k < MGO_D; k++) t *= m[k];
+  return t;
 }
 
 /* Number of level-l nodes along axis k: N_l keeps every 2^(L-l)-th node. */
@@ -180,35 +201,32 @@ void mgo_project_line_1d(const double *X, int64_t m, const double *z, double *y)
 /* Correction computation (Sec. 2, step 4): the L2 projection onto V_{l-1} of */
 /* the multilevel component z, one axis after the other, the contiguous axis  */
 /* first ("row sweep, then column sweep", Sec. 5.1).                          */
-/* z has level-l shape m[0..2]; y receives the level-(l-1) shape.             */
+/* z has level-l shape m[]; y receives the level-(l-1) shape.                 */
+/* Along axis k the array is (outer, a[k], inner): outer the product of the   */
+/* axes before k, inner of the axes after it; a line is one (outer, inner).  */
 /* ------------------------------------------------------------------------ */
-static int correction_box(const int64_t m_in[3], const int real[3],
-                          double *const Xl[3], const double *z, double *y) {
-  int64_t a[3] = {m_in[0], m_in[1], m_in[2]};
-  size_t total = (size_t)(a[0] * a[1] * a[2]);
-  double *cur = (double *)malloc(sizeof(double) * total);
+static int correction_box(const int64_t *m_in, const int *real,
+                          double *const *Xl, const double *z, double *y) {
+  int64_t a[MGO_D];
+  for (int k = 0; k < MGO_D; k++) a[k] = m_in[k];
+  double *cur = (double *)malloc(sizeof(double) * (size_t)box_total(a));
   if (!cur) return MGO_ERR_ALLOC;
-  memcpy(cur, z, sizeof(double) * total);
-  for (int k = 2; k >= 0; k--) {
+  memcpy(cur, z, sizeof(double) * (size_t)box_total(a));
+  for (int k = MGO_D - 1; k >= 0; k--) {
     if (!real[k]) continue;
     int64_t mk = a[k], mc = (mk + 1) / 2;
-    int64_t b[3] = {a[0], a[1], a[2]};
-    b[k] = mc;
-    double *next = (double *)malloc(sizeof(double) * (size_t)(b[0] * b[1] * b[2]));
+    int64_t outer = 1, inner = 1;
+    for (int i = 0; i < k; i++) outer *= a[i];
+    for (int i = k + 1; i < MGO_D; i++) inner *= a[i];
+    double *next = (double *)malloc(sizeof(double) * (size_t)(outer * mc * inner));
     double *line = (double *)malloc(sizeof(double) * (size_t)mk);
     double *res = (double *)malloc(sizeof(double) * (size_t)mc);
     if (!next || !line || !res) { free(cur); free(next); free(line); free(res); return MGO_ERR_ALLOC; }
-    /* strides of the current and next arrays */
-    int64_t sa[3] = {a[1] * a[2], a[2], 1};
-    int64_t sb[3] = {b[1] * b[2], b[2], 1};
-    int o1 = (k == 0) ? 1 : 0, o2 = (k == 2) ? 1 : 2; /* the two other axes */
-    for (int64_t p = 0; p < a[o1]; p++) {
-      for (int64_t q = 0; q < a[o2]; q++) {
-        int64_t base_a = p * sa[o1] + q * sa[o2];
-        int64_t base_b = p * sb[o1] + q * sb[o2];
-        for (int64_t j = 0; j < mk; j++) line[j] = cur[base_a + j * sa[k]];
+    for (int64_t o = 0; o < outer; o++) {
+      for (int64_t i = 0; i < inner; i++) {
+        for (int64_t j = 0; j < mk; j++) line[j] = cur[(o * mk + j) * inner + i];
         mgo_project_line_1d(Xl[k], mk, line, res);
-        for (int64_t J = 0; J < mc; J++) next[base_b + J * sb[k]] = res[J];
+        for (int64_t J = 0; J < mc; J++) next[(o * mc + J) * inner + i] = res[J];
       }
     }
     free(line);
@@ -217,7 +235,7 @@ static int correction_box(const int64_t m_in[3], const int real[3],
     cur = next;
     a[k] = mc;
   }
-  memcpy(y, cur, sizeof(double) * (size_t)(a[0] * a[1] * a[2]));
+  memcpy(y, cur, sizeof(double) * (size_t)box_total(a));
   free(cur);
   return MGO_OK;
 }
@@ -227,29 +245,31 @@ int mgo_correction(const double *z, double *y, int ndim, const int64_t *dims,
   grid_t g;
   int st = grid_init(&g, ndim, dims, coords);
   if (st) return st;
-  int64_t m[3] = {g.n[0], g.n[1], g.n[2]};
-  st = correction_box(m, g.real, g.X, z, y);
+  st = correction_box(g.n, g.real, g.X, z, y);
   grid_free(&g);
   return st;
 }
 
 /* ------------------------------------------------------------------------ */
-/* Level-l view of the interleaved array: level index (j0,j1,j2) is the fine */
-/* node (j0 s, j1 s, j2 s), s = 2^(L-l).                                      */
+/* Level-l view of the interleaved array: level index (j_0, ..., j_3) is the */
+/* fine node (j_0 s, ..., j_3 s), s = 2^(L-l).                                */
 /* ------------------------------------------------------------------------ */
 typedef struct {
   double *v;
-  int64_t stride[3]; /* fine-array stride times s, per axis */
-  int64_t m[3];
-  double *Xl[3];
-  int real[3];
+  int64_t stride[MGO_D]; /* fine-array stride times s, per axis */
+  int64_t m[MGO_D];
+  double *Xl[MGO_D];
+  int real[MGO_D];
 } level_view_t;
 
 static int view_init(level_view_t *w, const grid_t *g, double *v, int l) {
   int64_t s = (int64_t)1 << (g->L - l);
-  int64_t fs[3] = {g->n[1] * g->n[2], g->n[2], 1};
+  int64_t fs[MGO_D];
+  fs[MGO_D - 1] = 1;
+  for (int k = MGO_D - 2; k >= 0; k--) fs[k] = fs[k + 1] * g->n[k + 1];
   w->v = v;
-  for (int k = 0; k < 3; k++) {
+  for (int k = 0; k < MGO_D; k++) w->Xl[k] = NULL;
+  for (int k = 0; k < MGO_D; k++) {
     w->real[k] = g->real[k];
     w->m[k] = level_size(g, k, l);
     w->stride[k] = g->real[k] ? fs[k] * s : 0;
@@ -261,25 +281,28 @@ static int view_init(level_view_t *w, const grid_t *g, double *v, int l) {
 }
 
 static void view_free(level_view_t *w) {
-  for (int k = 0; k < 3; k++) { free(w->Xl[k]); w->Xl[k] = NULL; }
+  for (int k = 0; k < MGO_D; k++) { free(w->Xl[k]); w->Xl[k] = NULL; }
 }
 
-static double *at(const level_view_t *w, int64_t j0, int64_t j1, int64_t j2) {
-  return w->v + j0 * w->stride[0] + j1 * w->stride[1] + j2 * w->stride[2];
+static double *at(const level_view_t *w, const int64_t *j) {
+  int64_t off = 0;
+  for (int k = 0; k < MGO_D; k++) off += j[k] * w->stride[k];
+  return w->v + off;
 }
 
 /* Piecewise multilinear interpolant Pi_{l-1} at the level-l node j, built
  * from the 2^(#odd axes) nodal corners (eq. of Sec. 4.2: edge, plane and cube
- * nodes use 2, 4 and 8 corners with weights 1/2, 1/4, 1/8 on uniform grids). */
-static double interpolant(const level_view_t *w, const int64_t j[3]) {
-  int odd[3];
-  for (int k = 0; k < 3; k++) odd[k] = w->real[k] && (j[k] & 1);
+ * nodes use 2, 4 and 8 corners with weights 1/2, 1/4, 1/8 on uniform grids;
+ * a node odd on all four axes of a 4-D grid uses 16). */
+static double interpolant(const level_view_t *w, const int64_t *j) {
+  int odd[MGO_D];
+  for (int k = 0; k < MGO_D; k++) odd[k] = w->real[k] && (j[k] & 1);
   double pred = 0.0;
-  for (int c = 0; c < 8; c++) {
-    int64_t q[3];
+  for (int c = 0; c < (1 << MGO_D); c++) {
+    int64_t q[MGO_D];
     double wt = 1.0;
     int skip = 0;
-    for (int k = 0; k < 3; k++) {
+    for (int k = 0; k < MGO_D; k++) {
       int bit = (c >> k) & 1;
       if (!odd[k]) {
         if (bit) { skip = 1; break; }
@@ -293,13 +316,13 @@ static double interpolant(const level_view_t *w, const int64_t j[3]) {
       }
     }
     if (skip) continue;
-    pred += wt * *at(w, q[0], q[1], q[2]);
+    pred += wt * *at(w, q);
   }
   return pred;
 }
 
-static int is_nodal(const level_view_t *w, const int64_t j[3]) {
-  for (int k = 0; k < 3; k++)
+static int is_nodal(const level_view_t *w, const int64_t *j) {
+  for (int k = 0; k < MGO_D; k++)
     if (w->real[k] && (j[k] & 1)) return 0;
   return 1;
 }
@@ -307,36 +330,41 @@ static int is_nodal(const level_view_t *w, const int64_t j[3]) {
 /* The multilevel component (I - Pi_{l-1}) Q_l u as a level-l box: the value
  * stored at coefficient nodes, zero at nodal nodes. */
 static double *component_box(const level_view_t *w) {
-  size_t total = (size_t)(w->m[0] * w->m[1] * w->m[2]);
-  double *z = (double *)malloc(sizeof(double) * total);
+  double *z = (double *)malloc(sizeof(double) * (size_t)box_total(w->m));
   if (!z) return NULL;
   size_t t = 0;
-  for (int64_t j0 = 0; j0 < w->m[0]; j0++)
-    for (int64_t j1 = 0; j1 < w->m[1]; j1++)
-      for (int64_t j2 = 0; j2 < w->m[2]; j2++, t++) {
-        int64_t j[3] = {j0, j1, j2};
-        z[t] = is_nodal(w, j) ? 0.0 : *at(w, j0, j1, j2);
-      }
+  int64_t j[MGO_D] = {0};
+  do {
+    z[t++] = is_nodal(w, j) ? 0.0 : *at(w, j);
+  } while (next_index(j, w->m));
   return z;
+}
+
+/* Level-(l-1) box size of the view. */
+static void coarse_shape(const level_view_t *w, int64_t *mc) {
+  for (int k = 0; k < MGO_D; k++) mc[k] = w->real[k] ? (w->m[k] + 1) / 2 : 1;
+}
+
+/* The level-l index of the nodal node with coarse index J. */
+static void nodal_of(const level_view_t *w, const int64_t *J, int64_t *j) {
+  for (int k = 0; k < MGO_D; k++) j[k] = w->real[k] ? 2 * J[k] : 0;
 }
 
 /* Add sign * y (level-(l-1) box) to the nodal values. */
 static void apply_correction(const level_view_t *w, const double *y, double sign) {
-  int64_t mc[3];
-  for (int k = 0; k < 3; k++) mc[k] = w->real[k] ? (w->m[k] + 1) / 2 : 1;
+  int64_t mc[MGO_D], J[MGO_D] = {0}, j[MGO_D];
+  coarse_shape(w, mc);
   size_t t = 0;
-  for (int64_t J0 = 0; J0 < mc[0]; J0++)
-    for (int64_t J1 = 0; J1 < mc[1]; J1++)
-      for (int64_t J2 = 0; J2 < mc[2]; J2++, t++) {
-        double *p = at(w, w->real[0] ? 2 * J0 : 0, w->real[1] ? 2 * J1 : 0, w->real[2] ? 2 * J2 : 0);
-        *p += sign * y[t];
-      }
+  do {
+    nodal_of(w, J, j);
+    *at(w, j) += sign * y[t++];
+  } while (next_index(J, mc));
 }
 
 static size_t coarse_total(const level_view_t *w) {
-  size_t t = 1;
-  for (int k = 0; k < 3; k++) t *= (size_t)(w->real[k] ? (w->m[k] + 1) / 2 : 1);
-  return t;
+  int64_t mc[MGO_D];
+  coarse_shape(w, mc);
+  return (size_t)box_total(mc);
 }
 
 /* One decomposition step Q_l u -> (Q_{l-1} u, coefficients on N*_l), Sec. 2
@@ -347,14 +375,15 @@ static int decompose_level(const grid_t *g, double *v, int l) {
   if (st) { view_free(&w); return st; }
   /* steps 2+3 (coefficient computation): subtract the interpolant at every
    * coefficient node; nodal corners are never modified, so order is free. */
-  for (int64_t j0 = 0; j0 < w.m[0]; j0++)
-    for (int64_t j1 = 0; j1 < w.m[1]; j1++)
-      for (int64_t j2 = 0; j2 < w.m[2]; j2++) {
-        int64_t j[3] = {j0, j1, j2};
-        if (is_nodal(&w, j)) continue;
+  {
+    int64_t j[MGO_D] = {0};
+    do {
+      if (!is_nodal(&w, j)) {
         double pred = interpolant(&w, j);
-        *at(&w, j0, j1, j2) -= pred;
+        *at(&w, j) -= pred;
       }
+    } while (next_index(j, w.m));
+  }
   /* step 4 (correction computation) */
   double *z = component_box(&w);
   double *y = (double *)malloc(sizeof(double) * coarse_total(&w));
@@ -381,14 +410,13 @@ static int recompose_level(const grid_t *g, double *v, int l) {
   if (!st) apply_correction(&w, y, -1.0);
   /* step 4: add the interpolant of the corrected nodal values */
   if (!st) {
-    for (int64_t j0 = 0; j0 < w.m[0]; j0++)
-      for (int64_t j1 = 0; j1 < w.m[1]; j1++)
-        for (int64_t j2 = 0; j2 < w.m[2]; j2++) {
-          int64_t j[3] = {j0, j1, j2};
-          if (is_nodal(&w, j)) continue;
-          double pred = interpolant(&w, j);
-          *at(&w, j0, j1, j2) += pred;
-        }
+    int64_t j[MGO_D] = {0};
+    do {
+      if (!is_nodal(&w, j)) {
+        double pred = interpolant(&w, j);
+        *at(&w, j) += pred;
+      }
+    } while (next_index(j, w.m));
   }
   free(z);
   free(y);
@@ -432,34 +460,30 @@ void mgo_project_line_adjoint_1d(const double *X, int64_t m, const double *y, do
 }
 
 /* C^T: coarse box y (shape of the level-(l-1) grid) -> level-l box out.
- * The forward projection runs axes 2, 1, 0; its transpose runs 0, 1, 2. */
-static int correction_box_adjoint(const int64_t m_out[3], const int real[3],
-                                  double *const Xl[3], const double *y, double *out) {
-  int64_t a[3];
-  for (int k = 0; k < 3; k++) a[k] = real[k] ? (m_out[k] + 1) / 2 : m_out[k];
-  size_t total = (size_t)(a[0] * a[1] * a[2]);
-  double *cur = (double *)malloc(sizeof(double) * total);
+ * The forward projection runs the axes from the last to the first; its
+ * transpose runs them from the first to the last. */
+static int correction_box_adjoint(const int64_t *m_out, const int *real,
+                                  double *const *Xl, const double *y, double *out) {
+  int64_t a[MGO_D];
+  for (int k = 0; k < MGO_D; k++) a[k] = real[k] ? (m_out[k] + 1) / 2 : m_out[k];
+  double *cur = (double *)malloc(sizeof(double) * (size_t)box_total(a));
   if (!cur) return MGO_ERR_ALLOC;
-  memcpy(cur, y, sizeof(double) * total);
-  for (int k = 0; k < 3; k++) {
+  memcpy(cur, y, sizeof(double) * (size_t)box_total(a));
+  for (int k = 0; k < MGO_D; k++) {
     if (!real[k]) continue;
     int64_t mc = a[k], mk = m_out[k];
-    int64_t b[3] = {a[0], a[1], a[2]};
-    b[k] = mk;
-    double *next = (double *)malloc(sizeof(double) * (size_t)(b[0] * b[1] * b[2]));
+    int64_t outer = 1, inner = 1;
+    for (int i = 0; i < k; i++) outer *= a[i];
+    for (int i = k + 1; i < MGO_D; i++) inner *= a[i];
+    double *next = (double *)malloc(sizeof(double) * (size_t)(outer * mk * inner));
     double *line = (double *)malloc(sizeof(double) * (size_t)mc);
     double *res = (double *)malloc(sizeof(double) * (size_t)mk);
     if (!next || !line || !res) { free(cur); free(next); free(line); free(res); return MGO_ERR_ALLOC; }
-    int64_t sa[3] = {a[1] * a[2], a[2], 1};
-    int64_t sb[3] = {b[1] * b[2], b[2], 1};
-    int o1 = (k == 0) ? 1 : 0, o2 = (k == 2) ? 1 : 2;
-    for (int64_t p = 0; p < a[o1]; p++) {
-      for (int64_t q = 0; q < a[o2]; q++) {
-        int64_t base_a = p * sa[o1] + q * sa[o2];
-        int64_t base_b = p * sb[o1] + q * sb[o2];
-        for (int64_t J = 0; J < mc; J++) line[J] = cur[base_a + J * sa[k]];
+    for (int64_t o = 0; o < outer; o++) {
+      for (int64_t i = 0; i < inner; i++) {
+        for (int64_t J = 0; J < mc; J++) line[J] = cur[(o * mc + J) * inner + i];
         mgo_project_line_adjoint_1d(Xl[k], mk, line, res);
-        for (int64_t j = 0; j < mk; j++) next[base_b + j * sb[k]] = res[j];
+        for (int64_t j = 0; j < mk; j++) next[(o * mk + j) * inner + i] = res[j];
       }
     }
     free(line);
@@ -468,7 +492,7 @@ static int correction_box_adjoint(const int64_t m_out[3], const int real[3],
     cur = next;
     a[k] = mk;
   }
-  memcpy(out, cur, sizeof(double) * (size_t)(a[0] * a[1] * a[2]));
+  memcpy(out, cur, sizeof(double) * (size_t)box_total(a));
   free(cur);
   return MGO_OK;
 }
@@ -476,57 +500,54 @@ static int correction_box_adjoint(const int64_t m_out[3], const int real[3],
 /* sign * E^T: every coefficient node x sends weight * g(x) to each nodal
  * corner of its interpolant (the corner weights of interpolant()). */
 static void scatter_interpolant_transpose(const level_view_t *w, double sign) {
-  for (int64_t j0 = 0; j0 < w->m[0]; j0++)
-    for (int64_t j1 = 0; j1 < w->m[1]; j1++)
-      for (int64_t j2 = 0; j2 < w->m[2]; j2++) {
-        int64_t j[3] = {j0, j1, j2};
-        if (is_nodal(w, j)) continue;
-        double gx = *at(w, j0, j1, j2);
-        int odd[3];
-        for (int k = 0; k < 3; k++) odd[k] = w->real[k] && (j[k] & 1);
-        for (int c = 0; c < 8; c++) {
-          int64_t q[3];
-          double wt = 1.0;
-          int skip = 0;
-          for (int k = 0; k < 3; k++) {
-            int bit = (c >> k) & 1;
-            if (!odd[k]) {
-              if (bit) { skip = 1; break; }
-              q[k] = j[k];
-            } else if (bit == 0) {
-              q[k] = j[k] - 1;
-              wt *= w_left(w->Xl[k], j[k]);
-            } else {
-              q[k] = j[k] + 1;
-              wt *= w_right(w->Xl[k], j[k]);
-            }
-          }
-          if (skip) continue;
-          *at(w, q[0], q[1], q[2]) += sign * wt * gx;
+  int64_t j[MGO_D] = {0};
+  do {
+    if (is_nodal(w, j)) continue;
+    double gx = *at(w, j);
+    int odd[MGO_D];
+    for (int k = 0; k < MGO_D; k++) odd[k] = w->real[k] && (j[k] & 1);
+    for (int c = 0; c < (1 << MGO_D); c++) {
+      int64_t q[MGO_D];
+      double wt = 1.0;
+      int skip = 0;
+      for (int k = 0; k < MGO_D; k++) {
+        int bit = (c >> k) & 1;
+        if (!odd[k]) {
+          if (bit) { skip = 1; break; }
+          q[k] = j[k];
+        } else if (bit == 0) {
+          q[k] = j[k] - 1;
+          wt *= w_left(w->Xl[k], j[k]);
+        } else {
+          q[k] = j[k] + 1;
+          wt *= w_right(w->Xl[k], j[k]);
         }
       }
+      if (skip) continue;
+      *at(w, q) += sign * wt * gx;
+    }
+  } while (next_index(j, w->m));
 }
 
 /* Nodal values of the level-l view as a coarse box (the operator S). */
 static void gather_nodal(const level_view_t *w, double *y) {
-  int64_t mc[3];
-  for (int k = 0; k < 3; k++) mc[k] = w->real[k] ? (w->m[k] + 1) / 2 : 1;
+  int64_t mc[MGO_D], J[MGO_D] = {0}, j[MGO_D];
+  coarse_shape(w, mc);
   size_t t = 0;
-  for (int64_t J0 = 0; J0 < mc[0]; J0++)
-    for (int64_t J1 = 0; J1 < mc[1]; J1++)
-      for (int64_t J2 = 0; J2 < mc[2]; J2++, t++)
-        y[t] = *at(w, w->real[0] ? 2 * J0 : 0, w->real[1] ? 2 * J1 : 0, w->real[2] ? 2 * J2 : 0);
+  do {
+    nodal_of(w, J, j);
+    y[t++] = *at(w, j);
+  } while (next_index(J, mc));
 }
 
 /* g(x) += sign * t(x) at the coefficient nodes (the operator Z^T). */
 static void add_at_coefficients(const level_view_t *w, const double *t, double sign) {
   size_t i = 0;
-  for (int64_t j0 = 0; j0 < w->m[0]; j0++)
-    for (int64_t j1 = 0; j1 < w->m[1]; j1++)
-      for (int64_t j2 = 0; j2 < w->m[2]; j2++, i++) {
-        int64_t j[3] = {j0, j1, j2};
-        if (!is_nodal(w, j)) *at(w, j0, j1, j2) += sign * t[i];
-      }
+  int64_t j[MGO_D] = {0};
+  do {
+    if (!is_nodal(w, j)) *at(w, j) += sign * t[i];
+    i++;
+  } while (next_index(j, w->m));
 }
 
 /* D_l^T = (I - E^T)(I + Z C^T S), applied in place to the level-l view. */
@@ -535,7 +556,7 @@ static int decompose_level_adjoint(const grid_t *g, double *v, int l) {
   int st = view_init(&w, g, v, l);
   if (st) { view_free(&w); return st; }
   double *y = (double *)malloc(sizeof(double) * coarse_total(&w));
-  double *t = (double *)malloc(sizeof(double) * (size_t)(w.m[0] * w.m[1] * w.m[2]));
+  double *t = (double *)malloc(sizeof(double) * (size_t)box_total(w.m));
   if (!y || !t) { free(y); free(t); view_free(&w); return MGO_ERR_ALLOC; }
   gather_nodal(&w, y);
   st = correction_box_adjoint(w.m, w.real, w.Xl, y, t);
@@ -555,7 +576,7 @@ static int recompose_level_adjoint(const grid_t *g, double *v, int l) {
   int st = view_init(&w, g, v, l);
   if (st) { view_free(&w); return st; }
   double *y = (double *)malloc(sizeof(double) * coarse_total(&w));
-  double *t = (double *)malloc(sizeof(double) * (size_t)(w.m[0] * w.m[1] * w.m[2]));
+  double *t = (double *)malloc(sizeof(double) * (size_t)box_total(w.m));
   if (!y || !t) { free(y); free(t); view_free(&w); return MGO_ERR_ALLOC; }
   scatter_interpolant_transpose(&w, +1.0);
   gather_nodal(&w, y);
@@ -657,25 +678,28 @@ int mgo_adaptive_estimate(const double *v, int ndim, const int64_t *dims, const 
   double sl = 0.0, si = 0.0;
   int64_t cnt[3] = {0, 0, 0};
   int64_t cells[3];
-  for (int k = 0; k < 3; k++) cells[k] = (w.m[k] - 1) / 2;
+  /* the three real axes of a 3-D field are axes 1..3 of the padded grid */
+#define U3(a, b, c) (*at(&w, (const int64_t[MGO_D]){0, (a), (b), (c)}))
+  for (int k = 0; k < 3; k++) cells[k] = (w.m[k + 1] - 1) / 2;
   for (int64_t a0 = 1; a0 < cells[0]; a0 += 4)
     for (int64_t a1 = 1; a1 < cells[1]; a1 += 4)
       for (int64_t a2 = 1; a2 < cells[2]; a2 += 4)
         for (int r0 = 0; r0 < 3; r0++)
           for (int r1 = 0; r1 < 3; r1++)
             for (int r2 = 0; r2 < 3; r2++) {
-              int64_t j[3] = {2 * a0 + r0, 2 * a1 + r1, 2 * a2 + r2};
+              int64_t j[MGO_D] = {0, 2 * a0 + r0, 2 * a1 + r1, 2 * a2 + r2};
               int nodd = (r0 == 1) + (r1 == 1) + (r2 == 1);
               if (nodd == 0) continue;
-              double x = *at(&w, j[0], j[1], j[2]);
-              double lor = *at(&w, j[0], j[1] - 1, j[2]) + *at(&w, j[0] - 1, j[1], j[2]) +
-                           *at(&w, j[0], j[1], j[2] - 1) - *at(&w, j[0] - 1, j[1] - 1, j[2]) -
-                           *at(&w, j[0], j[1] - 1, j[2] - 1) - *at(&w, j[0] - 1, j[1], j[2] - 1) +
-                           *at(&w, j[0] - 1, j[1] - 1, j[2] - 1);
+              int64_t x0 = j[1], x1 = j[2], x2 = j[3];
+              double x = U3(x0, x1, x2);
+              double lor = U3(x0, x1 - 1, x2) + U3(x0 - 1, x1, x2) + U3(x0, x1, x2 - 1) -
+                           U3(x0 - 1, x1 - 1, x2) - U3(x0, x1 - 1, x2 - 1) - U3(x0 - 1, x1, x2 - 1) +
+                           U3(x0 - 1, x1 - 1, x2 - 1);
               sl += fabs(x - lor);
               si += fabs(x - interpolant(&w, j));
               cnt[nodd - 1]++;
             }
+#undef U3
   view_free(&w);
   grid_free(&g);
   *s_lorenzo = sl;
@@ -767,18 +791,16 @@ int mgo_level_map(int8_t *lev, int ndim, const int64_t *dims, int stop_level) {
   if (st) return st;
   if (stop_level < 0 || stop_level > g.L) { grid_free(&g); return MGO_ERR_LEVEL; }
   size_t t = 0;
-  for (int64_t i0 = 0; i0 < g.n[0]; i0++)
-    for (int64_t i1 = 0; i1 < g.n[1]; i1++)
-      for (int64_t i2 = 0; i2 < g.n[2]; i2++, t++) {
-        int64_t i[3] = {i0, i1, i2};
-        int lv = stop_level;
-        for (int k = 0; k < 3; k++) {
-          if (!g.real[k]) continue;
-          int a = axis_level(i[k], g.L, stop_level);
-          if (a > lv) lv = a;
-        }
-        lev[t] = (int8_t)lv;
-      }
+  int64_t i[MGO_D] = {0};
+  do {
+    int lv = stop_level;
+    for (int k = 0; k < MGO_D; k++) {
+      if (!g.real[k]) continue;
+      int a = axis_level(i[k], g.L, stop_level);
+      if (a > lv) lv = a;
+    }
+    lev[t++] = (int8_t)lv;
+  } while (next_index(i, g.n));
   grid_free(&g);
   return MGO_OK;
 }
@@ -798,29 +820,29 @@ int mgo_level_centric_index(int64_t *pos, int ndim, const int64_t *dims, int sto
   if (st) return st;
   if (stop_level < 0 || stop_level > g.L) { grid_free(&g); return MGO_ERR_LEVEL; }
   size_t t = 0;
-  for (int64_t i0 = 0; i0 < g.n[0]; i0++)
-    for (int64_t i1 = 0; i1 < g.n[1]; i1++)
-      for (int64_t i2 = 0; i2 < g.n[2]; i2++, t++) {
-        int64_t i[3] = {i0, i1, i2};
-        int lv = stop_level;
-        for (int k = 0; k < 3; k++)
-          if (g.real[k]) {
-            int a = axis_level(i[k], g.L, stop_level);
-            if (a > lv) lv = a;
-          }
-        int64_t s = (int64_t)1 << (g.L - lv);
-        int64_t p[3];
-        for (int k = 0; k < 3; k++) {
-          int64_t j = i[k] / s; /* level-lv index (the node is in N_lv) */
-          if (lv == stop_level) {
-            p[k] = j;
-          } else {
-            int64_t c = level_size(&g, k, lv - 1);
-            p[k] = (j & 1) ? c + (j - 1) / 2 : j / 2;
-          }
-        }
-        pos[t] = (p[0] * g.n[1] + p[1]) * g.n[2] + p[2];
+  int64_t i[MGO_D] = {0};
+  do {
+    int lv = stop_level;
+    for (int k = 0; k < MGO_D; k++)
+      if (g.real[k]) {
+        int a = axis_level(i[k], g.L, stop_level);
+        if (a > lv) lv = a;
       }
+    int64_t s = (int64_t)1 << (g.L - lv);
+    int64_t off = 0;
+    for (int k = 0; k < MGO_D; k++) {
+      int64_t j = i[k] / s; /* level-lv index (the node is in N_lv) */
+      int64_t p;
+      if (lv == stop_level) {
+        p = j;
+      } else {
+        int64_t c = level_size(&g, k, lv - 1);
+        p = (j & 1) ? c + (j - 1) / 2 : j / 2;
+      }
+      off = off * g.n[k] + p;
+    }
+    pos[t++] = off;
+  } while (next_index(i, g.n));
   grid_free(&g);
   return MGO_OK;
 }
@@ -866,7 +888,7 @@ double mgo_linf_constant(int ndim, const int64_t *dims, const double *const *coo
   double C = 1.0;
   for (int l = g.L; l > stop_level; l--) {
     double prod = 1.0;
-    for (int k = 0; k < 3; k++) {
+    for (int k = 0; k < MGO_D; k++) {
       if (!g.real[k]) continue;
       int64_t m = level_size(&g, k, l);
       double *Xl = (double *)malloc(sizeof(double) * (size_t)m);

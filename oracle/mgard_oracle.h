@@ -22,7 +22,7 @@ extern "C" {
 
 enum {
   MGO_OK = 0,
-  MGO_ERR_SHAPE = 2,   /* ndim not in [1,3] or some n_k not 2^m+1, m >= 1 */
+  MGO_ERR_SHAPE = 2,   /* ndim not in [1,4] or some n_k not 2^m+1, m >= 1 */
   MGO_ERR_COORDS = 3,  /* non-finite or non-increasing coordinates */
   MGO_ERR_LEVEL = 4,   /* stop level outside [0, L] */
   MGO_ERR_TOL = 5,     /* tolerance not positive and finite, or C < 1 */
