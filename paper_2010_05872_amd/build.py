@@ -21,6 +21,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE,
           "-Wall", "-Wno-unused-result"]
 SOURCES = [
     ("kernels.hip", DEVICE_FLAGS),
+    ("kernels4.hip", DEVICE_FLAGS),
     ("entropy.hip", DEVICE_FLAGS),
     # host code: FP64 tolerance arithmetic in source order, no contraction
     ("plan.cpp", ["-ffp-contract=off"]),

@@ -9,11 +9,13 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <unordered_map>
 #include <vector>
 
 #include "entropy.hpp"
 #include "kernels.hpp"
+#include "kernels4.hpp"
 #include "mgx.h"
 #include "plan.hpp"
 
@@ -779,12 +781,10 @@ mgx_status prepare(const void *in, void *out, mgx_dtype dtype, int ndim, const i
 
 // Level tolerances of Sec. 4.1, eq. (LinfTau) with the stop level of
 // Algorithm 1, in a fixed FP64 operation order.
-mgx_status tolerances(Plan *P, int ndim, double tol, int stop, double c_linf, double *tau) {
+// C: the L-infinity constant (c_linf when given, else the plan's default).
+mgx_status tau_schedule(double C, int L, int ndim, double tol, int stop, double *tau) {
   if (!(tol > 0.0) || !std::isfinite(tol)) return MGX_ERR_TOL;
-  if (std::isnan(c_linf) || std::isinf(c_linf)) return MGX_ERR_TOL;
-  double C = c_linf > 0.0 ? c_linf : P->linf_constant(stop);
-  if (!(C >= 1.0)) return MGX_ERR_TOL;
-  const int L = P->L;
+  if (!(C >= 1.0) || !std::isfinite(C)) return MGX_ERR_TOL;
   volatile double kappa = std::sqrt((double)(1 << ndim));
   double p = 1.0;
   for (int i = 0; i < L + 1 - stop; i++) p = p * kappa;
@@ -792,6 +792,12 @@ mgx_status tolerances(Plan *P, int ndim, double tol, int stop, double c_linf, do
   tau[0] = t;
   for (int l = 1; l <= L - stop; l++) tau[l] = tau[l - 1] * kappa;
   return MGX_OK;
+}
+
+mgx_status tolerances(Plan *P, int ndim, double tol, int stop, double c_linf, double *tau) {
+  if (std::isnan(c_linf) || std::isinf(c_linf)) return MGX_ERR_TOL;
+  if (!(tol > 0.0) || !std::isfinite(tol)) return MGX_ERR_TOL;
+  return tau_schedule(c_linf > 0.0 ? c_linf : P->linf_constant(stop), P->L, ndim, tol, stop, tau);
 }
 
 // tau_in (optional): the tolerances of levels stop .. L given by the caller
@@ -1339,6 +1345,388 @@ mgx_status run_batched(int nfields, const mgx_field *f, void *ws, size_t ws_byte
   return hip_status(le);
 }
 
+// ---- four-axis fields (the 4-D QMCPACK field of Sec. 6, Table 2) ----
+// A 4-D plan is four 1-D plans, one per axis.  Level l of the 4-D hierarchy
+// (L = min_k L_k, every axis halving together) is level l + off_k of axis k's
+// own hierarchy, off_k = L_k - L.
+struct Plan4 {
+  Plan *ax[4] = {};
+  int off[4] = {};
+  int64_t n[4] = {};
+  int L = 0;
+  int64_t m(int l, int k) const { return (n[k] - 1) / ((int64_t)1 << (L - l)) + 1; }
+  int64_t count(int l) const { return m(l, 0) * m(l, 1) * m(l, 2) * m(l, 3); }
+  // 1 + prod_k ||Mc^-1 R M||_inf, maximised over the levels above stop
+  double linf_constant(int stop) const {
+    double C = 1.0;
+    for (int l = L; l > stop; l--) {
+      double prod = 1.0;
+      for (int k = 0; k < 4; k++) prod *= ax[k]->axis_norm[l + off[k]][2];
+      if (1.0 + prod > C) C = 1.0 + prod;
+    }
+    return C;
+  }
+};
+
+// Shape of a 4-D field: every dim 2^m + 1 (1 <= m <= 13), fewer than 2^32 nodes.
+int parse_shape4(const int64_t *dims, int *L) {
+  if (!dims) return MGX_ERR_SHAPE;
+  int Lmin = 1 << 30;
+  int64_t total = 1;
+  for (int k = 0; k < 4; k++) {
+    int64_t n[3];
+    bool real[3];
+    int Lk;
+    if (parse_shape(1, &dims[k], n, real, &Lk)) return MGX_ERR_SHAPE;
+    Lmin = std::min(Lmin, Lk);
+    total *= dims[k];
+  }
+  if (total >= ((int64_t)1 << 32)) return MGX_ERR_SHAPE;  // flat 32-bit indexing
+  *L = Lmin;
+  return MGX_OK;
+}
+
+mgx_status get_plan4(const int64_t *dims, const double *const *coords, Plan4 *p) {
+  int L;
+  int st = parse_shape4(dims, &L);
+  if (st) return (mgx_status)st;
+  p->L = L;
+  for (int k = 0; k < 4; k++) {
+    const double *ck = coords ? coords[k] : nullptr;
+    p->ax[k] = get_plan(1, &dims[k], ck ? &ck : nullptr, &st);
+    if (!p->ax[k]) return (mgx_status)st;
+    p->off[k] = p->ax[k]->L - L;
+    p->n[k] = dims[k];
+  }
+  return MGX_OK;
+}
+
+// Workspace: the first two sweeps' outputs (A, B; later sweeps and the load
+// vector reuse them) and two compact level-(L-1) boxes (C, D).
+struct Layout4 {
+  size_t offA = 0, offB = 0, offC = 0, offD = 0, total = 0;
+};
+Layout4 layout4(const int64_t n[4], int L, int stop, size_t es) {
+  Layout4 w;
+  if (stop >= L) return w;
+  int64_t c[4];
+  for (int k = 0; k < 4; k++) c[k] = (n[k] - 1) / 2 + 1;
+  const int64_t a = n[0] * n[1] * n[2] * c[3], b = n[0] * n[1] * c[2] * c[3], cc = c[0] * c[1] * c[2] * c[3];
+  size_t off = 0;
+  w.offA = off;
+  off = align_up(off + (size_t)a * es, 256);
+  w.offB = off;
+  off = align_up(off + (size_t)b * es, 256);
+  w.offC = off;
+  off = align_up(off + (size_t)cc * es, 256);
+  w.offD = off;
+  off = align_up(off + (size_t)cc * es, 256);
+  w.total = off;
+  return w;
+}
+
+template <typename T>
+struct Level4 {
+  AxisTab<T> ax[4];
+  int64_t m[4], c[4];
+};
+
+template <typename T>
+mgx_status level4_tabs(const Plan4 &P, int l, bool fp64, Level4<T> *lv) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MGX_ERR_HIP;
+  for (int k = 0; k < 4; k++) {
+    int herr = 0;
+    const T *tab = (const T *)P.ax[k]->device_tables(dev, fp64, &herr);
+    if (!tab) return MGX_ERR_HIP;
+    lv->ax[k] = axis_tab(P.ax[k], l + P.off[k], 2, tab);
+    lv->m[k] = lv->ax[k].m;
+    lv->c[k] = lv->ax[k].c;
+  }
+  return MGX_OK;
+}
+
+template <typename T>
+Axis4<T> axis4(const AxisTab<T> &t) {
+  return Axis4<T>{t.wl, t.wr, t.w5, t.m, t.c};
+}
+
+// One sweep of R M along axis k of (outer, m_k, inner) -> (outer, c_k, inner).
+template <typename T>
+hipError_t sweep4(const AxisTab<T> &t, const T *in, T *out, int64_t outer, int64_t inner, int level,
+                  hipStream_t st) {
+  Sweep4Args<T> a{};
+  a.w5 = t.w5;
+  a.m = t.m;
+  a.c = t.c;
+  a.in = in;
+  a.out = out;
+  a.n = (uint32_t)(outer * t.c * inner);
+  a.inner = (uint32_t)inner;
+  a.dinner = make_div32((uint32_t)inner);
+  a.dc = make_div32((uint32_t)t.c);
+  return traced("sweep4", level, st, [&] { return launch_sweep4<T>(a, false, st); });
+}
+
+// Thomas solves of the coarse box (c0, c1, c2, c3) in place, axis 3 first;
+// the axis-0 solve applies out = in - y when `in` is given (recomposition).
+template <typename T>
+hipError_t solves4(const Level4<T> &lv, T *F, const T *in, T *out, int level, hipStream_t st) {
+  const int64_t c0 = lv.c[0], c1 = lv.c[1], c2 = lv.c[2], c3 = lv.c[3];
+  hipError_t e;
+  {
+    SolveArgs<T> a{F, c0 * c1 * c2, c3, (int)c3, lv.ax[3].mult, lv.ax[3].invd, lv.ax[3].qsup};
+    if ((e = traced("solve_contig", level, st, [&] { return launch_solve_contig<T>(a, st); })) != hipSuccess)
+      return e;
+  }
+  // axis k: lines of stride sj, x over the contiguous run of the later axes,
+  // `nouter` runs of stride so
+  auto strided = [&](int k, int64_t sj, int64_t nouter, int mode) {
+    StridedArgs<T> a{};
+    a.F = F;
+    a.c = (int)lv.c[k];
+    a.sj = sj;
+    a.nx = (int)sj;
+    a.so = sj * lv.c[k];
+    a.nouter = (int)nouter;
+    const AxisTab<T> &t = lv.ax[k];
+    a.mult = t.mult;
+    a.invd = t.invd;
+    a.qsup = t.qsup;
+    a.multb = t.multb;
+    a.invdb = t.invdb;
+    a.qsub = t.qsub;
+    a.mid = t.mid;
+    if (mode == kSolveApply) {
+      a.in = in;
+      a.ij = sj;
+      a.io = sj * lv.c[k];
+      a.out = out;
+      a.oj = sj;
+      a.oo = sj * lv.c[k];
+      a.sign = T(-1);
+    }
+    // long lines take a (runs x 256-column) grid whose second dimension is limited
+    const bool twisted = a.c <= (sizeof(T) == 4 ? 257 : 129);
+    if (!twisted && nouter > 65535) return hipErrorInvalidValue;
+    return traced(mode == kSolveApply ? "solve_strided_apply" : "solve_strided", level, st,
+                  [&] { return launch_solve_strided<T>(a, mode, st); });
+  };
+  if ((e = strided(2, c3, c0 * c1, kSolveInPlace)) != hipSuccess) return e;
+  if ((e = strided(1, c2 * c3, c0, kSolveInPlace)) != hipSuccess) return e;
+  return strided(0, c1 * c2 * c3, 1, in ? kSolveApply : kSolveInPlace);
+}
+
+template <typename T>
+hipError_t copy4(const T *src, const int64_t sp[3], T *dst, const int64_t dp[3], const int64_t b[4], int level,
+                 hipStream_t st) {
+  Copy4Args<T> a{};
+  a.src = src;
+  a.dst = dst;
+  for (int k = 0; k < 3; k++) {
+    a.sp[k] = sp[k];
+    a.dp[k] = dp[k];
+  }
+  for (int k = 0; k < 4; k++) a.b[k] = (int)b[k];
+  a.n = (uint32_t)(b[0] * b[1] * b[2] * b[3]);
+  a.d3 = make_div32((uint32_t)b[3]);
+  a.d2 = make_div32((uint32_t)b[2]);
+  a.d1 = make_div32((uint32_t)b[1]);
+  return traced("copy4", level, st, [&] { return launch_copy4<T>(a, st); });
+}
+
+void compact_pitches(const int64_t b[4], int64_t p[3]) {
+  p[2] = b[3];
+  p[1] = b[2] * b[3];
+  p[0] = b[1] * b[2] * b[3];
+}
+
+// Decomposition of a 4-D field, levels L .. stop+1 (Sec. 2): per level the
+// coefficients, the four load-vector sweeps and the four solves, whose result
+// Q_{l-1} u = Mc^{-1} (R M)^{x4} V is the next level's box.
+template <typename T>
+mgx_status run_decompose4(const Plan4 &P, int stop, const T *u, T *umc, char *ws, const Layout4 &lay,
+                          hipStream_t st) {
+  const int L = P.L;
+  const int64_t N = P.count(L);
+  if (stop == L) return hip_status(hipMemcpyAsync(umc, u, sizeof(T) * N, hipMemcpyDeviceToDevice, st));
+  int64_t up[3];
+  compact_pitches(P.n, up);
+  T *A = (T *)(ws + lay.offA), *B = (T *)(ws + lay.offB);
+  const T *V = u;
+  for (int l = L; l > stop; l--) {
+    Level4<T> lv;
+    mgx_status s = level4_tabs<T>(P, l, sizeof(T) == 8, &lv);
+    if (s) return s;
+    const int64_t *m = lv.m, *c = lv.c;
+    Coef4Args<T> ca{};
+    for (int k = 0; k < 4; k++) ca.ax[k] = axis4(lv.ax[k]);
+    ca.V = V;
+    ca.umc_w = umc;
+    for (int k = 0; k < 3; k++) ca.up[k] = up[k];
+    ca.n = (uint32_t)(m[0] * m[1] * m[2] * m[3]);
+    ca.d3 = make_div32((uint32_t)m[3]);
+    ca.d2 = make_div32((uint32_t)m[2]);
+    ca.d1 = make_div32((uint32_t)m[1]);
+    if (traced("coef4_dec", l, st, [&] { return launch_coef4<T>(ca, true, st); }) != hipSuccess) return MGX_ERR_HIP;
+    if (sweep4<T>(lv.ax[3], V, A, m[0] * m[1] * m[2], 1, l, st) != hipSuccess ||
+        sweep4<T>(lv.ax[2], A, B, m[0] * m[1], c[3], l, st) != hipSuccess ||
+        sweep4<T>(lv.ax[1], B, A, m[0], c[2] * c[3], l, st) != hipSuccess ||
+        sweep4<T>(lv.ax[0], A, B, 1, c[1] * c[2] * c[3], l, st) != hipSuccess)
+      return MGX_ERR_HIP;
+    if (solves4<T>(lv, B, nullptr, nullptr, l, st) != hipSuccess) return MGX_ERR_HIP;
+    V = B;
+  }
+  int64_t b[4], bp[3];
+  for (int k = 0; k < 4; k++) b[k] = P.m(stop, k);
+  compact_pitches(b, bp);
+  return copy4<T>(B, bp, umc, up, b, stop, st) != hipSuccess ? MGX_ERR_HIP : MGX_OK;
+}
+
+// Recomposition, levels stop+1 .. L: the load vector of the level's
+// coefficients (read from u_mc), the solves subtracting the correction from
+// the nodal values, then coefficients plus interpolant.
+template <typename T>
+mgx_status run_recompose4(const Plan4 &P, int stop, const T *umc, T *u, char *ws, const Layout4 &lay,
+                          hipStream_t st) {
+  const int L = P.L;
+  const int64_t N = P.count(L);
+  if (stop == L) return hip_status(hipMemcpyAsync(u, umc, sizeof(T) * N, hipMemcpyDeviceToDevice, st));
+  int64_t up[3];
+  compact_pitches(P.n, up);
+  T *A = (T *)(ws + lay.offA), *B = (T *)(ws + lay.offB), *C = (T *)(ws + lay.offC), *D = (T *)(ws + lay.offD);
+  {
+    int64_t b[4], bp[3];
+    for (int k = 0; k < 4; k++) b[k] = P.m(stop, k);
+    compact_pitches(b, bp);
+    if (copy4<T>(umc, up, D, bp, b, stop, st) != hipSuccess) return MGX_ERR_HIP;
+  }
+  for (int l = stop + 1; l <= L; l++) {
+    Level4<T> lv;
+    mgx_status s = level4_tabs<T>(P, l, sizeof(T) == 8, &lv);
+    if (s) return s;
+    const int64_t *m = lv.m, *c = lv.c;
+    Sweep4Args<T> g{};
+    g.w5 = lv.ax[3].w5;
+    g.m = (int)m[3];
+    g.c = (int)c[3];
+    g.out = A;
+    g.n = (uint32_t)(m[0] * m[1] * m[2] * c[3]);
+    g.inner = 1;
+    g.dinner = make_div32(1);
+    g.dc = make_div32((uint32_t)c[3]);
+    g.umc = umc;
+    for (int k = 0; k < 3; k++) g.up[k] = up[k];
+    g.m1 = (int)m[1];
+    g.m2 = (int)m[2];
+    for (int k = 0; k < 4; k++) g.cc[k] = (int)c[k];
+    g.dm2 = make_div32((uint32_t)m[2]);
+    g.dm1 = make_div32((uint32_t)m[1]);
+    if (traced("sweep4_gather", l, st, [&] { return launch_sweep4<T>(g, true, st); }) != hipSuccess ||
+        sweep4<T>(lv.ax[2], A, B, m[0] * m[1], c[3], l, st) != hipSuccess ||
+        sweep4<T>(lv.ax[1], B, A, m[0], c[2] * c[3], l, st) != hipSuccess ||
+        sweep4<T>(lv.ax[0], A, B, 1, c[1] * c[2] * c[3], l, st) != hipSuccess)
+      return MGX_ERR_HIP;
+    if (solves4<T>(lv, B, D, C, l, st) != hipSuccess) return MGX_ERR_HIP;
+    Coef4Args<T> ca{};
+    for (int k = 0; k < 4; k++) ca.ax[k] = axis4(lv.ax[k]);
+    ca.nodal = C;
+    ca.umc_r = umc;
+    for (int k = 0; k < 3; k++) ca.up[k] = up[k];
+    if (l == L) {
+      ca.out = u;
+      for (int k = 0; k < 3; k++) ca.op[k] = up[k];
+    } else {
+      ca.out = D;
+      compact_pitches(m, ca.op);
+    }
+    ca.n = (uint32_t)(m[0] * m[1] * m[2] * m[3]);
+    ca.d3 = make_div32((uint32_t)m[3]);
+    ca.d2 = make_div32((uint32_t)m[2]);
+    ca.d1 = make_div32((uint32_t)m[1]);
+    if (traced("coef4_rec", l, st, [&] { return launch_coef4<T>(ca, false, st); }) != hipSuccess) return MGX_ERR_HIP;
+  }
+  return MGX_OK;
+}
+
+// Validation of a 4-D decompose / recompose.
+mgx_status prepare4(const void *in, void *out, mgx_dtype dtype, const int64_t *dims, const double *const *coords,
+                    int stop, void *ws, size_t ws_bytes, Plan4 *P, Layout4 *lay) {
+  if (dtype != MGX_F32 && dtype != MGX_F64) return MGX_ERR_ARG;
+  int L;
+  int st = parse_shape4(dims, &L);
+  if (st) return (mgx_status)st;
+  if (!in || !out) return MGX_ERR_ARG;
+  const size_t es = elem_size(dtype);
+  const size_t bytes = (size_t)(dims[0] * dims[1] * dims[2] * dims[3]) * es;
+  if (overlaps(in, bytes, out, bytes)) return MGX_ERR_ARG;
+  mgx_status s = get_plan4(dims, coords, P);
+  if (s) return s;
+  if (stop < 0 || stop > L) return MGX_ERR_LEVEL;
+  *lay = layout4(P->n, L, stop, es);
+  if (lay->total > 0) {
+    if (!ws || ws_bytes < lay->total) return MGX_ERR_WORKSPACE;
+    if (overlaps(ws, lay->total, in, bytes) || overlaps(ws, lay->total, out, bytes)) return MGX_ERR_ARG;
+  }
+  return MGX_OK;
+}
+
+mgx_status decompose4(const void *u, void *u_mc, mgx_dtype dtype, const int64_t *dims, const double *const *coords,
+                      int stop, void *ws, size_t ws_bytes, hipStream_t st) {
+  Plan4 P;
+  Layout4 lay;
+  mgx_status s = prepare4(u, u_mc, dtype, dims, coords, stop, ws, ws_bytes, &P, &lay);
+  if (s) return s;
+  if (dtype == MGX_F32) return run_decompose4<float>(P, stop, (const float *)u, (float *)u_mc, (char *)ws, lay, st);
+  return run_decompose4<double>(P, stop, (const double *)u, (double *)u_mc, (char *)ws, lay, st);
+}
+
+mgx_status recompose4(const void *u_mc, void *u, mgx_dtype dtype, const int64_t *dims, const double *const *coords,
+                      int stop, void *ws, size_t ws_bytes, hipStream_t st) {
+  Plan4 P;
+  Layout4 lay;
+  mgx_status s = prepare4(u_mc, u, dtype, dims, coords, stop, ws, ws_bytes, &P, &lay);
+  if (s) return s;
+  if (dtype == MGX_F32) return run_recompose4<float>(P, stop, (const float *)u_mc, (float *)u, (char *)ws, lay, st);
+  return run_recompose4<double>(P, stop, (const double *)u_mc, (double *)u, (char *)ws, lay, st);
+}
+
+// Quantization arguments of a 4-D field (Sec. 4.1): tau_in, when given,
+// replaces the L-infinity schedule of tol.
+mgx_status quant_args4(const int64_t *dims, const double *const *coords, double tol, int stop, double c_linf,
+                       const double *tau_in, Quant4Args *qa) {
+  Plan4 P;
+  mgx_status s = get_plan4(dims, coords, &P);
+  if (s) return s;
+  const int L = P.L;
+  if (stop < 0 || stop > L) return MGX_ERR_LEVEL;
+  double tau[kMaxLevels];
+  if (tau_in) {
+    for (int i = 0; i <= L - stop; i++) {
+      if (!(tau_in[i] > 0.0) || !std::isfinite(tau_in[i])) return MGX_ERR_TOL;
+      tau[i] = tau_in[i];
+    }
+  } else {
+    if (std::isnan(c_linf) || std::isinf(c_linf)) return MGX_ERR_TOL;
+    if (!(tol > 0.0) || !std::isfinite(tol)) return MGX_ERR_TOL;
+    s = tau_schedule(c_linf > 0.0 ? c_linf : P.linf_constant(stop), L, 4, tol, stop, tau);
+    if (s) return s;
+  }
+  *qa = Quant4Args{};
+  qa->n = (uint32_t)P.count(L);
+  for (int k = 0; k < 4; k++) {
+    qa->nd[k] = (int)P.n[k];
+    qa->off[k] = P.ax[k]->L + 1 - L;  // log2(n_k - 1) - L
+  }
+  qa->d3 = make_div32((uint32_t)P.n[3]);
+  qa->d2 = make_div32((uint32_t)P.n[2]);
+  qa->d1 = make_div32((uint32_t)P.n[1]);
+  qa->first = stop;
+  qa->nlev = L + 1 - stop;
+  for (int i = 0; i < qa->nlev; i++) qa->q[i] = 2.0 * tau[i];
+  return MGX_OK;
+}
+
 }  // namespace
 }  // namespace mgx
 
@@ -1350,7 +1738,7 @@ const char *mgx_status_string(mgx_status s) {
   switch (s) {
     case MGX_OK: return "ok";
     case MGX_ERR_ARG: return "invalid argument";
-    case MGX_ERR_SHAPE: return "invalid shape (ndim 1..3, each dim 2^m+1 with 1<=m<=13)";
+    case MGX_ERR_SHAPE: return "invalid shape (ndim 1..4, each dim 2^m+1 with 1<=m<=13)";
     case MGX_ERR_COORDS: return "coordinates not finite or not strictly increasing";
     case MGX_ERR_LEVEL: return "stop level out of range";
     case MGX_ERR_TOL: return "invalid tolerance or L-infinity constant";
@@ -1362,6 +1750,11 @@ const char *mgx_status_string(mgx_status s) {
 }
 
 int mgx_num_levels(int ndim, const int64_t *dims) {
+  if (ndim == 4) {
+    int L4;
+    int st4 = parse_shape4(dims, &L4);
+    return st4 ? -st4 : L4;
+  }
   int64_t n[3];
   bool real[3];
   int L;
@@ -1371,6 +1764,11 @@ int mgx_num_levels(int ndim, const int64_t *dims) {
 
 size_t mgx_workspace_size(mgx_dtype dtype, int ndim, const int64_t *dims, int stop_level) {
   if (dtype != MGX_F32 && dtype != MGX_F64) return 0;
+  if (ndim == 4) {
+    int L4;
+    if (parse_shape4(dims, &L4) || stop_level < 0 || stop_level > L4) return 0;
+    return layout4(dims, L4, stop_level, elem_size(dtype)).total;
+  }
   int64_t n[3];
   bool real[3];
   int L;
@@ -1382,6 +1780,7 @@ size_t mgx_workspace_size(mgx_dtype dtype, int ndim, const int64_t *dims, int st
 mgx_status mgx_decompose(const void *u, void *u_mc, mgx_dtype dtype, int ndim, const int64_t *dims,
                          const double *const *coords, int stop_level, void *workspace, size_t workspace_bytes,
                          hipStream_t stream) {
+  if (ndim == 4) return decompose4(u, u_mc, dtype, dims, coords, stop_level, workspace, workspace_bytes, stream);
   Plan *P;
   Layout lay;
   const void *tab;
@@ -1402,6 +1801,7 @@ mgx_status mgx_decompose(const void *u, void *u_mc, mgx_dtype dtype, int ndim, c
 mgx_status mgx_recompose(const void *u_mc, void *u, mgx_dtype dtype, int ndim, const int64_t *dims,
                          const double *const *coords, int stop_level, void *workspace, size_t workspace_bytes,
                          hipStream_t stream) {
+  if (ndim == 4) return recompose4(u_mc, u, dtype, dims, coords, stop_level, workspace, workspace_bytes, stream);
   Plan *P;
   Layout lay;
   const void *tab;
@@ -1505,7 +1905,7 @@ mgx_status mgx_adaptive_estimate(const void *v, mgx_dtype dtype, int ndim, const
 }
 
 mgx_status mgx_dyadic_dims(int ndim, const int64_t *dims, int64_t *padded_out) {
-  if (ndim < 1 || ndim > 3 || !dims || !padded_out) return MGX_ERR_ARG;
+  if (ndim < 1 || ndim > 4 || !dims || !padded_out) return MGX_ERR_ARG;
   for (int k = 0; k < ndim; k++) {
     if (dims[k] < 2 || dims[k] > ((int64_t)1 << 30) + 1) return MGX_ERR_SHAPE;
     int64_t p = 3;
@@ -1526,9 +1926,31 @@ static void box3(int ndim, const int64_t *d, int64_t out[3]) {
 mgx_status mgx_pad(const void *u, void *u_pad, mgx_dtype dtype, int ndim, const int64_t *dims,
                    hipStream_t stream) {
   if (!u || !u_pad || (dtype != MGX_F32 && dtype != MGX_F64)) return MGX_ERR_ARG;
-  int64_t pd[3];
+  int64_t pd[4];
   mgx_status s = mgx_dyadic_dims(ndim, dims, pd);
   if (s) return s;
+  if (ndim == 4) {
+    const int64_t nn = dims[0] * dims[1] * dims[2] * dims[3], pn = pd[0] * pd[1] * pd[2] * pd[3];
+    const size_t es = elem_size(dtype);
+    if (pn >= ((int64_t)1 << 32) || overlaps(u, (size_t)nn * es, u_pad, (size_t)pn * es)) return MGX_ERR_ARG;
+    auto args = [&](auto *src, auto *dst) {
+      using T = std::remove_const_t<std::remove_pointer_t<decltype(src)>>;
+      Pad4Args<T> a{};
+      a.src = src;
+      a.dst = dst;
+      for (int k = 0; k < 4; k++) {
+        a.nsrc[k] = (int)dims[k];
+        a.ndst[k] = (int)pd[k];
+      }
+      a.n = (uint32_t)pn;
+      a.d3 = make_div32((uint32_t)pd[3]);
+      a.d2 = make_div32((uint32_t)pd[2]);
+      a.d1 = make_div32((uint32_t)pd[1]);
+      return a;
+    };
+    return hip_status(dtype == MGX_F32 ? launch_pad4<float>(args((const float *)u, (float *)u_pad), stream)
+                                       : launch_pad4<double>(args((const double *)u, (double *)u_pad), stream));
+  }
   int64_t n[3], p[3];
   box3(ndim, dims, n);
   box3(ndim, pd, p);
@@ -1551,9 +1973,19 @@ mgx_status mgx_pad(const void *u, void *u_pad, mgx_dtype dtype, int ndim, const 
 mgx_status mgx_crop(const void *u_pad, void *u, mgx_dtype dtype, int ndim, const int64_t *dims,
                     hipStream_t stream) {
   if (!u || !u_pad || (dtype != MGX_F32 && dtype != MGX_F64)) return MGX_ERR_ARG;
-  int64_t pd[3];
+  int64_t pd[4];
   mgx_status s = mgx_dyadic_dims(ndim, dims, pd);
   if (s) return s;
+  if (ndim == 4) {
+    const int64_t nn = dims[0] * dims[1] * dims[2] * dims[3], pn = pd[0] * pd[1] * pd[2] * pd[3];
+    const size_t es = elem_size(dtype);
+    if (pn >= ((int64_t)1 << 32) || overlaps(u, (size_t)nn * es, u_pad, (size_t)pn * es)) return MGX_ERR_ARG;
+    int64_t sp[3], dp[3];
+    compact_pitches(pd, sp);
+    compact_pitches(dims, dp);
+    return hip_status(dtype == MGX_F32 ? copy4<float>((const float *)u_pad, sp, (float *)u, dp, dims, -1, stream)
+                                       : copy4<double>((const double *)u_pad, sp, (double *)u, dp, dims, -1, stream));
+  }
   int64_t n[3], p[3];
   box3(ndim, dims, n);
   box3(ndim, pd, p);
@@ -1628,11 +2060,66 @@ mgx_status mgx_recompose_adjoint(const void *g_u, void *g_mc, mgx_dtype dtype, i
                                        (const double *)tab, stream);
 }
 
+// 4-D quantization; with stats, the per-level maxima and the out-of-range
+// counts come back like those of the 3-D pass.
+static mgx_status quantize4_common(const void *u_mc, int32_t *labels, mgx_dtype dtype, const int64_t *dims,
+                                   const double *const *coords, double tol_linf, int stop_level, double c_linf,
+                                   const double *tau_in, mgx_quant_stats *stats, hipStream_t stream) {
+  int L4;
+  int st4 = parse_shape4(dims, &L4);
+  if (st4) return (mgx_status)st4;
+  if (!u_mc || !labels) return MGX_ERR_ARG;
+  const size_t cnt = (size_t)(dims[0] * dims[1] * dims[2] * dims[3]);
+  if (overlaps(u_mc, cnt * elem_size(dtype), labels, cnt * 4)) return MGX_ERR_ARG;
+  Quant4Args qa;
+  mgx_status s = quant_args4(dims, coords, tol_linf, stop_level, c_linf, tau_in, &qa);
+  if (s) return s;
+  if (!stats) {
+    hipError_t e = traced("quantize4", -1, stream, [&] {
+      return dtype == MGX_F32 ? launch_quantize4<float>((const float *)u_mc, labels, qa, stream)
+                              : launch_quantize4<double>((const double *)u_mc, labels, qa, stream);
+    });
+    return hip_status(e);
+  }
+  StatsBuf &sb = stats_buf();
+  std::lock_guard<std::mutex> g(sb.mu);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MGX_ERR_HIP;
+  if ((int)sb.per_dev.size() <= dev) sb.per_dev.resize(dev + 1, nullptr);
+  const size_t sbytes = sizeof(int) * kMaxLevels + 2 * sizeof(unsigned long long);
+  if (!sb.per_dev[dev] && hipMalloc(&sb.per_dev[dev], sbytes) != hipSuccess) return MGX_ERR_HIP;
+  char *base = (char *)sb.per_dev[dev];
+  qa.stats_max = (int *)base;
+  qa.stats_ovf = (unsigned long long *)(base + sizeof(int) * kMaxLevels);
+  qa.stats_nan = qa.stats_ovf + 1;
+  if (hipMemsetAsync(base, 0, sbytes, stream) != hipSuccess) return MGX_ERR_HIP;
+  hipError_t e = traced("quantize4_stats", -1, stream, [&] {
+    return dtype == MGX_F32 ? launch_quantize4<float>((const float *)u_mc, labels, qa, stream)
+                            : launch_quantize4<double>((const double *)u_mc, labels, qa, stream);
+  });
+  if (e != hipSuccess) return MGX_ERR_HIP;
+  char host[sizeof(int) * kMaxLevels + 2 * sizeof(unsigned long long)];
+  if (hipMemcpyAsync(host, base, sbytes, hipMemcpyDeviceToHost, stream) != hipSuccess) return MGX_ERR_HIP;
+  if (hipStreamSynchronize(stream) != hipSuccess) return MGX_ERR_HIP;
+  std::memset(stats, 0, sizeof(*stats));
+  stats->first_level = qa.first;
+  stats->num_levels = qa.nlev;
+  std::memcpy(stats->max_abs_label, host, sizeof(int) * qa.nlev);
+  unsigned long long ovf, nan;
+  std::memcpy(&ovf, host + sizeof(int) * kMaxLevels, sizeof(ovf));
+  std::memcpy(&nan, host + sizeof(int) * kMaxLevels + sizeof(ovf), sizeof(nan));
+  stats->n_overflow = (int64_t)ovf;
+  stats->n_nonfinite = (int64_t)nan;
+  return (ovf || nan) ? MGX_ERR_RANGE : MGX_OK;
+}
+
 static mgx_status quantize_common(const void *u_mc, int32_t *labels, mgx_dtype dtype, int ndim,
                                   const int64_t *dims, const double *const *coords, double tol_linf,
                                   int stop_level, double c_linf, const double *tau_in, mgx_quant_stats *stats,
                                   hipStream_t stream) {
   if (dtype != MGX_F32 && dtype != MGX_F64) return MGX_ERR_ARG;
+  if (ndim == 4) return quantize4_common(u_mc, labels, dtype, dims, coords, tol_linf, stop_level, c_linf, tau_in,
+                                         stats, stream);
   int64_t n[3];
   bool real[3];
   int L;
@@ -1688,6 +2175,22 @@ static mgx_status dequantize_common(const int32_t *labels, void *u_mc, mgx_dtype
                                     const int64_t *dims, const double *const *coords, double tol_linf,
                                     int stop_level, double c_linf, const double *tau_in, hipStream_t stream) {
   if (dtype != MGX_F32 && dtype != MGX_F64) return MGX_ERR_ARG;
+  if (ndim == 4) {
+    int L4;
+    int st4 = parse_shape4(dims, &L4);
+    if (st4) return (mgx_status)st4;
+    if (!u_mc || !labels) return MGX_ERR_ARG;
+    const size_t cnt = (size_t)(dims[0] * dims[1] * dims[2] * dims[3]);
+    if (overlaps(u_mc, cnt * elem_size(dtype), labels, cnt * 4)) return MGX_ERR_ARG;
+    Quant4Args qa;
+    mgx_status s4 = quant_args4(dims, coords, tol_linf, stop_level, c_linf, tau_in, &qa);
+    if (s4) return s4;
+    hipError_t e = traced("dequantize4", -1, stream, [&] {
+      return dtype == MGX_F32 ? launch_dequantize4<float>(labels, (float *)u_mc, qa, stream)
+                              : launch_dequantize4<double>(labels, (double *)u_mc, qa, stream);
+    });
+    return hip_status(e);
+  }
   int64_t n[3];
   bool real[3];
   int L;
@@ -1775,6 +2278,11 @@ mgx_status mgx_label_entropy(const int32_t *labels, int ndim, const int64_t *dim
 }
 
 double mgx_linf_constant(int ndim, const int64_t *dims, const double *const *coords, int stop_level) {
+  if (ndim == 4) {
+    Plan4 P4;
+    if (get_plan4(dims, coords, &P4) || stop_level < 0 || stop_level > P4.L) return -1.0;
+    return P4.linf_constant(stop_level);
+  }
   int st = 0;
   Plan *P = get_plan(ndim, dims, coords, &st);
   if (!P || stop_level < 0 || stop_level > P->L) return -1.0;
@@ -1784,6 +2292,16 @@ double mgx_linf_constant(int ndim, const int64_t *dims, const double *const *coo
 mgx_status mgx_level_tolerances(int ndim, const int64_t *dims, const double *const *coords, double tol_linf,
                                 int stop_level, double c_linf, double *tau_out) {
   if (!tau_out) return MGX_ERR_ARG;
+  if (ndim == 4) {
+    Plan4 P4;
+    mgx_status s4 = get_plan4(dims, coords, &P4);
+    if (s4) return s4;
+    if (stop_level < 0 || stop_level > P4.L) return MGX_ERR_LEVEL;
+    if (std::isnan(c_linf) || std::isinf(c_linf)) return MGX_ERR_TOL;
+    if (!(tol_linf > 0.0) || !std::isfinite(tol_linf)) return MGX_ERR_TOL;
+    return tau_schedule(c_linf > 0.0 ? c_linf : P4.linf_constant(stop_level), P4.L, 4, tol_linf, stop_level,
+                        tau_out);
+  }
   int st = 0;
   Plan *P = get_plan(ndim, dims, coords, &st);
   if (!P) return (mgx_status)st;
@@ -1859,6 +2377,16 @@ int mgx_trace_read(mgx_kernel_time *out, int max) {
 mgx_status mgx_decompose_quantize(const void *u, void *u_mc, int32_t *labels, mgx_dtype dtype, int ndim,
                                   const int64_t *dims, const double *const *coords, double tol_linf, int stop_level,
                                   double c_linf, void *workspace, size_t workspace_bytes, hipStream_t stream) {
+  if (ndim == 4) {  // the separate passes; u_mc is required
+    if (!u_mc || !labels) return MGX_ERR_ARG;
+    const size_t cnt = (size_t)(dims ? dims[0] * dims[1] * dims[2] * dims[3] : 0);
+    if (overlaps(labels, cnt * 4, u, cnt * elem_size(dtype)) || overlaps(labels, cnt * 4, u_mc, cnt * elem_size(dtype)))
+      return MGX_ERR_ARG;
+    mgx_status s4 = decompose4(u, u_mc, dtype, dims, coords, stop_level, workspace, workspace_bytes, stream);
+    if (s4) return s4;
+    return quantize4_common(u_mc, labels, dtype, dims, coords, tol_linf, stop_level, c_linf, nullptr, nullptr,
+                            stream);
+  }
   Plan *P;
   Layout lay;
   const void *tab;
@@ -1885,6 +2413,16 @@ mgx_status mgx_dequantize_recompose(const int32_t *labels, void *u_mc, void *u, 
                                     const int64_t *dims, const double *const *coords, double tol_linf,
                                     int stop_level, double c_linf, void *workspace, size_t workspace_bytes,
                                     hipStream_t stream) {
+  if (ndim == 4) {  // the separate passes; u_mc is required
+    if (!u_mc || !labels) return MGX_ERR_ARG;
+    const size_t cnt = (size_t)(dims ? dims[0] * dims[1] * dims[2] * dims[3] : 0);
+    if (overlaps(labels, cnt * 4, u, cnt * elem_size(dtype)) || overlaps(labels, cnt * 4, u_mc, cnt * elem_size(dtype)))
+      return MGX_ERR_ARG;
+    mgx_status s4 = dequantize_common(labels, u_mc, dtype, 4, dims, coords, tol_linf, stop_level, c_linf, nullptr,
+                                      stream);
+    if (s4) return s4;
+    return recompose4(u_mc, u, dtype, dims, coords, stop_level, workspace, workspace_bytes, stream);
+  }
   Plan *P;
   Layout lay;
   const void *tab;

@@ -308,7 +308,8 @@ Plan *get_plan(int ndim, const int64_t *dims, const double *const *coords, int *
       std::vector<double> Y;
       for (int64_t i = 0; i < n[k]; i += s) Y.push_back(p->X[k][i]);
       build_axis(Y, a, p->tab64);
-      prod *= axis_norm(a, p->tab64);
+      p->axis_norm[l][k] = axis_norm(a, p->tab64);
+      prod *= p->axis_norm[l][k];
     }
     p->level_amp[l] = 1.0 + prod;
   }

@@ -54,6 +54,7 @@ struct Plan {
   std::vector<double> X[3];                  // fine coordinates
   AxisLevel ax[kMaxLevels][3];               // [l][k], l = 1..L
   double level_amp[kMaxLevels] = {};         // 1 + prod_k ||Mc^-1 R M||_inf at level l
+  double axis_norm[kMaxLevels][3] = {};      // ||Mc^-1 R M||_inf of axis k at level l (real axes)
   std::vector<double> tab64;                 // all tables, FP64
   std::vector<float> tab32;                  // same, rounded to FP32
   // device copies, one per device ordinal

@@ -34,15 +34,24 @@ def test_num_levels_and_workspace():
     assert mgx.num_levels((513, 513, 513)) == 8
     assert mgx.num_levels((257, 1025, 1025)) == 7
     assert mgx.num_levels((65,)) == 5
-    for bad in [(64,), (2,), (513, 512), (5, 5, 5, 5), (16385,)]:
+    for bad in [(64,), (2,), (513, 512), (5, 5, 5, 5, 5), (5, 5, 6, 5), (16385,), (2049, 2049, 1025, 3)]:
         with pytest.raises(mgx.MgxError):
             mgx.num_levels(bad)
+    # 4-D (Table 2's four-axis field, padded): the shortest axis sets L
+    assert mgx.num_levels((513, 129, 129, 129)) == 6
+    assert mgx.num_levels((5, 5, 5, 5)) == 1
     n = 513 ** 3
     ws = mgx.workspace_size(0, (513, 513, 513), 0)
     assert 0.25 * n * 4 < ws < 0.3 * n * 4
     assert mgx.workspace_size(0, (513, 513, 513), 8) == 0
     assert mgx.workspace_size(1, (65, 65, 65), 4) > 0
     assert mgx.workspace_size(7, (65, 65, 65), 0) == 0
+    # 4-D: two sweep buffers and two level-(L-1) boxes
+    n4 = (17, 9, 33, 9)
+    c4 = [(k - 1) // 2 + 1 for k in n4]
+    want = (n4[0] * n4[1] * n4[2] * c4[3] + n4[0] * n4[1] * c4[2] * c4[3] + 2 * int(np.prod(c4))) * 4
+    assert want <= mgx.workspace_size(0, n4, 0) <= want + 4 * 256
+    assert mgx.workspace_size(0, n4, mgx.num_levels(n4)) == 0
 
 
 def _call_decompose(u, out, dims, coords=None, stop=0, ws=0, nbytes=0, dtype=0):
@@ -74,10 +83,20 @@ def test_validation_before_launch():
     assert L.mgx_quantize(U, U, 0, 2, d, None, 1.0, 0, 0.0, None, None) == 1
     assert L.mgx_dequantize(U, O, 0, 2, d, None, 1.0, 7, 0.0, None) == 4
     assert mgx.lib().mgx_status_string(6).decode().startswith("quantization")
+    # 4-D fields take the same checks
+    assert _call_decompose(U, O, [9, 9, 9, 10], ws=W, nbytes=big) == 2
+    assert _call_decompose(U, O, [9, 9, 9, 9], ws=W, nbytes=big, stop=3) == 4
+    assert _call_decompose(U, O, [9, 9, 9, 9], ws=W, nbytes=16) == 7
+    assert _call_decompose(U, U + 8, [9, 9, 9, 9], ws=W, nbytes=big) == 1
+    bad4 = mgx.Coords((9, 9, 9, 9), [None, None, np.array([0, 1, 2, 3, 4, 5, 6, 6, 7.0]), None])
+    assert _call_decompose(U, O, [9, 9, 9, 9], coords=bad4.ptr, ws=W, nbytes=big) == 3
+    d4 = (ctypes.c_int64 * 4)(9, 9, 9, 9)
+    assert L.mgx_quantize(U, O, 0, 4, d4, None, -1.0, 0, 0.0, None, None) == 5
+    assert L.mgx_dequantize(U, O, 0, 4, d4, None, 1.0, 3, 0.0, None) == 4
 
 
 @pytest.mark.parametrize("shape,kind", [((65, 65, 65), None), ((17, 33, 65), "mixed"), ((129, 33), "random"),
-                                        ((257,), None)])
+                                        ((257,), None), ((17, 9, 33, 9), "random"), ((9, 9, 9, 9), None)])
 def test_host_tables_match_oracle(shape, kind):
     if kind == "mixed":
         coords = [workloads.tanh_coordinates(shape[0]), None, workloads.random_coordinates(shape[2], 1)]

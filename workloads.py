@@ -121,6 +121,15 @@ def layered_lognormal_field(shape=(257, 1025, 1025), seed: int = BASE_SEED + 3, 
     return u.to(dtype).contiguous(), [z, None, None]
 
 
+def orbital_field(shape=(288, 115, 69, 69), seed: int = BASE_SEED + 6, device="cpu", dtype=torch.float32):
+    """Four-axis workload shaped like the QMCPACK field of Table 2 (orbital
+    index x three spatial axes, non-dyadic): a unit-variance Gaussian random
+    field with P(k) ~ k^-4, wavenumbers along the orbital axis scaled by 4
+    (neighbouring orbitals only weakly alike)."""
+    G = gaussian_random_field(tuple(shape), 4.0, seed, device, axis_scale=(4.0, 1.0, 1.0, 1.0))
+    return G.to(dtype).contiguous()
+
+
 def batch_specs(count: int = 64, seed: int = BASE_SEED + 4):
     """Per-field shapes (each axis from {33,65,129,257}), spectral slopes in
     [2,4] and relative tolerances log-uniform in [1e-4, 1e-2]."""
