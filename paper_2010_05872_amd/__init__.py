@@ -456,9 +456,6 @@ def decompose_quantize(u, tol, coords=None, stop_level=0, c_linf=0.0, out=None, 
         out = None
     elif out is None:
         out = torch.empty_like(u)
-    ret = out
-    if out is None and u.dim() == 4:
-        out = torch.empty_like(u)  # 4-D: the separate passes, through u_mc
     if labels is None:
         labels = torch.empty(u.shape, dtype=torch.int32, device=u.device)
     if out is not None:
@@ -471,7 +468,7 @@ def decompose_quantize(u, tol, coords=None, stop_level=0, c_linf=0.0, out=None, 
                                         float(tol), int(stop_level), float(c_linf), ws.data_ptr(),
                                         ws.numel() * ws.element_size(), _stream(u.device))
     _check(code, "mgx_decompose_quantize")
-    return ret, labels
+    return out, labels
 
 
 def dequantize_recompose(labels, tol, dtype, coords=None, stop_level=0, c_linf=0.0, coef=None, out=None,
@@ -484,8 +481,6 @@ def dequantize_recompose(labels, tol, dtype, coords=None, stop_level=0, c_linf=0
     _check_tensor(labels, "labels")
     if out is None:
         out = torch.empty(labels.shape, dtype=dtype, device=labels.device)
-    if coef is None and labels.dim() == 4:
-        coef = torch.empty(labels.shape, dtype=dtype, device=labels.device)  # 4-D: the separate passes
     if coef is not None:
         _check_tensor(coef, "coef")
     _check_tensor(out, "out")

@@ -1451,10 +1451,22 @@ Axis4<T> axis4(const AxisTab<T> &t) {
   return Axis4<T>{t.wl, t.wr, t.w5, t.m, t.c};
 }
 
+// Chunks of the coefficient kernels' march along axis 0: about 16 M threads
+// in flight on large levels, at least 16 plane pairs per chunk.
+template <typename T>
+void march_chunks(Coef4Args<T> &a, int64_t c0) {
+  const int64_t npair = c0 - 1;
+  int64_t want = ((int64_t)1 << 24) / std::max<int64_t>(a.ncol, 1);
+  want = std::min<int64_t>(want, std::max<int64_t>(npair / 16, 1));
+  want = std::max<int64_t>(want, 1);
+  a.jchunk = (int)std::max<int64_t>((npair + want - 1) / want, 1);
+  a.nchunk = npair > 0 ? (int)((npair + a.jchunk - 1) / a.jchunk) : 1;
+}
+
 // One sweep of R M along axis k of (outer, m_k, inner) -> (outer, c_k, inner).
 template <typename T>
-hipError_t sweep4(const AxisTab<T> &t, const T *in, T *out, int64_t outer, int64_t inner, int level,
-                  hipStream_t st) {
+hipError_t sweep4(const char *name, const AxisTab<T> &t, const T *in, T *out, int64_t outer, int64_t inner,
+                  int level, hipStream_t st) {
   Sweep4Args<T> a{};
   a.w5 = t.w5;
   a.m = t.m;
@@ -1465,7 +1477,7 @@ hipError_t sweep4(const AxisTab<T> &t, const T *in, T *out, int64_t outer, int64
   a.inner = (uint32_t)inner;
   a.dinner = make_div32((uint32_t)inner);
   a.dc = make_div32((uint32_t)t.c);
-  return traced("sweep4", level, st, [&] { return launch_sweep4<T>(a, false, st); });
+  return traced(name, level, st, [&] { return launch_sweep4<T>(a, false, st); });
 }
 
 // Thomas solves of the coarse box (c0, c1, c2, c3) in place, axis 3 first;
@@ -1517,12 +1529,17 @@ hipError_t solves4(const Level4<T> &lv, T *F, const T *in, T *out, int level, hi
   return strided(0, c1 * c2 * c3, 1, in ? kSolveApply : kSolveInPlace);
 }
 
+// lab_r: read labels times q instead of src; lab_w: also (dst null: only)
+// write the labels of the values at the destination positions.
 template <typename T>
 hipError_t copy4(const T *src, const int64_t sp[3], T *dst, const int64_t dp[3], const int64_t b[4], int level,
-                 hipStream_t st) {
+                 hipStream_t st, const int32_t *lab_r = nullptr, int32_t *lab_w = nullptr, double q = 0.0) {
   Copy4Args<T> a{};
   a.src = src;
   a.dst = dst;
+  a.lab_r = lab_r;
+  a.lab_w = lab_w;
+  a.q = q;
   for (int k = 0; k < 3; k++) {
     a.sp[k] = sp[k];
     a.dp[k] = dp[k];
@@ -1532,7 +1549,8 @@ hipError_t copy4(const T *src, const int64_t sp[3], T *dst, const int64_t dp[3],
   a.d3 = make_div32((uint32_t)b[3]);
   a.d2 = make_div32((uint32_t)b[2]);
   a.d1 = make_div32((uint32_t)b[1]);
-  return traced("copy4", level, st, [&] { return launch_copy4<T>(a, st); });
+  const char *name = lab_w ? "copy4+q" : lab_r ? "copy4_dq" : "copy4";
+  return traced(name, level, st, [&] { return launch_copy4<T>(a, st); });
 }
 
 void compact_pitches(const int64_t b[4], int64_t p[3]) {
@@ -1544,14 +1562,19 @@ void compact_pitches(const int64_t b[4], int64_t p[3]) {
 // Decomposition of a 4-D field, levels L .. stop+1 (Sec. 2): per level the
 // coefficients, the four load-vector sweeps and the four solves, whose result
 // Q_{l-1} u = Mc^{-1} (R M)^{x4} V is the next level's box.
+// With labels (bin widths qa->q by level from stop), the level kernels also
+// (umc null: only) write the quantization labels.
 template <typename T>
 mgx_status run_decompose4(const Plan4 &P, int stop, const T *u, T *umc, char *ws, const Layout4 &lay,
-                          hipStream_t st) {
+                          hipStream_t st, int32_t *labels = nullptr, const Quant4Args *qa = nullptr) {
   const int L = P.L;
   const int64_t N = P.count(L);
-  if (stop == L) return hip_status(hipMemcpyAsync(umc, u, sizeof(T) * N, hipMemcpyDeviceToDevice, st));
   int64_t up[3];
   compact_pitches(P.n, up);
+  if (stop == L) {
+    if (!labels) return hip_status(hipMemcpyAsync(umc, u, sizeof(T) * N, hipMemcpyDeviceToDevice, st));
+    return copy4<T>(u, up, umc, up, P.n, L, st, nullptr, labels, qa->q[0]) != hipSuccess ? MGX_ERR_HIP : MGX_OK;
+  }
   T *A = (T *)(ws + lay.offA), *B = (T *)(ws + lay.offB);
   const T *V = u;
   for (int l = L; l > stop; l--) {
@@ -1563,16 +1586,22 @@ mgx_status run_decompose4(const Plan4 &P, int stop, const T *u, T *umc, char *ws
     for (int k = 0; k < 4; k++) ca.ax[k] = axis4(lv.ax[k]);
     ca.V = V;
     ca.umc_w = umc;
+    if (labels) {
+      ca.lab_w = labels;
+      ca.qc = qa->q[l - stop];
+    }
     for (int k = 0; k < 3; k++) ca.up[k] = up[k];
-    ca.n = (uint32_t)(m[0] * m[1] * m[2] * m[3]);
+    ca.ncol = (uint32_t)(m[1] * m[2] * m[3]);
     ca.d3 = make_div32((uint32_t)m[3]);
     ca.d2 = make_div32((uint32_t)m[2]);
-    ca.d1 = make_div32((uint32_t)m[1]);
-    if (traced("coef4_dec", l, st, [&] { return launch_coef4<T>(ca, true, st); }) != hipSuccess) return MGX_ERR_HIP;
-    if (sweep4<T>(lv.ax[3], V, A, m[0] * m[1] * m[2], 1, l, st) != hipSuccess ||
-        sweep4<T>(lv.ax[2], A, B, m[0] * m[1], c[3], l, st) != hipSuccess ||
-        sweep4<T>(lv.ax[1], B, A, m[0], c[2] * c[3], l, st) != hipSuccess ||
-        sweep4<T>(lv.ax[0], A, B, 1, c[1] * c[2] * c[3], l, st) != hipSuccess)
+    march_chunks(ca, c[0]);
+    if (traced(labels ? "coef4_dec+q" : "coef4_dec", l, st, [&] { return launch_coef4<T>(ca, true, st); }) !=
+        hipSuccess)
+      return MGX_ERR_HIP;
+    if (sweep4<T>("sweep4_a3", lv.ax[3], V, A, m[0] * m[1] * m[2], 1, l, st) != hipSuccess ||
+        sweep4<T>("sweep4_a2", lv.ax[2], A, B, m[0] * m[1], c[3], l, st) != hipSuccess ||
+        sweep4<T>("sweep4_a1", lv.ax[1], B, A, m[0], c[2] * c[3], l, st) != hipSuccess ||
+        sweep4<T>("sweep4_a0", lv.ax[0], A, B, 1, c[1] * c[2] * c[3], l, st) != hipSuccess)
       return MGX_ERR_HIP;
     if (solves4<T>(lv, B, nullptr, nullptr, l, st) != hipSuccess) return MGX_ERR_HIP;
     V = B;
@@ -1580,26 +1609,34 @@ mgx_status run_decompose4(const Plan4 &P, int stop, const T *u, T *umc, char *ws
   int64_t b[4], bp[3];
   for (int k = 0; k < 4; k++) b[k] = P.m(stop, k);
   compact_pitches(b, bp);
-  return copy4<T>(B, bp, umc, up, b, stop, st) != hipSuccess ? MGX_ERR_HIP : MGX_OK;
+  return copy4<T>(B, bp, umc, up, b, stop, st, nullptr, labels, labels ? qa->q[0] : 0.0) != hipSuccess
+             ? MGX_ERR_HIP
+             : MGX_OK;
 }
 
 // Recomposition, levels stop+1 .. L: the load vector of the level's
 // coefficients (read from u_mc), the solves subtracting the correction from
 // the nodal values, then coefficients plus interpolant.
+// With labels, the coefficients are read as labels times their level's bin
+// width instead of from umc (which may then be null).
 template <typename T>
 mgx_status run_recompose4(const Plan4 &P, int stop, const T *umc, T *u, char *ws, const Layout4 &lay,
-                          hipStream_t st) {
+                          hipStream_t st, const int32_t *labels = nullptr, const Quant4Args *qa = nullptr) {
   const int L = P.L;
   const int64_t N = P.count(L);
-  if (stop == L) return hip_status(hipMemcpyAsync(u, umc, sizeof(T) * N, hipMemcpyDeviceToDevice, st));
   int64_t up[3];
   compact_pitches(P.n, up);
+  if (stop == L) {
+    if (!labels) return hip_status(hipMemcpyAsync(u, umc, sizeof(T) * N, hipMemcpyDeviceToDevice, st));
+    return copy4<T>(umc, up, u, up, P.n, L, st, labels, nullptr, qa->q[0]) != hipSuccess ? MGX_ERR_HIP : MGX_OK;
+  }
   T *A = (T *)(ws + lay.offA), *B = (T *)(ws + lay.offB), *C = (T *)(ws + lay.offC), *D = (T *)(ws + lay.offD);
   {
     int64_t b[4], bp[3];
     for (int k = 0; k < 4; k++) b[k] = P.m(stop, k);
     compact_pitches(b, bp);
-    if (copy4<T>(umc, up, D, bp, b, stop, st) != hipSuccess) return MGX_ERR_HIP;
+    if (copy4<T>(umc, up, D, bp, b, stop, st, labels, nullptr, labels ? qa->q[0] : 0.0) != hipSuccess)
+      return MGX_ERR_HIP;
   }
   for (int l = stop + 1; l <= L; l++) {
     Level4<T> lv;
@@ -1622,16 +1659,24 @@ mgx_status run_recompose4(const Plan4 &P, int stop, const T *umc, T *u, char *ws
     for (int k = 0; k < 4; k++) g.cc[k] = (int)c[k];
     g.dm2 = make_div32((uint32_t)m[2]);
     g.dm1 = make_div32((uint32_t)m[1]);
-    if (traced("sweep4_gather", l, st, [&] { return launch_sweep4<T>(g, true, st); }) != hipSuccess ||
-        sweep4<T>(lv.ax[2], A, B, m[0] * m[1], c[3], l, st) != hipSuccess ||
-        sweep4<T>(lv.ax[1], B, A, m[0], c[2] * c[3], l, st) != hipSuccess ||
-        sweep4<T>(lv.ax[0], A, B, 1, c[1] * c[2] * c[3], l, st) != hipSuccess)
+    if (labels) {
+      g.lab = labels;
+      g.qc = qa->q[l - stop];
+    }
+    if (traced(labels ? "sweep4_gather+q" : "sweep4_gather", l, st, [&] { return launch_sweep4<T>(g, true, st); }) != hipSuccess ||
+        sweep4<T>("sweep4_a2", lv.ax[2], A, B, m[0] * m[1], c[3], l, st) != hipSuccess ||
+        sweep4<T>("sweep4_a1", lv.ax[1], B, A, m[0], c[2] * c[3], l, st) != hipSuccess ||
+        sweep4<T>("sweep4_a0", lv.ax[0], A, B, 1, c[1] * c[2] * c[3], l, st) != hipSuccess)
       return MGX_ERR_HIP;
     if (solves4<T>(lv, B, D, C, l, st) != hipSuccess) return MGX_ERR_HIP;
     Coef4Args<T> ca{};
     for (int k = 0; k < 4; k++) ca.ax[k] = axis4(lv.ax[k]);
     ca.nodal = C;
     ca.umc_r = umc;
+    if (labels) {
+      ca.lab_r = labels;
+      ca.qc = qa->q[l - stop];
+    }
     for (int k = 0; k < 3; k++) ca.up[k] = up[k];
     if (l == L) {
       ca.out = u;
@@ -1640,33 +1685,37 @@ mgx_status run_recompose4(const Plan4 &P, int stop, const T *umc, T *u, char *ws
       ca.out = D;
       compact_pitches(m, ca.op);
     }
-    ca.n = (uint32_t)(m[0] * m[1] * m[2] * m[3]);
+    ca.ncol = (uint32_t)(m[1] * m[2] * m[3]);
     ca.d3 = make_div32((uint32_t)m[3]);
     ca.d2 = make_div32((uint32_t)m[2]);
-    ca.d1 = make_div32((uint32_t)m[1]);
-    if (traced("coef4_rec", l, st, [&] { return launch_coef4<T>(ca, false, st); }) != hipSuccess) return MGX_ERR_HIP;
+    march_chunks(ca, c[0]);
+    if (traced(labels ? "coef4_rec+q" : "coef4_rec", l, st, [&] { return launch_coef4<T>(ca, false, st); }) !=
+        hipSuccess)
+      return MGX_ERR_HIP;
   }
   return MGX_OK;
 }
 
 // Validation of a 4-D decompose / recompose.
+// may_null: 1 = in, 2 = out may be null (the fused calls' u_mc).
 mgx_status prepare4(const void *in, void *out, mgx_dtype dtype, const int64_t *dims, const double *const *coords,
-                    int stop, void *ws, size_t ws_bytes, Plan4 *P, Layout4 *lay) {
+                    int stop, void *ws, size_t ws_bytes, Plan4 *P, Layout4 *lay, int may_null = 0) {
   if (dtype != MGX_F32 && dtype != MGX_F64) return MGX_ERR_ARG;
   int L;
   int st = parse_shape4(dims, &L);
   if (st) return (mgx_status)st;
-  if (!in || !out) return MGX_ERR_ARG;
+  if ((!in && !(may_null & 1)) || (!out && !(may_null & 2))) return MGX_ERR_ARG;
   const size_t es = elem_size(dtype);
   const size_t bytes = (size_t)(dims[0] * dims[1] * dims[2] * dims[3]) * es;
-  if (overlaps(in, bytes, out, bytes)) return MGX_ERR_ARG;
+  if (in && out && overlaps(in, bytes, out, bytes)) return MGX_ERR_ARG;
   mgx_status s = get_plan4(dims, coords, P);
   if (s) return s;
   if (stop < 0 || stop > L) return MGX_ERR_LEVEL;
   *lay = layout4(P->n, L, stop, es);
   if (lay->total > 0) {
     if (!ws || ws_bytes < lay->total) return MGX_ERR_WORKSPACE;
-    if (overlaps(ws, lay->total, in, bytes) || overlaps(ws, lay->total, out, bytes)) return MGX_ERR_ARG;
+    if ((in && overlaps(ws, lay->total, in, bytes)) || (out && overlaps(ws, lay->total, out, bytes)))
+      return MGX_ERR_ARG;
   }
   return MGX_OK;
 }
@@ -2377,15 +2426,23 @@ int mgx_trace_read(mgx_kernel_time *out, int max) {
 mgx_status mgx_decompose_quantize(const void *u, void *u_mc, int32_t *labels, mgx_dtype dtype, int ndim,
                                   const int64_t *dims, const double *const *coords, double tol_linf, int stop_level,
                                   double c_linf, void *workspace, size_t workspace_bytes, hipStream_t stream) {
-  if (ndim == 4) {  // the separate passes; u_mc is required
-    if (!u_mc || !labels) return MGX_ERR_ARG;
-    const size_t cnt = (size_t)(dims ? dims[0] * dims[1] * dims[2] * dims[3] : 0);
-    if (overlaps(labels, cnt * 4, u, cnt * elem_size(dtype)) || overlaps(labels, cnt * 4, u_mc, cnt * elem_size(dtype)))
-      return MGX_ERR_ARG;
-    mgx_status s4 = decompose4(u, u_mc, dtype, dims, coords, stop_level, workspace, workspace_bytes, stream);
+  if (ndim == 4) {  // labels written by the level kernels, u_mc optional
+    Plan4 P4;
+    Layout4 lay4;
+    mgx_status s4 = prepare4(u, u_mc, dtype, dims, coords, stop_level, workspace, workspace_bytes, &P4, &lay4, 2);
     if (s4) return s4;
-    return quantize4_common(u_mc, labels, dtype, dims, coords, tol_linf, stop_level, c_linf, nullptr, nullptr,
-                            stream);
+    if (!labels) return MGX_ERR_ARG;
+    const size_t cnt = (size_t)P4.count(P4.L), es = elem_size(dtype);
+    if ((u_mc && overlaps(labels, cnt * 4, u_mc, cnt * es)) || overlaps(labels, cnt * 4, u, cnt * es) ||
+        (lay4.total > 0 && overlaps(labels, cnt * 4, workspace, lay4.total)))
+      return MGX_ERR_ARG;
+    Quant4Args qa;
+    if ((s4 = quant_args4(dims, coords, tol_linf, stop_level, c_linf, nullptr, &qa))) return s4;
+    if (dtype == MGX_F32)
+      return run_decompose4<float>(P4, stop_level, (const float *)u, (float *)u_mc, (char *)workspace, lay4, stream,
+                                   labels, &qa);
+    return run_decompose4<double>(P4, stop_level, (const double *)u, (double *)u_mc, (char *)workspace, lay4,
+                                  stream, labels, &qa);
   }
   Plan *P;
   Layout lay;
@@ -2413,15 +2470,27 @@ mgx_status mgx_dequantize_recompose(const int32_t *labels, void *u_mc, void *u, 
                                     const int64_t *dims, const double *const *coords, double tol_linf,
                                     int stop_level, double c_linf, void *workspace, size_t workspace_bytes,
                                     hipStream_t stream) {
-  if (ndim == 4) {  // the separate passes; u_mc is required
-    if (!u_mc || !labels) return MGX_ERR_ARG;
-    const size_t cnt = (size_t)(dims ? dims[0] * dims[1] * dims[2] * dims[3] : 0);
-    if (overlaps(labels, cnt * 4, u, cnt * elem_size(dtype)) || overlaps(labels, cnt * 4, u_mc, cnt * elem_size(dtype)))
-      return MGX_ERR_ARG;
-    mgx_status s4 = dequantize_common(labels, u_mc, dtype, 4, dims, coords, tol_linf, stop_level, c_linf, nullptr,
-                                      stream);
+  if (ndim == 4) {  // with u_mc: dequantize into it, then recompose; without: straight from the labels
+    Plan4 P4;
+    Layout4 lay4;
+    mgx_status s4 = prepare4(u_mc, u, dtype, dims, coords, stop_level, workspace, workspace_bytes, &P4, &lay4, 1);
     if (s4) return s4;
-    return recompose4(u_mc, u, dtype, dims, coords, stop_level, workspace, workspace_bytes, stream);
+    if (!labels) return MGX_ERR_ARG;
+    const size_t cnt = (size_t)P4.count(P4.L), es = elem_size(dtype);
+    if ((u_mc && overlaps(labels, cnt * 4, u_mc, cnt * es)) || overlaps(labels, cnt * 4, u, cnt * es) ||
+        (lay4.total > 0 && overlaps(labels, cnt * 4, workspace, lay4.total)))
+      return MGX_ERR_ARG;
+    if (u_mc) {
+      if ((s4 = dequantize_common(labels, u_mc, dtype, 4, dims, coords, tol_linf, stop_level, c_linf, nullptr,
+                                  stream)))
+        return s4;
+      return recompose4(u_mc, u, dtype, dims, coords, stop_level, workspace, workspace_bytes, stream);
+    }
+    Quant4Args qa;
+    if ((s4 = quant_args4(dims, coords, tol_linf, stop_level, c_linf, nullptr, &qa))) return s4;
+    if (dtype == MGX_F32)
+      return run_recompose4<float>(P4, stop_level, nullptr, (float *)u, (char *)workspace, lay4, stream, labels, &qa);
+    return run_recompose4<double>(P4, stop_level, nullptr, (double *)u, (char *)workspace, lay4, stream, labels, &qa);
   }
   Plan *P;
   Layout lay;

@@ -4,7 +4,7 @@
 // The method is the one of Sec. 2 on a grid with four axes.  A level runs as
 //   k_coef4<DEC>      coefficients c = V - Pi V on N*_l (Pi over up to 16
 //                     nodal corners), stored at level-centric positions
-//                     (Sec. 5.1);
+//                     (Sec. 5.1), one thread per column marching along axis 0;
 //   k_sweep4 x 4      the load vector (R M)^{x4} V, one axis after the other
 //                     (Sec. 5.2 applies the fused mass-restriction stencil per
 //                     axis), each sweep halving one axis, the contiguous axis
@@ -24,6 +24,21 @@
 namespace mgx {
 namespace {
 
+// Quantization label of a coefficient and a coefficient of a label: the
+// operations of the separate (de)quantization passes (Sec. 4.1), so labels
+// written or read by the level kernels equal theirs bit for bit.
+template <typename T>
+__device__ __forceinline__ int32_t label4(T v, double q) {
+  const double t = (double)v / q;
+  return !(fabs(t) < 2147483647.0) ? INT32_MIN : (int32_t)rint(t);
+}
+// (the product is rounded on its own, never contracted into a following add)
+template <typename T>
+__device__ __forceinline__ T unlabel4(int32_t l, double q) {
+#pragma clang fp contract(off)
+  return (T)((double)l * q);
+}
+
 __device__ __forceinline__ uint32_t udiv(uint32_t n, const Div32 &v) {
   return v.d == 1 ? n : (uint32_t)__umul64hi((uint64_t)n, v.mag);
 }
@@ -39,58 +54,114 @@ __device__ __forceinline__ void split4(uint32_t i, const Div32 &d3, const Div32 
   j[0] = (int)r3;
 }
 
-template <typename T, bool DEC>
+// One thread per column (j1, j2, j3) of the level box and chunk of plane
+// pairs (blockIdx.y), marching along axis 0.
+// The interpolant factors: Pi V(j) = wl0 Q(j0 - 1) + wr0 Q(j0 + 1) for odd j0
+// and Q(j0) for even j0, where Q(p) is the interpolant over axes 1..3 of
+// plane p at the column (the value itself when the column is nodal in axes
+// 1..3).  Q of each even plane is computed once and kept for the odd plane
+// after it, so every value of the level box is read about once.
+template <typename T, bool DEC, bool LAB>
 __global__ void __launch_bounds__(256) k_coef4(Coef4Args<T> a) {
-  const int m1 = a.ax[1].m, m2 = a.ax[2].m, m3 = a.ax[3].m;
+  const int m0 = a.ax[0].m, m1 = a.ax[1].m, m2 = a.ax[2].m, m3 = a.ax[3].m;
   const int c1 = a.ax[1].c, c2 = a.ax[2].c, c3 = a.ax[3].c;
-  const uint64_t stride = (uint64_t)gridDim.x * 256u;
-  for (uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x; i < a.n; i += stride) {
-    int j[4];
-    split4((uint32_t)i, a.d3, a.d2, a.d1, j);
-    int odd = 0;
+  const uint32_t col = blockIdx.x * 256u + threadIdx.x;
+  if (col >= a.ncol) return;
+  int j[4];
+  {
+    const uint32_t r = udiv(col, a.d3);
+    j[3] = (int)(col - r * a.d3.d);
+    const uint32_t r2 = udiv(r, a.d2);
+    j[2] = (int)(r - r2 * a.d2.d);
+    j[1] = (int)r2;
+  }
+  // the column's nodal neighbours in axes 1..3 (level-l box for DEC, coarse
+  // box for REC): per axis the left (or, on an even index, the own) offset and
+  // the right one, with their weights
+  int64_t lo[4], hi[4];
+  T wlo[4], whi[4];
+  bool od[4];
+  {
+    const int64_t str[4] = {0, DEC ? (int64_t)m2 * m3 : (int64_t)c2 * c3, DEC ? m3 : c3, 1};
 #pragma unroll
-    for (int k = 0; k < 4; k++) odd |= (j[k] & 1) << k;
-    if (odd == 0) {
-      if (!DEC)
-        a.out[j[0] * a.op[0] + j[1] * a.op[1] + j[2] * a.op[2] + j[3]] =
-            a.nodal[(((int64_t)(j[0] >> 1) * c1 + (j[1] >> 1)) * c2 + (j[2] >> 1)) * c3 + (j[3] >> 1)];
-      continue;
+    for (int k = 1; k < 4; k++) {
+      od[k] = j[k] & 1;
+      const int jl = od[k] ? j[k] - 1 : j[k], jr = od[k] ? j[k] + 1 : j[k];
+      lo[k] = (DEC ? jl : (jl >> 1)) * str[k];
+      hi[k] = (DEC ? jr : (jr >> 1)) * str[k];
+      wlo[k] = od[k] ? a.ax[k].wl[j[k]] : T(1);
+      whi[k] = od[k] ? a.ax[k].wr[j[k]] : T(0);
     }
-    // interpolant over the nodal corners: for each odd axis the left (bit 0)
-    // and right (bit 1) neighbour
-    T pred = T(0);
-    for (int cn = 0; cn < 16; cn++) {
-      if (cn & ~odd) continue;
-      T w = T(1);
-      int q[4];
-#pragma unroll
-      for (int k = 0; k < 4; k++) {
-        if ((odd >> k) & 1) {
-          if ((cn >> k) & 1) {
-            q[k] = j[k] + 1;
-            w *= a.ax[k].wr[j[k]];
-          } else {
-            q[k] = j[k] - 1;
-            w *= a.ax[k].wl[j[k]];
-          }
-        } else {
-          q[k] = j[k];
-        }
-      }
-      const T v = DEC ? a.V[(((int64_t)q[0] * m1 + q[1]) * m2 + q[2]) * m3 + q[3]]
-                      : a.nodal[(((int64_t)(q[0] >> 1) * c1 + (q[1] >> 1)) * c2 + (q[2] >> 1)) * c3 + (q[3] >> 1)];
-      pred += w * v;
+  }
+  const bool odd = od[1] || od[2] || od[3];
+  const int64_t plane = DEC ? (int64_t)m1 * m2 * m3 : (int64_t)c1 * c2 * c3;
+  // no aliasing between the level box, the coarse box and the outputs: the
+  // loads of the next plane pair may pass the stores of the previous one
+  const T *__restrict__ src = DEC ? a.V : a.nodal;
+  const T *__restrict__ V = a.V;
+  T *__restrict__ umc_w = a.umc_w;
+  int32_t *__restrict__ lab_w = a.lab_w;
+  const T *__restrict__ umc_r = a.umc_r;
+  const int32_t *__restrict__ lab_r = a.lab_r;
+  T *__restrict__ out = a.out;
+  // Q(p): the interpolant over axes 1..3 at the column in plane p of src
+  // (fine plane index for DEC, coarse for REC), nested one axis at a time
+  auto Q = [&](int p) {
+    const T *b = src + (int64_t)p * plane;
+    auto row = [&](int64_t o) { return od[3] ? wlo[3] * b[o + lo[3]] + whi[3] * b[o + hi[3]] : b[o + lo[3]]; };
+    auto pln = [&](int64_t o) { return od[2] ? wlo[2] * row(o + lo[2]) + whi[2] * row(o + hi[2]) : row(o + lo[2]); };
+    return od[1] ? wlo[1] * pln(lo[1]) + whi[1] * pln(hi[1]) : pln(lo[1]);
+  };
+  // level-centric offsets of the column in u_mc, and its output offset
+  auto lcp = [&](int jj, int k) { return (jj & 1) ? a.ax[k].c + (jj >> 1) : (jj >> 1); };
+  const int64_t ucol = (int64_t)lcp(j[1], 1) * a.up[1] + (int64_t)lcp(j[2], 2) * a.up[2] + lcp(j[3], 3);
+  const int64_t vcol = ((int64_t)j[1] * m2 + j[2]) * m3 + j[3];
+  const int64_t ocol = j[1] * a.op[1] + j[2] * a.op[2] + j[3];
+  const int cc0 = a.ax[0].c;
+  // decompose: store coefficient c at u_mc offset u (and / or its label)
+  auto put = [&](int64_t u, T c) {
+    if (!LAB || umc_w) umc_w[u] = c;
+    if (LAB) lab_w[u] = label4<T>(c, a.qc);
+  };
+  // recompose: the coefficient at u_mc offset u
+  auto get = [&](int64_t u) { return LAB ? unlabel4<T>(lab_r[u], a.qc) : umc_r[u]; };
+  // this chunk's pairs (even plane 2J, odd plane 2J+1), J0 <= J < J1; the
+  // last chunk also takes the last even plane
+  const int npair = cc0 - 1;
+  const int J0 = (int)blockIdx.y * a.jchunk;
+  const int J1 = min(npair, J0 + a.jchunk);
+  const bool last = J1 == npair;
+  T qprev = Q(DEC ? 2 * J0 : J0);
+  // two pairs per iteration so that the loads of both are in flight together
+  int J = J0;
+  auto pair = [&](int J) {
+    const int je = 2 * J;
+    const T qnext = Q(DEC ? je + 2 : J + 1);
+    const T ve = DEC ? V[je * plane + vcol] : (odd ? get((int64_t)J * a.up[0] + ucol) : T(0));
+    const int64_t u = (int64_t)(cc0 + J) * a.up[0] + ucol;
+    const T vo = DEC ? V[(je + 1) * plane + vcol] : get(u);
+    const T pred = a.ax[0].wl[je + 1] * qprev + a.ax[0].wr[je + 1] * qnext;
+    if (DEC) {
+      if (odd) put((int64_t)J * a.up[0] + ucol, ve - qprev);
+      put(u, vo - pred);
+    } else {
+      out[je * a.op[0] + ocol] = odd ? ve + qprev : qprev;
+      out[(je + 1) * a.op[0] + ocol] = vo + pred;
     }
-    int64_t pos = 0;
-#pragma unroll
-    for (int k = 0; k < 4; k++) {
-      const int p = (j[k] & 1) ? a.ax[k].c + (j[k] >> 1) : (j[k] >> 1);
-      pos += (k < 3) ? (int64_t)p * a.up[k] : (int64_t)p;
-    }
-    if (DEC)
-      a.umc_w[pos] = a.V[i] - pred;
-    else
-      a.out[j[0] * a.op[0] + j[1] * a.op[1] + j[2] * a.op[2] + j[3]] = a.umc_r[pos] + pred;
+    qprev = qnext;
+  };
+  for (; J + 1 < J1; J += 2) {
+    pair(J);
+    pair(J + 1);
+  }
+  for (; J < J1; J++) pair(J);
+  if (!last) return;
+  // the last (even) plane
+  const int je = 2 * J;
+  if (DEC) {
+    if (odd) put((int64_t)J * a.up[0] + ucol, V[je * plane + vcol] - qprev);
+  } else {
+    out[je * a.op[0] + ocol] = odd ? get((int64_t)J * a.up[0] + ucol) + qprev : qprev;
   }
 }
 
@@ -125,7 +196,8 @@ __global__ void __launch_bounds__(256) k_sweep4(Sweep4Args<T> a) {
         const int jj = 2 * J + d - 2;
         if (jj < 0 || jj >= a.m) continue;
         if (nodal_row && (jj & 1) == 0) continue;  // nodal node: component zero
-        acc += a.w5[5 * J + d] * a.umc[base + lc(jj, 3)];
+        const int64_t u = base + lc(jj, 3);
+        acc += a.w5[5 * J + d] * (a.lab ? unlabel4<T>(a.lab[u], a.qc) : a.umc[u]);
       }
     }
     a.out[i] = acc;
@@ -138,8 +210,11 @@ __global__ void __launch_bounds__(256) k_copy4(Copy4Args<T> a) {
   for (uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x; i < a.n; i += stride) {
     int j[4];
     split4((uint32_t)i, a.d3, a.d2, a.d1, j);
-    a.dst[j[0] * a.dp[0] + j[1] * a.dp[1] + j[2] * a.dp[2] + j[3]] =
-        a.src[j[0] * a.sp[0] + j[1] * a.sp[1] + j[2] * a.sp[2] + j[3]];
+    const int64_t si = j[0] * a.sp[0] + j[1] * a.sp[1] + j[2] * a.sp[2] + j[3];
+    const int64_t di = j[0] * a.dp[0] + j[1] * a.dp[1] + j[2] * a.dp[2] + j[3];
+    const T v = a.lab_r ? unlabel4<T>(a.lab_r[si], a.q) : a.src[si];
+    if (a.dst) a.dst[di] = v;
+    if (a.lab_w) a.lab_w[di] = label4<T>(v, a.q);
   }
 }
 
@@ -259,11 +334,17 @@ unsigned grid_for(uint64_t n) {
 
 template <typename T>
 hipError_t launch_coef4(Coef4Args<T> a, bool dec, hipStream_t st) {
-  if (a.n == 0) return hipSuccess;
-  if (dec)
-    hipLaunchKernelGGL((k_coef4<T, true>), dim3(grid_for(a.n)), dim3(256), 0, st, a);
+  if (a.ncol == 0) return hipSuccess;
+  if (a.jchunk < 1 || a.nchunk < 1) return hipErrorInvalidValue;
+  const dim3 grid((a.ncol + 255) / 256, a.nchunk);
+  if (dec && a.lab_w)
+    hipLaunchKernelGGL((k_coef4<T, true, true>), grid, dim3(256), 0, st, a);
+  else if (dec)
+    hipLaunchKernelGGL((k_coef4<T, true, false>), grid, dim3(256), 0, st, a);
+  else if (a.lab_r)
+    hipLaunchKernelGGL((k_coef4<T, false, true>), grid, dim3(256), 0, st, a);
   else
-    hipLaunchKernelGGL((k_coef4<T, false>), dim3(grid_for(a.n)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_coef4<T, false, false>), grid, dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

@@ -35,7 +35,7 @@ struct Axis4 {
 };
 
 // Coefficients of one level (decomposition) or its recomposition, one
-// thread per node of the level-l box.
+// thread per column (j1, j2, j3) of the level-l box, marching along axis 0.
 //   decompose: u_mc[lc(j)] = V(j) - Pi V(j) at every coefficient node j
 //   recompose: out(j) = u_mc[lc(j)] + Pi nodal(j) at coefficient nodes,
 //              out(j) = nodal(j / 2) at nodal nodes
@@ -50,8 +50,15 @@ struct Coef4Args {
   int64_t up[3];        // u_mc pitches of axes 0..2
   T *out;               // recompose: level-l box out
   int64_t op[3];        // its pitches
-  uint32_t n;           // m0 m1 m2 m3
-  Div32 d3, d2, d1;     // by m3, m2, m1
+  uint32_t ncol;        // m1 m2 m3
+  Div32 d3, d2;         // by m3, m2
+  int jchunk, nchunk;   // plane pairs per chunk of the march, chunks (nchunk * jchunk >= c0 - 1)
+  // quantization labels (u_mc's layout) of the level's coefficients, bin
+  // width qc: decompose writes them (umc_w may then be null), recompose reads
+  // them instead of u_mc
+  int32_t *lab_w;
+  const int32_t *lab_r;
+  double qc;
 };
 
 // One load-vector sweep R M along one axis: in (outer, m, inner) ->
@@ -74,9 +81,14 @@ struct Sweep4Args {
   int m1, m2;          // level box sizes of axes 1, 2
   int cc[4];           // level-(l-1) node counts (level-centric offsets of odd indices)
   Div32 dm2, dm1;      // by m2, m1
+  const int32_t *lab;  // non-null: read labels (times qc) instead of u_mc
+  double qc;
 };
 
-// 4-D box copy with pitches (axis 3 contiguous on both sides).
+// 4-D box copy with pitches (axis 3 contiguous on both sides).  With lab_r
+// the values are labels (at the source's positions) times q; with lab_w the
+// values' labels are written at the destination's positions (dst may then
+// be null).
 template <typename T>
 struct Copy4Args {
   const T *src;
@@ -86,6 +98,9 @@ struct Copy4Args {
   uint32_t n;          // b0 b1 b2 b3
   int b[4];
   Div32 d3, d2, d1;
+  const int32_t *lab_r;
+  int32_t *lab_w;
+  double q;
 };
 
 // Quantization of a 4-D u_mc (level-centric layout), Sec. 4.1: the level of
@@ -112,7 +127,7 @@ struct Pad4Args {
   Div32 d3, d2, d1;    // by the destination's dims 3, 2, 1
 };
 
-template <typename T> hipError_t launch_coef4(Coef4Args<T> a, bool dec, hipStream_t st);
+template <typename T> hipError_t launch_coef4(Coef4Args<T> a, bool dec, hipStream_t st);  // labels: a.lab_w / a.lab_r
 template <typename T> hipError_t launch_sweep4(Sweep4Args<T> a, bool gather, hipStream_t st);
 template <typename T> hipError_t launch_copy4(Copy4Args<T> a, hipStream_t st);
 template <typename T> hipError_t launch_quantize4(const T *umc, int32_t *labels, Quant4Args a, hipStream_t st);
