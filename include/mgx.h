@@ -8,8 +8,17 @@
  * Conventions shared by every entry point
  * ----------------------------------------
  * - Arrays are C order with shape dims[0] x ... x dims[ndim-1]; the last axis
- *   is contiguous.  1 <= ndim <= 3.  Every dims[k] must be 2^m + 1 with
- *   1 <= m <= 13 (3 <= n <= 8193).
+ *   is contiguous.  1 <= ndim <= 3, and ndim = 4 (four-axis fields such as
+ *   the QMCPACK data of Sec. 6, Table 2) where an entry point says so.  Every
+ *   dims[k] must be 2^m + 1 with 1 <= m <= 13 (3 <= n <= 8193); a 4-D field
+ *   has fewer than 2^32 nodes.
+ * - Four-axis fields: mgx_num_levels, mgx_workspace_size, mgx_decompose,
+ *   mgx_recompose, mgx_quantize, mgx_dequantize, mgx_quantize_levels,
+ *   mgx_dequantize_levels, mgx_decompose_quantize, mgx_dequantize_recompose,
+ *   mgx_linf_constant, mgx_level_tolerances (kappa = 4), mgx_dyadic_dims,
+ *   mgx_pad and mgx_crop accept ndim = 4; every other entry point returns
+ *   MGX_ERR_SHAPE for it.  The layouts, the level-centric order and the
+ *   tolerance schedule are those of 1-D to 3-D fields with four axes.
  * - The level count L = min_k m_k - 1: all axes coarsen together and the
  *   coarsest grid N_0 has 3 nodes on the shortest axis.  Level l keeps every
  *   2^(L-l)-th node of the input grid N_L (Sec. 2).
@@ -53,7 +62,7 @@ typedef enum { MGX_F32 = 0, MGX_F64 = 1 } mgx_dtype;
 typedef enum {
   MGX_OK = 0,
   MGX_ERR_ARG = 1,       /* null pointer, in/out aliasing, bad enum value      */
-  MGX_ERR_SHAPE = 2,     /* ndim not in [1,3] or some dims[k] != 2^m+1, 1<=m<=13 */
+  MGX_ERR_SHAPE = 2,     /* ndim not in [1,3] (or 4 where supported), or some dims[k] != 2^m+1, 1<=m<=13 */
   MGX_ERR_COORDS = 3,    /* non-finite or not strictly increasing coordinates  */
   MGX_ERR_LEVEL = 4,     /* stop_level outside [0, L]                          */
   MGX_ERR_TOL = 5,       /* tolerance not positive and finite, or 0 < C < 1    */
