@@ -364,6 +364,8 @@ def main():
     ap.add_argument("--rel-tol", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extensions", action="store_true", help="skip the batched and adjoint comparisons")
+    ap.add_argument("--four-d-only", action="store_true",
+                    help="run only the 4-D workload section (its own JSON line), e.g. under a profiler")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of the field (counter calibration)")
     args = ap.parse_args()
@@ -380,6 +382,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.four_d_only:
+        print(json.dumps({"four_d": four_d_section(torch, mgx, workloads, dev, args.steps)}), flush=True)
+        return
     n = args.n
     shape = (n, n, n)
     u = workloads.turbulence_field(n, device=dev, dtype=torch.float32)

@@ -20,12 +20,13 @@
 // whose boxes fit in LDS run in one workgroup (k_tail_dec / k_tail_rec).
 // Also here: the quantization passes, the adjoint's prolongation
 // (k_prolong_mass), the adaptive decomposition's estimate, the dummy-node
-// padding and the sort keys of the label entropy.
+// padding.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 
 #include "kernels.hpp"
+#include "levelpos.hpp"
 
 // Tuning parameters (compile-time; overridable with -D for measurements).
 #ifndef MGX_STENCIL_DEPTH
@@ -1434,47 +1435,10 @@ hipError_t launch_pad_edge(PadArgs<T> a, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// Quantization (Sec. 4.1): label = rint(c / q_l) in FP64.
-// The level of a position in the level-centric layout is the smallest l whose
-// box holds it.  Along an axis with n - 1 = 2^m, the level-l box has
-// 2^(m-L+l) + 1 nodes, so position p >= 2 lies in level
-// max(first, bitlength(p-1) - (m - L)); positions 0 and 1 are in every box.
-// The array is processed flat, four consecutive elements per thread.
+// Quantization (Sec. 4.1): label = rint(c / q_l) in FP64, the level of an
+// element from its position (levelpos.hpp).  The array is processed flat,
+// four consecutive elements per thread.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int pos_level(uint32_t p, int off, int first) {
-  if (p < 2) return first;
-  const int bl = 32 - __clz((int)(p - 1));
-  return max(first, bl - off);
-}
-
-__device__ __forceinline__ int elem_level(uint32_t idx, const QuantArgs &a) {
-  // idx = (z * n1 + y) * n2 + x, all < 2^32; divisions by precomputed magics
-  const uint32_t row = (uint32_t)__umul64hi((uint64_t)idx, a.mag2);
-  const uint32_t x = idx - row * (uint32_t)a.n2;
-  const uint32_t z = a.n1 == 1 ? row : (uint32_t)__umul64hi((uint64_t)row, a.mag1);
-  const uint32_t y = row - z * (uint32_t)a.n1;
-  int l = pos_level(x, a.off[2], a.first);
-  l = max(l, pos_level(y, a.off[1], a.first));
-  l = max(l, pos_level(z, a.off[0], a.first));
-  return l;
-}
-
-__global__ void __launch_bounds__(256) k_entropy_keys(const int32_t *__restrict__ labels, uint64_t *__restrict__ keys,
-                                                     QuantArgs a) {
-  for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * 256) {
-    const int l = elem_level((uint32_t)i, a);
-    keys[i] = ((uint64_t)(uint32_t)(l - a.first) << 32) | (uint64_t)((uint32_t)labels[i] ^ 0x80000000u);
-  }
-}
-
-hipError_t launch_entropy_keys(const int32_t *labels, uint64_t *keys, const QuantArgs &qa, hipStream_t st) {
-  int64_t blocks = (qa.n + 255) / 256;
-  if (blocks > 8192) blocks = 8192;
-  if (blocks < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_entropy_keys, dim3((unsigned)blocks), dim3(256), 0, st, labels, keys, qa);
-  return hipGetLastError();
-}
-
 // Four consecutive elements of T / int32 as one 16-byte (float, int32) or
 // two 16-byte (double) accesses when the buffers are 16-byte aligned.
 template <typename T, bool VEC>

@@ -249,9 +249,6 @@ union OpArgs {
 };
 
 template <typename T> hipError_t launch_adaptive_estimate(EstimateArgs<T> a, int nblocks, hipStream_t st);
-// Sort keys of the labels for their per-level histogram: (level - first) in
-// the high word, the label with its sign bit flipped in the low word.
-hipError_t launch_entropy_keys(const int32_t *labels, uint64_t *keys, const QuantArgs &qa, hipStream_t st);
 constexpr int kEstimateThreads = 256;
 
 // Workgroups of one op (fills the tile-grid fields of stencil ops); -1 when

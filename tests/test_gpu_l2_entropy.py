@@ -50,3 +50,21 @@ def test_entropy_workspace_errors():
         mgx.label_entropy(lab, 0, workspace=small)
     H = mgx.label_entropy(lab, 0)
     assert np.allclose(H, 0.0)
+
+
+@pytest.mark.parametrize("spread", [100, 2 ** 20, 2 ** 30])
+def test_entropy_histogram_and_sort_paths(spread):
+    """Labels whose per-level ranges fit the histogram (the two smaller
+    spreads) and ranges too wide for it (the radix-sort path, with the extreme
+    labels INT32_MIN and INT32_MAX), against the oracle."""
+    shape = (33, 65, 65)
+    rng = np.random.default_rng(spread)
+    lab = rng.integers(-spread, spread + 1, size=shape).astype(np.int64)
+    lab = (lab * rng.random(shape) ** 3).astype(np.int32)  # many small values, a few large ones
+    if spread > 2 ** 26:  # the extreme labels too (sort path)
+        lab.flat[5] = np.iinfo(np.int32).min
+        lab.flat[7] = np.iinfo(np.int32).max
+    for stop in (0, 3):
+        H = mgx.label_entropy(torch.as_tensor(lab, device="cuda"), stop)
+        Href = oracle.label_entropy(oracle.from_level_centric(lab, stop), stop)
+        assert np.allclose(H, Href, rtol=1e-12, atol=1e-12), (spread, stop, H, Href)
