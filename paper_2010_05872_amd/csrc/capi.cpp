@@ -1453,11 +1453,17 @@ Axis4<T> axis4(const AxisTab<T> &t) {
 
 // Chunks of the coefficient kernels' march along axis 0: about 16 M threads
 // in flight on large levels, at least 16 plane pairs per chunk.
+#ifndef MGX_MARCH_THREADS
+#define MGX_MARCH_THREADS (1 << 24)
+#endif
+#ifndef MGX_MARCH_MINPAIRS
+#define MGX_MARCH_MINPAIRS 16
+#endif
 template <typename T>
 void march_chunks(Coef4Args<T> &a, int64_t c0) {
   const int64_t npair = c0 - 1;
-  int64_t want = ((int64_t)1 << 24) / std::max<int64_t>(a.ncol, 1);
-  want = std::min<int64_t>(want, std::max<int64_t>(npair / 16, 1));
+  int64_t want = (int64_t)MGX_MARCH_THREADS / std::max<int64_t>(a.ncol, 1);
+  want = std::min<int64_t>(want, std::max<int64_t>(npair / MGX_MARCH_MINPAIRS, 1));
   want = std::max<int64_t>(want, 1);
   a.jchunk = (int)std::max<int64_t>((npair + want - 1) / want, 1);
   a.nchunk = npair > 0 ? (int)((npair + a.jchunk - 1) / a.jchunk) : 1;

@@ -324,9 +324,12 @@ __global__ void __launch_bounds__(256) k_pad4(Pad4Args<T> a) {
   }
 }
 
+#ifndef MGX_GRID4_MAX
+#define MGX_GRID4_MAX 65536
+#endif
 unsigned grid_for(uint64_t n) {
   uint64_t g = (n + 255) / 256;
-  if (g > 65536) g = 65536;
+  if (g > MGX_GRID4_MAX) g = MGX_GRID4_MAX;
   return (unsigned)(g > 0 ? g : 1);
 }
 
