@@ -28,7 +28,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "decompose+recompose GB/s on 513^3 fp32 + % HBM roofline; batched vs plain"
 HBM_PEAK_GBPS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_2010_05872_amd", "csrc", "kernels.hip")
+# the device code of the profiled 1-D to 3-D kernels: their source and the headers it includes
+KERNEL_SRC = tuple(os.path.join(ROOT, "paper_2010_05872_amd", "csrc", f)
+                   for f in ("kernels.hip", "kernels.hpp", "levelpos.hpp"))
 
 
 def level_sizes(shape, L, l):
@@ -74,11 +76,12 @@ def algorithmic_bytes(name, level, shape, L, s):
     return table[name] * s
 
 
-def kernel_source_sha(path=KERNEL_SRC):
-    """sha256 of the kernel source's code: comments dropped, whitespace collapsed
-    (a comment edit leaves the measured kernels, and so their counters, valid)."""
+def kernel_source_sha(paths=KERNEL_SRC):
+    """sha256 of the kernels' code (source and headers, in order): comments
+    dropped, whitespace collapsed (a comment edit leaves the measured kernels,
+    and so their counters, valid)."""
     import re
-    src = open(path).read()
+    src = "\n".join(open(p).read() for p in paths)
     src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
     src = re.sub(r"//[^\n]*", " ", src)
     src = " ".join(src.split())
