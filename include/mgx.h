@@ -13,11 +13,12 @@
  *   dims[k] must be 2^m + 1 with 1 <= m <= 13 (3 <= n <= 8193); a 4-D field
  *   has fewer than 2^32 nodes.
  * - Four-axis fields: mgx_num_levels, mgx_workspace_size, mgx_decompose,
- *   mgx_recompose, mgx_quantize, mgx_dequantize, mgx_quantize_levels,
- *   mgx_dequantize_levels, mgx_decompose_quantize, mgx_dequantize_recompose,
- *   mgx_linf_constant, mgx_level_tolerances (kappa = 4), mgx_dyadic_dims,
- *   mgx_pad and mgx_crop accept ndim = 4; every other entry point returns
- *   MGX_ERR_SHAPE for it.  The layouts, the level-centric order and the
+ *   mgx_recompose, mgx_recompose_to, mgx_quantize, mgx_dequantize,
+ *   mgx_quantize_levels, mgx_dequantize_levels, mgx_decompose_quantize,
+ *   mgx_dequantize_recompose, mgx_label_entropy,
+ *   mgx_label_entropy_workspace_size, mgx_linf_constant, mgx_level_tolerances
+ *   (kappa = 4), mgx_dyadic_dims, mgx_pad and mgx_crop accept ndim = 4; every
+ *   other entry point returns MGX_ERR_SHAPE for it.  The layouts, the level-centric order and the
  *   tolerance schedule are those of 1-D to 3-D fields with four axes.
  * - The level count L = min_k m_k - 1: all axes coarsen together and the
  *   coarsest grid N_0 has 3 nodes on the shortest axis.  Level l keeps every

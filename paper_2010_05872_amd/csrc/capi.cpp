@@ -1624,14 +1624,28 @@ mgx_status run_decompose4(const Plan4 &P, int stop, const T *u, T *umc, char *ws
 // coefficients (read from u_mc), the solves subtracting the correction from
 // the nodal values, then coefficients plus interpolant.
 // With labels, the coefficients are read as labels times their level's bin
-// width instead of from umc (which may then be null).
+// width instead of from umc (which may then be null).  top (progressive
+// recomposition): the last level recomposed, u then receives the compact
+// level-top box Q_top u; -1 means L.
 template <typename T>
 mgx_status run_recompose4(const Plan4 &P, int stop, const T *umc, T *u, char *ws, const Layout4 &lay,
-                          hipStream_t st, const int32_t *labels = nullptr, const Quant4Args *qa = nullptr) {
+                          hipStream_t st, const int32_t *labels = nullptr, const Quant4Args *qa = nullptr,
+                          int top = -1) {
   const int L = P.L;
   const int64_t N = P.count(L);
   int64_t up[3];
   compact_pitches(P.n, up);
+  if (top < 0) top = L;
+  if (top < L) {
+    // Q_top u: the recomposition stopped after level top, out compact
+    int64_t b[4], bp[3];
+    for (int k = 0; k < 4; k++) b[k] = P.m(stop, k);
+    compact_pitches(b, bp);
+    if (top == stop)  // the stop box itself
+      return copy4<T>(umc, up, u, bp, b, stop, st, labels, nullptr, labels ? qa->q[0] : 0.0) != hipSuccess
+                 ? MGX_ERR_HIP
+                 : MGX_OK;
+  }
   if (stop == L) {
     if (!labels) return hip_status(hipMemcpyAsync(u, umc, sizeof(T) * N, hipMemcpyDeviceToDevice, st));
     return copy4<T>(umc, up, u, up, P.n, L, st, labels, nullptr, qa->q[0]) != hipSuccess ? MGX_ERR_HIP : MGX_OK;
@@ -1644,7 +1658,7 @@ mgx_status run_recompose4(const Plan4 &P, int stop, const T *umc, T *u, char *ws
     if (copy4<T>(umc, up, D, bp, b, stop, st, labels, nullptr, labels ? qa->q[0] : 0.0) != hipSuccess)
       return MGX_ERR_HIP;
   }
-  for (int l = stop + 1; l <= L; l++) {
+  for (int l = stop + 1; l <= top; l++) {
     Level4<T> lv;
     mgx_status s = level4_tabs<T>(P, l, sizeof(T) == 8, &lv);
     if (s) return s;
@@ -1684,9 +1698,9 @@ mgx_status run_recompose4(const Plan4 &P, int stop, const T *umc, T *u, char *ws
       ca.qc = qa->q[l - stop];
     }
     for (int k = 0; k < 3; k++) ca.up[k] = up[k];
-    if (l == L) {
+    if (l == top) {
       ca.out = u;
-      for (int k = 0; k < 3; k++) ca.op[k] = up[k];
+      compact_pitches(m, ca.op);  // the level-top box (at top = L the whole field)
     } else {
       ca.out = D;
       compact_pitches(m, ca.op);
@@ -1877,6 +1891,23 @@ mgx_status mgx_recompose(const void *u_mc, void *u, mgx_dtype dtype, int ndim, c
 mgx_status mgx_recompose_to(const void *u_mc, void *u_t, mgx_dtype dtype, int ndim, const int64_t *dims,
                             const double *const *coords, int stop_level, int target_level, void *workspace,
                             size_t workspace_bytes, hipStream_t stream) {
+  if (ndim == 4) {
+    Plan4 P4;
+    Layout4 lay4;
+    mgx_status s4 = prepare4(u_mc, nullptr, dtype, dims, coords, stop_level, workspace, workspace_bytes, &P4, &lay4, 2);
+    if (s4) return s4;
+    if (target_level < stop_level || target_level > P4.L) return MGX_ERR_LEVEL;
+    if (!u_t) return MGX_ERR_ARG;
+    const size_t es = elem_size(dtype);
+    const size_t in_bytes = (size_t)P4.count(P4.L) * es, out_bytes = (size_t)P4.count(target_level) * es;
+    if (overlaps(u_t, out_bytes, u_mc, in_bytes) || (lay4.total > 0 && overlaps(u_t, out_bytes, workspace, lay4.total)))
+      return MGX_ERR_ARG;
+    if (dtype == MGX_F32)
+      return run_recompose4<float>(P4, stop_level, (const float *)u_mc, (float *)u_t, (char *)workspace, lay4, stream,
+                                   nullptr, nullptr, target_level);
+    return run_recompose4<double>(P4, stop_level, (const double *)u_mc, (double *)u_t, (char *)workspace, lay4,
+                                  stream, nullptr, nullptr, target_level);
+  }
   Plan *P;
   Layout lay;
   const void *tab;
@@ -2293,6 +2324,11 @@ mgx_status mgx_dequantize_levels(const int32_t *labels, void *u_mc, mgx_dtype dt
 }
 
 size_t mgx_label_entropy_workspace_size(int ndim, const int64_t *dims, int stop_level) {
+  if (ndim == 4) {
+    int L4;
+    if (parse_shape4(dims, &L4) || stop_level < 0 || stop_level > L4) return 0;
+    return entropy_workspace(dims[0] * dims[1] * dims[2] * dims[3], L4 + 1 - stop_level);
+  }
   int64_t n[3];
   bool real[3];
   int L;
@@ -2303,6 +2339,30 @@ size_t mgx_label_entropy_workspace_size(int ndim, const int64_t *dims, int stop_
 mgx_status mgx_label_entropy(const int32_t *labels, int ndim, const int64_t *dims, int stop_level, double *bits_out,
                              void *workspace, size_t workspace_bytes, hipStream_t stream) {
   if (!labels || !bits_out) return MGX_ERR_ARG;
+  if (ndim == 4) {
+    int L4;
+    int st4 = parse_shape4(dims, &L4);
+    if (st4) return (mgx_status)st4;
+    if (stop_level < 0 || stop_level > L4) return MGX_ERR_LEVEL;
+    const int64_t cnt4 = dims[0] * dims[1] * dims[2] * dims[3];
+    const size_t need4 = entropy_workspace(cnt4, L4 + 1 - stop_level);
+    if (need4 == 0) return MGX_ERR_SHAPE;
+    if (!workspace || workspace_bytes < need4) return MGX_ERR_WORKSPACE;
+    if (overlaps(workspace, need4, labels, (size_t)cnt4 * 4)) return MGX_ERR_ARG;
+    double ones4[kMaxLevels];
+    for (int i = 0; i < kMaxLevels; i++) ones4[i] = 1.0;
+    Quant4Args qa4;
+    mgx_status s4 = quant_args4(dims, nullptr, 1.0, stop_level, 0.0, ones4, &qa4);
+    if (s4) return s4;
+    Plan4 P4;
+    if ((s4 = get_plan4(dims, nullptr, &P4))) return s4;
+    int64_t count4[kMaxLevels], prev4 = 0;
+    for (int l = stop_level; l <= L4; l++) {
+      count4[l - stop_level] = P4.count(l) - prev4;
+      prev4 = P4.count(l);
+    }
+    return hip_status(label_entropy(labels, qa4, count4, (char *)workspace, stream, bits_out));
+  }
   int64_t n[3];
   bool real[3];
   int L;

@@ -19,6 +19,7 @@
 #include "entropy.hpp"
 #include "kernels.hpp"
 #include "levelpos.hpp"
+#include "levelpos4.hpp"
 
 namespace mgx {
 
@@ -44,7 +45,10 @@ unsigned grid_of(int64_t n) {
 }
 
 // Largest |label| of every level (an overflowed label, INT32_MIN, counts as 2^31).
-__global__ void __launch_bounds__(kThreads) k_ent_range(const int32_t *__restrict__ labels, QuantArgs a,
+// A: the (de)quantization arguments of a 1-D to 3-D (QuantArgs) or 4-D
+// (Quant4Args) field; elem_level(i, a) gives the level of flat element i.
+template <typename A>
+__global__ void __launch_bounds__(kThreads) k_ent_range(const int32_t *__restrict__ labels, A a,
                                                         unsigned *__restrict__ maxabs) {
   __shared__ unsigned s_max[kMaxLevelsK];
   if (threadIdx.x < kMaxLevelsK) s_max[threadIdx.x] = 0;
@@ -74,7 +78,8 @@ __global__ void __launch_bounds__(kThreads) k_ent_range(const int32_t *__restric
 }
 
 // Counts of the keys off[l] + label + maxabs[l] in [wb, wb + nb).
-__global__ void __launch_bounds__(kThreads) k_ent_hist(const int32_t *__restrict__ labels, QuantArgs a,
+template <typename A>
+__global__ void __launch_bounds__(kThreads) k_ent_hist(const int32_t *__restrict__ labels, A a,
                                                        const unsigned *__restrict__ maxabs, const int64_t *__restrict__ koff,
                                                        LdsMap lm, int64_t wb, int64_t nb, unsigned *__restrict__ hist) {
   __shared__ unsigned s_h[kLdsBins];
@@ -146,7 +151,8 @@ __global__ void __launch_bounds__(kThreads) k_ent_terms(const unsigned *__restri
 // ---- sort path ----
 // Keys (level - first) << 32 | label with its sign bit flipped: ascending key
 // order is level, then label.
-__global__ void __launch_bounds__(kThreads) k_ent_keys(const int32_t *__restrict__ labels, QuantArgs a,
+template <typename A>
+__global__ void __launch_bounds__(kThreads) k_ent_keys(const int32_t *__restrict__ labels, A a,
                                                        uint64_t *__restrict__ keys) {
   const uint64_t stride = (uint64_t)gridDim.x * kThreads;
   for (uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x; i < (uint64_t)a.n; i += stride) {
@@ -228,7 +234,8 @@ Parts carve(char *ws) {
 }
 
 // The sort path: sums of c log2 c per level into s.
-hipError_t sort_sums(const int32_t *labels, const QuantArgs &qa, const Parts &p, hipStream_t st, double *s) {
+template <typename A>
+hipError_t sort_sums(const int32_t *labels, const A &qa, const Parts &p, hipStream_t st, double *s) {
   const int64_t n = qa.n;
   const int nlev = qa.nlev;
   uint64_t *keys_a = (uint64_t *)p.big;
@@ -237,7 +244,7 @@ hipError_t sort_sums(const int32_t *labels, const QuantArgs &qa, const Parts &p,
   void *temp = p.big + 2 * align256((size_t)n * 8) + align256((size_t)n * 4);
   const size_t temp_bytes = sort_temp(n);
   hipError_t e;
-  hipLaunchKernelGGL(k_ent_keys, dim3(grid_of(n)), dim3(kThreads), 0, st, labels, qa, keys_a);
+  hipLaunchKernelGGL((k_ent_keys<A>), dim3(grid_of(n)), dim3(kThreads), 0, st, labels, qa, keys_a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   size_t tb = temp_bytes;
   if ((e = hipcub::DeviceRadixSort::SortKeys(temp, tb, keys_a, keys_b, (int)n, 0, 64, st)) != hipSuccess) return e;
@@ -285,13 +292,14 @@ size_t entropy_workspace(int64_t n, int nlev) {
   return small_bytes() + std::max(align256((size_t)kHistBins * 4), sort_bytes(n));
 }
 
-hipError_t label_entropy(const int32_t *labels, const QuantArgs &qa, const int64_t *level_count, char *ws,
-                         hipStream_t st, double *bits_out) {
+template <typename A>
+hipError_t label_entropy(const int32_t *labels, const A &qa, const int64_t *level_count, char *ws, hipStream_t st,
+                         double *bits_out) {
   const int nlev = qa.nlev;
   Parts p = carve(ws);
   hipError_t e;
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, p.maxabs, (int64_t)kMaxLevelsK);
-  hipLaunchKernelGGL(k_ent_range, dim3(grid_of(qa.n)), dim3(kThreads), 0, st, labels, qa, p.maxabs);
+  hipLaunchKernelGGL((k_ent_range<A>), dim3(grid_of(qa.n)), dim3(kThreads), 0, st, labels, qa, p.maxabs);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   std::vector<unsigned> mx(kMaxLevelsK);
   if ((e = hipMemcpyAsync(mx.data(), p.maxabs, sizeof(unsigned) * kMaxLevelsK, hipMemcpyDeviceToHost, st)) !=
@@ -328,8 +336,8 @@ hipError_t label_entropy(const int32_t *labels, const QuantArgs &qa, const int64
     unsigned *hist = (unsigned *)p.big;
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_of(R)), dim3(kThreads), 0, st, hist, R);
     const unsigned hb = std::min<unsigned>(grid_of(qa.n), kHistBlocks);
-    hipLaunchKernelGGL(k_ent_hist, dim3(hb), dim3(kThreads), 0, st, labels, qa, p.maxabs, p.koff, lm, (int64_t)0, R,
-                       hist);
+    hipLaunchKernelGGL((k_ent_hist<A>), dim3(hb), dim3(kThreads), 0, st, labels, qa, p.maxabs, p.koff, lm, (int64_t)0,
+                       R, hist);
     hipLaunchKernelGGL(k_ent_terms, dim3(kTermBlocks), dim3(kThreads), 0, st, hist, (int64_t)0, R, p.koff, nlev,
                        p.partial);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -346,5 +354,10 @@ hipError_t label_entropy(const int32_t *labels, const QuantArgs &qa, const int64
   }
   return hipSuccess;
 }
+
+template hipError_t label_entropy<QuantArgs>(const int32_t *, const QuantArgs &, const int64_t *, char *,
+                                             hipStream_t, double *);
+template hipError_t label_entropy<Quant4Args>(const int32_t *, const Quant4Args &, const int64_t *, char *,
+                                              hipStream_t, double *);
 
 }  // namespace mgx

@@ -1,16 +1,19 @@
-// Per-level Shannon entropy of quantization labels (sort-based histogram).
+// Per-level Shannon entropy of quantization labels.
 #pragma once
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 
 #include "kernels.hpp"
+#include "kernels4.hpp"
 
 namespace mgx {
 // Workspace bytes for n labels in nlev levels.
 size_t entropy_workspace(int64_t n, int nlev);
 // bits_out[i]: entropy in bits per label of level qa.first + i, whose label
-// count is level_count[i].  Synchronizes st.
-hipError_t label_entropy(const int32_t *labels, const QuantArgs &qa, const int64_t *level_count, char *ws,
-                         hipStream_t st, double *bits_out);
+// count is level_count[i].  Synchronizes st.  A: QuantArgs (1-D to 3-D) or
+// Quant4Args (4-D).
+template <typename A>
+hipError_t label_entropy(const int32_t *labels, const A &qa, const int64_t *level_count, char *ws, hipStream_t st,
+                         double *bits_out);
 }  // namespace mgx

@@ -20,6 +20,7 @@
 #include <cstdint>
 
 #include "kernels4.hpp"
+#include "levelpos4.hpp"
 
 namespace mgx {
 namespace {
@@ -37,21 +38,6 @@ template <typename T>
 __device__ __forceinline__ T unlabel4(int32_t l, double q) {
 #pragma clang fp contract(off)
   return (T)((double)l * q);
-}
-
-__device__ __forceinline__ uint32_t udiv(uint32_t n, const Div32 &v) {
-  return v.d == 1 ? n : (uint32_t)__umul64hi((uint64_t)n, v.mag);
-}
-
-// Axis indices of flat index i of a box whose dims 3, 2, 1 divide as d3, d2, d1.
-__device__ __forceinline__ void split4(uint32_t i, const Div32 &d3, const Div32 &d2, const Div32 &d1, int j[4]) {
-  const uint32_t r = udiv(i, d3);
-  j[3] = (int)(i - r * d3.d);
-  const uint32_t r2 = udiv(r, d2);
-  j[2] = (int)(r - r2 * d2.d);
-  const uint32_t r3 = udiv(r2, d1);
-  j[1] = (int)(r2 - r3 * d1.d);
-  j[0] = (int)r3;
 }
 
 // One thread per column (j1, j2, j3) of the level box and chunk of plane
@@ -218,23 +204,6 @@ __global__ void __launch_bounds__(256) k_copy4(Copy4Args<T> a) {
   }
 }
 
-// Level of position p along an axis with n - 1 = 2^(L + off): the smallest
-// level whose box (2^(l + off) + 1 nodes) holds it, at least `first`.
-__device__ __forceinline__ int axis_pos_level(uint32_t p, int off, int first) {
-  if (p < 2) return first;
-  const int bl = 32 - __clz((int)(p - 1));
-  return max(first, bl - off);
-}
-
-__device__ __forceinline__ int level4(uint32_t i, const Quant4Args &a) {
-  int j[4];
-  split4(i, a.d3, a.d2, a.d1, j);
-  int l = a.first;
-#pragma unroll
-  for (int k = 0; k < 4; k++) l = max(l, axis_pos_level((uint32_t)j[k], a.off[k], a.first));
-  return l;
-}
-
 template <typename T>
 __global__ void __launch_bounds__(256) k_quantize4(const T *__restrict__ umc, int32_t *__restrict__ labels,
                                                    Quant4Args a) {
@@ -255,7 +224,7 @@ __global__ void __launch_bounds__(256) k_quantize4(const T *__restrict__ umc, in
   for (uint64_t b0 = (uint64_t)blockIdx.x * 256u; b0 < a.n; b0 += stride) {
     const uint64_t i = b0 + threadIdx.x;
     const bool in = i < a.n;
-    const int l = in ? level4((uint32_t)i, a) : a.first;
+    const int l = in ? elem_level((uint32_t)i, a) : a.first;
     int absl = 0;
     if (in) {
       const double t = (double)umc[i] / s_q[l - a.first];
@@ -306,7 +275,7 @@ __global__ void __launch_bounds__(256) k_dequantize4(const int32_t *__restrict__
   __syncthreads();
   const uint64_t stride = (uint64_t)gridDim.x * 256u;
   for (uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x; i < a.n; i += stride) {
-    const int l = level4((uint32_t)i, a);
+    const int l = elem_level((uint32_t)i, a);
     umc[i] = (T)((double)labels[i] * s_q[l - a.first]);
   }
 }

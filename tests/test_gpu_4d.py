@@ -184,3 +184,35 @@ def test_back_to_back_smaller_4d():
         scale = float(u.abs().max())
         assert np.abs(g.double().cpu().numpy() - ref).max() <= 1e-5 * scale
         assert (r.double() - u.double()).abs().max().item() <= 1e-5 * scale
+
+
+@pytest.mark.parametrize("stop", [0, 1])
+def test_progressive_and_entropy_4d(stop):
+    """Progressive recomposition of a 4-D field to every level t (Q_t u on the
+    level-t grid) and the per-level label entropy, against the oracle."""
+    shape = (17, 9, 33, 17)
+    _say(f"[4d progressive+entropy] {shape} stop {stop}")
+    coords = make_coords(shape, "random", 3)
+    u = make_field(shape, seed=4)
+    ud = torch.as_tensor(u, dtype=torch.float64, device="cuda")
+    scale = np.abs(u).max()
+    L = mgx.num_levels(shape)
+    g = mgx.decompose(ud, coords, stop)
+    g64 = oracle.from_level_centric(g.cpu().numpy(), stop)
+    for t in range(stop, L + 1):
+        got = mgx.recompose_to(g, t, coords, stop)
+        torch.cuda.synchronize()
+        want = oracle.recompose_to(g64, t, coords, stop)
+        assert got.shape == want.shape
+        assert np.abs(got.cpu().numpy() - want).max() <= 1e-12 * scale, t
+    tol = 1e-3 * float(u.max() - u.min())
+    lab = mgx.quantize(g, tol, coords, stop)
+    H = mgx.label_entropy(lab, stop)
+    Href = oracle.label_entropy(oracle.from_level_centric(lab.cpu().numpy(), stop), stop)
+    assert np.allclose(H, Href, rtol=1e-12, atol=1e-12), (H, Href)
+    # labels too wide for the histogram: the sort path
+    rng = np.random.default_rng(stop)
+    wide = (rng.integers(-2 ** 30, 2 ** 30, size=shape) * rng.random(shape) ** 3).astype(np.int32)
+    H = mgx.label_entropy(torch.as_tensor(wide, device="cuda"), stop)
+    Href = oracle.label_entropy(oracle.from_level_centric(wide, stop), stop)
+    assert np.allclose(H, Href, rtol=1e-12, atol=1e-12), (H, Href)
