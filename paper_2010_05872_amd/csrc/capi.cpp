@@ -1698,13 +1698,8 @@ mgx_status run_recompose4(const Plan4 &P, int stop, const T *umc, T *u, char *ws
       ca.qc = qa->q[l - stop];
     }
     for (int k = 0; k < 3; k++) ca.up[k] = up[k];
-    if (l == top) {
-      ca.out = u;
-      compact_pitches(m, ca.op);  // the level-top box (at top = L the whole field)
-    } else {
-      ca.out = D;
-      compact_pitches(m, ca.op);
-    }
+    ca.out = l == top ? u : D;  // the level-top box (at top = L the whole field) or the next level's nodal box
+    compact_pitches(m, ca.op);
     ca.ncol = (uint32_t)(m[1] * m[2] * m[3]);
     ca.d3 = make_div32((uint32_t)m[3]);
     ca.d2 = make_div32((uint32_t)m[2]);
