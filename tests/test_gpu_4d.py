@@ -53,6 +53,8 @@ CASES = [
     ((9, 9, 5, 257), torch.float32, "random"),  # 129-long contiguous solves
     ((513, 5, 5, 5), torch.float32, None),      # 257-long axis-0 lines (two-ended solve)
     ((513, 5, 5, 5), torch.float64, "random"),  # the same in fp64 (chunked sweeps)
+    ((8193, 5, 5, 5), torch.float32, None),     # longest axis 0: 256 march chunks, 4097-long chunked solves
+    ((5, 5, 5, 8193), torch.float64, "random"),  # longest contiguous axis: 4097-long wave-scan solves
 ]
 
 
