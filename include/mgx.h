@@ -150,9 +150,12 @@ mgx_status mgx_dequantize_levels(const int32_t *labels, void *u_mc, mgx_dtype dt
  * the estimated cost of storing the labels): bits_out[l - stop_level] =
  * -sum_k p_k log2 p_k over the distinct labels k of level l (the stop
  * level's whole box counts as one level), host, L + 1 - stop_level entries.
- * labels: device, level-centric layout of that stop level.  Workspace:
- * mgx_label_entropy_workspace_size bytes (about 20 bytes per label), must
- * not overlap labels.  Synchronizes `stream`.
+ * labels: device, level-centric layout of that stop level.  The counts come
+ * from one histogram pass when the levels' label ranges (2 max|label| + 1
+ * each) add up to at most 2^26; wider ranges are counted by a radix sort of
+ * (level, label) keys.  Workspace: mgx_label_entropy_workspace_size bytes
+ * (enough for either: about 20 bytes per label, at least 256 MiB), must not
+ * overlap labels.  Synchronizes `stream`.
  * Errors: MGX_ERR_ARG, _SHAPE, _LEVEL, _WORKSPACE, _HIP. */
 mgx_status mgx_label_entropy(const int32_t *labels, int ndim, const int64_t *dims, int stop_level, double *bits_out,
                              void *workspace, size_t workspace_bytes, hipStream_t stream);
