@@ -1483,6 +1483,12 @@ hipError_t sweep4(const char *name, const AxisTab<T> &t, const T *in, T *out, in
   a.inner = (uint32_t)inner;
   a.dinner = make_div32((uint32_t)inner);
   a.dc = make_div32((uint32_t)t.c);
+  // march form: about MGX_MARCH_THREADS threads, at least 8 outputs per chunk
+  const int64_t ncol = outer * inner;
+  int64_t want = std::max<int64_t>((int64_t)MGX_MARCH_THREADS / std::max<int64_t>(ncol, 1), 1);
+  want = std::min<int64_t>(want, std::max<int64_t>(t.c / 8, 1));
+  a.jchunk = (int)((t.c + want - 1) / want);
+  a.nchunk = (int)((t.c + a.jchunk - 1) / a.jchunk);
   return traced(name, level, st, [&] { return launch_sweep4<T>(a, false, st); });
 }
 

@@ -190,6 +190,41 @@ __global__ void __launch_bounds__(256) k_sweep4(Sweep4Args<T> a) {
   }
 }
 
+// The same sweep as one march per (o, i) column along the axis (inner >=
+// kSweepMarchInner: consecutive threads on consecutive i, coalesced): output J
+// needs inputs 2J-2 .. 2J+2, of which 2J-2 .. 2J carry over from output J-1,
+// so each input row is read once per chunk (plus two rows at its start).
+template <typename T>
+__global__ void __launch_bounds__(256) k_sweep4_march(Sweep4Args<T> a) {
+  const uint64_t col = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+  const uint64_t ncol = (uint64_t)a.n / (uint64_t)a.c;  // outer * inner
+  if (col >= ncol) return;
+  const uint32_t o = udiv((uint32_t)col, a.dinner);
+  const uint32_t ii = (uint32_t)col - o * a.inner;
+  const T *__restrict__ row = a.in + (int64_t)o * a.m * a.inner + ii;
+  T *__restrict__ out = a.out + (int64_t)o * a.c * a.inner + ii;
+  const T *__restrict__ w5 = a.w5;
+  const int64_t inner = a.inner;
+  const int m = a.m;
+  auto x = [&](int j) { return (j >= 0 && j < m) ? row[(int64_t)j * inner] : T(0); };
+  const int J0 = (int)blockIdx.y * a.jchunk, J1 = min(a.c, J0 + a.jchunk);
+  T xm2 = x(2 * J0 - 2), xm1 = x(2 * J0 - 1), x0 = x(2 * J0);
+  for (int J = J0; J < J1; J++) {
+    const T x1 = x(2 * J + 1), x2 = x(2 * J + 2);
+    const T *w = w5 + 5 * J;
+    T acc = T(0);
+    if (2 * J - 2 >= 0) acc += w[0] * xm2;
+    if (2 * J - 1 >= 0) acc += w[1] * xm1;
+    acc += w[2] * x0;
+    if (2 * J + 1 < m) acc += w[3] * x1;
+    if (2 * J + 2 < m) acc += w[4] * x2;
+    out[(int64_t)J * inner] = acc;
+    xm2 = x0;
+    xm1 = x1;
+    x0 = x2;
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_copy4(Copy4Args<T> a) {
   const uint64_t stride = (uint64_t)gridDim.x * 256u;
@@ -323,6 +358,12 @@ hipError_t launch_coef4(Coef4Args<T> a, bool dec, hipStream_t st) {
 template <typename T>
 hipError_t launch_sweep4(Sweep4Args<T> a, bool gather, hipStream_t st) {
   if (a.n == 0) return hipSuccess;
+  if (!gather && a.inner >= (uint32_t)kSweepMarchInner) {
+    if (a.jchunk < 1 || a.nchunk < 1 || (int64_t)a.jchunk * a.nchunk < a.c) return hipErrorInvalidValue;
+    const uint64_t ncol = (uint64_t)a.n / (uint64_t)a.c;
+    hipLaunchKernelGGL((k_sweep4_march<T>), dim3((unsigned)((ncol + 255) / 256), a.nchunk), dim3(256), 0, st, a);
+    return hipGetLastError();
+  }
   if (gather)
     hipLaunchKernelGGL((k_sweep4<T, true>), dim3(grid_for(a.n)), dim3(256), 0, st, a);
   else

@@ -83,7 +83,11 @@ struct Sweep4Args {
   Div32 dm2, dm1;      // by m2, m1
   const int32_t *lab;  // non-null: read labels (times qc) instead of u_mc
   double qc;
+  // march form (inner >= kSweepMarchInner, no gather): one thread per (o, i)
+  // column and chunk of jchunk outputs along the axis
+  int jchunk, nchunk;
 };
+constexpr int kSweepMarchInner = 32;
 
 // 4-D box copy with pitches (axis 3 contiguous on both sides).  With lab_r
 // the values are labels (at the source's positions) times q; with lab_w the
