@@ -22,6 +22,11 @@
 #include "kernels4.hpp"
 #include "levelpos4.hpp"
 
+// plane pairs per iteration of the coefficient kernels' march
+#ifndef MGX_MARCH_UNROLL
+#define MGX_MARCH_UNROLL 1
+#endif
+
 namespace mgx {
 namespace {
 
@@ -118,7 +123,8 @@ __global__ void __launch_bounds__(256) k_coef4(Coef4Args<T> a) {
   const int J1 = min(npair, J0 + a.jchunk);
   const bool last = J1 == npair;
   T qprev = Q(DEC ? 2 * J0 : J0);
-  // two pairs per iteration so that the loads of both are in flight together
+  // MGX_MARCH_UNROLL pairs per iteration (unrolling measured slower for the
+  // recomposition kernel, equal for the decomposition)
   int J = J0;
   auto pair = [&](int J) {
     const int je = 2 * J;
@@ -136,9 +142,9 @@ __global__ void __launch_bounds__(256) k_coef4(Coef4Args<T> a) {
     }
     qprev = qnext;
   };
-  for (; J + 1 < J1; J += 2) {
-    pair(J);
-    pair(J + 1);
+  for (; J + MGX_MARCH_UNROLL - 1 < J1; J += MGX_MARCH_UNROLL) {
+#pragma unroll
+    for (int k = 0; k < MGX_MARCH_UNROLL; k++) pair(J + k);
   }
   for (; J < J1; J++) pair(J);
   if (!last) return;
