@@ -851,6 +851,39 @@ StatsBuf &stats_buf() {
   return *s;
 }
 
+// The statistics buffer of the current device (per-level max |label| and the
+// out-of-range counts), cleared on `stream`; nullptr on a HIP error.  The
+// caller holds stats_buf().mu until it has read the buffer back.
+char *stats_device(hipStream_t stream) {
+  StatsBuf &sb = stats_buf();
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  if ((int)sb.per_dev.size() <= dev) sb.per_dev.resize(dev + 1, nullptr);
+  const size_t sbytes = sizeof(int) * kMaxLevels + 2 * sizeof(unsigned long long);
+  if (!sb.per_dev[dev] && hipMalloc(&sb.per_dev[dev], sbytes) != hipSuccess) return nullptr;
+  if (hipMemsetAsync(sb.per_dev[dev], 0, sbytes, stream) != hipSuccess) return nullptr;
+  return (char *)sb.per_dev[dev];
+}
+
+// Waits for `stream` and fills *stats from the buffer; MGX_ERR_RANGE when some
+// label overflowed or some coefficient was not finite.
+mgx_status stats_read(const char *base, int first, int nlev, mgx_quant_stats *stats, hipStream_t stream) {
+  const size_t sbytes = sizeof(int) * kMaxLevels + 2 * sizeof(unsigned long long);
+  char host[sizeof(int) * kMaxLevels + 2 * sizeof(unsigned long long)];
+  if (hipMemcpyAsync(host, base, sbytes, hipMemcpyDeviceToHost, stream) != hipSuccess) return MGX_ERR_HIP;
+  if (hipStreamSynchronize(stream) != hipSuccess) return MGX_ERR_HIP;
+  std::memset(stats, 0, sizeof(*stats));
+  stats->first_level = first;
+  stats->num_levels = nlev;
+  std::memcpy(stats->max_abs_label, host, sizeof(int) * nlev);
+  unsigned long long ovf, nan;
+  std::memcpy(&ovf, host + sizeof(int) * kMaxLevels, sizeof(ovf));
+  std::memcpy(&nan, host + sizeof(int) * kMaxLevels + sizeof(ovf), sizeof(nan));
+  stats->n_overflow = (int64_t)ovf;
+  stats->n_nonfinite = (int64_t)nan;
+  return (ovf || nan) ? MGX_ERR_RANGE : MGX_OK;
+}
+
 // The corner box of a level (level L-1: the coarser levels' coefficients)
 // as the visited region of a quantization pass.
 void quant_box(const Plan *P, QuantArgs &qa, int level = -1) {
@@ -2168,36 +2201,18 @@ static mgx_status quantize4_common(const void *u_mc, int32_t *labels, mgx_dtype 
     });
     return hip_status(e);
   }
-  StatsBuf &sb = stats_buf();
-  std::lock_guard<std::mutex> g(sb.mu);
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return MGX_ERR_HIP;
-  if ((int)sb.per_dev.size() <= dev) sb.per_dev.resize(dev + 1, nullptr);
-  const size_t sbytes = sizeof(int) * kMaxLevels + 2 * sizeof(unsigned long long);
-  if (!sb.per_dev[dev] && hipMalloc(&sb.per_dev[dev], sbytes) != hipSuccess) return MGX_ERR_HIP;
-  char *base = (char *)sb.per_dev[dev];
+  std::lock_guard<std::mutex> g(stats_buf().mu);
+  char *base = stats_device(stream);
+  if (!base) return MGX_ERR_HIP;
   qa.stats_max = (int *)base;
   qa.stats_ovf = (unsigned long long *)(base + sizeof(int) * kMaxLevels);
   qa.stats_nan = qa.stats_ovf + 1;
-  if (hipMemsetAsync(base, 0, sbytes, stream) != hipSuccess) return MGX_ERR_HIP;
   hipError_t e = traced("quantize4_stats", -1, stream, [&] {
     return dtype == MGX_F32 ? launch_quantize4<float>((const float *)u_mc, labels, qa, stream)
                             : launch_quantize4<double>((const double *)u_mc, labels, qa, stream);
   });
   if (e != hipSuccess) return MGX_ERR_HIP;
-  char host[sizeof(int) * kMaxLevels + 2 * sizeof(unsigned long long)];
-  if (hipMemcpyAsync(host, base, sbytes, hipMemcpyDeviceToHost, stream) != hipSuccess) return MGX_ERR_HIP;
-  if (hipStreamSynchronize(stream) != hipSuccess) return MGX_ERR_HIP;
-  std::memset(stats, 0, sizeof(*stats));
-  stats->first_level = qa.first;
-  stats->num_levels = qa.nlev;
-  std::memcpy(stats->max_abs_label, host, sizeof(int) * qa.nlev);
-  unsigned long long ovf, nan;
-  std::memcpy(&ovf, host + sizeof(int) * kMaxLevels, sizeof(ovf));
-  std::memcpy(&nan, host + sizeof(int) * kMaxLevels + sizeof(ovf), sizeof(nan));
-  stats->n_overflow = (int64_t)ovf;
-  stats->n_nonfinite = (int64_t)nan;
-  return (ovf || nan) ? MGX_ERR_RANGE : MGX_OK;
+  return stats_read(base, qa.first, qa.nlev, stats, stream);
 }
 
 static mgx_status quantize_common(const void *u_mc, int32_t *labels, mgx_dtype dtype, int ndim,
@@ -2226,36 +2241,18 @@ static mgx_status quantize_common(const void *u_mc, int32_t *labels, mgx_dtype d
     });
     return hip_status(e);
   }
-  StatsBuf &sb = stats_buf();
-  std::lock_guard<std::mutex> g(sb.mu);
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return MGX_ERR_HIP;
-  if ((int)sb.per_dev.size() <= dev) sb.per_dev.resize(dev + 1, nullptr);
-  const size_t sbytes = sizeof(int) * kMaxLevels + 2 * sizeof(unsigned long long);
-  if (!sb.per_dev[dev] && hipMalloc(&sb.per_dev[dev], sbytes) != hipSuccess) return MGX_ERR_HIP;
-  char *base = (char *)sb.per_dev[dev];
+  std::lock_guard<std::mutex> g(stats_buf().mu);
+  char *base = stats_device(stream);
+  if (!base) return MGX_ERR_HIP;
   qa.stats_max = (int *)base;
   qa.stats_ovf = (unsigned long long *)(base + sizeof(int) * kMaxLevels);
   qa.stats_nan = qa.stats_ovf + 1;
-  if (hipMemsetAsync(base, 0, sbytes, stream) != hipSuccess) return MGX_ERR_HIP;
   hipError_t e = traced("quantize_stats", -1, stream, [&] {
     return dtype == MGX_F32 ? launch_quantize<float>((const float *)u_mc, labels, qa, true, stream)
                             : launch_quantize<double>((const double *)u_mc, labels, qa, true, stream);
   });
   if (e != hipSuccess) return MGX_ERR_HIP;
-  char host[sizeof(int) * kMaxLevels + 2 * sizeof(unsigned long long)];
-  if (hipMemcpyAsync(host, base, sbytes, hipMemcpyDeviceToHost, stream) != hipSuccess) return MGX_ERR_HIP;
-  if (hipStreamSynchronize(stream) != hipSuccess) return MGX_ERR_HIP;
-  std::memset(stats, 0, sizeof(*stats));
-  stats->first_level = qa.first;
-  stats->num_levels = qa.nlev;
-  std::memcpy(stats->max_abs_label, host, sizeof(int) * qa.nlev);
-  unsigned long long ovf, nan;
-  std::memcpy(&ovf, host + sizeof(int) * kMaxLevels, sizeof(ovf));
-  std::memcpy(&nan, host + sizeof(int) * kMaxLevels + sizeof(ovf), sizeof(nan));
-  stats->n_overflow = (int64_t)ovf;
-  stats->n_nonfinite = (int64_t)nan;
-  return (ovf || nan) ? MGX_ERR_RANGE : MGX_OK;
+  return stats_read(base, qa.first, qa.nlev, stats, stream);
 }
 
 static mgx_status dequantize_common(const int32_t *labels, void *u_mc, mgx_dtype dtype, int ndim,
