@@ -374,8 +374,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not "
-                                   "part of this build (fields shard across GPUs without exchange)"}))
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; runs on several GPUs are not "
+                                   "supported (fields shard across GPUs without exchange)"}))
         sys.exit(2)
 
     import torch

@@ -173,7 +173,7 @@ __device__ __forceinline__ float label_rcp(double q) {
 // single FMA (its rounding cannot turn a sum >= 0.5 into one below), it
 // fails for |t| >= 2^20 (labels stay far inside int32) and for non-finite
 // t; there *ok is false and the FP64 division decides.  Relies on IEEE
-// subnormals (no flush to zero in this build).
+// subnormals (the kernels are compiled without flush to zero).
 __device__ __forceinline__ int32_t label_fast(float v, float rq, bool &ok) {
   const float t = v * rq;
   const float r = rintf(t);
