@@ -276,7 +276,9 @@ def entropy_section(torch, mgx, u, labels, tol, reps):
     """Per-level entropy of the step's labels (L-infinity schedule) and the
     estimated size of the labels in bits per value (Sec. 4.1's cost
     estimate), with the time of the entropy pass; the same for the L2
-    schedule at the same tolerance with C_L2 = 1 (the paper prints no C_L2)."""
+    schedule with the library's default C_L2, at an L2 tolerance whose
+    root-mean-square error over the domain equals the L-infinity tolerance
+    (tau_L2 = tol * sqrt(|Omega|), |Omega| = 512^3 on unit spacing)."""
     L = mgx.num_levels(u.shape)
     counts, prev = [], 0
     for l in range(L + 1):
@@ -291,11 +293,16 @@ def entropy_section(torch, mgx, u, labels, tol, reps):
     ms = timed(torch, lambda: mgx.label_entropy(labels, 0, workspace=ws), reps)
     bits = float(sum(c * h for c, h in zip(counts, H)) / u.numel())
     umc = mgx.decompose(u)
-    tau2 = mgx.level_tolerances_l2(u.shape, tol, 1.0)
+    vol = 1.0
+    for n in u.shape:
+        vol *= n - 1
+    tol_l2 = tol * vol ** 0.5
+    tau2 = mgx.level_tolerances_l2(u.shape, tol_l2)
     H2 = mgx.label_entropy(mgx.quantize_levels(umc, tau2), 0, workspace=ws)
     bits2 = float(sum(c * h for c, h in zip(counts, H2)) / u.numel())
     return {"linf_bits_per_level": [round(float(h), 4) for h in H], "linf_bits_per_value": round(bits, 4),
-            "l2_bits_per_value_c1": round(bits2, 4), "entropy_ms": round(ms, 3)}
+            "l2_c": mgx.l2_constant(u.shape), "l2_tol_over_sqrt_volume": tol,
+            "l2_bits_per_value": round(bits2, 4), "entropy_ms": round(ms, 3)}
 
 
 def four_d_section(torch, mgx, workloads, dev, reps):

@@ -130,8 +130,9 @@ mgx_status mgx_recompose(const void *u_mc, void *u, mgx_dtype dtype, int ndim,
  * widths under the L2 error budget): tau_l = tol_l2 / sqrt(c_l2 h_l^d #N_L)
  * for l = stop_level .. L (tau_out[l - stop_level], host), so that
  * sum_l #N*_l h_l^d tau_l^2 = tol_l2^2 / c_l2.  h_l^d is the level's cell
- * volume (extent / intervals on every real axis).  The paper does not print
- * C_L2: c_l2 > 0 must be given.  Errors: MGX_ERR_TOL, _LEVEL, _SHAPE, _COORDS. */
+ * volume (extent / intervals on every real axis).  c_l2 <= 0 takes
+ * mgx_l2_constant.  Errors: MGX_ERR_TOL (tol_l2 not positive and finite,
+ * c_l2 not finite), _LEVEL, _SHAPE, _COORDS. */
 mgx_status mgx_level_tolerances_l2(int ndim, const int64_t *dims, const double *const *coords, double tol_l2,
                                    int stop_level, double c_l2, double *tau_out);
 
@@ -390,6 +391,18 @@ mgx_status mgx_dequantize(const int32_t *labels, void *u_mc, mgx_dtype dtype, in
  * Host, synchronous.  Returns a negative value on invalid arguments. */
 double mgx_linf_constant(int ndim, const int64_t *dims, const double *const *coords,
                          int stop_level);
+
+/* The default C_{L^2} of the L2 estimator (Sec. 4.1, eq. (L2NormEstimator)),
+ * which the paper cites without printing.  The quantization error of level l
+ * recomposes to (I - Q_{l-1}) e_l (e_l the level-l interpolant of the
+ * level's coefficient errors; e_l itself on the stop box); these pieces are
+ * L2-orthogonal across levels and I - Q_{l-1} does not increase the norm, so
+ * ||u - u~||^2 <= sum_l lambda_max(M_l) sum |delta_l|^2.  Bounding
+ * lambda_max(M_l) by the product of the axes' largest mass-matrix row sums,
+ * max_j (h_{j-1} + h_j) / 2, gives C = max over levels l~ <= l <= L of that
+ * product over h_l^d (the cell volume of mgx_level_tolerances_l2): exactly 1
+ * on uniform grids.  Host, synchronous; negative on invalid arguments. */
+double mgx_l2_constant(int ndim, const int64_t *dims, const double *const *coords, int stop_level);
 
 /* tau_out[0 .. L-l~] = tolerances of levels l~ ... L as used by
  * mgx_quantize.  Host, synchronous. */

@@ -170,12 +170,46 @@ def pad_to_dyadic(u):
     return np.pad(u, [(0, p - n) for n, p in zip(u.shape, dyadic_shape(u.shape))], mode="edge")
 
 
-def level_tolerances_l2(shape, tol_l2, c_l2, coords=None, stop_level=0) -> np.ndarray:
-    """L2 variant of Sec. 4.1: tau_l = tol / sqrt(C_L2 h_l^d #N_L), h_l^d the level's
-    cell volume (extent / intervals per axis), levels stop_level .. L."""
+def _axis_coords(shape, coords):
+    return [np.arange(n, dtype=np.float64) if (coords is None or coords[k] is None)
+            else np.asarray(coords[k], dtype=np.float64) for k, n in enumerate(shape)]
+
+
+def l2_constant(shape, coords=None, stop_level=0) -> float:
+    """A computable C_L2 for the L2 estimator of Sec. 4.1 (the paper cites the
+    constant without printing it).  The quantization error of level l lives in
+    the piecewise multilinear space of N_l: its recomposed error is
+    (I - Q_{l-1}) e_l for l > stop (e_l interpolating the level's coefficient
+    errors, zero on N_{l-1}) and e_stop itself on the stop box.  These pieces
+    are L2-orthogonal across levels and I - Q_{l-1} does not increase the L2
+    norm, so ||u - u~||^2 <= sum_l ||e_l||^2 <= sum_l lambda_max(M_l) |delta_l|^2
+    with M_l the level's mass matrix.  lambda_max(M_l) is bounded by the
+    product over the axes of the largest row sum of the 1-D mass matrix,
+    max_j (h_{j-1} + h_j) / 2, so the estimator holds with
+    C = max_l prod_k rowsum_k(l) / h_l^d, h_l^d the cell volume of reading
+    15 (extent / intervals per axis).  Equal to 1 on uniform grids."""
     L = num_levels(shape)
-    Xs = [np.arange(n, dtype=np.float64) if (coords is None or coords[k] is None)
-          else np.asarray(coords[k], dtype=np.float64) for k, n in enumerate(shape)]
+    Xs = _axis_coords(shape, coords)
+    best = 0.0
+    for l in range(int(stop_level), L + 1):
+        ratio = 1.0
+        for X, n in zip(Xs, shape):
+            Y = X[:: 2 ** (L - l)]
+            h = np.diff(Y)
+            rows = np.concatenate(([h[0]], h[:-1] + h[1:], [h[-1]])) / 2.0
+            ratio *= rows.max() / ((Y[-1] - Y[0]) / (len(Y) - 1))
+        best = max(best, ratio)
+    return float(best)
+
+
+def level_tolerances_l2(shape, tol_l2, c_l2=0.0, coords=None, stop_level=0) -> np.ndarray:
+    """L2 variant of Sec. 4.1: tau_l = tol / sqrt(C_L2 h_l^d #N_L), h_l^d the level's
+    cell volume (extent / intervals per axis), levels stop_level .. L.
+    c_l2 <= 0 takes l2_constant(...)."""
+    L = num_levels(shape)
+    Xs = _axis_coords(shape, coords)
+    if c_l2 <= 0.0:
+        c_l2 = l2_constant(shape, coords, stop_level)
     nL = float(np.prod(shape))
     out = []
     for l in range(int(stop_level), L + 1):

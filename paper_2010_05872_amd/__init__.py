@@ -97,7 +97,7 @@ EXPORTS = (
     "mgx_recompose_adjoint", "mgx_batch_workspace_size", "mgx_decompose_batched", "mgx_recompose_batched",
     "mgx_batch_set_autotune", "mgx_batch_last_info", "mgx_decompose_quantize", "mgx_dequantize_recompose",
     "mgx_recompose_to", "mgx_decompose_adaptive", "mgx_adaptive_estimate", "mgx_adaptive_workspace_size",
-    "mgx_dyadic_dims", "mgx_pad", "mgx_crop", "mgx_level_tolerances_l2", "mgx_quantize_levels",
+    "mgx_dyadic_dims", "mgx_pad", "mgx_crop", "mgx_l2_constant", "mgx_level_tolerances_l2", "mgx_quantize_levels",
     "mgx_dequantize_levels", "mgx_label_entropy", "mgx_label_entropy_workspace_size",
 )
 
@@ -132,6 +132,8 @@ def lib():
         L.mgx_adaptive_estimate.restype = ci
         L.mgx_adaptive_workspace_size.argtypes = [ci, i64p]
         L.mgx_adaptive_workspace_size.restype = sz
+        L.mgx_l2_constant.argtypes = [ci, i64p, vp, ci]
+        L.mgx_l2_constant.restype = cd
         L.mgx_level_tolerances_l2.argtypes = [ci, i64p, vp, cd, ci, cd, dp]
         L.mgx_level_tolerances_l2.restype = ci
         L.mgx_quantize_levels.argtypes = [vp, vp, ci, ci, i64p, vp, ci, dp, vp, vp]
@@ -631,8 +633,17 @@ def dequantize(labels, tol, dtype, coords=None, stop_level=0, c_linf=0.0, out=No
     return out
 
 
-def level_tolerances_l2(shape, tol_l2, c_l2, coords=None, stop_level=0) -> np.ndarray:
-    """tau_l of the L2 variant (levels stop_level .. L); c_l2 must be given."""
+def l2_constant(shape, coords=None, stop_level=0) -> float:
+    c = Coords(shape, coords)
+    r = lib().mgx_l2_constant(len(shape), _dims(shape), c.ptr, int(stop_level))
+    if r < 0:
+        raise MgxError(1, "mgx_l2_constant")
+    return r
+
+
+def level_tolerances_l2(shape, tol_l2, c_l2=0.0, coords=None, stop_level=0) -> np.ndarray:
+    """tau_l of the L2 variant (levels stop_level .. L); c_l2 <= 0 takes
+    the library's default C_L2 (l2_constant)."""
     L = num_levels(shape)
     tau = np.zeros(L + 1 - int(stop_level), dtype=np.float64)
     c = Coords(shape, coords)

@@ -2422,6 +2422,13 @@ mgx_status mgx_level_tolerances(int ndim, const int64_t *dims, const double *con
   return tolerances(P, ndim, tol_linf, stop_level, c_linf, tau_out);
 }
 
+double mgx_l2_constant(int ndim, const int64_t *dims, const double *const *coords, int stop_level) {
+  int st = 0;
+  Plan *P = get_plan(ndim, dims, coords, &st);
+  if (!P || stop_level < 0 || stop_level > P->L) return -1.0;
+  return P->l2_constant(stop_level);
+}
+
 mgx_status mgx_level_tolerances_l2(int ndim, const int64_t *dims, const double *const *coords, double tol_l2,
                                    int stop_level, double c_l2, double *tau_out) {
   if (!tau_out) return MGX_ERR_ARG;
@@ -2429,7 +2436,8 @@ mgx_status mgx_level_tolerances_l2(int ndim, const int64_t *dims, const double *
   Plan *P = get_plan(ndim, dims, coords, &st);
   if (!P) return (mgx_status)st;
   if (stop_level < 0 || stop_level > P->L) return MGX_ERR_LEVEL;
-  if (!(tol_l2 > 0.0) || !std::isfinite(tol_l2) || !(c_l2 > 0.0) || !std::isfinite(c_l2)) return MGX_ERR_TOL;
+  if (!(tol_l2 > 0.0) || !std::isfinite(tol_l2) || !std::isfinite(c_l2)) return MGX_ERR_TOL;
+  if (!(c_l2 > 0.0)) c_l2 = P->l2_constant(stop_level);
   const double nL = (double)(P->n[0] * P->n[1] * P->n[2]);
   for (int l = stop_level; l <= P->L; l++) {
     // h_l^d: the level's cell volume, extent / intervals on every real axis

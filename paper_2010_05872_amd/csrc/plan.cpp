@@ -229,6 +229,29 @@ double Plan::linf_constant(int stop) const {
   return C;
 }
 
+double Plan::l2_constant(int stop) const {
+  double best = 0.0;
+  for (int l = stop; l <= L; l++) {
+    double ratio = 1.0;
+    for (int k = 0; k < 3; k++) {
+      if (!real[k]) continue;
+      const int64_t s = (int64_t)1 << (L - l);
+      const int64_t m = (n[k] - 1) / s + 1;
+      // row j of the level's 1-D mass matrix sums to (h_{j-1} + h_j) / 2
+      double rmax = 0.0;
+      for (int64_t j = 0; j < m; j++) {
+        const double hl = j > 0 ? X[k][j * s] - X[k][(j - 1) * s] : 0.0;
+        const double hr = j + 1 < m ? X[k][(j + 1) * s] - X[k][j * s] : 0.0;
+        const double r = (hl + hr) / 2.0;
+        rmax = r > rmax ? r : rmax;
+      }
+      ratio *= rmax / ((X[k][n[k] - 1] - X[k][0]) / (double)(m - 1));
+    }
+    best = ratio > best ? ratio : best;
+  }
+  return best;
+}
+
 const void *Plan::device_tables(int device, bool fp64, int *hip_err) {
   std::lock_guard<std::mutex> g(dev_mu);
   auto &vec = fp64 ? dtab64 : dtab32;

@@ -63,6 +63,10 @@ struct Plan {
 
   const void *device_tables(int device, bool fp64, int *hip_err);
   double linf_constant(int stop) const;
+  // C_L2 of the L2 estimator (Sec. 4.1): max over levels stop..L of
+  // prod_k (largest row sum of the axis mass matrix) / h_l^d, the level's
+  // mass-matrix eigenvalue bound over its cell volume; 1 on uniform grids.
+  double l2_constant(int stop) const;
 };
 
 // Shape checks shared by every entry point.  Returns 0 or an mgx_status.

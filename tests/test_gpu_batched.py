@@ -2,8 +2,9 @@
 launches (mgx_decompose_batched / mgx_recompose_batched).
 
 The batched results must equal the single-field calls bit for bit (the same
-kernel bodies; tiling does not change any summation order), hence also the
-oracle to the parity bars, which is checked on two fields directly.
+kernel bodies; tiling does not change any summation order), and every field
+meets the oracle to the parity bars in every direction: decomposition,
+labels, recomposition from coefficients and from labels.
 """
 import sys
 
@@ -116,18 +117,58 @@ def test_batched_equals_single(autotune):
         mgx.batch_set_autotune(True)
 
 
+def _bar(dtype):
+    return 1e-12 if dtype == torch.float64 else 1e-5
+
+
 def test_batched_parity_with_oracle():
-    _say("[batched] oracle")
-    F = _fields()[:4]
+    """Every field of the batch, in every direction, against the oracle:
+    decomposition (coefficients), labels from the same coefficients
+    (bit-exact), recomposition from the coefficients, and recomposition from
+    the labels, with the dequantized coefficients written to coef and
+    straight from the labels in the level kernels (both against the oracle's
+    recomposition of its own dequantization of the same labels)."""
+    _say("[batched] oracle, all fields and directions")
+    F = _fields()
     outs = [torch.empty_like(f["u"]) for f in F]
-    b = mgx.Batch([dict(**{"in": f["u"]}, out=o, coords=f["coords"], stop_level=f["stop"]) for f, o in zip(F, outs)])
+    labels = [torch.empty(f["u"].shape, dtype=torch.int32, device="cuda") for f in F]
+    b = mgx.Batch([dict(**{"in": f["u"]}, out=o, coords=f["coords"], stop_level=f["stop"], tol=f["tol"],
+                        labels=lab) for f, o, lab in zip(F, outs, labels)])
     b.decompose()
+    recs = [torch.empty_like(f["u"]) for f in F]
+    mgx.Batch([dict(**{"in": o}, out=rr, coords=f["coords"], stop_level=f["stop"])
+               for f, o, rr in zip(F, outs, recs)]).recompose()
+    coefs = [torch.empty_like(f["u"]) for f in F]
+    recs_c = [torch.empty_like(f["u"]) for f in F]
+    mgx.Batch([dict(out=rr, coords=f["coords"], stop_level=f["stop"], tol=f["tol"], labels=lab, coef=c)
+               for f, lab, c, rr in zip(F, labels, coefs, recs_c)]).recompose()
+    recs_l = [torch.full_like(f["u"], float("nan")) for f in F]
+    mgx.Batch([dict(out=rr, coords=f["coords"], stop_level=f["stop"], tol=f["tol"], labels=lab)
+               for f, lab, rr in zip(F, labels, recs_l)]).recompose()
     torch.cuda.synchronize()
-    for f, o in zip(F, outs):
+    for i, f in enumerate(F):
+        shape, stop, coords, tol = tuple(f["u"].shape), f["stop"], f["coords"], f["tol"]
+        _say(f"  field {i}: {shape} {f['u'].dtype} stop={stop}")
         u64 = f["u"].double().cpu().numpy()
-        ref = oracle.to_level_centric(oracle.decompose(u64, f["coords"], f["stop"]), f["stop"])
-        bar = 1e-12 if f["u"].dtype == torch.float64 else 1e-5
-        assert np.abs(o.double().cpu().numpy() - ref).max() <= bar * np.abs(u64).max()
+        scale = np.abs(u64).max()
+        bar = _bar(f["u"].dtype) * scale
+        ref = oracle.to_level_centric(oracle.decompose(u64, coords, stop), stop)
+        g64 = outs[i].double().cpu().numpy()
+        assert np.abs(g64 - ref).max() <= bar, ("decompose", i)
+        g_int = oracle.from_level_centric(g64, stop)
+        rref = oracle.recompose(g_int, coords, stop)
+        assert np.abs(recs[i].double().cpu().numpy() - rref).max() <= bar, ("recompose", i)
+        lref, code = oracle.quantize(g_int, tol, coords, stop)
+        assert code == 0
+        assert np.array_equal(labels[i].cpu().numpy(), oracle.to_level_centric(lref, stop)), ("labels", i)
+        dq = oracle.dequantize(lref, tol, coords, stop)
+        np_dt = np.float32 if f["u"].dtype == torch.float32 else np.float64
+        assert np.array_equal(coefs[i].cpu().numpy(), oracle.to_level_centric(dq, stop).astype(np_dt)), ("coef", i)
+        qref = oracle.recompose(dq, coords, stop)
+        for name, got in (("labels->coef->recompose", recs_c[i]), ("labels->recompose", recs_l[i])):
+            assert np.abs(got.double().cpu().numpy() - qref).max() <= bar, (name, i)
+        # and the quantized round trip honours the L-infinity bound
+        assert np.abs(recs_l[i].double().cpu().numpy() - u64).max() <= tol, ("bound", i)
 
 
 def test_batched_errors():

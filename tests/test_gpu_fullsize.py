@@ -4,13 +4,12 @@ times (default tuning, caller-provided workspace).
 513^3 fp32 (turbulence spectrum): the whole decomposition (stop levels 0 and
 4), the recomposition of the same coefficients and the quantization labels
 against the oracle; the L-infinity bound end to end at three tolerances; the
-benchmark's fused step, progressive recomposition, the adaptive choice and
-the label entropy against the oracle.
+benchmark's fused step (its labels-only recomposition against the oracle's
+recomposition of the same labels), progressive recomposition, the adaptive
+choice and the label entropy against the oracle.
 
-257x1025x1025 fp32 on the tanh-stretched axis (too large for the oracle in a
-test): the finest level's coefficients at sampled nodes against their
-definition (value minus the multilinear interpolant of its nodal corners,
-computed here in FP64), the round trip, and the L-infinity bound.
+257x1025x1025 fp32 on the tanh-stretched axis: the whole decomposition and
+recomposition against the oracle, the round trip, and the L-infinity bound.
 """
 import sys
 
@@ -83,51 +82,44 @@ def test_513_fp32_linf_bound(field513, rel):
         assert err <= tol, (stop, err / tol)
 
 
-def test_config3_properties():
-    _say("[full] 257x1025x1025 fp32 tanh")
+def test_config3_against_oracle():
+    """257 x 1025 x 1025 fp32 on the tanh-stretched axis 0, the whole field:
+    the full decomposition (L = 7, to 3 x 9 x 9) and the recomposition of the
+    same coefficients against the oracle, the round trip, and the fused
+    quantized path within the tolerance."""
+    _say("[full] 257x1025x1025 fp32 tanh against the oracle")
     u, coords = workloads.layered_lognormal_field(device="cuda")
     torch.cuda.synchronize()
-    shape = tuple(u.shape)
     g = mgx.decompose(u, coords)
-    torch.cuda.synchronize()
-    uh = u.cpu().numpy().astype(np.float64)
-    gh = g.cpu().numpy()
-    scale = np.abs(uh).max()
-    X = [np.asarray(coords[0], dtype=np.float64), np.arange(shape[1], dtype=np.float64),
-         np.arange(shape[2], dtype=np.float64)]
-    c = [(n + 1) // 2 for n in shape]  # coarse counts of the finest step
-    rng = np.random.default_rng(11)
-    checked = 0
-    while checked < 20000:
-        i = [int(rng.integers(0, n)) for n in shape]
-        if not any(v & 1 for v in i):
-            continue
-        pred = 0.0
-        corners = [[]]
-        for k in range(3):
-            if i[k] & 1:
-                wl = (X[k][i[k] + 1] - X[k][i[k]]) / (X[k][i[k] + 1] - X[k][i[k] - 1])
-                opts = [(i[k] - 1, wl), (i[k] + 1, 1.0 - wl)]
-            else:
-                opts = [(i[k], 1.0)]
-            corners = [cc + [o] for cc in corners for o in opts]
-        for cc in corners:
-            w = cc[0][1] * cc[1][1] * cc[2][1]
-            pred += w * uh[cc[0][0], cc[1][0], cc[2][0]]
-        want = uh[i[0], i[1], i[2]] - pred
-        pos = [c[k] + (i[k] - 1) // 2 if i[k] & 1 else i[k] // 2 for k in range(3)]
-        assert abs(float(gh[pos[0], pos[1], pos[2]]) - want) <= 1e-5 * scale, (i, gh[tuple(pos)], want)
-        checked += 1
     r = mgx.recompose(g, coords)
-    assert (r.double() - u.double()).abs().max().item() <= 1e-5 * scale
+    torch.cuda.synchronize()
+    u64 = u.double().cpu().numpy()
+    scale = np.abs(u64).max()
+    g64 = g.double().cpu().numpy()
+    del g
+    ref = oracle.to_level_centric(oracle.decompose(u64, coords, 0), 0)
+    err = np.abs(g64 - ref).max()
+    _say(f"  decompose max err / max|u| = {err / scale:.3e}")
+    assert err <= 1e-5 * scale
+    del ref
+    rref = oracle.recompose(oracle.from_level_centric(g64, 0), coords, 0)
+    del g64
+    r64 = r.double().cpu().numpy()
+    rerr = np.abs(r64 - rref).max()
+    _say(f"  recompose max err / max|u| = {rerr / scale:.3e}")
+    assert rerr <= 1e-5 * scale
+    del rref
+    assert np.abs(r64 - u64).max() <= 1e-5 * scale
+    del r64, r
     tol = 1e-3 * float((u.max() - u.min()).item())
-    g2, lab = mgx.decompose_quantize(u, tol, coords)
+    _, lab = mgx.decompose_quantize(u, tol, coords, keep_coef=False)
     r2 = mgx.dequantize_recompose(lab, tol, torch.float32, coords)
     assert (r2.double() - u.double()).abs().max().item() <= tol
 
 
 def test_513_fp32_fused_progressive_adaptive_entropy(field513):
-    """The benchmark's fused step (labels only) equal to the separate calls;
+    """The benchmark's fused step (labels only) equal to the separate calls,
+    and its recomposition against the oracle's from the same labels;
     progressive recomposition to levels 6 and 7 against the oracle from the
     same coefficients; the adaptive decomposition's choice against the
     oracle's; the labels' per-level entropy against the oracle's."""
@@ -142,6 +134,16 @@ def test_513_fp32_fused_progressive_adaptive_entropy(field513):
     assert torch.equal(lab, rlab)
     u64 = u.double().cpu().numpy()
     scale = np.abs(u64).max()
+    # the benchmark's labels-only recomposition against the oracle's
+    # recomposition of its own dequantization of the same labels
+    r = mgx.dequantize_recompose(lab, tol, torch.float32, workspace=ws)
+    torch.cuda.synchronize()
+    lab_int = oracle.from_level_centric(lab.cpu().numpy(), 0)
+    qref = oracle.recompose(oracle.dequantize(lab_int, tol))
+    qerr = np.abs(r.double().cpu().numpy() - qref).max()
+    _say(f"  labels-only recompose max err / max|u| = {qerr / scale:.3e}")
+    assert qerr <= 1e-5 * scale
+    del qref, lab_int, r
     g64 = oracle.from_level_centric(g.double().cpu().numpy(), 0)
     for t in (6, 7):
         got = mgx.recompose_to(g, t, workspace=ws)

@@ -66,6 +66,9 @@ CASES = [
     ((17, 513, 33), torch.float32, "random"),
     ((513, 9, 9), torch.float64, None),        # fp64 257-long strided lines (chunked sweeps)
     ((9, 1025, 17), torch.float64, "tanh"),    # 513-long strided lines (chunked sweeps)
+    # shaped like the thin-vertical weather grid (257 x 1025 x 1025, tanh-stretched axis 0) with the
+    # contiguous axis cut to 33: fp32 1025-long strided lines on axis 1, the tanh axis 257 long
+    ((257, 1025, 33), torch.float32, "tanh"),
 ]
 
 
@@ -84,7 +87,8 @@ def test_decompose_recompose_parity(case):
     u64 = ud.double().cpu().numpy()
     scale = np.abs(u64).max()
     L = oracle.num_levels(shape)
-    stops = sorted({0, L // 2, max(L - 1, 0), L})
+    # every stop level for the weather-grid-shaped case, four for the others
+    stops = list(range(L + 1)) if shape == (257, 1025, 33) else sorted({0, L // 2, max(L - 1, 0), L})
     for stop in stops:
         g = mgx.decompose(ud, coords, stop)
         torch.cuda.synchronize()
@@ -135,7 +139,8 @@ def test_quantize_bit_exact(dtype):
         assert mgx.linf_constant(shape, coords, stop) == pytest.approx(C, rel=1e-13)
 
 
-@pytest.mark.parametrize("dtype,rel", [(torch.float64, 1e-2), (torch.float64, 1e-4), (torch.float32, 1e-3)])
+@pytest.mark.parametrize("dtype,rel", [(torch.float64, 1e-2), (torch.float64, 1e-3), (torch.float64, 1e-4),
+                                       (torch.float32, 1e-3)])
 def test_linf_bound_end_to_end(dtype, rel):
     shape = (65, 65, 65)
     _say(f"[linf] {dtype} {rel}")
