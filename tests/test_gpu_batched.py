@@ -130,21 +130,24 @@ def test_batched_parity_with_oracle():
     recomposition of its own dequantization of the same labels)."""
     _say("[batched] oracle, all fields and directions")
     F = _fields()
+    # the oracle's constant on both sides: labels and dequantized values then compare bit for bit
+    for f in F:
+        f["C"] = oracle.linf_constant(tuple(f["u"].shape), f["coords"], f["stop"])
     outs = [torch.empty_like(f["u"]) for f in F]
     labels = [torch.empty(f["u"].shape, dtype=torch.int32, device="cuda") for f in F]
     b = mgx.Batch([dict(**{"in": f["u"]}, out=o, coords=f["coords"], stop_level=f["stop"], tol=f["tol"],
-                        labels=lab) for f, o, lab in zip(F, outs, labels)])
+                        c_linf=f["C"], labels=lab) for f, o, lab in zip(F, outs, labels)])
     b.decompose()
     recs = [torch.empty_like(f["u"]) for f in F]
     mgx.Batch([dict(**{"in": o}, out=rr, coords=f["coords"], stop_level=f["stop"])
                for f, o, rr in zip(F, outs, recs)]).recompose()
     coefs = [torch.empty_like(f["u"]) for f in F]
     recs_c = [torch.empty_like(f["u"]) for f in F]
-    mgx.Batch([dict(out=rr, coords=f["coords"], stop_level=f["stop"], tol=f["tol"], labels=lab, coef=c)
-               for f, lab, c, rr in zip(F, labels, coefs, recs_c)]).recompose()
+    mgx.Batch([dict(out=rr, coords=f["coords"], stop_level=f["stop"], tol=f["tol"], c_linf=f["C"],
+                         labels=lab, coef=c) for f, lab, c, rr in zip(F, labels, coefs, recs_c)]).recompose()
     recs_l = [torch.full_like(f["u"], float("nan")) for f in F]
-    mgx.Batch([dict(out=rr, coords=f["coords"], stop_level=f["stop"], tol=f["tol"], labels=lab)
-               for f, lab, rr in zip(F, labels, recs_l)]).recompose()
+    mgx.Batch([dict(out=rr, coords=f["coords"], stop_level=f["stop"], tol=f["tol"], c_linf=f["C"],
+                         labels=lab) for f, lab, rr in zip(F, labels, recs_l)]).recompose()
     torch.cuda.synchronize()
     for i, f in enumerate(F):
         shape, stop, coords, tol = tuple(f["u"].shape), f["stop"], f["coords"], f["tol"]
@@ -158,10 +161,10 @@ def test_batched_parity_with_oracle():
         g_int = oracle.from_level_centric(g64, stop)
         rref = oracle.recompose(g_int, coords, stop)
         assert np.abs(recs[i].double().cpu().numpy() - rref).max() <= bar, ("recompose", i)
-        lref, code = oracle.quantize(g_int, tol, coords, stop)
+        lref, code = oracle.quantize(g_int, tol, coords, stop, c_linf=f["C"])
         assert code == 0
         assert np.array_equal(labels[i].cpu().numpy(), oracle.to_level_centric(lref, stop)), ("labels", i)
-        dq = oracle.dequantize(lref, tol, coords, stop)
+        dq = oracle.dequantize(lref, tol, coords, stop, c_linf=f["C"])
         np_dt = np.float32 if f["u"].dtype == torch.float32 else np.float64
         assert np.array_equal(coefs[i].cpu().numpy(), oracle.to_level_centric(dq, stop).astype(np_dt)), ("coef", i)
         qref = oracle.recompose(dq, coords, stop)
