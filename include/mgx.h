@@ -264,6 +264,29 @@ mgx_status mgx_dequantize_recompose(const int32_t *labels, void *u_mc, void *u, 
                                     int stop_level, double c_linf, void *workspace, size_t workspace_bytes,
                                     hipStream_t stream);
 
+/* ---- Decomposition without allocation ----
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * mgx_decompose with the same results (the same kernels), but its level
+ * tables and its workspace live in a static device array of the library,
+ * MGX_NOALLOC_SCRATCH_BYTES per device, held from the library's load until
+ * the process ends.  The call allocates no device memory: the tables (a few
+ * hundred KB at most) are copied from host memory into the array on `stream`
+ * (hipMemcpyAsync from pageable memory, which may wait for the copy), then
+ * the level kernels run with the array as their workspace.  No part of the
+ * array needs to start at zero: every call writes what it reads.  Every
+ * call on one device shares that device's array: calls that overlap on one
+ * device (other streams, other host threads) race; calls in order on one
+ * stream do not.  Tracing (mgx_trace_enable) does not record these calls.
+ *   u, u_mc, dtype, ndim, dims, coords, stop_level: as mgx_decompose.
+ * Errors: MGX_ERR_WORKSPACE when the tables (256-byte aligned) plus
+ * mgx_workspace_size(...) exceed MGX_NOALLOC_SCRATCH_BYTES (e.g. 257^3 fp32
+ * fits, 513^3 fp32 does not); MGX_ERR_SHAPE for ndim = 4; otherwise those of
+ * mgx_decompose. */
+#define MGX_NOALLOC_SCRATCH_BYTES (32u << 20)
+mgx_status mgx_decompose_noalloc(const void *u, void *u_mc, mgx_dtype dtype, int ndim, const int64_t *dims,
+                                 const double *const *coords, int stop_level, hipStream_t stream);
+
 /* ---- Adjoints (project extension, not in the paper) ----
  * The transposes of the linear maps mgx_decompose (D) and mgx_recompose
  * (R = D^{-1}): for all x, y, <D x, y> = <x, D^T y>.  They let gradients of

@@ -98,7 +98,7 @@ EXPORTS = (
     "mgx_batch_set_autotune", "mgx_batch_last_info", "mgx_decompose_quantize", "mgx_dequantize_recompose",
     "mgx_recompose_to", "mgx_decompose_adaptive", "mgx_adaptive_estimate", "mgx_adaptive_workspace_size",
     "mgx_dyadic_dims", "mgx_pad", "mgx_crop", "mgx_l2_constant", "mgx_level_tolerances_l2", "mgx_quantize_levels",
-    "mgx_dequantize_levels", "mgx_label_entropy", "mgx_label_entropy_workspace_size",
+    "mgx_dequantize_levels", "mgx_label_entropy", "mgx_label_entropy_workspace_size", "mgx_decompose_noalloc",
 )
 
 _lib = None
@@ -132,6 +132,8 @@ def lib():
         L.mgx_adaptive_estimate.restype = ci
         L.mgx_adaptive_workspace_size.argtypes = [ci, i64p]
         L.mgx_adaptive_workspace_size.restype = sz
+        L.mgx_decompose_noalloc.argtypes = [vp, vp, ci, ci, i64p, vp, ci, vp]
+        L.mgx_decompose_noalloc.restype = ci
         L.mgx_l2_constant.argtypes = [ci, i64p, vp, ci]
         L.mgx_l2_constant.restype = cd
         L.mgx_level_tolerances_l2.argtypes = [ci, i64p, vp, cd, ci, cd, dp]
@@ -307,6 +309,22 @@ def decompose(u, coords=None, stop_level=0, out=None, workspace=None):
     code = lib().mgx_decompose(u.data_ptr(), out.data_ptr(), _dtype_code(u), u.dim(), _dims(u.shape), c.ptr,
                                int(stop_level), ws.data_ptr(), ws.numel() * ws.element_size(), _stream(u.device))
     _check(code, "mgx_decompose")
+    return out
+
+
+def decompose_noalloc(u, coords=None, stop_level=0, out=None):
+    """decompose() through mgx_decompose_noalloc: the library's static device
+    array holds the tables and the workspace (no device allocation in the
+    library; out, when None, is allocated here by torch)."""
+    import torch
+    _check_tensor(u, "u")
+    if out is None:
+        out = torch.empty_like(u)
+    _check_tensor(out, "out")
+    c = Coords(u.shape, coords)
+    code = lib().mgx_decompose_noalloc(u.data_ptr(), out.data_ptr(), _dtype_code(u), u.dim(), _dims(u.shape), c.ptr,
+                                       int(stop_level), _stream(u.device))
+    _check(code, "mgx_decompose_noalloc")
     return out
 
 

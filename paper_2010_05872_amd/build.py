@@ -23,6 +23,7 @@ SOURCES = [
     ("kernels.hip", DEVICE_FLAGS),
     ("kernels4.hip", DEVICE_FLAGS),
     ("entropy.hip", DEVICE_FLAGS),
+    ("noalloc.hip", DEVICE_FLAGS),
     # host code: FP64 tolerance arithmetic in source order, no contraction
     ("plan.cpp", ["-ffp-contract=off"]),
     ("capi.cpp", ["-ffp-contract=off"]),

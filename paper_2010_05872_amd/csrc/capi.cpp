@@ -17,6 +17,7 @@
 #include "kernels.hpp"
 #include "kernels4.hpp"
 #include "mgx.h"
+#include "placed.hpp"
 #include "plan.hpp"
 
 namespace mgx {
@@ -164,6 +165,7 @@ struct Emitter {
   hipStream_t st = nullptr;
   Tuning tn{};
   std::vector<RecordedOp<T>> *rec = nullptr;
+  bool untraced = false;  // never bracket launches with events (callers that must not allocate)
   // immediate mode only: called before and after each launch with (kind, level)
   std::function<hipError_t(int, int)> before, after;
   int base = 0, step = 0, phase = 0;
@@ -177,6 +179,7 @@ struct Emitter {
       return hipSuccess;
     }
     hipError_t e;
+    if (untraced) return launch_op<T>(kind, mode, a, tn, st);
     if (before && (e = before(kind, level)) != hipSuccess) return e;
     e = traced(name, level, st, [&] { return launch_op<T>(kind, mode, a, tn, st); });
     if (e == hipSuccess && after) e = after(kind, level);
@@ -747,9 +750,11 @@ mgx_status run_recompose_adjoint(Plan *P, int stop, const T *gu, T *gmc, char *w
 }
 
 // Common validation of decompose / recompose.
+// With placed != null the tables are not looked up on the device (the caller
+// copies them to memory of its own) and *tab stays untouched.
 mgx_status prepare(const void *in, void *out, mgx_dtype dtype, int ndim, const int64_t *dims,
                    const double *const *coords, int stop, void *ws, size_t ws_bytes, Plan **plan,
-                   Layout *lay, const void **tab, bool adjoint = false, int may_null = 0) {
+                   Layout *lay, const void **tab, bool adjoint = false, int may_null = 0, bool placed = false) {
   if (dtype != MGX_F32 && dtype != MGX_F64) return MGX_ERR_ARG;
   int64_t n[3];
   bool real[3];
@@ -770,12 +775,13 @@ mgx_status prepare(const void *in, void *out, mgx_dtype dtype, int ndim, const i
     if ((in && overlaps(ws, lay->total, in, bytes)) || (out && overlaps(ws, lay->total, out, bytes)))
       return MGX_ERR_ARG;
   }
+  *plan = P;
+  if (placed) return MGX_OK;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return MGX_ERR_HIP;
   int herr = 0;
   *tab = P->device_tables(dev, dtype == MGX_F64, &herr);
   if (!*tab) return MGX_ERR_HIP;
-  *plan = P;
   return MGX_OK;
 }
 
@@ -1831,6 +1837,52 @@ mgx_status quant_args4(const int64_t *dims, const double *const *coords, double 
 }
 
 }  // namespace
+}  // namespace mgx
+
+namespace mgx {
+
+mgx_status decompose_placed(const void *u, void *u_mc, mgx_dtype dtype, int ndim, const int64_t *dims,
+                            const double *const *coords, int stop_level, char *region, size_t region_bytes,
+                            hipStream_t stream) {
+  if (ndim == 4) return MGX_ERR_SHAPE;
+  if (!region) return MGX_ERR_ARG;
+  if (dtype != MGX_F32 && dtype != MGX_F64) return MGX_ERR_ARG;
+  // the plan (host) first: its table size decides where the workspace starts
+  int st = 0;
+  int64_t n[3];
+  bool real[3];
+  int L;
+  if ((st = parse_shape(ndim, dims, n, real, &L)) != 0) return (mgx_status)st;
+  Plan *P = get_plan(ndim, dims, coords, &st);
+  if (!P) return (mgx_status)st;
+  const bool f64 = dtype == MGX_F64;
+  const void *host_tab = f64 ? (const void *)P->tab64.data() : (const void *)P->tab32.data();
+  const size_t tab_bytes = f64 ? P->tab64.size() * sizeof(double) : P->tab32.size() * sizeof(float);
+  const size_t ws_off = align_up(tab_bytes, 256);
+  if (ws_off > region_bytes) return MGX_ERR_WORKSPACE;
+  Layout lay;
+  const void *unused = nullptr;
+  mgx_status s = prepare(u, u_mc, dtype, ndim, dims, coords, stop_level, region + ws_off, region_bytes - ws_off, &P,
+                         &lay, &unused, false, 0, true);
+  if (s) return s;
+  if (overlaps(region, ws_off, u, (size_t)(n[0] * n[1] * n[2]) * elem_size(dtype)) ||
+      overlaps(region, ws_off, u_mc, (size_t)(n[0] * n[1] * n[2]) * elem_size(dtype)))
+    return MGX_ERR_ARG;
+  if (hipMemcpyAsync(region, host_tab, tab_bytes, hipMemcpyHostToDevice, stream) != hipSuccess) return MGX_ERR_HIP;
+  if (!f64) {
+    Emitter<float> em;
+    em.st = stream;
+    em.untraced = true;
+    return run_decompose<float>(P, stop_level, (const float *)u, (float *)u_mc, region + ws_off, lay,
+                                (const float *)region, em);
+  }
+  Emitter<double> em;
+  em.st = stream;
+  em.untraced = true;
+  return run_decompose<double>(P, stop_level, (const double *)u, (double *)u_mc, region + ws_off, lay,
+                               (const double *)region, em);
+}
+
 }  // namespace mgx
 
 using namespace mgx;
