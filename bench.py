@@ -432,6 +432,9 @@ def main():
         "dequantize_recompose": lambda: mgx.dequantize_recompose(labels, tol, torch.float32, out=ut, workspace=ws),
         "decompose_quantize_keep_coef": lambda: mgx.decompose_quantize(u, tol, out=umc, labels=labels,
                                                                        workspace=ws),
+        # with statistics: out-of-range counts, per-level max |label| and the status (waits for the stream)
+        "decompose_quantize_stats": lambda: mgx.decompose_quantize(u, tol, labels=labels, workspace=ws,
+                                                                   keep_coef=False, stats=True),
         "dequantize_recompose_keep_coef": lambda: mgx.dequantize_recompose(labels, tol, torch.float32, coef=uq,
                                                                            out=ut, workspace=ws),
         "decompose": lambda: mgx.decompose(u, out=umc, workspace=ws),

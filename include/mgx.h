@@ -11,7 +11,10 @@
  *   is contiguous.  1 <= ndim <= 3, and ndim = 4 (four-axis fields such as
  *   the QMCPACK data of Sec. 6, Table 2) where an entry point says so.  Every
  *   dims[k] must be 2^m + 1 with 1 <= m <= 13 (3 <= n <= 8193); a 4-D field
- *   has fewer than 2^32 nodes.
+ *   has fewer than 2^32 nodes.  Every call that quantizes or dequantizes
+ *   (mgx_quantize, mgx_dequantize, their _levels forms, the fused calls, the
+ *   batched calls with labels, mgx_label_entropy) indexes the field with 32
+ *   bits and returns MGX_ERR_SHAPE for 2^32 nodes or more, whatever ndim.
  * - Four-axis fields: mgx_num_levels, mgx_workspace_size, mgx_decompose,
  *   mgx_recompose, mgx_recompose_to, mgx_quantize, mgx_dequantize,
  *   mgx_quantize_levels, mgx_dequantize_levels, mgx_decompose_quantize,
@@ -58,7 +61,10 @@
 extern "C" {
 #endif
 
-typedef enum { MGX_F32 = 0, MGX_F64 = 1 } mgx_dtype;
+/* The *_ENUM_MAX members only widen each enum to every non-negative int, so
+ * that a C caller's out-of-range value is a value of the type the library
+ * (written in C++) can test and reject; they are never valid arguments. */
+typedef enum { MGX_F32 = 0, MGX_F64 = 1, MGX_DTYPE_ENUM_MAX = 0x7fffffff } mgx_dtype;
 
 typedef enum {
   MGX_OK = 0,
@@ -70,7 +76,8 @@ typedef enum {
   MGX_ERR_RANGE = 6,     /* a quantization label overflowed int32 or a
                             coefficient was not finite (quantize with stats)    */
   MGX_ERR_WORKSPACE = 7, /* workspace NULL or smaller than mgx_workspace_size  */
-  MGX_ERR_HIP = 8        /* the HIP runtime reported an error                  */
+  MGX_ERR_HIP = 8,       /* the HIP runtime reported an error                  */
+  MGX_STATUS_ENUM_MAX = 0x7fffffff
 } mgx_status;
 
 #define MGX_MAX_LEVELS 16
@@ -233,30 +240,35 @@ mgx_status mgx_recompose_to(const void *u_mc, void *u_t, mgx_dtype dtype, int nd
                             const double *const *coords, int stop_level, int target_level, void *workspace,
                             size_t workspace_bytes, hipStream_t stream);
 
-/* mgx_decompose followed by mgx_quantize (no statistics) in one call, with
- * the same results (Sec. 4.1 quantization of the Sec. 3 decomposition):
- * every kernel that produces coefficients of a level also writes their
- * labels, so no separate pass over u_mc is made.
+/* mgx_decompose followed by mgx_quantize in one call, with the same results
+ * (Sec. 4.1 quantization of the Sec. 2 decomposition, Alg. 1's quantize
+ * step): every kernel that produces coefficients of a level also writes
+ * their labels, so no separate pass over u_mc is made.
  *   u_mc     out: device, level-centric layout, or NULL: then only labels
  *            are written (the stop level's box goes through the workspace).
  *   labels   out: device, int32, same shape; must not overlap u, u_mc or
- *            the workspace.
- * A build with MGX_FUSED_OVERLAP (and u_mc given) instead runs the
- * decomposition and a separate quantization, the finest level's on a second
- * stream of the library (measured slower on MI355X).
- * Errors as mgx_decompose and mgx_quantize (MGX_ERR_TOL). */
+ *            the workspace.  A coefficient whose |c/q_l| >= 2^31-1 or that
+ *            is not finite gets INT32_MIN.
+ *   stats    NULL: fully asynchronous; out-of-range coefficients are not
+ *            reported.  Non-NULL (host): the level kernels also reduce the
+ *            per-level max |label| (one atomic per wave) and count
+ *            out-of-range coefficients (on their rare exact-division path),
+ *            the call waits for the stream, fills *stats as mgx_quantize does
+ *            and returns MGX_ERR_RANGE when some coefficient was out of
+ *            range.  Four-axis fields take the per-level maxima in one more
+ *            pass over the labels.
+ * Errors as mgx_decompose and mgx_quantize (MGX_ERR_TOL, MGX_ERR_RANGE). */
 mgx_status mgx_decompose_quantize(const void *u, void *u_mc, int32_t *labels, mgx_dtype dtype, int ndim,
                                   const int64_t *dims, const double *const *coords, double tol_linf,
                                   int stop_level, double c_linf, void *workspace, size_t workspace_bytes,
-                                  hipStream_t stream);
+                                  mgx_quant_stats *stats, hipStream_t stream);
 
 /* mgx_dequantize(labels) followed by mgx_recompose into u, with the same
  * results.
  *   u_mc     NULL: the recomposition's kernels read each coefficient as its
  *            label times the level's bin width (no u_mc pass); or device,
  *            dtype: the dequantized coefficients are written there first and
- *            recomposed from (with MGX_FUSED_OVERLAP the finest level is
- *            dequantized on the library's second stream).
+ *            recomposed from.
  *   labels   in: device, int32; must not overlap u, u_mc or the workspace.
  * Errors as mgx_recompose and mgx_dequantize. */
 mgx_status mgx_dequantize_recompose(const int32_t *labels, void *u_mc, void *u, mgx_dtype dtype, int ndim,
@@ -341,6 +353,9 @@ typedef struct {
   void *coef;                /* recompose from labels: NULL, the level kernels read the
                                 labels; or a device buffer (dims, dtype) that receives the
                                 dequantized coefficients first                             */
+  mgx_quant_stats *stats;    /* decompose with labels: NULL, or host statistics of this
+                                field as mgx_decompose_quantize fills them (the batched call
+                                then waits for the stream); unused otherwise               */
 } mgx_field;
 
 typedef struct {
@@ -357,9 +372,12 @@ size_t mgx_batch_workspace_size(int nfields, const mgx_field *fields);
 
 /* Every field as mgx_decompose, with labels != NULL as
  * mgx_decompose_quantize (labels written by the level kernels; the same
- * labels as mgx_quantize, without statistics).  Outputs and labels of
- * different fields must not overlap.  Errors: those of the single-field
- * calls (the first failing field decides), MGX_ERR_WORKSPACE, MGX_ERR_HIP. */
+ * labels as mgx_quantize).  A field with stats != NULL gets the statistics
+ * of mgx_decompose_quantize: the call then waits for the stream and returns
+ * MGX_ERR_RANGE when some such field had an out-of-range coefficient (every
+ * field's stats are filled).  Outputs and labels of different fields must
+ * not overlap.  Errors: those of the single-field calls (the first failing
+ * field decides), MGX_ERR_WORKSPACE, MGX_ERR_HIP, MGX_ERR_RANGE. */
 mgx_status mgx_decompose_batched(int nfields, const mgx_field *fields, void *workspace,
                                  size_t workspace_bytes, hipStream_t stream);
 
@@ -369,6 +387,16 @@ mgx_status mgx_decompose_batched(int nfields, const mgx_field *fields, void *wor
  * it (the same results either way). */
 mgx_status mgx_recompose_batched(int nfields, const mgx_field *fields, void *workspace,
                                  size_t workspace_bytes, hipStream_t stream);
+
+/* Frees what the library caches across calls: the level plans of every
+ * (shape, coordinates) seen so far, with their device tables, and the
+ * captured graphs of batches.  Those caches otherwise grow with the number
+ * of distinct shapes, coordinate sets and batches a process uses, until it
+ * ends.  Synchronizes every device that holds cached memory.  No other call
+ * of the library may run, on any thread, while this one does; later calls
+ * rebuild what they need.  The statistics buffer and the static array of
+ * mgx_decompose_noalloc are not affected.  Errors: MGX_ERR_HIP. */
+mgx_status mgx_release_cached(void);
 
 /* Autotuning of batches on first use: 1 (default) or 0 (default shape). */
 mgx_status mgx_batch_set_autotune(int on);

@@ -68,6 +68,7 @@ class Field(ctypes.Structure):
         ("c_linf", ctypes.c_double),
         ("labels", ctypes.c_void_p),
         ("coef", ctypes.c_void_p),
+        ("stats", ctypes.c_void_p),
     ]
 
 
@@ -99,6 +100,7 @@ EXPORTS = (
     "mgx_recompose_to", "mgx_decompose_adaptive", "mgx_adaptive_estimate", "mgx_adaptive_workspace_size",
     "mgx_dyadic_dims", "mgx_pad", "mgx_crop", "mgx_l2_constant", "mgx_level_tolerances_l2", "mgx_quantize_levels",
     "mgx_dequantize_levels", "mgx_label_entropy", "mgx_label_entropy_workspace_size", "mgx_decompose_noalloc",
+    "mgx_release_cached",
 )
 
 _lib = None
@@ -120,7 +122,7 @@ def lib():
         L.mgx_num_levels.restype = ci
         L.mgx_workspace_size.argtypes = [ci, ci, i64p, ci]
         L.mgx_workspace_size.restype = sz
-        L.mgx_decompose_quantize.argtypes = [vp, vp, vp, ci, ci, i64p, vp, cd, ci, cd, vp, sz, vp]
+        L.mgx_decompose_quantize.argtypes = [vp, vp, vp, ci, ci, i64p, vp, cd, ci, cd, vp, sz, vp, vp]
         L.mgx_decompose_quantize.restype = ci
         L.mgx_dequantize_recompose.argtypes = [vp, vp, vp, ci, ci, i64p, vp, cd, ci, cd, vp, sz, vp]
         L.mgx_dequantize_recompose.restype = ci
@@ -164,6 +166,8 @@ def lib():
             f = getattr(L, name)
             f.argtypes = [ci, fp, vp, sz, vp]
             f.restype = ci
+        L.mgx_release_cached.argtypes = []
+        L.mgx_release_cached.restype = ci
         L.mgx_batch_set_autotune.argtypes = [ci]
         L.mgx_batch_set_autotune.restype = ci
         L.mgx_batch_last_info.argtypes = [ctypes.POINTER(BatchInfo)]
@@ -465,11 +469,13 @@ def adaptive_estimate(v, shape, level, coords=None, workspace=None):
 
 
 def decompose_quantize(u, tol, coords=None, stop_level=0, c_linf=0.0, out=None, labels=None, workspace=None,
-                       keep_coef=True):
+                       keep_coef=True, stats=False):
     """decompose then quantize (same labels and coefficients as the separate
     calls), the labels written by the decomposition's own kernels.  With
     keep_coef=False no u_mc is written (out is ignored) and None is returned
-    in its place.  Returns (u_mc, labels)."""
+    in its place.  Returns (u_mc, labels); with stats=True
+    (u_mc, labels, stats dict, status code), the code 6 (MGX_ERR_RANGE) when
+    some coefficient was out of range."""
     import torch
     _check_tensor(u, "u")
     if not keep_coef:
@@ -483,10 +489,16 @@ def decompose_quantize(u, tol, coords=None, stop_level=0, c_linf=0.0, out=None, 
     _check_tensor(labels, "labels")
     ws, _ = _workspace(u, stop_level, workspace)
     c = Coords(u.shape, coords)
+    st = QuantStats() if stats else None
     code = lib().mgx_decompose_quantize(u.data_ptr(), out.data_ptr() if out is not None else None,
                                         labels.data_ptr(), _dtype_code(u), u.dim(), _dims(u.shape), c.ptr,
                                         float(tol), int(stop_level), float(c_linf), ws.data_ptr(),
-                                        ws.numel() * ws.element_size(), _stream(u.device))
+                                        ws.numel() * ws.element_size(), ctypes.byref(st) if st is not None else None,
+                                        _stream(u.device))
+    if stats:
+        if code not in (0, 6):
+            _check(code, "mgx_decompose_quantize")
+        return out, labels, st.as_dict(), code
     _check(code, "mgx_decompose_quantize")
     return out, labels
 
@@ -548,7 +560,9 @@ class Batch:
     fields: list of dicts with keys
       in (tensor), out (tensor), coords (per-axis list or None), stop_level,
       tol (with labels), c_linf, labels (int32 tensor or None), coef (tensor or
-      None: recompose from labels; None reads the labels in the level kernels).
+      None: recompose from labels; None reads the labels in the level kernels),
+      stats (decompose with labels: True asks for the field's quantization
+      statistics, read back with stats() after decompose()).
     The same Batch object (same tensors) replays the captured graph; the
     workspace is allocated once per Batch.
     """
@@ -556,6 +570,8 @@ class Batch:
     def __init__(self, fields, workspace=None):
         import torch
         self._keep = []
+        self._stats = {}
+        self.code = 0
         n = len(fields)
         self.arr = (Field * n)()
         dev = None
@@ -583,6 +599,10 @@ class Batch:
             x.labels = lab.data_ptr() if lab is not None else None
             coef = f.get("coef")
             x.coef = coef.data_ptr() if coef is not None else None
+            if f.get("stats"):
+                st = QuantStats()
+                self._stats[i] = st
+                x.stats = ctypes.cast(ctypes.byref(st), ctypes.c_void_p)
             self._keep.extend([t for t in (t_in, t_out, lab, coef) if t is not None])
         self.n = n
         self.device = dev
@@ -594,12 +614,27 @@ class Batch:
         self.ws_bytes = self.workspace.numel() * self.workspace.element_size()
 
     def decompose(self):
-        _check(lib().mgx_decompose_batched(self.n, self.arr, self.workspace.data_ptr(), self.ws_bytes,
-                                           _stream(self.device)), "mgx_decompose_batched")
+        """Raises MgxError unless the status is 0, or 6 (MGX_ERR_RANGE) with
+        statistics asked for (then kept in self.code; see stats())."""
+        code = lib().mgx_decompose_batched(self.n, self.arr, self.workspace.data_ptr(), self.ws_bytes,
+                                           _stream(self.device))
+        self.code = code
+        if not (code == 6 and self._stats):
+            _check(code, "mgx_decompose_batched")
+
+    def stats(self):
+        """{field index: statistics dict} of the fields that asked for them."""
+        return {i: st.as_dict() for i, st in self._stats.items()}
 
     def recompose(self):
         _check(lib().mgx_recompose_batched(self.n, self.arr, self.workspace.data_ptr(), self.ws_bytes,
                                            _stream(self.device)), "mgx_recompose_batched")
+
+
+def release_cached() -> None:
+    """Free the library's cached level plans and batch graphs (no other call
+    of the library may be running)."""
+    _check(lib().mgx_release_cached(), "mgx_release_cached")
 
 
 def batch_set_autotune(on: bool) -> None:

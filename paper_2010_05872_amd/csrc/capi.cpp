@@ -333,6 +333,8 @@ mgx_status run_decompose(Plan *P, int stop, const T *u, T *umc, char *ws, const 
       s.lab_w = labels;
       s.qc = qa->q[l - stop];
       s.rqc = label_rcp_host(s.qc);
+      s.rng = qa->stats_ovf;  // [0] overflow, [1] non-finite (stats_nan follows it)
+      s.smax = qa->stats_max ? qa->stats_max + (l - stop) : nullptr;
     }
     hipError_t e = em.op(kOpLoadVecDec, 0, labels ? "load_vector_dec+q" : "load_vector_dec", l, o);
     if (e != hipSuccess) return MGX_ERR_HIP;
@@ -360,6 +362,8 @@ mgx_status run_decompose(Plan *P, int stop, const T *u, T *umc, char *ws, const 
       o.tl.lab_w = labels;
       for (int i = 0; i < o.tl.nlev; i++) o.tl.q[i] = qa->q[lay.lt - i - stop];
       o.tl.q[o.tl.nlev] = qa->q[0];
+      o.tl.rng = qa->stats_ovf;
+      o.tl.smax = qa->stats_max;
     }
     if (em.op(kOpTailDec, 0, labels ? "tail_dec+q" : "tail_dec", lay.lt, o) != hipSuccess) return MGX_ERR_HIP;
   } else if (labels) {  // the stop box's labels, after the last level
@@ -907,144 +911,26 @@ void quant_box(const Plan *P, QuantArgs &qa, int level = -1) {
   (void)L;
 }
 
-// ---- fused quantization: the finest level on a second stream ----
-// The finest level holds 7/8 of the coefficients and is complete after its
-// first kernel, while the coarser levels are many small latency-bound
-// launches; quantizing (or dequantizing) the finest level on a library
-// stream overlaps the two.  Results are those of the separate calls.
-struct SideStreams {
-  std::mutex mu;
-  std::vector<hipStream_t> st;
-  std::vector<hipEvent_t> ev;  // per device: fork and join events
-};
-SideStreams &side_streams() {
-  static SideStreams *s = new SideStreams();
-  return *s;
-}
-
-// Locks the side-stream state of the current device (held by the caller for
-// the whole enqueue sequence) and returns its stream and two events.
-mgx_status side_stream(std::unique_lock<std::mutex> &lk, hipStream_t *q, hipEvent_t *fork, hipEvent_t *join) {
-  SideStreams &S = side_streams();
-  lk = std::unique_lock<std::mutex>(S.mu);
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return MGX_ERR_HIP;
-  if ((int)S.st.size() <= dev) {
-    S.st.resize(dev + 1, nullptr);
-    S.ev.resize(2 * (dev + 1), nullptr);
-  }
-  if (!S.st[dev]) {
-    if (hipStreamCreateWithFlags(&S.st[dev], hipStreamNonBlocking) != hipSuccess) return MGX_ERR_HIP;
-    for (int i = 0; i < 2; i++)
-      if (hipEventCreateWithFlags(&S.ev[2 * dev + i], hipEventDisableTiming) != hipSuccess) return MGX_ERR_HIP;
-  }
-  *q = S.st[dev];
-  *fork = S.ev[2 * dev];
-  *join = S.ev[2 * dev + 1];
-  return MGX_OK;
-}
-
-// Overlap of the finest level's (de)quantization with the coarse levels on
-// a second stream: measured slower than running the two in sequence on this
-// part (the side pass takes every compute unit and the latency-bound coarse
-// kernels wait for slots), so off by default.
-#ifndef MGX_FUSED_OVERLAP
-#define MGX_FUSED_OVERLAP 0
-#endif
-
+// The fused calls: the level kernels write (decomposition) or read
+// (recomposition) the labels themselves.
 template <typename T>
 mgx_status run_decompose_quantize(Plan *P, int stop, const T *u, T *umc, int32_t *labels, QuantArgs qa, char *ws,
                                   const Layout &lay, const T *tab, hipStream_t st) {
-  if (!MGX_FUSED_OVERLAP || !umc) {  // labels written by the level kernels themselves
-    Emitter<T> em;
-    em.st = st;
-    return run_decompose<T>(P, stop, u, umc, ws, lay, tab, em, labels, &qa);
-  }
-  const int L = P->L;
-  std::unique_lock<std::mutex> lk;
-  hipStream_t q;
-  hipEvent_t fork, join;
-  mgx_status s = side_stream(lk, &q, &fork, &join);
-  if (s) return s;
-  QuantArgs fine = qa, rest = qa;
-  fine.sel_lo = fine.sel_hi = L;
-  fine.max_blocks = MGX_SIDE_BLOCKS;
-  rest.sel_hi = L - 1;
-  if (L > 0) quant_box(P, rest);
-  bool forked = false;
-  // The finest level's coefficients are final once its first kernel ran;
-  // its quantization starts after the level's last kernel, when the stream
-  // turns to the small latency-bound levels.
-  auto fork_quantize = [&]() -> hipError_t {
-    forked = true;
-    hipError_t e = hipEventRecord(fork, st);
-    if (e == hipSuccess) e = hipStreamWaitEvent(q, fork, 0);
-    if (e == hipSuccess)
-      e = traced("quantize_finest", -1, q, [&] { return launch_quantize<T>(umc, labels, fine, false, q); });
-    if (e == hipSuccess) e = hipEventRecord(join, q);
-    return e;
-  };
   Emitter<T> em;
   em.st = st;
-  em.before = [&](int kind, int level) -> hipError_t {
-    (void)kind;
-    return (!forked && level < L) ? fork_quantize() : hipSuccess;
-  };
-  s = run_decompose<T>(P, stop, u, umc, ws, lay, tab, em);
-  if (s) return s;
-  if (!forked && fork_quantize() != hipSuccess) return MGX_ERR_HIP;
-  if (rest.sel_hi >= rest.sel_lo &&
-      traced("quantize_coarse", -1, st, [&] { return launch_quantize<T>(umc, labels, rest, false, st); }) !=
-          hipSuccess)
-    return MGX_ERR_HIP;
-  return hip_status(hipStreamWaitEvent(st, join, 0));
+  return run_decompose<T>(P, stop, u, umc, ws, lay, tab, em, labels, &qa);
 }
 
 template <typename T>
 mgx_status run_dequantize_recompose(Plan *P, int stop, const int32_t *labels, T *umc, T *u, QuantArgs qa,
                                     char *ws, const Layout &lay, const T *tab, hipStream_t st) {
-  if (!MGX_FUSED_OVERLAP || !umc) {
-    Emitter<T> em;
-    em.st = st;
-    if (!umc)  // coefficients read from the labels by the level kernels
-      return run_recompose<T>(P, stop, nullptr, u, ws, lay, tab, em, labels, &qa);
-    if (traced("dequantize", -1, st, [&] { return launch_dequantize<T>(labels, umc, qa, st); }) != hipSuccess)
-      return MGX_ERR_HIP;
-    return run_recompose<T>(P, stop, umc, u, ws, lay, tab, em);
-  }
-  const int L = P->L;
-  std::unique_lock<std::mutex> lk;
-  hipStream_t q;
-  hipEvent_t fork, join;
-  mgx_status s = side_stream(lk, &q, &fork, &join);
-  if (s) return s;
-  QuantArgs fine = qa, rest = qa;
-  fine.sel_lo = fine.sel_hi = L;
-  fine.max_blocks = MGX_SIDE_BLOCKS;
-  rest.sel_hi = L - 1;
-  if (L > 0) quant_box(P, rest);
-  // the coarse levels first (small; the recomposition starts with them),
-  // then the finest level beside the coarse recomposition
-  if (rest.sel_hi >= rest.sel_lo &&
-      traced("dequantize_coarse", -1, st, [&] { return launch_dequantize<T>(labels, umc, rest, st); }) != hipSuccess)
-    return MGX_ERR_HIP;
-  if (hipEventRecord(fork, st) != hipSuccess || hipStreamWaitEvent(q, fork, 0) != hipSuccess) return MGX_ERR_HIP;
-  if (traced("dequantize_finest", -1, q, [&] { return launch_dequantize<T>(labels, umc, fine, q); }) != hipSuccess ||
-      hipEventRecord(join, q) != hipSuccess)
-    return MGX_ERR_HIP;
-  bool joined = false;
   Emitter<T> em;
   em.st = st;
-  em.before = [&](int kind, int level) -> hipError_t {
-    (void)kind;
-    if (joined || level < L) return hipSuccess;
-    joined = true;  // first launch that reads finest-level coefficients
-    return hipStreamWaitEvent(st, join, 0);
-  };
-  s = run_recompose<T>(P, stop, umc, u, ws, lay, tab, em);
-  if (s) return s;
-  if (!joined) return hip_status(hipStreamWaitEvent(st, join, 0));
-  return MGX_OK;
+  if (!umc)  // coefficients read from the labels by the level kernels
+    return run_recompose<T>(P, stop, nullptr, u, ws, lay, tab, em, labels, &qa);
+  if (traced("dequantize", -1, st, [&] { return launch_dequantize<T>(labels, umc, qa, st); }) != hipSuccess)
+    return MGX_ERR_HIP;
+  return run_recompose<T>(P, stop, umc, u, ws, lay, tab, em);
 }
 
 // ---- batches of fields (multi-field launches in one captured graph) ----
@@ -1099,9 +985,15 @@ mgx_status batch_validate(int nfields, const mgx_field *f, bool dec, std::vector
   return MGX_OK;
 }
 
+// Bytes of one field's statistics slot in a batch: per-level max |label|
+// (kMaxLevels ints) then the overflow and non-finite counts.
+constexpr size_t kStatSlot = 128;
+static_assert(sizeof(int) * kMaxLevels + 2 * sizeof(unsigned long long) <= kStatSlot, "statistics slot");
+
+// stat: the field's statistics slot (device), or null.
 template <typename T>
 mgx_status batch_record(const mgx_field &x, const BatchField &b, char *ws, bool dec,
-                        std::vector<RecordedOp<T>> &ops) {
+                        std::vector<RecordedOp<T>> &ops, char *stat = nullptr) {
   Emitter<T> em;
   em.rec = &ops;
   char *w = ws + b.ws_off;
@@ -1111,6 +1003,11 @@ mgx_status batch_record(const mgx_field &x, const BatchField &b, char *ws, bool 
       Plan *P;
       mgx_status s = quant_args(x.ndim, x.dims, x.coords, x.tol_linf, x.stop_level, x.c_linf, &qa, &P);
       if (s) return s;
+      if (stat) {  // the level kernels reduce their statistics there
+        qa.stats_max = (int *)stat;
+        qa.stats_ovf = (unsigned long long *)(stat + sizeof(int) * kMaxLevels);
+        qa.stats_nan = qa.stats_ovf + 1;
+      }
       return run_decompose<T>(b.P, x.stop_level, (const T *)x.in, (T *)x.out, w, b.lay, (const T *)b.tab, em,
                               x.labels, &qa);
     }
@@ -1200,10 +1097,16 @@ mgx_status batch_plan(std::vector<RecordedOp<T>> ops, const Tuning &tn, std::vec
 struct BatchEntry {
   hipGraphExec_t exec = nullptr;
   void *dev = nullptr;
+  void *stat = nullptr;       // statistics slots of the fields that ask for them
+  std::vector<int> slot;      // per field: its slot, or -1
+  int nslot = 0;
   int launches = 0;
   Tuning tn{};
   double tuned_ms = 0.0;
 };
+
+// A field of a decomposition batch that asks for statistics.
+bool batch_wants_stats(const mgx_field &x, bool dec) { return dec && x.labels && x.stats; }
 
 struct BatchCache {
   std::mutex mu;
@@ -1221,8 +1124,10 @@ thread_local mgx_batch_info g_batch_info{};
 void batch_entry_free(BatchEntry &e) {
   if (e.exec) (void)hipGraphExecDestroy(e.exec);
   if (e.dev) (void)hipFree(e.dev);
+  if (e.stat) (void)hipFree(e.stat);
   e.exec = nullptr;
   e.dev = nullptr;
+  e.stat = nullptr;
 }
 
 // Records every field, plans the launches for tn, uploads the argument
@@ -1231,26 +1136,40 @@ mgx_status batch_build(int nfields, const mgx_field *f, const std::vector<BatchF
                        const Tuning &tn, hipStream_t cs, BatchEntry &out) {
   std::vector<RecordedOp<float>> o32;
   std::vector<RecordedOp<double>> o64;
+  out.slot.assign(nfields, -1);
+  out.nslot = 0;
+  for (int i = 0; i < nfields; i++)
+    if (batch_wants_stats(f[i], dec)) out.slot[i] = out.nslot++;
+  if (out.nslot > 0 && hipMalloc(&out.stat, kStatSlot * out.nslot) != hipSuccess) return MGX_ERR_HIP;
   for (int i = 0; i < nfields; i++) {
-    mgx_status s = f[i].dtype == MGX_F32 ? batch_record<float>(f[i], bf[i], ws, dec, o32)
-                                         : batch_record<double>(f[i], bf[i], ws, dec, o64);
-    if (s) return s;
+    char *stat = out.slot[i] >= 0 ? (char *)out.stat + kStatSlot * out.slot[i] : nullptr;
+    mgx_status s = f[i].dtype == MGX_F32 ? batch_record<float>(f[i], bf[i], ws, dec, o32, stat)
+                                         : batch_record<double>(f[i], bf[i], ws, dec, o64, stat);
+    if (s) {
+      batch_entry_free(out);
+      return s;
+    }
   }
   std::vector<BatchLaunch> launches;
   std::vector<char> blob;
   mgx_status s = batch_plan<float>(o32, tn, launches, blob);
-  if (s) return s;
-  if ((s = batch_plan<double>(o64, tn, launches, blob))) return s;
+  if (!s) s = batch_plan<double>(o64, tn, launches, blob);
   void *dev = nullptr;
-  if (hipMalloc(&dev, blob.size() > 0 ? blob.size() : 256) != hipSuccess) return MGX_ERR_HIP;
+  if (!s && hipMalloc(&dev, blob.size() > 0 ? blob.size() : 256) != hipSuccess) s = MGX_ERR_HIP;
+  if (s) {
+    batch_entry_free(out);
+    return s;
+  }
   if (!blob.empty() && hipMemcpy(dev, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) {
     (void)hipFree(dev);
+    batch_entry_free(out);
     return MGX_ERR_HIP;
   }
   char *d = (char *)dev;
   hipGraph_t graph = nullptr;
   if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     (void)hipFree(dev);
+    batch_entry_free(out);
     return MGX_ERR_HIP;
   }
   hipError_t le = hipSuccess;
@@ -1267,6 +1186,7 @@ mgx_status batch_build(int nfields, const mgx_field *f, const std::vector<BatchF
   if (le != hipSuccess || ce != hipSuccess || !graph) {
     if (graph) (void)hipGraphDestroy(graph);
     (void)hipFree(dev);
+    batch_entry_free(out);
     return MGX_ERR_HIP;
   }
   hipGraphExec_t exec = nullptr;
@@ -1274,6 +1194,7 @@ mgx_status batch_build(int nfields, const mgx_field *f, const std::vector<BatchF
   (void)hipGraphDestroy(graph);
   if (ie != hipSuccess) {
     (void)hipFree(dev);
+    batch_entry_free(out);
     return MGX_ERR_HIP;
   }
   out.exec = exec;
@@ -1302,13 +1223,31 @@ double batch_time(const BatchEntry &e, hipStream_t cs, int reps) {
   return ms;
 }
 
+// The key of a batch's graph: every member the recorded launches depend on
+// (never the struct's raw bytes: its padding and unused entries are
+// arbitrary in a caller's struct, and the stats pointer itself may change
+// from call to call; only whether it is set matters).
 std::string batch_key(int nfields, const mgx_field *f, const void *ws, bool dec, const std::vector<BatchField> &bf) {
   std::string k;
+  auto put = [&](const void *p, size_t n) { k.append((const char *)p, n); };
   k.push_back(dec ? 'D' : 'R');
-  k.append((const char *)&ws, sizeof(ws));
+  put(&ws, sizeof(ws));
   for (int i = 0; i < nfields; i++) {
-    k.append((const char *)&f[i], sizeof(mgx_field));
-    k.append((const char *)&bf[i].P, sizeof(Plan *));  // coordinates by content
+    const mgx_field &x = f[i];
+    put(&x.in, sizeof(x.in));
+    put(&x.out, sizeof(x.out));
+    put(&x.dtype, sizeof(x.dtype));
+    put(&x.ndim, sizeof(x.ndim));
+    for (int a = 0; a < x.ndim && a < 3; a++) put(&x.dims[a], sizeof(int64_t));
+    put(&x.stop_level, sizeof(x.stop_level));
+    put(&x.labels, sizeof(x.labels));
+    if (x.labels) {
+      put(&x.tol_linf, sizeof(x.tol_linf));
+      put(&x.c_linf, sizeof(x.c_linf));
+      if (!dec) put(&x.coef, sizeof(x.coef));
+    }
+    k.push_back(batch_wants_stats(x, dec) ? 'S' : '-');
+    put(&bf[i].P, sizeof(Plan *));  // coordinates by content
   }
   return k;
 }
@@ -1379,9 +1318,40 @@ mgx_status run_batched(int nfields, const mgx_field *f, void *ws, size_t ws_byte
   g_batch_info.target_blocks = e.tn.target_blocks;
   g_batch_info.min_zchunk = e.tn.min_zchunk;
   g_batch_info.tuned_ms = e.tuned_ms;
+  if (e.nslot > 0 && hipMemsetAsync(e.stat, 0, kStatSlot * e.nslot, stream) != hipSuccess) return MGX_ERR_HIP;
   hipError_t le = traced(dec ? "decompose_batched" : "recompose_batched", -2, stream,
                          [&] { return hipGraphLaunch(e.exec, stream); });
-  return hip_status(le);
+  if (le != hipSuccess || e.nslot == 0) return hip_status(le);
+  // statistics (reduced by the level kernels): one read-back
+  std::vector<QuantArgs> qas(nfields);
+  for (int i = 0; i < nfields; i++) {
+    if (e.slot[i] < 0) continue;
+    Plan *P;
+    if ((s = quant_args(f[i].ndim, f[i].dims, f[i].coords, f[i].tol_linf, f[i].stop_level, f[i].c_linf, &qas[i],
+                        &P)))
+      return s;
+  }
+  std::vector<char> host(kStatSlot * e.nslot);
+  if (hipMemcpyAsync(host.data(), e.stat, host.size(), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return MGX_ERR_HIP;
+  bool range = false;
+  for (int i = 0; i < nfields; i++) {
+    if (e.slot[i] < 0) continue;
+    const char *h = host.data() + kStatSlot * e.slot[i];
+    mgx_quant_stats *st = f[i].stats;
+    std::memset(st, 0, sizeof(*st));
+    st->first_level = qas[i].first;
+    st->num_levels = qas[i].nlev;
+    std::memcpy(st->max_abs_label, h, sizeof(int) * qas[i].nlev);
+    unsigned long long ovf, nan;
+    std::memcpy(&ovf, h + sizeof(int) * kMaxLevels, sizeof(ovf));
+    std::memcpy(&nan, h + sizeof(int) * kMaxLevels + sizeof(ovf), sizeof(nan));
+    st->n_overflow = (int64_t)ovf;
+    st->n_nonfinite = (int64_t)nan;
+    range = range || ovf || nan;
+  }
+  return range ? MGX_ERR_RANGE : MGX_OK;
 }
 
 // ---- four-axis fields (the 4-D QMCPACK field of Sec. 6, Table 2) ----
@@ -1584,13 +1554,15 @@ hipError_t solves4(const Level4<T> &lv, T *F, const T *in, T *out, int level, hi
 // write the labels of the values at the destination positions.
 template <typename T>
 hipError_t copy4(const T *src, const int64_t sp[3], T *dst, const int64_t dp[3], const int64_t b[4], int level,
-                 hipStream_t st, const int32_t *lab_r = nullptr, int32_t *lab_w = nullptr, double q = 0.0) {
+                 hipStream_t st, const int32_t *lab_r = nullptr, int32_t *lab_w = nullptr, double q = 0.0,
+                 unsigned long long *rng = nullptr) {
   Copy4Args<T> a{};
   a.src = src;
   a.dst = dst;
   a.lab_r = lab_r;
   a.lab_w = lab_w;
   a.q = q;
+  a.rng = rng;
   for (int k = 0; k < 3; k++) {
     a.sp[k] = sp[k];
     a.dp[k] = dp[k];
@@ -1624,7 +1596,9 @@ mgx_status run_decompose4(const Plan4 &P, int stop, const T *u, T *umc, char *ws
   compact_pitches(P.n, up);
   if (stop == L) {
     if (!labels) return hip_status(hipMemcpyAsync(umc, u, sizeof(T) * N, hipMemcpyDeviceToDevice, st));
-    return copy4<T>(u, up, umc, up, P.n, L, st, nullptr, labels, qa->q[0]) != hipSuccess ? MGX_ERR_HIP : MGX_OK;
+    return copy4<T>(u, up, umc, up, P.n, L, st, nullptr, labels, qa->q[0], qa->stats_ovf) != hipSuccess
+               ? MGX_ERR_HIP
+               : MGX_OK;
   }
   T *A = (T *)(ws + lay.offA), *B = (T *)(ws + lay.offB);
   const T *V = u;
@@ -1640,6 +1614,7 @@ mgx_status run_decompose4(const Plan4 &P, int stop, const T *u, T *umc, char *ws
     if (labels) {
       ca.lab_w = labels;
       ca.qc = qa->q[l - stop];
+      ca.rng = qa->stats_ovf;  // [0] overflow, [1] non-finite (stats_nan follows it)
     }
     for (int k = 0; k < 3; k++) ca.up[k] = up[k];
     ca.ncol = (uint32_t)(m[1] * m[2] * m[3]);
@@ -1660,7 +1635,8 @@ mgx_status run_decompose4(const Plan4 &P, int stop, const T *u, T *umc, char *ws
   int64_t b[4], bp[3];
   for (int k = 0; k < 4; k++) b[k] = P.m(stop, k);
   compact_pitches(b, bp);
-  return copy4<T>(B, bp, umc, up, b, stop, st, nullptr, labels, labels ? qa->q[0] : 0.0) != hipSuccess
+  return copy4<T>(B, bp, umc, up, b, stop, st, nullptr, labels, labels ? qa->q[0] : 0.0,
+                  labels ? qa->stats_ovf : nullptr) != hipSuccess
              ? MGX_ERR_HIP
              : MGX_OK;
 }
@@ -1900,6 +1876,7 @@ const char *mgx_status_string(mgx_status s) {
     case MGX_ERR_RANGE: return "quantization label out of int32 range or non-finite coefficient";
     case MGX_ERR_WORKSPACE: return "workspace missing or too small";
     case MGX_ERR_HIP: return "HIP runtime error";
+    default: break;
   }
   return "unknown status";
 }
@@ -2549,57 +2526,87 @@ int mgx_trace_read(mgx_kernel_time *out, int max) {
 
 mgx_status mgx_decompose_quantize(const void *u, void *u_mc, int32_t *labels, mgx_dtype dtype, int ndim,
                                   const int64_t *dims, const double *const *coords, double tol_linf, int stop_level,
-                                  double c_linf, void *workspace, size_t workspace_bytes, hipStream_t stream) {
+                                  double c_linf, void *workspace, size_t workspace_bytes, mgx_quant_stats *stats,
+                                  hipStream_t stream) {
+  if (!labels) return MGX_ERR_ARG;  // checked before any HIP call
+  // with stats: the statistics buffer (held until it is read back) takes the
+  // level kernels' per-level maxima and out-of-range counts (four axes: the
+  // counts, then one pass over the labels for the maxima)
+  std::unique_lock<std::mutex> stats_lock;
+  char *sbase = nullptr;
+  auto attach = [&](int **mx, unsigned long long **ovf, unsigned long long **nan) -> mgx_status {
+    if (!stats) return MGX_OK;
+    stats_lock = std::unique_lock<std::mutex>(stats_buf().mu);
+    if (!(sbase = stats_device(stream))) return MGX_ERR_HIP;
+    *mx = (int *)sbase;
+    *ovf = (unsigned long long *)(sbase + sizeof(int) * kMaxLevels);
+    *nan = *ovf + 1;
+    return MGX_OK;
+  };
   if (ndim == 4) {  // labels written by the level kernels, u_mc optional
+    Quant4Args qa;
+    mgx_status s4 = quant_args4(dims, coords, tol_linf, stop_level, c_linf, nullptr, &qa);
+    if (s4) return s4;
     Plan4 P4;
     Layout4 lay4;
-    mgx_status s4 = prepare4(u, u_mc, dtype, dims, coords, stop_level, workspace, workspace_bytes, &P4, &lay4, 2);
-    if (s4) return s4;
-    if (!labels) return MGX_ERR_ARG;
+    if ((s4 = prepare4(u, u_mc, dtype, dims, coords, stop_level, workspace, workspace_bytes, &P4, &lay4, 2)))
+      return s4;
     const size_t cnt = (size_t)P4.count(P4.L), es = elem_size(dtype);
     if ((u_mc && overlaps(labels, cnt * 4, u_mc, cnt * es)) || overlaps(labels, cnt * 4, u, cnt * es) ||
         (lay4.total > 0 && overlaps(labels, cnt * 4, workspace, lay4.total)))
       return MGX_ERR_ARG;
-    Quant4Args qa;
-    if ((s4 = quant_args4(dims, coords, tol_linf, stop_level, c_linf, nullptr, &qa))) return s4;
+    int *mx = nullptr;
+    if ((s4 = attach(&mx, &qa.stats_ovf, &qa.stats_nan))) return s4;
     if (dtype == MGX_F32)
-      return run_decompose4<float>(P4, stop_level, (const float *)u, (float *)u_mc, (char *)workspace, lay4, stream,
-                                   labels, &qa);
-    return run_decompose4<double>(P4, stop_level, (const double *)u, (double *)u_mc, (char *)workspace, lay4,
+      s4 = run_decompose4<float>(P4, stop_level, (const float *)u, (float *)u_mc, (char *)workspace, lay4, stream,
+                                 labels, &qa);
+    else
+      s4 = run_decompose4<double>(P4, stop_level, (const double *)u, (double *)u_mc, (char *)workspace, lay4,
                                   stream, labels, &qa);
+    if (s4 || !stats) return s4;
+    if (label_max_abs<Quant4Args>(labels, qa, mx, stream) != hipSuccess) return MGX_ERR_HIP;
+    return stats_read(sbase, qa.first, qa.nlev, stats, stream);
   }
+  if (dtype != MGX_F32 && dtype != MGX_F64) return MGX_ERR_ARG;
+  QuantArgs qa;
+  Plan *Pq;
+  mgx_status s = quant_args(ndim, dims, coords, tol_linf, stop_level, c_linf, &qa, &Pq);
+  if (s) return s;
   Plan *P;
   Layout lay;
   const void *tab;
-  mgx_status s = prepare(u, u_mc, dtype, ndim, dims, coords, stop_level, workspace, workspace_bytes, &P, &lay, &tab,
-                         false, 2);
-  if (s) return s;
-  if (!labels) return MGX_ERR_ARG;
+  if ((s = prepare(u, u_mc, dtype, ndim, dims, coords, stop_level, workspace, workspace_bytes, &P, &lay, &tab, false,
+                   2)))
+    return s;
   const size_t cnt = (size_t)(P->n[0] * P->n[1] * P->n[2]);
   if ((u_mc && overlaps(labels, cnt * 4, u_mc, cnt * elem_size(dtype))) ||
       overlaps(labels, cnt * 4, u, cnt * elem_size(dtype)) ||
       (lay.total > 0 && overlaps(labels, cnt * 4, workspace, lay.total)))
     return MGX_ERR_ARG;
-  QuantArgs qa;
-  Plan *Pq;
-  if ((s = quant_args(ndim, dims, coords, tol_linf, stop_level, c_linf, &qa, &Pq))) return s;
+  if ((s = attach(&qa.stats_max, &qa.stats_ovf, &qa.stats_nan))) return s;  // the level kernels take them all
   if (dtype == MGX_F32)
-    return run_decompose_quantize<float>(P, stop_level, (const float *)u, (float *)u_mc, labels, qa,
-                                         (char *)workspace, lay, (const float *)tab, stream);
-  return run_decompose_quantize<double>(P, stop_level, (const double *)u, (double *)u_mc, labels, qa,
-                                        (char *)workspace, lay, (const double *)tab, stream);
+    s = run_decompose_quantize<float>(P, stop_level, (const float *)u, (float *)u_mc, labels, qa, (char *)workspace,
+                                      lay, (const float *)tab, stream);
+  else
+    s = run_decompose_quantize<double>(P, stop_level, (const double *)u, (double *)u_mc, labels, qa,
+                                       (char *)workspace, lay, (const double *)tab, stream);
+  if (s || !stats) return s;
+  return stats_read(sbase, qa.first, qa.nlev, stats, stream);
 }
 
 mgx_status mgx_dequantize_recompose(const int32_t *labels, void *u_mc, void *u, mgx_dtype dtype, int ndim,
                                     const int64_t *dims, const double *const *coords, double tol_linf,
                                     int stop_level, double c_linf, void *workspace, size_t workspace_bytes,
                                     hipStream_t stream) {
+  if (!labels) return MGX_ERR_ARG;  // labels and tolerance checked before any HIP call
   if (ndim == 4) {  // with u_mc: dequantize into it, then recompose; without: straight from the labels
+    Quant4Args qa;
+    mgx_status s4 = quant_args4(dims, coords, tol_linf, stop_level, c_linf, nullptr, &qa);
+    if (s4) return s4;
     Plan4 P4;
     Layout4 lay4;
-    mgx_status s4 = prepare4(u_mc, u, dtype, dims, coords, stop_level, workspace, workspace_bytes, &P4, &lay4, 1);
-    if (s4) return s4;
-    if (!labels) return MGX_ERR_ARG;
+    if ((s4 = prepare4(u_mc, u, dtype, dims, coords, stop_level, workspace, workspace_bytes, &P4, &lay4, 1)))
+      return s4;
     const size_t cnt = (size_t)P4.count(P4.L), es = elem_size(dtype);
     if ((u_mc && overlaps(labels, cnt * 4, u_mc, cnt * es)) || overlaps(labels, cnt * 4, u, cnt * es) ||
         (lay4.total > 0 && overlaps(labels, cnt * 4, workspace, lay4.total)))
@@ -2610,27 +2617,26 @@ mgx_status mgx_dequantize_recompose(const int32_t *labels, void *u_mc, void *u, 
         return s4;
       return recompose4(u_mc, u, dtype, dims, coords, stop_level, workspace, workspace_bytes, stream);
     }
-    Quant4Args qa;
-    if ((s4 = quant_args4(dims, coords, tol_linf, stop_level, c_linf, nullptr, &qa))) return s4;
     if (dtype == MGX_F32)
       return run_recompose4<float>(P4, stop_level, nullptr, (float *)u, (char *)workspace, lay4, stream, labels, &qa);
     return run_recompose4<double>(P4, stop_level, nullptr, (double *)u, (char *)workspace, lay4, stream, labels, &qa);
   }
+  if (dtype != MGX_F32 && dtype != MGX_F64) return MGX_ERR_ARG;
+  QuantArgs qa;
+  Plan *Pq;
+  mgx_status s = quant_args(ndim, dims, coords, tol_linf, stop_level, c_linf, &qa, &Pq);
+  if (s) return s;
   Plan *P;
   Layout lay;
   const void *tab;
-  mgx_status s = prepare(u_mc, u, dtype, ndim, dims, coords, stop_level, workspace, workspace_bytes, &P, &lay, &tab,
-                         false, 1);
-  if (s) return s;
-  if (!labels) return MGX_ERR_ARG;
+  if ((s = prepare(u_mc, u, dtype, ndim, dims, coords, stop_level, workspace, workspace_bytes, &P, &lay, &tab, false,
+                   1)))
+    return s;
   const size_t cnt = (size_t)(P->n[0] * P->n[1] * P->n[2]);
   if ((u_mc && overlaps(labels, cnt * 4, u_mc, cnt * elem_size(dtype))) ||
       overlaps(labels, cnt * 4, u, cnt * elem_size(dtype)) ||
       (lay.total > 0 && overlaps(labels, cnt * 4, workspace, lay.total)))
     return MGX_ERR_ARG;
-  QuantArgs qa;
-  Plan *Pq;
-  if ((s = quant_args(ndim, dims, coords, tol_linf, stop_level, c_linf, &qa, &Pq))) return s;
   if (dtype == MGX_F32)
     return run_dequantize_recompose<float>(P, stop_level, labels, (float *)u_mc, (float *)u, qa, (char *)workspace,
                                            lay, (const float *)tab, stream);
@@ -2653,6 +2659,26 @@ mgx_status mgx_decompose_batched(int nfields, const mgx_field *fields, void *wor
 mgx_status mgx_recompose_batched(int nfields, const mgx_field *fields, void *workspace, size_t workspace_bytes,
                                  hipStream_t stream) {
   return run_batched(nfields, fields, workspace, workspace_bytes, stream, false);
+}
+
+mgx_status mgx_release_cached(void) {
+  bool err = false;
+  {
+    BatchCache &C = batch_cache();
+    std::lock_guard<std::mutex> g(C.mu);
+    if (!C.map.empty()) {
+      int cur = 0, ndev = 0;
+      if (hipGetDevice(&cur) != hipSuccess || hipGetDeviceCount(&ndev) != hipSuccess) return MGX_ERR_HIP;
+      for (int d = 0; d < ndev; d++)  // graphs may still run on any device
+        if (hipSetDevice(d) != hipSuccess || hipDeviceSynchronize() != hipSuccess) err = true;
+      if (hipSetDevice(cur) != hipSuccess) err = true;
+      for (auto &kv : C.map) batch_entry_free(kv.second);
+      C.map.clear();
+      C.order.clear();
+    }
+  }
+  if (release_plans()) err = true;
+  return err ? MGX_ERR_HIP : MGX_OK;
 }
 
 mgx_status mgx_batch_set_autotune(int on) {

@@ -44,10 +44,11 @@ unsigned grid_of(int64_t n) {
   return (unsigned)(g > 0 ? g : 1);
 }
 
-// Largest |label| of every level (an overflowed label, INT32_MIN, counts as 2^31).
+// Largest |label| of every level (an overflowed label, INT32_MIN, counts as
+// 2^31, or with SKIP_OUT as 0: the quantizer's statistics leave it out).
 // A: the (de)quantization arguments of a 1-D to 3-D (QuantArgs) or 4-D
 // (Quant4Args) field; elem_level(i, a) gives the level of flat element i.
-template <typename A>
+template <typename A, bool SKIP_OUT>
 __global__ void __launch_bounds__(kThreads) k_ent_range(const int32_t *__restrict__ labels, A a,
                                                         unsigned *__restrict__ maxabs) {
   __shared__ unsigned s_max[kMaxLevelsK];
@@ -61,7 +62,7 @@ __global__ void __launch_bounds__(kThreads) k_ent_range(const int32_t *__restric
     const bool in = i < (uint64_t)a.n;
     const int l = in ? elem_level((uint32_t)i, a) : a.first;
     const int32_t v = in ? labels[i] : 0;
-    const unsigned m = v < 0 ? 0u - (unsigned)v : (unsigned)v;
+    const unsigned m = (SKIP_OUT && v == INT32_MIN) ? 0u : v < 0 ? 0u - (unsigned)v : (unsigned)v;
     unsigned long long todo = __ballot(in);
     while (todo) {
       const int leader = __ffsll((long long)todo) - 1;
@@ -299,7 +300,7 @@ hipError_t label_entropy(const int32_t *labels, const A &qa, const int64_t *leve
   Parts p = carve(ws);
   hipError_t e;
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, p.maxabs, (int64_t)kMaxLevelsK);
-  hipLaunchKernelGGL((k_ent_range<A>), dim3(grid_of(qa.n)), dim3(kThreads), 0, st, labels, qa, p.maxabs);
+  hipLaunchKernelGGL((k_ent_range<A, false>), dim3(grid_of(qa.n)), dim3(kThreads), 0, st, labels, qa, p.maxabs);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   std::vector<unsigned> mx(kMaxLevelsK);
   if ((e = hipMemcpyAsync(mx.data(), p.maxabs, sizeof(unsigned) * kMaxLevelsK, hipMemcpyDeviceToHost, st)) !=
@@ -355,6 +356,15 @@ hipError_t label_entropy(const int32_t *labels, const A &qa, const int64_t *leve
   return hipSuccess;
 }
 
+template <typename A>
+hipError_t label_max_abs(const int32_t *labels, const A &qa, int *max_abs, hipStream_t st) {
+  hipLaunchKernelGGL((k_ent_range<A, true>), dim3(grid_of(qa.n)), dim3(kThreads), 0, st, labels, qa,
+                     (unsigned *)max_abs);
+  return hipGetLastError();
+}
+
+template hipError_t label_max_abs<QuantArgs>(const int32_t *, const QuantArgs &, int *, hipStream_t);
+template hipError_t label_max_abs<Quant4Args>(const int32_t *, const Quant4Args &, int *, hipStream_t);
 template hipError_t label_entropy<QuantArgs>(const int32_t *, const QuantArgs &, const int64_t *, char *,
                                              hipStream_t, double *);
 template hipError_t label_entropy<Quant4Args>(const int32_t *, const Quant4Args &, const int64_t *, char *,

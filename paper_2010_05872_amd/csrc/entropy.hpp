@@ -16,4 +16,9 @@ size_t entropy_workspace(int64_t n, int nlev);
 template <typename A>
 hipError_t label_entropy(const int32_t *labels, const A &qa, const int64_t *level_count, char *ws, hipStream_t st,
                          double *bits_out);
+// max_abs[i] (device, zeroed by the caller) = largest |label| of level
+// qa.first + i, leaving out INT32_MIN labels (out-of-range coefficients).
+// Asynchronous on st.
+template <typename A>
+hipError_t label_max_abs(const int32_t *labels, const A &qa, int *max_abs, hipStream_t st);
 }  // namespace mgx

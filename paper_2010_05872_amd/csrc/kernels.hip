@@ -124,30 +124,6 @@ __device__ __forceinline__ void st_at(T *base, uint32_t byte_off, T v) {
   *(T *)((char *)base + byte_off) = v;
 }
 
-// Accesses of data that one pass writes or reads exactly once (outputs of
-// the level kernels, the coefficients read by the interpolation): with
-// MGX_STREAM_HINT bit 0 (stores) / bit 1 (loads) they carry the
-// non-temporal cache hint.
-#ifndef MGX_STREAM_HINT
-#define MGX_STREAM_HINT 0
-#endif
-template <typename T>
-__device__ __forceinline__ void st_once(T *base, uint32_t byte_off, T v) {
-#if MGX_STREAM_HINT & 1
-  __builtin_nontemporal_store(v, (T *)((char *)base + byte_off));
-#else
-  *(T *)((char *)base + byte_off) = v;
-#endif
-}
-template <typename T>
-__device__ __forceinline__ T ld_once(const T *base, uint32_t byte_off) {
-#if MGX_STREAM_HINT & 2
-  return __builtin_nontemporal_load((const T *)((const char *)base + byte_off));
-#else
-  return *(const T *)((const char *)base + byte_off);
-#endif
-}
-
 // The quantizer's decision for one coefficient: rint(c / q) in FP64 (a
 // correctly rounded division, ties to even), INT32_MIN when out of range or
 // not finite -- the same operations as the quantization pass, so labels
@@ -190,6 +166,15 @@ __device__ __forceinline__ int32_t label_of(T v, double q, float rq) {
   const int32_t l = label_fast(v, rq, ok);
   if (__builtin_expect(ok, 1)) return l;
   return label_of<T>(v, q);
+}
+// Counts a coefficient whose label is INT32_MIN: rng[0] when c/q is finite
+// (|c/q| >= 2^31 - 1), rng[1] when it is not.  Callers reach it only where the
+// label came from the FP64 division, which fields without such coefficients
+// take rarely or never.
+template <typename T>
+__device__ __forceinline__ void count_out_of_range(unsigned long long *rng, T v, double q) {
+  const double t = (double)v / q;
+  atomicAdd(&rng[(isnan(t) || isinf(t)) ? 1 : 0], 1ull);
 }
 // A coefficient from its label (the dequantization pass's operations).
 template <typename T>
@@ -266,7 +251,9 @@ __device__ __forceinline__ int opaque(int v) {
 // de-interleaved in LDS (even columns first), so both the restriction and
 // the interpolation corners read consecutive LDS words.  Planes are fetched
 // DEPTH iterations ahead into register buffers.
-template <typename T, int TX, int TY, int NT, bool DEC, bool LAB>
+// LAB: 0 no labels; 1 labels (decompose: written, recompose: read); 2
+// (decompose) labels and the largest |label| written, reduced into a.smax.
+template <typename T, int TX, int TY, int NT, bool DEC, int LAB>
 __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const int lb) {
   constexpr int HR = 2 * TY + 5;  // region rows incl. halo and the extension
   constexpr int W = 2 * TX + 5;   // region row pitch
@@ -412,6 +399,7 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
   const int rowOdd = (int)(c1 * a.up1) * (int)sizeof(T);  // level-centric shift of odd rows (bytes)
   const int colOdd = c2 * (int)sizeof(T);                   // ... and of odd columns
 
+  int lmax = 0;  // LAB == 2: largest |label| this thread wrote
   T acc[3][NOUT];
 #pragma unroll
   for (int s = 0; s < 3; s++)
@@ -455,11 +443,13 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
         for (int p = p0; p < 4; p++) {
           const uint32_t off = oE + ((p & 1) ? colOdd : 0u) + ((p & 2) ? rowOdd : 0u);
           if ((f >> p) & 1u) {
-            if (wc) st_once(cbase, off, cv[p]);
+            if (wc) st_at(cbase, off, cv[p]);
             if (LAB) {
               bool ok;
-              st_at(lbase, lab_off<T>(off), label_fast(cv[p], rq, ok));
+              const int32_t lf = label_fast(cv[p], rq, ok);
+              st_at(lbase, lab_off<T>(off), lf);
               slow |= (unsigned)!ok << p;
+              if (LAB == 2) lmax = max(lmax, lf < 0 ? -lf : lf);  // 0 where !ok
             }
           }
         }
@@ -468,7 +458,10 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
           for (int p = p0; p < 4; p++)
             if ((slow >> p) & 1u) {
               const uint32_t off = oE + ((p & 1) ? colOdd : 0u) + ((p & 2) ? rowOdd : 0u);
-              st_at(lbase, lab_off<T>(off), label_of<T>(cv[p], a.qc));
+              const int32_t lab = label_of<T>(cv[p], a.qc);
+              st_at(lbase, lab_off<T>(off), lab);
+              if (lab == INT32_MIN && a.rng) count_out_of_range(a.rng, cv[p], a.qc);
+              if (LAB == 2 && lab != INT32_MIN) lmax = max(lmax, lab < 0 ? -lab : lab);
             }
         }
       };
@@ -543,7 +536,7 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
         T *const fbase = a.F + (int64_t)Zdone * a.fp0;
 #pragma unroll
         for (int k = 0; k < NOUT; k++)
-          if ((yact >> k) & 1u) st_once(fbase, (uint32_t)foff[k], acc[0][k]);
+          if ((yact >> k) & 1u) st_at(fbase, (uint32_t)foff[k], acc[0][k]);
       }
 #pragma unroll
       for (int k = 0; k < NOUT; k++) {
@@ -580,9 +573,13 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
 #pragma unroll
   for (int d = 0; d < DEPTH - 1; d++)
     if (j + d <= jend) plane(j + d, st[d]);
+  if (LAB == 2) {  // the level's largest |label|: one atomic per wave
+    for (int off = 32; off > 0; off >>= 1) lmax = max(lmax, __shfl_xor(lmax, off));
+    if ((tid & 63) == 0 && lmax > 0) atomicMax(a.smax, lmax);
+  }
 }
 
-template <typename T, int TX, int TY, int NT, bool DEC, bool LAB>
+template <typename T, int TX, int TY, int NT, bool DEC, int LAB>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(DEC ? MGX_STENCIL_WAVES : MGX_REC_WAVES, 8)))
 k_load_vector(StencilArgs<T> a) {
   load_vector_body<T, TX, TY, NT, DEC, LAB>(a, xcd_remap(blockIdx.x, gridDim.x));
@@ -1029,13 +1026,13 @@ __device__ __forceinline__ void interp_add_body(const InterpArgs<T> a, const int
       const T *be = a.umc + pe, *bo = a.umc + po;
 #pragma unroll
       for (int k = 0; k < NB; k++) {
-        cv[k][0] = ld_once(be, (uint32_t)bEO[k]);
-        cv[k][1] = ld_once(be, (uint32_t)bOE[k]);
-        cv[k][2] = ld_once(be, (uint32_t)bOO[k]);
-        cv[k][3] = ld_once(bo, (uint32_t)bEE[k]);
-        cv[k][4] = ld_once(bo, (uint32_t)bEO[k]);
-        cv[k][5] = ld_once(bo, (uint32_t)bOE[k]);
-        cv[k][6] = ld_once(bo, (uint32_t)bOO[k]);
+        cv[k][0] = ld_at(be, (uint32_t)bEO[k]);
+        cv[k][1] = ld_at(be, (uint32_t)bOE[k]);
+        cv[k][2] = ld_at(be, (uint32_t)bOO[k]);
+        cv[k][3] = ld_at(bo, (uint32_t)bEE[k]);
+        cv[k][4] = ld_at(bo, (uint32_t)bEO[k]);
+        cv[k][5] = ld_at(bo, (uint32_t)bOE[k]);
+        cv[k][6] = ld_at(bo, (uint32_t)bOO[k]);
       }
     }
   };
@@ -1062,20 +1059,20 @@ __device__ __forceinline__ void interp_add_body(const InterpArgs<T> a, const int
       const T e10 = wyl * A00 + wyr * A10;
       const T e11 = wyl * ea + wyr * eb;
       const uint32_t o0 = (uint32_t)bOut[k];
-      if (f & 1u) st_once(oe, o0, A00);
-      if (f & 2u) st_once(oe, o0 + ES, cv[k][0] + ea);
-      if (f & 4u) st_once(oe, o0 + outRow, cv[k][1] + e10);
-      if (f & 8u) st_once(oe, o0 + outRow + ES, cv[k][2] + e11);
+      if (f & 1u) st_at(oe, o0, A00);
+      if (f & 2u) st_at(oe, o0 + ES, cv[k][0] + ea);
+      if (f & 4u) st_at(oe, o0 + outRow, cv[k][1] + e10);
+      if (f & 8u) st_at(oe, o0 + outRow + ES, cv[k][2] + e11);
       if (odd_in) {
         const T B00 = sN[sb][n], B01 = sN[sb][n + 1], B10 = sN[sb][n + NW], B11 = sN[sb][n + NW + 1];
         const T fa = wxl * B00 + wxr * B01;
         const T fb = wxl * B10 + wxr * B11;
         const T f10 = wyl * B00 + wyr * B10;
         const T f11 = wyl * fa + wyr * fb;
-        if (f & 1u) st_once(oo, o0, cv[k][3] + (wzl * A00 + wzr * B00));
-        if (f & 2u) st_once(oo, o0 + ES, cv[k][4] + (wzl * ea + wzr * fa));
-        if (f & 4u) st_once(oo, o0 + outRow, cv[k][5] + (wzl * e10 + wzr * f10));
-        if (f & 8u) st_once(oo, o0 + outRow + ES, cv[k][6] + (wzl * e11 + wzr * f11));
+        if (f & 1u) st_at(oo, o0, cv[k][3] + (wzl * A00 + wzr * B00));
+        if (f & 2u) st_at(oo, o0 + ES, cv[k][4] + (wzl * ea + wzr * fa));
+        if (f & 4u) st_at(oo, o0 + outRow, cv[k][5] + (wzl * e10 + wzr * f10));
+        if (f & 8u) st_at(oo, o0 + outRow + ES, cv[k][6] + (wzl * e11 + wzr * f11));
       }
     }
     // loads for step J+AH after every store of this step (partial waits later)
@@ -1575,6 +1572,11 @@ __device__ __forceinline__ void quantize_body(const T *__restrict__ umc, int32_t
       }
     }
   }
+  if (!STATS && a.stats_ovf) {
+    // out-of-range counts without the other statistics (rare: per thread)
+    if (my_ovf) atomicAdd(a.stats_ovf, my_ovf);
+    if (my_nan) atomicAdd(a.stats_nan, my_nan);
+  }
   if (STATS) {
     for (int off = 32; off > 0; off >>= 1) {
       my_ovf += __shfl_xor(my_ovf, off);
@@ -1655,6 +1657,7 @@ __device__ __forceinline__ void quantize_box_body(const T *__restrict__ umc, int
   if (threadIdx.x < kMaxLevelsK) s_q[threadIdx.x] = a.q[threadIdx.x];
   __syncthreads();
   const uint32_t B = (uint32_t)a.bn;
+  int lmax = 0;  // largest |label| written (kept when one level is selected and stats_max is set)
   for (uint32_t i = (uint32_t)b * 256u + threadIdx.x; i < B; i += (uint32_t)nb * 256u) {
     const uint32_t row = (uint32_t)__umul64hi((uint64_t)i, a.bmag2);
     const uint32_t x = i - row * (uint32_t)a.b2;
@@ -1666,7 +1669,15 @@ __device__ __forceinline__ void quantize_box_body(const T *__restrict__ umc, int
     if (l < a.sel_lo || l > a.sel_hi) continue;
     const uint32_t idx = (z * (uint32_t)a.n1 + y) * (uint32_t)a.n2 + x;
     const double t = (double)umc[a.box_compact ? i : idx] / s_q[l - a.first];
-    labels[idx] = !(fabs(t) < 2147483647.0) ? INT32_MIN : (int32_t)rint(t);
+    const bool out = !(fabs(t) < 2147483647.0);
+    const int32_t lab = out ? INT32_MIN : (int32_t)rint(t);
+    labels[idx] = lab;
+    if (out && a.stats_ovf) atomicAdd((isnan(t) || isinf(t)) ? a.stats_nan : a.stats_ovf, 1ull);
+    if (!out) lmax = max(lmax, lab < 0 ? -lab : lab);
+  }
+  if (a.stats_max && a.sel_lo == a.sel_hi) {  // every lane reaches this point
+    for (int off = 32; off > 0; off >>= 1) lmax = max(lmax, __shfl_xor(lmax, off));
+    if ((threadIdx.x & 63) == 0 && lmax > 0) atomicMax(&a.stats_max[a.sel_lo - a.first], lmax);
   }
 }
 
@@ -1850,7 +1861,7 @@ static bool tile_grid(int c0, int c1, int c2, int TX, int TY, int *ntx, int *nty
   return true;
 }
 
-template <typename T, typename TL, bool DEC, bool LAB>
+template <typename T, typename TL, bool DEC, int LAB>
 hipError_t launch_load_vector_t(StencilArgs<T> a, hipStream_t st, Tuning tn) {
   constexpr int TX = TL::TX, TY = TL::TY, NT = TL::NT;
   if (!tile_grid(a.ax[0].c, a.ax[1].c, a.ax[2].c, TX, TY, &a.ntx, &a.nty, &a.nzc, &a.tz, tn))
@@ -1863,11 +1874,12 @@ hipError_t launch_load_vector_t(StencilArgs<T> a, hipStream_t st, Tuning tn) {
 template <typename T>
 hipError_t launch_load_vector(StencilArgs<T> a, bool dec, hipStream_t st, Tuning tn) {
   if (dec) {
-    if (a.lab_w) return launch_load_vector_t<T, DecTiles<T>, true, true>(a, st, tn);
-    return launch_load_vector_t<T, DecTiles<T>, true, false>(a, st, tn);
+    if (a.lab_w && a.smax) return launch_load_vector_t<T, DecTiles<T>, true, 2>(a, st, tn);
+    if (a.lab_w) return launch_load_vector_t<T, DecTiles<T>, true, 1>(a, st, tn);
+    return launch_load_vector_t<T, DecTiles<T>, true, 0>(a, st, tn);
   }
-  if (a.lab_r) return launch_load_vector_t<T, RecLabTiles<T>, false, true>(a, st, tn);
-  return launch_load_vector_t<T, Tiles<T>, false, false>(a, st, tn);
+  if (a.lab_r) return launch_load_vector_t<T, RecLabTiles<T>, false, 1>(a, st, tn);
+  return launch_load_vector_t<T, Tiles<T>, false, 0>(a, st, tn);
 }
 
 // Large levels take the one-plane-per-workgroup interpolation (compact store
@@ -2033,7 +2045,6 @@ hipError_t launch_quantize(const T *umc, int32_t *labels, QuantArgs a, bool stat
     return hipGetLastError();
   }
   dim3 grid(quant_grid(a.n));
-  if (a.max_blocks > 0 && grid.x > (unsigned)a.max_blocks) grid.x = (unsigned)a.max_blocks;
   const bool vec = aligned16(umc) && aligned16(labels);
   if (stats) {
     if (vec)
@@ -2058,7 +2069,6 @@ hipError_t launch_dequantize(const int32_t *labels, T *umc, QuantArgs a, hipStre
     return hipGetLastError();
   }
   dim3 grid(quant_grid(a.n));
-  if (a.max_blocks > 0 && grid.x > (unsigned)a.max_blocks) grid.x = (unsigned)a.max_blocks;
   if (aligned16(umc) && aligned16(labels))
     hipLaunchKernelGGL((k_dequantize<T, true>), grid, dim3(256), 0, st, labels, umc, a);
   else
@@ -2245,6 +2255,7 @@ __device__ __forceinline__ void tail_dec_body(const TailArgs<T> &a) {
     __syncthreads();
   }
   const T *V = sV;
+  int lmax = 0;  // with a.smax: largest |label| of the current level written by this thread
   for (int i = 0; i < a.nlev; i++) {
     const TailAxis<T>(&ax)[3] = tabs[i];
     const int m1 = ax[1].m, m2 = ax[2].m, c0 = ax[0].c, c1 = ax[1].c, c2 = ax[2].c;
@@ -2258,8 +2269,15 @@ __device__ __forceinline__ void tail_dec_body(const TailArgs<T> &a) {
       const T v = V[q] - tail_interp<T>(V, 2 * m1 * m2, 2 * m2, 2, ax, j0, j1, j2);
       const int64_t pos = lcp(j0, c0) * a.up0 + lcp(j1, c1) * a.up1 + lcp(j2, c2);
       if (a.umc) a.umc[pos] = v;
-      if (a.lab_w) a.lab_w[pos] = label_of(v, a.q[i], label_rcp(a.q[i]));
+      if (a.lab_w) {
+        const int32_t lab = label_of(v, a.q[i], label_rcp(a.q[i]));
+        a.lab_w[pos] = lab;
+        if (lab == INT32_MIN && a.rng) count_out_of_range(a.rng, v, a.q[i]);
+        if (lab != INT32_MIN) lmax = max(lmax, lab < 0 ? -lab : lab);
+      }
     }
+    if (a.smax && lmax > 0) atomicMax(&a.smax[a.nlev - i], lmax);  // level lt - i; the tail is small
+    lmax = 0;
     // Q_{l-1} u = Mc^{-1} (R M)^{x3} V (as in the tiled decomposition)
     T *F = (i & 1) ? fB : fA;
     tail_load_vector<T>(ax, V, g1, g2, F);
@@ -2269,8 +2287,14 @@ __device__ __forceinline__ void tail_dec_body(const TailArgs<T> &a) {
         const int X = q % c2, r = q / c2, Y = r % c1, Z = r / c1;
         const int64_t pos = Z * a.up0 + Y * a.up1 + X;
         if (a.umc) a.umc[pos] = F[q];
-        if (a.lab_w) a.lab_w[pos] = label_of(F[q], a.q[a.nlev], label_rcp(a.q[a.nlev]));
+        if (a.lab_w) {
+          const int32_t lab = label_of(F[q], a.q[a.nlev], label_rcp(a.q[a.nlev]));
+          a.lab_w[pos] = lab;
+          if (lab == INT32_MIN && a.rng) count_out_of_range(a.rng, F[q], a.q[a.nlev]);
+          if (lab != INT32_MIN) lmax = max(lmax, lab < 0 ? -lab : lab);
+        }
       }
+      if (a.smax && lmax > 0) atomicMax(&a.smax[0], lmax);
     }
     V = F;
   }
@@ -2377,7 +2401,7 @@ __device__ __forceinline__ int find_op(const int *__restrict__ start, int n, int
   return lo;
 }
 
-template <typename T, int TX, int TY, int NT, bool DEC, bool LAB>
+template <typename T, int TX, int TY, int NT, bool DEC, int LAB>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(DEC ? MGX_STENCIL_WAVES : MGX_REC_WAVES, 8)))
 k_load_vector_multi(MultiArgs<T> m) {
   const int g = xcd_remap(blockIdx.x, gridDim.x);
@@ -2453,12 +2477,12 @@ __global__ void __launch_bounds__(256) k_copy_box_multi(MultiArgs<T> m) {
   copy_box_body<T>(m.args[f].cp, g - m.start[f], m.start[f + 1] - m.start[f]);
 }
 
-template <typename T, bool VEC>
+template <typename T, bool VEC, bool STATS>
 __global__ void __launch_bounds__(256) k_quantize_multi(MultiArgs<T> m) {
   const int g = blockIdx.x;
   const int f = find_op(m.start, m.n, g);
   const QuantJob<T> &j = m.args[f].qj;
-  quantize_body<T, false, VEC>(j.umc, j.labels, j.a, g - m.start[f], m.start[f + 1] - m.start[f]);
+  quantize_body<T, STATS, VEC>(j.umc, j.labels, j.a, g - m.start[f], m.start[f + 1] - m.start[f]);
 }
 
 template <typename T, bool VEC>
@@ -2560,11 +2584,13 @@ template <typename T>
 int op_key(int kind, int mode, const OpArgs<T> &a) {
   switch (kind) {
     case kOpSolveContig: return a.so.c;
-    case kOpLoadVecDec: return a.st.lab_w ? 1 : 0;
+    case kOpLoadVecDec: return a.st.lab_w ? (a.st.smax ? 2 : 1) : 0;
     case kOpLoadVecRec: return a.st.lab_r ? 1 : 0;
     case kOpInterpAdd: return (interp_plane(a.ia) ? 1 : 0) | (a.ia.lab ? 2 : 0);
     case kOpSolveStrided: return (a.sd.c << 4) | (mode << 1) | (strided_deep(a.sd) ? 1 : 0);
-    case kOpQuantize: return a.qj.a.box ? 2 : (aligned16(a.qj.umc) && aligned16(a.qj.labels));
+    // flat passes with statistics (per-level maxima and counts): 4 | vector form
+    case kOpQuantize:
+      return a.qj.a.box ? 2 : ((a.qj.a.stats_max ? 4 : 0) | (aligned16(a.qj.umc) && aligned16(a.qj.labels)));
     case kOpDequantize: return a.dj.a.box ? 2 : (aligned16(a.dj.umc) && aligned16(a.dj.labels));
     default: return 0;
   }
@@ -2579,7 +2605,8 @@ hipError_t launch_op(int kind, int mode, OpArgs<T> a, const Tuning &tn, hipStrea
     case kOpSolveContig: return launch_solve_contig<T>(a.so, st);
     case kOpSolveStrided: return launch_solve_strided<T>(a.sd, mode, st);
     case kOpApply: return launch_apply<T>(a.sd, st);
-    case kOpQuantize: return launch_quantize<T>(a.qj.umc, a.qj.labels, a.qj.a, false, st);
+    case kOpQuantize:  // the flat pass with statistics when they are asked for
+      return launch_quantize<T>(a.qj.umc, a.qj.labels, a.qj.a, !a.qj.a.box && a.qj.a.stats_max != nullptr, st);
     case kOpDequantize: return launch_dequantize<T>(a.dj.labels, a.dj.umc, a.dj.a, st);
     case kOpCopyBox: return launch_copy_box<T>(a.cp, st);
     case kOpTailDec:
@@ -2619,12 +2646,13 @@ hipError_t launch_op_multi(int kind, int key, const OpArgs<T> *dargs, const int 
   MultiArgs<T> m{dargs, dstart, n};
   switch (kind) {
     case kOpLoadVecDec:
-      if (key) MGX_MULTI((k_load_vector_multi<T, TX, TY, NT, true, true>), NT);
-      else MGX_MULTI((k_load_vector_multi<T, TX, TY, NT, true, false>), NT);
+      if (key == 2) MGX_MULTI((k_load_vector_multi<T, TX, TY, NT, true, 2>), NT);
+      else if (key) MGX_MULTI((k_load_vector_multi<T, TX, TY, NT, true, 1>), NT);
+      else MGX_MULTI((k_load_vector_multi<T, TX, TY, NT, true, 0>), NT);
       break;
     case kOpLoadVecRec:
-      if (key) MGX_MULTI((k_load_vector_multi<T, TX, TY, NT, false, true>), NT);
-      else MGX_MULTI((k_load_vector_multi<T, TX, TY, NT, false, false>), NT);
+      if (key) MGX_MULTI((k_load_vector_multi<T, TX, TY, NT, false, 1>), NT);
+      else MGX_MULTI((k_load_vector_multi<T, TX, TY, NT, false, 0>), NT);
       break;
     case kOpInterpAdd: {
       constexpr int IX = InterpTiles<T>::TX, IY = InterpTiles<T>::TY, INT = InterpTiles<T>::NT;
@@ -2642,9 +2670,13 @@ hipError_t launch_op_multi(int kind, int key, const OpArgs<T> *dargs, const int 
     case kOpTailDec: MGX_MULTI((k_tail_dec_multi<T>), kTailThreads); break;
     case kOpTailRec: MGX_MULTI((k_tail_rec_multi<T>), kTailThreads); break;
     case kOpQuantize:
-      if (key == 2) MGX_MULTI((k_quantize_box_multi<T>), 256);
-      else if (key) MGX_MULTI((k_quantize_multi<T, true>), 256);
-      else MGX_MULTI((k_quantize_multi<T, false>), 256);
+      switch (key) {
+        case 2: MGX_MULTI((k_quantize_box_multi<T>), 256); break;
+        case 1: MGX_MULTI((k_quantize_multi<T, true, false>), 256); break;
+        case 5: MGX_MULTI((k_quantize_multi<T, true, true>), 256); break;
+        case 4: MGX_MULTI((k_quantize_multi<T, false, true>), 256); break;
+        default: MGX_MULTI((k_quantize_multi<T, false, false>), 256); break;
+      }
       break;
     case kOpDequantize:
       if (key == 2) MGX_MULTI((k_dequantize_box_multi<T>), 256);

@@ -39,6 +39,10 @@ struct StencilArgs {
   const int32_t *lab_r;       // recompose: read labels instead of coefficients
   double qc;                  // bin width q_l of the level's coefficients (labels)
   float rqc;                  // 1/q_l rounded to FP32 (NaN outside FP32's normal range)
+  // decompose with labels: counts of coefficients whose label is INT32_MIN,
+  // [0] finite |c/q| >= 2^31 - 1, [1] c/q not finite (null: not counted)
+  unsigned long long *rng;
+  int *smax;                  // decompose with labels: the level's max |label| (atomicMax; null: not taken)
   int ntx, nty, nzc, tz;      // set by the launcher
 };
 
@@ -160,6 +164,9 @@ struct TailArgs {
   int32_t *lab_w;                // decompose: also (umc null: only) write labels
   const int32_t *lab_r;          // recompose: read labels instead of coefficients
   double q[kTailMax + 1];        // bin widths: q[i] of level lt - i, q[nlev] of the stop box
+  unsigned long long *rng;       // decompose: out-of-range counts as StencilArgs::rng (nullable)
+  int *smax;                     // decompose: max |label| per level from the stop level up:
+                                 // smax[nlev - i] of level lt - i, smax[0] of the stop box (nullable)
 };
 
 struct QuantArgs {
@@ -173,23 +180,16 @@ struct QuantArgs {
   int b1, b2;
   int64_t bn;                 // b0 * b1 * b2
   uint64_t bmag1, bmag2;      // ceil(2^64 / b1), ceil(2^64 / b2)
-  int max_blocks;             // > 0: at most this many workgroups (work running beside other kernels)
   int box_compact;            // box mode: the coefficient side is a compact b0 x b1 x b2 buffer
   double q[kMaxLevelsK];      // bin width per level
   int *stats_max;             // [nlev] device
+  // out-of-range counts, added to whenever they are set (nullable)
   unsigned long long *stats_ovf, *stats_nan;
 };
 
 // Launch shape of the tiled stencil kernels: the workgroups a launch aims
 // for, and the fewest coarse planes one workgroup marches through on large
 // levels (smaller levels take one coarse plane per workgroup).
-// Workgroups of a (de)quantization pass that runs on the library's second
-// stream beside the coarse levels; 0: the pass's full grid (a capped grid
-// leaves compute units to the main stream but makes the pass the longer
-// branch, measured slower at every cap tried).
-#ifndef MGX_SIDE_BLOCKS
-#define MGX_SIDE_BLOCKS 0
-#endif
 #ifndef MGX_TUNE_TARGET
 #define MGX_TUNE_TARGET 2048
 #endif

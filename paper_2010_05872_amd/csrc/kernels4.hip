@@ -22,11 +22,6 @@
 #include "kernels4.hpp"
 #include "levelpos4.hpp"
 
-// plane pairs per iteration of the coefficient kernels' march
-#ifndef MGX_MARCH_UNROLL
-#define MGX_MARCH_UNROLL 1
-#endif
-
 namespace mgx {
 namespace {
 
@@ -37,6 +32,13 @@ template <typename T>
 __device__ __forceinline__ int32_t label4(T v, double q) {
   const double t = (double)v / q;
   return !(fabs(t) < 2147483647.0) ? INT32_MIN : (int32_t)rint(t);
+}
+// A label of INT32_MIN counted: rng[0] for a finite |c/q| >= 2^31 - 1,
+// rng[1] for a c/q that is not finite.
+template <typename T>
+__device__ __forceinline__ void count_range4(unsigned long long *rng, T v, double q) {
+  const double t = (double)v / q;
+  atomicAdd(&rng[(isnan(t) || isinf(t)) ? 1 : 0], 1ull);
 }
 // (the product is rounded on its own, never contracted into a following add)
 template <typename T>
@@ -54,7 +56,7 @@ __device__ __forceinline__ T unlabel4(int32_t l, double q) {
 // after it, so every value of the level box is read about once.
 template <typename T, bool DEC, bool LAB>
 __global__ void __launch_bounds__(256) k_coef4(Coef4Args<T> a) {
-  const int m0 = a.ax[0].m, m1 = a.ax[1].m, m2 = a.ax[2].m, m3 = a.ax[3].m;
+  const int m1 = a.ax[1].m, m2 = a.ax[2].m, m3 = a.ax[3].m;
   const int c1 = a.ax[1].c, c2 = a.ax[2].c, c3 = a.ax[3].c;
   const uint32_t col = blockIdx.x * 256u + threadIdx.x;
   if (col >= a.ncol) return;
@@ -112,7 +114,11 @@ __global__ void __launch_bounds__(256) k_coef4(Coef4Args<T> a) {
   // decompose: store coefficient c at u_mc offset u (and / or its label)
   auto put = [&](int64_t u, T c) {
     if (!LAB || umc_w) umc_w[u] = c;
-    if (LAB) lab_w[u] = label4<T>(c, a.qc);
+    if (LAB) {
+      const int32_t l = label4<T>(c, a.qc);
+      lab_w[u] = l;
+      if (l == INT32_MIN && a.rng) count_range4(a.rng, c, a.qc);
+    }
   };
   // recompose: the coefficient at u_mc offset u
   auto get = [&](int64_t u) { return LAB ? unlabel4<T>(lab_r[u], a.qc) : umc_r[u]; };
@@ -123,9 +129,8 @@ __global__ void __launch_bounds__(256) k_coef4(Coef4Args<T> a) {
   const int J1 = min(npair, J0 + a.jchunk);
   const bool last = J1 == npair;
   T qprev = Q(DEC ? 2 * J0 : J0);
-  // MGX_MARCH_UNROLL pairs per iteration (unrolling measured slower for the
+  // one plane pair per iteration (unrolling measured slower for the
   // recomposition kernel, equal for the decomposition)
-  int J = J0;
   auto pair = [&](int J) {
     const int je = 2 * J;
     const T qnext = Q(DEC ? je + 2 : J + 1);
@@ -142,13 +147,10 @@ __global__ void __launch_bounds__(256) k_coef4(Coef4Args<T> a) {
     }
     qprev = qnext;
   };
-  for (; J + MGX_MARCH_UNROLL - 1 < J1; J += MGX_MARCH_UNROLL) {
-#pragma unroll
-    for (int k = 0; k < MGX_MARCH_UNROLL; k++) pair(J + k);
-  }
-  for (; J < J1; J++) pair(J);
+  for (int J = J0; J < J1; J++) pair(J);
   if (!last) return;
   // the last (even) plane
+  const int J = J1;
   const int je = 2 * J;
   if (DEC) {
     if (odd) put((int64_t)J * a.up[0] + ucol, V[je * plane + vcol] - qprev);
@@ -241,7 +243,11 @@ __global__ void __launch_bounds__(256) k_copy4(Copy4Args<T> a) {
     const int64_t di = j[0] * a.dp[0] + j[1] * a.dp[1] + j[2] * a.dp[2] + j[3];
     const T v = a.lab_r ? unlabel4<T>(a.lab_r[si], a.q) : a.src[si];
     if (a.dst) a.dst[di] = v;
-    if (a.lab_w) a.lab_w[di] = label4<T>(v, a.q);
+    if (a.lab_w) {
+      const int32_t l = label4<T>(v, a.q);
+      a.lab_w[di] = l;
+      if (l == INT32_MIN && a.rng) count_range4(a.rng, v, a.q);
+    }
   }
 }
 

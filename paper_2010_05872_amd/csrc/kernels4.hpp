@@ -59,6 +59,9 @@ struct Coef4Args {
   int32_t *lab_w;
   const int32_t *lab_r;
   double qc;
+  // decompose with labels: counts of labels set to INT32_MIN, [0] finite
+  // |c/q| >= 2^31 - 1, [1] c/q not finite (null: not counted)
+  unsigned long long *rng;
 };
 
 // One load-vector sweep R M along one axis: in (outer, m, inner) ->
@@ -105,6 +108,7 @@ struct Copy4Args {
   const int32_t *lab_r;
   int32_t *lab_w;
   double q;
+  unsigned long long *rng;  // with lab_w: out-of-range counts as Coef4Args::rng (nullable)
 };
 
 // Quantization of a 4-D u_mc (level-centric layout), Sec. 4.1: the level of

@@ -276,6 +276,31 @@ const void *Plan::device_tables(int device, bool fp64, int *hip_err) {
   return vec[device];
 }
 
+int release_plans() {
+  Cache &C = cache();
+  std::lock_guard<std::mutex> g(C.mu);
+  int err = 0, cur = -1;
+  bool any = false;
+  for (auto &kv : C.plans) {
+    Plan &p = *kv.second;
+    std::lock_guard<std::mutex> gd(p.dev_mu);
+    for (std::vector<void *> *v : {&p.dtab64, &p.dtab32})
+      for (size_t d = 0; d < v->size(); d++)
+        if ((*v)[d]) {
+          if (!any && hipGetDevice(&cur) != hipSuccess) cur = -1;
+          any = true;
+          // the tables may still be read by work enqueued on that device
+          if (hipSetDevice((int)d) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
+              hipFree((*v)[d]) != hipSuccess)
+            err = 1;
+          (*v)[d] = nullptr;
+        }
+  }
+  C.plans.clear();
+  if (any && cur >= 0 && hipSetDevice(cur) != hipSuccess) err = 1;
+  return err;
+}
+
 Plan *get_plan(int ndim, const int64_t *dims, const double *const *coords, int *status) {
   int64_t n[3];
   bool real[3];

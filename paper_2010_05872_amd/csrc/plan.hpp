@@ -73,7 +73,13 @@ struct Plan {
 int parse_shape(int ndim, const int64_t *dims, int64_t n[3], bool real[3], int *L);
 
 // Looks up or builds the plan for (ndim, dims, coords).  Returns nullptr and
-// sets *status on invalid coordinates.
+// sets *status on invalid coordinates.  Plans live until release_plans().
 Plan *get_plan(int ndim, const int64_t *dims, const double *const *coords, int *status);
+
+// Drops every cached plan and frees its device tables (after synchronizing
+// each device that holds some; the current device is restored).  No other
+// call of the library may run meanwhile.  Returns nonzero if the HIP runtime
+// reported an error.
+int release_plans();
 
 }  // namespace mgx

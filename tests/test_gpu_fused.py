@@ -148,3 +148,87 @@ def test_fused_labels_near_ties():
     pos = lab.cpu().numpy()[np.ix_(*lc)]
     want = np.rint(host.astype(np.float64) / q).astype(np.int32)
     assert np.array_equal(pos[coef_node], want[coef_node])
+
+
+RANGE_CASES = [
+    ((17, 17, 17), torch.float32, 0),    # every level in the single-workgroup tail
+    ((65, 65, 65), torch.float32, 0),    # tiled levels, then the tail
+    ((65, 65, 65), torch.float32, 4),    # the stop box by the corner-box pass
+    ((33, 65), torch.float64, 0),
+    ((33, 33, 33), torch.float32, 4),    # stop = L: one flat pass
+    ((9, 9, 9, 9), torch.float32, 0),    # four axes
+    ((9, 17, 9, 9), torch.float64, 2),
+]
+
+
+def _range_field(shape, dt, bad):
+    u = torch.as_tensor(workloads.gaussian_random_field(shape, slope=3.0, seed=12), dtype=dt, device="cuda")
+    if bad:
+        mid = tuple(n // 2 for n in shape)
+        u[mid] = float("nan")
+        u[(1,) * len(shape)] = 1e30 if dt == torch.float32 else 1e300
+    return u
+
+
+@pytest.mark.parametrize("case", RANGE_CASES, ids=lambda c: f"{'x'.join(map(str, c[0]))}-{str(c[1])[6:]}-stop{c[2]}")
+@pytest.mark.parametrize("bad", [True, False])
+def test_fused_range_reporting(case, bad):
+    """The fused call with statistics reports what the separate quantization
+    reports: the same labels, the same per-level max |label|, the same
+    overflow and non-finite counts, and MGX_ERR_RANGE exactly when they are
+    nonzero (a NaN and a huge value in the input spread to many
+    coefficients)."""
+    shape, dt, stop = case
+    print(f"[fused range] {shape} {dt} stop={stop} bad={bad}", flush=True)
+    u = _range_field(shape, dt, bad)
+    tol = 1e-3
+    for keep in (True, False):
+        _, lab, st, code = mgx.decompose_quantize(u, tol, None, stop, keep_coef=keep, stats=True)
+        umc = mgx.decompose(u, None, stop)
+        rlab, rst, rcode = mgx.quantize(umc, tol, None, stop, stats=True)
+        torch.cuda.synchronize()
+        assert torch.equal(lab, rlab)
+        assert st == rst, (st, rst)
+        assert code == rcode == (6 if bad else 0)
+        if bad:
+            assert st["n_nonfinite"] > 0 and st["n_overflow"] > 0
+        # without statistics the same labels come back and no status is raised
+        _, lab2 = mgx.decompose_quantize(u, tol, None, stop, keep_coef=keep)
+        torch.cuda.synchronize()
+        assert torch.equal(lab2, rlab)
+
+
+def test_batched_range_reporting():
+    """Batched decomposition with labels: the fields that ask for statistics
+    get the single-field call's, and the call returns MGX_ERR_RANGE when one
+    of them overflowed; replaying the batch on clean inputs clears it."""
+    print("[fused range] batched", flush=True)
+    specs = [((17, 17, 17), torch.float32, 0, True), ((65, 33, 65), torch.float32, 0, False),
+             ((33, 65), torch.float64, 1, True), ((65, 65, 65), torch.float32, 4, False)]
+    us = [_range_field(s, dt, bad) for s, dt, _, bad in specs]
+    outs = [torch.empty_like(u) for u in us]
+    labs = [torch.empty(u.shape, dtype=torch.int32, device="cuda") for u in us]
+    b = mgx.Batch([dict(**{"in": u}, out=o, stop_level=stop, tol=1e-3, labels=lab, stats=(i != 1))
+                   for i, (u, o, lab, (_, _, stop, _)) in enumerate(zip(us, outs, labs, specs))])
+    b.decompose()
+    torch.cuda.synchronize()
+    assert b.code == 6
+    got = b.stats()
+    assert sorted(got) == [0, 2, 3]
+    for i in got:
+        _, lab, st, code = mgx.decompose_quantize(us[i], 1e-3, None, specs[i][2], stats=True)
+        torch.cuda.synchronize()
+        assert torch.equal(labs[i], lab)
+        assert got[i] == st, (i, got[i], st)
+        assert code == (6 if specs[i][3] else 0)
+    # the same batch on clean inputs: statistics cleared, status OK
+    for u, (s, dt, _, bad) in zip(us, specs):
+        if bad:
+            u.copy_(_range_field(s, dt, False))
+    b.decompose()
+    torch.cuda.synchronize()
+    assert b.code == 0
+    for i, st in b.stats().items():
+        assert st["n_overflow"] == 0 and st["n_nonfinite"] == 0
+        _, _, ref, _ = mgx.decompose_quantize(us[i], 1e-3, None, specs[i][2], stats=True)
+        assert st == ref

@@ -176,6 +176,11 @@ def test_determinism():
     assert torch.equal(a, b)
     ra, rb = mgx.recompose(a), mgx.recompose(a)
     assert torch.equal(ra, rb)
+    # the same after the library's caches (plans, device tables) are dropped
+    torch.cuda.synchronize()
+    mgx.release_cached()
+    assert torch.equal(mgx.decompose(u), a)
+    assert torch.equal(mgx.recompose(a), ra)
 
 
 def test_error_status_on_device_calls():
