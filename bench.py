@@ -365,6 +365,117 @@ def four_d_section(torch, mgx, workloads, dev, reps):
     return out
 
 
+def _event_ms(torch, fn, reps):
+    """Mean ms per call of fn() from HIP events on the current stream (where
+    the library launches)."""
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def _dominant(mgx, torch, fn, reps, shape, L, s):
+    """The longest kernel of fn() by HIP events (per launch), its algorithmic
+    bytes and HBM rate."""
+    mgx.trace_enable(True)
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    kt = mgx.trace_read()
+    mgx.trace_enable(False)
+    dom = max(kt, key=lambda k: k["total_ms"])
+    avg = dom["total_ms"] / dom["count"]
+    alg = algorithmic_bytes(dom["name"], dom["level"], shape, L, s)
+    return {"kernel": f"{dom['name']}@level{dom['level']}", "avg_launch_ms": round(avg, 5),
+            "algorithmic_bytes_per_launch": alg, "achieved": round(alg / (avg * 1e-3) / 1e9, 1),
+            "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(alg / (avg * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+
+
+def config1_section(torch, mgx, workloads, dev, reps):
+    """65^3 fp64 sum of three sinusoids plus noise, full decomposition (L = 5,
+    to 3^3), tau = 1e-3 * range: the four separate operations (launch-bound,
+    2.2 MB: the field stays in the caches)."""
+    u = torch.as_tensor(workloads.sinusoid_field(65), dtype=torch.float64, device=dev)
+    tol = 1e-3 * float((u.max() - u.min()).item())
+    ws = torch.empty(mgx.workspace_size(mgx.MGX_F64, u.shape, 0), dtype=torch.uint8, device=dev)
+    umc, uq, ut = torch.empty_like(u), torch.empty_like(u), torch.empty_like(u)
+    lab = torch.empty(u.shape, dtype=torch.int32, device=dev)
+    ops = {"decompose": lambda: mgx.decompose(u, out=umc, workspace=ws),
+           "quantize": lambda: mgx.quantize(umc, tol, out=lab),
+           "dequantize": lambda: mgx.dequantize(lab, tol, torch.float64, out=uq),
+           "recompose": lambda: mgx.recompose(uq, out=ut, workspace=ws)}
+    ms = {k: _event_ms(torch, f, reps) for k, f in ops.items()}
+    err = float((ut - u).abs().max().item())
+    nb = u.numel() * 8
+    return {"shape": [65, 65, 65], "dtype": "f64", "tau_over_range": 1e-3,
+            "op_ms": {k: round(v, 4) for k, v in ms.items()},
+            "op_GBps": {k: round(nb / (v * 1e-3) / 1e9, 2) for k, v in ms.items()},
+            "dec_rec_GBps": round(2 * nb / ((ms["decompose"] + ms["recompose"]) * 1e-3) / 1e9, 2),
+            "max_err_over_tau": round(err / tol, 5)}
+
+
+def config2_variants_section(torch, mgx, u, labels, ut, ws, reps):
+    """The benchmark field at the other tolerances of its configuration
+    (1e-2 and 1e-4 * range, full decomposition) and with the decomposition
+    stopped at level 4 (a 33^3 box kept, at 1e-3 * range): the fused step's
+    time, rate and error."""
+    rng = float((u.max() - u.min()).item())
+    out = {}
+    N = u.numel()
+    for rel, stop in ((1e-2, 0), (1e-4, 0), (1e-3, 4)):
+        tol = rel * rng
+        w = ws if stop == 0 else torch.empty(mgx.workspace_size(mgx.MGX_F32, u.shape, stop), dtype=torch.uint8,
+                                             device=u.device)
+
+        def step():
+            mgx.decompose_quantize(u, tol, None, stop, labels=labels, workspace=w, keep_coef=False)
+            mgx.dequantize_recompose(labels, tol, torch.float32, None, stop, out=ut, workspace=w)
+
+        ms = _event_ms(torch, step, reps)
+        err = float((ut.double() - u.double()).abs().max().item())
+        out[f"tau{rel:g}_stop{stop}"] = {"ms_per_step": round(ms, 4), "GBps": round(2 * N * 4 / (ms * 1e-3) / 1e9, 2),
+                                         "max_err_over_tau": round(err / tol, 5)}
+    return out
+
+
+def config3_section(torch, mgx, workloads, dev, reps):
+    """257 x 1025 x 1025 fp32, tanh-stretched vertical axis (spacing ratio 20),
+    layered log-normal field: decompose and recompose (L = 7, to 3 x 9 x 9),
+    and the fused step at tau = 1e-3 * range, with the roofline figure of the
+    dominant kernel of decompose + recompose."""
+    u, coords = workloads.layered_lognormal_field(device=dev)
+    shape = tuple(u.shape)
+    L = mgx.num_levels(shape)
+    tol = 1e-3 * float((u.max() - u.min()).item())
+    ws = torch.empty(mgx.workspace_size(mgx.MGX_F32, shape, 0), dtype=torch.uint8, device=dev)
+    umc, ut = torch.empty_like(u), torch.empty_like(u)
+    lab = torch.empty(shape, dtype=torch.int32, device=dev)
+    dec = lambda: mgx.decompose(u, coords, out=umc, workspace=ws)  # noqa: E731
+    rec = lambda: mgx.recompose(umc, coords, out=ut, workspace=ws)  # noqa: E731
+    t_dec = _event_ms(torch, dec, reps)
+    t_rec = _event_ms(torch, rec, reps)
+
+    def step():
+        mgx.decompose_quantize(u, tol, coords, labels=lab, workspace=ws, keep_coef=False)
+        mgx.dequantize_recompose(lab, tol, torch.float32, coords, out=ut, workspace=ws)
+
+    t_step = _event_ms(torch, step, reps)
+    err = float((ut.double() - u.double()).abs().max().item())
+    roof = _dominant(mgx, torch, lambda: (dec(), rec()), max(2, reps // 2), shape, L, 4)
+    N = u.numel()
+    out = {"shape": list(shape), "levels": L, "decompose_ms": round(t_dec, 4), "recompose_ms": round(t_rec, 4),
+           "dec_rec_GBps": round(2 * N * 4 / ((t_dec + t_rec) * 1e-3) / 1e9, 2),
+           "fused_step_ms": round(t_step, 4), "fused_step_GBps": round(2 * N * 4 / (t_step * 1e-3) / 1e9, 2),
+           "max_err_over_tau": round(err / tol, 5), "roofline": roof}
+    del u, umc, ut, lab, ws
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -520,6 +631,10 @@ def main():
         "max_err_over_tau": round(err / tol, 5),
     }
     if not args.no_extensions:
+        reps = max(3, args.steps // 4)
+        out["config1"] = config1_section(torch, mgx, workloads, dev, max(5, args.steps))
+        out["config2_variants"] = config2_variants_section(torch, mgx, u, labels, ut, ws, reps)
+        out["config3"] = config3_section(torch, mgx, workloads, dev, reps)
         mgx.decompose(u, out=umc, workspace=ws)
         out["progressive"] = progressive_section(torch, mgx, u, umc, ws, max(3, args.steps // 4))
         out["adaptive"] = adaptive_section(torch, mgx, u, umc, ws, max(3, args.steps // 4))

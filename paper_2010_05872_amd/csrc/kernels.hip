@@ -777,6 +777,117 @@ __device__ __forceinline__ void solve_strided_body(const StridedArgs<T> a, const
   }
 }
 
+// ---------------------------------------------------------------------------
+// k_solve_seg: Thomas solve along a strided axis for lines too long for the
+// two-ended register solve.  Each line is cut into P = blockDim.x / 64
+// segments of SEG nodes (the last segment also takes the final node): one
+// wave per segment, one lane per line, lanes on consecutive lines, i.e. on
+// consecutive contiguous indices (coalesced).  Both sweeps are first-order
+// affine recurrences (forward f'_J = f_J - mult_J f'_{J-1}, backward
+// y_J = invd_J f'_J - qsup_J y_{J+1}); every lane composes the maps of its
+// segment in registers (f'_J = A_J + B_J f'_in, y_J = C_J + D_J y_out), the
+// segments' maps are chained through LDS, and each lane replays its segment
+// with the value entering it.  Every node is read once and written once.
+// ---------------------------------------------------------------------------
+constexpr int kSegMaxWaves = 16;
+
+template <typename T, int SEG, int MODE>
+__device__ __forceinline__ void solve_seg_body(const StridedArgs<T> a, const int b) {
+  __shared__ T sA[kSegMaxWaves][64], sB[kSegMaxWaves][64];
+  const int P = (int)(blockDim.x >> 6);
+  const int lane = (int)(threadIdx.x & 63);
+  const int s = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // wave-uniform: scalar table loads
+  const int64_t line = (int64_t)b * 64 + lane;
+  const bool act = line < (int64_t)a.nx * a.nouter;
+  const int o = act ? (int)(line / a.nx) : 0;
+  const int x = act ? (int)(line - (int64_t)o * a.nx) : 0;
+  T *const p = a.F + (int64_t)o * a.so + x;
+  const int64_t sj = a.sj;
+  const int J0 = s * SEG;
+  const bool last = s == P - 1;  // this segment also holds node c - 1
+  T v[SEG + 1];
+#pragma unroll
+  for (int k = 0; k < SEG; k++) v[k] = act ? p[(int64_t)(J0 + k) * sj] : T(0);
+  v[SEG] = (act && last) ? p[(int64_t)(J0 + SEG) * sj] : T(0);
+  // ---- forward: the segment's map from zero, and its multiplier ----
+  T A = T(0), B = T(1);
+#pragma unroll
+  for (int k = 0; k < SEG; k++) {
+    const T m = ldu(a.mult, J0 + k);  // mult[0] = 0
+    A = v[k] - m * A;
+    B = -m * B;
+    v[k] = A;
+  }
+  if (last) {
+    const T m = ldu(a.mult, J0 + SEG);
+    A = v[SEG] - m * A;
+    B = -m * B;
+    v[SEG] = A;
+  }
+  sA[s][lane] = A;
+  sB[s][lane] = B;
+  __syncthreads();
+  T fin = T(0);
+  for (int t = 0; t < s; t++) fin = sA[t][lane] + sB[t][lane] * fin;
+  __syncthreads();  // sA / sB are reused by the backward exchange
+  {
+    T Bk = T(1);
+#pragma unroll
+    for (int k = 0; k < SEG; k++) {
+      Bk = -ldu(a.mult, J0 + k) * Bk;
+      v[k] = v[k] + Bk * fin;
+    }
+    if (last) {
+      Bk = -ldu(a.mult, J0 + SEG) * Bk;
+      v[SEG] = v[SEG] + Bk * fin;
+    }
+  }
+  // ---- backward: y from the segment's end (qsup[c-1] = 0 ends the line) ----
+  T C = T(0), D = T(1);
+  if (last) {
+    C = ldu(a.invd, J0 + SEG) * v[SEG];
+    D = T(0);
+    v[SEG] = C;
+  }
+#pragma unroll
+  for (int k = SEG - 1; k >= 0; k--) {
+    const T q = ldu(a.qsup, J0 + k);
+    C = ldu(a.invd, J0 + k) * v[k] - q * C;
+    D = -q * D;
+    v[k] = C;
+  }
+  sA[s][lane] = C;
+  sB[s][lane] = D;
+  __syncthreads();
+  T yout = T(0);
+  for (int t = P - 1; t > s; t--) yout = sA[t][lane] + sB[t][lane] * yout;
+  {
+    T Dk = last ? T(0) : T(1);
+#pragma unroll
+    for (int k = SEG - 1; k >= 0; k--) {
+      Dk = -ldu(a.qsup, J0 + k) * Dk;
+      v[k] = v[k] + Dk * yout;
+    }
+  }
+  if (!act) return;
+  auto put = [&](const int J, const T y) {
+    if (MODE == kSolveApply)
+      a.out[(int64_t)J * a.oj + (int64_t)o * a.oo + x] = a.in[(int64_t)J * a.ij + (int64_t)o * a.io + x] + a.sign * y;
+    else if (MODE == kSolveStore)
+      a.out[(int64_t)J * a.oj + (int64_t)o * a.oo + x] = y;
+    else
+      p[(int64_t)J * sj] = y;
+  };
+#pragma unroll
+  for (int k = 0; k < SEG; k++) put(J0 + k, v[k]);
+  if (last) put(J0 + SEG, v[SEG]);
+}
+
+template <typename T, int SEG, int MODE>
+__global__ void __launch_bounds__(64 * kSegMaxWaves) k_solve_seg(StridedArgs<T> a) {
+  solve_seg_body<T, SEG, MODE>(a, blockIdx.x);
+}
+
 template <typename T, int MODE, int CH>
 __global__ void __launch_bounds__(256) k_solve_strided(StridedArgs<T> a) {
   solve_strided_body<T, MODE, CH>(a, blockIdx.x, blockIdx.y);
@@ -1967,6 +2078,19 @@ static void launch_chunked(StridedArgs<T> a, int mode, hipStream_t st) {
     hipLaunchKernelGGL((k_solve_strided<T, kSolveInPlace, CH>), grid, dim3(256), 0, st, a);
 }
 
+// Segment length of the segmented solve (register budget: SEG + 1 values per
+// lane) and whether a line of c nodes takes it: longer than the two-ended
+// solve handles, and at most kSegMaxWaves segments.
+template <typename T>
+constexpr int seg_len() {
+  return sizeof(T) == 8 ? 16 : 32;
+}
+template <typename T>
+static bool strided_seg(int c) {
+  const bool twisted = c <= 129 || (sizeof(T) == 4 && c == 257);
+  return !twisted && c > 2 * seg_len<T>() && (c - 1) % seg_len<T>() == 0 && (c - 1) / seg_len<T>() <= kSegMaxWaves;
+}
+
 template <typename T>
 hipError_t launch_solve_strided(StridedArgs<T> a, int mode, hipStream_t st) {
   // two-ended register solve for lines that fit (half a line in registers)
@@ -1986,8 +2110,22 @@ hipError_t launch_solve_strided(StridedArgs<T> a, int mode, hipStream_t st) {
       break;
     default: break;
   }
-  // longer lines: chunked sweeps; few lines (one wave per SIMD or less) use
-  // deep chunks to keep enough loads in flight
+  // longer lines: segments of the line on the waves of a workgroup when the
+  // line has at most kSegMaxWaves segments
+  if (strided_seg<T>(a.c)) {
+    constexpr int SEG = seg_len<T>();
+    const int P = (a.c - 1) / SEG;
+    dim3 grid((unsigned)(((int64_t)a.nx * a.nouter + 63) / 64));
+    if (mode == kSolveApply)
+      hipLaunchKernelGGL((k_solve_seg<T, SEG, kSolveApply>), grid, dim3(64 * P), 0, st, a);
+    else if (mode == kSolveStore)
+      hipLaunchKernelGGL((k_solve_seg<T, SEG, kSolveStore>), grid, dim3(64 * P), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_solve_seg<T, SEG, kSolveInPlace>), grid, dim3(64 * P), 0, st, a);
+    return hipGetLastError();
+  }
+  // the longest lines: chunked sweeps; few lines (one wave per SIMD or less)
+  // use deep chunks to keep enough loads in flight
   const bool deep = (int64_t)a.nx * a.nouter < (1 << 18);
   constexpr int CS = sizeof(T) == 8 ? 8 : 16;
   constexpr int CD = sizeof(T) == 8 ? MGX_DEEP_CH / 2 : MGX_DEEP_CH;
@@ -2463,6 +2601,13 @@ __global__ void __launch_bounds__(256) k_solve_strided_multi(MultiArgs<T> m) {
   solve_strided_body<T, MODE, CH>(a, b % nbx, b / nbx);
 }
 
+template <typename T, int SEG, int MODE>
+__global__ void __launch_bounds__(64 * kSegMaxWaves) k_solve_seg_multi(MultiArgs<T> m) {
+  const int g = blockIdx.x;
+  const int f = find_op(m.start, m.n, g);
+  solve_seg_body<T, SEG, MODE>(m.args[f].sd, g - m.start[f]);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_apply_multi(MultiArgs<T> m) {
   const int g = blockIdx.x;
@@ -2568,6 +2713,7 @@ int op_blocks(int kind, int mode, OpArgs<T> &a, const Tuning &tn) {
     }
     case kOpSolveStrided: {
       if (strided_twisted<T>(a.sd.c)) return (int)(((int64_t)a.sd.nx * a.sd.nouter + 127) / 128);
+      if (strided_seg<T>(a.sd.c)) return (int)(((int64_t)a.sd.nx * a.sd.nouter + 63) / 64);
       return (int)(((int64_t)a.sd.nx + 255) / 256 * a.sd.nouter);
     }
     case kOpApply: return (a.sd.nx + 255) / 256;
@@ -2717,6 +2863,14 @@ hipError_t launch_op_multi(int kind, int key, const OpArgs<T> *dargs, const int 
               twisted_multi<T, 257>(mode, m, total, st);
               break;
             }
+          }
+          if (strided_seg<T>(c)) {  // one op kind per launch: every line of it has c nodes
+            constexpr int SEG = seg_len<T>();
+            const int NTS = 64 * ((c - 1) / SEG);
+            if (mode == kSolveApply) MGX_MULTI((k_solve_seg_multi<T, SEG, kSolveApply>), NTS);
+            else if (mode == kSolveStore) MGX_MULTI((k_solve_seg_multi<T, SEG, kSolveStore>), NTS);
+            else MGX_MULTI((k_solve_seg_multi<T, SEG, kSolveInPlace>), NTS);
+            break;
           }
           {
             constexpr int CS = sizeof(T) == 8 ? 8 : 16;

@@ -35,6 +35,7 @@ SPECS = [
     ((65, 65, 65), torch.float64, None, 5),   # stop = L: copy only
     ((257, 33, 65), torch.float32, "tanh", 0),
     ((65, 65, 65), torch.float32, "random", 4),  # stop box outside the single-workgroup tail
+    ((1025, 17), torch.float32, None, 0),     # 513-long strided lines: the segmented solve
 ]
 
 

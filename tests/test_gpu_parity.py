@@ -69,6 +69,12 @@ CASES = [
     # shaped like the thin-vertical weather grid (257 x 1025 x 1025, tanh-stretched axis 0) with the
     # contiguous axis cut to 33: fp32 1025-long strided lines on axis 1, the tanh axis 257 long
     ((257, 1025, 33), torch.float32, "tanh"),
+    # strided lines of 513 (fp32) and 257 (fp64) nodes, the segmented solve's longest, as the last
+    # solve; 1025 (fp32) and 513 (fp64) nodes take the chunked sweeps
+    ((1025, 65), torch.float32, "random"),
+    ((513, 33), torch.float64, None),
+    ((2049, 17), torch.float32, "random"),
+    ((1025, 33), torch.float64, None),
 ]
 
 
