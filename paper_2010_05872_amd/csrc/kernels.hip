@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "kernels.hpp"
 #include "levelpos.hpp"
@@ -270,6 +271,8 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
   constexpr int NOUT = (GH * GW + NT - 1) / NT;  // y-restriction outputs per thread
   constexpr int NB = NOUT;                       // 2x2 coefficient blocks per thread
 
+  // a fetched word: a label when recomposing from labels, else a value
+  using R = typename std::conditional<(!DEC && LAB != 0), int32_t, T>::type;
   __shared__ T sV[NV][HR * W];
   // x-restricted rows of the plane, double-buffered by plane parity: the one
   // barrier per plane then separates every LDS write from the reads of the
@@ -315,11 +318,13 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
     else
       goff[k] = in ? (int)(lc_pos(j1, c1) * a.up1 + lc_pos(j2, c2)) * (int)sizeof(T) : 0;
   }
-  // issue the loads of fine plane j into registers (zeros outside).  Every
-  // lane issues every load (masked lanes read a valid element and discard
-  // it), so the number of outstanding memory operations is static and later
-  // waits can be partial.
-  auto fetch = [&](int j, T (&st)[NE]) {
+  // issue the loads of fine plane j into registers.  Every lane issues every
+  // load (masked lanes read a valid element), so the number of outstanding
+  // memory operations is static and later waits can be partial.  The words
+  // are kept raw (labels unconverted, masked lanes unmasked) until the
+  // commit: an operation on a loaded value at the fetch would make the
+  // compiler wait for the load there and drain the prefetch.
+  auto fetch = [&](int j, R (&st)[NE]) {
     const bool pin = j >= 0 && j < m0;
     const T *base = DEC ? a.V + (int64_t)(pin ? j : 0) * a.vp0 : a.umc_r + (pin ? lc_pos(j, c0) : 0) * a.up0;
     const int32_t *lbase = (!DEC && LAB) ? a.lab_r + (pin ? lc_pos(j, c0) : 0) * a.up0 : nullptr;
@@ -327,22 +332,32 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
     // component; their lanes read the plane's first element instead (one
     // shared line) rather than the coarse corner
     const bool skip_nodal = !DEC && !(j & 1);
-    const unsigned keep = skip_nodal ? (valid & ~yxeven) : valid;
 #pragma unroll
     for (int k = 0; k < NE; k++) {
       const uint32_t off = (skip_nodal && ((yxeven >> k) & 1u)) ? 0u : (uint32_t)goff[k];
-      T v;
-      if (!DEC && LAB)
-        v = from_label<T>(ld_at(lbase, lab_off<T>(off)), a.qc);
+      if constexpr (!DEC && LAB)
+        st[k] = ld_at(lbase, lab_off<T>(off));
       else
-        v = ld_at(base, off);
-      st[k] = (pin && ((keep >> k) & 1u)) ? v : T(0);
+        st[k] = ld_at(base, off);
     }
   };
-  auto commit = [&](int slot, const T (&st)[NE]) {
+  // the words of plane j into LDS slot `slot`: zeros outside the grid and,
+  // when recomposing, at nodal nodes; labels times the bin width
+  auto commit = [&](int slot, int j, const R (&st)[NE]) {
+    const bool pin = j >= 0 && j < m0;
+    const bool skip_nodal = !DEC && !(j & 1);
+    const unsigned keep = pin ? (skip_nodal ? (valid & ~yxeven) : valid) : 0u;
 #pragma unroll
-    for (int k = 0; k < NE; k++)
-      if ((inlds >> k) & 1u) sV[slot][loff[k]] = st[k];
+    for (int k = 0; k < NE; k++) {
+      if ((inlds >> k) & 1u) {
+        T v;
+        if constexpr (!DEC && LAB)
+          v = from_label<T>(st[k], a.qc);
+        else
+          v = st[k];
+        sV[slot][loff[k]] = ((keep >> k) & 1u) ? v : T(0);
+      }
+    }
   };
   auto slot_of = [&](int j) { return (j + 4) % NV; };
 
@@ -409,8 +424,8 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
   // one plane of the march; st holds plane j + AHEAD on entry and receives
   // plane j + AHEAD + DEPTH on exit.  The commit of plane j + AHEAD goes to a
   // slot this iteration does not read (last read two iterations ago).
-  auto plane = [&](int j, T (&st)[NE]) {
-    commit(slot_of(j + AHEAD), st);
+  auto plane = [&](int j, R (&st)[NE]) {
+    commit(slot_of(j + AHEAD), j + AHEAD, st);
     const bool plane_in = (j >= 0 && j < m0);
     const int pz = j & 1;
     const int s0 = slot_of(j);
@@ -552,17 +567,17 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
   };
 
   const int jstart = 2 * Z0 - 2, jend = 2 * Z1;  // both even
-  T st[DEPTH][NE];
+  R st[DEPTH][NE];
   {
     // the planes before the march and the first DEPTH planes of it are all
     // requested before the first commit waits
-    T p0[NE], p1[NE];
+    R p0[NE], p1[NE];
     fetch(jstart, p0);
     if (DEC) fetch(jstart + 1, p1);
 #pragma unroll
     for (int d = 0; d < DEPTH; d++) fetch(jstart + AHEAD + d, st[d]);
-    commit(slot_of(jstart), p0);
-    if (DEC) commit(slot_of(jstart + 1), p1);
+    commit(slot_of(jstart), jstart, p0);
+    if (DEC) commit(slot_of(jstart + 1), jstart + 1, p1);
   }
   __syncthreads();
   int j = jstart;
