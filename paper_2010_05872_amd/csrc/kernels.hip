@@ -10,8 +10,10 @@
 //   k_solve_contig      coarse mass-matrix solve along the contiguous axis
 //                       (one wavefront scan of the Thomas recurrences);
 //   k_solve_twisted     solves along the strided axes (two-ended Thomas, one
-//                       line per lane; k_solve_strided for long lines), the
-//                       last one storing Q_{l-1} u = M_c^{-1} F.
+//                       line per lane, up to 129 nodes; k_solve_seg for longer
+//                       lines: segments of a line on the waves of a workgroup;
+//                       k_solve_strided for the longest), the last one storing
+//                       Q_{l-1} u = M_c^{-1} F.
 // Mass apply, restriction and the solve act on different tensor axes, so the
 // three load-vector stencils run first, on the fine grid, and the three
 // solves afterwards on the 8x smaller coarse grid.  Recomposition uses
@@ -58,19 +60,19 @@
 #define MGX_F32_TY 16
 #endif
 #ifndef MGX_F32_DEC_TX
-#define MGX_F32_DEC_TX MGX_F32_TX
+#define MGX_F32_DEC_TX 64
 #endif
 #ifndef MGX_F32_DEC_TY
-#define MGX_F32_DEC_TY MGX_F32_TY
+#define MGX_F32_DEC_TY 8
 #endif
 #ifndef MGX_F32_DEC_NT
 #define MGX_F32_DEC_NT MGX_F32_NT
 #endif
 #ifndef MGX_F32_RECLAB_TX
-#define MGX_F32_RECLAB_TX 64
+#define MGX_F32_RECLAB_TX 32
 #endif
 #ifndef MGX_F32_RECLAB_TY
-#define MGX_F32_RECLAB_TY 8
+#define MGX_F32_RECLAB_TY 16
 #endif
 #ifndef MGX_F32_INTERP_TX
 #define MGX_F32_INTERP_TX 64
@@ -2102,13 +2104,29 @@ constexpr int seg_len() {
 }
 template <typename T>
 static bool strided_seg(int c) {
-  const bool twisted = c <= 129 || (sizeof(T) == 4 && c == 257);
-  return !twisted && c > 2 * seg_len<T>() && (c - 1) % seg_len<T>() == 0 && (c - 1) / seg_len<T>() <= kSegMaxWaves;
+  return c > 129 && (c - 1) % seg_len<T>() == 0 && (c - 1) / seg_len<T>() <= kSegMaxWaves;
+}
+
+template <typename T>
+static hipError_t launch_seg(StridedArgs<T> a, int mode, hipStream_t st) {
+  constexpr int SEG = seg_len<T>();
+  const int P = (a.c - 1) / SEG;
+  dim3 grid((unsigned)(((int64_t)a.nx * a.nouter + 63) / 64));
+  if (mode == kSolveApply)
+    hipLaunchKernelGGL((k_solve_seg<T, SEG, kSolveApply>), grid, dim3(64 * P), 0, st, a);
+  else if (mode == kSolveStore)
+    hipLaunchKernelGGL((k_solve_seg<T, SEG, kSolveStore>), grid, dim3(64 * P), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_solve_seg<T, SEG, kSolveInPlace>), grid, dim3(64 * P), 0, st, a);
+  return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_solve_strided(StridedArgs<T> a, int mode, hipStream_t st) {
-  // two-ended register solve for lines that fit (half a line in registers)
+  // lines of up to 129 nodes: the two-ended register solve (half a line in
+  // registers); longer ones: segments of the line on the waves of a
+  // workgroup (measured faster at 257 fp32 nodes: 34 against 40 us per
+  // in-place pass of the 513^3 field's finest level)
   switch (a.c) {
     case 3: launch_twisted_c<T, 3>(a, mode, st); return hipGetLastError();
     case 5: launch_twisted_c<T, 5>(a, mode, st); return hipGetLastError();
@@ -2117,28 +2135,9 @@ hipError_t launch_solve_strided(StridedArgs<T> a, int mode, hipStream_t st) {
     case 33: launch_twisted_c<T, 33>(a, mode, st); return hipGetLastError();
     case 65: launch_twisted_c<T, 65>(a, mode, st); return hipGetLastError();
     case 129: launch_twisted_c<T, 129>(a, mode, st); return hipGetLastError();
-    case 257:
-      if constexpr (sizeof(T) == 4) {
-        launch_twisted_c<T, 257>(a, mode, st);
-        return hipGetLastError();
-      }
-      break;
     default: break;
   }
-  // longer lines: segments of the line on the waves of a workgroup when the
-  // line has at most kSegMaxWaves segments
-  if (strided_seg<T>(a.c)) {
-    constexpr int SEG = seg_len<T>();
-    const int P = (a.c - 1) / SEG;
-    dim3 grid((unsigned)(((int64_t)a.nx * a.nouter + 63) / 64));
-    if (mode == kSolveApply)
-      hipLaunchKernelGGL((k_solve_seg<T, SEG, kSolveApply>), grid, dim3(64 * P), 0, st, a);
-    else if (mode == kSolveStore)
-      hipLaunchKernelGGL((k_solve_seg<T, SEG, kSolveStore>), grid, dim3(64 * P), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_solve_seg<T, SEG, kSolveInPlace>), grid, dim3(64 * P), 0, st, a);
-    return hipGetLastError();
-  }
+  if (strided_seg<T>(a.c)) return launch_seg<T>(a, mode, st);
   // the longest lines: chunked sweeps; few lines (one wave per SIMD or less)
   // use deep chunks to keep enough loads in flight
   const bool deep = (int64_t)a.nx * a.nouter < (1 << 18);
@@ -2688,7 +2687,7 @@ static int contig_group(int c) {  // G: lanes per line
 
 template <typename T>
 static bool strided_twisted(int c) {
-  return c <= 129 || (sizeof(T) == 4 && c == 257);
+  return c <= 129;
 }
 template <typename T>
 static bool strided_deep(const StridedArgs<T> &a) {
@@ -2873,12 +2872,6 @@ hipError_t launch_op_multi(int kind, int key, const OpArgs<T> *dargs, const int 
         case 65: twisted_multi<T, 65>(mode, m, total, st); break;
         case 129: twisted_multi<T, 129>(mode, m, total, st); break;
         default:
-          if constexpr (sizeof(T) == 4) {
-            if (c == 257) {
-              twisted_multi<T, 257>(mode, m, total, st);
-              break;
-            }
-          }
           if (strided_seg<T>(c)) {  // one op kind per launch: every line of it has c nodes
             constexpr int SEG = seg_len<T>();
             const int NTS = 64 * ((c - 1) / SEG);
