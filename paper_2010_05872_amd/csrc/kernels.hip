@@ -190,6 +190,23 @@ __device__ __forceinline__ uint32_t lab_off(uint32_t off) {
   return sizeof(T) == 4 ? off : off >> 1;
 }
 
+// Two adjacent elements (a at byte offset off, b after it) in one store
+// instruction, or only a.  The pair is aligned to the element size only (the
+// offset of an odd row or an odd plane of an odd-pitch box is not a multiple
+// of twice the element size); gfx9 global stores take such addresses.
+template <typename T>
+__device__ __forceinline__ void st_pair(T *base, uint32_t byte_off, T a, T b, bool two) {
+  typedef T pair_t __attribute__((ext_vector_type(2), aligned(sizeof(T))));
+  if (two) {
+    pair_t v;
+    v.x = a;
+    v.y = b;
+    *(pair_t *)((char *)base + byte_off) = v;
+  } else {
+    *(T *)((char *)base + byte_off) = a;
+  }
+}
+
 // Column of region column q in a de-interleaved LDS row: even columns first,
 // then odd ones (stride-1 reads in the restriction along x).
 template <int TX>
@@ -1308,19 +1325,16 @@ __device__ __forceinline__ void interp_plane_body(const InterpArgs<T> a, const i
   const uint32_t o0 = (uint32_t)(((2 * (Y0 + ba)) * (int)a.op1 + 2 * (X0 + bb)) * ES);
   const uint32_t orow = (uint32_t)((int)a.op1 * ES);
   T *const oe = a.out + (int64_t)(2 * J) * a.op0;
-  st_at(oe, o0, A00);
-  if (q1ok) st_at(oe, o0 + ES, cv0 + ea);
-  if (r1ok) st_at(oe, o0 + orow, cv1 + e10);
-  if (r1ok && q1ok) st_at(oe, o0 + orow + ES, cv2 + e11);
+  // each fine row's even and odd column in one store
+  st_pair(oe, o0, A00, cv0 + ea, q1ok);
+  if (r1ok) st_pair(oe, o0 + orow, cv1 + e10, cv2 + e11, q1ok);
   if (odd_in) {
     const T B00 = sN[1][n], B01 = sN[1][n + 1], B10 = sN[1][n + NW], B11 = sN[1][n + NW + 1];
     const T fa = wxl * B00 + wxr * B01, fb = wxl * B10 + wxr * B11;
     const T f10 = wyl * B00 + wyr * B10, f11 = wyl * fa + wyr * fb;
     T *const oo = a.out + (int64_t)(2 * J + 1) * a.op0;
-    st_at(oo, o0, cv3 + (wzl * A00 + wzr * B00));
-    if (q1ok) st_at(oo, o0 + ES, cv4 + (wzl * ea + wzr * fa));
-    if (r1ok) st_at(oo, o0 + orow, cv5 + (wzl * e10 + wzr * f10));
-    if (r1ok && q1ok) st_at(oo, o0 + orow + ES, cv6 + (wzl * e11 + wzr * f11));
+    st_pair(oo, o0, cv3 + (wzl * A00 + wzr * B00), cv4 + (wzl * ea + wzr * fa), q1ok);
+    if (r1ok) st_pair(oo, o0 + orow, cv5 + (wzl * e10 + wzr * f10), cv6 + (wzl * e11 + wzr * f11), q1ok);
   }
 }
 
