@@ -36,6 +36,7 @@ SPECS = [
     ((257, 33, 65), torch.float32, "tanh", 0),
     ((65, 65, 65), torch.float32, "random", 4),  # stop box outside the single-workgroup tail
     ((1025, 17), torch.float32, None, 0),     # 513-long strided lines: the segmented solve
+    ((33, 65, 129), torch.float32, "random", 0),  # contiguous-axis lines of 65 coarse nodes
 ]
 
 

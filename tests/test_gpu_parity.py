@@ -71,6 +71,9 @@ CASES = [
     ((257, 1025, 33), torch.float32, "tanh"),
     # strided lines of 513 (fp32) and 257 (fp64) nodes, the segmented solve's longest, as the last
     # solve; 1025 (fp32) and 513 (fp64) nodes take the chunked sweeps
+    # 3-D fp32 boxes with wide coarse planes (contiguous-axis lines of 65 and 129 coarse nodes)
+    ((33, 129, 257), torch.float32, "mixed"),
+    ((17, 513, 129), torch.float32, "random"),
     ((1025, 65), torch.float32, "random"),
     ((513, 33), torch.float64, None),
     ((2049, 17), torch.float32, "random"),
