@@ -38,6 +38,9 @@
 #ifndef MGX_INTERP_PLANE
 #define MGX_INTERP_PLANE 1
 #endif
+#ifndef MGX_INTERP_NP
+#define MGX_INTERP_NP 2
+#endif
 #ifndef MGX_INTERP_AHEAD
 #define MGX_INTERP_AHEAD 2
 #endif
@@ -1261,37 +1264,37 @@ __global__ void __launch_bounds__(NT) k_interp_add(InterpArgs<T> a) {
 // ---------------------------------------------------------------------------
 template <typename T, int TX, int TY, int NTP, bool LAB>
 __device__ __forceinline__ void interp_plane_body(const InterpArgs<T> a, const int lb) {
+  constexpr int NP = MGX_INTERP_NP;   // coarse planes per workgroup
   constexpr int NW = TX + 2, NH = TY + 2, BW = TX + 1;
-  constexpr int NNP = (2 * NH * NW + NTP - 1) / NTP;  // nodal loads per thread (planes J, J+1)
+  constexpr int NNP = ((NP + 1) * NH * NW + NTP - 1) / NTP;  // nodal loads per thread (planes J0 .. J0+NP)
   constexpr int ES = (int)sizeof(T);
-  __shared__ T sN[2][NH * NW];
+  __shared__ T sN[NP + 1][NH * NW];
   const int tid = threadIdx.x;
   const int m0 = a.ax[0].m, m1 = a.ax[1].m, m2 = a.ax[2].m;
   const int c0 = a.ax[0].c, c1 = a.ax[1].c, c2 = a.ax[2].c;
   const int tx = lb % a.ntx;
   const int t2 = lb / a.ntx;
   const int ty = t2 % a.nty;
-  const int J = t2 / a.nty;
+  const int J0 = (t2 / a.nty) * NP;
   const int X0 = tx * TX, X1 = (tx == a.ntx - 1) ? c2 : X0 + TX;
   const int Y0 = ty * TY, Y1 = (ty == a.nty - 1) ? c1 : Y0 + TY;
   const int ncx = min(X1 - X0 + 1, c2 - X0), ncy = min(Y1 - Y0 + 1, c1 - Y0);
   const int fq = min(2 * X1, m2) - 2 * X0;
   const int fr = min(2 * Y1, m1) - 2 * Y0;
-  const bool odd_in = 2 * J + 1 < m0;
-  // nodal planes J and J+1 (zeros outside the box)
+  // nodal planes J0 .. J0+NP (zeros outside the box)
   T nv[NNP];
 #pragma unroll
   for (int k = 0; k < NNP; k++) {
     const int idx = tid + NTP * k;
     const int p = idx / (NH * NW), rem = idx - p * (NH * NW);
     const int r = rem / NW, q = rem - r * NW;
-    const int Jp = J + p;
-    const bool ok = idx < 2 * NH * NW && r < ncy && q < ncx && Jp < c0;
+    const int Jp = J0 + p;
+    const bool ok = idx < (NP + 1) * NH * NW && r < ncy && q < ncx && Jp < c0;
     const T *src = a.nodal + (int64_t)(ok ? Jp : 0) * a.np0;
     const T x = ld_at(src, (uint32_t)(ok ? ((Y0 + r) * (int)a.np1 + X0 + q) * ES : 0));
     nv[k] = ok ? x : T(0);
   }
-  // this thread's 2x2 block and its coefficients
+  // this thread's 2x2 block and its coefficients in every plane pair
   const int ba = tid / BW, bb = tid - ba * BW;
   const bool blk = ba < TY + 1;
   const bool r0ok = blk && 2 * ba < fr, r1ok = blk && 2 * ba + 1 < fr;
@@ -1301,43 +1304,63 @@ __device__ __forceinline__ void interp_plane_body(const InterpArgs<T> a, const i
   const int rO = r1ok && inbox ? rE + (int)(c1 * a.up1) * ES : rE;
   const int cE = (X0 + (inbox ? bb : 0)) * ES;
   const int cO = q1ok && inbox ? cE + c2 * ES : cE;
-  const int64_t pe = (int64_t)J * a.up0, po = (int64_t)(odd_in ? c0 + J : J) * a.up0;
   auto coef = [&](int64_t plane, int off) -> T {
     if (LAB) return from_label<T>(ld_at(a.lab + plane, lab_off<T>((uint32_t)off)), a.qc);
     return ld_at(a.umc + plane, (uint32_t)off);
   };
-  const T cv0 = coef(pe, rE + cO), cv1 = coef(pe, rO + cE), cv2 = coef(pe, rO + cO);
-  const T cv3 = coef(po, rE + cE), cv4 = coef(po, rE + cO), cv5 = coef(po, rO + cE), cv6 = coef(po, rO + cO);
+  T cv[NP][7];
+#pragma unroll
+  for (int p = 0; p < NP; p++) {
+    const int J = min(J0 + p, c0 - 1);
+    const bool odd_in = 2 * J + 1 < m0;
+    const int64_t pe = (int64_t)J * a.up0, po = (int64_t)(odd_in ? c0 + J : J) * a.up0;
+    cv[p][0] = coef(pe, rE + cO);
+    cv[p][1] = coef(pe, rO + cE);
+    cv[p][2] = coef(pe, rO + cO);
+    cv[p][3] = coef(po, rE + cE);
+    cv[p][4] = coef(po, rE + cO);
+    cv[p][5] = coef(po, rO + cE);
+    cv[p][6] = coef(po, rO + cO);
+  }
   const T wxl = q1ok ? a.ax[2].wl[2 * X0 + 2 * bb + 1] : T(0), wxr = q1ok ? a.ax[2].wr[2 * X0 + 2 * bb + 1] : T(0);
   const T wyl = r1ok ? a.ax[1].wl[2 * Y0 + 2 * ba + 1] : T(0), wyr = r1ok ? a.ax[1].wr[2 * Y0 + 2 * ba + 1] : T(0);
-  const T wzl = odd_in ? ldu(a.ax[0].wl, 2 * J + 1) : T(0), wzr = odd_in ? ldu(a.ax[0].wr, 2 * J + 1) : T(0);
 #pragma unroll
   for (int k = 0; k < NNP; k++) {
     const int idx = tid + NTP * k;
-    if (idx < 2 * NH * NW) (&sN[0][0])[idx] = nv[k];
+    if (idx < (NP + 1) * NH * NW) (&sN[0][0])[idx] = nv[k];
   }
   __syncthreads();
   if (!inbox) return;
   const int n = ba * NW + bb;
-  const T A00 = sN[0][n], A01 = sN[0][n + 1], A10 = sN[0][n + NW], A11 = sN[0][n + NW + 1];
-  const T ea = wxl * A00 + wxr * A01, eb = wxl * A10 + wxr * A11;
-  const T e10 = wyl * A00 + wyr * A10, e11 = wyl * ea + wyr * eb;
   const uint32_t o0 = (uint32_t)(((2 * (Y0 + ba)) * (int)a.op1 + 2 * (X0 + bb)) * ES);
   const uint32_t orow = (uint32_t)((int)a.op1 * ES);
-  T *const oe = a.out + (int64_t)(2 * J) * a.op0;
-  // each fine row's even and odd column in one store
-  st_pair(oe, o0, A00, cv0 + ea, q1ok);
-  if (r1ok) st_pair(oe, o0 + orow, cv1 + e10, cv2 + e11, q1ok);
-  if (odd_in) {
-    const T B00 = sN[1][n], B01 = sN[1][n + 1], B10 = sN[1][n + NW], B11 = sN[1][n + NW + 1];
+  T A00 = sN[0][n], A01 = sN[0][n + 1], A10 = sN[0][n + NW], A11 = sN[0][n + NW + 1];
+  T ea = wxl * A00 + wxr * A01, eb = wxl * A10 + wxr * A11;
+  T e10 = wyl * A00 + wyr * A10, e11 = wyl * ea + wyr * eb;
+#pragma unroll
+  for (int p = 0; p < NP; p++) {
+    const int J = J0 + p;
+    if (J >= c0) break;
+    const bool odd_in = 2 * J + 1 < m0;
+    T *const oe = a.out + (int64_t)(2 * J) * a.op0;
+    // each fine row's even and odd column in one store
+    st_pair(oe, o0, A00, cv[p][0] + ea, q1ok);
+    if (r1ok) st_pair(oe, o0 + orow, cv[p][1] + e10, cv[p][2] + e11, q1ok);
+    if (!odd_in) break;
+    const T B00 = sN[p + 1][n], B01 = sN[p + 1][n + 1], B10 = sN[p + 1][n + NW], B11 = sN[p + 1][n + NW + 1];
     const T fa = wxl * B00 + wxr * B01, fb = wxl * B10 + wxr * B11;
     const T f10 = wyl * B00 + wyr * B10, f11 = wyl * fa + wyr * fb;
+    const T wzl = ldu(a.ax[0].wl, 2 * J + 1), wzr = ldu(a.ax[0].wr, 2 * J + 1);
     T *const oo = a.out + (int64_t)(2 * J + 1) * a.op0;
-    st_pair(oo, o0, cv3 + (wzl * A00 + wzr * B00), cv4 + (wzl * ea + wzr * fa), q1ok);
-    if (r1ok) st_pair(oo, o0 + orow, cv5 + (wzl * e10 + wzr * f10), cv6 + (wzl * e11 + wzr * f11), q1ok);
+    st_pair(oo, o0, cv[p][3] + (wzl * A00 + wzr * B00), cv[p][4] + (wzl * ea + wzr * fa), q1ok);
+    if (r1ok) st_pair(oo, o0 + orow, cv[p][5] + (wzl * e10 + wzr * f10), cv[p][6] + (wzl * e11 + wzr * f11), q1ok);
+    // plane J + 1's interpolant serves the next pair's even plane
+    A00 = B00;
+    ea = fa;
+    e10 = f10;
+    e11 = f11;
   }
 }
-
 template <typename T, int TX, int TY, int NTP, bool LAB>
 __global__ void __launch_bounds__(NTP) k_interp_plane(InterpArgs<T> a) {
   interp_plane_body<T, TX, TY, NTP, LAB>(a, xcd_remap(blockIdx.x, gridDim.x));
@@ -2041,10 +2064,10 @@ hipError_t launch_interp_add(InterpArgs<T> a, hipStream_t st, Tuning tn) {
   if (!tile_grid(a.ax[0].c, a.ax[1].c, a.ax[2].c, TX, TY, &a.ntx, &a.nty, &a.nzc, &a.tz, tn))
     return hipErrorInvalidValue;
   if (interp_plane(a)) {
-    // one coarse plane per workgroup
+    // MGX_INTERP_NP coarse planes per workgroup
     constexpr int NTP = interp_plane_threads<T>();
-    a.nzc = a.ax[0].c;
-    a.tz = 1;
+    a.nzc = (a.ax[0].c + MGX_INTERP_NP - 1) / MGX_INTERP_NP;
+    a.tz = MGX_INTERP_NP;
     dim3 grid(a.ntx * a.nty * a.nzc);
     if (a.lab)
       hipLaunchKernelGGL((k_interp_plane<T, TX, TY, NTP, true>), grid, dim3(NTP), 0, st, a);
@@ -2729,8 +2752,8 @@ int op_blocks(int kind, int mode, OpArgs<T> &a, const Tuning &tn) {
       constexpr int IX = InterpTiles<T>::TX, IY = InterpTiles<T>::TY;
       if (!tile_grid(s.ax[0].c, s.ax[1].c, s.ax[2].c, IX, IY, &s.ntx, &s.nty, &s.nzc, &s.tz, tn)) return -1;
       if (interp_plane(s)) {
-        s.nzc = s.ax[0].c;
-        s.tz = 1;
+        s.nzc = (s.ax[0].c + MGX_INTERP_NP - 1) / MGX_INTERP_NP;
+        s.tz = MGX_INTERP_NP;
       }
       return s.ntx * s.nty * s.nzc;
     }
