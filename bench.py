@@ -259,7 +259,11 @@ def progressive_section(torch, mgx, u, umc, ws, reps):
 
 def adaptive_section(torch, mgx, u, umc, ws, reps):
     """Adaptive decomposition of the benchmark field at three tolerances:
-    the stop level chosen and the time, against the full decomposition."""
+    the stop level chosen and the time, against the full decomposition; and
+    of a field of the same shape that is a sum of three products of two
+    one-axis waves (period 2 pi n / 8 nodes), which Lorenzo's predictor
+    reproduces up to rounding, so that the estimate stops the decomposition
+    early (the time of the levels gated off included)."""
     rng = float((u.max() - u.min()).item())
     out = {}
     for rel in (1e-2, 1e-3, 1e-4):
@@ -269,7 +273,19 @@ def adaptive_section(torch, mgx, u, umc, ws, reps):
         ms = timed(torch, fn, reps)
         out[f"{rel:g}"] = {"stop_level": res["stop"], "ms": round(ms, 4)}
     full_ms = timed(torch, lambda: mgx.decompose(u, out=umc, workspace=ws), reps)
-    return {"tau_over_range": out, "full_decompose_ms": round(full_ms, 4)}
+    s = u.shape[0] / 8
+    z, y, x = (torch.arange(k, device=u.device, dtype=torch.float64) / s for k in u.shape)
+    z, y, x = z[:, None, None], y[None, :, None], x[None, None, :]
+    wave = (torch.sin(x) * torch.cos(y) + torch.sin(y + 1) * torch.cos(z) + torch.cos(x) * torch.sin(z)).to(u.dtype)
+    del x, y, z
+    wrng = float((wave.max() - wave.min()).item())
+    res = {}
+    fn = lambda: res.update(stop=mgx.decompose_adaptive(wave, 1e-3 * wrng, out=umc, workspace=ws)[1])  # noqa: E731
+    fn()
+    wave_ms = timed(torch, fn, reps)
+    del wave
+    return {"tau_over_range": out, "full_decompose_ms": round(full_ms, 4),
+            "two_axis_waves_1e-3": {"stop_level": res["stop"], "ms": round(wave_ms, 4)}}
 
 
 def entropy_section(torch, mgx, u, labels, tol, reps):

@@ -202,7 +202,9 @@ mgx_status mgx_crop(const void *u_pad, void *u, mgx_dtype dtype, int ndim, const
  *   tol_linf, c_linf  as mgx_quantize.
  *   stop_level_out    out: host, the chosen stop level.
  *   workspace     mgx_workspace_size(dtype, ..., 0) bytes.
- * Synchronizes `stream` once per level (the decision is taken on the host).
+ * The decisions are taken on the device: every level's estimate, decision
+ * and kernels are enqueued at once, the levels below the stop doing nothing,
+ * and `stream` is synchronized once, at the end, to read the stop level.
  * Errors: MGX_ERR_SHAPE for fewer than three real axes; otherwise as
  * mgx_decompose and mgx_quantize (MGX_ERR_TOL). */
 mgx_status mgx_decompose_adaptive(const void *u, void *u_mc, mgx_dtype dtype, int ndim, const int64_t *dims,

@@ -30,7 +30,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 int64_t round4(int64_t v) { return (v + 3) / 4 * 4; }
 
 struct Layout {
-  size_t offA = 0, offB = 0, offF = 0, offG = 0, offS = 0, total = 0;
+  size_t offA = 0, offB = 0, offF = 0, offG = 0, offS = 0, offE = 0, total = 0;
   int lt = -1;  // finest level of the single-workgroup tail, -1: none
 };
 
@@ -75,6 +75,9 @@ Layout layout(const int64_t n[3], const bool real[3], int L, int stop, size_t es
   for (int k = 0; k < 3; k++) cS *= real[k] ? (n[k] - 1) / ((int64_t)1 << (L - stop)) + 1 : 1;
   w.offS = off;
   off = align_up(off + (size_t)cS * es, 256);
+  // the adaptive decomposition's decision state (two ints)
+  w.offE = off;
+  off += 256;
   w.total = off;
   return w;
 }
@@ -168,12 +171,26 @@ struct Emitter {
   bool untraced = false;  // never bracket launches with events (callers that must not allocate)
   // immediate mode only: called before and after each launch with (kind, level)
   std::function<hipError_t(int, int)> before, after;
+  // immediate mode only: the device flag that gates the stencil and solve
+  // launches (they do nothing while it is 0), null: ungated
+  const int *gate = nullptr;
   int base = 0, step = 0, phase = 0;
   void begin_step(int s) {
     step = base + s;
     phase = 0;
   }
-  hipError_t op(int kind, int mode, const char *name, int level, const OpArgs<T> &a) {
+  hipError_t op(int kind, int mode, const char *name, int level, const OpArgs<T> &in) {
+    OpArgs<T> a = in;
+    if (gate) {
+      switch (kind) {
+        case kOpLoadVecDec:
+        case kOpLoadVecRec: a.st.gate = gate; break;
+        case kOpSolveContig: a.so.gate = gate; break;
+        case kOpSolveStrided:
+        case kOpApply: a.sd.gate = gate; break;
+        default: return hipErrorInvalidValue;
+      }
+    }
     if (rec) {
       rec->push_back({kind, mode, step, phase++, name, level, a});
       return hipSuccess;
@@ -506,59 +523,73 @@ mgx_status tolerances(Plan *P, int ndim, double tol, int stop, double c_linf, do
 // Penalty factors of the estimate (Sec. 4.2, 3-D, in units of tau0).
 constexpr double kPenLorenzo = 1.22, kPenEdge = 0.369, kPenPlane = 0.259, kPenCube = 0.182;
 
-// The estimate's sums on the level-l box V (pitches vp0, vp1): enqueued on
-// st, then the host waits and adds the workgroups' partial sums in order.
-// counts: sampled edge, plane and cube nodes (12, 6, 1 per block).
-template <typename T>
-mgx_status adaptive_sums(Plan *P, int l, const T *V, int64_t vp0, int64_t vp1, const double *tab64, double *part,
-                         hipStream_t st, double *s_lor, double *s_int, int64_t counts[3]) {
+// Sampled 3^3 blocks of the estimate on level l (cells a = 1, 5, 9, ... per
+// axis) and its sampled edge, plane and cube nodes (12, 6, 1 per block).
+int64_t estimate_blocks(const Plan *P, int l, int nbk[3], int64_t counts[3]) {
   int64_t m[3];
   level_box(P, l, m);
-  int nbk[3];
   for (int k = 0; k < 3; k++) {
     const int64_t cells = (m[k] - 1) / 2;
-    nbk[k] = cells > 1 ? (int)((cells - 2) / 4 + 1) : 0;  // cells a = 1, 5, 9, ... < cells
+    nbk[k] = cells > 1 ? (int)((cells - 2) / 4 + 1) : 0;
   }
   const int64_t nb = (int64_t)nbk[0] * nbk[1] * nbk[2];
   counts[0] = 12 * nb;
   counts[1] = 6 * nb;
   counts[2] = nb;
-  *s_lor = *s_int = 0.0;
-  if (nb == 0) return MGX_OK;
-  EstimateArgs<T> a{};
-  a.V = V;
-  a.vp0 = vp0;
-  a.vp1 = vp1;
-  a.nb0 = nbk[0];
-  a.nb1 = nbk[1];
-  a.nb2 = nbk[2];
-  for (int k = 0; k < 3; k++) {
-    a.wl[k] = tab64 + P->ax[l][k].off_wl;
-    a.wr[k] = tab64 + P->ax[l][k].off_wr;
+  return nb;
+}
+
+int estimate_workgroups(int64_t nb) { return (int)((nb + kEstimateThreads - 1) / kEstimateThreads); }
+
+// Enqueues the estimate on the level-l box V (pitches vp0, vp1) and the
+// decision kernel on st; nothing waits.  part: the per-workgroup sums;
+// sums (nullable): the two totals; state (nullable): the decision state,
+// which also gates the estimate unless this is the first decision.
+template <typename T>
+mgx_status enqueue_estimate(Plan *P, int l, const T *V, int64_t vp0, int64_t vp1, const double *tab64, double *part,
+                            double *sums, int *state, bool first, double tau0, hipStream_t st) {
+  int nbk[3];
+  int64_t cnt[3];
+  const int64_t nb = estimate_blocks(P, l, nbk, cnt);
+  const int nwg = estimate_workgroups(nb);
+  if (nb > 0) {
+    EstimateArgs<T> a{};
+    a.V = V;
+    a.vp0 = vp0;
+    a.vp1 = vp1;
+    a.nb0 = nbk[0];
+    a.nb1 = nbk[1];
+    a.nb2 = nbk[2];
+    for (int k = 0; k < 3; k++) {
+      a.wl[k] = tab64 + P->ax[l][k].off_wl;
+      a.wr[k] = tab64 + P->ax[l][k].off_wr;
+    }
+    a.partial = part;
+    a.gate = first ? nullptr : state;
+    if (traced("adaptive_estimate", l, st, [&] { return launch_adaptive_estimate<T>(a, nwg, st); }) != hipSuccess)
+      return MGX_ERR_HIP;
   }
-  a.partial = part;
-  const int nwg = (int)((nb + kEstimateThreads - 1) / kEstimateThreads);
-  if (traced("adaptive_estimate", l, st, [&] { return launch_adaptive_estimate<T>(a, nwg, st); }) != hipSuccess)
+  DecideArgs d{};
+  d.partial = part;
+  d.nwg = nwg;
+  d.sums = sums;
+  d.state = state;
+  d.level = l;
+  d.first = first ? 1 : 0;
+  d.pen_lor = kPenLorenzo * tau0 * (double)(cnt[0] + cnt[1] + cnt[2]);
+  d.pen_int = (kPenEdge * (double)cnt[0] + kPenPlane * (double)cnt[1] + kPenCube * (double)cnt[2]) * tau0;
+  if (traced("adaptive_decide", l, st, [&] { return launch_adaptive_decide(d, st); }) != hipSuccess)
     return MGX_ERR_HIP;
-  std::vector<double> h((size_t)nwg * 2);
-  if (hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess)
-    return MGX_ERR_HIP;
-  double sl = 0.0, si = 0.0;
-  for (int i = 0; i < nwg; i++) {
-    sl += h[2 * i];
-    si += h[2 * i + 1];
-  }
-  *s_lor = sl;
-  *s_int = si;
   return MGX_OK;
 }
 
-// Level by level from L: the estimate of Q_l u, then either stop (Lorenzo's
-// estimate below the interpolation's: *stop_out = l) or one decomposition
-// level.  Q_{l-1} u goes to the compact A/B boxes; the last one is copied
-// into u_mc's corner at the end.  The estimate's partial sums use the load
-// vector's buffer F, which the level's kernels overwrite only afterwards.
+// All levels are enqueued at once, decided on the device: per level from L
+// the estimate of Q_l u and its decision, then the level's kernels, which
+// run only while the decision state says go on.  One wait at the end reads
+// the stop level; Q_stop u (u itself, or the compact A/B box the last run
+// level wrote, untouched by the gated levels below) is then copied into
+// u_mc's corner.  The estimate's partial sums use the load vector's buffer
+// F, which the level's kernels overwrite only after the decision.
 template <typename T>
 mgx_status run_decompose_adaptive(Plan *P, int ndim, const T *u, T *umc, double tol, double c_linf, char *ws,
                                   const Layout &lay, const T *tab, const double *tab64, hipStream_t st,
@@ -568,25 +599,17 @@ mgx_status run_decompose_adaptive(Plan *P, int ndim, const T *u, T *umc, double 
   const int64_t up0 = n1 * n2, up1 = n2;
   T *A = (T *)(ws + lay.offA), *B = (T *)(ws + lay.offB), *F = (T *)(ws + lay.offF);
   double *part = (double *)(ws + lay.offF);
+  int *state = (int *)(ws + lay.offE);
   Emitter<T> em;
   em.st = st;
+  em.gate = state;
   const T *src = u;
   int64_t sp0 = up0, sp1 = up1;
-  int stop = 0;
   for (int l = L; l >= 1; l--) {
     double tau[kMaxLevels];
     mgx_status s = tolerances(P, ndim, tol, l, c_linf, tau);
     if (s) return s;
-    double sl, si;
-    int64_t cnt[3];
-    if ((s = adaptive_sums<T>(P, l, src, sp0, sp1, tab64, part, st, &sl, &si, cnt))) return s;
-    const double n = (double)(cnt[0] + cnt[1] + cnt[2]);
-    const double el = sl + kPenLorenzo * tau[0] * n;
-    const double ei = si + (kPenEdge * (double)cnt[0] + kPenPlane * (double)cnt[1] + kPenCube * (double)cnt[2]) * tau[0];
-    if (el < ei) {
-      stop = l;
-      break;
-    }
+    if ((s = enqueue_estimate<T>(P, l, src, sp0, sp1, tab64, part, nullptr, state, l == L, tau[0], st))) return s;
     AxisTab<T> ax[3] = {axis_tab(P, l, 0, tab), axis_tab(P, l, 1, tab), axis_tab(P, l, 2, tab)};
     const int c1 = ax[1].c, c2 = ax[2].c;
     const int64_t cp1 = c2, cp0 = (int64_t)c1 * c2;
@@ -611,8 +634,23 @@ mgx_status run_decompose_adaptive(Plan *P, int ndim, const T *u, T *umc, double 
     sp0 = cp0;
     sp1 = cp1;
   }
+  int stop = -1;
+  if (hipMemcpyAsync(&stop, state + 1, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return MGX_ERR_HIP;
+  if (stop < 0 || stop > L) return MGX_ERR_HIP;
   int64_t m[3];
   level_box(P, stop, m);
+  if (stop < L) {  // Q_s u for s < L sits in the box level s + 1 wrote
+    src = ((L - 1 - stop) % 2 == 0) ? A : B;
+    sp0 = m[1] * m[2];
+    sp1 = m[2];
+  } else {
+    src = u;
+    sp0 = up0;
+    sp1 = up1;
+  }
+  em.gate = nullptr;
   if (copy_box<T>(src, sp0, sp1, umc, up0, up1, (int)m[0], (int)m[1], (int)m[2], stop, em) != hipSuccess)
     return MGX_ERR_HIP;
   *stop_out = stop;
@@ -2046,11 +2084,21 @@ mgx_status mgx_adaptive_estimate(const void *v, mgx_dtype dtype, int ndim, const
   if (hipGetDevice(&dev) != hipSuccess) return MGX_ERR_HIP;
   const double *tab64 = (const double *)P->device_tables(dev, true, &herr);
   if (!tab64) return MGX_ERR_HIP;
-  if (dtype == MGX_F32)
-    return adaptive_sums<float>(P, level, (const float *)v, m[1] * m[2], m[2], tab64, (double *)workspace, stream,
-                                &sums_out[0], &sums_out[1], counts_out);
-  return adaptive_sums<double>(P, level, (const double *)v, m[1] * m[2], m[2], tab64, (double *)workspace, stream,
-                               &sums_out[0], &sums_out[1], counts_out);
+  int nbk[3];
+  const int nwg = estimate_workgroups(estimate_blocks(P, level, nbk, counts_out));
+  double *part = (double *)workspace, *sums = part + 2 * (int64_t)nwg;
+  const mgx_status s = dtype == MGX_F32 ? enqueue_estimate<float>(P, level, (const float *)v, m[1] * m[2], m[2], tab64, part, sums,
+                                                 nullptr, true, 0.0, stream)
+                                        : enqueue_estimate<double>(P, level, (const double *)v, m[1] * m[2], m[2],
+                                                                   tab64, part, sums, nullptr, true, 0.0, stream);
+  if (s) return s;
+  double h[2];
+  if (hipMemcpyAsync(h, sums, sizeof(h), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return MGX_ERR_HIP;
+  sums_out[0] = h[0];
+  sums_out[1] = h[1];
+  return MGX_OK;
 }
 
 mgx_status mgx_dyadic_dims(int ndim, const int64_t *dims, int64_t *padded_out) {
@@ -2164,7 +2212,8 @@ size_t mgx_adaptive_workspace_size(int ndim, const int64_t *dims) {
     const int64_t cells = real[k] ? (n[k] - 1) / 2 : 0;
     nb *= cells > 1 ? (cells - 2) / 4 + 1 : 1;
   }
-  return (size_t)((nb + kEstimateThreads - 1) / kEstimateThreads) * 2 * sizeof(double);
+  // per-workgroup sums of the finest level, then the two totals
+  return (size_t)(((nb + kEstimateThreads - 1) / kEstimateThreads) * 2 + 2) * sizeof(double);
 }
 
 size_t mgx_adjoint_workspace_size(mgx_dtype dtype, int ndim, const int64_t *dims, int stop_level) {

@@ -619,6 +619,7 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
 template <typename T, int TX, int TY, int NT, bool DEC, int LAB>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(DEC ? MGX_STENCIL_WAVES : MGX_REC_WAVES, 8)))
 k_load_vector(StencilArgs<T> a) {
+  if (a.gate && *a.gate == 0) return;
   load_vector_body<T, TX, TY, NT, DEC, LAB>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
 
@@ -718,6 +719,7 @@ __device__ __forceinline__ void solve_contig_body(const SolveArgs<T> a, const in
 
 template <typename T, int E, int G>
 __global__ void __launch_bounds__(256) k_solve_contig(SolveArgs<T> a) {
+  if (a.gate && *a.gate == 0) return;
   solve_contig_body<T, E, G>(a, blockIdx.x);
 }
 
@@ -922,11 +924,13 @@ __device__ __forceinline__ void solve_seg_body(const StridedArgs<T> a, const int
 
 template <typename T, int SEG, int MODE>
 __global__ void __launch_bounds__(64 * kSegMaxWaves) k_solve_seg(StridedArgs<T> a) {
+  if (a.gate && *a.gate == 0) return;
   solve_seg_body<T, SEG, MODE>(a, blockIdx.x);
 }
 
 template <typename T, int MODE, int CH>
 __global__ void __launch_bounds__(256) k_solve_strided(StridedArgs<T> a) {
+  if (a.gate && *a.gate == 0) return;
   solve_strided_body<T, MODE, CH>(a, blockIdx.x, blockIdx.y);
 }
 
@@ -1035,6 +1039,7 @@ __device__ __forceinline__ void solve_twisted_body(const StridedArgs<T> a, const
 
 template <typename T, int C, int MODE>
 __global__ void __launch_bounds__(256) k_solve_twisted(StridedArgs<T> a) {
+  if (a.gate && *a.gate == 0) return;
   solve_twisted_body<T, C, MODE>(a, blockIdx.x);
 }
 
@@ -1049,6 +1054,7 @@ __device__ __forceinline__ void apply_body(const StridedArgs<T> a, const int bx)
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_apply(StridedArgs<T> a) {
+  if (a.gate && *a.gate == 0) return;
   apply_body<T>(a, blockIdx.x);
 }
 
@@ -1886,10 +1892,11 @@ __global__ void __launch_bounds__(256) k_dequantize_box(const int32_t *__restric
 // per axis (the block and its Lorenzo neighbours), and for each of the 19
 // coefficient nodes adds |u - Lorenzo prediction| and |u - multilinear
 // interpolant| (FP64, weights of the level's coordinates).  Each workgroup
-// writes its two sums; the host adds them in workgroup order.
+// writes its two sums; k_adaptive_decide adds them up.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(kEstimateThreads) k_adaptive_estimate(EstimateArgs<T> a) {
+  if (a.gate && *a.gate == 0) return;
   __shared__ double sl[kEstimateThreads], si[kEstimateThreads];
   const int nb = a.nb0 * a.nb1 * a.nb2;
   const int b = blockIdx.x * kEstimateThreads + threadIdx.x;
@@ -1957,6 +1964,53 @@ template <typename T>
 hipError_t launch_adaptive_estimate(EstimateArgs<T> a, int nblocks, hipStream_t st) {
   if (nblocks < 1) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_adaptive_estimate<T>), dim3((unsigned)nblocks), dim3(kEstimateThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+// k_adaptive_decide: one workgroup adds the estimate's per-workgroup sums
+// (thread t takes workgroups t, t + 256, ... in order, then a fixed tree), so
+// the totals do not depend on timing.  With a state it takes the decision of
+// Sec. 4.2 on the device: the decomposition stops at this level when the
+// Lorenzo estimate (sum + penalty) is below the interpolation's, and the
+// level kernels that follow, gated on state[0], then do nothing.  Once the
+// state says stop, later decisions leave it as it is.
+__global__ void __launch_bounds__(kEstimateThreads) k_adaptive_decide(DecideArgs a) {
+  if (a.state && !a.first && a.state[0] == 0) return;
+  __shared__ double sl[kEstimateThreads], si[kEstimateThreads];
+  double x = 0.0, y = 0.0;
+  for (int i = threadIdx.x; i < a.nwg; i += kEstimateThreads) {
+    x += a.partial[2 * i];
+    y += a.partial[2 * i + 1];
+  }
+  sl[threadIdx.x] = x;
+  si[threadIdx.x] = y;
+  __syncthreads();
+  for (int h = kEstimateThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      sl[threadIdx.x] += sl[threadIdx.x + h];
+      si[threadIdx.x] += si[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  if (a.sums) {
+    a.sums[0] = sl[0];
+    a.sums[1] = si[0];
+  }
+  if (a.state) {
+    if (sl[0] + a.pen_lor < si[0] + a.pen_int) {
+      a.state[0] = 0;
+      a.state[1] = a.level;
+    } else {
+      a.state[0] = 1;
+      if (a.first) a.state[1] = 0;
+    }
+  }
+}
+
+hipError_t launch_adaptive_decide(DecideArgs a, hipStream_t st) {
+  if (a.nwg < 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_adaptive_decide, dim3(1), dim3(kEstimateThreads), 0, st, a);
   return hipGetLastError();
 }
 

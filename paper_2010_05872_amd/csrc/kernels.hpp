@@ -43,6 +43,7 @@ struct StencilArgs {
   // [0] finite |c/q| >= 2^31 - 1, [1] c/q not finite (null: not counted)
   unsigned long long *rng;
   int *smax;                  // decompose with labels: the level's max |label| (atomicMax; null: not taken)
+  const int *gate;            // nullable: the launch does nothing while *gate == 0 (adaptive decomposition)
   int ntx, nty, nzc, tz;      // set by the launcher
 };
 
@@ -66,6 +67,7 @@ struct SolveArgs {            // contiguous-axis solve, in place on F rows
   int64_t nlines, pitch;
   int c;
   const T *mult, *invd, *qsup;
+  const int *gate;            // as StencilArgs::gate
 };
 
 // Adaptive decomposition estimate (3-D): one thread per sampled 3^3 block
@@ -77,6 +79,19 @@ struct EstimateArgs {
   int nb0, nb1, nb2;            // sampled cells per axis
   const double *wl[3], *wr[3];  // FP64 interpolation weights of level l, by level index
   double *partial;              // per workgroup: sum |u - Lorenzo|, sum |u - interpolant|
+  const int *gate;              // as StencilArgs::gate
+};
+
+// The estimate's decision: the partial sums of one estimate launch added up
+// (fixed order), and the adaptive decomposition's state updated on the device.
+struct DecideArgs {
+  const double *partial;        // [2 * nwg] from the estimate
+  int nwg;
+  double *sums;                 // nullable: the two totals out
+  int *state;                   // nullable: [0] 1 while the decomposition goes on, [1] its stop level
+  int level;                    // the level the estimate was taken on
+  int first;                    // nonzero: the first decision (initialises the state, ignores [0])
+  double pen_lor, pen_int;      // penalty terms added to the two sums before they are compared
 };
 
 template <typename T>
@@ -94,6 +109,7 @@ struct StridedArgs {          // strided-axis solve (optionally applying)
   T *out;                     // apply: nodal out (index J*oj + o*oo + x)
   int64_t oj, oo;
   T sign;
+  const int *gate;            // as StencilArgs::gate
 };
 
 // Adjoint: the transposed load-vector operator (M P) along every axis, from a
@@ -249,6 +265,7 @@ union OpArgs {
 };
 
 template <typename T> hipError_t launch_adaptive_estimate(EstimateArgs<T> a, int nblocks, hipStream_t st);
+hipError_t launch_adaptive_decide(DecideArgs a, hipStream_t st);
 constexpr int kEstimateThreads = 256;
 
 // Workgroups of one op (fills the tile-grid fields of stencil ops); -1 when
