@@ -291,7 +291,9 @@ def adaptive_section(torch, mgx, u, umc, ws, reps):
 def entropy_section(torch, mgx, u, labels, tol, reps):
     """Per-level entropy of the step's labels (L-infinity schedule) and the
     estimated size of the labels in bits per value (Sec. 4.1's cost
-    estimate), with the time of the entropy pass; the same for the L2
+    estimate), with the time of the entropy pass, alone and given the
+    fused quantizer's per-level maxima (one read of the labels); the same
+    for the L2
     schedule with the library's default C_L2, at an L2 tolerance whose
     root-mean-square error over the domain equals the L-infinity tolerance
     (tau_L2 = tol * sqrt(|Omega|), |Omega| = 512^3 on unit spacing)."""
@@ -307,6 +309,14 @@ def entropy_section(torch, mgx, u, labels, tol, reps):
                      device=u.device)
     H = mgx.label_entropy(labels, 0, workspace=ws)
     ms = timed(torch, lambda: mgx.label_entropy(labels, 0, workspace=ws), reps)
+    wsd = torch.empty(mgx.workspace_size(mgx.MGX_F32, u.shape, 0), dtype=torch.uint8, device=u.device)
+    _, lab_s, st, _ = mgx.decompose_quantize(u, tol, labels=torch.empty_like(labels), workspace=wsd,
+                                             keep_coef=False, stats=True)
+    del wsd
+    same = bool(torch.equal(lab_s, labels))
+    Hb = mgx.label_entropy(lab_s, 0, workspace=ws, stats=st)
+    ms_b = timed(torch, lambda: mgx.label_entropy(lab_s, 0, workspace=ws, stats=st), reps)
+    del lab_s
     bits = float(sum(c * h for c, h in zip(counts, H)) / u.numel())
     umc = mgx.decompose(u)
     vol = 1.0
@@ -318,7 +328,9 @@ def entropy_section(torch, mgx, u, labels, tol, reps):
     bits2 = float(sum(c * h for c, h in zip(counts, H2)) / u.numel())
     return {"linf_bits_per_level": [round(float(h), 4) for h in H], "linf_bits_per_value": round(bits, 4),
             "l2_c": mgx.l2_constant(u.shape), "l2_tol_over_sqrt_volume": tol,
-            "l2_bits_per_value": round(bits2, 4), "entropy_ms": round(ms, 3)}
+            "l2_bits_per_value": round(bits2, 4), "entropy_ms": round(ms, 3),
+            "entropy_given_maxima_ms": round(ms_b, 3),
+            "given_maxima_equal": bool(same and list(Hb) == list(H))}
 
 
 def four_d_section(torch, mgx, workloads, dev, reps):

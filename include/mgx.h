@@ -162,12 +162,26 @@ mgx_status mgx_dequantize_levels(const int32_t *labels, void *u_mc, mgx_dtype dt
  * from one histogram pass when the levels' label ranges (2 max|label| + 1
  * each) add up to at most 2^26; wider ranges are counted by a radix sort of
  * (level, label) keys.  Workspace: mgx_label_entropy_workspace_size bytes
- * (enough for either: about 20 bytes per label, at least 256 MiB), must not
+ * (enough for either: about 20 bytes per label, at least 292 MiB), must not
  * overlap labels.  Synchronizes `stream`.
  * Errors: MGX_ERR_ARG, _SHAPE, _LEVEL, _WORKSPACE, _HIP. */
 mgx_status mgx_label_entropy(const int32_t *labels, int ndim, const int64_t *dims, int stop_level, double *bits_out,
                              void *workspace, size_t workspace_bytes, hipStream_t stream);
 size_t mgx_label_entropy_workspace_size(int ndim, const int64_t *dims, int stop_level);
+
+/* mgx_label_entropy with the statistics of the quantizing call that wrote
+ * the labels (stats: host, as returned by mgx_quantize, mgx_quantize_levels
+ * or mgx_decompose_quantize with the same shape and stop level): its per-level
+ * max |label| sets the histogram's key ranges, so the labels are read once
+ * instead of twice.  Statistics of another stop level, or that count
+ * out-of-range labels, are not used (the call then finds the maxima itself);
+ * a label beyond its level's stated maximum is detected and the call counts
+ * again with the maxima found on the labels, so wrong statistics cost time,
+ * never correctness.  Same results, workspace and errors as
+ * mgx_label_entropy (MGX_ERR_ARG for a null stats). */
+mgx_status mgx_label_entropy_bounded(const int32_t *labels, int ndim, const int64_t *dims, int stop_level,
+                                     const mgx_quant_stats *stats, double *bits_out, void *workspace,
+                                     size_t workspace_bytes, hipStream_t stream);
 
 /* Non-dyadic sizes (the dummy nodes of Sec. 6.2.2): an axis of n nodes is
  * padded to the next 2^m + 1 >= n (m >= 1) with dummy nodes after the last

@@ -100,7 +100,7 @@ EXPORTS = (
     "mgx_recompose_to", "mgx_decompose_adaptive", "mgx_adaptive_estimate", "mgx_adaptive_workspace_size",
     "mgx_dyadic_dims", "mgx_pad", "mgx_crop", "mgx_l2_constant", "mgx_level_tolerances_l2", "mgx_quantize_levels",
     "mgx_dequantize_levels", "mgx_label_entropy", "mgx_label_entropy_workspace_size", "mgx_decompose_noalloc",
-    "mgx_release_cached",
+    "mgx_release_cached", "mgx_label_entropy_bounded",
 )
 
 _lib = None
@@ -146,6 +146,8 @@ def lib():
         L.mgx_dequantize_levels.restype = ci
         L.mgx_label_entropy.argtypes = [vp, ci, i64p, ci, dp, vp, sz, vp]
         L.mgx_label_entropy.restype = ci
+        L.mgx_label_entropy_bounded.argtypes = [vp, ci, i64p, ci, vp, dp, vp, sz, vp]
+        L.mgx_label_entropy_bounded.restype = ci
         L.mgx_label_entropy_workspace_size.argtypes = [ci, i64p, ci]
         L.mgx_label_entropy_workspace_size.restype = sz
         L.mgx_dyadic_dims.argtypes = [ci, i64p, i64p]
@@ -745,8 +747,11 @@ def dequantize_levels(labels, tau, dtype, coords=None, stop_level=0, out=None):
     return out
 
 
-def label_entropy(labels, stop_level=0, workspace=None) -> np.ndarray:
-    """Shannon entropy (bits per label) of the labels of each level stop_level .. L."""
+def label_entropy(labels, stop_level=0, workspace=None, stats=None) -> np.ndarray:
+    """Shannon entropy (bits per label) of the labels of each level stop_level .. L.
+    stats: the statistics dict of the quantizing call that wrote the labels
+    (decompose_quantize(..., stats=True)); its per-level maxima spare the
+    pass that finds them."""
     import torch
     _check_tensor(labels, "labels")
     shape = tuple(labels.shape)
@@ -754,10 +759,23 @@ def label_entropy(labels, stop_level=0, workspace=None) -> np.ndarray:
     if workspace is None:
         workspace = torch.empty(max(need, 8), dtype=torch.uint8, device=labels.device)
     bits = np.zeros(num_levels(shape) + 1 - int(stop_level), dtype=np.float64)
-    code = lib().mgx_label_entropy(labels.data_ptr(), len(shape), _dims(shape), int(stop_level),
-                                   bits.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), workspace.data_ptr(),
-                                   workspace.numel() * workspace.element_size(), _stream(labels.device))
-    _check(code, "mgx_label_entropy")
+    bp = bits.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    wb = workspace.numel() * workspace.element_size()
+    if stats is None:
+        code = lib().mgx_label_entropy(labels.data_ptr(), len(shape), _dims(shape), int(stop_level), bp,
+                                       workspace.data_ptr(), wb, _stream(labels.device))
+        _check(code, "mgx_label_entropy")
+        return bits
+    st = QuantStats()
+    st.first_level = int(stats["first_level"])
+    st.num_levels = len(stats["max_abs_label"])
+    for i, m in enumerate(stats["max_abs_label"]):
+        st.max_abs_label[i] = int(m)
+    st.n_overflow = int(stats["n_overflow"])
+    st.n_nonfinite = int(stats["n_nonfinite"])
+    code = lib().mgx_label_entropy_bounded(labels.data_ptr(), len(shape), _dims(shape), int(stop_level),
+                                           ctypes.byref(st), bp, workspace.data_ptr(), wb, _stream(labels.device))
+    _check(code, "mgx_label_entropy_bounded")
     return bits
 
 

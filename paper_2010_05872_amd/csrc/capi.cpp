@@ -2412,8 +2412,10 @@ size_t mgx_label_entropy_workspace_size(int ndim, const int64_t *dims, int stop_
   return entropy_workspace(n[0] * n[1] * n[2], L + 1 - stop_level);
 }
 
-mgx_status mgx_label_entropy(const int32_t *labels, int ndim, const int64_t *dims, int stop_level, double *bits_out,
-                             void *workspace, size_t workspace_bytes, hipStream_t stream) {
+// known_max: host, the quantizer's per-level maxima, or null.
+static mgx_status entropy_common(const int32_t *labels, int ndim, const int64_t *dims, int stop_level,
+                                 double *bits_out, void *workspace, size_t workspace_bytes, const int32_t *known_max,
+                                 hipStream_t stream) {
   if (!labels || !bits_out) return MGX_ERR_ARG;
   if (ndim == 4) {
     int L4;
@@ -2437,7 +2439,7 @@ mgx_status mgx_label_entropy(const int32_t *labels, int ndim, const int64_t *dim
       count4[l - stop_level] = P4.count(l) - prev4;
       prev4 = P4.count(l);
     }
-    return hip_status(label_entropy(labels, qa4, count4, (char *)workspace, stream, bits_out));
+    return hip_status(label_entropy(labels, qa4, count4, (char *)workspace, stream, bits_out, known_max));
   }
   int64_t n[3];
   bool real[3];
@@ -2465,7 +2467,29 @@ mgx_status mgx_label_entropy(const int32_t *labels, int ndim, const int64_t *dim
     count[l - stop_level] = box - prev;
     prev = box;
   }
-  return hip_status(label_entropy(labels, qa, count, (char *)workspace, stream, bits_out));
+  return hip_status(label_entropy(labels, qa, count, (char *)workspace, stream, bits_out, known_max));
+}
+
+mgx_status mgx_label_entropy(const int32_t *labels, int ndim, const int64_t *dims, int stop_level, double *bits_out,
+                             void *workspace, size_t workspace_bytes, hipStream_t stream) {
+  return entropy_common(labels, ndim, dims, stop_level, bits_out, workspace, workspace_bytes, nullptr, stream);
+}
+
+mgx_status mgx_label_entropy_bounded(const int32_t *labels, int ndim, const int64_t *dims, int stop_level,
+                                     const mgx_quant_stats *stats, double *bits_out, void *workspace,
+                                     size_t workspace_bytes, hipStream_t stream) {
+  if (!stats) return MGX_ERR_ARG;
+  const int L = mgx_num_levels(ndim, dims);
+  if (L < 0) return (mgx_status)-L;
+  if (stop_level < 0 || stop_level > L) return MGX_ERR_LEVEL;
+  // statistics of another stop level, or with out-of-range labels (left out
+  // of the maxima): the maxima are found on the labels instead
+  bool use = stats->first_level == stop_level && stats->num_levels == L + 1 - stop_level &&
+             stats->n_overflow == 0 && stats->n_nonfinite == 0;
+  for (int i = 0; use && i < stats->num_levels; i++)
+    if (stats->max_abs_label[i] < 0) use = false;
+  return entropy_common(labels, ndim, dims, stop_level, bits_out, workspace, workspace_bytes,
+                        use ? stats->max_abs_label : nullptr, stream);
 }
 
 double mgx_linf_constant(int ndim, const int64_t *dims, const double *const *coords, int stop_level) {

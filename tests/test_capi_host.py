@@ -93,6 +93,16 @@ def test_validation_before_launch():
     d4 = (ctypes.c_int64 * 4)(9, 9, 9, 9)
     assert L.mgx_quantize(U, O, 0, 4, d4, None, -1.0, 0, 0.0, None, None) == 5
     assert L.mgx_dequantize(U, O, 0, 4, d4, None, 1.0, 3, 0.0, None) == 4
+    # the entropy with the quantizer's statistics: null statistics, a bad
+    # level or a short workspace are refused before any launch
+    bits = (ctypes.c_double * 16)()
+    st = mgx.QuantStats()
+    st.num_levels = 7
+    assert L.mgx_label_entropy_bounded(U, 2, d, 0, None, bits, W, big, None) == 1
+    assert L.mgx_label_entropy_bounded(U, 2, d, 7, ctypes.byref(st), bits, W, big, None) == 4
+    assert L.mgx_label_entropy_bounded(U, 2, d, 0, ctypes.byref(st), bits, W, 16, None) == 7
+    d3 = (ctypes.c_int64 * 2)(65, 64)
+    assert L.mgx_label_entropy_bounded(U, 2, d3, 0, ctypes.byref(st), bits, W, big, None) == 2
 
 
 @pytest.mark.parametrize("shape,kind", [((65, 65, 65), None), ((17, 33, 65), "mixed"), ((129, 33), "random"),

@@ -68,3 +68,34 @@ def test_entropy_histogram_and_sort_paths(spread):
         H = mgx.label_entropy(torch.as_tensor(lab, device="cuda"), stop)
         Href = oracle.label_entropy(oracle.from_level_centric(lab, stop), stop)
         assert np.allclose(H, Href, rtol=1e-12, atol=1e-12), (spread, stop, H, Href)
+
+
+@pytest.mark.parametrize("case", [((65, 129, 33), torch.float32, 0), ((129, 65), torch.float64, 2),
+                                  ((17, 9, 17, 9), torch.float32, 0)],
+                         ids=lambda c: f"{'x'.join(map(str, c[0]))}-{str(c[1])[6:]}-stop{c[2]}")
+def test_entropy_with_quantizer_maxima(case):
+    """label_entropy given the fused quantizer's statistics (one pass over the
+    labels) equals the plain call and the oracle; maxima that are too small
+    (labels beyond them) or statistics of another stop level or with
+    out-of-range labels still give the exact entropies."""
+    shape, dt, stop = case
+    print(f"[entropy-bounded] {shape} {dt} stop {stop}", flush=True)
+    u = torch.as_tensor(workloads.gaussian_random_field(shape, slope=3.0, seed=41), dtype=dt, device="cuda")
+    tol = 1e-3 * float((u.max() - u.min()).item())
+    _, lab, st, code = mgx.decompose_quantize(u, tol, stop_level=stop, stats=True)
+    assert code == 0
+    Href = oracle.label_entropy(oracle.from_level_centric(lab.cpu().numpy(), stop), stop)
+    H0 = mgx.label_entropy(lab, stop)
+    H1 = mgx.label_entropy(lab, stop, stats=st)
+    assert np.array_equal(H0, H1)
+    assert np.allclose(H1, Href, rtol=1e-12, atol=1e-12)
+    # maxima one short on every level: the labels at the maxima are detected
+    short = dict(st, max_abs_label=[max(m - 1, 0) for m in st["max_abs_label"]])
+    assert np.array_equal(mgx.label_entropy(lab, stop, stats=short), H0)
+    # larger maxima than needed: the same counts over wider key ranges
+    wide = dict(st, max_abs_label=[2 * m + 5 for m in st["max_abs_label"]])
+    assert np.allclose(mgx.label_entropy(lab, stop, stats=wide), H0, rtol=1e-12, atol=1e-12)
+    # statistics that cannot be used are ignored
+    assert np.array_equal(mgx.label_entropy(lab, stop, stats=dict(st, n_overflow=1)), H0)
+    other = dict(st, first_level=stop + 1, max_abs_label=st["max_abs_label"][1:])
+    assert np.array_equal(mgx.label_entropy(lab, stop, stats=other), H0)
