@@ -379,6 +379,8 @@ typedef struct {
   int target_blocks;         /* chosen launch shape of the stencil kernels                  */
   int min_zchunk;
   double tuned_ms;           /* time of the chosen graph during tuning (0: not tuned)       */
+  int tune_source;           /* 0: default shape, 1: timed by this process, 2: read from the
+                                tuning cache file (MGX_TUNE_CACHE)                         */
 } mgx_batch_info;
 
 /* Workspace bytes for mgx_decompose_batched / mgx_recompose_batched (the
@@ -414,7 +416,14 @@ mgx_status mgx_recompose_batched(int nfields, const mgx_field *fields, void *wor
  * mgx_decompose_noalloc are not affected.  Errors: MGX_ERR_HIP. */
 mgx_status mgx_release_cached(void);
 
-/* Autotuning of batches on first use: 1 (default) or 0 (default shape). */
+/* Autotuning of batches on first use: 1 (default) or 0 (default shape).
+ * With the environment variable MGX_TUNE_CACHE set to a file path, tuned
+ * shapes persist across processes: a batch met for the first time is
+ * looked up there by a signature of its fields' dtypes, dims, stop levels,
+ * label / coefficient / statistics use and coordinate values (not their
+ * addresses) and built with the stored shape without timing; each shape
+ * timed is appended as one text line.  Read at every first meeting of a
+ * batch; an unreadable or unwritable file is ignored. */
 mgx_status mgx_batch_set_autotune(int on);
 
 /* Shape of the most recent batched call of this thread. */

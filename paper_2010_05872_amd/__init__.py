@@ -78,6 +78,7 @@ class BatchInfo(ctypes.Structure):
         ("target_blocks", ctypes.c_int),
         ("min_zchunk", ctypes.c_int),
         ("tuned_ms", ctypes.c_double),
+        ("tune_source", ctypes.c_int),
     ]
 
 
@@ -647,7 +648,7 @@ def batch_last_info() -> dict:
     info = BatchInfo()
     _check(lib().mgx_batch_last_info(ctypes.byref(info)), "mgx_batch_last_info")
     return {"launches": info.launches, "target_blocks": info.target_blocks, "min_zchunk": info.min_zchunk,
-            "tuned_ms": info.tuned_ms}
+            "tuned_ms": info.tuned_ms, "tune_source": info.tune_source}
 
 
 def quantize(u_mc, tol, coords=None, stop_level=0, c_linf=0.0, out=None, stats=False):

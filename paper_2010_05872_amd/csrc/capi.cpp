@@ -6,6 +6,8 @@
 #include <atomic>
 #include <functional>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -1132,6 +1134,83 @@ mgx_status batch_plan(std::vector<RecordedOp<T>> ops, const Tuning &tn, std::vec
   return MGX_OK;
 }
 
+// ---- persisted autotuning ----
+// A batch's best launch shape depends on its fields' shapes, not on where
+// they live, so the tuned shapes can outlive the process: with the
+// environment variable MGX_TUNE_CACHE naming a file, a batch met for the
+// first time looks its signature up there (a line "<signature> <target
+// blocks> <min z chunk> <mid z chunk> <ms>") and is built with the shape it
+// finds, without timing; a batch that is timed appends its line.  The
+// signature covers the direction and, per field, the dtype, dims, stop
+// level, which of labels / coefficients / statistics are used, and a hash
+// of the coordinate values.  An unreadable file is ignored.
+uint64_t fnv1a(const void *p, size_t n, uint64_t h) {
+  const unsigned char *c = (const unsigned char *)p;
+  for (size_t i = 0; i < n; i++) {
+    h ^= c[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+std::string batch_signature(int nfields, const mgx_field *f, bool dec) {
+  uint64_t h[2] = {1469598103934665603ull, 7809847782465536322ull};  // two seeds: 128 bits
+  auto put = [&](const void *p, size_t n) {
+    h[0] = fnv1a(p, n, h[0]);
+    h[1] = fnv1a(p, n, h[1]);
+  };
+  const char d = dec ? 'D' : 'R';
+  put(&d, 1);
+  put(&nfields, sizeof(nfields));
+  for (int i = 0; i < nfields; i++) {
+    const mgx_field &x = f[i];
+    const int32_t v[5] = {(int32_t)x.dtype, x.ndim, x.stop_level, x.labels ? 1 : 0,
+                          (x.labels && !dec && x.coef) || (dec && x.labels && x.stats) ? 1 : 0};
+    put(v, sizeof(v));
+    for (int a = 0; a < x.ndim && a < 3; a++) {
+      put(&x.dims[a], sizeof(int64_t));
+      const char has = x.coords[a] ? 1 : 0;
+      put(&has, 1);
+      if (x.coords[a]) put(x.coords[a], sizeof(double) * (size_t)x.dims[a]);
+    }
+  }
+  char buf[40];
+  std::snprintf(buf, sizeof(buf), "%016llx%016llx", (unsigned long long)h[0], (unsigned long long)h[1]);
+  return buf;
+}
+
+// The tuned shape of a signature in the cache file, if any.
+bool tune_cache_find(const std::string &sig, Tuning *tn, double *ms) {
+  const char *path = std::getenv("MGX_TUNE_CACHE");
+  if (!path || !*path) return false;
+  FILE *fp = std::fopen(path, "r");
+  if (!fp) return false;
+  char line[256];
+  bool found = false;
+  while (std::fgets(line, sizeof(line), fp)) {
+    char key[64];
+    Tuning t;
+    double m = 0.0;
+    if (std::sscanf(line, "%63s %d %d %d %lf", key, &t.target_blocks, &t.min_zchunk, &t.mid_zchunk, &m) == 5 &&
+        sig == key && t.target_blocks > 0 && t.min_zchunk > 0 && t.mid_zchunk > 0) {
+      *tn = t;  // the last matching line wins
+      *ms = m;
+      found = true;
+    }
+  }
+  std::fclose(fp);
+  return found;
+}
+
+void tune_cache_add(const std::string &sig, const Tuning &tn, double ms) {
+  const char *path = std::getenv("MGX_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE *fp = std::fopen(path, "a");
+  if (!fp) return;
+  std::fprintf(fp, "%s %d %d %d %.6f\n", sig.c_str(), tn.target_blocks, tn.min_zchunk, tn.mid_zchunk, ms);
+  std::fclose(fp);
+}
+
 struct BatchEntry {
   hipGraphExec_t exec = nullptr;
   void *dev = nullptr;
@@ -1141,6 +1220,7 @@ struct BatchEntry {
   int launches = 0;
   Tuning tn{};
   double tuned_ms = 0.0;
+  int tune_source = 0;        // 0 default shape, 1 timed here, 2 read from the tuning cache file
 };
 
 // A field of a decomposition batch that asks for statistics.
@@ -1306,9 +1386,18 @@ mgx_status run_batched(int nfields, const mgx_field *f, void *ws, size_t ws_byte
   hipStream_t cs = C.streams[dev];
   const std::string key = batch_key(nfields, f, ws, dec, bf);
   auto it = C.map.find(key);
+  Tuning cached;
+  double cached_ms = 0.0;
+  std::string sig;
+  if (it == C.map.end() && g_batch_autotune.load()) sig = batch_signature(nfields, f, dec);
   if (it == C.map.end()) {
     BatchEntry best;
-    if (g_batch_autotune.load()) {
+    if (!sig.empty() && tune_cache_find(sig, &cached, &cached_ms)) {
+      s = batch_build(nfields, f, bf, (char *)ws, dec, cached, cs, best);
+      if (s) return s;
+      best.tuned_ms = cached_ms;
+      best.tune_source = 2;
+    } else if (g_batch_autotune.load()) {
       // candidate launch shapes of the stencil kernels; inputs must be ready
       if (hipStreamSynchronize(stream) != hipSuccess) return MGX_ERR_HIP;
       const Tuning cand[] = {{2048, 8, 8}, {512, 4, 4}, {128, 2, 2}, {8192, 8, 4}};
@@ -1331,10 +1420,12 @@ mgx_status run_batched(int nfields, const mgx_field *f, void *ws, size_t ws_byte
           best = e;
           best_ms = ms;
           best.tuned_ms = ms;
+          best.tune_source = 1;
         } else {
           batch_entry_free(e);
         }
       }
+      tune_cache_add(sig, best.tn, best_ms);
     } else {
       s = batch_build(nfields, f, bf, (char *)ws, dec, Tuning{}, cs, best);
       if (s) return s;
@@ -1356,6 +1447,7 @@ mgx_status run_batched(int nfields, const mgx_field *f, void *ws, size_t ws_byte
   g_batch_info.target_blocks = e.tn.target_blocks;
   g_batch_info.min_zchunk = e.tn.min_zchunk;
   g_batch_info.tuned_ms = e.tuned_ms;
+  g_batch_info.tune_source = e.tune_source;
   if (e.nslot > 0 && hipMemsetAsync(e.stat, 0, kStatSlot * e.nslot, stream) != hipSuccess) return MGX_ERR_HIP;
   hipError_t le = traced(dec ? "decompose_batched" : "recompose_batched", -2, stream,
                          [&] { return hipGraphLaunch(e.exec, stream); });

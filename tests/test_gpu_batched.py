@@ -186,3 +186,44 @@ def test_batched_errors():
     with pytest.raises(mgx.MgxError) as e:
         mgx.Batch([dict(**{"in": u}, out=u)]).decompose()
     assert e.value.code == 1
+
+
+def test_tune_cache_persists(tmp_path, monkeypatch):
+    """MGX_TUNE_CACHE: a batch timed once appends its shape to the file; the
+    same field shapes at other addresses, after the in-process caches are
+    dropped, are built from the file without timing and give the same
+    results; malformed lines are skipped."""
+    _say("[batched] tune cache")
+    path = tmp_path / "tune.txt"
+    path.write_text("not a line\n0123 1 2\n")
+    monkeypatch.setenv("MGX_TUNE_CACHE", str(path))
+    specs = [((33, 17, 65), torch.float32), ((65, 33), torch.float64), ((17, 129, 17), torch.float32)]
+
+    def run():
+        us = [torch.as_tensor(workloads.gaussian_random_field(s, slope=3.0, seed=70 + i), dtype=dt, device="cuda")
+              for i, (s, dt) in enumerate(specs)]
+        outs = [torch.empty_like(u) for u in us]
+        mgx.Batch([dict(**{"in": u}, out=o) for u, o in zip(us, outs)]).decompose()
+        torch.cuda.synchronize()
+        for u, o in zip(us, outs):
+            assert torch.equal(o, mgx.decompose(u))
+        return mgx.batch_last_info()
+
+    mgx.batch_set_autotune(True)
+    try:
+        mgx.release_cached()
+        first = run()
+        assert first["tune_source"] == 1
+        lines = [ln.split() for ln in path.read_text().splitlines() if len(ln.split()) == 5]
+        assert len(lines) == 1
+        assert int(lines[0][1]) == first["target_blocks"] and int(lines[0][2]) == first["min_zchunk"]
+        mgx.release_cached()
+        second = run()
+        assert second["tune_source"] == 2
+        assert second["target_blocks"] == first["target_blocks"]
+        assert second["min_zchunk"] == first["min_zchunk"]
+        assert second["tuned_ms"] == pytest.approx(float(lines[0][4]), rel=1e-6)
+        assert len([ln for ln in path.read_text().splitlines() if len(ln.split()) == 5]) == 1
+    finally:
+        monkeypatch.delenv("MGX_TUNE_CACHE")
+        mgx.release_cached()
