@@ -517,6 +517,8 @@ def main():
                     help="run only the 4-D workload section (its own JSON line), e.g. under a profiler")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of the field (counter calibration)")
+    ap.add_argument("--only", choices=["entropy", "adaptive", "batched", "adjoint", "config1", "config3"],
+                    help="run only this section (its own JSON line), e.g. under a profiler")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -534,6 +536,12 @@ def main():
     if args.four_d_only:
         print(json.dumps({"four_d": four_d_section(torch, mgx, workloads, dev, args.steps)}), flush=True)
         return
+    reps_x = max(3, args.steps // 4)
+    if args.only in ("batched", "adjoint", "config1", "config3"):
+        fn = {"batched": batched_section, "adjoint": adjoint_section, "config1": config1_section,
+              "config3": config3_section}[args.only]
+        print(json.dumps({args.only: fn(torch, mgx, workloads, dev, reps_x)}), flush=True)
+        return
     n = args.n
     shape = (n, n, n)
     u = workloads.turbulence_field(n, device=dev, dtype=torch.float32)
@@ -550,6 +558,14 @@ def main():
     def step():
         mgx.decompose_quantize(u, tol, labels=labels, workspace=ws, keep_coef=False)
         mgx.dequantize_recompose(labels, tol, torch.float32, out=ut, workspace=ws)
+
+    if args.only == "entropy":
+        mgx.decompose_quantize(u, tol, labels=labels, workspace=ws, keep_coef=False)
+        print(json.dumps({"entropy": entropy_section(torch, mgx, u, labels, tol, reps_x)}), flush=True)
+        return
+    if args.only == "adaptive":
+        print(json.dumps({"adaptive": adaptive_section(torch, mgx, u, umc, ws, reps_x)}), flush=True)
+        return
 
     for _ in range(args.warmup):
         step()
