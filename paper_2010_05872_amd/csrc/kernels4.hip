@@ -18,12 +18,20 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "kernels4.hpp"
 #include "levelpos4.hpp"
 
 namespace mgx {
 namespace {
+
+// A uniform table entry through the constant address space: a scalar load,
+// so waiting for it never waits for the vector loads in flight.
+template <typename T>
+__device__ __forceinline__ T ldu4(const T *p, int i) {
+  return ((const __attribute__((address_space(4))) T *)p)[i];
+}
 
 // Quantization label of a coefficient and a coefficient of a label: the
 // operations of the separate (de)quantization passes (Sec. 4.1), so labels
@@ -54,6 +62,14 @@ __device__ __forceinline__ T unlabel4(int32_t l, double q) {
 // plane p at the column (the value itself when the column is nodal in axes
 // 1..3).  Q of each even plane is computed once and kept for the odd plane
 // after it, so every value of the level box is read about once.
+// Memory: a pair's words (the 8 corners of Q's stencil in the next even plane
+// -- on an axis where the column is even both corners are the same node --,
+// and the pair's own two values) are loaded together, without branches, and
+// one pair ahead: pair J+1's loads are issued before pair J's stores, and the
+// loaded words are used only in the next step (two register buffers, the
+// loop unrolled twice), so the march waits for memory once per pair at most
+// and the wait overlaps a pair of work.  The arithmetic is that of the nested
+// form (per axis: wl x(lo) + wr x(hi) on odd, x(lo) on even), unchanged.
 template <typename T, bool DEC, bool LAB>
 __global__ void __launch_bounds__(256) k_coef4(Coef4Args<T> a) {
   const int m1 = a.ax[1].m, m2 = a.ax[2].m, m3 = a.ax[3].m;
@@ -97,13 +113,15 @@ __global__ void __launch_bounds__(256) k_coef4(Coef4Args<T> a) {
   const T *__restrict__ umc_r = a.umc_r;
   const int32_t *__restrict__ lab_r = a.lab_r;
   T *__restrict__ out = a.out;
-  // Q(p): the interpolant over axes 1..3 at the column in plane p of src
-  // (fine plane index for DEC, coarse for REC), nested one axis at a time
-  auto Q = [&](int p) {
-    const T *b = src + (int64_t)p * plane;
-    auto row = [&](int64_t o) { return od[3] ? wlo[3] * b[o + lo[3]] + whi[3] * b[o + hi[3]] : b[o + lo[3]]; };
-    auto pln = [&](int64_t o) { return od[2] ? wlo[2] * row(o + lo[2]) + whi[2] * row(o + hi[2]) : row(o + lo[2]); };
-    return od[1] ? wlo[1] * pln(lo[1]) + whi[1] * pln(hi[1]) : pln(lo[1]);
+  // offsets of the 8 corners (bit 2: axis 1, bit 1: axis 2, bit 0: axis 3)
+  int64_t coff[8];
+#pragma unroll
+  for (int c = 0; c < 8; c++) coff[c] = ((c & 4) ? hi[1] : lo[1]) + ((c & 2) ? hi[2] : lo[2]) + ((c & 1) ? hi[3] : lo[3]);
+  // Q from the 8 loaded corners, nested one axis at a time
+  auto Qof = [&](const T (&x)[8]) {
+    auto row = [&](int b) { return od[3] ? wlo[3] * x[b] + whi[3] * x[b + 1] : x[b]; };
+    auto pln = [&](int b) { return od[2] ? wlo[2] * row(b) + whi[2] * row(b + 2) : row(b); };
+    return od[1] ? wlo[1] * pln(0) + whi[1] * pln(4) : pln(0);
   };
   // level-centric offsets of the column in u_mc, and its output offset
   auto lcp = [&](int jj, int k) { return (jj & 1) ? a.ax[k].c + (jj >> 1) : (jj >> 1); };
@@ -120,88 +138,179 @@ __global__ void __launch_bounds__(256) k_coef4(Coef4Args<T> a) {
       if (l == INT32_MIN && a.rng) count_range4(a.rng, c, a.qc);
     }
   };
-  // recompose: the coefficient at u_mc offset u
-  auto get = [&](int64_t u) { return LAB ? unlabel4<T>(lab_r[u], a.qc) : umc_r[u]; };
+  // recompose: a pair's coefficient words stay raw (labels) until used
+  using W = typename std::conditional<(!DEC && LAB), int32_t, T>::type;
+  auto val = [&](W w) -> T {
+    if constexpr (!DEC && LAB)
+      return unlabel4<T>(w, a.qc);
+    else
+      return w;
+  };
+  const W *__restrict__ cw = DEC ? nullptr : (LAB ? (const W *)lab_r : (const W *)umc_r);
   // this chunk's pairs (even plane 2J, odd plane 2J+1), J0 <= J < J1; the
   // last chunk also takes the last even plane
   const int npair = cc0 - 1;
   const int J0 = (int)blockIdx.y * a.jchunk;
   const int J1 = min(npair, J0 + a.jchunk);
   const bool last = J1 == npair;
-  T qprev = Q(DEC ? 2 * J0 : J0);
-  // one plane pair per iteration (unrolling measured slower for the
-  // recomposition kernel, equal for the decomposition)
-  auto pair = [&](int J) {
-    const int je = 2 * J;
-    const T qnext = Q(DEC ? je + 2 : J + 1);
-    const T ve = DEC ? V[je * plane + vcol] : (odd ? get((int64_t)J * a.up[0] + ucol) : T(0));
-    const int64_t u = (int64_t)(cc0 + J) * a.up[0] + ucol;
-    const T vo = DEC ? V[(je + 1) * plane + vcol] : get(u);
-    const T pred = a.ax[0].wl[je + 1] * qprev + a.ax[0].wr[je + 1] * qnext;
-    if (DEC) {
-      if (odd) put((int64_t)J * a.up[0] + ucol, ve - qprev);
-      put(u, vo - pred);
+  // the words of pair J: the corners of Q in plane 2J+2 (DEC) or J+1 (REC,
+  // coarse), the even plane's value and the odd plane's; plane indices are
+  // clamped into the box for J = npair (only its even value is used)
+  struct Words {
+    T q[8];
+    W e, o;
+  };
+  const int plast = DEC ? 2 * npair : npair;  // the last even plane (fine or coarse index)
+  auto fetch = [&](int J, Words &w) {
+    const T *b = src + (int64_t)min(DEC ? 2 * J + 2 : J + 1, plast) * plane;
+#pragma unroll
+    for (int c = 0; c < 8; c++) w.q[c] = b[coff[c]];
+    if constexpr (DEC) {
+      w.e = V[(int64_t)(2 * J) * plane + vcol];
+      w.o = V[(int64_t)min(2 * J + 1, plast) * plane + vcol];
     } else {
-      out[je * a.op[0] + ocol] = odd ? ve + qprev : qprev;
-      out[(je + 1) * a.op[0] + ocol] = vo + pred;
+      w.e = cw[(int64_t)J * a.up[0] + ucol];
+      w.o = cw[(int64_t)(cc0 + min(J, npair - 1)) * a.up[0] + ucol];
+    }
+  };
+  T qprev;
+  {
+    const T *b = src + (int64_t)(DEC ? 2 * J0 : J0) * plane;
+    T x[8];
+#pragma unroll
+    for (int c = 0; c < 8; c++) x[c] = b[coff[c]];
+    qprev = Qof(x);
+  }
+  auto pair = [&](int J, const Words &w) {
+    const int je = 2 * J;
+    const T qnext = Qof(w.q);
+    const int64_t u = (int64_t)(cc0 + J) * a.up[0] + ucol;
+    const T pred = ldu4(a.ax[0].wl, je + 1) * qprev + ldu4(a.ax[0].wr, je + 1) * qnext;
+    if (DEC) {
+      if (odd) put((int64_t)J * a.up[0] + ucol, val(w.e) - qprev);
+      put(u, val(w.o) - pred);
+    } else {
+      out[je * a.op[0] + ocol] = odd ? val(w.e) + qprev : qprev;
+      out[(je + 1) * a.op[0] + ocol] = val(w.o) + pred;
     }
     qprev = qnext;
   };
-  for (int J = J0; J < J1; J++) pair(J);
-  if (!last) return;
-  // the last (even) plane
-  const int J = J1;
-  const int je = 2 * J;
-  if (DEC) {
-    if (odd) put((int64_t)J * a.up[0] + ucol, V[je * plane + vcol] - qprev);
-  } else {
-    out[je * a.op[0] + ocol] = odd ? get((int64_t)J * a.up[0] + ucol) + qprev : qprev;
+  // the last (even) plane, from the words of pair J1
+  auto finish = [&](const Words &w) {
+    if (!last) return;
+    const int J = J1;
+    if (DEC) {
+      if (odd) put((int64_t)J * a.up[0] + ucol, val(w.e) - qprev);
+    } else {
+      out[(2 * J) * a.op[0] + ocol] = odd ? val(w.e) + qprev : qprev;
+    }
+  };
+  Words wa, wb;
+  fetch(J0, wa);
+  for (int J = J0;;) {
+    if (J == J1) {
+      finish(wa);
+      break;
+    }
+    fetch(J + 1, wb);
+    pair(J, wa);
+    if (++J == J1) {
+      finish(wb);
+      break;
+    }
+    fetch(J + 1, wa);
+    pair(J, wb);
+    ++J;
   }
 }
 
-template <typename T, bool GATHER>
+// One output per thread and step of a grid-stride loop, kSweepU steps taken
+// together: their inputs are all loaded (at positions clamped into the row or
+// the array, without branches) before any output is computed or stored, so a
+// thread has kSweepU outputs' loads in flight instead of one's.  The terms are
+// summed as before (a term outside the row, or at a nodal node of a gathered
+// row, is skipped), in the same order.
+constexpr int kSweepU = 4;
+template <typename T, bool GATHER, bool LABG>
 __global__ void __launch_bounds__(256) k_sweep4(Sweep4Args<T> a) {
+  // LABG: the gathered inputs are labels, raw until summed
+  using W = typename std::conditional<LABG, int32_t, T>::type;
   const uint64_t stride = (uint64_t)gridDim.x * 256u;
-  for (uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x; i < a.n; i += stride) {
-    const uint32_t t = udiv((uint32_t)i, a.dinner);
-    const uint32_t ii = (uint32_t)i - t * a.inner;
-    const uint32_t o = udiv(t, a.dc);
-    const int J = (int)(t - o * (uint32_t)a.c);
-    T acc = T(0);
-    if (!GATHER) {
-      const T *row = a.in + (int64_t)o * a.m * a.inner + ii;
+  for (uint64_t i0 = (uint64_t)blockIdx.x * 256u + threadIdx.x; i0 < a.n; i0 += kSweepU * stride) {
+    W x[kSweepU][5];
+    T wt[kSweepU][5];  // the stencil weights, loaded with the inputs
+    int Js[kSweepU];
+    bool skipn[kSweepU];  // gather: a nodal row, whose even inputs are zero
 #pragma unroll
-      for (int d = 0; d < 5; d++) {
-        const int jj = 2 * J + d - 2;
-        if (jj < 0 || jj >= a.m) continue;
-        acc += a.w5[5 * J + d] * row[(int64_t)jj * a.inner];
-      }
-    } else {
-      // o = (j0 m1 + j1) m2 + j2 of the level box; the sweep runs along axis 3
-      const uint32_t r = udiv(o, a.dm2);
-      const int j2 = (int)(o - r * (uint32_t)a.m2);
-      const int j0 = (int)udiv(r, a.dm1);
-      const int j1 = (int)(r - (uint32_t)j0 * (uint32_t)a.m1);
-      const bool nodal_row = ((j0 | j1 | j2) & 1) == 0;
-      auto lc = [&](int j, int k) { return (j & 1) ? a.cc[k] + (j >> 1) : (j >> 1); };
-      const int64_t base = (int64_t)lc(j0, 0) * a.up[0] + (int64_t)lc(j1, 1) * a.up[1] + (int64_t)lc(j2, 2) * a.up[2];
+    for (int u = 0; u < kSweepU; u++) {
+      const uint64_t iu = i0 + (uint64_t)u * stride;
+      const uint32_t i = (uint32_t)min(iu, (uint64_t)a.n - 1);
+      const uint32_t t = udiv(i, a.dinner);
+      const uint32_t ii = i - t * a.inner;
+      const uint32_t o = udiv(t, a.dc);
+      const int J = (int)(t - o * (uint32_t)a.c);
+      Js[u] = J;
+      skipn[u] = false;
 #pragma unroll
-      for (int d = 0; d < 5; d++) {
-        const int jj = 2 * J + d - 2;
-        if (jj < 0 || jj >= a.m) continue;
-        if (nodal_row && (jj & 1) == 0) continue;  // nodal node: component zero
-        const int64_t u = base + lc(jj, 3);
-        acc += a.w5[5 * J + d] * (a.lab ? unlabel4<T>(a.lab[u], a.qc) : a.umc[u]);
+      for (int d = 0; d < 5; d++) wt[u][d] = a.w5[5 * J + d];
+      if constexpr (!GATHER) {
+        const T *row = a.in + (int64_t)o * a.m * a.inner + ii;
+#pragma unroll
+        for (int d = 0; d < 5; d++) {
+          const int jj = min(max(2 * J + d - 2, 0), a.m - 1);
+          x[u][d] = row[(int64_t)jj * a.inner];
+        }
+      } else {
+        // o = (j0 m1 + j1) m2 + j2 of the level box; the sweep runs along axis 3
+        const uint32_t r = udiv(o, a.dm2);
+        const int j2 = (int)(o - r * (uint32_t)a.m2);
+        const int j0 = (int)udiv(r, a.dm1);
+        const int j1 = (int)(r - (uint32_t)j0 * (uint32_t)a.m1);
+        skipn[u] = ((j0 | j1 | j2) & 1) == 0;
+        auto lc = [&](int j, int k) { return (j & 1) ? a.cc[k] + (j >> 1) : (j >> 1); };
+        const int64_t base = (int64_t)lc(j0, 0) * a.up[0] + (int64_t)lc(j1, 1) * a.up[1] + (int64_t)lc(j2, 2) * a.up[2];
+#pragma unroll
+        for (int d = 0; d < 5; d++) {
+          const int jj = min(max(2 * J + d - 2, 0), a.m - 1);
+          const int64_t q = base + lc(jj, 3);
+          if constexpr (LABG)
+            x[u][d] = a.lab[q];
+          else
+            x[u][d] = (W)a.umc[q];
+        }
       }
     }
-    a.out[i] = acc;
+#pragma unroll
+    for (int u = 0; u < kSweepU; u++) {
+      const uint64_t iu = i0 + (uint64_t)u * stride;
+      if (iu >= a.n) break;
+      const int J = Js[u];
+      T acc = T(0);
+#pragma unroll
+      for (int d = 0; d < 5; d++) {
+        const int jj = 2 * J + d - 2;
+        if (jj < 0 || jj >= a.m) continue;
+        if (GATHER && skipn[u] && (jj & 1) == 0) continue;  // nodal node: component zero
+        T v;
+        if constexpr (LABG)
+          v = unlabel4<T>(x[u][d], a.qc);
+        else
+          v = x[u][d];
+        acc += wt[u][d] * v;
+      }
+      a.out[iu] = acc;
+    }
   }
 }
 
 // The same sweep as one march per (o, i) column along the axis (inner >=
 // kSweepMarchInner: consecutive threads on consecutive i, coalesced): output J
 // needs inputs 2J-2 .. 2J+2, of which 2J-2 .. 2J carry over from output J-1,
-// so each input row is read once per chunk (plus two rows at its start).
+// so each input row is read once per chunk (plus two rows at its start).  The
+// two new inputs of output J+1 are loaded before output J is computed and
+// stored (two register pairs, the loop unrolled twice), so the march keeps
+// one output's loads in flight; inputs outside the axis load a clamped
+// position and count as zero.
 template <typename T>
 __global__ void __launch_bounds__(256) k_sweep4_march(Sweep4Args<T> a) {
   const uint64_t col = (uint64_t)blockIdx.x * 256u + threadIdx.x;
@@ -214,22 +323,35 @@ __global__ void __launch_bounds__(256) k_sweep4_march(Sweep4Args<T> a) {
   const T *__restrict__ w5 = a.w5;
   const int64_t inner = a.inner;
   const int m = a.m;
-  auto x = [&](int j) { return (j >= 0 && j < m) ? row[(int64_t)j * inner] : T(0); };
+  auto ld = [&](int j) { return row[(int64_t)min(max(j, 0), m - 1) * inner]; };
+  auto x = [&](int j, T v) { return (j >= 0 && j < m) ? v : T(0); };
   const int J0 = (int)blockIdx.y * a.jchunk, J1 = min(a.c, J0 + a.jchunk);
-  T xm2 = x(2 * J0 - 2), xm1 = x(2 * J0 - 1), x0 = x(2 * J0);
-  for (int J = J0; J < J1; J++) {
-    const T x1 = x(2 * J + 1), x2 = x(2 * J + 2);
-    const T *w = w5 + 5 * J;
+  if (J0 >= J1) return;
+  T xm2 = x(2 * J0 - 2, ld(2 * J0 - 2)), xm1 = x(2 * J0 - 1, ld(2 * J0 - 1)), x0 = x(2 * J0, ld(2 * J0));
+  auto step = [&](int J, T r1, T r2) {
+    const T x1 = x(2 * J + 1, r1), x2 = x(2 * J + 2, r2);
+    // J is the same on every lane: the weights come through scalar loads
     T acc = T(0);
-    if (2 * J - 2 >= 0) acc += w[0] * xm2;
-    if (2 * J - 1 >= 0) acc += w[1] * xm1;
-    acc += w[2] * x0;
-    if (2 * J + 1 < m) acc += w[3] * x1;
-    if (2 * J + 2 < m) acc += w[4] * x2;
+    if (2 * J - 2 >= 0) acc += ldu4(w5, 5 * J) * xm2;
+    if (2 * J - 1 >= 0) acc += ldu4(w5, 5 * J + 1) * xm1;
+    acc += ldu4(w5, 5 * J + 2) * x0;
+    if (2 * J + 1 < m) acc += ldu4(w5, 5 * J + 3) * x1;
+    if (2 * J + 2 < m) acc += ldu4(w5, 5 * J + 4) * x2;
     out[(int64_t)J * inner] = acc;
     xm2 = x0;
     xm1 = x1;
     x0 = x2;
+  };
+  T a1 = ld(2 * J0 + 1), a2 = ld(2 * J0 + 2), b1, b2;
+  for (int J = J0;;) {
+    b1 = ld(2 * J + 3);
+    b2 = ld(2 * J + 4);
+    step(J, a1, a2);
+    if (++J == J1) break;
+    a1 = ld(2 * J + 3);
+    a2 = ld(2 * J + 4);
+    step(J, b1, b2);
+    if (++J == J1) break;
   }
 }
 
@@ -376,10 +498,13 @@ hipError_t launch_sweep4(Sweep4Args<T> a, bool gather, hipStream_t st) {
     hipLaunchKernelGGL((k_sweep4_march<T>), dim3((unsigned)((ncol + 255) / 256), a.nchunk), dim3(256), 0, st, a);
     return hipGetLastError();
   }
-  if (gather)
-    hipLaunchKernelGGL((k_sweep4<T, true>), dim3(grid_for(a.n)), dim3(256), 0, st, a);
+  const unsigned g = grid_for((a.n + kSweepU - 1) / kSweepU);
+  if (gather && a.lab)
+    hipLaunchKernelGGL((k_sweep4<T, true, true>), dim3(g), dim3(256), 0, st, a);
+  else if (gather)
+    hipLaunchKernelGGL((k_sweep4<T, true, false>), dim3(g), dim3(256), 0, st, a);
   else
-    hipLaunchKernelGGL((k_sweep4<T, false>), dim3(grid_for(a.n)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_sweep4<T, false, false>), dim3(g), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
