@@ -231,14 +231,16 @@ __global__ void __launch_bounds__(256) k_coef4(Coef4Args<T> a) {
 // summed as before (a term outside the row, or at a nodal node of a gathered
 // row, is skipped), in the same order.
 constexpr int kSweepU = 4;
-template <typename T, bool GATHER, bool LABG>
-__global__ void __launch_bounds__(256) k_sweep4(Sweep4Args<T> a) {
+constexpr int kSweepLdsW = 2560;
+// The sweep's loop; weights from wt_src (LDS or global, per WLDS).
+template <typename T, bool GATHER, bool LABG, bool WLDS>
+__device__ __forceinline__ void sweep4_body(const Sweep4Args<T> &a, const T *__restrict__ wt_src) {
   // LABG: the gathered inputs are labels, raw until summed
   using W = typename std::conditional<LABG, int32_t, T>::type;
   const uint64_t stride = (uint64_t)gridDim.x * 256u;
   for (uint64_t i0 = (uint64_t)blockIdx.x * 256u + threadIdx.x; i0 < a.n; i0 += kSweepU * stride) {
     W x[kSweepU][5];
-    T wt[kSweepU][5];  // the stencil weights, loaded with the inputs
+    T wt[kSweepU][5];  // the stencil weights, read with the inputs
     int Js[kSweepU];
     bool skipn[kSweepU];  // gather: a nodal row, whose even inputs are zero
 #pragma unroll
@@ -252,7 +254,12 @@ __global__ void __launch_bounds__(256) k_sweep4(Sweep4Args<T> a) {
       Js[u] = J;
       skipn[u] = false;
 #pragma unroll
-      for (int d = 0; d < 5; d++) wt[u][d] = a.w5[5 * J + d];
+      for (int d = 0; d < 5; d++) {
+        if constexpr (WLDS)
+          wt[u][d] = ((const __attribute__((address_space(3))) T *)wt_src)[5 * J + d];
+        else
+          wt[u][d] = wt_src[5 * J + d];
+      }
       if constexpr (!GATHER) {
         const T *row = a.in + (int64_t)o * a.m * a.inner + ii;
 #pragma unroll
@@ -300,6 +307,24 @@ __global__ void __launch_bounds__(256) k_sweep4(Sweep4Args<T> a) {
       }
       a.out[iu] = acc;
     }
+  }
+}
+
+// The stencil weights of the axis (5 per output index) are copied to LDS
+// when they fit kSweepLdsW entries, so that only the inputs go through the
+// texture/address units (the sweeps are bound by their load instructions).
+// The stencil weights of the axis (5 per output index) are copied to LDS
+// when they fit kSweepLdsW entries, so that only the inputs go through the
+// texture/address units (the sweeps are bound by their load instructions).
+template <typename T, bool GATHER, bool LABG>
+__global__ void __launch_bounds__(256) k_sweep4(Sweep4Args<T> a) {
+  __shared__ T s_w[kSweepLdsW];
+  if (5 * a.c <= kSweepLdsW) {
+    for (int k = threadIdx.x; k < 5 * a.c; k += 256) s_w[k] = a.w5[k];
+    __syncthreads();
+    sweep4_body<T, GATHER, LABG, true>(a, s_w);
+  } else {
+    sweep4_body<T, GATHER, LABG, false>(a, a.w5);
   }
 }
 
