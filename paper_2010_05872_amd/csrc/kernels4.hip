@@ -56,7 +56,11 @@ __device__ __forceinline__ T unlabel4(int32_t l, double q) {
 }
 
 // One thread per column (j1, j2, j3) of the level box and chunk of plane
-// pairs (blockIdx.y), marching along axis 0.
+// pairs (blockIdx.y), marching along axis 0.  A wave takes 62 consecutive
+// columns (lanes 1..62) plus one on either side (lanes 0 and 63, which only
+// load): the axis-3 neighbours j3 - 1, j3 + 1 of a column with odd j3 (never
+// the first or last of its row) are then the neighbouring lanes, whose values
+// come by lane shuffles, so a lane loads Q's corners only at its own j3.
 // The interpolant factors: Pi V(j) = wl0 Q(j0 - 1) + wr0 Q(j0 + 1) for odd j0
 // and Q(j0) for even j0, where Q(p) is the interpolant over axes 1..3 of
 // plane p at the column (the value itself when the column is nodal in axes
@@ -70,12 +74,17 @@ __device__ __forceinline__ T unlabel4(int32_t l, double q) {
 // loop unrolled twice), so the march waits for memory once per pair at most
 // and the wait overlaps a pair of work.  The arithmetic is that of the nested
 // form (per axis: wl x(lo) + wr x(hi) on odd, x(lo) on even), unchanged.
+constexpr int kCoefCols = 62;  // output columns per wave of k_coef4
 template <typename T, bool DEC, bool LAB>
 __global__ void __launch_bounds__(256) k_coef4(Coef4Args<T> a) {
   const int m1 = a.ax[1].m, m2 = a.ax[2].m, m3 = a.ax[3].m;
   const int c1 = a.ax[1].c, c2 = a.ax[2].c, c3 = a.ax[3].c;
-  const uint32_t col = blockIdx.x * 256u + threadIdx.x;
-  if (col >= a.ncol) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t wcol = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kCoefCols - 1 + lane;
+  // every lane runs the march (the shuffles need the whole wave); only lanes
+  // 1..62 of real columns store
+  const bool active = lane >= 1 && lane <= kCoefCols && wcol < (int64_t)a.ncol;
+  const uint32_t col = (uint32_t)min(max(wcol, (int64_t)0), (int64_t)a.ncol - 1);
   int j[4];
   {
     const uint32_t r = udiv(col, a.d3);
@@ -113,15 +122,26 @@ __global__ void __launch_bounds__(256) k_coef4(Coef4Args<T> a) {
   const T *__restrict__ umc_r = a.umc_r;
   const int32_t *__restrict__ lab_r = a.lab_r;
   T *__restrict__ out = a.out;
-  // offsets of the 8 corners (bit 2: axis 1, bit 1: axis 2, bit 0: axis 3)
-  int64_t coff[8];
+  // offsets of the 4 corner rows at the lane's own axis-3 position (bit 1:
+  // axis 1, bit 0: axis 2); the own position is j3 (DEC) or the coarse j3 >> 1
+  // (REC), whose axis-3 neighbours are: DEC lanes - 1 and + 1; REC the own
+  // value and lane + 1 (for odd j3, (j3 - 1) / 2 and (j3 + 1) / 2)
+  const int64_t own3 = DEC ? j[3] : (j[3] >> 1);
+  int64_t coff[4];
 #pragma unroll
-  for (int c = 0; c < 8; c++) coff[c] = ((c & 4) ? hi[1] : lo[1]) + ((c & 2) ? hi[2] : lo[2]) + ((c & 1) ? hi[3] : lo[3]);
-  // Q from the 8 loaded corners, nested one axis at a time
-  auto Qof = [&](const T (&x)[8]) {
-    auto row = [&](int b) { return od[3] ? wlo[3] * x[b] + whi[3] * x[b + 1] : x[b]; };
-    auto pln = [&](int b) { return od[2] ? wlo[2] * row(b) + whi[2] * row(b + 2) : row(b); };
-    return od[1] ? wlo[1] * pln(0) + whi[1] * pln(4) : pln(0);
+  for (int c = 0; c < 4; c++) coff[c] = ((c & 2) ? hi[1] : lo[1]) + ((c & 1) ? hi[2] : lo[2]) + own3;
+  // Q from the 4 loaded corner rows, nested one axis at a time (axis 3 first,
+  // as wl x(lo) + wr x(hi) on an odd index and x(lo) on an even one)
+  auto Qof = [&](const T (&x)[4]) {
+    T r[4];
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+      const T dn = __shfl_down(x[c], 1);
+      const T lo3v = DEC ? __shfl_up(x[c], 1) : x[c];
+      r[c] = od[3] ? wlo[3] * lo3v + whi[3] * dn : x[c];
+    }
+    auto pln = [&](int b) { return od[2] ? wlo[2] * r[b] + whi[2] * r[b + 1] : r[b]; };
+    return od[1] ? wlo[1] * pln(0) + whi[1] * pln(2) : pln(0);
   };
   // level-centric offsets of the column in u_mc, and its output offset
   auto lcp = [&](int jj, int k) { return (jj & 1) ? a.ax[k].c + (jj >> 1) : (jj >> 1); };
@@ -157,14 +177,14 @@ __global__ void __launch_bounds__(256) k_coef4(Coef4Args<T> a) {
   // coarse), the even plane's value and the odd plane's; plane indices are
   // clamped into the box for J = npair (only its even value is used)
   struct Words {
-    T q[8];
+    T q[4];
     W e, o;
   };
   const int plast = DEC ? 2 * npair : npair;  // the last even plane (fine or coarse index)
   auto fetch = [&](int J, Words &w) {
     const T *b = src + (int64_t)min(DEC ? 2 * J + 2 : J + 1, plast) * plane;
 #pragma unroll
-    for (int c = 0; c < 8; c++) w.q[c] = b[coff[c]];
+    for (int c = 0; c < 4; c++) w.q[c] = b[coff[c]];
     if constexpr (DEC) {
       w.e = V[(int64_t)(2 * J) * plane + vcol];
       w.o = V[(int64_t)min(2 * J + 1, plast) * plane + vcol];
@@ -176,9 +196,9 @@ __global__ void __launch_bounds__(256) k_coef4(Coef4Args<T> a) {
   T qprev;
   {
     const T *b = src + (int64_t)(DEC ? 2 * J0 : J0) * plane;
-    T x[8];
+    T x[4];
 #pragma unroll
-    for (int c = 0; c < 8; c++) x[c] = b[coff[c]];
+    for (int c = 0; c < 4; c++) x[c] = b[coff[c]];
     qprev = Qof(x);
   }
   auto pair = [&](int J, const Words &w) {
@@ -186,18 +206,20 @@ __global__ void __launch_bounds__(256) k_coef4(Coef4Args<T> a) {
     const T qnext = Qof(w.q);
     const int64_t u = (int64_t)(cc0 + J) * a.up[0] + ucol;
     const T pred = ldu4(a.ax[0].wl, je + 1) * qprev + ldu4(a.ax[0].wr, je + 1) * qnext;
-    if (DEC) {
-      if (odd) put((int64_t)J * a.up[0] + ucol, val(w.e) - qprev);
-      put(u, val(w.o) - pred);
-    } else {
-      out[je * a.op[0] + ocol] = odd ? val(w.e) + qprev : qprev;
-      out[(je + 1) * a.op[0] + ocol] = val(w.o) + pred;
+    if (active) {
+      if (DEC) {
+        if (odd) put((int64_t)J * a.up[0] + ucol, val(w.e) - qprev);
+        put(u, val(w.o) - pred);
+      } else {
+        out[je * a.op[0] + ocol] = odd ? val(w.e) + qprev : qprev;
+        out[(je + 1) * a.op[0] + ocol] = val(w.o) + pred;
+      }
     }
     qprev = qnext;
   };
   // the last (even) plane, from the words of pair J1
   auto finish = [&](const Words &w) {
-    if (!last) return;
+    if (!last || !active) return;
     const int J = J1;
     if (DEC) {
       if (odd) put((int64_t)J * a.up[0] + ucol, val(w.e) - qprev);
@@ -502,7 +524,7 @@ template <typename T>
 hipError_t launch_coef4(Coef4Args<T> a, bool dec, hipStream_t st) {
   if (a.ncol == 0) return hipSuccess;
   if (a.jchunk < 1 || a.nchunk < 1) return hipErrorInvalidValue;
-  const dim3 grid((a.ncol + 255) / 256, a.nchunk);
+  const dim3 grid((a.ncol + 4 * kCoefCols - 1) / (4 * kCoefCols), a.nchunk);
   if (dec && a.lab_w)
     hipLaunchKernelGGL((k_coef4<T, true, true>), grid, dim3(256), 0, st, a);
   else if (dec)
