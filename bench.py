@@ -369,12 +369,12 @@ def four_d_section(torch, mgx, workloads, dev, reps):
     kernels = sorted(({"name": k["name"], "level": k["level"], "avg_ms": round(k["total_ms"] / k["count"], 5)}
                       for k in kt), key=lambda k: -k["avg_ms"])[:8]
     # algorithmic bytes of the finest level's largest passes (fp32): the
-    # coefficient pass reads the level box and writes its coefficient nodes
-    # (15/16 of it), the first sweep reads the box (or the coefficients) and
-    # writes half of it, the recomposition's last pass reads the coefficients
-    # and writes the box
+    # decomposition's coefficient pass reads the level box and writes its
+    # coefficient nodes' labels (15/16 of it) and the first load-vector sweep
+    # (half of it); the recomposition's first sweep reads the labels and
+    # writes half the box, its last pass reads the labels and writes the box
     fin = {k["name"]: k["total_ms"] / k["count"] for k in kt if k["level"] == L}
-    per_unit = {"coef4_dec+q": 1 + 15 / 16, "sweep4_a3": 1.5, "sweep4_gather+q": 15 / 16 + 0.5,
+    per_unit = {"coef4_dec+q": 1 + 15 / 16 + 0.5, "sweep4_gather+q": 15 / 16 + 0.5,
                 "coef4_rec+q": 15 / 16 + 1}
     rates = {k: round(P * f * 4 / (fin[k] * 1e-3) / 1e9, 1) for k, f in per_unit.items() if k in fin}
     out = {

@@ -1751,11 +1751,11 @@ mgx_status run_decompose4(const Plan4 &P, int stop, const T *u, T *umc, char *ws
     ca.d3 = make_div32((uint32_t)m[3]);
     ca.d2 = make_div32((uint32_t)m[2]);
     march_chunks(ca, c[0]);
+    ca.g = A;  // the coefficient march also takes the axis-3 sweep
     if (traced(labels ? "coef4_dec+q" : "coef4_dec", l, st, [&] { return launch_coef4<T>(ca, true, st); }) !=
         hipSuccess)
       return MGX_ERR_HIP;
-    if (sweep4<T>("sweep4_a3", lv.ax[3], V, A, m[0] * m[1] * m[2], 1, l, st) != hipSuccess ||
-        sweep4<T>("sweep4_a2", lv.ax[2], A, B, m[0] * m[1], c[3], l, st) != hipSuccess ||
+    if (sweep4<T>("sweep4_a2", lv.ax[2], A, B, m[0] * m[1], c[3], l, st) != hipSuccess ||
         sweep4<T>("sweep4_a1", lv.ax[1], B, A, m[0], c[2] * c[3], l, st) != hipSuccess ||
         sweep4<T>("sweep4_a0", lv.ax[0], A, B, 1, c[1] * c[2] * c[3], l, st) != hipSuccess)
       return MGX_ERR_HIP;

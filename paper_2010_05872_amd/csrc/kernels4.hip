@@ -56,11 +56,16 @@ __device__ __forceinline__ T unlabel4(int32_t l, double q) {
 }
 
 // One thread per column (j1, j2, j3) of the level box and chunk of plane
-// pairs (blockIdx.y), marching along axis 0.  A wave takes 62 consecutive
-// columns (lanes 1..62) plus one on either side (lanes 0 and 63, which only
-// load): the axis-3 neighbours j3 - 1, j3 + 1 of a column with odd j3 (never
-// the first or last of its row) are then the neighbouring lanes, whose values
-// come by lane shuffles, so a lane loads Q's corners only at its own j3.
+// pairs (blockIdx.y), marching along axis 0.  A wave takes 60 consecutive
+// columns (lanes 2..61) plus two on either side (lanes 0, 1, 62, 63, which
+// only load): the axis-3 neighbours j3 - 1, j3 + 1 of a column with odd j3
+// (never the first or last of its row) are then the neighbouring lanes, whose
+// values come by lane shuffles, so a lane loads Q's corners only at its own
+// j3.  With a.g the decomposition also takes the first load-vector sweep
+// (R M along axis 3) of the planes it reads: the lane of an even j3 = 2 J3
+// sums w5[5 J3 + d] x(j3 + d - 2) over the lanes j3 - 2 .. j3 + 2 of its row
+// (terms outside the row skipped, the order of k_sweep4), so the level box is
+// read once for both.
 // The interpolant factors: Pi V(j) = wl0 Q(j0 - 1) + wr0 Q(j0 + 1) for odd j0
 // and Q(j0) for even j0, where Q(p) is the interpolant over axes 1..3 of
 // plane p at the column (the value itself when the column is nodal in axes
@@ -74,16 +79,17 @@ __device__ __forceinline__ T unlabel4(int32_t l, double q) {
 // loop unrolled twice), so the march waits for memory once per pair at most
 // and the wait overlaps a pair of work.  The arithmetic is that of the nested
 // form (per axis: wl x(lo) + wr x(hi) on odd, x(lo) on even), unchanged.
-constexpr int kCoefCols = 62;  // output columns per wave of k_coef4
+constexpr int kCoefHalo = 2;                     // load-only lanes on either side of a wave
+constexpr int kCoefCols = 64 - 2 * kCoefHalo;  // output columns per wave of k_coef4
 template <typename T, bool DEC, bool LAB>
 __global__ void __launch_bounds__(256) k_coef4(Coef4Args<T> a) {
   const int m1 = a.ax[1].m, m2 = a.ax[2].m, m3 = a.ax[3].m;
   const int c1 = a.ax[1].c, c2 = a.ax[2].c, c3 = a.ax[3].c;
   const int lane = threadIdx.x & 63;
-  const int64_t wcol = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kCoefCols - 1 + lane;
-  // every lane runs the march (the shuffles need the whole wave); only lanes
-  // 1..62 of real columns store
-  const bool active = lane >= 1 && lane <= kCoefCols && wcol < (int64_t)a.ncol;
+  const int64_t wcol = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kCoefCols - kCoefHalo + lane;
+  // every lane runs the march (the shuffles need the whole wave); only the
+  // inner lanes of real columns store
+  const bool active = lane >= kCoefHalo && lane < kCoefHalo + kCoefCols && wcol < (int64_t)a.ncol;
   const uint32_t col = (uint32_t)min(max(wcol, (int64_t)0), (int64_t)a.ncol - 1);
   int j[4];
   {
@@ -149,6 +155,33 @@ __global__ void __launch_bounds__(256) k_coef4(Coef4Args<T> a) {
   const int64_t vcol = ((int64_t)j[1] * m2 + j[2]) * m3 + j[3];
   const int64_t ocol = j[1] * a.op[1] + j[2] * a.op[2] + j[3];
   const int cc0 = a.ax[0].c;
+  // the fused axis-3 sweep: the lane's 5 weights (even j3 = 2 J3) and output row
+  const bool gout = DEC && a.g && active && !(j[3] & 1);
+  const int J3 = j[3] >> 1;
+  T g5[5];
+#pragma unroll
+  for (int d = 0; d < 5; d++) g5[d] = (DEC && a.g && !(j[3] & 1)) ? a.ax[3].w5[5 * J3 + d] : T(0);
+  const int64_t gplane = (int64_t)m1 * m2 * c3;
+  const int64_t grow = ((int64_t)j[1] * m2 + j[2]) * c3 + J3;
+  // the sweep output of plane p from the lane's value v of that plane (all
+  // lanes shuffle; the even lanes store)
+  auto sweep3 = [&](int p, T v) {
+    if (!DEC || !a.g) return;
+    T x[5];
+    x[0] = __shfl_up(v, 2);
+    x[1] = __shfl_up(v, 1);
+    x[2] = v;
+    x[3] = __shfl_down(v, 1);
+    x[4] = __shfl_down(v, 2);
+    T acc = T(0);
+#pragma unroll
+    for (int d = 0; d < 5; d++) {
+      const int jj = j[3] + d - 2;
+      if (jj < 0 || jj >= m3) continue;
+      acc += g5[d] * x[d];
+    }
+    if (gout) a.g[(int64_t)p * gplane + grow] = acc;
+  };
   // decompose: store coefficient c at u_mc offset u (and / or its label)
   auto put = [&](int64_t u, T c) {
     if (!LAB || umc_w) umc_w[u] = c;
@@ -206,6 +239,10 @@ __global__ void __launch_bounds__(256) k_coef4(Coef4Args<T> a) {
     const T qnext = Qof(w.q);
     const int64_t u = (int64_t)(cc0 + J) * a.up[0] + ucol;
     const T pred = ldu4(a.ax[0].wl, je + 1) * qprev + ldu4(a.ax[0].wr, je + 1) * qnext;
+    if (DEC) {
+      sweep3(je, val(w.e));
+      sweep3(je + 1, val(w.o));
+    }
     if (active) {
       if (DEC) {
         if (odd) put((int64_t)J * a.up[0] + ucol, val(w.e) - qprev);
@@ -219,8 +256,10 @@ __global__ void __launch_bounds__(256) k_coef4(Coef4Args<T> a) {
   };
   // the last (even) plane, from the words of pair J1
   auto finish = [&](const Words &w) {
-    if (!last || !active) return;
+    if (!last) return;
     const int J = J1;
+    if (DEC) sweep3(2 * J, val(w.e));
+    if (!active) return;
     if (DEC) {
       if (odd) put((int64_t)J * a.up[0] + ucol, val(w.e) - qprev);
     } else {

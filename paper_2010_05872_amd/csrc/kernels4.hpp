@@ -62,6 +62,9 @@ struct Coef4Args {
   // decompose with labels: counts of labels set to INT32_MIN, [0] finite
   // |c/q| >= 2^31 - 1, [1] c/q not finite (null: not counted)
   unsigned long long *rng;
+  // decompose (nullable): also the first load-vector sweep, R M along axis 3
+  // of the level box, out (m0, m1, m2, c3) compact, as k_sweep4 computes it
+  T *g;
 };
 
 // One load-vector sweep R M along one axis: in (outer, m, inner) ->
