@@ -283,8 +283,9 @@ OpArgs<T> tail_args(const Plan *P, int stop, const T *tab, char *ws, const Layou
   for (int i = 0; i < t.nlev; i++)
     for (int k = 0; k < 3; k++) {
       const AxisLevel &a = P->ax[lay.lt - i][k];
-      t.ax[i][k] = TailAxis<T>{tab + a.off_wl, tab + a.off_wr,   tab + a.off_w5, tab + a.off_mult,
-                               tab + a.off_invd, tab + a.off_qsup, (int)a.m,       (int)a.c};
+      t.ax[i][k] = TailAxis<T>{tab + a.off_wl,   tab + a.off_wr, tab + a.off_w5,  tab + a.off_mult,
+                               tab + a.off_invd, tab + a.off_qsup, (int)a.m,      (int)a.c,
+                               tail_magic(a.m),  tail_magic(a.c)};
     }
   (void)ws;
   return o;

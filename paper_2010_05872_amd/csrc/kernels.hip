@@ -2360,12 +2360,21 @@ __device__ __forceinline__ void tail_tables(const TailArgs<T> &a, T *sT, TailAxi
         b[q] = v;
       }
       if (threadIdx.x == 0)
-        ax[i][k] = TailAxis<T>{b, b + m, b + 2 * m, b + 2 * m + 5 * c, b + 2 * m + 6 * c, b + 2 * m + 7 * c, m, c};
+        ax[i][k] = TailAxis<T>{b, b + m, b + 2 * m, b + 2 * m + 5 * c, b + 2 * m + 6 * c, b + 2 * m + 7 * c, m, c,
+                               g.mm, g.cm};
     }
   __syncthreads();
 }
 
 __device__ __forceinline__ int lcp(int j, int c) { return (j & 1) ? c + (j >> 1) : (j >> 1); }
+
+// q / d and q % d for the tail's small boxes, from d's magic (TailAxis::mm,
+// cm): one multiply instead of an integer division sequence.  The phases of
+// a tail step split a linear index into box coordinates for every node, and
+// with one workgroup on one CU those divisions were most of their time.
+__device__ __forceinline__ int tdiv(int q, int d, uint32_t mg) {
+  return d > 1 ? (int)__umulhi((uint32_t)q, mg) : q;
+}
 
 // Weights and corner offsets (along one axis) of the multilinear interpolant
 // at level index j: corners lo/hi in units of the coarse index.
@@ -2408,8 +2417,9 @@ template <typename T>
 __device__ __forceinline__ void tail_load_vector(const TailAxis<T> (&ax)[3], const T *V, T *g1, T *g2, T *F) {
   const int m0 = ax[0].m, m1 = ax[1].m, m2 = ax[2].m, c0 = ax[0].c, c1 = ax[1].c, c2 = ax[2].c;
   const int tid = threadIdx.x;
+  const uint32_t c1g = ax[1].cm, c2g = ax[2].cm;
   for (int i = tid; i < m0 * m1 * c2; i += kTailThreads) {
-    const int X = i % c2, r = i / c2;
+    const int r = tdiv(i, c2, c2g), X = i - r * c2;
     T acc = T(0);
 #pragma unroll
     for (int d = 0; d < 5; d++) {
@@ -2420,7 +2430,7 @@ __device__ __forceinline__ void tail_load_vector(const TailAxis<T> (&ax)[3], con
   }
   __syncthreads();
   for (int i = tid; i < m0 * c1 * c2; i += kTailThreads) {
-    const int X = i % c2, r = i / c2, Y = r % c1, z = r / c1;
+    const int r = tdiv(i, c2, c2g), X = i - r * c2, z = tdiv(r, c1, c1g), Y = r - z * c1;
     T acc = T(0);
 #pragma unroll
     for (int d = 0; d < 5; d++) {
@@ -2431,7 +2441,7 @@ __device__ __forceinline__ void tail_load_vector(const TailAxis<T> (&ax)[3], con
   }
   __syncthreads();
   for (int i = tid; i < c0 * c1 * c2; i += kTailThreads) {
-    const int X = i % c2, r = i / c2, Y = r % c1, Z = r / c1;
+    const int r = tdiv(i, c2, c2g), X = i - r * c2, Z = tdiv(r, c1, c1g), Y = r - Z * c1;
     T acc = T(0);
 #pragma unroll
     for (int d = 0; d < 5; d++) {
@@ -2456,7 +2466,8 @@ __device__ __forceinline__ void tail_solves(const TailAxis<T> (&ax)[3], T *F) {
     const int nl = n[o1] * n[o2];
     const T *mult = ax[k].mult, *invd = ax[k].invd, *qsup = ax[k].qsup;
     if (tid < nl) {
-      T *p = F + (tid / n[o2]) * stride[o1] + (tid % n[o2]) * stride[o2];
+      const int t1 = tdiv(tid, n[o2], o2 == 2 ? ax[2].cm : ax[1].cm);
+      T *p = F + t1 * stride[o1] + (tid - t1 * n[o2]) * stride[o2];
       const int s = stride[k];
       T prev = p[0];
       for (int J = 1; J < c; J++) {
@@ -2484,13 +2495,14 @@ __device__ __forceinline__ void tail_dec_body(const TailArgs<T> &a) {
   tail_tables<T>(a, sT, tabs);
   {  // the level-lt box into LDS (all loads issued before the first wait)
     const int m0 = a.ax[0][0].m, m1 = a.ax[0][1].m, m2 = a.ax[0][2].m, n = m0 * m1 * m2;
+    const uint32_t m1g = a.ax[0][1].mm, m2g = a.ax[0][2].mm;
     constexpr int R = (kTailV + kTailThreads - 1) / kTailThreads;
     T r[R];
 #pragma unroll
     for (int k = 0; k < R; k++) {
-      const int q = tid + k * kTailThreads;
-      const int j2 = q % m2, t = q / m2, j1 = t % m1, j0 = t / m1;
-      r[k] = q < n ? a.src[j0 * a.sp0 + j1 * a.sp1 + j2] : T(0);
+      const int q = min(tid + k * kTailThreads, n - 1);
+      const int t = tdiv(q, m2, m2g), j2 = q - t * m2, j0 = tdiv(t, m1, m1g), j1 = t - j0 * m1;
+      r[k] = tid + k * kTailThreads < n ? a.src[j0 * a.sp0 + j1 * a.sp1 + j2] : T(0);
     }
 #pragma unroll
     for (int k = 0; k < R; k++)
@@ -2504,8 +2516,9 @@ __device__ __forceinline__ void tail_dec_body(const TailArgs<T> &a) {
     const int m1 = ax[1].m, m2 = ax[2].m, c0 = ax[0].c, c1 = ax[1].c, c2 = ax[2].c;
     const int m0 = ax[0].m;
     // coefficients of the level's non-nodal nodes, at level-centric positions
+    const uint32_t m1g = ax[1].mm, m2g = ax[2].mm;
     for (int q = tid; q < m0 * m1 * m2; q += kTailThreads) {
-      const int j2 = q % m2, r = q / m2, j1 = r % m1, j0 = r / m1;
+      const int r = tdiv(q, m2, m2g), j2 = q - r * m2, j0 = tdiv(r, m1, m1g), j1 = r - j0 * m1;
       if (!((j0 | j1 | j2) & 1)) continue;
       // nodal corners of V at level indices: the interpolant reads V at
       // 2*lo, 2*hi, i.e. a coarse view with doubled pitches
@@ -2527,7 +2540,7 @@ __device__ __forceinline__ void tail_dec_body(const TailArgs<T> &a) {
     tail_solves<T>(ax, F);
     if (i == a.nlev - 1) {
       for (int q = tid; q < c0 * c1 * c2; q += kTailThreads) {
-        const int X = q % c2, r = q / c2, Y = r % c1, Z = r / c1;
+        const int r = tdiv(q, c2, ax[2].cm), X = q - r * c2, Z = tdiv(r, c1, ax[1].cm), Y = r - Z * c1;
         const int64_t pos = Z * a.up0 + Y * a.up1 + X;
         if (a.umc) a.umc[pos] = F[q];
         if (a.lab_w) {
@@ -2557,7 +2570,7 @@ __device__ __forceinline__ void tail_rec_body(const TailArgs<T> &a) {
     const TailAxis<T>(&ax)[3] = tabs[a.nlev - 1];
     const int c0 = ax[0].c, c1 = ax[1].c, c2 = ax[2].c;
     for (int q = tid; q < c0 * c1 * c2; q += kTailThreads) {
-      const int X = q % c2, r = q / c2, Y = r % c1, Z = r / c1;
+      const int r = tdiv(q, c2, ax[2].cm), X = q - r * c2, Z = tdiv(r, c1, ax[1].cm), Y = r - Z * c1;
       const int64_t pos = Z * a.up0 + Y * a.up1 + X;
       vB[q] = a.lab_r ? from_label<T>(a.lab_r[pos], a.q[a.nlev]) : U[pos];
     }
@@ -2574,7 +2587,8 @@ __device__ __forceinline__ void tail_rec_body(const TailArgs<T> &a) {
 #pragma unroll
       for (int k = 0; k < R; k++) {
         const int q = tid + k * kTailThreads;
-        const int j2 = q % m2, t = q / m2, j1 = t % m1, j0 = t / m1;
+        const int qc = min(q, n - 1);
+        const int t = tdiv(qc, m2, ax[2].mm), j2 = qc - t * m2, j0 = tdiv(t, m1, ax[1].mm), j1 = t - j0 * m1;
         const bool coef = q < n && ((j0 | j1 | j2) & 1);
         const int64_t pos = coef ? lcp(j0, c0) * a.up0 + lcp(j1, c1) * a.up1 + lcp(j2, c2) : 0;
         if (a.lab_r) {
@@ -2598,7 +2612,7 @@ __device__ __forceinline__ void tail_rec_body(const TailArgs<T> &a) {
     // level box: nodal values, coefficients plus the interpolant
     const bool last = i == a.nlev - 1;
     for (int q = tid; q < m0 * m1 * m2; q += kTailThreads) {
-      const int j2 = q % m2, r = q / m2, j1 = r % m1, j0 = r / m1;
+      const int r = tdiv(q, m2, ax[2].mm), j2 = q - r * m2, j0 = tdiv(r, m1, ax[1].mm), j1 = r - j0 * m1;
       const T v = ((j0 | j1 | j2) & 1) ? sZ[q] + tail_interp<T>(fA, c1 * c2, c2, 1, ax, j0, j1, j2)
                                        : fA[((j0 >> 1) * c1 + (j1 >> 1)) * c2 + (j2 >> 1)];
       if (last)

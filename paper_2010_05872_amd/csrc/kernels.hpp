@@ -164,7 +164,12 @@ template <typename T>
 struct TailAxis {
   const T *wl, *wr, *w5, *mult, *invd, *qsup;
   int m, c;
+  // ceil(2^32 / m) and ceil(2^32 / c), 0 for 1: the tail's index splits
+  // (q / m as the high half of q * mm, exact for q * m < 2^32)
+  uint32_t mm, cm;
 };
+// ceil(2^32 / d) for the tail's divisions (d >= 1; 0 for d = 1)
+inline uint32_t tail_magic(int64_t d) { return d > 1 ? (uint32_t)((((uint64_t)1 << 32) + d - 1) / d) : 0u; }
 
 template <typename T>
 struct TailArgs {
