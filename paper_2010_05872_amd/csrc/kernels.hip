@@ -2339,30 +2339,65 @@ constexpr int kTailLds = kTailV + kTailG1 + kTailG2 + 2 * kTailF;
 // per level and axis: wl, wr (m each), w5 (5c), mult, invd, qsup (c each)
 constexpr int kTailTab = 2 * kTailM + 8 * kTailC;
 
-// Copies the tables of the tail's levels into LDS (they are read inside
-// dependent chains, e.g. every step of a line solve) and returns views of
-// them.  Ends with a workgroup barrier.
+// LDS-typed pointers for the tail: with generic pointers the compiler emits
+// flat accesses, which wait on the vector memory counter too, so every LDS
+// read would first wait for the level's label and coefficient stores.
 template <typename T>
-__device__ __forceinline__ void tail_tables(const TailArgs<T> &a, T *sT, TailAxis<T> (&ax)[kTailMax][3]) {
-  for (int i = 0; i < a.nlev; i++)
-    for (int k = 0; k < 3; k++) {
-      const TailAxis<T> &g = a.ax[i][k];
-      T *b = sT + (i * 3 + k) * kTailTab;
+using lds = __attribute__((address_space(3))) T;
+
+// One axis of one tail level, its tables in LDS: wl, wr (m each), w5 (5c),
+// mult, invd, qsup (c each), laid out in that order from b.
+template <typename T>
+struct TailTab {
+  lds<const T> *b;
+  int m, c;
+  uint32_t mm, cm;  // division magics as in TailAxis
+  __device__ __forceinline__ T wl(int j) const { return b[j]; }
+  __device__ __forceinline__ T wr(int j) const { return b[m + j]; }
+  __device__ __forceinline__ T w5(int i) const { return b[2 * m + i]; }
+  __device__ __forceinline__ T mult(int j) const { return b[2 * m + 5 * c + j]; }
+  __device__ __forceinline__ T invd(int j) const { return b[2 * m + 6 * c + j]; }
+  __device__ __forceinline__ T qsup(int j) const { return b[2 * m + 7 * c + j]; }
+};
+
+// Copies the tables of the tail's levels into LDS (they are read inside
+// dependent chains, e.g. every step of a line solve) and fills their views.
+// Each pair of waves takes one (level, axis) slot per round, 128 words, and
+// every round's load is issued before the first word is stored.  Ends with a
+// workgroup barrier.
+template <typename T>
+__device__ __forceinline__ void tail_tables(const TailArgs<T> &a, lds<T> *sT, TailTab<T> (&ax)[kTailMax][3]) {
+  static_assert(kTailTab <= 128, "one slot per pair of waves");
+  constexpr int kSlots = kTailThreads / 128, kRounds = (kTailMax * 3 + kSlots - 1) / kSlots;
+  const int tid = threadIdx.x, q = tid & 127;
+  const int s0 = __builtin_amdgcn_readfirstlane(tid >> 7);
+  T v[kRounds];
+  bool st[kRounds];
+#pragma unroll
+  for (int r = 0; r < kRounds; r++) {
+    const int sl = s0 + kSlots * r;
+    st[r] = false;
+    v[r] = T(0);
+    if (sl < 3 * a.nlev) {
+      const TailAxis<T> &g = a.ax[sl / 3][sl % 3];
       const int m = g.m, c = g.c;
-      for (int q = threadIdx.x; q < 2 * m + 8 * c; q += kTailThreads) {
-        T v;
-        if (q < m) v = g.wl[q];
-        else if (q < 2 * m) v = g.wr[q - m];
-        else if (q < 2 * m + 5 * c) v = g.w5[q - 2 * m];
-        else if (q < 2 * m + 6 * c) v = g.mult[q - 2 * m - 5 * c];
-        else if (q < 2 * m + 7 * c) v = g.invd[q - 2 * m - 6 * c];
-        else v = g.qsup[q - 2 * m - 7 * c];
-        b[q] = v;
-      }
-      if (threadIdx.x == 0)
-        ax[i][k] = TailAxis<T>{b, b + m, b + 2 * m, b + 2 * m + 5 * c, b + 2 * m + 6 * c, b + 2 * m + 7 * c, m, c,
-                               g.mm, g.cm};
+      const T *src = q < m           ? g.wl + q
+                     : q < 2 * m     ? g.wr + (q - m)
+                     : q < 2 * m + 5 * c ? g.w5 + (q - 2 * m)
+                     : q < 2 * m + 6 * c ? g.mult + (q - 2 * m - 5 * c)
+                     : q < 2 * m + 7 * c ? g.invd + (q - 2 * m - 6 * c)
+                                         : g.qsup + min(q - 2 * m - 7 * c, c - 1);
+      st[r] = q < 2 * m + 8 * c;
+      v[r] = *src;
     }
+  }
+#pragma unroll
+  for (int r = 0; r < kRounds; r++)
+    if (st[r]) sT[(s0 + kSlots * r) * kTailTab + q] = v[r];
+  if (tid < 3 * a.nlev) {
+    const TailAxis<T> &g = a.ax[tid / 3][tid % 3];
+    ax[tid / 3][tid % 3] = TailTab<T>{sT + tid * kTailTab, g.m, g.c, g.mm, g.cm};
+  }
   __syncthreads();
 }
 
@@ -2379,12 +2414,12 @@ __device__ __forceinline__ int tdiv(int q, int d, uint32_t mg) {
 // Weights and corner offsets (along one axis) of the multilinear interpolant
 // at level index j: corners lo/hi in units of the coarse index.
 template <typename T>
-__device__ __forceinline__ void tail_corner(const TailAxis<T> &ax, int j, int &lo, int &hi, T &wlo, T &whi) {
+__device__ __forceinline__ void tail_corner(const TailTab<T> &ax, int j, int &lo, int &hi, T &wlo, T &whi) {
   if (j & 1) {
     lo = (j - 1) >> 1;
     hi = (j + 1) >> 1;
-    wlo = ax.wl[j];
-    whi = ax.wr[j];
+    wlo = ax.wl(j);
+    whi = ax.wr(j);
   } else {
     lo = hi = j >> 1;
     wlo = T(1);
@@ -2394,8 +2429,8 @@ __device__ __forceinline__ void tail_corner(const TailAxis<T> &ax, int j, int &l
 
 // Interpolant at level node (j0,j1,j2) from a coarse box C (pitches cp0, cp1).
 template <typename T>
-__device__ __forceinline__ T tail_interp(const T *C, int cp0, int cp1, int cp2, const TailAxis<T> (&ax)[3], int j0,
-                                         int j1, int j2) {
+__device__ __forceinline__ T tail_interp(const lds<T> *C, int cp0, int cp1, int cp2, const TailTab<T> (&ax)[3],
+                                         int j0, int j1, int j2) {
   int lo[3], hi[3];
   T wlo[3], whi[3];
   tail_corner(ax[0], j0, lo[0], hi[0], wlo[0], whi[0]);
@@ -2414,7 +2449,8 @@ __device__ __forceinline__ T tail_interp(const T *C, int cp0, int cp1, int cp2, 
 
 // F = (R M)^{x3} of the level box V (compact, in LDS), via g1 and g2.
 template <typename T>
-__device__ __forceinline__ void tail_load_vector(const TailAxis<T> (&ax)[3], const T *V, T *g1, T *g2, T *F) {
+__device__ __forceinline__ void tail_load_vector(const TailTab<T> (&ax)[3], const lds<T> *V, lds<T> *g1, lds<T> *g2,
+                                                 lds<T> *F) {
   const int m0 = ax[0].m, m1 = ax[1].m, m2 = ax[2].m, c0 = ax[0].c, c1 = ax[1].c, c2 = ax[2].c;
   const int tid = threadIdx.x;
   const uint32_t c1g = ax[1].cm, c2g = ax[2].cm;
@@ -2424,7 +2460,7 @@ __device__ __forceinline__ void tail_load_vector(const TailAxis<T> (&ax)[3], con
 #pragma unroll
     for (int d = 0; d < 5; d++) {
       const int x = 2 * X + d - 2;
-      if (x >= 0 && x < m2) acc += ax[2].w5[X * 5 + d] * V[r * m2 + x];
+      if (x >= 0 && x < m2) acc += ax[2].w5(X * 5 + d) * V[r * m2 + x];
     }
     g1[i] = acc;
   }
@@ -2435,7 +2471,7 @@ __device__ __forceinline__ void tail_load_vector(const TailAxis<T> (&ax)[3], con
 #pragma unroll
     for (int d = 0; d < 5; d++) {
       const int y = 2 * Y + d - 2;
-      if (y >= 0 && y < m1) acc += ax[1].w5[Y * 5 + d] * g1[(z * m1 + y) * c2 + X];
+      if (y >= 0 && y < m1) acc += ax[1].w5(Y * 5 + d) * g1[(z * m1 + y) * c2 + X];
     }
     g2[i] = acc;
   }
@@ -2446,7 +2482,7 @@ __device__ __forceinline__ void tail_load_vector(const TailAxis<T> (&ax)[3], con
 #pragma unroll
     for (int d = 0; d < 5; d++) {
       const int z = 2 * Z + d - 2;
-      if (z >= 0 && z < m0) acc += ax[0].w5[Z * 5 + d] * g2[(z * c1 + Y) * c2 + X];
+      if (z >= 0 && z < m0) acc += ax[0].w5(Z * 5 + d) * g2[(z * c1 + Y) * c2 + X];
     }
     F[i] = acc;
   }
@@ -2455,7 +2491,7 @@ __device__ __forceinline__ void tail_load_vector(const TailAxis<T> (&ax)[3], con
 
 // Thomas solves of the coarse mass matrix along x, y and z, in place on F.
 template <typename T>
-__device__ __forceinline__ void tail_solves(const TailAxis<T> (&ax)[3], T *F) {
+__device__ __forceinline__ void tail_solves(const TailTab<T> (&ax)[3], lds<T> *F) {
   const int c0 = ax[0].c, c1 = ax[1].c, c2 = ax[2].c;
   const int tid = threadIdx.x;
   const int n[3] = {c0, c1, c2};
@@ -2464,20 +2500,20 @@ __device__ __forceinline__ void tail_solves(const TailAxis<T> (&ax)[3], T *F) {
     const int c = n[k];
     const int o1 = k == 0 ? 1 : 0, o2 = k == 2 ? 1 : 2;
     const int nl = n[o1] * n[o2];
-    const T *mult = ax[k].mult, *invd = ax[k].invd, *qsup = ax[k].qsup;
+    const TailTab<T> &t = ax[k];
     if (tid < nl) {
       const int t1 = tdiv(tid, n[o2], o2 == 2 ? ax[2].cm : ax[1].cm);
-      T *p = F + t1 * stride[o1] + (tid - t1 * n[o2]) * stride[o2];
+      lds<T> *p = F + t1 * stride[o1] + (tid - t1 * n[o2]) * stride[o2];
       const int s = stride[k];
       T prev = p[0];
       for (int J = 1; J < c; J++) {
-        prev = p[J * s] - mult[J] * prev;
+        prev = p[J * s] - t.mult(J) * prev;
         p[J * s] = prev;
       }
-      T y = invd[c - 1] * prev;
+      T y = t.invd(c - 1) * prev;
       p[(c - 1) * s] = y;
       for (int J = c - 2; J >= 0; J--) {
-        y = invd[J] * p[J * s] - qsup[J] * y;
+        y = t.invd(J) * p[J * s] - t.qsup(J) * y;
         p[J * s] = y;
       }
     }
@@ -2487,11 +2523,13 @@ __device__ __forceinline__ void tail_solves(const TailAxis<T> (&ax)[3], T *F) {
 
 template <typename T>
 __device__ __forceinline__ void tail_dec_body(const TailArgs<T> &a) {
-  __shared__ T sm[kTailLds];
-  __shared__ T sT[kTailMax * 3 * kTailTab];
-  T *const sV = sm, *const g1 = sV + kTailV, *const g2 = g1 + kTailG1, *const fA = g2 + kTailG2, *const fB = fA + kTailF;
+  __shared__ T sm_[kTailLds];
+  __shared__ T sT_[kTailMax * 3 * kTailTab];
+  lds<T> *const sm = (lds<T> *)sm_, *const sT = (lds<T> *)sT_;
+  lds<T> *const sV = sm, *const g1 = sV + kTailV, *const g2 = g1 + kTailG1, *const fA = g2 + kTailG2,
+                *const fB = fA + kTailF;
   const int tid = threadIdx.x;
-  __shared__ TailAxis<T> tabs[kTailMax][3];  // views of sT
+  __shared__ TailTab<T> tabs[kTailMax][3];  // views of sT
   tail_tables<T>(a, sT, tabs);
   {  // the level-lt box into LDS (all loads issued before the first wait)
     const int m0 = a.ax[0][0].m, m1 = a.ax[0][1].m, m2 = a.ax[0][2].m, n = m0 * m1 * m2;
@@ -2500,21 +2538,23 @@ __device__ __forceinline__ void tail_dec_body(const TailArgs<T> &a) {
     T r[R];
 #pragma unroll
     for (int k = 0; k < R; k++) {
-      const int q = min(tid + k * kTailThreads, n - 1);
+      const int q = min(tid + k * kTailThreads, n - 1);  // lanes past the box reload its last node
       const int t = tdiv(q, m2, m2g), j2 = q - t * m2, j0 = tdiv(t, m1, m1g), j1 = t - j0 * m1;
-      r[k] = tid + k * kTailThreads < n ? a.src[j0 * a.sp0 + j1 * a.sp1 + j2] : T(0);
+      r[k] = a.src[j0 * a.sp0 + j1 * a.sp1 + j2];
     }
 #pragma unroll
     for (int k = 0; k < R; k++)
       if (tid + k * kTailThreads < n) sV[tid + k * kTailThreads] = r[k];
     __syncthreads();
   }
-  const T *V = sV;
+  const lds<T> *V = sV;
   int lmax = 0;  // with a.smax: largest |label| of the current level written by this thread
   for (int i = 0; i < a.nlev; i++) {
-    const TailAxis<T>(&ax)[3] = tabs[i];
+    const TailTab<T>(&ax)[3] = tabs[i];
     const int m1 = ax[1].m, m2 = ax[2].m, c0 = ax[0].c, c1 = ax[1].c, c2 = ax[2].c;
     const int m0 = ax[0].m;
+    const double qi = a.q[i];
+    const float rqi = label_rcp(qi);
     // coefficients of the level's non-nodal nodes, at level-centric positions
     const uint32_t m1g = ax[1].mm, m2g = ax[2].mm;
     for (int q = tid; q < m0 * m1 * m2; q += kTailThreads) {
@@ -2526,27 +2566,30 @@ __device__ __forceinline__ void tail_dec_body(const TailArgs<T> &a) {
       const int64_t pos = lcp(j0, c0) * a.up0 + lcp(j1, c1) * a.up1 + lcp(j2, c2);
       if (a.umc) a.umc[pos] = v;
       if (a.lab_w) {
-        const int32_t lab = label_of(v, a.q[i], label_rcp(a.q[i]));
+        const int32_t lab = label_of(v, qi, rqi);
         a.lab_w[pos] = lab;
-        if (lab == INT32_MIN && a.rng) count_out_of_range(a.rng, v, a.q[i]);
+        if (lab == INT32_MIN && a.rng) count_out_of_range(a.rng, v, qi);
         if (lab != INT32_MIN) lmax = max(lmax, lab < 0 ? -lab : lab);
       }
     }
     if (a.smax && lmax > 0) atomicMax(&a.smax[a.nlev - i], lmax);  // level lt - i; the tail is small
     lmax = 0;
     // Q_{l-1} u = Mc^{-1} (R M)^{x3} V (as in the tiled decomposition)
-    T *F = (i & 1) ? fB : fA;
+    lds<T> *F = (i & 1) ? fB : fA;
     tail_load_vector<T>(ax, V, g1, g2, F);
     tail_solves<T>(ax, F);
     if (i == a.nlev - 1) {
+      const double qs = a.q[a.nlev];
+      const float rqs = label_rcp(qs);
       for (int q = tid; q < c0 * c1 * c2; q += kTailThreads) {
         const int r = tdiv(q, c2, ax[2].cm), X = q - r * c2, Z = tdiv(r, c1, ax[1].cm), Y = r - Z * c1;
         const int64_t pos = Z * a.up0 + Y * a.up1 + X;
-        if (a.umc) a.umc[pos] = F[q];
+        const T f = F[q];
+        if (a.umc) a.umc[pos] = f;
         if (a.lab_w) {
-          const int32_t lab = label_of(F[q], a.q[a.nlev], label_rcp(a.q[a.nlev]));
+          const int32_t lab = label_of(f, qs, rqs);
           a.lab_w[pos] = lab;
-          if (lab == INT32_MIN && a.rng) count_out_of_range(a.rng, F[q], a.q[a.nlev]);
+          if (lab == INT32_MIN && a.rng) count_out_of_range(a.rng, f, qs);
           if (lab != INT32_MIN) lmax = max(lmax, lab < 0 ? -lab : lab);
         }
       }
@@ -2558,46 +2601,60 @@ __device__ __forceinline__ void tail_dec_body(const TailArgs<T> &a) {
 
 template <typename T>
 __device__ __forceinline__ void tail_rec_body(const TailArgs<T> &a) {
-  __shared__ T sm[kTailLds];
-  __shared__ T sT[kTailMax * 3 * kTailTab];
-  T *const sZ = sm, *const g1 = sZ + kTailV, *const g2 = g1 + kTailG1, *const fA = g2 + kTailG2, *const vB = fA + kTailF;
+  __shared__ T sm_[kTailLds];
+  __shared__ T sT_[kTailMax * 3 * kTailTab];
+  lds<T> *const sm = (lds<T> *)sm_, *const sT = (lds<T> *)sT_;
+  lds<T> *const sZ = sm, *const g1 = sZ + kTailV, *const g2 = g1 + kTailG1, *const fA = g2 + kTailG2,
+                *const vB = fA + kTailF;
   const int tid = threadIdx.x;
-  __shared__ TailAxis<T> tabs[kTailMax][3];  // views of sT
+  __shared__ TailTab<T> tabs[kTailMax][3];  // views of sT
   tail_tables<T>(a, sT, tabs);
   const T *U = a.umc_r;
   // nodal values of the level below: the stop box of u_mc first
   {
-    const TailAxis<T>(&ax)[3] = tabs[a.nlev - 1];
+    const TailTab<T>(&ax)[3] = tabs[a.nlev - 1];
     const int c0 = ax[0].c, c1 = ax[1].c, c2 = ax[2].c;
+    const double qs = a.q[a.nlev];
     for (int q = tid; q < c0 * c1 * c2; q += kTailThreads) {
       const int r = tdiv(q, c2, ax[2].cm), X = q - r * c2, Z = tdiv(r, c1, ax[1].cm), Y = r - Z * c1;
       const int64_t pos = Z * a.up0 + Y * a.up1 + X;
-      vB[q] = a.lab_r ? from_label<T>(a.lab_r[pos], a.q[a.nlev]) : U[pos];
+      vB[q] = a.lab_r ? from_label<T>(a.lab_r[pos], qs) : U[pos];
     }
   }
   for (int i = 0; i < a.nlev; i++) {
-    const TailAxis<T>(&ax)[3] = tabs[a.nlev - 1 - i];
+    const TailTab<T>(&ax)[3] = tabs[a.nlev - 1 - i];
     const int m0 = ax[0].m, m1 = ax[1].m, m2 = ax[2].m, c0 = ax[0].c, c1 = ax[1].c, c2 = ax[2].c;
     // the level's coefficients (zero at nodal nodes) into LDS, all loads
     // issued before the first wait
     {
       const int n = m0 * m1 * m2;
+      const double qi = a.q[a.nlev - 1 - i];
       constexpr int R = (kTailV + kTailThreads - 1) / kTailThreads;
-      T r[R];
+      int64_t pos[R];
+      unsigned coef = 0;
 #pragma unroll
       for (int k = 0; k < R; k++) {
         const int q = tid + k * kTailThreads;
         const int qc = min(q, n - 1);
         const int t = tdiv(qc, m2, ax[2].mm), j2 = qc - t * m2, j0 = tdiv(t, m1, ax[1].mm), j1 = t - j0 * m1;
-        const bool coef = q < n && ((j0 | j1 | j2) & 1);
-        const int64_t pos = coef ? lcp(j0, c0) * a.up0 + lcp(j1, c1) * a.up1 + lcp(j2, c2) : 0;
-        if (a.lab_r) {
-          const int32_t lv = a.lab_r[pos];
-          r[k] = coef ? from_label<T>(lv, a.q[a.nlev - 1 - i]) : T(0);
-        } else {
-          const T cvv = U[pos];
-          r[k] = coef ? cvv : T(0);
-        }
+        const bool cf = q < n && ((j0 | j1 | j2) & 1);
+        coef |= (unsigned)cf << k;
+        pos[k] = cf ? lcp(j0, c0) * a.up0 + lcp(j1, c1) * a.up1 + lcp(j2, c2) : 0;
+      }
+      // every load issued unconditionally (nodal lanes read element 0) and
+      // converted only after the last one, so the thread waits once
+      T r[R];
+      if (a.lab_r) {
+        int32_t w[R];
+#pragma unroll
+        for (int k = 0; k < R; k++) w[k] = a.lab_r[pos[k]];
+#pragma unroll
+        for (int k = 0; k < R; k++) r[k] = ((coef >> k) & 1u) ? from_label<T>(w[k], qi) : T(0);
+      } else {
+#pragma unroll
+        for (int k = 0; k < R; k++) r[k] = U[pos[k]];
+#pragma unroll
+        for (int k = 0; k < R; k++) r[k] = ((coef >> k) & 1u) ? r[k] : T(0);
       }
 #pragma unroll
       for (int k = 0; k < R; k++)
