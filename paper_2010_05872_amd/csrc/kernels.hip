@@ -2415,19 +2415,18 @@ __device__ __forceinline__ int tdiv(int q, int d, uint32_t mg) {
 // at level index j: corners lo/hi in units of the coarse index.
 template <typename T>
 __device__ __forceinline__ void tail_corner(const TailTab<T> &ax, int j, int &lo, int &hi, T &wlo, T &whi) {
-  if (j & 1) {
-    lo = (j - 1) >> 1;
-    hi = (j + 1) >> 1;
-    wlo = ax.wl(j);
-    whi = ax.wr(j);
-  } else {
-    lo = hi = j >> 1;
-    wlo = T(1);
-    whi = T(0);
-  }
+  const int odd = j & 1;
+  const T l = ax.wl(j), r = ax.wr(j);
+  lo = (j - odd) >> 1;
+  hi = (j + odd) >> 1;
+  wlo = odd ? l : T(1);
+  whi = odd ? r : T(0);
 }
 
 // Interpolant at level node (j0,j1,j2) from a coarse box C (pitches cp0, cp1).
+// All eight corners are read and summed in a fixed order; a corner of weight
+// zero (an even index) adds a signed zero, which leaves the sum's value as
+// it is.  Without branches the reads of a node go out together.
 template <typename T>
 __device__ __forceinline__ T tail_interp(const lds<T> *C, int cp0, int cp1, int cp2, const TailTab<T> (&ax)[3],
                                          int j0, int j1, int j2) {
@@ -2440,9 +2439,8 @@ __device__ __forceinline__ T tail_interp(const lds<T> *C, int cp0, int cp1, int 
 #pragma unroll
   for (int c = 0; c < 8; c++) {
     const T w = ((c & 1) ? whi[0] : wlo[0]) * ((c & 2) ? whi[1] : wlo[1]) * ((c & 4) ? whi[2] : wlo[2]);
-    if (w != T(0))
-      acc += w * C[((c & 1) ? hi[0] : lo[0]) * cp0 + ((c & 2) ? hi[1] : lo[1]) * cp1 +
-                   ((c & 4) ? hi[2] : lo[2]) * cp2];
+    acc += w * C[((c & 1) ? hi[0] : lo[0]) * cp0 + ((c & 2) ? hi[1] : lo[1]) * cp1 +
+                 ((c & 4) ? hi[2] : lo[2]) * cp2];
   }
   return acc;
 }
@@ -2458,9 +2456,11 @@ __device__ __forceinline__ void tail_load_vector(const TailTab<T> (&ax)[3], cons
     const int r = tdiv(i, c2, c2g), X = i - r * c2;
     T acc = T(0);
 #pragma unroll
-    for (int d = 0; d < 5; d++) {
+    for (int d = 0; d < 5; d++) {  // taps outside the box: weight 0 on a node inside
       const int x = 2 * X + d - 2;
-      if (x >= 0 && x < m2) acc += ax[2].w5(X * 5 + d) * V[r * m2 + x];
+      const bool in = x >= 0 && x < m2;
+      const T w = ax[2].w5(X * 5 + d);
+      acc += (in ? w : T(0)) * V[r * m2 + (in ? x : 0)];
     }
     g1[i] = acc;
   }
@@ -2471,7 +2471,9 @@ __device__ __forceinline__ void tail_load_vector(const TailTab<T> (&ax)[3], cons
 #pragma unroll
     for (int d = 0; d < 5; d++) {
       const int y = 2 * Y + d - 2;
-      if (y >= 0 && y < m1) acc += ax[1].w5(Y * 5 + d) * g1[(z * m1 + y) * c2 + X];
+      const bool in = y >= 0 && y < m1;
+      const T w = ax[1].w5(Y * 5 + d);
+      acc += (in ? w : T(0)) * g1[(z * m1 + (in ? y : 0)) * c2 + X];
     }
     g2[i] = acc;
   }
@@ -2482,7 +2484,9 @@ __device__ __forceinline__ void tail_load_vector(const TailTab<T> (&ax)[3], cons
 #pragma unroll
     for (int d = 0; d < 5; d++) {
       const int z = 2 * Z + d - 2;
-      if (z >= 0 && z < m0) acc += ax[0].w5(Z * 5 + d) * g2[(z * c1 + Y) * c2 + X];
+      const bool in = z >= 0 && z < m0;
+      const T w = ax[0].w5(Z * 5 + d);
+      acc += (in ? w : T(0)) * g2[((in ? z : 0) * c1 + Y) * c2 + X];
     }
     F[i] = acc;
   }
@@ -2490,6 +2494,9 @@ __device__ __forceinline__ void tail_load_vector(const TailTab<T> (&ax)[3], cons
 }
 
 // Thomas solves of the coarse mass matrix along x, y and z, in place on F.
+// A thread takes one line: its values and factors are read into registers
+// first (lines have at most kTailC nodes), so the two sweeps' dependent
+// chains run in registers rather than through LDS round trips.
 template <typename T>
 __device__ __forceinline__ void tail_solves(const TailTab<T> (&ax)[3], lds<T> *F) {
   const int c0 = ax[0].c, c1 = ax[1].c, c2 = ax[2].c;
@@ -2505,17 +2512,30 @@ __device__ __forceinline__ void tail_solves(const TailTab<T> (&ax)[3], lds<T> *F
       const int t1 = tdiv(tid, n[o2], o2 == 2 ? ax[2].cm : ax[1].cm);
       lds<T> *p = F + t1 * stride[o1] + (tid - t1 * n[o2]) * stride[o2];
       const int s = stride[k];
-      T prev = p[0];
-      for (int J = 1; J < c; J++) {
-        prev = p[J * s] - t.mult(J) * prev;
-        p[J * s] = prev;
+      T x[kTailC], mu[kTailC], iv[kTailC], qs[kTailC];
+#pragma unroll
+      for (int J = 0; J < kTailC; J++) {
+        const int Jc = min(J, c - 1);
+        x[J] = p[Jc * s];
+        mu[J] = t.mult(Jc);
+        iv[J] = t.invd(Jc);
+        qs[J] = t.qsup(Jc);
       }
-      T y = t.invd(c - 1) * prev;
-      p[(c - 1) * s] = y;
-      for (int J = c - 2; J >= 0; J--) {
-        y = t.invd(J) * p[J * s] - t.qsup(J) * y;
-        p[J * s] = y;
+#pragma unroll
+      for (int J = 1; J < kTailC; J++) {
+        const T f = x[J] - mu[J] * x[J - 1];
+        x[J] = J < c ? f : x[J];
       }
+      T y = T(0);
+#pragma unroll
+      for (int J = kTailC - 1; J >= 0; J--) {
+        const T b = J == c - 1 ? iv[J] * x[J] : iv[J] * x[J] - qs[J] * y;
+        y = J < c ? b : y;
+        x[J] = y;
+      }
+#pragma unroll
+      for (int J = 0; J < kTailC; J++)
+        if (J < c) p[J * s] = x[J];
     }
     __syncthreads();
   }
@@ -2559,10 +2579,11 @@ __device__ __forceinline__ void tail_dec_body(const TailArgs<T> &a) {
     const uint32_t m1g = ax[1].mm, m2g = ax[2].mm;
     for (int q = tid; q < m0 * m1 * m2; q += kTailThreads) {
       const int r = tdiv(q, m2, m2g), j2 = q - r * m2, j0 = tdiv(r, m1, m1g), j1 = r - j0 * m1;
-      if (!((j0 | j1 | j2) & 1)) continue;
       // nodal corners of V at level indices: the interpolant reads V at
-      // 2*lo, 2*hi, i.e. a coarse view with doubled pitches
+      // 2*lo, 2*hi, i.e. a coarse view with doubled pitches.  Computed at
+      // nodal nodes too (no divergence), stored only at the others.
       const T v = V[q] - tail_interp<T>(V, 2 * m1 * m2, 2 * m2, 2, ax, j0, j1, j2);
+      if (!((j0 | j1 | j2) & 1)) continue;
       const int64_t pos = lcp(j0, c0) * a.up0 + lcp(j1, c1) * a.up1 + lcp(j2, c2);
       if (a.umc) a.umc[pos] = v;
       if (a.lab_w) {
@@ -2670,8 +2691,9 @@ __device__ __forceinline__ void tail_rec_body(const TailArgs<T> &a) {
     const bool last = i == a.nlev - 1;
     for (int q = tid; q < m0 * m1 * m2; q += kTailThreads) {
       const int r = tdiv(q, m2, ax[2].mm), j2 = q - r * m2, j0 = tdiv(r, m1, ax[1].mm), j1 = r - j0 * m1;
-      const T v = ((j0 | j1 | j2) & 1) ? sZ[q] + tail_interp<T>(fA, c1 * c2, c2, 1, ax, j0, j1, j2)
-                                       : fA[((j0 >> 1) * c1 + (j1 >> 1)) * c2 + (j2 >> 1)];
+      const T vc = sZ[q] + tail_interp<T>(fA, c1 * c2, c2, 1, ax, j0, j1, j2);
+      const T vn = fA[((j0 >> 1) * c1 + (j1 >> 1)) * c2 + (j2 >> 1)];
+      const T v = ((j0 | j1 | j2) & 1) ? vc : vn;
       if (last)
         a.dst[j0 * a.dp0 + j1 * a.dp1 + j2] = v;
       else
