@@ -1990,6 +1990,24 @@ mgx_status decompose_placed(const void *u, void *u_mc, mgx_dtype dtype, int ndim
                                (const double *)region, em);
 }
 
+// The 4-D gather of mgx_pad and mgx_crop: dst (ddims) node j takes src
+// (sdims) node min(j, sdims - 1) per axis.
+template <typename T>
+Pad4Args<T> pad4_args(const T *src, T *dst, const int64_t *sdims, const int64_t *ddims) {
+  Pad4Args<T> a{};
+  a.src = src;
+  a.dst = dst;
+  for (int k = 0; k < 4; k++) {
+    a.nsrc[k] = (int)sdims[k];
+    a.ndst[k] = (int)ddims[k];
+  }
+  a.n = (uint32_t)(ddims[0] * ddims[1] * ddims[2] * ddims[3]);
+  a.d3 = make_div32((uint32_t)ddims[3]);
+  a.d2 = make_div32((uint32_t)ddims[2]);
+  a.d1 = make_div32((uint32_t)ddims[1]);
+  return a;
+}
+
 }  // namespace mgx
 
 using namespace mgx;
@@ -2223,23 +2241,9 @@ mgx_status mgx_pad(const void *u, void *u_pad, mgx_dtype dtype, int ndim, const 
     const int64_t nn = dims[0] * dims[1] * dims[2] * dims[3], pn = pd[0] * pd[1] * pd[2] * pd[3];
     const size_t es = elem_size(dtype);
     if (pn >= ((int64_t)1 << 32) || overlaps(u, (size_t)nn * es, u_pad, (size_t)pn * es)) return MGX_ERR_ARG;
-    auto args = [&](auto *src, auto *dst) {
-      using T = std::remove_const_t<std::remove_pointer_t<decltype(src)>>;
-      Pad4Args<T> a{};
-      a.src = src;
-      a.dst = dst;
-      for (int k = 0; k < 4; k++) {
-        a.nsrc[k] = (int)dims[k];
-        a.ndst[k] = (int)pd[k];
-      }
-      a.n = (uint32_t)pn;
-      a.d3 = make_div32((uint32_t)pd[3]);
-      a.d2 = make_div32((uint32_t)pd[2]);
-      a.d1 = make_div32((uint32_t)pd[1]);
-      return a;
-    };
-    return hip_status(dtype == MGX_F32 ? launch_pad4<float>(args((const float *)u, (float *)u_pad), stream)
-                                       : launch_pad4<double>(args((const double *)u, (double *)u_pad), stream));
+    return hip_status(dtype == MGX_F32 ? launch_pad4<float>(pad4_args((const float *)u, (float *)u_pad, dims, pd), stream)
+                                       : launch_pad4<double>(pad4_args((const double *)u, (double *)u_pad, dims, pd),
+                                                             stream));
   }
   int64_t n[3], p[3];
   box3(ndim, dims, n);
@@ -2270,11 +2274,9 @@ mgx_status mgx_crop(const void *u_pad, void *u, mgx_dtype dtype, int ndim, const
     const int64_t nn = dims[0] * dims[1] * dims[2] * dims[3], pn = pd[0] * pd[1] * pd[2] * pd[3];
     const size_t es = elem_size(dtype);
     if (pn >= ((int64_t)1 << 32) || overlaps(u, (size_t)nn * es, u_pad, (size_t)pn * es)) return MGX_ERR_ARG;
-    int64_t sp[3], dp[3];
-    compact_pitches(pd, sp);
-    compact_pitches(dims, dp);
-    return hip_status(dtype == MGX_F32 ? copy4<float>((const float *)u_pad, sp, (float *)u, dp, dims, -1, stream)
-                                       : copy4<double>((const double *)u_pad, sp, (double *)u, dp, dims, -1, stream));
+    return hip_status(dtype == MGX_F32
+                          ? launch_pad4<float>(pad4_args((const float *)u_pad, (float *)u, pd, dims), stream)
+                          : launch_pad4<double>(pad4_args((const double *)u_pad, (double *)u, pd, dims), stream));
   }
   int64_t n[3], p[3];
   box3(ndim, dims, n);

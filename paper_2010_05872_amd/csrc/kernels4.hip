@@ -535,16 +535,59 @@ __global__ void __launch_bounds__(256) k_dequantize4(const int32_t *__restrict__
   }
 }
 
+// Four consecutive destination nodes per thread: one index split per four
+// nodes (the split was most of the per-node work), the four source reads
+// issued together, one 16-byte store (two for FP64) where the four are whole.
+// A quad that runs past a destination row's end continues in the next row.
 template <typename T>
 __global__ void __launch_bounds__(256) k_pad4(Pad4Args<T> a) {
   const uint64_t stride = (uint64_t)gridDim.x * 256u;
-  for (uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x; i < a.n; i += stride) {
+  const uint32_t nq = (a.n + 3u) / 4u;
+  const int n1 = a.ndst[1], n2 = a.ndst[2], n3 = a.ndst[3], s3 = a.nsrc[3];
+  const bool vec = ((uintptr_t)a.dst & 15u) == 0;
+  for (uint64_t t = (uint64_t)blockIdx.x * 256u + threadIdx.x; t < nq; t += stride) {
+    const uint32_t i0 = (uint32_t)t * 4u;
     int j[4];
-    split4((uint32_t)i, a.d3, a.d2, a.d1, j);
-    int64_t s = 0;
+    split4(i0, a.d3, a.d2, a.d1, j);
+    // source row of destination row (j0, j1, j2), the last real one past the edges
+    auto srow = [&]() -> int64_t {
+      int64_t r = 0;
 #pragma unroll
-    for (int k = 0; k < 4; k++) s = s * a.nsrc[k] + min(j[k], a.nsrc[k] - 1);
-    a.dst[i] = a.src[s];
+      for (int k = 0; k < 3; k++) r = r * a.nsrc[k] + min(j[k], a.nsrc[k] - 1);
+      return r * s3;
+    };
+    int64_t rb = srow();
+    int col = j[3];
+    T v[4];
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      if (col == n3) {  // into the next destination row
+        col = 0;
+        if (++j[2] == n2) {
+          j[2] = 0;
+          if (++j[1] == n1) {
+            j[1] = 0;
+            ++j[0];
+          }
+        }
+        rb = srow();
+      }
+      const bool in = i0 + (uint32_t)e < a.n;
+      v[e] = a.src[in ? rb + min(col, s3 - 1) : 0];
+      ++col;
+    }
+    if (vec && i0 + 4u <= a.n) {
+      if constexpr (sizeof(T) == 4) {
+        *(float4 *)(a.dst + i0) = make_float4(v[0], v[1], v[2], v[3]);
+      } else {
+        *(double2 *)(a.dst + i0) = make_double2(v[0], v[1]);
+        *(double2 *)(a.dst + i0 + 2) = make_double2(v[2], v[3]);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; e++)
+        if (i0 + (uint32_t)e < a.n) a.dst[i0 + e] = v[e];
+    }
   }
 }
 
@@ -618,7 +661,7 @@ hipError_t launch_dequantize4(const int32_t *labels, T *umc, Quant4Args a, hipSt
 template <typename T>
 hipError_t launch_pad4(Pad4Args<T> a, hipStream_t st) {
   if (a.n == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_pad4<T>), dim3(grid_for(a.n)), dim3(256), 0, st, a);
+  hipLaunchKernelGGL((k_pad4<T>), dim3(grid_for((a.n + 3) / 4)), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

@@ -128,7 +128,8 @@ struct Quant4Args {
 };
 
 // Edge padding of a non-dyadic 4-D box to a dyadic one (each dummy node takes
-// the value of the nearest real node).
+// the value of the nearest real node): destination node j takes source node
+// min(j, nsrc - 1) on every axis.  With nsrc >= ndst the same gather crops.
 template <typename T>
 struct Pad4Args {
   const T *src;

@@ -172,6 +172,22 @@ def test_padded_4d_path():
     assert (back.double() - u.double()).abs().max().item() <= tol
 
 
+@pytest.mark.parametrize("shape,dt", [((6, 5, 2, 3), torch.float32), ((7, 3, 5, 2), torch.float64),
+                                      ((10, 3, 4, 13), torch.float32), ((3, 2, 2, 2), torch.float64)],
+                         ids=lambda v: "x".join(map(str, v)) if isinstance(v, tuple) else str(v)[6:])
+def test_pad4_bit_exact(shape, dt):
+    """4-D padding equal to the oracle's for boxes whose padded rows are shorter
+    than the four nodes a pad thread writes (quads crossing several row ends),
+    and element counts that are not a multiple of four."""
+    _say(f"[4d pad] {shape} {dt}")
+    u = torch.as_tensor(make_field(shape, seed=len(shape) + shape[0]), dtype=dt, device="cuda")
+    p = mgx.pad(u)
+    torch.cuda.synchronize()
+    assert tuple(p.shape) == oracle.dyadic_shape(shape)
+    assert np.array_equal(p.double().cpu().numpy(), oracle.pad_to_dyadic(u.double().cpu().numpy()))
+    assert torch.equal(mgx.crop(p, shape), u)
+
+
 def test_back_to_back_smaller_4d():
     """Two calls sharing one workspace, the second on a smaller field."""
     ws = torch.full((mgx.workspace_size(mgx.MGX_F32, (17, 17, 33, 17), 0) // 4 + 64,), float("nan"),
