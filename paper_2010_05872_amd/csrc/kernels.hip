@@ -848,6 +848,15 @@ __device__ __forceinline__ void solve_seg_body(const StridedArgs<T> a, const int
 #pragma unroll
   for (int k = 0; k < SEG; k++) v[k] = act ? p[(int64_t)(J0 + k) * sj] : T(0);
   v[SEG] = (act && last) ? p[(int64_t)(J0 + SEG) * sj] : T(0);
+  // apply: the nodal values are requested now and arrive during the solve (read
+  // next to each store, every read would wait for the stores before it)
+  T nod[MODE == kSolveApply ? SEG + 1 : 1];
+  if (MODE == kSolveApply) {
+    const T *const q = a.in + (int64_t)o * a.io + x;  // lanes past the lines read line 0
+#pragma unroll
+    for (int k = 0; k < SEG; k++) nod[k] = q[(int64_t)(J0 + k) * a.ij];
+    if (last) nod[SEG] = q[(int64_t)(J0 + SEG) * a.ij];
+  }
   // ---- forward: the segment's map from zero, and its multiplier ----
   T A = T(0), B = T(1);
 #pragma unroll
@@ -909,17 +918,18 @@ __device__ __forceinline__ void solve_seg_body(const StridedArgs<T> a, const int
     }
   }
   if (!act) return;
-  auto put = [&](const int J, const T y) {
+  auto put = [&](const int k, const T y) {
+    const int J = J0 + k;
     if (MODE == kSolveApply)
-      a.out[(int64_t)J * a.oj + (int64_t)o * a.oo + x] = a.in[(int64_t)J * a.ij + (int64_t)o * a.io + x] + a.sign * y;
+      a.out[(int64_t)J * a.oj + (int64_t)o * a.oo + x] = nod[MODE == kSolveApply ? k : 0] + a.sign * y;
     else if (MODE == kSolveStore)
       a.out[(int64_t)J * a.oj + (int64_t)o * a.oo + x] = y;
     else
       p[(int64_t)J * sj] = y;
   };
 #pragma unroll
-  for (int k = 0; k < SEG; k++) put(J0 + k, v[k]);
-  if (last) put(J0 + SEG, v[SEG]);
+  for (int k = 0; k < SEG; k++) put(k, v[k]);
+  if (last) put(SEG, v[SEG]);
 }
 
 template <typename T, int SEG, int MODE>
