@@ -53,6 +53,9 @@
 #ifndef MGX_REC_WAVES
 #define MGX_REC_WAVES MGX_STENCIL_WAVES
 #endif
+#ifndef MGX_SEG_MINC  // shortest strided lines solved in segments over several waves
+#define MGX_SEG_MINC 129
+#endif
 #ifndef MGX_DEEP_CH
 #define MGX_DEEP_CH 32
 #endif
@@ -2205,7 +2208,8 @@ constexpr int seg_len() {
 }
 template <typename T>
 static bool strided_seg(int c) {
-  return c > 129 && (c - 1) % seg_len<T>() == 0 && (c - 1) / seg_len<T>() <= kSegMaxWaves;
+  return c >= MGX_SEG_MINC && (c - 1) % seg_len<T>() == 0 && (c - 1) / seg_len<T>() >= 2 &&
+         (c - 1) / seg_len<T>() <= kSegMaxWaves;
 }
 
 template <typename T>
@@ -2224,10 +2228,12 @@ static hipError_t launch_seg(StridedArgs<T> a, int mode, hipStream_t st) {
 
 template <typename T>
 hipError_t launch_solve_strided(StridedArgs<T> a, int mode, hipStream_t st) {
-  // lines of up to 129 nodes: the two-ended register solve (half a line in
-  // registers); longer ones: segments of the line on the waves of a
-  // workgroup (measured faster at 257 fp32 nodes: 34 against 40 us per
-  // in-place pass of the 513^3 field's finest level)
+  // lines of MGX_SEG_MINC nodes and more: segments of the line on the waves
+  // of a workgroup (measured faster at 257 fp32 nodes: 34 against 40 us per
+  // in-place pass of the 513^3 field's finest level; at 129, 5 us off the
+  // 513^3 step); shorter ones: the two-ended register solve (half a line in
+  // registers)
+  if (strided_seg<T>(a.c)) return launch_seg<T>(a, mode, st);
   switch (a.c) {
     case 3: launch_twisted_c<T, 3>(a, mode, st); return hipGetLastError();
     case 5: launch_twisted_c<T, 5>(a, mode, st); return hipGetLastError();
@@ -2238,7 +2244,6 @@ hipError_t launch_solve_strided(StridedArgs<T> a, int mode, hipStream_t st) {
     case 129: launch_twisted_c<T, 129>(a, mode, st); return hipGetLastError();
     default: break;
   }
-  if (strided_seg<T>(a.c)) return launch_seg<T>(a, mode, st);
   // the longest lines: chunked sweeps; few lines (one wave per SIMD or less)
   // use deep chunks to keep enough loads in flight
   const bool deep = (int64_t)a.nx * a.nouter < (1 << 18);
@@ -2881,7 +2886,7 @@ static int contig_group(int c) {  // G: lanes per line
 
 template <typename T>
 static bool strided_twisted(int c) {
-  return c <= 129;
+  return c <= 129 && !strided_seg<T>(c);
 }
 template <typename T>
 static bool strided_deep(const StridedArgs<T> &a) {
@@ -3057,6 +3062,14 @@ hipError_t launch_op_multi(int kind, int key, const OpArgs<T> *dargs, const int 
     case kOpSolveStrided: {
       const int c = key >> 4, mode = (key >> 1) & 7;
       const bool deep = key & 1;
+      if (strided_seg<T>(c)) {  // one op kind per launch: every line of it has c nodes
+        constexpr int SEG = seg_len<T>();
+        const int NTS = 64 * ((c - 1) / SEG);
+        if (mode == kSolveApply) MGX_MULTI((k_solve_seg_multi<T, SEG, kSolveApply>), NTS);
+        else if (mode == kSolveStore) MGX_MULTI((k_solve_seg_multi<T, SEG, kSolveStore>), NTS);
+        else MGX_MULTI((k_solve_seg_multi<T, SEG, kSolveInPlace>), NTS);
+        break;
+      }
       switch (c) {
         case 3: twisted_multi<T, 3>(mode, m, total, st); break;
         case 5: twisted_multi<T, 5>(mode, m, total, st); break;
@@ -3065,16 +3078,7 @@ hipError_t launch_op_multi(int kind, int key, const OpArgs<T> *dargs, const int 
         case 33: twisted_multi<T, 33>(mode, m, total, st); break;
         case 65: twisted_multi<T, 65>(mode, m, total, st); break;
         case 129: twisted_multi<T, 129>(mode, m, total, st); break;
-        default:
-          if (strided_seg<T>(c)) {  // one op kind per launch: every line of it has c nodes
-            constexpr int SEG = seg_len<T>();
-            const int NTS = 64 * ((c - 1) / SEG);
-            if (mode == kSolveApply) MGX_MULTI((k_solve_seg_multi<T, SEG, kSolveApply>), NTS);
-            else if (mode == kSolveStore) MGX_MULTI((k_solve_seg_multi<T, SEG, kSolveStore>), NTS);
-            else MGX_MULTI((k_solve_seg_multi<T, SEG, kSolveInPlace>), NTS);
-            break;
-          }
-          {
+        default: {
             constexpr int CS = sizeof(T) == 8 ? 8 : 16;
             constexpr int CD = sizeof(T) == 8 ? MGX_DEEP_CH / 2 : MGX_DEEP_CH;
             if (deep) chunked_multi<T, CD>(mode, m, total, st);
