@@ -661,7 +661,10 @@ hipError_t launch_dequantize4(const int32_t *labels, T *umc, Quant4Args a, hipSt
 template <typename T>
 hipError_t launch_pad4(Pad4Args<T> a, hipStream_t st) {
   if (a.n == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_pad4<T>), dim3(grid_for((a.n + 3) / 4)), dim3(256), 0, st, a);
+  // one quad per thread: a grid-stride loop would make each iteration's reads
+  // wait for the previous iteration's stores (one vector memory counter)
+  const uint64_t g = ((uint64_t)a.n + 1023) / 1024;
+  hipLaunchKernelGGL((k_pad4<T>), dim3((unsigned)(g > 0 ? g : 1)), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
