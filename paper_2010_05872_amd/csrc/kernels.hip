@@ -279,7 +279,9 @@ __device__ __forceinline__ int opaque(int v) {
 // DEPTH iterations ahead into register buffers.
 // LAB: 0 no labels; 1 labels (decompose: written, recompose: read); 2
 // (decompose) labels and the largest |label| written, reduced into a.smax.
-template <typename T, int TX, int TY, int NT, bool DEC, int LAB>
+// WC false: the coefficients are not written (a.umc_w is null), known at
+// compile time, so the labels-only decomposition carries no per-node test.
+template <typename T, int TX, int TY, int NT, bool DEC, int LAB, bool WC = true>
 __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const int lb) {
   constexpr int HR = 2 * TY + 5;  // region rows incl. halo and the extension
   constexpr int W = 2 * TX + 5;   // region row pitch
@@ -471,7 +473,7 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
     if (DEC && (a.umc_w != nullptr || LAB) && plane_in && j >= own_p0 && j < own_p1) {
       T *const cbase = a.umc_w + lc_pos(j, c0) * a.up0;
       int32_t *const lbase = LAB ? a.lab_w + lc_pos(j, c0) * a.up0 : nullptr;
-      const bool wc = a.umc_w != nullptr;
+      const bool wc = WC && a.umc_w != nullptr;
       // the coefficients cv[p0..3] of one 2x2 block (nodes 00, 01, 10, 11 at
       // byte offsets oE + {0, colOdd, rowOdd, rowOdd + colOdd}) to u_mc and /
       // or their labels, for the nodes in f.  Labels are stored from the FP32
@@ -619,11 +621,11 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
   }
 }
 
-template <typename T, int TX, int TY, int NT, bool DEC, int LAB>
+template <typename T, int TX, int TY, int NT, bool DEC, int LAB, bool WC = true>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(DEC ? MGX_STENCIL_WAVES : MGX_REC_WAVES, 8)))
 k_load_vector(StencilArgs<T> a) {
   if (a.gate && *a.gate == 0) return;
-  load_vector_body<T, TX, TY, NT, DEC, LAB>(a, xcd_remap(blockIdx.x, gridDim.x));
+  load_vector_body<T, TX, TY, NT, DEC, LAB, WC>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -2099,6 +2101,12 @@ hipError_t launch_load_vector_t(StencilArgs<T> a, hipStream_t st, Tuning tn) {
   if (!tile_grid(a.ax[0].c, a.ax[1].c, a.ax[2].c, TX, TY, &a.ntx, &a.nty, &a.nzc, &a.tz, tn))
     return hipErrorInvalidValue;
   dim3 grid(a.ntx * a.nty * a.nzc);
+  if constexpr (DEC && LAB != 0) {
+    if (!a.umc_w) {  // labels only
+      hipLaunchKernelGGL((k_load_vector<T, TX, TY, NT, DEC, LAB, false>), grid, dim3(NT), 0, st, a);
+      return hipGetLastError();
+    }
+  }
   hipLaunchKernelGGL((k_load_vector<T, TX, TY, NT, DEC, LAB>), grid, dim3(NT), 0, st, a);
   return hipGetLastError();
 }
