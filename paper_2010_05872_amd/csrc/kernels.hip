@@ -10,10 +10,10 @@
 //   k_solve_contig      coarse mass-matrix solve along the contiguous axis
 //                       (one wavefront scan of the Thomas recurrences);
 //   k_solve_twisted     solves along the strided axes (two-ended Thomas, one
-//                       line per lane, up to 129 nodes; k_solve_seg for longer
-//                       lines: segments of a line on the waves of a workgroup;
-//                       k_solve_strided for the longest), the last one storing
-//                       Q_{l-1} u = M_c^{-1} F.
+//                       line per lane, up to 65 nodes; k_solve_seg from 129
+//                       nodes, MGX_SEG_MINC: segments of a line on the waves of
+//                       a workgroup; k_solve_strided for the longest), the
+//                       last one storing Q_{l-1} u = M_c^{-1} F.
 // Mass apply, restriction and the solve act on different tensor axes, so the
 // three load-vector stencils run first, on the fine grid, and the three
 // solves afterwards on the 8x smaller coarse grid.  Recomposition uses
