@@ -2750,6 +2750,25 @@ struct MultiArgs {
   int n;
 };
 
+// The op's arguments, read through the constant address space (the buffer is
+// written before the launch and only read during it).  Pointers loaded from
+// constant memory are known to be global; loaded through a generic pointer,
+// every access through them would be a flat instruction, whose waits also
+// wait for the LDS operations in flight.  Used by the stencil and solve
+// kernels (the elementwise and tail kernels index their arguments
+// dynamically, which a copy would place in scratch).
+// (The host compilation pass also type-checks this device function but never
+// runs it; the copy out of the constant address space is a device-pass
+// construct, so the host pass reads the generic pointer.)
+template <typename T>
+__device__ __forceinline__ OpArgs<T> op_args(const MultiArgs<T> &m, int f) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return ((const __attribute__((address_space(4))) OpArgs<T> *)m.args)[f];
+#else
+  return m.args[f];
+#endif
+}
+
 __device__ __forceinline__ int find_op(const int *__restrict__ start, int n, int g) {
   int lo = 0, hi = n - 1;
   while (lo < hi) {
@@ -2765,21 +2784,21 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(DEC ? M
 k_load_vector_multi(MultiArgs<T> m) {
   const int g = xcd_remap(blockIdx.x, gridDim.x);
   const int f = find_op(m.start, m.n, g);
-  load_vector_body<T, TX, TY, NT, DEC, LAB>(m.args[f].st, g - m.start[f]);
+  load_vector_body<T, TX, TY, NT, DEC, LAB>(op_args(m, f).st, g - m.start[f]);
 }
 
 template <typename T, int TX, int TY, int NT, bool LAB>
 __global__ void __launch_bounds__(NT) k_interp_add_multi(MultiArgs<T> m) {
   const int g = xcd_remap(blockIdx.x, gridDim.x);
   const int f = find_op(m.start, m.n, g);
-  interp_add_body<T, TX, TY, NT, LAB>(m.args[f].ia, g - m.start[f]);
+  interp_add_body<T, TX, TY, NT, LAB>(op_args(m, f).ia, g - m.start[f]);
 }
 
 template <typename T, int TX, int TY, int NTP, bool LAB>
 __global__ void __launch_bounds__(NTP) k_interp_plane_multi(MultiArgs<T> m) {
   const int g = xcd_remap(blockIdx.x, gridDim.x);
   const int f = find_op(m.start, m.n, g);
-  interp_plane_body<T, TX, TY, NTP, LAB>(m.args[f].ia, g - m.start[f]);
+  interp_plane_body<T, TX, TY, NTP, LAB>(op_args(m, f).ia, g - m.start[f]);
 }
 
 template <typename T>
@@ -2802,14 +2821,14 @@ template <typename T, int E, int G>
 __global__ void __launch_bounds__(256) k_solve_contig_multi(MultiArgs<T> m) {
   const int g = blockIdx.x;
   const int f = find_op(m.start, m.n, g);
-  solve_contig_body<T, E, G>(m.args[f].so, g - m.start[f]);
+  solve_contig_body<T, E, G>(op_args(m, f).so, g - m.start[f]);
 }
 
 template <typename T, int C, int MODE>
 __global__ void __launch_bounds__(256) k_solve_twisted_multi(MultiArgs<T> m) {
   const int g = blockIdx.x;
   const int f = find_op(m.start, m.n, g);
-  const StridedArgs<T> a = m.args[f].sd;
+  const StridedArgs<T> a = op_args(m, f).sd;
   solve_twisted_body<T, C, MODE>(a, g - m.start[f]);
 }
 
@@ -2817,7 +2836,7 @@ template <typename T, int MODE, int CH>
 __global__ void __launch_bounds__(256) k_solve_strided_multi(MultiArgs<T> m) {
   const int g = blockIdx.x;
   const int f = find_op(m.start, m.n, g);
-  const StridedArgs<T> a = m.args[f].sd;
+  const StridedArgs<T> a = op_args(m, f).sd;
   const int b = g - m.start[f], nbx = (a.nx + 255) / 256;
   solve_strided_body<T, MODE, CH>(a, b % nbx, b / nbx);
 }
@@ -2826,21 +2845,21 @@ template <typename T, int SEG, int MODE>
 __global__ void __launch_bounds__(64 * kSegMaxWaves) k_solve_seg_multi(MultiArgs<T> m) {
   const int g = blockIdx.x;
   const int f = find_op(m.start, m.n, g);
-  solve_seg_body<T, SEG, MODE>(m.args[f].sd, g - m.start[f]);
+  solve_seg_body<T, SEG, MODE>(op_args(m, f).sd, g - m.start[f]);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_apply_multi(MultiArgs<T> m) {
   const int g = blockIdx.x;
   const int f = find_op(m.start, m.n, g);
-  apply_body<T>(m.args[f].sd, g - m.start[f]);
+  apply_body<T>(op_args(m, f).sd, g - m.start[f]);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_copy_box_multi(MultiArgs<T> m) {
   const int g = blockIdx.x;
   const int f = find_op(m.start, m.n, g);
-  copy_box_body<T>(m.args[f].cp, g - m.start[f], m.start[f + 1] - m.start[f]);
+  copy_box_body<T>(op_args(m, f).cp, g - m.start[f], m.start[f + 1] - m.start[f]);
 }
 
 template <typename T, bool VEC, bool STATS>
