@@ -376,7 +376,9 @@ __device__ __forceinline__ void load_vector_body(const StencilArgs<T> a, const i
     const unsigned keep = pin ? (skip_nodal ? (valid & ~yxeven) : valid) : 0u;
 #pragma unroll
     for (int k = 0; k < NE; k++) {
-      if ((inlds >> k) & 1u) {
+      // every element but the last of each thread lies in the region
+      // ((NE - 1) NT < HR WL): only the last needs the (divergent) test
+      if (k < NE - 1 || ((inlds >> k) & 1u)) {
         T v;
         if constexpr (!DEC && LAB)
           v = from_label<T>(st[k], a.qc);
