@@ -337,14 +337,18 @@ __device__ __forceinline__ void sweep4_body(const Sweep4Args<T> &a, const T *__r
         skipn[u] = ((j0 | j1 | j2) & 1) == 0;
         auto lc = [&](int j, int k) { return (j & 1) ? a.cc[k] + (j >> 1) : (j >> 1); };
         const int64_t base = (int64_t)lc(j0, 0) * a.up[0] + (int64_t)lc(j1, 1) * a.up[1] + (int64_t)lc(j2, 2) * a.up[2];
+        // taps 2J-2 .. 2J+2 along axis 3: even ones at J-1, J, J+1 of the row's
+        // even part, odd ones at J-1, J of its odd part (from cc[3]); a tap
+        // outside the axis reads a node inside it and is dropped by its weight
+        const int Jm = max(J - 1, 0), Jp = min(J + 1, a.c - 1), Jo = min(J, a.c - 2);
+        const int64_t qo = base + a.cc[3];
+        const int64_t q[5] = {base + Jm, qo + Jm, base + J, qo + Jo, base + Jp};
 #pragma unroll
         for (int d = 0; d < 5; d++) {
-          const int jj = min(max(2 * J + d - 2, 0), a.m - 1);
-          const int64_t q = base + lc(jj, 3);
           if constexpr (LABG)
-            x[u][d] = a.lab[q];
+            x[u][d] = a.lab[q[d]];
           else
-            x[u][d] = (W)a.umc[q];
+            x[u][d] = (W)a.umc[q[d]];
         }
       }
     }
@@ -356,15 +360,17 @@ __device__ __forceinline__ void sweep4_body(const Sweep4Args<T> &a, const T *__r
       T acc = T(0);
 #pragma unroll
       for (int d = 0; d < 5; d++) {
-        const int jj = 2 * J + d - 2;
-        if (jj < 0 || jj >= a.m) continue;
-        if (GATHER && skipn[u] && (jj & 1) == 0) continue;  // nodal node: component zero
+        // taps outside the axis, and (gather) nodal nodes, whose component is
+        // zero, add nothing; selected rather than branched around
+        const bool in = d < 2 ? J > 0 : (d > 2 ? J < a.c - 1 : true);
+        const bool use = in && !(GATHER && skipn[u] && (d & 1) == 0);
         T v;
         if constexpr (LABG)
           v = unlabel4<T>(x[u][d], a.qc);
         else
           v = x[u][d];
-        acc += wt[u][d] * v;
+        const T acc1 = acc + wt[u][d] * v;
+        acc = use ? acc1 : acc;
       }
       a.out[iu] = acc;
     }
