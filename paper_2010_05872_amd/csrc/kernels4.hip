@@ -308,8 +308,9 @@ __device__ __forceinline__ void sweep4_body(const Sweep4Args<T> &a, const T *__r
     for (int u = 0; u < kSweepU; u++) {
       const uint64_t iu = i0 + (uint64_t)u * stride;
       const uint32_t i = (uint32_t)min(iu, (uint64_t)a.n - 1);
-      const uint32_t t = udiv(i, a.dinner);
-      const uint32_t ii = i - t * a.inner;
+      // the gathering sweep runs along the contiguous axis (inner = 1)
+      const uint32_t t = GATHER ? i : udiv(i, a.dinner);
+      const uint32_t ii = GATHER ? 0u : i - t * a.inner;
       const uint32_t o = udiv(t, a.dc);
       const int J = (int)(t - o * (uint32_t)a.c);
       Js[u] = J;
@@ -336,13 +337,15 @@ __device__ __forceinline__ void sweep4_body(const Sweep4Args<T> &a, const T *__r
         const int j1 = (int)(r - (uint32_t)j0 * (uint32_t)a.m1);
         skipn[u] = ((j0 | j1 | j2) & 1) == 0;
         auto lc = [&](int j, int k) { return (j & 1) ? a.cc[k] + (j >> 1) : (j >> 1); };
-        const int64_t base = (int64_t)lc(j0, 0) * a.up[0] + (int64_t)lc(j1, 1) * a.up[1] + (int64_t)lc(j2, 2) * a.up[2];
+        // element indices in 32 bits (4-D boxes hold fewer than 2^32 nodes)
+        const uint32_t base = (uint32_t)lc(j0, 0) * (uint32_t)a.up[0] + (uint32_t)lc(j1, 1) * (uint32_t)a.up[1] +
+                              (uint32_t)lc(j2, 2) * (uint32_t)a.up[2];
         // taps 2J-2 .. 2J+2 along axis 3: even ones at J-1, J, J+1 of the row's
         // even part, odd ones at J-1, J of its odd part (from cc[3]); a tap
         // outside the axis reads a node inside it and is dropped by its weight
-        const int Jm = max(J - 1, 0), Jp = min(J + 1, a.c - 1), Jo = min(J, a.c - 2);
-        const int64_t qo = base + a.cc[3];
-        const int64_t q[5] = {base + Jm, qo + Jm, base + J, qo + Jo, base + Jp};
+        const uint32_t Jm = max(J - 1, 0), Jp = min(J + 1, a.c - 1), Jo = min(J, a.c - 2);
+        const uint32_t qo = base + (uint32_t)a.cc[3];
+        const uint32_t q[5] = {base + Jm, qo + Jm, base + (uint32_t)J, qo + Jo, base + Jp};
 #pragma unroll
         for (int d = 0; d < 5; d++) {
           if constexpr (LABG)
