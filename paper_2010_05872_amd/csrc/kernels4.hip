@@ -74,11 +74,13 @@ __device__ __forceinline__ T unlabel4(int32_t l, double q) {
 // Memory: a pair's words (the 8 corners of Q's stencil in the next even plane
 // -- on an axis where the column is even both corners are the same node --,
 // and the pair's own two values) are loaded together, without branches, and
-// one pair ahead: pair J+1's loads are issued before pair J's stores, and the
-// loaded words are used only in the next step (two register buffers, the
-// loop unrolled twice), so the march waits for memory once per pair at most
-// and the wait overlaps a pair of work.  The arithmetic is that of the nested
-// form (per axis: wl x(lo) + wr x(hi) on odd, x(lo) on even), unchanged.
+// two pairs ahead: pair J+2's loads are issued before pair J's stores (three
+// register buffers, the loop unrolled three times).  One counter covers both
+// loads and stores and drains in order, so waiting for pair J's words also
+// waits for whatever was issued before them; one pair ahead, that was the
+// previous pair's stores and most of pair J+1's loads.  The arithmetic is
+// that of the nested form (per axis: wl x(lo) + wr x(hi) on odd, x(lo) on
+// even), unchanged.
 constexpr int kCoefHalo = 2;                     // load-only lanes on either side of a wave
 constexpr int kCoefCols = 64 - 2 * kCoefHalo;  // output columns per wave of k_coef4
 template <typename T, bool DEC, bool LAB>
@@ -266,21 +268,28 @@ __global__ void __launch_bounds__(256) k_coef4(Coef4Args<T> a) {
       out[(2 * J) * a.op[0] + ocol] = odd ? val(w.e) + qprev : qprev;
     }
   };
-  Words wa, wb;
-  fetch(J0, wa);
+  Words w0, w1, w2;
+  fetch(J0, w0);
+  fetch(min(J0 + 1, J1), w1);
   for (int J = J0;;) {
     if (J == J1) {
-      finish(wa);
+      finish(w0);
       break;
     }
-    fetch(J + 1, wb);
-    pair(J, wa);
+    fetch(min(J + 2, J1), w2);
+    pair(J, w0);
     if (++J == J1) {
-      finish(wb);
+      finish(w1);
       break;
     }
-    fetch(J + 1, wa);
-    pair(J, wb);
+    fetch(min(J + 2, J1), w0);
+    pair(J, w1);
+    if (++J == J1) {
+      finish(w2);
+      break;
+    }
+    fetch(min(J + 2, J1), w1);
+    pair(J, w2);
     ++J;
   }
 }
