@@ -56,9 +56,9 @@ __device__ __forceinline__ T unlabel4(int32_t l, double q) {
 }
 
 // One thread per column (j1, j2, j3) of the level box and chunk of plane
-// pairs (blockIdx.y), marching along axis 0.  A wave takes 60 consecutive
-// columns (lanes 2..61) plus two on either side (lanes 0, 1, 62, 63, which
-// only load): the axis-3 neighbours j3 - 1, j3 + 1 of a column with odd j3
+// pairs (the logical block's row), marching along axis 0.  A wave takes 60
+// consecutive columns (lanes 2..61) plus two on either side (lanes 0, 1, 62,
+// 63, which only load): the axis-3 neighbours j3 - 1, j3 + 1 of a column with odd j3
 // (never the first or last of its row) are then the neighbouring lanes, whose
 // values come by lane shuffles, so a lane loads Q's corners only at its own
 // j3.  With a.g the decomposition also takes the first load-vector sweep
@@ -83,12 +83,24 @@ __device__ __forceinline__ T unlabel4(int32_t l, double q) {
 // even), unchanged.
 constexpr int kCoefHalo = 2;                     // load-only lanes on either side of a wave
 constexpr int kCoefCols = 64 - 2 * kCoefHalo;  // output columns per wave of k_coef4
+// Workgroups are dispatched to the 8 XCDs (each with its own L2) in turn.
+// Logical block of the b-th workgroup of nb: each XCD takes a contiguous
+// range of logical blocks, columns first and then chunks, so the rows
+// j1 - 1 and j1 + 1 whose nodes a column's interpolant reads, and the lines
+// that two neighbouring workgroups share, are fetched into one L2.
+__device__ __forceinline__ uint64_t xcd_block4(uint64_t b, uint64_t nb) {
+  const uint64_t q = nb >> 3, r = nb & 7, xcd = b & 7;
+  return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + (b >> 3);
+}
+
 template <typename T, bool DEC, bool LAB>
 __global__ void __launch_bounds__(256) k_coef4(Coef4Args<T> a) {
   const int m1 = a.ax[1].m, m2 = a.ax[2].m, m3 = a.ax[3].m;
   const int c1 = a.ax[1].c, c2 = a.ax[2].c, c3 = a.ax[3].c;
   const int lane = threadIdx.x & 63;
-  const int64_t wcol = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kCoefCols - kCoefHalo + lane;
+  const uint64_t lb = xcd_block4(blockIdx.x + (uint64_t)blockIdx.y * gridDim.x, (uint64_t)gridDim.x * gridDim.y);
+  const uint64_t bx = lb % gridDim.x, by = lb / gridDim.x;
+  const int64_t wcol = ((int64_t)bx * 4 + (threadIdx.x >> 6)) * kCoefCols - kCoefHalo + lane;
   // every lane runs the march (the shuffles need the whole wave); only the
   // inner lanes of real columns store
   const bool active = lane >= kCoefHalo && lane < kCoefHalo + kCoefCols && wcol < (int64_t)a.ncol;
@@ -205,7 +217,7 @@ __global__ void __launch_bounds__(256) k_coef4(Coef4Args<T> a) {
   // this chunk's pairs (even plane 2J, odd plane 2J+1), J0 <= J < J1; the
   // last chunk also takes the last even plane
   const int npair = cc0 - 1;
-  const int J0 = (int)blockIdx.y * a.jchunk;
+  const int J0 = (int)by * a.jchunk;
   const int J1 = min(npair, J0 + a.jchunk);
   const bool last = J1 == npair;
   // the words of pair J: the corners of Q in plane 2J+2 (DEC) or J+1 (REC,
