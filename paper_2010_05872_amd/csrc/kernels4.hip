@@ -320,7 +320,8 @@ __device__ __forceinline__ void sweep4_body(const Sweep4Args<T> &a, const T *__r
   // LABG: the gathered inputs are labels, raw until summed
   using W = typename std::conditional<LABG, int32_t, T>::type;
   const uint64_t stride = (uint64_t)gridDim.x * 256u;
-  for (uint64_t i0 = (uint64_t)blockIdx.x * 256u + threadIdx.x; i0 < a.n; i0 += kSweepU * stride) {
+  const uint64_t lb = xcd_block4(blockIdx.x, gridDim.x);  // neighbouring blocks under one L2
+  for (uint64_t i0 = lb * 256u + threadIdx.x; i0 < a.n; i0 += kSweepU * stride) {
     W x[kSweepU][5];
     T wt[kSweepU][5];  // the stencil weights, read with the inputs
     int Js[kSweepU];
@@ -429,7 +430,10 @@ __global__ void __launch_bounds__(256) k_sweep4(Sweep4Args<T> a) {
 // position and count as zero.
 template <typename T>
 __global__ void __launch_bounds__(256) k_sweep4_march(Sweep4Args<T> a) {
-  const uint64_t col = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+  // logical block: each XCD takes a contiguous range of columns (as k_coef4)
+  const uint64_t lb = xcd_block4(blockIdx.x + (uint64_t)blockIdx.y * gridDim.x, (uint64_t)gridDim.x * gridDim.y);
+  const uint64_t bx = lb % gridDim.x, by = lb / gridDim.x;
+  const uint64_t col = bx * 256u + threadIdx.x;
   const uint64_t ncol = (uint64_t)a.n / (uint64_t)a.c;  // outer * inner
   if (col >= ncol) return;
   const uint32_t o = udiv((uint32_t)col, a.dinner);
@@ -441,7 +445,7 @@ __global__ void __launch_bounds__(256) k_sweep4_march(Sweep4Args<T> a) {
   const int m = a.m;
   auto ld = [&](int j) { return row[(int64_t)min(max(j, 0), m - 1) * inner]; };
   auto x = [&](int j, T v) { return (j >= 0 && j < m) ? v : T(0); };
-  const int J0 = (int)blockIdx.y * a.jchunk, J1 = min(a.c, J0 + a.jchunk);
+  const int J0 = (int)by * a.jchunk, J1 = min(a.c, J0 + a.jchunk);
   if (J0 >= J1) return;
   T xm2 = x(2 * J0 - 2, ld(2 * J0 - 2)), xm1 = x(2 * J0 - 1, ld(2 * J0 - 1)), x0 = x(2 * J0, ld(2 * J0));
   auto step = [&](int J, T r1, T r2) {
