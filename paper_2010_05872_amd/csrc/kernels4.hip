@@ -87,7 +87,10 @@ constexpr int kCoefCols = 64 - 2 * kCoefHalo;  // output columns per wave of k_c
 // Logical block of the b-th workgroup of nb: each XCD takes a contiguous
 // range of logical blocks, columns first and then chunks, so the rows
 // j1 - 1 and j1 + 1 whose nodes a column's interpolant reads, and the lines
-// that two neighbouring workgroups share, are fetched into one L2.
+// that two neighbouring workgroups share, are fetched into one L2.  The
+// order is that of the three-axis level kernels (xcd_remap in kernels.hip),
+// with 64-bit block counts, since a four-axis grid's blocks times chunks
+// may pass 2^31.
 __device__ __forceinline__ uint64_t xcd_block4(uint64_t b, uint64_t nb) {
   const uint64_t q = nb >> 3, r = nb & 7, xcd = b & 7;
   return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + (b >> 3);
